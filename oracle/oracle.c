@@ -1,0 +1,891 @@
+/*
+ * CPU oracle for photon-path verification.  TEST INFRASTRUCTURE ONLY: see
+ * oracle.h.  Every function states the passage of the paper it follows
+ * (Moreau, Doggett, Sintorn, "Path Verification for Dynamic Indirect
+ * Illumination") or the published method it restates.
+ *
+ * Readings taken where the paper is silent (each is also listed in the design
+ * notes of the repository):
+ *  - photons store their position in place of the incoming direction; the
+ *    incoming direction is the difference of consecutive positions;
+ *  - a segment is blocked by a triangle (two-sided) crossed strictly inside
+ *    the open interval (eps_end, L - eps_end) of its length L;
+ *  - only objects whose transform changed are tested; a segment whose end
+ *    photon lies on a moved object is invalid;
+ *  - world vertices are fp32(fma(m0,x,fma(m1,y,fma(m2,z,t)))) evaluated in FP64;
+ *  - random numbers come from Philox4x64-10 keyed (seed, 0) with counter
+ *    (path, frame, vertex, tag); uniforms are the top 24 bits times 2^-24;
+ *  - cosine-weighted directions: Shirley-Chiu concentric map lifted to the
+ *    hemisphere (Malley), tangent frame from Duff et al. 2017;
+ *  - no Russian roulette: paths run to B photons or to a ray that escapes.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define HIT_NONE 0xffffffffu
+#define CHUNK 32
+#define T_FAR 16.0
+
+/* ------------------------------------------------------------------------ */
+/* path information word (Section 4: cell 22 bits, segment count 4 bits,     */
+/* retrace start 4 bits, replace 1 bit, reuse light 1 bit)                   */
+
+static uint32_t info_cell(uint32_t w) { return w & 0x3fffffu; }
+static uint32_t info_nseg(uint32_t w) { return (w >> 22) & 15u; }
+static uint32_t info_start(uint32_t w) { return (w >> 26) & 15u; }
+static uint32_t info_replace(uint32_t w) { return (w >> 30) & 1u; }
+static uint32_t info_reuse(uint32_t w) { return (w >> 31) & 1u; }
+static uint32_t info_make(uint32_t cell, uint32_t nseg, uint32_t start, uint32_t replace,
+                          uint32_t reuse) {
+  return (cell & 0x3fffffu) | ((nseg & 15u) << 22) | ((start & 15u) << 26) |
+         ((replace & 1u) << 30) | ((reuse & 1u) << 31);
+}
+
+uint32_t or_info_make(uint32_t cell, uint32_t nseg, uint32_t start, uint32_t replace,
+                      uint32_t reuse) {
+  return info_make(cell, nseg, start, replace, reuse);
+}
+
+/* ------------------------------------------------------------------------ */
+/* small FP64 vector helpers                                                 */
+
+static void sub3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
+static void load3f(const float* p, double o[3]) { o[0] = p[0]; o[1] = p[1]; o[2] = p[2]; }
+static void store3f(float* p, const double o[3]) {
+  p[0] = (float)o[0]; p[1] = (float)o[1]; p[2] = (float)o[2];
+}
+static double clamp01(double x) { return x < 0 ? 0 : (x > 1 ? 1 : x); }
+
+/* ------------------------------------------------------------------------ */
+/* Transform of dynamic-object vertices (Section 3.2 needs the current       */
+/* frame's geometry; rounding fixed by the reading above).                   */
+
+void or_transform(int64_t n_verts, const float* local, const float* m, float* out) {
+  for (int64_t i = 0; i < n_verts; ++i) {
+    double x = local[3 * i], y = local[3 * i + 1], z = local[3 * i + 2];
+    for (int r = 0; r < 3; ++r) {
+      double v = fma((double)m[4 * r + 0], x,
+                     fma((double)m[4 * r + 1], y, fma((double)m[4 * r + 2], z, (double)m[4 * r + 3])));
+      out[3 * i + r] = (float)v;
+    }
+  }
+}
+
+/* moved <=> any of the 12 floats differs bitwise */
+int or_xf_moved(const float* a, const float* b) {
+  return memcmp(a, b, 12 * sizeof(float)) != 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), restated from its      */
+/* published definition: ten rounds of two 64x64->128 multiplies, the key     */
+/* bumped by the Weyl constants between rounds.                              */
+
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+void or_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint64_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(M0, c0, &hi0, &lo0);
+    mulhilo64(M1, c2, &hi1, &lo1);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += W0; k1 += W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* uniform in [0,1): top 24 bits, exactly representable in FP32 */
+static double u24(uint64_t x) { return (double)(x >> 40) * (1.0 / 16777216.0); }
+
+static void draw4(uint64_t seed, uint64_t path, uint64_t frame, uint64_t vertex, uint64_t tag,
+                  double u[4]) {
+  uint64_t ctr[4] = {path, frame, vertex, tag}, key[2] = {seed, 0}, r[4];
+  or_philox4x64(ctr, key, r);
+  for (int i = 0; i < 4; ++i) u[i] = u24(r[i]);
+}
+
+/* Shirley & Chiu 1997 concentric square-to-disk map, lifted to the cosine-  */
+/* weighted hemisphere (Malley's method): returns local (x, y, z), z >= 0.   */
+void or_cosine_local(double u1, double u2, double out[3]) {
+  double a = 2.0 * u1 - 1.0, b = 2.0 * u2 - 1.0, r, phi;
+  const double PI = 3.14159265358979323846;
+  if (a == 0.0 && b == 0.0) {
+    r = 0.0; phi = 0.0;
+  } else if (fabs(a) > fabs(b)) {
+    r = a; phi = (PI / 4.0) * (b / a);
+  } else {
+    r = b; phi = PI / 2.0 - (PI / 4.0) * (a / b);
+  }
+  double x = r * cos(phi), y = r * sin(phi);
+  double z2 = 1.0 - x * x - y * y;
+  out[0] = x; out[1] = y; out[2] = z2 > 0.0 ? sqrt(z2) : 0.0;
+}
+
+/* Duff, Burgess, Christensen, Hery, Kensler, Liani, Villemin, "Building an  */
+/* Orthonormal Basis, Revisited", JCGT 2017: tangents t, b of unit normal n. */
+void or_onb(const double n[3], double t[3], double b[3]) {
+  double sign = n[2] >= 0.0 ? 1.0 : -1.0;
+  double a = -1.0 / (sign + n[2]);
+  double c = n[0] * n[1] * a;
+  t[0] = 1.0 + sign * n[0] * n[0] * a; t[1] = sign * c; t[2] = -sign * n[0];
+  b[0] = c; b[1] = sign + n[1] * n[1] * a; b[2] = -n[1];
+}
+
+/* cosine-weighted direction about unit normal n */
+void or_cosine_dir(double u1, double u2, const double n[3], double out[3]) {
+  double l[3], t[3], b[3];
+  or_cosine_local(u1, u2, l);
+  or_onb(n, t, b);
+  for (int i = 0; i < 3; ++i) out[i] = l[0] * t[i] + l[1] * b[i] + l[2] * n[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry predicates                                                        */
+
+/* Moller & Trumbore 1997, two-sided, FP64: line o + t d against triangle.   */
+/* Returns 1 with (t,u,v) when det != 0 (plane crossing); inside-ness is      */
+/* left to the caller (u >= 0, v >= 0, u + v <= 1).                          */
+static int mt_plane(const double o[3], const double d[3], const double v0[3], const double v1[3],
+                    const double v2[3], double* t, double* u, double* v) {
+  double e1[3], e2[3], p[3], s[3], q[3];
+  sub3(v1, v0, e1);
+  sub3(v2, v0, e2);
+  cross3(d, e2, p);
+  double det = dot3(e1, p);
+  if (det == 0.0) return 0;
+  double inv = 1.0 / det;
+  sub3(o, v0, s);
+  *u = dot3(s, p) * inv;
+  cross3(s, e1, q);
+  *v = dot3(d, q) * inv;
+  *t = dot3(e2, q) * inv;
+  return 1;
+}
+
+static int inside_uv(double u, double v) { return u >= 0.0 && v >= 0.0 && u + v <= 1.0; }
+
+/* Exported for tests: 1 if the segment a->b is blocked by the triangle in   */
+/* the sense of Section 3.2 with an endpoint tolerance eps.                  */
+int or_segment_blocked_tri(const double a[3], const double b[3], const double* tri, double eps) {
+  double d[3], t, u, v;
+  sub3(b, a, d);
+  double L = norm3(d);
+  if (!mt_plane(a, d, tri, tri + 3, tri + 6, &t, &u, &v)) return 0;
+  double s = t * L;
+  return inside_uv(u, v) && s > eps && s < L - eps;
+}
+
+/* Closest distance between segments p0p1 and q0q1 (Ericson, Real-Time       */
+/* Collision Detection, 2005, section 5.1.9), FP64.                          */
+double or_segseg_dist(const double p0[3], const double p1[3], const double q0[3], const double q1[3]) {
+  double d1[3], d2[3], r[3];
+  sub3(p1, p0, d1);
+  sub3(q1, q0, d2);
+  sub3(p0, q0, r);
+  double a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+  double s, t;
+  if (a <= 1e-300 && e <= 1e-300) {
+    s = t = 0.0;
+  } else if (a <= 1e-300) {
+    s = 0.0; t = clamp01(f / e);
+  } else {
+    double c = dot3(d1, r);
+    if (e <= 1e-300) {
+      t = 0.0; s = clamp01(-c / a);
+    } else {
+      double b = dot3(d1, d2), den = a * e - b * b;
+      s = den != 0.0 ? clamp01((b * f - c * e) / den) : 0.0;
+      t = (b * s + f) / e;
+      if (t < 0.0) {
+        t = 0.0; s = clamp01(-c / a);
+      } else if (t > 1.0) {
+        t = 1.0; s = clamp01((b - c) / a);
+      }
+    }
+  }
+  double c1[3], c2[3], w[3];
+  for (int i = 0; i < 3; ++i) { c1[i] = p0[i] + d1[i] * s; c2[i] = q0[i] + d2[i] * t; }
+  sub3(c1, c2, w);
+  return norm3(w);
+}
+
+static double tri_edge_dist(const double s0[3], const double s1[3], const double v[9]) {
+  double m = or_segseg_dist(s0, s1, v, v + 3);
+  double m2 = or_segseg_dist(s0, s1, v + 3, v + 6);
+  double m3 = or_segseg_dist(s0, s1, v + 6, v);
+  if (m2 < m) m = m2;
+  if (m3 < m) m = m3;
+  return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* exactness-preserving pre-reject: chunks of consecutive same-object tris   */
+
+typedef struct {
+  double lo[3], hi[3];
+  int64_t first;
+  int32_t count;
+  uint32_t obj;
+} chunk_t;
+
+typedef struct {
+  const or_scene* s;
+  chunk_t* ch;
+  int64_t n_ch;
+} accel_t;
+
+static void accel_build(accel_t* a, const or_scene* s) {
+  a->s = s;
+  a->ch = (chunk_t*)malloc(sizeof(chunk_t) * (size_t)(s->n_tris / 1 + 1));
+  a->n_ch = 0;
+  int64_t t = 0;
+  while (t < s->n_tris) {
+    chunk_t* c = &a->ch[a->n_ch++];
+    c->first = t;
+    c->obj = s->tri_obj[t];
+    c->count = 0;
+    for (int k = 0; k < 3; ++k) { c->lo[k] = INFINITY; c->hi[k] = -INFINITY; }
+    while (t < s->n_tris && c->count < CHUNK && s->tri_obj[t] == c->obj) {
+      for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < 3; ++k) {
+          double x = s->verts[9 * t + 3 * v + k];
+          if (x < c->lo[k]) c->lo[k] = x;
+          if (x > c->hi[k]) c->hi[k] = x;
+        }
+      ++c->count;
+      ++t;
+    }
+  }
+}
+
+static void accel_free(accel_t* a) { free(a->ch); }
+
+/* does o + t d, t in [t0, t1], come within pad of the box? (slab test)      */
+static int seg_box(const double o[3], const double d[3], double t0, double t1, const double lo[3],
+                   const double hi[3], double pad) {
+  for (int k = 0; k < 3; ++k) {
+    double l = lo[k] - pad, h = hi[k] + pad;
+    if (d[k] == 0.0) {
+      if (o[k] < l || o[k] > h) return 0;
+    } else {
+      double ta = (l - o[k]) / d[k], tb = (h - o[k]) / d[k];
+      if (ta > tb) { double x = ta; ta = tb; tb = x; }
+      if (ta > t0) t0 = ta;
+      if (tb < t1) t1 = tb;
+      if (t0 > t1) return 0;
+    }
+  }
+  return 1;
+}
+
+static void tri_verts(const or_scene* s, int64_t t, double v[9]) {
+  for (int i = 0; i < 9; ++i) v[i] = s->verts[9 * t + i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3.2: is segment a->b blocked by a triangle of a moved object?      */
+/* Result: 0 clear, 1 blocked.  *amb |= flags when some triangle lies within  */
+/* the band of the decision (edge or endpoint) and no triangle blocks it      */
+/* with margin.                                                               */
+
+static int seg_blocked_moved(const accel_t* A, const double a[3], const double b[3], double band,
+                             uint32_t* amb) {
+  const or_scene* s = A->s;
+  double d[3];
+  sub3(b, a, d);
+  double L = norm3(d);
+  if (L <= 0.0) return 0;
+  double e = s->eps_end;
+  double tlo = (e - band) / L, thi = (L - e + band) / L;
+  if (tlo < 0) tlo = 0;
+  if (thi > 1) thi = 1;
+  if (tlo > thi) return 0;
+  double s0[3], s1[3];
+  for (int i = 0; i < 3; ++i) { s0[i] = a[i] + tlo * d[i]; s1[i] = a[i] + thi * d[i]; }
+  int blocked = 0, certain = 0;
+  uint32_t local_amb = 0;
+  for (int64_t c = 0; c < A->n_ch && !certain; ++c) {
+    const chunk_t* ch = &A->ch[c];
+    if (ch->obj == 0 || !s->obj_moved[ch->obj]) continue;
+    if (!seg_box(a, d, tlo, thi, ch->lo, ch->hi, band + 1e-9)) continue;
+    for (int64_t t = ch->first; t < ch->first + ch->count; ++t) {
+      double v[9], tt, u, w;
+      tri_verts(s, t, v);
+      double ed = tri_edge_dist(s0, s1, v);
+      int near_edge = ed <= band;
+      int hit = 0, near_end = 0;
+      if (mt_plane(a, d, v, v + 3, v + 6, &tt, &u, &w)) {
+        double dist = tt * L;
+        int in = inside_uv(u, w);
+        hit = in && dist > e && dist < L - e;
+        near_end = in && (fabs(dist - e) <= band || fabs(dist - (L - e)) <= band);
+      }
+      if (hit) blocked = 1;
+      if (hit && !near_edge && !near_end) { certain = 1; break; }
+      if (near_edge) local_amb |= OR_AMB_EDGE;
+      if (near_end) local_amb |= OR_AMB_END;
+    }
+  }
+  if (!certain) *amb |= local_amb;
+  return blocked;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closest hit over every triangle (static and dynamic), two-sided, with the  */
+/* ray o + t w (w unit), t > eps_end.  Ties at equal t: lowest triangle id.   */
+
+typedef struct {
+  double t;
+  int64_t tri;
+} hit_t;
+
+static hit_t closest_hit(const accel_t* A, const double o[3], const double w[3], double band,
+                         uint32_t* amb) {
+  const or_scene* s = A->s;
+  double e = s->eps_end;
+  hit_t h = {INFINITY, -1};
+  for (int64_t c = 0; c < A->n_ch; ++c) {
+    const chunk_t* ch = &A->ch[c];
+    double tmax = h.tri >= 0 ? h.t : T_FAR;
+    if (!seg_box(o, w, e, tmax, ch->lo, ch->hi, 1e-9)) continue;
+    for (int64_t t = ch->first; t < ch->first + ch->count; ++t) {
+      double v[9], tt, u, vv;
+      tri_verts(s, t, v);
+      if (!mt_plane(o, w, v, v + 3, v + 6, &tt, &u, &vv)) continue;
+      if (!inside_uv(u, vv) || !(tt > e)) continue;
+      if (tt < h.t || (tt == h.t && t < h.tri)) { h.t = tt; h.tri = t; }
+    }
+  }
+  /* ambiguity: any triangle edge within band of the travelled ray, a second
+     surface within band of the hit distance, or a crossing within band of
+     eps_end */
+  double tend = h.tri >= 0 ? h.t + band : T_FAR;
+  double s0[3], s1[3];
+  for (int i = 0; i < 3; ++i) { s0[i] = o[i] + (e - band) * w[i]; s1[i] = o[i] + tend * w[i]; }
+  for (int64_t c = 0; c < A->n_ch; ++c) {
+    const chunk_t* ch = &A->ch[c];
+    if (!seg_box(o, w, e - band, tend, ch->lo, ch->hi, band + 1e-9)) continue;
+    for (int64_t t = ch->first; t < ch->first + ch->count; ++t) {
+      double v[9], tt, u, vv;
+      tri_verts(s, t, v);
+      if (tri_edge_dist(s0, s1, v) <= band) *amb |= OR_AMB_EDGE;
+      if (mt_plane(o, w, v, v + 3, v + 6, &tt, &u, &vv) && inside_uv(u, vv)) {
+        if (fabs(tt - e) <= band) *amb |= OR_AMB_END;
+        if (t != h.tri && h.tri >= 0 && fabs(tt - h.t) <= band) *amb |= OR_AMB_TIE;
+      }
+    }
+  }
+  return h;
+}
+
+/* geometric normal of a triangle (unit, FP64) */
+static void tri_normal(const or_scene* s, int64_t t, double n[3]) {
+  double v[9], e1[3], e2[3];
+  tri_verts(s, t, v);
+  sub3(v + 3, v, e1);
+  sub3(v + 6, v, e2);
+  cross3(e1, e2, n);
+  double l = norm3(n);
+  for (int i = 0; i < 3; ++i) n[i] /= l;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3.1, "Update path origins" for an area light: keep the outgoing    */
+/* direction, intersect it with the moved light's plane; invalid when the     */
+/* new origin falls outside the light or the direction leaves its back side.  */
+
+static void light_frame(const float* xf, double c[3], double eu[3], double ev[3], double n[3]) {
+  for (int r = 0; r < 3; ++r) {
+    eu[r] = xf[4 * r + 0];
+    ev[r] = xf[4 * r + 1];
+    n[r] = xf[4 * r + 2];
+    c[r] = xf[4 * r + 3];
+  }
+  double l = norm3(n);
+  for (int r = 0; r < 3; ++r) n[r] /= l;
+}
+
+int or_light_update(const float* xf, const float* half, const double x0[3], const double x1[3],
+                    double eps, double band, double out[3], uint32_t* amb) {
+  double c[3], eu[3], ev[3], n[3], w[3];
+  light_frame(xf, c, eu, ev, n);
+  sub3(x1, x0, w);
+  double len = norm3(w);
+  if (len <= 0.0) return 0;
+  for (int i = 0; i < 3; ++i) w[i] /= len;
+  double dn = dot3(w, n);
+  if (fabs(dn) <= band) *amb |= OR_AMB_LIGHT;
+  if (!(dn > 0.0)) return 0;
+  double q[3];
+  sub3(x1, c, q);
+  double sdist = dot3(q, n) / dn;
+  if (fabs(sdist - eps) <= band) *amb |= OR_AMB_LIGHT;
+  if (!(sdist > eps)) return 0;
+  double p[3];
+  for (int i = 0; i < 3; ++i) p[i] = x1[i] - sdist * w[i];
+  double r[3];
+  sub3(p, c, r);
+  double u = dot3(r, eu), v = dot3(r, ev);
+  if (fabs(fabs(u) - half[0]) <= band || fabs(fabs(v) - half[1]) <= band) *amb |= OR_AMB_LIGHT;
+  if (!(fabs(u) <= half[0] && fabs(v) <= half[1])) return 0;
+  for (int i = 0; i < 3; ++i) out[i] = p[i];
+  return 1;
+}
+
+static int light_of(const or_scene* s, int64_t p) {
+  for (int l = 0; l < s->n_lights; ++l)
+    if (p >= s->light_base[l] && p < s->light_base[l + 1]) return l;
+  return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* path vertex access: x_0 = origin, x_j = row j-1                            */
+
+static void vtx(const or_store* st, int64_t p, int j, double o[3]) {
+  if (j == 0)
+    load3f(st->origin + 3 * p, o);
+  else
+    load3f(st->pos + 3 * ((int64_t)(j - 1) * st->n_paths + p), o);
+}
+static uint32_t vhit(const or_store* st, int64_t p, int j) {
+  return st->hit[(int64_t)(j - 1) * st->n_paths + p];
+}
+static int hit_on_moved(const or_scene* s, uint32_t h) {
+  if (h == HIT_NONE || (int64_t)h >= s->n_tris) return 0;
+  uint32_t o = s->tri_obj[h];
+  return o != 0 && s->obj_moved[o];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dynamic occlusions (Section 3.2) preceded by the origin update (Section   */
+/* 3.1), per path, by definition: segments are tested in order from the one  */
+/* leaving the light, and the first invalid one and all later ones are        */
+/* scheduled for re-tracing.  The origin is rewritten for moved lights and    */
+/* the information word gets replace / start / reuse-light.                   */
+
+static void verify_path(const or_scene* s, const accel_t* A, or_store* st, int64_t p,
+                        uint32_t* amb_out, int32_t* examined_out) {
+  const double band = s->band_verify;
+  uint32_t w = st->info[p];
+  uint32_t n = info_nseg(w), cell = info_cell(w);
+  uint32_t a = 0;
+  int ex = 0, done = 0;
+  int l = light_of(s, p);
+  uint32_t out = info_make(cell, n, 0, 0, 0);
+  if (l >= 0 && s->light_moved[l]) {
+    double x0[3], x1[3], nx[3];
+    if (n == 0) {
+      done = 1; /* no photon to aim at: a new light sample is drawn */
+    } else {
+      vtx(st, p, 0, x0);
+      vtx(st, p, 1, x1);
+      if (or_light_update(s->light_xf + 12 * l, s->light_half + 2 * l, x0, x1, s->eps_end, band,
+                          nx, &a))
+        store3f(st->origin + 3 * p, nx);
+      else
+        done = 1;
+    }
+    if (done) out = info_make(cell, n, 0, 1, 0);
+  }
+  for (uint32_t j = 0; j < n && !done; ++j) {
+    double xa[3], xb[3];
+    vtx(st, p, (int)j, xa);
+    vtx(st, p, (int)j + 1, xb);
+    ++ex;
+    int inv = hit_on_moved(s, vhit(st, p, (int)j + 1));
+    if (!inv) inv = seg_blocked_moved(A, xa, xb, band, &a);
+    if (inv) {
+      out = info_make(cell, n, j, 1, 1);
+      done = 1;
+    }
+  }
+  st->info[p] = out;
+  *amb_out = a;
+  *examined_out = ex;
+}
+
+/* all paths; out: amb[p] flags, examined[p] segments examined */
+void or_verify(const or_scene* s, or_store* st, uint32_t* amb, int32_t* examined) {
+  accel_t A;
+  accel_build(&A, s);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t p = 0; p < st->n_paths; ++p) verify_path(s, &A, st, p, &amb[p], &examined[p]);
+  accel_free(&A);
+}
+
+/* only the listed paths (a sample); amb / examined indexed like the list */
+void or_verify_list(const or_scene* s, or_store* st, const int64_t* list, int64_t n_list,
+                    uint32_t* amb, int32_t* examined) {
+  accel_t A;
+  accel_build(&A, s);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n_list; ++i) verify_path(s, &A, st, list[i], &amb[i], &examined[i]);
+  accel_free(&A);
+}
+
+/* stand-alone segment query for tests: returns 0/1, amb flags */
+int or_segment_query(const or_scene* s, const double a[3], const double b[3], uint32_t* amb) {
+  accel_t A;
+  accel_build(&A, s);
+  int r = seg_blocked_moved(&A, a, b, s->band_verify, amb);
+  accel_free(&A);
+  return r;
+}
+
+/* stand-alone closest-hit query for tests */
+int64_t or_closest_query(const or_scene* s, const double o[3], const double w[3], double* t,
+                         uint32_t* amb) {
+  accel_t A;
+  accel_build(&A, s);
+  hit_t h = closest_hit(&A, o, w, s->band_trace, amb);
+  accel_free(&A);
+  *t = h.t;
+  return h.tri;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Re-tracing (Section 3.2 naive; Section 3.3 / Algorithm 1 error-based)     */
+
+typedef struct {
+  const or_scene* s;
+  const accel_t* A;
+  or_store* st;
+  uint64_t seed;
+  uint64_t frame;
+  float T;
+} rctx;
+
+static void put_photon(or_store* st, int64_t p, int row, const double x[3], uint32_t hit,
+                       const float e[3], float radius) {
+  int64_t i = (int64_t)row * st->n_paths + p;
+  store3f(st->pos + 3 * i, x);
+  st->hit[i] = hit;
+  st->energy[3 * i + 0] = e[0];
+  st->energy[3 * i + 1] = e[1];
+  st->energy[3 * i + 2] = e[2];
+  st->radius[i] = radius;
+}
+
+static void clear_rows(or_store* st, int64_t p, int from) {
+  for (int r = from; r < st->B; ++r) {
+    int64_t i = (int64_t)r * st->n_paths + p;
+    st->pos[3 * i] = st->pos[3 * i + 1] = st->pos[3 * i + 2] = 0.0f;
+    st->hit[i] = HIT_NONE;
+    st->energy[3 * i] = st->energy[3 * i + 1] = st->energy[3 * i + 2] = 0.0f;
+    st->radius[i] = 0.0f;
+  }
+}
+
+static void energy_row(const or_store* st, int64_t p, int row, float e[3]) {
+  int64_t i = (int64_t)row * st->n_paths + p;
+  e[0] = st->energy[3 * i]; e[1] = st->energy[3 * i + 1]; e[2] = st->energy[3 * i + 2];
+}
+
+/* E_next = E (x) albedo, per channel, rounded to FP32 (the product of two    */
+/* FP32 numbers is exact in FP64, so this is the FP32 product)                */
+static void reflect(const or_scene* s, const float e[3], uint32_t tri, float out[3]) {
+  const float* rho = s->albedo + 3 * s->tri_mat[tri];
+  for (int c = 0; c < 3; ++c) out[c] = (float)((double)e[c] * (double)rho[c]);
+}
+
+/* Trace new bounces from photon row 'row0' (vertex x_{row0+1}) with energy  */
+/* e_row0 already stored, sampling cosine-weighted directions, up to B.      */
+/* w_in: direction that arrived at that vertex.  Returns the photon count.   */
+static int naive_tail(rctx* c, int64_t p, int row0, const double x_in[3], const double w_in[3],
+                      uint32_t tri_in, const float e_in[3], uint32_t* amb, int* traces) {
+  double x[3] = {x_in[0], x_in[1], x_in[2]}, w[3] = {w_in[0], w_in[1], w_in[2]};
+  uint32_t tri = tri_in;
+  float e[3] = {e_in[0], e_in[1], e_in[2]};
+  int row = row0;
+  while (row + 1 < c->st->B) {
+    double n[3], u[4], wn[3];
+    tri_normal(c->s, tri, n);
+    if (dot3(n, w) > 0.0)
+      for (int i = 0; i < 3; ++i) n[i] = -n[i];
+    draw4(c->seed, (uint64_t)p, c->frame, (uint64_t)(row + 1), 1, u);
+    or_cosine_dir(u[0], u[1], n, wn);
+    hit_t h = closest_hit(c->A, x, wn, c->s->band_trace, amb);
+    ++*traces;
+    if (h.tri < 0) break;
+    double xn[3];
+    for (int i = 0; i < 3; ++i) xn[i] = x[i] + h.t * wn[i];
+    float en[3];
+    reflect(c->s, e, tri, en);
+    ++row;
+    put_photon(c->st, p, row, xn, (uint32_t)h.tri, en, c->s->radius);
+    for (int i = 0; i < 3; ++i) { x[i] = xn[i]; w[i] = wn[i]; }
+    tri = (uint32_t)h.tri;
+    e[0] = en[0]; e[1] = en[1]; e[2] = en[2];
+  }
+  return row + 1;
+}
+
+/* Trace segment k from x_k along direction w and continue naively.          */
+/* Writes photons rows k.., returns the photon count.                          */
+static int naive_from(rctx* c, int64_t p, int k, const double xk[3], const double w[3],
+                      uint32_t* amb, int* traces) {
+  const or_scene* s = c->s;
+  or_store* st = c->st;
+  int l = light_of(s, p);
+  hit_t h = closest_hit(c->A, xk, w, s->band_trace, amb);
+  ++*traces;
+  if (h.tri < 0) return k;
+  double xn[3];
+  for (int i = 0; i < 3; ++i) xn[i] = xk[i] + h.t * w[i];
+  float en[3];
+  if (k == 0) {
+    int64_t Nl = s->light_base[l + 1] - s->light_base[l];
+    for (int ch = 0; ch < 3; ++ch) en[ch] = (float)((double)s->light_power[3 * l + ch] / (double)Nl);
+  } else {
+    float ek[3];
+    energy_row(st, p, k - 1, ek);
+    reflect(s, ek, vhit(st, p, k), en);
+  }
+  put_photon(st, p, k, xn, (uint32_t)h.tri, en, s->radius);
+  return naive_tail(c, p, k, xn, w, (uint32_t)h.tri, en, amb, traces);
+}
+
+/* new light sample: position uniform on the rectangle, direction cosine-    */
+/* weighted about the light normal, both from one Philox draw (tag 0)        */
+void or_light_sample(const float* xf, const float* half, uint64_t seed, uint64_t path,
+                     uint64_t frame, double x0[3], double w[3]) {
+  double u[4], c[3], eu[3], ev[3], n[3], l[3];
+  draw4(seed, path, frame, 0, 0, u);
+  light_frame(xf, c, eu, ev, n);
+  double a = (2.0 * u[0] - 1.0) * half[0], b = (2.0 * u[1] - 1.0) * half[1];
+  for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * ev[i];
+  or_cosine_local(u[2], u[3], l);
+  for (int i = 0; i < 3; ++i) w[i] = l[0] * eu[i] + l[1] * ev[i] + l[2] * n[i];
+}
+
+/* Section 3.3 energy test, Equation 2, per channel, inclusive, evaluated in */
+/* FP32 (the precision of the stored energies).                              */
+int or_eq2(const float en[3], const float eo[3], float T) {
+  for (int c = 0; c < 3; ++c) {
+    volatile float d = en[c] - eo[c];
+    volatile float te = T * eo[c];
+    volatile float mte = -te;
+    if (!(mte <= d && d <= te)) return 0;
+  }
+  return 1;
+}
+
+static void retrace_path(rctx* c, int64_t p, uint32_t* amb, int* traces) {
+  const or_scene* s = c->s;
+  or_store* st = c->st;
+  uint32_t w = st->info[p];
+  uint32_t n = info_nseg(w), k = info_start(w), cell = info_cell(w);
+  int newn;
+  *traces = 0;
+  if (!info_replace(w)) return;
+  if (k == 0 && !info_reuse(w)) {
+    int l = light_of(s, p);
+    double x0[3], w0[3];
+    or_light_sample(s->light_xf + 12 * l, s->light_half + 2 * l, c->seed, (uint64_t)p, c->frame, x0,
+                    w0);
+    store3f(st->origin + 3 * p, x0);
+    double x0f[3];
+    vtx(st, p, 0, x0f);
+    newn = naive_from(c, p, 0, x0f, w0, amb, traces);
+  } else if (c->T < 0.0f) {
+    double xa[3], xb[3], d[3];
+    vtx(st, p, (int)k, xa);
+    vtx(st, p, (int)k + 1, xb);
+    sub3(xb, xa, d);
+    double L = norm3(d);
+    for (int i = 0; i < 3; ++i) d[i] /= L;
+    newn = naive_from(c, p, (int)k, xa, d, amb, traces);
+  } else {
+    /* Algorithm 1 with the readings: trace iff blocked, origin moved, or end
+       photon on a moved object; after an accepted re-hit that lands within
+       eps_close of the old vertex, the following segment is kept without a
+       trace when it is itself clear */
+    int j = (int)k, need = 1;
+    newn = (int)n;
+    while (j < newn) {
+      double xa[3], xb[3];
+      vtx(st, p, j, xa);
+      vtx(st, p, j + 1, xb);
+      if (!need) {
+        int inv = hit_on_moved(s, vhit(st, p, j + 1));
+        if (!inv) inv = seg_blocked_moved(c->A, xa, xb, s->band_trace, amb);
+        if (!inv) { ++j; continue; }
+      }
+      double d[3];
+      sub3(xb, xa, d);
+      double L = norm3(d);
+      for (int i = 0; i < 3; ++i) d[i] /= L;
+      hit_t h = closest_hit(c->A, xa, d, s->band_trace, amb);
+      ++*traces;
+      if (h.tri < 0) { newn = j; break; }
+      double hp[3];
+      for (int i = 0; i < 3; ++i) hp[i] = xa[i] + h.t * d[i];
+      if (j == newn - 1) {
+        float e[3];
+        energy_row(st, p, j, e);
+        put_photon(st, p, j, hp, (uint32_t)h.tri, e, s->radius);
+        break;
+      }
+      /* energy reflected at the new hit towards the old next photon */
+      double xc[3], d2[3], nh[3];
+      vtx(st, p, j + 2, xc);
+      sub3(xc, hp, d2);
+      tri_normal(s, h.tri, nh);
+      double c1 = dot3(d, nh), l2 = norm3(d2);
+      double c2 = l2 > 0 ? dot3(d2, nh) / l2 : 0.0;
+      if (fabs(c1) <= s->band_trace || fabs(c2) <= s->band_trace) *amb |= OR_AMB_HEMI;
+      float ein[3], en[3], eo[3];
+      energy_row(st, p, j, ein);
+      energy_row(st, p, j + 1, eo);
+      if (c1 * c2 < 0.0)
+        reflect(s, ein, (uint32_t)h.tri, en);
+      else
+        en[0] = en[1] = en[2] = 0.0f;
+      if (!or_eq2(en, eo, c->T)) {
+        /* energies differ: keep the new hit and resample from it */
+        float ej[3];
+        energy_row(st, p, j, ej);
+        put_photon(st, p, j, hp, (uint32_t)h.tri, ej, s->radius);
+        newn = naive_tail(c, p, j, hp, d, (uint32_t)h.tri, ej, amb, traces);
+        break;
+      }
+      double dd[3];
+      sub3(hp, xb, dd);
+      double dist = norm3(dd);
+      if (fabs(dist - s->eps_close) <= s->band_trace) *amb |= OR_AMB_CLOSE;
+      uint32_t old_hit = vhit(st, p, j + 1);
+      if (dist <= s->eps_close && !hit_on_moved(s, (uint32_t)h.tri) && !hit_on_moved(s, old_hit) &&
+          !hit_on_moved(s, vhit(st, p, j + 2)) &&
+          !seg_blocked_moved(c->A, xb, xc, s->band_trace, amb)) {
+        j += 2;
+        need = 0;
+        continue;
+      }
+      float ej[3];
+      energy_row(st, p, j, ej);
+      put_photon(st, p, j, hp, (uint32_t)h.tri, ej, s->radius);
+      ++j;
+      need = 1;
+    }
+  }
+  clear_rows(st, p, newn);
+  st->info[p] = info_make(cell, (uint32_t)newn, 0, 0, 0);
+}
+
+/* Re-trace every path whose replace bit is set (store updated in place).    */
+/* T < 0: naive re-tracing from the first invalid segment (Section 3.2);     */
+/* T >= 0: the error-based walk (Section 3.3, Algorithm 1, Equation 2).      */
+void or_retrace(const or_scene* s, or_store* st, float T, uint64_t seed, uint64_t frame,
+                uint32_t* amb, int32_t* traces) {
+  accel_t A;
+  accel_build(&A, s);
+  rctx c = {s, &A, st, seed, frame, T};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t p = 0; p < st->n_paths; ++p) {
+    uint32_t a = 0;
+    int tr = 0;
+    retrace_path(&c, p, &a, &tr);
+    amb[p] = a;
+    traces[p] = tr;
+  }
+  accel_free(&A);
+}
+
+/* Re-trace only the listed paths (a sample), same semantics. */
+void or_retrace_list(const or_scene* s, or_store* st, float T, uint64_t seed, uint64_t frame,
+                     const int64_t* list, int64_t n_list, uint32_t* amb, int32_t* traces) {
+  accel_t A;
+  accel_build(&A, s);
+  rctx c = {s, &A, st, seed, frame, T};
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n_list; ++i) {
+    uint32_t a = 0;
+    int tr = 0;
+    retrace_path(&c, list[i], &a, &tr);
+    amb[i] = a;
+    traces[i] = tr;
+  }
+  accel_free(&A);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Differentiation form: deposited energy of every photon recomputed from    */
+/* the materials along its path, E_{p,j} = (Phi_l / N_l) prod_{i<j} rho(x_i), */
+/* and its gradients with respect to albedo and light power, FP64.           */
+
+void or_energy_forward(const or_scene* s, int64_t N, int32_t B, const uint32_t* hit,
+                       const uint32_t* info, const double* albedo, const double* power,
+                       double* E /* [B][N][3] */) {
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < N; ++p) {
+    int l = light_of(s, p);
+    double Nl = (double)(s->light_base[l + 1] - s->light_base[l]);
+    uint32_t n = info_nseg(info[p]);
+    double e[3];
+    for (int c = 0; c < 3; ++c) e[c] = power[3 * l + c] / Nl;
+    for (int r = 0; r < B; ++r) {
+      int64_t i = (int64_t)r * N + p;
+      if ((uint32_t)r < n) {
+        if (r > 0) {
+          uint32_t m = s->tri_mat[hit[(int64_t)(r - 1) * N + p]];
+          for (int c = 0; c < 3; ++c) e[c] *= albedo[3 * m + c];
+        }
+        for (int c = 0; c < 3; ++c) E[3 * i + c] = e[c];
+      } else {
+        for (int c = 0; c < 3; ++c) E[3 * i + c] = 0.0;
+      }
+    }
+  }
+}
+
+/* L = sum g . E; dL/drho_{m,c} = sum over photons j and vertices i<j with    */
+/* material m of g_{j,c} E_{j,c} / rho_{m,c}; dL/dPhi_{l,c} = sum g E / Phi.  */
+/* Written with the division so that it is the plain derivative of the       */
+/* product; requires rho, Phi > 0.  Serial accumulation in FP64.             */
+void or_energy_backward(const or_scene* s, int64_t N, int32_t B, const uint32_t* hit,
+                        const uint32_t* info, const double* albedo, const double* power,
+                        const double* gE, int32_t n_mat, double* g_albedo, double* g_power) {
+  double* E = (double*)malloc(sizeof(double) * 3 * (size_t)N * (size_t)B);
+  or_energy_forward(s, N, B, hit, info, albedo, power, E);
+  memset(g_albedo, 0, sizeof(double) * 3 * (size_t)n_mat);
+  memset(g_power, 0, sizeof(double) * 3 * (size_t)s->n_lights);
+  for (int64_t p = 0; p < N; ++p) {
+    int l = light_of(s, p);
+    uint32_t n = info_nseg(info[p]);
+    for (uint32_t j = 0; j < n; ++j) {
+      int64_t ij = (int64_t)j * N + p;
+      for (int c = 0; c < 3; ++c) {
+        double ge = gE[3 * ij + c] * E[3 * ij + c];
+        g_power[3 * l + c] += ge / power[3 * l + c];
+        for (uint32_t i = 1; i <= j; ++i) {
+          uint32_t m = s->tri_mat[hit[(int64_t)(i - 1) * N + p]];
+          g_albedo[3 * m + c] += ge / albedo[3 * m + c];
+        }
+      }
+    }
+  }
+  free(E);
+}

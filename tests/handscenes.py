@@ -1,0 +1,76 @@
+"""Hand-built scenes for the oracle pins (plain data, no method arithmetic)."""
+import numpy as np
+
+import oracle as O
+
+# open box [0,1]^3 in the triangle order of the tiny configuration:
+# floor 0-1, ceiling 2-3, left 4-5, right 6-7, back 8-9
+BOX = np.array([
+    [[0, 0, 0], [1, 0, 0], [1, 0, 1]], [[0, 0, 0], [1, 0, 1], [0, 0, 1]],
+    [[0, 1, 0], [0, 1, 1], [1, 1, 1]], [[0, 1, 0], [1, 1, 1], [1, 1, 0]],
+    [[0, 0, 0], [0, 0, 1], [0, 1, 1]], [[0, 0, 0], [0, 1, 1], [0, 1, 0]],
+    [[1, 0, 0], [1, 1, 0], [1, 1, 1]], [[1, 0, 0], [1, 1, 1], [1, 0, 1]],
+    [[0, 0, 0], [0, 1, 0], [1, 1, 0]], [[0, 0, 0], [1, 1, 0], [1, 0, 0]],
+], np.float32)
+
+
+def cube_tris(center, side):
+    c = np.asarray(center, np.float64)
+    h = side / 2.0
+    lo, hi = c - h, c + h
+    x0, y0, z0 = lo
+    x1, y1, z1 = hi
+    P = lambda x, y, z: [x, y, z]
+    q = [
+        (P(x0, y0, z0), P(x1, y0, z0), P(x1, y0, z1), P(x0, y0, z1)),
+        (P(x0, y1, z0), P(x0, y1, z1), P(x1, y1, z1), P(x1, y1, z0)),
+        (P(x0, y0, z0), P(x0, y1, z0), P(x1, y1, z0), P(x1, y0, z0)),
+        (P(x0, y0, z1), P(x1, y0, z1), P(x1, y1, z1), P(x0, y1, z1)),
+        (P(x0, y0, z0), P(x0, y0, z1), P(x0, y1, z1), P(x0, y1, z0)),
+        (P(x1, y0, z0), P(x1, y1, z0), P(x1, y1, z1), P(x1, y0, z1)),
+    ]
+    tris = []
+    for a, b, c_, d in q:
+        tris += [(a, b, c_), (a, c_, d)]
+    return np.asarray(tris, np.float32)
+
+
+# light 0.2 x 0.2 just under the ceiling, facing -y
+LIGHT_DOWN = np.array([1, 0, 0, 0.5, 0, 0, -1, 0.999, 0, 1, 0, 0.5], np.float32)
+
+
+def box_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_paths=1, light_moved=False,
+              light_xf=LIGHT_DOWN):
+    """Box plus optional cube blockers (each its own object), as a FrameScene."""
+    tris = [BOX]
+    obj = [np.zeros(10, np.uint32)]
+    mat = [np.zeros(10, np.uint32)]
+    for i, (center, side) in enumerate(blockers):
+        t = cube_tris(center, side)
+        tris.append(t)
+        obj.append(np.full(12, i + 1, np.uint32))
+        mat.append(np.ones(12, np.uint32))
+    verts = np.concatenate(tris).reshape(-1, 9)
+    return O.FrameScene(
+        verts=verts, tri_obj=np.concatenate(obj), tri_mat=np.concatenate(mat),
+        obj_moved=np.array([0] + [1 if moved else 0] * len(blockers), np.uint8),
+        albedo=np.array([[albedo_box] * 3, [albedo_blocker] * 3], np.float32),
+        light_xf=np.asarray(light_xf, np.float32)[None], light_half=np.array([[0.1, 0.1]], np.float32),
+        light_power=np.ones((1, 3), np.float32), light_moved=np.array([1 if light_moved else 0], np.uint8),
+        light_base=np.array([0, n_paths], np.int64))
+
+
+def store_from_paths(paths, B):
+    """paths: list of (origin, [(pos, hit_tri), ...]) -> oracle Store with energies 1/N * 0.7^j."""
+    N = len(paths)
+    st = O.Store.empty(N, B)
+    for p, (orig, photons) in enumerate(paths):
+        st.origin[p] = orig
+        e = np.float32(1.0) / np.float32(N)
+        for r, (pos, hit) in enumerate(photons):
+            st.pos[r, p] = pos
+            st.hit[r, p] = hit
+            st.energy[r, p] = e
+            e = np.float32(e * np.float32(0.7))
+        st.info[p] = O.info_make(0, len(photons), 0, 0, 0)
+    return st

@@ -1,0 +1,548 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test ties one oracle function to a value fixed by the paper, a closed
+form, exact arithmetic, brute force on a tiny input or a library routine, so
+that a dropped term, a wrong sign or a swapped index in the oracle fails here.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_06906_amd import scenes
+from tests import handscenes as H
+
+# ---------------------------------------------------------------------------
+# random numbers: Philox4x64-10 against numpy's independent implementation
+
+
+def test_philox_matches_numpy():
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        key = rng.integers(0, 2**63, 2, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, 2, dtype=np.uint64)
+        ctr = rng.integers(0, 2**63, 4, dtype=np.uint64)
+        ctr[0] = ctr[0] | np.uint64(1)  # numpy advances the counter before drawing
+        bg = np.random.Philox(key=key, counter=ctr - np.array([1, 0, 0, 0], np.uint64))
+        ref = bg.random_raw(4)
+        assert np.array_equal(O.philox4x64(ctr, key), ref)
+
+
+def test_philox_counter_sensitivity():
+    base = O.philox4x64([1, 2, 3, 4], [5, 0])
+    for i in range(4):
+        c = [1, 2, 3, 4]
+        c[i] += 1
+        assert not np.array_equal(O.philox4x64(c, [5, 0]), base)
+    assert not np.array_equal(O.philox4x64([1, 2, 3, 4], [6, 0]), base)
+
+
+# ---------------------------------------------------------------------------
+# rigid transform of dynamic vertices
+
+
+def _exact_world(m, p):
+    return [Fraction(float(m[4 * r])) * Fraction(float(p[0])) + Fraction(float(m[4 * r + 1])) * Fraction(float(p[1]))
+            + Fraction(float(m[4 * r + 2])) * Fraction(float(p[2])) + Fraction(float(m[4 * r + 3])) for r in range(3)]
+
+
+def test_transform_identity_and_dyadic():
+    rng = np.random.default_rng(1)
+    v = rng.uniform(-1, 1, (100, 3)).astype(np.float32)
+    I = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], np.float32)
+    assert np.array_equal(O.transform(v, I), v)
+    # 90 degree rotation about y plus dyadic translation: exact
+    R = np.array([0, 0, 1, 0.25, 0, 1, 0, -0.5, -1, 0, 0, 0.125], np.float32)
+    w = O.transform(v, R)
+    exp = np.stack([v[:, 2] + np.float32(0.25), v[:, 1] - np.float32(0.5), -v[:, 0] + np.float32(0.125)], 1)
+    # sums of a dyadic and a float32 may round; compare against exact rationals
+    for i in range(20):
+        ex = _exact_world(R, v[i])
+        for r in range(3):
+            assert abs(Fraction(float(w[i, r])) - ex[r]) <= Fraction(float(np.spacing(np.float32(abs(float(ex[r])))))) / 2
+    assert np.max(np.abs(w - exp)) < 1e-6
+
+
+def test_transform_within_one_ulp_of_exact():
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        m = rng.uniform(-2, 2, 12).astype(np.float32)
+        p = rng.uniform(-1, 1, 3).astype(np.float32)
+        w = O.transform(p[None], m)[0]
+        ex = _exact_world(m, p)
+        for r in range(3):
+            ulp = Fraction(float(np.spacing(np.float32(abs(float(ex[r]))))))
+            assert abs(Fraction(float(w[r])) - ex[r]) <= ulp
+
+
+def test_moved_is_bitwise():
+    a = np.arange(12, dtype=np.float32)
+    b = a.copy()
+    assert not O.xf_moved(a, b)
+    b[5] = np.nextafter(b[5], np.float32(100))
+    assert O.xf_moved(a, b)
+    c = a.copy()
+    c[0] = -0.0  # +0 vs -0 differ bitwise
+    assert O.xf_moved(a, c)
+
+
+# ---------------------------------------------------------------------------
+# segment / triangle predicates against exact integer orientation tests
+
+
+def _orient(a, b, c, d):
+    m = [[b[i] - a[i] for i in range(3)], [c[i] - a[i] for i in range(3)], [d[i] - a[i] for i in range(3)]]
+    return (m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
+            + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
+
+
+def test_segment_triangle_vs_exact_orientation():
+    rng = np.random.default_rng(3)
+    n_checked = n_hit = 0
+    for _ in range(4000):
+        P = [tuple(int(x) for x in rng.integers(-20, 21, 3)) for _ in range(5)]
+        a, b, v0, v1, v2 = P
+        oa, ob = _orient(v0, v1, v2, a), _orient(v0, v1, v2, b)
+        e = [_orient(a, b, v0, v1), _orient(a, b, v1, v2), _orient(a, b, v2, v0)]
+        if oa == 0 or ob == 0 or 0 in e:
+            continue  # degenerate: excluded from the exact comparison
+        exact = (oa > 0) != (ob > 0) and (all(x > 0 for x in e) or all(x < 0 for x in e))
+        got = O.segment_blocked_tri(np.array(a, float), np.array(b, float),
+                                    np.array([v0, v1, v2], float).reshape(9), 0.0)
+        assert got == exact
+        n_checked += 1
+        n_hit += exact
+    assert n_checked > 2000 and n_hit > 50
+
+
+def test_segment_eps_end_interval():
+    tri = np.array([[0, -1, -1], [0, 1, -1], [0, 0, 2]], float).reshape(9)
+    # crossing at distance 0.3 from a along a unit-length segment
+    a, b = np.array([-0.3, 0, 0]), np.array([0.7, 0, 0])
+    assert O.segment_blocked_tri(a, b, tri, 0.1)
+    assert not O.segment_blocked_tri(a, b, tri, 0.35)    # crossing inside eps of the start
+    a2, b2 = np.array([-0.95, 0, 0]), np.array([0.05, 0, 0])
+    assert not O.segment_blocked_tri(a2, b2, tri, 0.1)   # crossing within eps of the end
+
+
+def test_segseg_distance_closed_forms():
+    d = O.segseg_dist([0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0])
+    assert d == pytest.approx(1.0)                       # parallel, offset 1
+    assert O.segseg_dist([0, 0, 0], [2, 0, 0], [1, -1, 0], [1, 1, 0]) == pytest.approx(0.0)  # crossing
+    assert O.segseg_dist([0, 0, 0], [1, 0, 0], [0.5, -1, 2], [0.5, 1, 2]) == pytest.approx(2.0)  # skew
+    assert O.segseg_dist([0, 0, 0], [1, 0, 0], [3, 0, 0], [4, 0, 0]) == pytest.approx(2.0)  # collinear gap
+    # brute force on random segments
+    rng = np.random.default_rng(4)
+    s = np.linspace(0, 1, 201)
+    for _ in range(30):
+        p0, p1, q0, q1 = rng.uniform(-1, 1, (4, 3))
+        P = p0 + s[:, None] * (p1 - p0)
+        Q = q0 + s[:, None] * (q1 - q0)
+        brute = np.min(np.linalg.norm(P[:, None] - Q[None], axis=2))
+        d = O.segseg_dist(p0, p1, q0, q1)
+        assert d <= brute + 1e-12 and brute - d < 0.02
+
+
+# ---------------------------------------------------------------------------
+# verification hand cases (Sections 3.1, 3.2)
+
+
+def _worked_path():
+    # light origin -> floor -> right wall -> left wall
+    return ([0.5, 0.999, 0.5], [([0.5, 0, 0.5], 0), ([1, 0.5, 0.5], 7), ([0, 0.5, 0.25], 4)])
+
+
+def test_worked_case_blocker_on_second_segment():
+    # blocker of side 0.1 near (0.75, 0.25, 0.5), shifted 0.01 along x so that segment 1
+    # enters and leaves through face interiors
+    fs = H.box_scene(blockers=[((0.76, 0.25, 0.5), 0.1)])
+    st = H.store_from_paths([_worked_path()], 3)
+    amb, ex = O.verify(fs, st)
+    f = O.info_fields(st.info)
+    assert (f["replace"][0], f["start"][0], f["reuse"][0], f["nseg"][0]) == (1, 1, 1, 3)
+    assert amb[0] == 0 and ex[0] == 2
+
+
+def test_worked_case_through_cube_edges_is_ambiguous():
+    # centred exactly at (0.75, 0.25, 0.5) the segment crosses the cube surface only on
+    # two of its edges: the decision is within the edge band and must be flagged
+    fs = H.box_scene(blockers=[((0.75, 0.25, 0.5), 0.1)])
+    st = H.store_from_paths([_worked_path()], 3)
+    amb, ex = O.verify(fs, st)
+    assert amb[0] & O.AMB_EDGE
+    assert O.info_fields(st.info)["start"][0] == 1
+
+
+@pytest.mark.parametrize("j", [0, 1, 2])
+def test_blocker_on_known_segment_invalidates_exactly_it(j):
+    orig, photons = _worked_path()
+    pts = [np.array(orig, float)] + [np.array(p, float) for p, _ in photons]
+    # small generic offset so that the crossing avoids the cube's face diagonals
+    mid = 0.5 * (pts[j] + pts[j + 1]) + np.array([0.0031, 0.0017, -0.0043])
+    fs = H.box_scene(blockers=[(tuple(mid), 0.04)])
+    st = H.store_from_paths([(orig, photons)], 3)
+    amb, ex = O.verify(fs, st)
+    f = O.info_fields(st.info)
+    assert f["replace"][0] == 1 and f["start"][0] == j and amb[0] == 0 and ex[0] == j + 1
+
+
+def test_unmoved_blocker_is_not_tested():
+    fs = H.box_scene(blockers=[((0.75, 0.25, 0.5), 0.1)], moved=False)
+    st = H.store_from_paths([_worked_path()], 3)
+    O.verify(fs, st)
+    assert O.info_fields(st.info)["replace"][0] == 0
+
+
+def test_photon_on_moved_object_invalidates_its_segment():
+    orig, photons = _worked_path()
+    photons = list(photons)
+    photons[1] = (photons[1][0], 10)   # second photon recorded on the (moved) cube
+    fs = H.box_scene(blockers=[((0.2, 0.8, 0.8), 0.05)])  # far from every segment
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    f = O.info_fields(st.info)
+    assert f["replace"][0] == 1 and f["start"][0] == 1
+
+
+def test_static_scene_reuses_every_path():
+    sc = scenes.make_tiny(n_paths=4096)
+    fs0 = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    st2 = st.copy()
+    O.verify(O.frame_scene(sc, 0, 0), st2)
+    assert O.info_fields(st2.info)["replace"].sum() == 0
+    assert np.array_equal(st2.pos, st.pos) and np.array_equal(st2.origin, st.origin)
+
+
+def test_segment_near_edge_is_flagged():
+    # segment passing within 1e-7 of a cube edge
+    fs = H.box_scene(blockers=[((0.5, 0.5, 0.5), 0.2)])
+    a = np.array([0.1, 0.6 + 1e-7, 0.4 - 0.3])
+    b = np.array([0.9, 0.6 + 1e-7, 0.4 - 0.3])
+    blocked, amb = O.segment_query(fs, a, b)
+    assert not blocked
+    a2 = np.array([0.1, 0.6 - 1e-7, 0.4]); b2 = np.array([0.9, 0.6 - 1e-7, 0.4])  # grazes the top face edge
+    blocked2, amb2 = O.segment_query(fs, a2, b2)
+    assert amb2 & O.AMB_EDGE
+
+
+# ---------------------------------------------------------------------------
+# light origin update closed forms (Section 3.1)
+
+
+def test_light_update_in_plane_translation():
+    x0 = np.array([0.52, 0.999, 0.47])
+    x1 = np.array([0.3, 0.0, 0.8])
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(0.03)  # translate along local u (world x)
+    ok, nx, amb = O.light_update(xf, [0.1, 0.1], x0, x1)
+    assert ok and amb == 0
+    np.testing.assert_allclose(nx, x0, atol=1e-12)      # same plane: same world origin
+    xf2 = H.LIGHT_DOWN.copy()
+    xf2[3] += np.float32(0.2)                           # now outside the rectangle
+    ok2, _, _ = O.light_update(xf2, [0.1, 0.1], x0, x1)
+    assert not ok2
+
+
+def test_light_update_normal_shift():
+    x0 = np.array([0.52, 0.999, 0.47])
+    x1 = np.array([0.3, 0.0, 0.8])
+    w = (x1 - x0) / np.linalg.norm(x1 - x0)
+    delta = 0.01
+    xf = H.LIGHT_DOWN.copy()
+    xf[7] = np.float32(0.999 - delta)                   # plane moved by delta along the normal (-y)
+    ok, nx, _ = O.light_update(xf, [0.1, 0.1], x0, x1)
+    n = np.array([0.0, -1.0, 0.0])
+    expect = x0 + (delta / np.dot(w, n)) * w
+    # the stored light centre is FP32; compare with the FP32 plane height
+    expect = x0 + ((0.999 - float(xf[7])) / np.dot(w, n)) * w
+    assert ok
+    np.testing.assert_allclose(nx, expect, atol=1e-12)
+
+
+def test_light_update_rotation_behind_plane_is_invalid():
+    x0 = np.array([0.5, 0.999, 0.5])
+    x1 = np.array([0.9, 0.95, 0.5])                     # grazing direction (mostly +x)
+    ang = math.radians(-20)                             # tilt the light about z so its normal turns towards -x
+    R = np.array([[math.cos(ang), -math.sin(ang), 0], [math.sin(ang), math.cos(ang), 0], [0, 0, 1]]) @ \
+        np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]])
+    xf = np.zeros((3, 4))
+    xf[:, :3] = R
+    xf[:, 3] = [0.5, 0.999, 0.5]
+    ok, _, _ = O.light_update(xf.astype(np.float32).reshape(12), [0.1, 0.1], x0, x1)
+    n = R[:, 2]
+    assert np.dot((x1 - x0) / np.linalg.norm(x1 - x0), n) < 0
+    assert not ok
+
+
+# ---------------------------------------------------------------------------
+# closest hit (re-tracing) against analytic box hits
+
+
+def test_closest_hit_box_walls():
+    fs = H.box_scene()
+    tri, t, amb = O.closest_query(fs, [0.5, 0.3, 0.6], [1, 0, 0])
+    assert tri == 7 and t == pytest.approx(0.5, abs=1e-15) and amb == 0
+    tri, t, amb = O.closest_query(fs, [0.5, 0.3, 0.6], [0, 0, -1])
+    assert tri in (8, 9) and t == pytest.approx(0.6, abs=1e-15)
+    tri, t, amb = O.closest_query(fs, [0.5, 0.3, 0.6], [0, 0, 1])
+    assert tri == -1                                     # open front: escapes
+    w = np.array([1.0, 0.5, 0.0]) / math.hypot(1.0, 0.5)
+    tri, t, _ = O.closest_query(fs, [0.5, 0.5, 0.3], w)
+    assert tri in (6, 7) and t == pytest.approx(0.5 * math.hypot(1.0, 0.5), abs=1e-12)
+    w = np.array([1.0, 1.0, 0.0]) / math.sqrt(2)          # straight into the right/ceiling edge
+    _, _, amb = O.closest_query(fs, [0.5, 0.5, 0.3], w)
+    assert amb & O.AMB_EDGE
+
+
+def test_closest_hit_prefers_nearer_blocker():
+    fs = H.box_scene(blockers=[((0.8, 0.3, 0.6), 0.1)])
+    tri, t, _ = O.closest_query(fs, [0.5, 0.3, 0.6], [1, 0, 0])
+    assert 10 <= tri < 22 and t == pytest.approx(0.25, abs=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# sampling: concentric map and tangent frame
+
+
+def test_concentric_map_points_and_frame():
+    np.testing.assert_allclose(O.cosine_local(0.5, 0.5), [0, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(O.cosine_local(1.0, 0.5), [1, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(O.cosine_local(0.5, 1.0), [0, 1, 0], atol=1e-15)
+    np.testing.assert_allclose(O.cosine_local(0.0, 0.5), [-1, 0, 0], atol=1e-15)
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        t, b = O.onb(n)
+        M = np.stack([t, b, n])
+        np.testing.assert_allclose(M @ M.T, np.eye(3), atol=1e-12)
+        assert np.linalg.det(M) == pytest.approx(1.0, abs=1e-12)
+
+
+def test_cosine_moments():
+    rng = np.random.default_rng(6)
+    n = np.array([0.3, -0.5, 0.8])
+    n /= np.linalg.norm(n)
+    u = rng.random((40000, 2))
+    d = np.array([O.cosine_dir(a, b, n) for a, b in u])
+    np.testing.assert_allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-12)
+    c = d @ n
+    assert c.min() >= 0
+    # cosine-weighted density cos/pi: E[cos] = 2/3, E[cos^2] = 1/2, mean direction (2/3) n
+    assert c.mean() == pytest.approx(2 / 3, abs=0.005)
+    assert (c ** 2).mean() == pytest.approx(0.5, abs=0.005)
+    np.testing.assert_allclose(d.mean(0), (2 / 3) * n, atol=0.008)
+
+
+def test_light_sample_on_rectangle_and_hemisphere():
+    xs, ws = [], []
+    for p in range(2000):
+        x0, w = O.light_sample(H.LIGHT_DOWN, [0.1, 0.1], 11, p, 0)
+        xs.append(x0)
+        ws.append(w)
+    xs, ws = np.array(xs), np.array(ws)
+    assert np.all(np.abs(xs[:, 0] - 0.5) <= 0.1 + 1e-7) and np.all(np.abs(xs[:, 2] - 0.5) <= 0.1 + 1e-7)
+    np.testing.assert_allclose(xs[:, 1], 0.999, atol=1e-7)
+    assert np.all(ws[:, 1] <= 0) and (-ws[:, 1]).mean() == pytest.approx(2 / 3, abs=0.02)
+
+
+# ---------------------------------------------------------------------------
+# Equation 2 closed form (inclusive, per channel)
+
+
+def test_eq2_boundaries():
+    one = np.ones(3, np.float32)
+    assert O.eq2(one * np.float32(1.5), one, 0.5)
+    assert O.eq2(one * np.float32(0.5), one, 0.5)
+    assert not O.eq2(one * np.nextafter(np.float32(1.5), np.float32(2)), one, 0.5)
+    # 0.5 - 2^-25 differs from 1 by a tie of FP32 spacing that rounds to exactly -0.5
+    # (the test is evaluated in FP32): accepted; 0.5 - 2^-23 is not
+    assert O.eq2(one * np.float32(0.5 - 2.0 ** -25), one, 0.5)
+    assert not O.eq2(one * np.float32(0.5 - 2.0 ** -23), one, 0.5)
+    assert O.eq2(one, one, 0.0) and not O.eq2(one * np.float32(1.0000001), one, 0.0)
+    assert not O.eq2(one, one, -1.0)                     # T < 0 never accepts
+    mixed = np.array([1.0, 1.0, 1.2], np.float32)
+    assert not O.eq2(mixed, one, 0.1)                    # every channel must pass
+
+
+# ---------------------------------------------------------------------------
+# energies: analytic albedo product (closed form) and conservation
+
+
+def test_energies_are_albedo_products():
+    sc = scenes.make_tiny()
+    fs0 = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    n = O.info_fields(st.info)["nseg"]
+    # the paper's photon power: E_1 = Phi / N = 1 / 16384
+    assert np.all(st.energy[0, n >= 1] == np.float32(1.0 / 16384))
+    tri_mat = fs0.tri_mat
+    for p in range(0, sc.n_paths, 97):
+        e = 1.0 / 16384
+        for r in range(int(n[p])):
+            assert st.energy[r, p, 0] == pytest.approx(e, rel=1e-6)
+            e *= float(sc.albedo[tri_mat[st.hit[r, p]], 0])
+    # on walls only (albedo 0.7) the second and third photons carry 0.7 and 0.49 of E_1
+    walls = (n == 3) & np.all(st.hit[:3] < 10, axis=0)
+    assert walls.sum() > 100
+    np.testing.assert_allclose(st.energy[1, walls, 0], 0.7 / 16384, rtol=1e-6)
+    np.testing.assert_allclose(st.energy[2, walls, 0], 0.49 / 16384, rtol=1e-6)
+
+
+def test_initial_trace_photons_lie_on_their_triangles():
+    sc = scenes.make_tiny(n_paths=2048)
+    fs0 = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    n = O.info_fields(st.info)["nseg"]
+    V = fs0.verts.reshape(-1, 3, 3).astype(np.float64)
+    for r in range(sc.max_bounces):
+        idx = np.flatnonzero(n > r)
+        tri = V[st.hit[r, idx]]
+        p = st.pos[r, idx].astype(np.float64)
+        nrm = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+        nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+        dist = np.abs(np.einsum("ij,ij->i", p - tri[:, 0], nrm))
+        assert dist.max() < 1e-6
+    # consecutive photons see each other (no triangle strictly between them)
+    assert np.all(st.hit[:, n == 0] == O.HIT_NONE)
+
+
+# ---------------------------------------------------------------------------
+# re-tracing: naive and error-based invariants, Figure 1 scenarios
+
+
+def _frame_pair(n_paths=4096, T=-1.0):
+    sc = scenes.make_tiny(n_paths=n_paths)
+    fs0 = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    fs1 = O.frame_scene(sc, 1, 0)
+    O.verify(fs1, st)
+    return sc, fs1, st
+
+
+def test_retrace_never_traces_more_than_full_invalidation():
+    sc, fs1, st = _frame_pair()
+    k = O.info_fields(st.info)["start"].astype(int)
+    rep = O.info_fields(st.info)["replace"].astype(bool)
+    for T in (-1.0, 0.0, 0.01, 0.5):
+        s2 = st.copy()
+        _, tr = O.retrace(fs1, s2, T, sc.seed, 1)
+        assert np.all(tr[rep] <= sc.max_bounces - k[rep])
+        assert np.all(tr[~rep] == 0)
+
+
+def test_retrace_result_is_valid_at_new_frame():
+    sc, fs1, st = _frame_pair()
+    s2 = st.copy()
+    amb, _ = O.retrace(fs1, s2, -1.0, sc.seed, 1)
+    assert O.info_fields(s2.info)["replace"].sum() == 0
+    s3 = s2.copy()
+    # a second verification against the same frame (nothing moves) keeps every path
+    fs_static = O.frame_scene(sc, 1, 1)
+    O.verify(fs_static, s3)
+    assert O.info_fields(s3.info)["replace"].sum() == 0
+
+
+def test_figure1_last_segment_only_new_hit():
+    # path: light -> floor -> right wall -> back wall; blocker in front of the back wall
+    orig = [0.5, 0.999, 0.5]
+    photons = [([0.5, 0.0, 0.5], 0), ([1.0, 0.4, 0.5], 7), ([0.6, 0.5, 0.0], 8)]
+    fs = H.box_scene(blockers=[((0.7, 0.47, 0.15), 0.1)], albedo_blocker=0.7)
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    f = O.info_fields(st.info)
+    assert f["replace"][0] == 1 and f["start"][0] == 2
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert tr[0] == 1                                   # only the new end point is computed
+    assert np.array_equal(st.pos[:2], before.pos[:2])
+    assert 10 <= st.hit[2, 0] < 22                      # lands on the blocker
+    assert np.array_equal(st.energy, before.energy)     # energies untouched
+    assert O.info_fields(st.info)["nseg"][0] == 3
+
+
+def test_figure1_first_segment_resampled_when_energy_differs():
+    orig = [0.5, 0.999, 0.5]
+    photons = [([0.5, 0.0, 0.5], 0), ([1.0, 0.4, 0.5], 7), ([0.6, 0.5, 0.0], 8)]
+    fs = H.box_scene(blockers=[((0.503, 0.5, 0.498), 0.1)], albedo_blocker=0.3)
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    assert O.info_fields(st.info)["start"][0] == 0
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert 10 <= st.hit[0, 0] < 22                      # new first photon on the blocker
+    assert not np.array_equal(st.pos[1], before.pos[1])  # BRDF resampled from it
+    assert st.energy[1, 0, 0] == np.float32(st.energy[0, 0, 0] * np.float32(0.3))
+
+
+def test_figure1_first_segment_kept_tail_when_energy_close():
+    # blocker with the same albedo as the floor: the new first photon can see the old second one
+    orig = [0.5, 0.999, 0.5]
+    photons = [([0.5, 0.0, 0.5], 0), ([1.0, 0.4, 0.5], 7), ([0.6, 0.5, 0.0], 8)]
+    fs = H.box_scene(blockers=[((0.503, 0.3, 0.498), 0.1)], albedo_blocker=0.7)
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert 10 <= st.hit[0, 0] < 22
+    # x_2 is re-aimed from the new x_1; it lands back on the right wall close to before
+    assert st.hit[1, 0] in (6, 7)
+    assert np.linalg.norm(st.pos[1, 0] - before.pos[1, 0]) < 1e-4
+    assert np.array_equal(st.pos[2], before.pos[2])      # third photon kept as is
+    assert np.array_equal(st.energy, before.energy)
+
+
+# ---------------------------------------------------------------------------
+# queue, compaction: library routines and brute force
+
+
+def test_queue_and_compaction_brute_force():
+    sc, fs1, st = _frame_pair(n_paths=512)
+    q = O.queue(st.info)
+    loop = [p for p in range(st.n_paths) if (int(st.info[p]) >> 30) & 1]
+    assert q.tolist() == loop
+    pos, en = O.compact_photons(st)
+    n = O.info_fields(st.info)["nseg"]
+    ref_p, ref_e = [], []
+    for r in range(st.B):
+        for p in range(st.n_paths):
+            if r < n[p]:
+                ref_p.append(st.pos[r, p])
+                ref_e.append(st.energy[r, p])
+    assert np.array_equal(pos, np.array(ref_p)) and np.array_equal(en, np.array(ref_e))
+
+
+# ---------------------------------------------------------------------------
+# differentiation: central finite differences of the FP64 forward
+
+
+def test_energy_gradient_matches_finite_differences():
+    sc = scenes.make_tiny(n_paths=512)
+    fs0 = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    rng = np.random.default_rng(8)
+    alb = np.array([[0.7, 0.6, 0.5], [0.5, 0.4, 0.3]])
+    pw = np.array([[1.0, 2.0, 0.5]])
+    g = rng.uniform(0, 1, (st.B, st.n_paths, 3))
+    E = O.energy_forward(fs0, st, alb, pw)
+    # forward equals the stored FP32 energies when albedo/power are the scene's own
+    E0 = O.energy_forward(fs0, st, sc.albedo.astype(np.float64), sc.light_power.astype(np.float64))
+    np.testing.assert_allclose(E0, st.energy, rtol=1e-6, atol=0)
+    ga, gp = O.energy_backward(fs0, st, alb, pw, g)
+    h = 1e-3
+    for m in range(2):
+        for c in range(3):
+            a1, a2 = alb.copy(), alb.copy()
+            a1[m, c] += h
+            a2[m, c] -= h
+            fd = (np.sum(g * O.energy_forward(fs0, st, a1, pw)) - np.sum(g * O.energy_forward(fs0, st, a2, pw))) / (2 * h)
+            assert ga[m, c] == pytest.approx(fd, rel=1e-5, abs=1e-12)
+    for c in range(3):
+        p1, p2 = pw.copy(), pw.copy()
+        p1[0, c] += h
+        p2[0, c] -= h
+        fd = (np.sum(g * O.energy_forward(fs0, st, alb, p1)) - np.sum(g * O.energy_forward(fs0, st, alb, p2))) / (2 * h)
+        assert gp[0, c] == pytest.approx(fd, rel=1e-9)
+    assert np.sum(E) > 0
