@@ -1,0 +1,199 @@
+"""Throughput of the photon-path verification hot path on one MI355X.
+
+One step = one frame of the paper-scale workload: new object / light
+transforms, transform + hierarchy refit, origin update + dynamic-occlusion
+verification, work-queue compaction, error-based re-trace (T = 1%) and photon
+compaction.  Inputs are resident in HBM before the timed region.  Prints one
+JSON line (metric: verified path segments per second).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def light_moved(sc, f):
+    import numpy as np
+    a, b = sc.light_xforms[f], sc.light_xforms[f - 1]
+    return [not np.array_equal(a[l].view(np.uint32), b[l].view(np.uint32)) for l in range(a.shape[0])]
+
+
+def cpu_baseline(config_fn, target_s, T):
+    """The oracle (untuned) on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle as O
+    n = 512
+    while True:
+        sc = config_fn(n_paths=n, frames=2)
+        fs0 = O.frame_scene(sc, 0)
+        st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+        fs1 = O.frame_scene(sc, 1, 0)
+        t0 = time.perf_counter()
+        _, ex = O.verify(fs1, st)
+        O.retrace(fs1, st, T, sc.seed, 1)
+        dt = time.perf_counter() - t0
+        log("cpu baseline: %d paths, %.2f s" % (n, dt))
+        if dt >= target_s * 0.5 or n >= 1 << 19:
+            break
+        n = int(min(1 << 19, n * max(2.0, min(16.0, target_s / max(dt, 1e-3)))))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": float(ex.sum()) / dt, "unit": "segments/s", "cores": cores, "kind": "oracle",
+            "sample": "%d paths of the same scene, one frame (verify + error-based re-trace), %.1f s" % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="paper", choices=["tiny", "mid", "paper"])
+    ap.add_argument("--paths", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only; multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2111_06906_amd import engine, scenes
+
+    cfg = {"tiny": scenes.make_tiny, "mid": scenes.make_mid, "paper": scenes.make_paper}[args.config]
+    frames = 1 + args.warmup + args.steps
+    kw = {"frames": max(frames, 2)}
+    if args.paths:
+        kw["n_paths"] = args.paths
+    t0 = time.perf_counter()
+    sc = cfg(**kw)
+    T = sc.threshold if sc.threshold >= 0 else 0.01
+    log("scene %s: %d static + %d dynamic tris, %d paths, B=%d, %d frames (%.1f s)" % (
+        sc.name, sc.n_static, sc.n_dynamic_tris(), sc.n_paths, sc.max_bounces, frames, time.perf_counter() - t0))
+
+    torch.cuda.set_device(0)
+    ctx = engine.Context(sc)
+    st = ctx.new_store()
+    N, B = sc.n_paths, sc.max_bounces
+    cap = N * B
+    out_pos = torch.empty((cap, 3), dtype=torch.float32, device="cuda")
+    out_en = torch.empty((cap, 3), dtype=torch.float32, device="cuda")
+    out_cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.frame_begin(0)
+    ctx.initial_trace(st, sc.seed, 0)
+    torch.cuda.synchronize()
+    log("frame 0 traced")
+
+    def step(f, ev, stats):
+        ev[0].record()
+        ctx.frame_begin(f)
+        ev[1].record()
+        ctx.verify(st, stats, build_queue=False)
+        ev[2].record()
+        ctx.build_queue(st)
+        ev[3].record()
+        ctx.retrace(st, T, sc.seed, f, stats)
+        ev[4].record()
+        ctx.compact_photons_into(st, out_pos, out_en, out_cnt)
+        ev[5].record()
+
+    for f in range(1, 1 + args.warmup):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        step(f, ev, None)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+    stats = [ctx.new_stats() for _ in range(K)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(K):
+        step(1 + args.warmup + i, evs[i], stats[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    names = ["frame_begin", "verify", "queue", "retrace", "compact_photons"]
+    phase = {n: 0.0 for n in names}
+    verify_ms = []
+    seg = 0
+    bytes_verify = 0
+    sd = [ctx.stats_dict(s) for s in stats]
+    for i in range(K):
+        f = 1 + args.warmup + i
+        for j, n in enumerate(names):
+            phase[n] += evs[i][j].elapsed_time(evs[i][j + 1])
+        verify_ms.append(evs[i][1].elapsed_time(evs[i][2]))
+        seg += sd[i]["segments_examined"]
+        moved_paths = sum(int(sc.light_paths[l]) for l, m in enumerate(light_moved(sc, f)) if m)
+        origin_writes = max(0, moved_paths - sd[i]["paths_light_lost"])
+        bytes_verify += 20 * N + 16 * sd[i]["segments_examined"] + 12 * origin_writes
+    tot = {k: sum(s[k] for s in sd) for k in sd[0]}
+    avg_verify_s = sum(verify_ms) / K / 1e3
+    achieved = bytes_verify / K / avg_verify_s / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "verify_traffic.json")
+    if os.path.exists(tf):
+        try:
+            traffic = json.load(open(tf)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    res = {
+        "metric": "verified path segments/s",
+        "value": seg / wall,
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": wall / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d paths x %d bounces, %d static + %d dynamic triangles in %d objects, "
+                               "%d lights (%s), energy threshold %g" % (
+                                   sc.name, N, B, sc.n_static, sc.n_dynamic_tris(), sc.n_dynamic,
+                                   sc.light_half.shape[0], "moving" if sc.meta.get("lights_move") else "static", T),
+                   "paths": N, "max_bounces": B, "frames_timed": K},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": "k_verify",
+                     "algorithmic_bytes_per_launch": bytes_verify / K, "avg_launch_ms": avg_verify_s * 1e3},
+        "phases_ms_per_frame": {k: v / K for k, v in phase.items()},
+        "per_frame": {"segments_examined": tot["segments_examined"] / K, "paths_invalid": tot["paths_invalid"] / K,
+                      "paths_light_lost": tot["paths_light_lost"] / K, "rays_traced": tot["rays_traced"] / K,
+                      "photons_written": tot["photons_written"] / K, "reuse_accepted": tot["reuse_accepted"] / K,
+                      "photons_compacted": int(out_cnt.item())},
+    }
+    log(json.dumps(res["phases_ms_per_frame"]))
+    # the paper's comparator on the same GPU: re-trace every path every frame
+    base_ms = []
+    for i in range(3):
+        f = 1 + args.warmup + (i % K)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.frame_begin(f)
+        e0.record()
+        ctx.queue_all(st)
+        ctx.retrace(st, -1.0, sc.seed, 1000 + i)
+        e1.record()
+        torch.cuda.synchronize()
+        base_ms.append(e0.elapsed_time(e1))
+    res["baseline_retrace_all_ms"] = sum(base_ms) / len(base_ms)
+    ctx.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, T)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * pv.h -- C-ABI of the MI355X photon-path verification library.
+ *
+ * Implements the per-frame hot path of Moreau, Doggett and Sintorn, "Path
+ * Verification for Dynamic Indirect Illumination": photon paths stored by the
+ * previous frame are verified against the current frame's dynamic geometry
+ * and moving area lights, and each invalidated path is re-traced from its
+ * first invalid segment, optionally keeping path tails whose reflected energy
+ * stays within the error threshold of Equation 2.
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are DEVICE pointers (HIP global memory on the
+ *    context's device); h_* are HOST pointers.  Scene data passed at upload is
+ *    copied; the path store and outputs stay caller-owned and must remain
+ *    valid until the context's stream has completed the call.
+ *  - All work is enqueued on the context's stream (the one given to
+ *    pv_create); no call synchronises the stream except pv_upload_scene,
+ *    pv_set_light_paths and pv_reserve.
+ *  - Return value: PV_OK (0) or a negative PV_ERR_* code.  Argument errors are
+ *    detected on the host before anything is enqueued; pv_last_error() then
+ *    describes the problem.  Faults of enqueued work surface as PV_ERR_HIP on
+ *    a later call that synchronises.  No C++ exception crosses this boundary.
+ *  - One context per stream/thread; calls on one context are not thread safe.
+ *  - Verify, queue, re-trace and compaction calls allocate nothing: their
+ *    scratch space is reserved by pv_reserve, so they may be captured in a
+ *    HIP graph.
+ *
+ * Path store (Section 4 of the paper, with the photon position stored in place
+ * of the incoming direction, which is the difference of consecutive
+ * positions): paths are columns, bounce rows are contiguous, so all lanes that
+ * load the i-th photon of their path touch consecutive memory.
+ *   pos_hit [B][stride] float4 {x, y, z, hit}: photon x_{r+1} in row r;
+ *           hit = global triangle id (bit pattern in .w), 0xFFFFFFFF = none
+ *   energy  [B][stride] float4 {r, g, b, radius}: flux arriving at the photon
+ *   origin  [3][stride] float: world-space light sample x_0 (x row, y row, z row)
+ *   info    [stride] uint32 (Section 4 path-information word):
+ *           bits 0..21 distribution-map cell, 22..25 segment count n (0..15),
+ *           26..29 first segment to re-trace, 30 replace, 31 reuse light
+ *   Paths [light_base[l], light_base[l+1]) belong to light l.
+ *
+ * Global triangle ids: static triangles first (0..S-1, upload order), then
+ * each dynamic object's triangles in upload order.
+ */
+#ifndef PV_H
+#define PV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pv_ctx pv_ctx;
+typedef int32_t pv_status;
+
+enum {
+  PV_OK = 0,
+  PV_ERR_ARG = -1,      /* invalid argument (null pointer, size out of range) */
+  PV_ERR_OOM = -2,      /* device allocation failed */
+  PV_ERR_HIP = -3,      /* a HIP runtime call failed */
+  PV_ERR_CAPACITY = -4, /* request exceeds what pv_reserve provided */
+  PV_ERR_STATE = -5     /* call out of order (e.g. verify before upload) */
+};
+
+#define PV_MAX_BOUNCES 15   /* 4-bit segment count of the information word */
+#define PV_MAX_OBJECTS 64   /* dynamic objects per scene */
+#define PV_MAX_LIGHTS 8
+#define PV_HIT_NONE 0xFFFFFFFFu
+
+typedef struct {
+  uint32_t n_paths;       /* columns in use */
+  uint32_t max_bounces;   /* B, rows, 1..PV_MAX_BOUNCES */
+  uint32_t stride;        /* floats4 between rows; >= n_paths, multiple of 64 */
+  void* d_pos_hit;        /* float4 [B][stride] */
+  void* d_energy;         /* float4 [B][stride] */
+  float* d_origin;        /* float  [3][stride] */
+  uint32_t* d_info;       /* uint32 [stride] */
+} pv_path_store;
+
+/* Scene description for pv_upload_scene; every pointer is a HOST pointer and
+ * is copied.  Vertices are float[9] per triangle (v0, v1, v2).  Dynamic
+ * objects are rigid and given in object space; their placement comes from
+ * pv_frame_begin each frame. */
+typedef struct {
+  uint32_t n_static;             /* static triangles */
+  const float* h_static_verts;   /* [n_static][9] world space */
+  const uint32_t* h_static_mat;  /* [n_static] material ids */
+  uint32_t n_objects;            /* dynamic objects, <= PV_MAX_OBJECTS */
+  const uint32_t* h_obj_tris;    /* [n_objects] triangle counts */
+  const float* h_obj_verts;      /* [sum obj_tris][9] object space, objects in order */
+  const uint32_t* h_obj_mat;     /* [sum obj_tris] material ids */
+  uint32_t n_materials;
+  const float* h_albedo;         /* [n_materials][3] diffuse albedo rho */
+  uint32_t n_lights;             /* rectangular area lights, <= PV_MAX_LIGHTS */
+  const float* h_light_half;     /* [n_lights][2] half extents along local u, v */
+  const float* h_light_power;    /* [n_lights][3] radiant power Phi */
+  float eps_end;                 /* segment endpoint tolerance (scene units) */
+  float eps_close;               /* AreClose tolerance of Algorithm 1 (scene units) */
+  float photon_radius;           /* radius written into new photons */
+} pv_scene_desc;
+
+/* Device counters accumulated by the calls that take a pv_stats* (may be
+ * NULL).  Zero them (device memory) before the frame if per-frame values are
+ * wanted. */
+typedef struct {
+  unsigned long long segments_examined;  /* segments tested by verify */
+  unsigned long long paths_invalid;      /* paths given the replace bit */
+  unsigned long long paths_light_lost;   /* of those: origin left the moved light */
+  unsigned long long rays_traced;        /* closest-hit rays of the re-trace */
+  unsigned long long photons_written;    /* photons written by the re-trace */
+  unsigned long long reuse_accepted;     /* Equation 2 acceptances (error-based walk) */
+  unsigned long long paths_truncated;    /* re-traced paths ending on an escaping ray */
+  unsigned long long reserved;
+} pv_stats;
+
+/* --- context ----------------------------------------------------------- */
+
+/* Create a context on the current HIP device; all work goes to 'hip_stream'
+ * (a hipStream_t; NULL = the null stream). */
+pv_status pv_create(pv_ctx** out, void* hip_stream);
+void pv_destroy(pv_ctx* ctx);
+/* Last error message of the context (or of the last failed pv_create when ctx
+ * is NULL).  Valid until the next call on the context. */
+const char* pv_last_error(const pv_ctx* ctx);
+
+/* Copy the scene to the device and build its bounding-volume hierarchies
+ * (static world and one per rigid dynamic object, topology in object space).
+ * Synchronises the stream.  Replaces any previous scene. */
+pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* desc);
+
+/* Paths per light: light l owns the next h_counts[l] paths of the store,
+ * lights in order, so E_1 = Phi_l / h_counts[l] (photon power of Section 3).
+ * Synchronises.  The counts must add up to the n_paths of every store used
+ * afterwards. */
+pv_status pv_set_light_paths(pv_ctx* ctx, const uint32_t* h_counts);
+
+/* Reserve scratch (work queue, per-block counters) for stores of up to
+ * max_paths paths and max_bounces rows.  Synchronises.  Must precede
+ * verify/queue/retrace/compact calls. */
+pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces);
+
+/* --- per frame --------------------------------------------------------- */
+
+/* Section 3 (dynamic objects, dynamic lights): start a frame with new rigid
+ * transforms.  d_obj_xf: [n_objects][12] device floats, row-major 3x4 [R|t]
+ * (world = R p + t); d_light_xf: [n_lights][12] rigid light transforms (light
+ * local z = emitting normal, the light is the rectangle |u|<=hu, |v|<=hv of
+ * its local z=0 plane).  An object or light is "moved" when any of its 12
+ * floats differs bitwise from the previous frame's; the first call marks
+ * everything moved.  Then transforms the moved objects' triangles to world
+ * space (each coordinate the FP64 evaluation of fma(r0,x,fma(r1,y,fma(r2,z,t)))
+ * rounded to FP32) and refits their hierarchies. */
+pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_light_xf);
+
+/* Sections 3.1 and 3.2 (update path origins, dynamic occlusions): for each
+ * path of a moved light, keep the outgoing direction and move x_0 onto the
+ * light's new plane (invalid when outside the rectangle or behind the light:
+ * replace=1, start=0, reuse_light=0); then test the segments in order from the
+ * light against every triangle of the moved objects (two-sided, hit strictly
+ * inside (eps_end, L-eps_end)), a segment also being invalid when its end
+ * photon lies on a moved object; the first invalid segment k gives replace=1,
+ * start=k, reuse_light=1.  The store's info and origin are rewritten, and the
+ * per-block counts of replaced paths are left for pv_build_queue. */
+pv_status pv_verify_paths(pv_ctx* ctx, const pv_path_store* store, pv_stats* d_stats);
+
+/* Section 4 (pruned-paths array, here the re-trace work list): compact the
+ * ids of the paths whose replace bit was set by the last pv_verify_paths into
+ * the context's work queue, in ascending order (stable ballot + prefix-sum
+ * compaction), so that re-tracing packs active paths into few waves. */
+pv_status pv_build_queue(pv_ctx* ctx, const pv_path_store* store);
+
+/* Full invalidation (the paper's baseline, and frame 0): mark every path
+ * replace=1, start=0, reuse_light=0 and queue them all. */
+pv_status pv_queue_all(pv_ctx* ctx, const pv_path_store* store);
+
+/* Copy the current work queue: d_out receives up to 'capacity' path ids,
+ * *d_count (device) the queue length. */
+pv_status pv_copy_queue(pv_ctx* ctx, uint32_t* d_out, uint32_t capacity, uint32_t* d_count);
+
+/* Re-trace the queued paths (Section 3.2 / 3.3).  threshold < 0: naive --
+ * re-trace from the first invalid segment along its stored direction, then
+ * sample cosine-weighted diffuse bounces up to B photons (energy multiplied by
+ * the albedo at each bounce, E_1 = Phi_l / N_l).  threshold >= 0: the
+ * error-based walk of Algorithm 1 with Equation 2 evaluated per channel in
+ * FP32 against the stored energies.  Random numbers: Philox4x64-10 keyed
+ * (seed, 0), counter (path, frame, vertex, tag). */
+pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed,
+                           uint32_t frame, pv_stats* d_stats);
+
+/* Existing photons in (row, path) order: d_out_pos / d_out_energy receive
+ * float[3] per photon (at most 'capacity' written), *d_count the true count. */
+pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
+                             float* d_out_energy, uint32_t capacity, uint32_t* d_count);
+
+/* --- differentiation form ------------------------------------------------ */
+
+/* Deposited energy of every photon recomputed from the path's materials:
+ * E[r][p][c] = Phi_{l,c}/N_l * prod_{i=1..r} albedo[m(x_i)][c] for r < n_p, else 0.
+ * d_albedo [n_materials][3], d_power [n_lights][3], d_E [B][n_paths][3]. */
+pv_status pv_energy_forward(pv_ctx* ctx, const pv_path_store* store, const float* d_albedo,
+                            const float* d_power, float* d_E);
+/* Gradients of L = sum gE * E with the validity masks held fixed.
+ * d_gE [B][n_paths][3]; outputs d_g_albedo [n_materials][3], d_g_power [n_lights][3]
+ * (overwritten). */
+pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const float* d_albedo,
+                             const float* d_power, const float* d_gE, float* d_g_albedo,
+                             float* d_g_power);
+
+/* --- host utilities ------------------------------------------------------ */
+
+/* Bytes of the store layout for n paths and B rows (Table 1 of the paper
+ * counts 32 B per photon, 4 B path information and 12 B origin per path). */
+uint64_t pv_store_bytes(uint64_t n_paths, uint32_t max_bounces);
+/* Pack / unpack the path-information word. */
+uint32_t pv_info_pack(uint32_t cell, uint32_t nseg, uint32_t start, uint32_t replace, uint32_t reuse);
+void pv_info_unpack(uint32_t w, uint32_t* cell, uint32_t* nseg, uint32_t* start, uint32_t* replace,
+                    uint32_t* reuse);
+/* Library version string. */
+const char* pv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,189 @@
+"""ctypes binding of libpv.so (the C-ABI declared in include/pv.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Loading fails loudly when the library has not been built; there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpv.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pv.h")
+
+PV_OK, PV_ERR_ARG, PV_ERR_OOM, PV_ERR_HIP, PV_ERR_CAPACITY, PV_ERR_STATE = 0, -1, -2, -3, -4, -5
+PV_MAX_BOUNCES, PV_MAX_OBJECTS, PV_MAX_LIGHTS = 15, 64, 8
+HIT_NONE = 0xFFFFFFFF
+_NAMES = {0: "PV_OK", -1: "PV_ERR_ARG", -2: "PV_ERR_OOM", -3: "PV_ERR_HIP", -4: "PV_ERR_CAPACITY",
+          -5: "PV_ERR_STATE"}
+
+
+class PVError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class PathStore(C.Structure):
+    _fields_ = [("n_paths", C.c_uint32), ("max_bounces", C.c_uint32), ("stride", C.c_uint32),
+                ("d_pos_hit", C.c_void_p), ("d_energy", C.c_void_p), ("d_origin", C.c_void_p),
+                ("d_info", C.c_void_p)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("n_static", C.c_uint32), ("h_static_verts", C.c_void_p), ("h_static_mat", C.c_void_p),
+                ("n_objects", C.c_uint32), ("h_obj_tris", C.c_void_p), ("h_obj_verts", C.c_void_p),
+                ("h_obj_mat", C.c_void_p), ("n_materials", C.c_uint32), ("h_albedo", C.c_void_p),
+                ("n_lights", C.c_uint32), ("h_light_half", C.c_void_p), ("h_light_power", C.c_void_p),
+                ("eps_end", C.c_float), ("eps_close", C.c_float), ("photon_radius", C.c_float)]
+
+
+STAT_FIELDS = ["segments_examined", "paths_invalid", "paths_light_lost", "rays_traced", "photons_written",
+               "reuse_accepted", "paths_truncated", "reserved"]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_ulonglong) for n in STAT_FIELDS]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpv.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    try:
+        import torch  # noqa: F401  -- load torch's HIP runtime first so both share it
+    except ImportError:
+        pass
+    L = C.CDLL(LIB_PATH)
+    P, U32, I32, U64, F = C.c_void_p, C.c_uint32, C.c_int32, C.c_uint64, C.c_float
+    sig = {
+        "pv_create": ([C.POINTER(P), P], I32),
+        "pv_destroy": ([P], None),
+        "pv_last_error": ([P], C.c_char_p),
+        "pv_upload_scene": ([P, C.POINTER(SceneDesc)], I32),
+        "pv_set_light_paths": ([P, P], I32),
+        "pv_reserve": ([P, U32, U32], I32),
+        "pv_frame_begin": ([P, P, P], I32),
+        "pv_verify_paths": ([P, C.POINTER(PathStore), P], I32),
+        "pv_build_queue": ([P, C.POINTER(PathStore)], I32),
+        "pv_queue_all": ([P, C.POINTER(PathStore)], I32),
+        "pv_copy_queue": ([P, P, U32, P], I32),
+        "pv_retrace_paths": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
+        "pv_compact_photons": ([P, C.POINTER(PathStore), P, P, U32, P], I32),
+        "pv_energy_forward": ([P, C.POINTER(PathStore), P, P, P], I32),
+        "pv_energy_backward": ([P, C.POINTER(PathStore), P, P, P, P, P], I32),
+        "pv_store_bytes": ([U64, U32], U64),
+        "pv_info_pack": ([U32, U32, U32, U32, U32], U32),
+        "pv_info_unpack": ([U32, P, P, P, P, P], None),
+        "pv_version": ([], C.c_char_p),
+    }
+    optional = {
+        "pv_batch_create": ([P, P, P, U32], I32),
+        "pv_batch_destroy": ([P], None),
+        "pv_batch_frame": ([P, P, P, F, U64, U32, P], I32),
+    }
+    for name, (args, res) in list(sig.items()) + list(optional.items()):
+        if not hasattr(L, name):
+            if name in optional:
+                continue
+            raise RuntimeError("libpv.so lacks %s" % name)
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def declared_symbols():
+    """Function names declared in include/pv.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pv_[a-z_]+)\s*\(", txt)))
+
+
+def check(code, ctx=None):
+    if code != PV_OK:
+        msg = lib().pv_last_error(ctx)
+        raise PVError(code, msg.decode() if msg else "")
+    return code
+
+
+def create(stream=None):
+    ctx = C.c_void_p()
+    check(lib().pv_create(C.byref(ctx), stream))
+    return ctx
+
+
+def destroy(ctx):
+    lib().pv_destroy(ctx)
+
+
+def upload_scene(ctx, desc):
+    check(lib().pv_upload_scene(ctx, C.byref(desc)), ctx)
+
+
+def set_light_paths(ctx, counts_ptr):
+    check(lib().pv_set_light_paths(ctx, counts_ptr), ctx)
+
+
+def reserve(ctx, max_paths, max_bounces):
+    check(lib().pv_reserve(ctx, max_paths, max_bounces), ctx)
+
+
+def frame_begin(ctx, d_obj_xf, d_light_xf):
+    check(lib().pv_frame_begin(ctx, d_obj_xf, d_light_xf), ctx)
+
+
+def verify_paths(ctx, store, d_stats=None):
+    check(lib().pv_verify_paths(ctx, C.byref(store), d_stats), ctx)
+
+
+def build_queue(ctx, store):
+    check(lib().pv_build_queue(ctx, C.byref(store)), ctx)
+
+
+def queue_all(ctx, store):
+    check(lib().pv_queue_all(ctx, C.byref(store)), ctx)
+
+
+def copy_queue(ctx, d_out, capacity, d_count):
+    check(lib().pv_copy_queue(ctx, d_out, capacity, d_count), ctx)
+
+
+def retrace_paths(ctx, store, threshold, seed, frame, d_stats=None):
+    check(lib().pv_retrace_paths(ctx, C.byref(store), C.c_float(threshold), seed, frame, d_stats), ctx)
+
+
+def compact_photons(ctx, store, d_pos, d_energy, capacity, d_count):
+    check(lib().pv_compact_photons(ctx, C.byref(store), d_pos, d_energy, capacity, d_count), ctx)
+
+
+def energy_forward(ctx, store, d_albedo, d_power, d_E):
+    check(lib().pv_energy_forward(ctx, C.byref(store), d_albedo, d_power, d_E), ctx)
+
+
+def energy_backward(ctx, store, d_albedo, d_power, d_gE, d_g_albedo, d_g_power):
+    check(lib().pv_energy_backward(ctx, C.byref(store), d_albedo, d_power, d_gE, d_g_albedo, d_g_power), ctx)
+
+
+def store_bytes(n_paths, max_bounces):
+    return int(lib().pv_store_bytes(n_paths, max_bounces))
+
+
+def info_pack(cell, nseg, start, replace, reuse):
+    return int(lib().pv_info_pack(cell, nseg, start, replace, reuse))
+
+
+def info_unpack(w):
+    out = [C.c_uint32() for _ in range(5)]
+    lib().pv_info_unpack(w, *[C.byref(o) for o in out])
+    return tuple(o.value for o in out)

@@ -1,0 +1,713 @@
+// Host side of the C-ABI: contexts, scene upload with host-built hierarchy
+// topology, scratch reservation and the per-frame calls.  Every public
+// function validates its arguments before enqueuing anything and never lets a
+// C++ exception escape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pv_device.h"
+#include "pv_launch.h"
+
+using pv::LeafRec;
+using pv::LightDev;
+using pv::Node;
+using pv::ObjDev;
+using pv::SceneDev;
+using pv::Tri;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Alloc {
+  std::vector<void*> ptrs;
+  ~Alloc() { release(); }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct pv_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  std::string err;
+  // scene
+  bool uploaded = false, frame_started = false;
+  Alloc scene_mem;
+  SceneDev hs{};               // host image of the descriptor
+  SceneDev* d_scene = nullptr; // device descriptor (one entry)
+  uint32_t* d_state = nullptr; // first-frame flag
+  uint2* d_tri_tiles = nullptr;
+  uint32_t n_tri_tiles = 0;
+  uint2* d_leaf_tiles = nullptr;
+  uint32_t n_leaf_tiles = 0;
+  const float** d_in_ptrs = nullptr;  // [2]: object / light transform inputs of the frame
+  uint32_t n_materials = 0, n_lights = 0, n_objects = 0;
+  std::vector<uint32_t> h_light_paths;  // filled at binding
+  // scratch
+  bool reserved = false;
+  Alloc res_mem;
+  uint32_t max_paths = 0, max_bounces = 0, max_blocks = 0;
+  uint2* d_path_tiles = nullptr;
+  uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr,
+           *d_head = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr;
+  float* d_partial = nullptr;
+  // bound store
+  bool bound = false;
+  bool counts_ready = false;   // per-block replace counts written by verify
+  pv_path_store bstore{};
+};
+
+namespace {
+
+pv_status fail(pv_ctx* c, pv_status code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define CK(call)                                                                                     \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess) return fail(ctx, PV_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(Alloc& a, T** out, size_t count) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  a.ptrs.push_back(p);
+  *out = static_cast<T*>(p);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t upload(Alloc& a, T** out, const T* src, size_t count, hipStream_t s) {
+  hipError_t e = dalloc(a, out, count);
+  if (e != hipSuccess || count == 0) return e;
+  return hipMemcpyAsync(*out, src, count * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy topology on the host: 30-bit Morton codes of triangle centroids,
+// sorted, split top-down at the highest differing code bit (the binary radix
+// tree of the sorted codes; equal codes split at the middle), nodes numbered
+// in depth-first order so the left child of an internal node follows it.
+
+uint32_t expand10(uint32_t v) {
+  v &= 1023u;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+struct HostBvh {
+  std::vector<Node> nodes;
+  std::vector<uint32_t> order;   // leaf position -> input triangle
+  std::vector<LeafRec> leaves;   // first/parent relative
+  std::vector<int32_t> parent;   // per node: parent*2+side or -1
+  int32_t root = 0;
+  uint32_t max_depth = 0;        // deepest leaf (root = 0)
+};
+
+// traversal keeps at most one pending child per level
+constexpr uint32_t kMaxDepth = pv::kLdsStack + pv::kPrivStack - 1;
+
+HostBvh build_topology(const float* v9, uint32_t n, uint32_t leaf_max) {
+  HostBvh h;
+  std::vector<uint32_t> code(n);
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  std::vector<float> cen(3 * (size_t)n);
+  for (uint32_t i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      float c = (v9[9 * (size_t)i + k] + v9[9 * (size_t)i + 3 + k] + v9[9 * (size_t)i + 6 + k]) / 3.0f;
+      cen[3 * (size_t)i + k] = c;
+      lo[k] = std::min(lo[k], c);
+      hi[k] = std::max(hi[k], c);
+    }
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+      float ext = hi[k] - lo[k];
+      float u = ext > 0 ? (cen[3 * (size_t)i + k] - lo[k]) / ext : 0.5f;
+      q[k] = (uint32_t)std::min(1023.0f, std::max(0.0f, u * 1024.0f));
+    }
+    code[i] = (expand10(q[0]) << 2) | (expand10(q[1]) << 1) | expand10(q[2]);
+  }
+  h.order.resize(n);
+  for (uint32_t i = 0; i < n; ++i) h.order[i] = i;
+  std::stable_sort(h.order.begin(), h.order.end(), [&](uint32_t a, uint32_t b) { return code[a] < code[b]; });
+  std::vector<uint32_t> sc(n);
+  for (uint32_t i = 0; i < n; ++i) sc[i] = code[h.order[i]];
+
+  struct Item {
+    uint32_t lo, hi;
+    int32_t parent;
+    uint32_t side;
+    uint32_t depth;
+  };
+  std::vector<Item> stack;
+  stack.push_back({0, n - 1, -1, 0, 0});
+  auto set_child = [&](int32_t parent, uint32_t side, int32_t childcode) {
+    if (parent < 0)
+      h.root = childcode;
+    else if (side == 0)
+      h.nodes[parent].d.x = childcode;
+    else
+      h.nodes[parent].d.y = childcode;
+  };
+  while (!stack.empty()) {
+    Item it = stack.back();
+    stack.pop_back();
+    uint32_t cnt = it.hi - it.lo + 1;
+    h.max_depth = std::max(h.max_depth, it.depth);
+    if (cnt <= leaf_max) {
+      set_child(it.parent, it.side, pv::leaf_code(it.lo, cnt));
+      h.leaves.push_back({it.lo, cnt, it.parent, it.side});
+      continue;
+    }
+    uint32_t split;
+    if (sc[it.lo] == sc[it.hi]) {
+      split = (it.lo + it.hi) / 2;
+    } else {
+      int bit = 31 - __builtin_clz(sc[it.lo] ^ sc[it.hi]);
+      uint32_t a = it.lo + 1, b = it.hi;  // first index with the bit set
+      while (a < b) {
+        uint32_t m = (a + b) / 2;
+        if ((sc[m] >> bit) & 1u)
+          b = m;
+        else
+          a = m + 1;
+      }
+      split = a - 1;
+    }
+    int32_t id = (int32_t)h.nodes.size();
+    Node nd{};
+    nd.d = make_int4(0, 0, it.parent < 0 ? -1 : it.parent * 2 + (int)it.side, 0);
+    h.nodes.push_back(nd);
+    h.parent.push_back(nd.d.z);
+    set_child(it.parent, it.side, id);
+    stack.push_back({split + 1, it.hi, id, 1, it.depth + 1});
+    stack.push_back({it.lo, split, id, 0, it.depth + 1});
+  }
+  return h;
+}
+
+inline float pad_lo(float x) { return x - (1e-6f + std::fabs(x) * 1e-6f); }
+inline float pad_hi(float x) { return x + (1e-6f + std::fabs(x) * 1e-6f); }
+
+// child boxes of every node from leaf-order world vertices (static world)
+void host_boxes(HostBvh& h, const float* v9_leaf_order) {
+  auto leaf_box = [&](int32_t code, float* b) {
+    uint32_t f = pv::leaf_first(code), c = pv::leaf_count(code);
+    for (int k = 0; k < 3; ++k) {
+      b[k] = INFINITY;
+      b[3 + k] = -INFINITY;
+    }
+    for (uint32_t i = f; i < f + c; ++i)
+      for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < 3; ++k) {
+          float x = v9_leaf_order[9 * (size_t)i + 3 * v + k];
+          b[k] = std::min(b[k], x);
+          b[3 + k] = std::max(b[3 + k], x);
+        }
+    for (int k = 0; k < 3; ++k) {
+      b[k] = pad_lo(b[k]);
+      b[3 + k] = pad_hi(b[3 + k]);
+    }
+  };
+  std::vector<float> nb(6 * h.nodes.size());
+  for (int64_t i = (int64_t)h.nodes.size() - 1; i >= 0; --i) {
+    Node& nd = h.nodes[i];
+    float cb[2][6];
+    int32_t ch[2] = {nd.d.x, nd.d.y};
+    for (int s = 0; s < 2; ++s) {
+      if (ch[s] < 0)
+        leaf_box(ch[s], cb[s]);
+      else
+        std::memcpy(cb[s], &nb[6 * (size_t)ch[s]], sizeof(cb[s]));
+    }
+    float* f = reinterpret_cast<float*>(&nd);
+    std::memcpy(f, cb[0], 6 * sizeof(float));
+    std::memcpy(f + 6, cb[1], 6 * sizeof(float));
+    for (int k = 0; k < 3; ++k) {
+      nb[6 * i + k] = std::min(cb[0][k], cb[1][k]);
+      nb[6 * i + 3 + k] = std::max(cb[0][3 + k], cb[1][3 + k]);
+    }
+  }
+}
+
+bool finite_all(const float* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+std::vector<uint2> make_tiles(uint32_t scene, uint32_t n) {
+  std::vector<uint2> t;
+  for (uint32_t f = 0; f < n; f += pv::kBlock) t.push_back(make_uint2(scene, f));
+  return t;
+}
+
+pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
+  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
+  if (!ctx->reserved) return fail(ctx, PV_ERR_STATE, "pv_reserve has not been called");
+  if (!st) return fail(ctx, PV_ERR_ARG, "store is NULL");
+  if (!st->d_pos_hit || !st->d_energy || !st->d_origin || !st->d_info)
+    return fail(ctx, PV_ERR_ARG, "store has a NULL array");
+  if (st->max_bounces < 1 || st->max_bounces > PV_MAX_BOUNCES)
+    return fail(ctx, PV_ERR_ARG, "max_bounces out of range 1..15");
+  if (st->stride < st->n_paths || st->stride % 64 != 0)
+    return fail(ctx, PV_ERR_ARG, "stride must be >= n_paths and a multiple of 64");
+  if (st->n_paths > ctx->max_paths || st->max_bounces > ctx->max_bounces)
+    return fail(ctx, PV_ERR_CAPACITY, "store exceeds the reserved size");
+  if (((uintptr_t)st->d_pos_hit | (uintptr_t)st->d_energy) & 15u)
+    return fail(ctx, PV_ERR_ARG, "pos_hit / energy must be 16-byte aligned");
+  if (ctx->bound && std::memcmp(&ctx->bstore, st, sizeof(*st)) == 0) return PV_OK;
+  // light path ranges must cover the store exactly
+  uint32_t total = 0;
+  for (uint32_t l = 0; l < ctx->n_lights; ++l) total += ctx->h_light_paths[l];
+  if (total != st->n_paths) return fail(ctx, PV_ERR_ARG, "light path counts do not add up to n_paths");
+  ctx->hs.pos = static_cast<float4*>(st->d_pos_hit);
+  ctx->hs.energy = static_cast<float4*>(st->d_energy);
+  ctx->hs.origin = st->d_origin;
+  ctx->hs.info = st->d_info;
+  ctx->hs.stride = st->stride;
+  ctx->hs.n_paths = st->n_paths;
+  ctx->hs.B = st->max_bounces;
+  CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
+  uint32_t gb[2] = {0, st->n_paths};
+  CK(hipMemcpyAsync(ctx->d_gbase, gb, sizeof(gb), hipMemcpyHostToDevice, ctx->stream));
+  ctx->bstore = *st;
+  ctx->bound = true;
+  ctx->counts_ready = false;
+  return PV_OK;
+}
+
+uint32_t path_blocks(uint32_t n) { return (n + pv::kBlock - 1) / pv::kBlock; }
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* pv_version(void) { return "pv-mi355x 0.1 (gfx950)"; }
+
+uint64_t pv_store_bytes(uint64_t n_paths, uint32_t max_bounces) {
+  return n_paths * (32ull * max_bounces + 4ull + 12ull);
+}
+
+uint32_t pv_info_pack(uint32_t cell, uint32_t nseg, uint32_t start, uint32_t replace, uint32_t reuse) {
+  return pv::info_pack(cell, nseg, start, replace, reuse);
+}
+
+void pv_info_unpack(uint32_t w, uint32_t* cell, uint32_t* nseg, uint32_t* start, uint32_t* replace,
+                    uint32_t* reuse) {
+  if (cell) *cell = pv::info_cell(w);
+  if (nseg) *nseg = pv::info_nseg(w);
+  if (start) *start = pv::info_start(w);
+  if (replace) *replace = pv::info_replace(w);
+  if (reuse) *reuse = pv::info_reuse(w);
+}
+
+const char* pv_last_error(const pv_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+pv_status pv_create(pv_ctx** out, void* hip_stream) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return PV_ERR_ARG;
+  }
+  *out = nullptr;
+  pv_ctx* ctx = new (std::nothrow) pv_ctx();
+  if (!ctx) {
+    g_create_error = "host allocation failed";
+    return PV_ERR_OOM;
+  }
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipGetDevice(&ctx->device);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, ctx->device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("no HIP device: ") + hipGetErrorString(e);
+    delete ctx;
+    return PV_ERR_HIP;
+  }
+  ctx->n_cu = prop.multiProcessorCount;
+  *out = ctx;
+  return PV_OK;
+}
+
+void pv_destroy(pv_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
+  if (!ctx) return PV_ERR_ARG;
+  try {
+    if (!d) return fail(ctx, PV_ERR_ARG, "desc is NULL");
+    if (d->n_objects > PV_MAX_OBJECTS) return fail(ctx, PV_ERR_ARG, "too many dynamic objects");
+    if (d->n_lights < 1 || d->n_lights > PV_MAX_LIGHTS) return fail(ctx, PV_ERR_ARG, "n_lights out of range 1..8");
+    if (d->n_materials < 1 || !d->h_albedo) return fail(ctx, PV_ERR_ARG, "no materials");
+    if (d->n_static && (!d->h_static_verts || !d->h_static_mat)) return fail(ctx, PV_ERR_ARG, "static arrays NULL");
+    if (!d->h_light_half || !d->h_light_power) return fail(ctx, PV_ERR_ARG, "light arrays NULL");
+    if (!(d->eps_end > 0.0f) || !(d->eps_close >= 0.0f)) return fail(ctx, PV_ERR_ARG, "bad tolerances");
+    uint64_t n_dyn = 0;
+    for (uint32_t o = 0; o < d->n_objects; ++o) {
+      if (!d->h_obj_tris || d->h_obj_tris[o] == 0) return fail(ctx, PV_ERR_ARG, "object without triangles");
+      n_dyn += d->h_obj_tris[o];
+    }
+    if (n_dyn && (!d->h_obj_verts || !d->h_obj_mat)) return fail(ctx, PV_ERR_ARG, "object arrays NULL");
+    if ((uint64_t)d->n_static + n_dyn >= (1ull << 28)) return fail(ctx, PV_ERR_ARG, "too many triangles");
+    if (d->n_static + n_dyn == 0) return fail(ctx, PV_ERR_ARG, "empty scene");
+    if (!finite_all(d->h_static_verts, 9 * (size_t)d->n_static) || !finite_all(d->h_obj_verts, 9 * n_dyn))
+      return fail(ctx, PV_ERR_ARG, "non-finite vertex");
+    for (uint64_t i = 0; i < d->n_static; ++i)
+      if (d->h_static_mat[i] >= d->n_materials) return fail(ctx, PV_ERR_ARG, "static material id out of range");
+    for (uint64_t i = 0; i < n_dyn; ++i)
+      if (d->h_obj_mat[i] >= d->n_materials) return fail(ctx, PV_ERR_ARG, "object material id out of range");
+
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->scene_mem.release();
+    ctx->uploaded = ctx->frame_started = ctx->bound = false;
+    hipStream_t s = ctx->stream;
+    Alloc& A = ctx->scene_mem;
+    SceneDev hs{};
+    const uint32_t S = d->n_static;
+    const uint32_t T = S + (uint32_t)n_dyn;
+
+    // materials by global triangle id
+    std::vector<uint32_t> tri_mat(T);
+    for (uint32_t i = 0; i < S; ++i) tri_mat[i] = d->h_static_mat[i];
+    for (uint64_t i = 0; i < n_dyn; ++i) tri_mat[S + i] = d->h_obj_mat[i];
+    uint32_t* d_tri_mat;
+    CK(upload(A, &d_tri_mat, tri_mat.data(), T, s));
+    float* d_albedo;
+    CK(upload(A, &d_albedo, d->h_albedo, 3 * (size_t)d->n_materials, s));
+    hs.tri_mat = d_tri_mat;
+    hs.albedo = d_albedo;
+    hs.n_tris_total = T;
+
+    // static world: topology + boxes on the host
+    std::vector<Node> snodes;
+    std::vector<Tri> stris;
+    hs.n_static = S;
+    hs.sroot = 0;
+    if (S) {
+      HostBvh hb = build_topology(d->h_static_verts, S, 4);
+      std::vector<float> v9(9 * (size_t)S);
+      stris.resize(S);
+      for (uint32_t i = 0; i < S; ++i) {
+        const float* v = d->h_static_verts + 9 * (size_t)hb.order[i];
+        std::memcpy(&v9[9 * (size_t)i], v, 9 * sizeof(float));
+        uint32_t gid = hb.order[i];
+        stris[i].t0 = make_float4(v[0], v[1], v[2], 0.0f);
+        stris[i].t1 = make_float4(v[3], v[4], v[5], 0.0f);
+        stris[i].t2 = make_float4(v[6], v[7], v[8], 0.0f);
+        std::memcpy(&stris[i].t0.w, &gid, 4);
+        std::memcpy(&stris[i].t1.w, &tri_mat[gid], 4);
+      }
+      if (hb.max_depth > kMaxDepth) return fail(ctx, PV_ERR_CAPACITY, "static hierarchy too deep");
+      host_boxes(hb, v9.data());
+      snodes = std::move(hb.nodes);
+      hs.sroot = hb.root;
+    }
+    Node* d_snodes;
+    Tri* d_stris;
+    CK(upload(A, &d_snodes, snodes.data(), snodes.size(), s));
+    CK(upload(A, &d_stris, stris.data(), stris.size(), s));
+    hs.snodes = d_snodes;
+    hs.stris = d_stris;
+
+    // dynamic objects: topology in object space, boxes refit per frame
+    std::vector<ObjDev> objs(d->n_objects);
+    std::vector<float> dlocal(9 * n_dyn);
+    std::vector<uint32_t> dgid(n_dyn);
+    std::vector<LeafRec> leaves;
+    std::vector<int32_t> nparent;
+    std::vector<Node> dnodes;
+    uint32_t tri_base = 0, gbase = S;
+    for (uint32_t o = 0; o < d->n_objects; ++o) {
+      uint32_t n = d->h_obj_tris[o];
+      const float* v = d->h_obj_verts + 9 * (size_t)tri_base;
+      HostBvh hb = build_topology(v, n, 2);
+      if (hb.max_depth > kMaxDepth) return fail(ctx, PV_ERR_CAPACITY, "object hierarchy too deep");
+      uint32_t node_base = (uint32_t)dnodes.size(), leaf_base = (uint32_t)leaves.size();
+      auto rebase = [&](int32_t c) {
+        return c >= 0 ? c + (int32_t)node_base
+                      : pv::leaf_code(pv::leaf_first(c) + tri_base, pv::leaf_count(c));
+      };
+      for (Node nd : hb.nodes) {
+        nd.d.x = rebase(nd.d.x);
+        nd.d.y = rebase(nd.d.y);
+        if (nd.d.z >= 0) nd.d.z += 2 * (int32_t)node_base;
+        dnodes.push_back(nd);
+        nparent.push_back(nd.d.z);
+      }
+      for (LeafRec L : hb.leaves) {
+        L.first += tri_base;
+        if (L.parent >= 0) L.parent += (int32_t)node_base;
+        leaves.push_back(L);
+      }
+      for (uint32_t i = 0; i < n; ++i) {
+        std::memcpy(&dlocal[9 * (size_t)(tri_base + i)], v + 9 * (size_t)hb.order[i], 9 * sizeof(float));
+        dgid[tri_base + i] = gbase + hb.order[i];
+      }
+      ObjDev& ob = objs[o];
+      ob.gbase = gbase;
+      ob.n_tris = n;
+      ob.tri_base = tri_base;
+      ob.node_base = node_base;
+      ob.n_leaves = (uint32_t)hb.leaves.size();
+      ob.leaf_base = leaf_base;
+      ob.root = rebase(hb.root);
+      tri_base += n;
+      gbase += n;
+    }
+    Node* d_dnodes;
+    Tri* d_dtris;
+    float* d_dlocal;
+    uint32_t *d_dgid, *d_counter;
+    LeafRec* d_leaves;
+    int32_t* d_nparent;
+    ObjDev* d_objs;
+    CK(upload(A, &d_dnodes, dnodes.data(), dnodes.size(), s));
+    CK(dalloc(A, &d_dtris, n_dyn));
+    CK(upload(A, &d_dlocal, dlocal.data(), dlocal.size(), s));
+    CK(upload(A, &d_dgid, dgid.data(), dgid.size(), s));
+    CK(upload(A, &d_leaves, leaves.data(), leaves.size(), s));
+    CK(upload(A, &d_nparent, nparent.data(), nparent.size(), s));
+    CK(dalloc(A, &d_counter, dnodes.size()));
+    CK(upload(A, &d_objs, objs.data(), objs.size(), s));
+    hs.dnodes = d_dnodes;
+    hs.dtris = d_dtris;
+    hs.dlocal = d_dlocal;
+    hs.dtri_gid = d_dgid;
+    hs.dleaves = d_leaves;
+    hs.dnode_parent = d_nparent;
+    hs.dcounter = d_counter;
+    hs.objs = d_objs;
+    hs.n_obj = d->n_objects;
+    hs.n_dyn_tris = (uint32_t)n_dyn;
+    CK(dalloc(A, &hs.obj_aabb, 6 * (size_t)d->n_objects));
+    CK(dalloc(A, &hs.obj_xf_cur, 12 * (size_t)d->n_objects));
+    CK(dalloc(A, &hs.obj_xf_prev, 12 * (size_t)d->n_objects));
+    CK(dalloc(A, &hs.obj_moved, d->n_objects));
+
+    // lights (path ranges filled at store binding time)
+    std::vector<LightDev> lights(d->n_lights);
+    for (uint32_t l = 0; l < d->n_lights; ++l) {
+      lights[l].half[0] = d->h_light_half[2 * l];
+      lights[l].half[1] = d->h_light_half[2 * l + 1];
+      for (int c = 0; c < 3; ++c) lights[l].power[c] = d->h_light_power[3 * l + c];
+      lights[l].path_base = lights[l].path_count = 0;
+    }
+    LightDev* d_lights;
+    CK(upload(A, &d_lights, lights.data(), lights.size(), s));
+    hs.lights = d_lights;
+    hs.n_lights = d->n_lights;
+    CK(dalloc(A, &hs.light_xf_cur, 12 * (size_t)d->n_lights));
+    CK(dalloc(A, &hs.light_xf_prev, 12 * (size_t)d->n_lights));
+    CK(dalloc(A, &hs.light_moved, d->n_lights));
+    hs.eps_end = d->eps_end;
+    hs.eps_close = d->eps_close;
+    hs.radius = d->photon_radius;
+    hs.gpath_base = 0;
+
+    CK(dalloc(A, &ctx->d_scene, 1));
+    CK(dalloc(A, &ctx->d_state, 1));
+    uint32_t one = 1;
+    CK(hipMemcpyAsync(ctx->d_state, &one, 4, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(ctx->d_scene, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+    std::vector<uint2> tt = make_tiles(0, (uint32_t)n_dyn), lt = make_tiles(0, (uint32_t)leaves.size());
+    CK(upload(A, &ctx->d_tri_tiles, tt.data(), tt.size(), s));
+    CK(upload(A, &ctx->d_leaf_tiles, lt.data(), lt.size(), s));
+    ctx->n_tri_tiles = (uint32_t)tt.size();
+    ctx->n_leaf_tiles = (uint32_t)lt.size();
+    CK(dalloc(A, &ctx->d_in_ptrs, 2));
+    CK(hipStreamSynchronize(s));
+    ctx->hs = hs;
+    ctx->n_materials = d->n_materials;
+    ctx->n_lights = d->n_lights;
+    ctx->n_objects = d->n_objects;
+    ctx->h_light_paths.assign(d->n_lights, 0);
+    ctx->uploaded = true;
+    return PV_OK;
+  } catch (const std::exception& e) {
+    return fail(ctx, PV_ERR_OOM, std::string("host exception: ") + e.what());
+  }
+}
+
+// Paths per light: light l owns paths [sum_{i<l} counts[i], ... + counts[l]).
+pv_status pv_set_light_paths(pv_ctx* ctx, const uint32_t* h_counts) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
+  if (!h_counts) return fail(ctx, PV_ERR_ARG, "counts is NULL");
+  std::vector<LightDev> lights(ctx->n_lights);
+  CK(hipMemcpy(lights.data(), ctx->hs.lights, sizeof(LightDev) * ctx->n_lights, hipMemcpyDeviceToHost));
+  uint32_t base = 0;
+  for (uint32_t l = 0; l < ctx->n_lights; ++l) {
+    lights[l].path_base = base;
+    lights[l].path_count = h_counts[l];
+    ctx->h_light_paths[l] = h_counts[l];
+    base += h_counts[l];
+  }
+  CK(hipMemcpy(const_cast<LightDev*>(ctx->hs.lights), lights.data(), sizeof(LightDev) * ctx->n_lights,
+               hipMemcpyHostToDevice));
+  ctx->bound = false;
+  return PV_OK;
+}
+
+pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
+  if (!ctx) return PV_ERR_ARG;
+  if (max_paths == 0 || max_paths > (1u << 30)) return fail(ctx, PV_ERR_ARG, "max_paths out of range");
+  if (max_bounces < 1 || max_bounces > PV_MAX_BOUNCES) return fail(ctx, PV_ERR_ARG, "max_bounces out of range");
+  try {
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->res_mem.release();
+    ctx->reserved = ctx->bound = false;
+    Alloc& A = ctx->res_mem;
+    uint32_t nb = path_blocks(max_paths);
+    std::vector<uint2> tiles = make_tiles(0, max_paths);
+    CK(upload(A, &ctx->d_path_tiles, tiles.data(), tiles.size(), ctx->stream));
+    CK(dalloc(A, &ctx->d_block_cnt, nb));
+    CK(dalloc(A, &ctx->d_offsets, nb));
+    CK(dalloc(A, &ctx->d_queue, max_paths));
+    CK(dalloc(A, &ctx->d_qcount, 1));
+    CK(dalloc(A, &ctx->d_head, 1));
+    CK(dalloc(A, &ctx->d_pcounts, (size_t)nb * max_bounces));
+    CK(dalloc(A, &ctx->d_poffsets, (size_t)nb * max_bounces));
+    CK(dalloc(A, &ctx->d_gbase, 2));
+    CK(dalloc(A, &ctx->d_partial, (size_t)nb * 3 * (256 + PV_MAX_LIGHTS)));
+    CK(hipMemsetAsync(ctx->d_qcount, 0, 4, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->max_paths = max_paths;
+    ctx->max_bounces = max_bounces;
+    ctx->max_blocks = nb;
+    ctx->reserved = true;
+    return PV_OK;
+  } catch (const std::exception& e) {
+    return fail(ctx, PV_ERR_OOM, std::string("host exception: ") + e.what());
+  }
+}
+
+pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_light_xf) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
+  if ((ctx->n_objects && !d_obj_xf) || !d_light_xf) return fail(ctx, PV_ERR_ARG, "transform array is NULL");
+  const float* in[2] = {d_obj_xf, d_light_xf};
+  CK(hipMemcpyAsync(ctx->d_in_ptrs, in, sizeof(in), hipMemcpyHostToDevice, ctx->stream));
+  CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->d_state, ctx->stream));
+  CK(pv::launch_transform(ctx->d_scene, ctx->d_tri_tiles, ctx->n_tri_tiles, ctx->stream));
+  CK(pv::launch_refit(ctx->d_scene, ctx->d_leaf_tiles, ctx->n_leaf_tiles, ctx->stream));
+  ctx->frame_started = true;
+  return PV_OK;
+}
+
+pv_status pv_verify_paths(pv_ctx* ctx, const pv_path_store* store, pv_stats* d_stats) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
+  uint32_t nb = path_blocks(store->n_paths);
+  CK(pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, d_stats, ctx->stream));
+  ctx->counts_ready = true;
+  return PV_OK;
+}
+
+pv_status pv_build_queue(pv_ctx* ctx, const pv_path_store* store) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!ctx->counts_ready) return fail(ctx, PV_ERR_STATE, "pv_verify_paths has not been called");
+  uint32_t nb = path_blocks(store->n_paths);
+  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->stream));
+  CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_queue_all(pv_ctx* ctx, const pv_path_store* store) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  uint32_t nb = path_blocks(store->n_paths);
+  CK(pv::launch_mark_all(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, ctx->stream));
+  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->stream));
+  CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_copy_queue(pv_ctx* ctx, uint32_t* d_out, uint32_t capacity, uint32_t* d_count) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!ctx->reserved) return fail(ctx, PV_ERR_STATE, "pv_reserve has not been called");
+  if (!d_out || !d_count) return fail(ctx, PV_ERR_ARG, "output is NULL");
+  uint32_t n = std::min(capacity, ctx->bound ? ctx->bstore.n_paths : 0u);
+  if (n) CK(hipMemcpyAsync(d_out, ctx->d_queue, 4 * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+  CK(hipMemcpyAsync(d_count, ctx->d_qcount, 4, hipMemcpyDeviceToDevice, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed, uint32_t frame,
+                           pv_stats* d_stats) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
+  if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
+  uint32_t blocks = (uint32_t)ctx->n_cu * 8;
+  CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold, seed,
+                        frame, d_stats, blocks, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos, float* d_out_energy,
+                             uint32_t capacity, uint32_t* d_count) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!d_count || (capacity && (!d_out_pos || !d_out_energy))) return fail(ctx, PV_ERR_ARG, "output is NULL");
+  uint32_t nb = path_blocks(store->n_paths);
+  CK(pv::launch_photon_count(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_pcounts, ctx->stream));
+  CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, nullptr, ctx->stream));
+  CK(pv::launch_photon_scatter(ctx->d_scene, ctx->d_path_tiles, nb, store->max_bounces, ctx->d_poffsets, d_out_pos,
+                               d_out_energy, capacity, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_energy_forward(pv_ctx* ctx, const pv_path_store* store, const float* d_albedo, const float* d_power,
+                            float* d_E) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!d_albedo || !d_power || !d_E) return fail(ctx, PV_ERR_ARG, "NULL argument");
+  CK(pv::launch_energy_fwd(ctx->d_scene, ctx->d_path_tiles, path_blocks(store->n_paths), d_albedo, d_power, d_E,
+                           ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const float* d_albedo, const float* d_power,
+                             const float* d_gE, float* d_g_albedo, float* d_g_power) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!d_albedo || !d_power || !d_gE || !d_g_albedo || !d_g_power) return fail(ctx, PV_ERR_ARG, "NULL argument");
+  if (ctx->n_materials > 256) return fail(ctx, PV_ERR_CAPACITY, "backward supports at most 256 materials");
+  CK(pv::launch_energy_bwd(ctx->d_scene, ctx->d_path_tiles, path_blocks(store->n_paths), d_albedo, d_power, d_gE,
+                           ctx->n_materials, ctx->n_lights, ctx->d_partial, d_g_albedo, d_g_power, ctx->stream));
+  return PV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,966 @@
+// HIP kernels of the path-verification hot path (gfx950).
+//
+//   k_frame_begin   moved flags for objects / lights, transform history
+//   k_transform     world-space triangles of moved objects (FP64 fma chain -> FP32)
+//   k_refit         bottom-up box refit of moved objects' hierarchies
+//   k_verify        Section 3.1 origin update + Section 3.2 dynamic occlusions,
+//                   first invalid segment, per-block replace counts
+//   k_scan          exclusive scan of per-block counts (single block)
+//   k_scatter_queue stable re-trace work queue (wave ballot + prefix)
+//   k_mark_all      full invalidation (baseline / frame 0)
+//   k_retrace       persistent re-trace over the device work queue
+//   k_photon_count / k_photon_scatter   compaction of existing photons
+//   k_energy_fwd / k_energy_bwd / k_reduce_partials   differentiation form
+#include "pv_device.h"
+#include "pv_launch.h"
+
+namespace pv {
+
+__device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
+__device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// block-wide sum of one value per thread (kBlock threads), result to all
+__device__ inline unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// frame begin: one thread per (scene, object) and per (scene, light)
+
+__global__ void k_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
+                              const float* const* light_in, uint32_t* state) {
+  int s = blockIdx.x;
+  if (s >= n_scenes) return;
+  SceneDev& S = scenes[s];
+  const uint32_t first = state[s];
+  for (uint32_t o = threadIdx.x; o < S.n_obj; o += blockDim.x) {
+    const float* nw = obj_in[s] + 12 * o;
+    float* cur = S.obj_xf_cur + 12 * o;
+    float* prev = S.obj_xf_prev + 12 * o;
+    uint32_t moved = first;
+    for (int i = 0; i < 12; ++i) {
+      float c = cur[i], n = nw[i];
+      moved |= (__float_as_uint(c) != __float_as_uint(n)) ? 1u : 0u;
+      prev[i] = c;
+      cur[i] = n;
+    }
+    S.obj_moved[o] = moved;
+  }
+  for (uint32_t l = threadIdx.x; l < S.n_lights; l += blockDim.x) {
+    const float* nw = light_in[s] + 12 * l;
+    float* cur = S.light_xf_cur + 12 * l;
+    float* prev = S.light_xf_prev + 12 * l;
+    uint32_t moved = 0;  // a light's first placement does not invalidate anything
+    if (!first) {
+      for (int i = 0; i < 12; ++i) moved |= (__float_as_uint(cur[i]) != __float_as_uint(nw[i])) ? 1u : 0u;
+    }
+    for (int i = 0; i < 12; ++i) {
+      prev[i] = cur[i];
+      cur[i] = nw[i];
+    }
+    S.light_moved[l] = moved;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) state[s] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// transform: one thread per dynamic triangle record; tiles = (scene, first record)
+
+__device__ inline uint32_t object_of_record(const SceneDev& S, uint32_t rec) {
+  uint32_t lo = 0, hi = S.n_obj;  // find o with tri_base[o] <= rec < tri_base[o+1]
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (S.objs[mid].tri_base <= rec)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline float xform_coord(const float* m, int r, float x, float y, float z) {
+  double v = fma((double)m[4 * r + 0], (double)x,
+                 fma((double)m[4 * r + 1], (double)y, fma((double)m[4 * r + 2], (double)z, (double)m[4 * r + 3])));
+  return (float)v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_transform(SceneDev* scenes, const uint2* tiles) {
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  uint32_t rec = tile.y + threadIdx.x;
+  if (rec >= S.n_dyn_tris) return;
+  uint32_t o = object_of_record(S, rec);
+  // counters of this object's nodes are reset here, before the refit kernel
+  const ObjDev& ob = S.objs[o];
+  uint32_t local = rec - ob.tri_base;
+  if (S.obj_moved[o] && local + 1 < ob.n_leaves) S.dcounter[ob.node_base + local] = 0;
+  if (!S.obj_moved[o]) return;
+  const float* m = S.obj_xf_cur + 12 * o;
+  const float* v = S.dlocal + 9 * (size_t)rec;
+  float w[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) w[3 * k + r] = xform_coord(m, r, v[3 * k], v[3 * k + 1], v[3 * k + 2]);
+  uint32_t gid = S.dtri_gid[rec];
+  Tri t;
+  t.t0 = make_float4(w[0], w[1], w[2], __uint_as_float(gid));
+  t.t1 = make_float4(w[3], w[4], w[5], __uint_as_float(S.tri_mat[gid]));
+  t.t2 = make_float4(w[6], w[7], w[8], 0.0f);
+  S.dtris[rec] = t;
+}
+
+// ---------------------------------------------------------------------------
+// refit: one thread per leaf of a moved object; the second child to arrive at
+// a node computes its box and continues upwards (atomic visit counters)
+
+__device__ inline float pad_lo(float x) { return x - (1e-6f + fabsf(x) * 1e-6f); }
+__device__ inline float pad_hi(float x) { return x + (1e-6f + fabsf(x) * 1e-6f); }
+
+// Child boxes are written float by float: the two siblings of a node write
+// disjoint words (child0 = floats 0..5, child1 = floats 6..11) concurrently.
+__device__ inline void write_child_box(Node* nd, uint32_t side, const float lo[3], const float hi[3]) {
+  float* f = reinterpret_cast<float*>(nd) + 6 * side;
+  f[0] = lo[0];
+  f[1] = lo[1];
+  f[2] = lo[2];
+  f[3] = hi[0];
+  f[4] = hi[1];
+  f[5] = hi[2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_refit(SceneDev* scenes, const uint2* tiles) {
+  uint2 tile = tiles[blockIdx.x];
+  SceneDev& S = scenes[tile.x];
+  uint32_t li = tile.y + threadIdx.x;
+  uint32_t n_leaves_total = S.n_obj ? (S.objs[S.n_obj - 1].leaf_base + S.objs[S.n_obj - 1].n_leaves) : 0;
+  if (li >= n_leaves_total) return;
+  LeafRec L = S.dleaves[li];
+  uint32_t o = object_of_record(S, L.first);
+  if (!S.obj_moved[o]) return;
+  float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  for (uint32_t i = 0; i < L.count; ++i) {
+    Tri t = S.dtris[L.first + i];
+    float4 vs[3] = {t.t0, t.t1, t.t2};
+    for (int k = 0; k < 3; ++k) {
+      lo[0] = fminf(lo[0], vs[k].x); hi[0] = fmaxf(hi[0], vs[k].x);
+      lo[1] = fminf(lo[1], vs[k].y); hi[1] = fmaxf(hi[1], vs[k].y);
+      lo[2] = fminf(lo[2], vs[k].z); hi[2] = fmaxf(hi[2], vs[k].z);
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = pad_lo(lo[k]);
+    hi[k] = pad_hi(hi[k]);
+  }
+  int32_t parent = L.parent;
+  uint32_t side = L.side;
+  while (true) {
+    if (parent < 0) {
+      float* ob = S.obj_aabb + 6 * o;
+      for (int k = 0; k < 3; ++k) {
+        ob[k] = lo[k];
+        ob[3 + k] = hi[k];
+      }
+      return;
+    }
+    Node* nd = S.dnodes + parent;
+    write_child_box(nd, side, lo, hi);
+    __threadfence();
+    uint32_t prev = atomicAdd(&S.dcounter[parent], 1u);
+    if (prev == 0) return;  // the sibling has not arrived yet
+    __threadfence();
+    // both child boxes are now final; read them past any stale cache line
+    const volatile float* q = (const volatile float*)nd;
+    float v[12];
+    for (int k = 0; k < 12; ++k) v[k] = q[k];
+    lo[0] = fminf(v[0], v[6]); lo[1] = fminf(v[1], v[7]); lo[2] = fminf(v[2], v[8]);
+    hi[0] = fmaxf(v[3], v[9]); hi[1] = fmaxf(v[4], v[10]); hi[2] = fmaxf(v[5], v[11]);
+    int32_t pp = S.dnode_parent[parent];
+    if (pp < 0) {
+      parent = -1;
+    } else {
+      side = (uint32_t)pp & 1u;
+      parent = pp >> 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// verification (Sections 3.1 and 3.2)
+
+struct MovedSet {
+  int n;
+  int32_t root[PV_MAX_OBJECTS];
+  float box[PV_MAX_OBJECTS][6];
+  uint32_t glo[PV_MAX_OBJECTS], ghi[PV_MAX_OBJECTS];
+};
+
+__device__ inline void load_moved(const SceneDev& S, MovedSet& M) {
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (uint32_t o = 0; o < S.n_obj; ++o) {
+      if (!S.obj_moved[o]) continue;
+      const ObjDev& ob = S.objs[o];
+      M.root[n] = ob.root;
+      for (int k = 0; k < 6; ++k) M.box[n][k] = S.obj_aabb[6 * o + k];
+      M.glo[n] = ob.gbase;
+      M.ghi[n] = ob.gbase + ob.n_tris;
+      ++n;
+    }
+    M.n = n;
+  }
+  __syncthreads();
+}
+
+__device__ inline bool on_moved(const MovedSet& M, uint32_t hit) {
+  for (int i = 0; i < M.n; ++i)
+    if (hit >= M.glo[i] && hit < M.ghi[i]) return true;
+  return false;
+}
+
+__device__ inline bool blocked_by_moved(const SceneDev& S, const MovedSet& M, const Ray& r, Stack& st) {
+  for (int i = 0; i < M.n; ++i) {
+    const float* b = M.box[i];
+    if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, r.tmax) == __builtin_inff()) continue;
+    if (bvh_any(S.dnodes, S.dtris, M.root[i], r, st)) return true;
+  }
+  return false;
+}
+
+__device__ inline Ray segment_ray(float3 a, float3 b, float eps) {
+  float3 d = sub(b, a);
+  float L = length(d);
+  float tmin = L > 0.0f ? eps / L : 1.0f;
+  return make_ray(a, d, tmin, 1.0f - tmin);
+}
+
+__device__ inline int light_of(const SceneDev& S, uint32_t p) {
+  for (uint32_t l = 0; l < S.n_lights; ++l)
+    if (p - S.lights[l].path_base < S.lights[l].path_count) return (int)l;
+  return -1;
+}
+
+// Section 3.1 for a rectangular area light: keep the outgoing direction and
+// intersect it with the light's current plane.
+__device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 x1, float3* out) {
+  const float* xf = S.light_xf_cur + 12 * l;
+  float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
+  float3 n = f3(xf[2], xf[6], xf[10]), c = f3(xf[3], xf[7], xf[11]);
+  n = mul(n, 1.0f / length(n));
+  float3 w = sub(x1, x0);
+  float len = length(w);
+  if (!(len > 0.0f)) return false;
+  w = mul(w, 1.0f / len);
+  float dn = dot(w, n);
+  if (!(dn > 0.0f)) return false;
+  float sdist = dot(sub(x1, c), n) / dn;
+  if (!(sdist > S.eps_end)) return false;
+  float3 p = sub(x1, mul(w, sdist));
+  float3 r = sub(p, c);
+  float u = dot(r, eu), v = dot(r, ev);
+  if (!(fabsf(u) <= S.lights[l].half[0] && fabsf(v) <= S.lights[l].half[1])) return false;
+  *out = p;
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
+                                                   uint32_t* __restrict__ block_cnt, pv_stats* stats) {
+  __shared__ uint32_t sstack[kLdsStack * kBlock];
+  __shared__ MovedSet M;
+  __shared__ unsigned long long sred[kBlock / 64];
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  load_moved(S, M);
+  Stack st;
+  st.lds = sstack + threadIdx.x;
+  st.sp = 0;
+  uint32_t p = tile.y + threadIdx.x;
+  bool active = p < S.n_paths;
+  uint32_t ex = 0, repl = 0, lost = 0;
+  if (active) {
+    const size_t stride = S.stride;
+    uint32_t w = S.info[p];
+    uint32_t n = min(info_nseg(w), S.B), cell = info_cell(w);
+    uint32_t out = info_pack(cell, n, 0, 0, 0);
+    bool done = false;
+    float3 a = f3(S.origin[p], S.origin[stride + p], S.origin[2 * stride + p]);
+    float4 row = n > 0 ? S.pos[p] : make_float4(0, 0, 0, 0);
+    int l = light_of(S, p);
+    if (l >= 0 && S.light_moved[l]) {
+      float3 na;
+      if (n > 0 && light_update(S, l, a, xyz(row), &na)) {
+        a = na;
+        S.origin[p] = na.x;
+        S.origin[stride + p] = na.y;
+        S.origin[2 * stride + p] = na.z;
+      } else {
+        out = info_pack(cell, n, 0, 1, 0);
+        done = true;
+        lost = 1;
+      }
+    }
+    for (uint32_t j = 0; j < n && !done; ++j) {
+      if (j > 0) row = S.pos[j * stride + p];
+      float3 b = xyz(row);
+      ++ex;
+      bool inv = on_moved(M, __float_as_uint(row.w));
+      if (!inv && M.n > 0) {
+        Ray r = segment_ray(a, b, S.eps_end);
+        inv = blocked_by_moved(S, M, r, st);
+      }
+      if (inv) {
+        out = info_pack(cell, n, j, 1, 1);
+        done = true;
+      }
+      a = b;
+    }
+    S.info[p] = out;
+    repl = info_replace(out);
+  }
+  // per-block count of replaced paths for the queue
+  unsigned long long nrep = block_sum_u64(repl, sred);
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = (uint32_t)nrep;
+  if (stats) {
+    unsigned long long nex = block_sum_u64(ex, sred);
+    unsigned long long nlost = block_sum_u64(lost, sred);
+    if (threadIdx.x == 0) {
+      atomicAdd(&stats->segments_examined, nex);
+      atomicAdd(&stats->paths_invalid, nrep);
+      atomicAdd(&stats->paths_light_lost, nlost);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of n counts by one block of 1024 threads; total -> *total,
+// and the work-queue head reset
+
+__global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint32_t n,
+                                               uint32_t* total, uint32_t* head) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry_sh;
+  if (threadIdx.x == 0) carry_sh = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n; base += 1024) {
+    uint32_t i = base + threadIdx.x;
+    uint32_t v = i < n ? in[i] : 0u;
+    // inclusive wave scan
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t y = __shfl_up(x, o, 64);
+      if ((int)lane_id() >= o) x += y;
+    }
+    if (lane_id() == 63) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      uint32_t s = wsum[threadIdx.x];
+      for (int o = 1; o < 16; o <<= 1) {
+        uint32_t y = __shfl_up(s, o, 64);
+        if ((int)threadIdx.x >= o) s += y;
+      }
+      wsum[threadIdx.x] = s;  // inclusive over waves
+    }
+    __syncthreads();
+    uint32_t wpre = (threadIdx.x >> 6) ? wsum[(threadIdx.x >> 6) - 1] : 0u;
+    uint32_t carry = carry_sh;
+    if (i < n) out[i] = carry + wpre + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_sh = carry + wsum[15];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *total = carry_sh;
+    if (head) *head = 0;
+  }
+}
+
+// stable queue: ascending global path ids with the replace bit
+__global__ __launch_bounds__(kBlock) void k_scatter_queue(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
+                                                          const uint32_t* __restrict__ offsets, uint32_t* __restrict__ queue) {
+  __shared__ uint32_t wcnt[kBlock / 64];
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  uint32_t p = tile.y + threadIdx.x;
+  bool flag = p < S.n_paths && info_replace(S.info[p]);
+  uint64_t bal = __ballot(flag);
+  if (lane_id() == 0) wcnt[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t pre = 0;
+  for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) pre += wcnt[w];
+  if (flag) queue[offsets[blockIdx.x] + pre + (uint32_t)__popcll(bal & lanemask_lt())] = S.gpath_base + p;
+}
+
+// full invalidation: every path replace=1, start=0, reuse_light=0; queue = all
+__global__ __launch_bounds__(kBlock) void k_mark_all(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
+                                                     uint32_t* __restrict__ block_cnt) {
+  __shared__ unsigned long long sred[kBlock / 64];
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  uint32_t p = tile.y + threadIdx.x;
+  uint32_t f = 0;
+  if (p < S.n_paths) {
+    uint32_t w = S.info[p];
+    S.info[p] = info_pack(info_cell(w), info_nseg(w), 0, 1, 0);
+    f = 1;
+  }
+  unsigned long long c = block_sum_u64(f, sred);
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = (uint32_t)c;
+}
+
+// ---------------------------------------------------------------------------
+// re-tracing (Section 3.2 naive, Section 3.3 / Algorithm 1 error-based)
+
+struct Hit {
+  float t;
+  uint32_t gid;
+  uint32_t rec;
+  const Tri* set;
+};
+
+constexpr float kTFar = 16.0f;
+
+__device__ inline Hit closest_hit(const SceneDev& S, float3 o, float3 w, Stack& st) {
+  Ray r = make_ray(o, w, S.eps_end, kTFar);
+  Hit h;
+  h.t = kTFar;
+  h.gid = kHitNone;
+  h.rec = 0;
+  h.set = nullptr;
+  if (S.n_static) bvh_closest(S.snodes, S.stris, S.sroot, r, st, &h.t, &h.gid, &h.rec, &h.set);
+  for (uint32_t o2 = 0; o2 < S.n_obj; ++o2) {
+    const float* b = S.obj_aabb + 6 * o2;
+    if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h.t) == __builtin_inff()) continue;
+    bvh_closest(S.dnodes, S.dtris, S.objs[o2].root, r, st, &h.t, &h.gid, &h.rec, &h.set);
+  }
+  return h;
+}
+
+__device__ inline float3 hit_normal(const Hit& h) {
+  Tri t = h.set[h.rec];
+  float3 v0 = xyz(t.t0), v1 = xyz(t.t1), v2 = xyz(t.t2);
+  float3 n = cross(sub(v1, v0), sub(v2, v0));
+  return mul(n, 1.0f / length(n));
+}
+
+__device__ inline uint32_t hit_material(const Hit& h) { return __float_as_uint(h.set[h.rec].t1.w); }
+
+__device__ inline float3 vertex(const SceneDev& S, uint32_t p, uint32_t j) {
+  const size_t stride = S.stride;
+  if (j == 0) return f3(S.origin[p], S.origin[stride + p], S.origin[2 * stride + p]);
+  return xyz(S.pos[(size_t)(j - 1) * stride + p]);
+}
+
+__device__ inline uint32_t vertex_hit(const SceneDev& S, uint32_t p, uint32_t j) {
+  return __float_as_uint(S.pos[(size_t)(j - 1) * S.stride + p].w);
+}
+
+__device__ inline float3 energy_row(const SceneDev& S, uint32_t p, uint32_t row) {
+  return xyz(S.energy[(size_t)row * S.stride + p]);
+}
+
+__device__ inline void put_photon(const SceneDev& S, uint32_t p, uint32_t row, float3 x, uint32_t gid, float3 e) {
+  size_t i = (size_t)row * S.stride + p;
+  S.pos[i] = make_float4(x.x, x.y, x.z, __uint_as_float(gid));
+  S.energy[i] = make_float4(e.x, e.y, e.z, S.radius);
+}
+
+// material of a stored hit id (ids beyond the scene map to material 0)
+__device__ inline uint32_t mat_of(const SceneDev& S, uint32_t hit) {
+  return hit < S.n_tris_total ? S.tri_mat[hit] : 0u;
+}
+
+__device__ inline float3 reflect_energy(const SceneDev& S, float3 e, uint32_t mat) {
+  const float* rho = S.albedo + 3 * mat;
+  return f3(__fmul_rn(e.x, rho[0]), __fmul_rn(e.y, rho[1]), __fmul_rn(e.z, rho[2]));
+}
+
+struct RCount {
+  uint32_t rays, photons, accepted, truncated;
+};
+
+// new bounces from the photon in 'row' (position x, arriving direction w,
+// triangle normal n_tri, material mat, energy e) up to B photons
+__device__ inline uint32_t naive_tail(const SceneDev& S, uint32_t p, uint32_t row, float3 x, float3 w, float3 ntri,
+                                      uint32_t mat, float3 e, uint64_t seed, uint32_t frame, Stack& st, RCount& rc) {
+  while (row + 1 < S.B) {
+    float3 n = dot(ntri, w) > 0.0f ? mul(ntri, -1.0f) : ntri;
+    float u[4];
+    draw4(seed, p, frame, row + 1, 1, u);
+    float3 l = cosine_local(u[0], u[1]);
+    float3 t, b;
+    onb(n, &t, &b);
+    float3 wn = add(add(mul(t, l.x), mul(b, l.y)), mul(n, l.z));
+    Hit h = closest_hit(S, x, wn, st);
+    ++rc.rays;
+    if (h.gid == kHitNone) {
+      ++rc.truncated;
+      break;
+    }
+    float3 xn = add(x, mul(wn, h.t));
+    float3 en = reflect_energy(S, e, mat);
+    ++row;
+    put_photon(S, p, row, xn, h.gid, en);
+    ++rc.photons;
+    x = xn;
+    w = wn;
+    ntri = hit_normal(h);
+    mat = hit_material(h);
+    e = en;
+  }
+  return row + 1;
+}
+
+// trace segment k from x_k along unit w, then continue naively
+__device__ inline uint32_t naive_from(const SceneDev& S, uint32_t p, uint32_t k, float3 xk, float3 w, int l,
+                                      uint64_t seed, uint32_t frame, Stack& st, RCount& rc) {
+  Hit h = closest_hit(S, xk, w, st);
+  ++rc.rays;
+  if (h.gid == kHitNone) {
+    ++rc.truncated;
+    return k;
+  }
+  float3 xn = add(xk, mul(w, h.t));
+  float3 en;
+  if (k == 0) {
+    float N = (float)S.lights[l].path_count;
+    en = f3(__fdiv_rn(S.lights[l].power[0], N), __fdiv_rn(S.lights[l].power[1], N),
+            __fdiv_rn(S.lights[l].power[2], N));
+  } else {
+    en = reflect_energy(S, energy_row(S, p, k - 1), mat_of(S, vertex_hit(S, p, k)));
+  }
+  put_photon(S, p, k, xn, h.gid, en);
+  ++rc.photons;
+  return naive_tail(S, p, k, xn, w, hit_normal(h), hit_material(h), en, seed, frame, st, rc);
+}
+
+__device__ inline bool eq2(float3 en, float3 eo, float T) {
+  float d0 = __fsub_rn(en.x, eo.x), d1 = __fsub_rn(en.y, eo.y), d2 = __fsub_rn(en.z, eo.z);
+  float t0 = __fmul_rn(T, eo.x), t1 = __fmul_rn(T, eo.y), t2 = __fmul_rn(T, eo.z);
+  return (-t0 <= d0 && d0 <= t0) && (-t1 <= d1 && d1 <= t1) && (-t2 <= d2 && d2 <= t2);
+}
+
+__device__ inline bool on_moved_obj(const SceneDev& S, uint32_t hit) {
+  if (hit == kHitNone || hit < S.n_static) return false;
+  for (uint32_t o = 0; o < S.n_obj; ++o) {
+    const ObjDev& ob = S.objs[o];
+    if (hit - ob.gbase < ob.n_tris) return S.obj_moved[o] != 0;
+  }
+  return false;
+}
+
+__device__ inline bool seg_blocked_moved(const SceneDev& S, float3 a, float3 b, Stack& st) {
+  Ray r = segment_ray(a, b, S.eps_end);
+  for (uint32_t o = 0; o < S.n_obj; ++o) {
+    if (!S.obj_moved[o]) continue;
+    const float* bx = S.obj_aabb + 6 * o;
+    if (box_entry(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, r.tmax) == __builtin_inff()) continue;
+    if (bvh_any(S.dnodes, S.dtris, S.objs[o].root, r, st)) return true;
+  }
+  return false;
+}
+
+__device__ inline void clear_rows(const SceneDev& S, uint32_t p, uint32_t from) {
+  for (uint32_t r = from; r < S.B; ++r) {
+    size_t i = (size_t)r * S.stride + p;
+    S.pos[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(kHitNone));
+    S.energy[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
+__device__ inline float3 normalize3(float3 v) { return mul(v, 1.0f / length(v)); }
+
+__device__ void retrace_path(const SceneDev& S, uint32_t p, float T, uint64_t seed, uint32_t frame, Stack& st,
+                             RCount& rc) {
+  uint32_t w = S.info[p];
+  if (!info_replace(w)) return;
+  uint32_t n = min(info_nseg(w), S.B), k = info_start(w), cell = info_cell(w);
+  int l = light_of(S, p);
+  if (l < 0) return;
+  bool reuse = info_reuse(w) != 0;
+  if (k >= n) {  // nothing to keep: a new light sample
+    k = 0;
+    reuse = false;
+  }
+  uint32_t newn;
+  if (k == 0 && !reuse) {
+    // new light sample: position uniform on the rectangle, direction
+    // cosine-weighted about the light normal (one Philox draw, tag 0)
+    const float* xf = S.light_xf_cur + 12 * l;
+    float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
+    float3 nl = normalize3(f3(xf[2], xf[6], xf[10])), c = f3(xf[3], xf[7], xf[11]);
+    float u[4];
+    draw4(seed, p, frame, 0, 0, u);
+    float a = (2.0f * u[0] - 1.0f) * S.lights[l].half[0], b = (2.0f * u[1] - 1.0f) * S.lights[l].half[1];
+    float3 x0 = add(c, add(mul(eu, a), mul(ev, b)));
+    float3 lc = cosine_local(u[2], u[3]);
+    float3 w0 = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
+    const size_t stride = S.stride;
+    S.origin[p] = x0.x;
+    S.origin[stride + p] = x0.y;
+    S.origin[2 * stride + p] = x0.z;
+    newn = naive_from(S, p, 0, x0, w0, l, seed, frame, st, rc);
+  } else if (T < 0.0f) {
+    float3 xa = vertex(S, p, k), xb = vertex(S, p, k + 1);
+    newn = naive_from(S, p, k, xa, normalize3(sub(xb, xa)), l, seed, frame, st, rc);
+  } else {
+    // Algorithm 1: trace iff blocked, origin moved or end photon on a moved
+    // object; keep the rest of the path when Equation 2 holds
+    uint32_t j = k;
+    bool need = true;
+    newn = n;
+    while (j < newn) {
+      float3 xa = vertex(S, p, j), xb = vertex(S, p, j + 1);
+      if (!need) {
+        bool inv = on_moved_obj(S, vertex_hit(S, p, j + 1));
+        if (!inv) inv = seg_blocked_moved(S, xa, xb, st);
+        if (!inv) {
+          ++j;
+          continue;
+        }
+      }
+      float3 d = normalize3(sub(xb, xa));
+      Hit h = closest_hit(S, xa, d, st);
+      ++rc.rays;
+      if (h.gid == kHitNone) {
+        newn = j;
+        ++rc.truncated;
+        break;
+      }
+      float3 hp = add(xa, mul(d, h.t));
+      float3 ej = energy_row(S, p, j);
+      if (j == newn - 1) {
+        put_photon(S, p, j, hp, h.gid, ej);
+        ++rc.photons;
+        break;
+      }
+      float3 xc = vertex(S, p, j + 2);
+      float3 d2 = sub(xc, hp);
+      float3 nh = hit_normal(h);
+      float c1 = dot(d, nh), l2 = length(d2);
+      float c2 = l2 > 0.0f ? dot(d2, nh) / l2 : 0.0f;
+      uint32_t mat = hit_material(h);
+      float3 en = (c1 * c2 < 0.0f) ? reflect_energy(S, ej, mat) : f3(0.0f, 0.0f, 0.0f);
+      float3 eo = energy_row(S, p, j + 1);
+      if (!eq2(en, eo, T)) {
+        put_photon(S, p, j, hp, h.gid, ej);
+        ++rc.photons;
+        newn = naive_tail(S, p, j, hp, d, nh, mat, ej, seed, frame, st, rc);
+        break;
+      }
+      ++rc.accepted;
+      float dist = length(sub(hp, xb));
+      if (dist <= S.eps_close && !on_moved_obj(S, h.gid) && !on_moved_obj(S, vertex_hit(S, p, j + 1)) &&
+          !on_moved_obj(S, vertex_hit(S, p, j + 2)) && !seg_blocked_moved(S, xb, xc, st)) {
+        j += 2;
+        need = false;
+        continue;
+      }
+      put_photon(S, p, j, hp, h.gid, ej);
+      ++rc.photons;
+      ++j;
+      need = true;
+    }
+  }
+  clear_rows(S, p, newn);
+  S.info[p] = info_pack(cell, newn, 0, 0, 0);
+}
+
+__device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_t gp) {
+  int lo = 0, hi = n_scenes;  // gbase[s] <= gp < gbase[s+1]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (gbase[mid] <= gp)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_retrace(const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ gbase,
+                                                    int n_scenes, const uint32_t* __restrict__ queue,
+                                                    const uint32_t* __restrict__ qcount, uint32_t* head, float T,
+                                                    uint64_t seed, uint32_t frame, pv_stats* stats) {
+  __shared__ uint32_t sstack[kLdsStack * kBlock];
+  __shared__ unsigned long long sred[kBlock / 64];
+  Stack st;
+  st.lds = sstack + threadIdx.x;
+  st.sp = 0;
+  RCount rc = {0, 0, 0, 0};
+  const uint32_t count = *qcount;
+  while (true) {
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(head, 64u);
+    base = __shfl(base, 0, 64);
+    if (base >= count) break;
+    uint32_t qi = base + lane_id();
+    if (qi < count) {
+      uint32_t gp = queue[qi];
+      uint32_t s = scene_of(gbase, n_scenes, gp);
+      retrace_path(scenes[s], gp - gbase[s], T, seed, frame, st, rc);
+    }
+  }
+  if (stats) {
+    unsigned long long a = block_sum_u64(rc.rays, sred);
+    unsigned long long b = block_sum_u64(rc.photons, sred);
+    unsigned long long c = block_sum_u64(rc.accepted, sred);
+    unsigned long long d = block_sum_u64(rc.truncated, sred);
+    if (threadIdx.x == 0) {
+      atomicAdd(&stats->rays_traced, a);
+      atomicAdd(&stats->photons_written, b);
+      atomicAdd(&stats->reuse_accepted, c);
+      atomicAdd(&stats->paths_truncated, d);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// compaction of existing photons: counts per (row, block), scan, scatter
+
+__global__ __launch_bounds__(kBlock) void k_photon_count(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
+                                                         uint32_t n_blocks, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t wc[PV_MAX_BOUNCES][kBlock / 64];
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  uint32_t p = tile.y + threadIdx.x;
+  uint32_t n = p < S.n_paths ? min(info_nseg(S.info[p]), S.B) : 0u;
+  for (uint32_t r = 0; r < S.B; ++r) {
+    uint64_t bal = __ballot(n > r);
+    if (lane_id() == 0) wc[r][threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+  }
+  __syncthreads();
+  if (threadIdx.x < S.B) {
+    uint32_t c = 0;
+    for (int w = 0; w < kBlock / 64; ++w) c += wc[threadIdx.x][w];
+    counts[threadIdx.x * n_blocks + blockIdx.x] = c;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_photon_scatter(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
+                                                           uint32_t n_blocks, const uint32_t* __restrict__ offsets,
+                                                           float* __restrict__ out_pos, float* __restrict__ out_e,
+                                                           uint32_t capacity) {
+  __shared__ uint32_t wcnt[kBlock / 64];
+  uint32_t r = blockIdx.y;
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  if (r >= S.B) return;
+  uint32_t p = tile.y + threadIdx.x;
+  bool flag = p < S.n_paths && min(info_nseg(S.info[p]), S.B) > r;
+  uint64_t bal = __ballot(flag);
+  if (lane_id() == 0) wcnt[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t pre = 0;
+  for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) pre += wcnt[w];
+  if (!flag) return;
+  uint32_t idx = offsets[r * n_blocks + blockIdx.x] + pre + (uint32_t)__popcll(bal & lanemask_lt());
+  if (idx >= capacity) return;
+  size_t i = (size_t)r * S.stride + p;
+  float4 x = S.pos[i], e = S.energy[i];
+  out_pos[3 * (size_t)idx + 0] = x.x;
+  out_pos[3 * (size_t)idx + 1] = x.y;
+  out_pos[3 * (size_t)idx + 2] = x.z;
+  out_e[3 * (size_t)idx + 0] = e.x;
+  out_e[3 * (size_t)idx + 1] = e.y;
+  out_e[3 * (size_t)idx + 2] = e.z;
+}
+
+// ---------------------------------------------------------------------------
+// differentiation form
+
+__global__ __launch_bounds__(kBlock) void k_energy_fwd(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
+                                                       const float* __restrict__ albedo, const float* __restrict__ power,
+                                                       float* __restrict__ E) {
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  uint32_t p = tile.y + threadIdx.x;
+  if (p >= S.n_paths) return;
+  uint32_t n = min(info_nseg(S.info[p]), S.B);
+  int l = light_of(S, p);
+  if (l < 0) return;
+  float N = (float)S.lights[l].path_count;
+  float3 e = f3(__fdiv_rn(power[3 * l], N), __fdiv_rn(power[3 * l + 1], N), __fdiv_rn(power[3 * l + 2], N));
+  const size_t np = S.n_paths;
+  for (uint32_t r = 0; r < S.B; ++r) {
+    float* o = E + 3 * ((size_t)r * np + p);
+    if (r < n) {
+      if (r > 0) {
+        uint32_t m = mat_of(S, __float_as_uint(S.pos[(size_t)(r - 1) * S.stride + p].w));
+        e = f3(__fmul_rn(e.x, albedo[3 * m]), __fmul_rn(e.y, albedo[3 * m + 1]), __fmul_rn(e.z, albedo[3 * m + 2]));
+      }
+      o[0] = e.x;
+      o[1] = e.y;
+      o[2] = e.z;
+    } else {
+      o[0] = o[1] = o[2] = 0.0f;
+    }
+  }
+}
+
+// One thread per path.  With P_j = prod_{i<j} rho_i (photon j has energy
+// Phi/N * P_j) and R_i = g_{i+1} + rho_{i+1} R_{i+1} (R_{n-1} = 0, photon
+// rows 0..n-1, vertex i = row i), the contribution of vertex i to the
+// albedo gradient is Phi/N * P_i * R_i (division free), and the power
+// gradient is sum_j g_j P_j / N.  Block partials (LDS atomics) go to
+// partial[block][M*3 + L*3] for a deterministic FP64 reduction.
+__global__ __launch_bounds__(kBlock) void k_energy_bwd(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
+                                                       const float* __restrict__ albedo, const float* __restrict__ power,
+                                                       const float* __restrict__ gE, uint32_t n_mat,
+                                                       float* __restrict__ partial) {
+  extern __shared__ float acc[];  // n_mat*3 + n_lights*3
+  uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  const uint32_t width = 3 * (n_mat + S.n_lights);
+  for (uint32_t i = threadIdx.x; i < width; i += blockDim.x) acc[i] = 0.0f;
+  __syncthreads();
+  uint32_t p = tile.y + threadIdx.x;
+  if (p < S.n_paths) {
+    uint32_t n = min(info_nseg(S.info[p]), S.B);
+    int l = light_of(S, p);
+    if (l < 0) n = 0;
+    float N = l >= 0 ? (float)S.lights[l].path_count : 1.0f;
+    const size_t np = S.n_paths;
+    uint32_t mats[PV_MAX_BOUNCES];
+    for (uint32_t r = 0; r + 1 < n; ++r) mats[r] = mat_of(S, __float_as_uint(S.pos[(size_t)r * S.stride + p].w));
+    for (int c = 0; c < 3; ++c) {
+      // prefix products P_r for r = 0..n-1
+      float P[PV_MAX_BOUNCES];
+      float pr = 1.0f;
+      float gp = 0.0f;
+      for (uint32_t r = 0; r < n; ++r) {
+        if (r > 0) pr *= albedo[3 * mats[r - 1] + c];
+        P[r] = pr;
+        gp += gE[3 * ((size_t)r * np + p) + c] * pr;
+      }
+      if (n == 0) break;
+      atomicAdd(&acc[3 * n_mat + 3 * l + c], gp / N);
+      float scale = power[3 * l + c] / N;
+      float R = 0.0f;
+      for (int i = (int)n - 2; i >= 0; --i) {
+        // R_i = g_{i+1} + rho_{i+1} R_{i+1}
+        float g1 = gE[3 * ((size_t)(i + 1) * np + p) + c];
+        float rho1 = (i + 1 <= (int)n - 2) ? albedo[3 * mats[i + 1] + c] : 0.0f;
+        R = g1 + rho1 * R;
+        atomicAdd(&acc[3 * mats[i] + c], scale * P[i] * R);
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < width; i += blockDim.x) partial[(size_t)blockIdx.x * width + i] = acc[i];
+}
+
+__global__ void k_reduce_partials(const float* __restrict__ partial, uint32_t n_blocks, uint32_t width,
+                                  float* __restrict__ g_albedo, uint32_t n_mat3, float* __restrict__ g_power) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= width) return;
+  double s = 0.0;
+  for (uint32_t b = 0; b < n_blocks; ++b) s += (double)partial[(size_t)b * width + i];
+  if (i < n_mat3)
+    g_albedo[i] = (float)s;
+  else
+    g_power[i - n_mat3] = (float)s;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (host side)
+
+hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
+                              const float* const* light_in, uint32_t* state, hipStream_t s) {
+  hipLaunchKernelGGL(k_frame_begin, dim3(n_scenes), dim3(64), 0, s, scenes, n_scenes, obj_in, light_in, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_transform(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_transform, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_refit(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_refit, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
+                         pv_stats* stats, hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_verify, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, block_cnt, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total, head);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_queue(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* offsets,
+                                uint32_t* queue, hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_queue, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, offsets, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
+                           hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_all, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, block_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
+                          const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
+                          pv_stats* stats, uint32_t n_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_retrace, dim3(n_blocks), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head, T,
+                     seed, frame, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
+                               hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_photon_count, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, n_tiles, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t B,
+                                 const uint32_t* offsets, float* out_pos, float* out_e, uint32_t capacity,
+                                 hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_photon_scatter, dim3(n_tiles, B), dim3(kBlock), 0, s, scenes, tiles, n_tiles, offsets, out_pos,
+                     out_e, capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_fwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,
+                             const float* power, float* E, hipStream_t s) {
+  if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_energy_fwd, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, albedo, power, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_bwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,
+                             const float* power, const float* gE, uint32_t n_mat, uint32_t n_lights, float* partial,
+                             float* g_albedo, float* g_power, hipStream_t s) {
+  uint32_t width = 3 * (n_mat + n_lights);
+  if (n_tiles) {
+    hipLaunchKernelGGL(k_energy_bwd, dim3(n_tiles), dim3(kBlock), width * sizeof(float), s, scenes, tiles, albedo,
+                       power, gE, n_mat, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_reduce_partials, dim3((width + 255) / 256), dim3(256), 0, s, partial, n_tiles, width, g_albedo,
+                     3 * n_mat, g_power);
+  return hipGetLastError();
+}
+
+}  // namespace pv

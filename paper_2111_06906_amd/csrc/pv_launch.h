@@ -1,0 +1,35 @@
+// Host-callable launch wrappers of the library's kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pv_device.h"
+
+namespace pv {
+
+hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
+                              const float* const* light_in, uint32_t* state, hipStream_t s);
+hipError_t launch_transform(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
+hipError_t launch_refit(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
+hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
+                         pv_stats* stats, hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
+                       hipStream_t s);
+hipError_t launch_scatter_queue(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* offsets,
+                                uint32_t* queue, hipStream_t s);
+hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
+                           hipStream_t s);
+hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
+                          const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
+                          pv_stats* stats, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
+                               hipStream_t s);
+hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t B,
+                                 const uint32_t* offsets, float* out_pos, float* out_e, uint32_t capacity,
+                                 hipStream_t s);
+hipError_t launch_energy_fwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,
+                             const float* power, float* E, hipStream_t s);
+hipError_t launch_energy_bwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,
+                             const float* power, const float* gE, uint32_t n_mat, uint32_t n_lights, float* partial,
+                             float* g_albedo, float* g_power, hipStream_t s);
+
+}  // namespace pv

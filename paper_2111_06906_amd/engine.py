@@ -1,0 +1,188 @@
+"""Python-side owner of a scene context and its device path store.
+
+PyTorch only provides device memory and the stream; every computation is a
+call into libpv.so through the ctypes binding.  On a machine without a HIP
+device, constructing a Context raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .scenes import Scene
+
+F32 = torch.float32
+I32 = torch.int32
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Store:
+    """Device path store (layout of include/pv.h)."""
+
+    def __init__(self, n_paths, max_bounces, device="cuda"):
+        if not 1 <= max_bounces <= L.PV_MAX_BOUNCES:
+            raise ValueError("max_bounces out of range")
+        self.n_paths = int(n_paths)
+        self.B = int(max_bounces)
+        self.stride = max(64, (self.n_paths + 63) // 64 * 64)
+        self.pos_hit = torch.zeros((self.B, self.stride, 4), dtype=F32, device=device)
+        self.pos_hit.view(I32)[:, :, 3] = -1  # hit = 0xFFFFFFFF
+        self.energy = torch.zeros((self.B, self.stride, 4), dtype=F32, device=device)
+        self.origin = torch.zeros((3, self.stride), dtype=F32, device=device)
+        self.info = torch.zeros((self.stride,), dtype=I32, device=device)
+
+    def cstruct(self):
+        return L.PathStore(self.n_paths, self.B, self.stride, self.pos_hit.data_ptr(), self.energy.data_ptr(),
+                           self.origin.data_ptr(), self.info.data_ptr())
+
+    # plain layout used by the tests: pos [B,N,3], hit [B,N], energy [B,N,3],
+    # radius [B,N], origin [N,3], info [N] (layout conversion only)
+    def to_numpy(self, cols=None):
+        n = self.n_paths
+        ph = self.pos_hit[:, :n].cpu().numpy()
+        en = self.energy[:, :n].cpu().numpy()
+        d = dict(pos=np.ascontiguousarray(ph[..., :3]),
+                 hit=np.ascontiguousarray(ph[..., 3]).view(np.uint32),
+                 energy=np.ascontiguousarray(en[..., :3]), radius=np.ascontiguousarray(en[..., 3]),
+                 origin=np.ascontiguousarray(self.origin[:, :n].cpu().numpy().T),
+                 info=self.info[:n].cpu().numpy().view(np.uint32).copy())
+        if cols is not None:
+            cols = np.asarray(cols)
+            d = {k: (np.ascontiguousarray(v[:, cols]) if k in ("pos", "hit", "energy", "radius")
+                     else np.ascontiguousarray(v[cols])) for k, v in d.items()}
+        return d
+
+    def load_numpy(self, d, cols=None):
+        """Write plain-layout arrays into all columns, or into the given ones."""
+        dev = self.pos_hit.device
+        ph = np.concatenate([d["pos"], d["hit"].view(np.float32)[..., None]], axis=-1).astype(np.float32)
+        en = np.concatenate([d["energy"], d["radius"][..., None]], axis=-1).astype(np.float32)
+        idx = torch.arange(self.n_paths, device=dev) if cols is None else torch.as_tensor(
+            np.asarray(cols, np.int64), device=dev)
+        self.pos_hit[:, idx] = torch.from_numpy(ph).to(dev)
+        self.energy[:, idx] = torch.from_numpy(en).to(dev)
+        self.origin[:, idx] = torch.from_numpy(np.ascontiguousarray(d["origin"].T)).to(dev)
+        self.info[idx] = torch.from_numpy(d["info"].astype(np.uint32).view(np.int32)).to(dev)
+
+
+class Context:
+    """One scene on the device: upload, per-frame transforms, the method's calls."""
+
+    def __init__(self, scene: Scene, max_paths=None, max_bounces=None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.scene = scene
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ctx = L.create(C.c_void_p(self.stream.cuda_stream))
+        self._upload(scene)
+        counts = np.ascontiguousarray(scene.light_paths, np.uint32)
+        L.set_light_paths(self.ctx, _np_ptr(counts))
+        self.max_paths = int(max_paths or scene.n_paths)
+        self.max_bounces = int(max_bounces or scene.max_bounces)
+        L.reserve(self.ctx, self.max_paths, self.max_bounces)
+        self.obj_xf = torch.from_numpy(np.ascontiguousarray(scene.obj_xforms, np.float32)).cuda()
+        self.light_xf = torch.from_numpy(np.ascontiguousarray(scene.light_xforms, np.float32)).cuda()
+        if self.obj_xf.numel() == 0:
+            self.obj_xf = torch.zeros((scene.n_frames, 1, 12), dtype=F32, device="cuda")
+
+    def _upload(self, sc: Scene):
+        sv = np.ascontiguousarray(sc.static_verts.reshape(-1, 9), np.float32)
+        sm = np.ascontiguousarray(sc.static_mat, np.uint32)
+        ot = np.ascontiguousarray([o.shape[0] for o in sc.obj_local] or [0], np.uint32)
+        ov = np.ascontiguousarray(np.concatenate([o.reshape(-1, 9) for o in sc.obj_local]) if sc.obj_local
+                                  else np.zeros((1, 9)), np.float32)
+        om = np.ascontiguousarray(np.concatenate(sc.obj_mat) if sc.obj_mat else np.zeros(1), np.uint32)
+        alb = np.ascontiguousarray(sc.albedo, np.float32)
+        lh = np.ascontiguousarray(sc.light_half, np.float32)
+        lp = np.ascontiguousarray(sc.light_power, np.float32)
+        self._keep = (sv, sm, ot, ov, om, alb, lh, lp)
+        desc = L.SceneDesc(sv.shape[0], _np_ptr(sv), _np_ptr(sm), len(sc.obj_local), _np_ptr(ot), _np_ptr(ov),
+                           _np_ptr(om), alb.shape[0], _np_ptr(alb), lh.shape[0], _np_ptr(lh), _np_ptr(lp),
+                           sc.eps_end, sc.eps_close, sc.photon_radius)
+        L.upload_scene(self.ctx, desc)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_store(self, n_paths=None):
+        return Store(n_paths or self.scene.n_paths, self.scene.max_bounces)
+
+    def new_stats(self):
+        return torch.zeros(len(L.STAT_FIELDS), dtype=torch.int64, device="cuda")
+
+    @staticmethod
+    def stats_dict(t):
+        return dict(zip(L.STAT_FIELDS, t.cpu().tolist()))
+
+    # --- the method's calls ---------------------------------------------
+    def frame_begin(self, frame):
+        L.frame_begin(self.ctx, _ptr(self.obj_xf[frame]), _ptr(self.light_xf[frame]))
+
+    def verify(self, store, stats=None, build_queue=True):
+        L.verify_paths(self.ctx, store.cstruct(), _ptr(stats))
+        if build_queue:
+            L.build_queue(self.ctx, store.cstruct())
+
+    def build_queue(self, store):
+        L.build_queue(self.ctx, store.cstruct())
+
+    def queue_all(self, store):
+        L.queue_all(self.ctx, store.cstruct())
+
+    def queue(self):
+        out = torch.zeros(self.max_paths, dtype=I32, device="cuda")
+        cnt = torch.zeros(1, dtype=I32, device="cuda")
+        L.copy_queue(self.ctx, _ptr(out), self.max_paths, _ptr(cnt))
+        n = int(cnt.item())
+        return out[:n].cpu().numpy().view(np.uint32)
+
+    def retrace(self, store, threshold, seed, frame, stats=None):
+        L.retrace_paths(self.ctx, store.cstruct(), float(threshold), int(seed), int(frame), _ptr(stats))
+
+    def compact_photons(self, store, capacity=None):
+        cap = store.n_paths * store.B if capacity is None else int(capacity)
+        pos = torch.zeros((max(cap, 1), 3), dtype=F32, device="cuda")
+        en = torch.zeros((max(cap, 1), 3), dtype=F32, device="cuda")
+        cnt = torch.zeros(1, dtype=I32, device="cuda")
+        L.compact_photons(self.ctx, store.cstruct(), _ptr(pos), _ptr(en), cap, _ptr(cnt))
+        n = int(cnt.item())
+        return pos[:min(n, cap)], en[:min(n, cap)], n
+
+    def compact_photons_into(self, store, pos, en, cnt):
+        """Compaction into preallocated outputs; no host synchronisation."""
+        L.compact_photons(self.ctx, store.cstruct(), _ptr(pos), _ptr(en), pos.shape[0], _ptr(cnt))
+
+    def energy_forward(self, store, albedo, power):
+        E = torch.empty((store.B, store.n_paths, 3), dtype=F32, device="cuda")
+        L.energy_forward(self.ctx, store.cstruct(), _ptr(albedo.contiguous()), _ptr(power.contiguous()), _ptr(E))
+        return E
+
+    def energy_backward(self, store, albedo, power, gE):
+        ga = torch.empty_like(albedo)
+        gp = torch.empty_like(power)
+        L.energy_backward(self.ctx, store.cstruct(), _ptr(albedo.contiguous()), _ptr(power.contiguous()),
+                          _ptr(gE.contiguous()), _ptr(ga), _ptr(gp))
+        return ga, gp
+
+    def initial_trace(self, store, seed, frame=0, stats=None):
+        """Frame-0 photon paths (every path a new light sample)."""
+        self.queue_all(store)
+        self.retrace(store, -1.0, seed, frame, stats)

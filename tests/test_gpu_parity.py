@@ -1,0 +1,236 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Inputs come from the seeded scene generator; every oracle input is either
+generated or produced by the oracle itself (its own frame-0 trace), never by
+the HIP path.  The GPU receives the oracle's frame-0 store, so both sides
+verify and re-trace identical FP32 data.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_06906_amd import scenes
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2111_06906_amd import engine
+    return engine
+
+
+def _amb_ok(*ambs):
+    m = None
+    for a in ambs:
+        m = (a == 0) if m is None else (m & (a == 0))
+    return m
+
+
+def _setup(E, sc, frames_done=(0,)):
+    ctx = E.Context(sc)
+    for f in frames_done:
+        ctx.frame_begin(f)
+    return ctx
+
+
+def _oracle_frame0(sc):
+    fs0 = O.frame_scene(sc, 0)
+    st, amb, tr = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    return st, amb
+
+
+# ---------------------------------------------------------------------------
+# tiny configuration: the full path, element by element
+
+
+def test_tiny_initial_trace(E):
+    sc = scenes.make_tiny(n_paths=16384 + 77)  # ragged last tile
+    log("tiny initial trace N=%d B=%d" % (sc.n_paths, sc.max_bounces))
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    stats = ctx.new_stats()
+    ctx.initial_trace(st, sc.seed, 0, stats)
+    gpu = st.to_numpy()
+    ora, amb = _oracle_frame0(sc)
+    ok = _amb_ok(amb)
+    log("  ambiguous paths excluded: %d" % (~ok).sum())
+    assert (~ok).sum() < 0.01 * sc.n_paths
+    H.compare_stores(gpu, ora, ok, "frame0")
+    s = ctx.stats_dict(stats)
+    assert s["photons_written"] == int(((gpu["info"] >> 22) & 15).sum())
+
+
+def test_tiny_verify_queue_and_retrace(E):
+    sc = scenes.make_tiny(n_paths=16384 + 77)
+    ora0, amb0 = _oracle_frame0(sc)
+    for T in (-1.0, 0.0, 0.01, 0.5):
+        log("tiny frame 1 T=%g" % T)
+        ctx = _setup(E, sc)
+        st = ctx.new_store()
+        st.load_numpy(H.from_oracle(ora0))
+        ctx.frame_begin(1)
+        stats = ctx.new_stats()
+        ctx.verify(st, stats)
+        gpu_v = st.to_numpy()
+        q = ctx.queue()
+        ora = ora0.copy()
+        ambv, ex = O.verify(O.frame_scene(sc, 1, 0), ora)
+        ok = _amb_ok(amb0, ambv)
+        # verification: bit-exact info words and origins outside the bands
+        assert np.array_equal(gpu_v["info"][ok], ora.info[ok])
+        assert np.array_equal(gpu_v["origin"], ora.origin)
+        # queue: ascending ids of the GPU's replaced paths; equal to the oracle's
+        rep = np.flatnonzero((gpu_v["info"] >> 30) & 1)
+        assert np.array_equal(q, rep)
+        oq = O.queue(ora.info)
+        assert np.array_equal(q[ok[q]], oq[ok[oq]])
+        s = ctx.stats_dict(stats)
+        assert s["paths_invalid"] == rep.size
+        if ok.all():
+            assert s["segments_examined"] == int(ex.sum())
+        log("  replaced %d of %d, ambiguous %d" % (rep.size, sc.n_paths, (~ok).sum()))
+        assert rep.size > 100
+        # re-trace
+        ctx.retrace(st, T, sc.seed, 1, stats)
+        gpu_r = st.to_numpy()
+        ambr, tr = O.retrace(O.frame_scene(sc, 1, 0), ora, T, sc.seed, 1)
+        ok2 = ok & _amb_ok(ambr)
+        log("  retrace: excluded %d" % (~ok2).sum())
+        H.compare_stores(gpu_r, ora, ok2, "retrace T=%g" % T)
+        s = ctx.stats_dict(stats)
+        if ok2.all():
+            assert s["rays_traced"] == int(tr.sum())
+        ctx.close()
+
+
+def test_static_frame_reuses_everything(E):
+    sc = scenes.make_tiny(n_paths=4096)
+    ora0, _ = _oracle_frame0(sc)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    st.load_numpy(H.from_oracle(ora0))
+    before = st.to_numpy()
+    ctx.frame_begin(0)  # same transforms again: nothing moved
+    ctx.verify(st)
+    after = st.to_numpy()
+    assert ctx.queue().size == 0
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    ctx.retrace(st, 0.01, sc.seed, 1)
+    again = st.to_numpy()
+    for k in before:
+        assert np.array_equal(before[k], again[k]), k
+
+
+def test_compact_photons_exact(E):
+    sc = scenes.make_tiny(n_paths=5000)
+    ora0, _ = _oracle_frame0(sc)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    st.load_numpy(H.from_oracle(ora0))
+    pos, en, n = ctx.compact_photons(st)
+    rp, re = O.compact_photons(ora0)
+    assert n == rp.shape[0]
+    assert np.array_equal(pos.cpu().numpy(), rp) and np.array_equal(en.cpu().numpy(), re)
+    # capacity below the count: the true count is reported, only the first entries written
+    pos2, en2, n2 = ctx.compact_photons(st, capacity=1000)
+    assert n2 == n and np.array_equal(pos2.cpu().numpy(), rp[:1000])
+
+
+def test_max_bounces_fifteen(E):
+    sc = scenes.make_tiny(n_paths=2048, max_bounces=15)
+    log("tiny B=15")
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    ctx.initial_trace(st, sc.seed, 0)
+    gpu = st.to_numpy()
+    ora, amb = _oracle_frame0(sc)
+    H.compare_stores(gpu, ora, _amb_ok(amb), "B=15 frame0")
+    assert ((gpu["info"] >> 22) & 15).max() == 15
+
+
+# ---------------------------------------------------------------------------
+# room scenes: several frames in lockstep (each frame both sides start from
+# the oracle's store of the previous frame)
+
+
+def _lockstep(E, sc, n_frames, T, label):
+    ora, amb0 = _oracle_frame0(sc)
+    ok_paths = _amb_ok(amb0)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    total_rep = 0
+    for f in range(1, n_frames):
+        log("%s frame %d T=%g N=%d" % (label, f, T, sc.n_paths))
+        st.load_numpy(H.from_oracle(ora))
+        ctx.frame_begin(f)
+        ctx.verify(st)
+        gv = st.to_numpy()
+        fs = O.frame_scene(sc, f, f - 1)
+        ambv, _ = O.verify(fs, ora)
+        ok = ok_paths & _amb_ok(ambv)
+        assert np.array_equal(gv["info"][ok], ora.info[ok])
+        assert np.abs(gv["origin"][ok] - ora.origin[ok]).max(initial=0) <= H.POS_TOL
+        total_rep += int(((gv["info"] >> 30) & 1).sum())
+        ctx.retrace(st, T, sc.seed, f)
+        gr = st.to_numpy()
+        ambr, _ = O.retrace(fs, ora, T, sc.seed, f)
+        ok2 = ok & _amb_ok(ambr)
+        log("  excluded %d of %d" % ((~ok2).sum(), sc.n_paths))
+        assert (~ok2).sum() <= 0.05 * sc.n_paths
+        H.compare_stores(gr, ora, ok2, "%s frame %d" % (label, f))
+        ok_paths = ok2
+    assert total_rep > 0
+    ctx.close()
+
+
+def test_mid_rooms_lockstep(E):
+    sc = scenes.make_mid(n_paths=6000 + 19, frames=4)
+    _lockstep(E, sc, 4, -1.0, "mid naive")
+
+
+def test_mid_rooms_lockstep_error_based(E):
+    sc = scenes.make_mid(n_paths=6000 + 19, frames=4, threshold=0.01)
+    _lockstep(E, sc, 4, 0.01, "mid error-based")
+
+
+def test_paper_rooms_moving_lights(E):
+    sc = scenes.make_paper(n_paths=4096 + 13, frames=3)
+    _lockstep(E, sc, 3, 0.01, "paper")
+
+
+# ---------------------------------------------------------------------------
+# differentiation form
+
+
+def test_energy_forward_backward(E):
+    import torch
+    sc = scenes.make_mid(n_paths=4096 + 5, frames=2)
+    ora0, _ = _oracle_frame0(sc)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    st.load_numpy(H.from_oracle(ora0))
+    rng = np.random.default_rng(5)
+    alb = rng.uniform(0.3, 0.8, (sc.albedo.shape[0], 3)).astype(np.float32)
+    pw = rng.uniform(0.5, 2.0, (sc.light_power.shape[0], 3)).astype(np.float32)
+    Eg = ctx.energy_forward(st, torch.from_numpy(alb).cuda(), torch.from_numpy(pw).cuda()).cpu().numpy()
+    fs0 = O.frame_scene(sc, 0)
+    Eo = O.energy_forward(fs0, ora0, alb.astype(np.float64), pw.astype(np.float64))
+    nz = Eo != 0
+    assert np.array_equal(Eg == 0, ~nz)
+    assert (np.abs(Eg[nz] - Eo[nz]) / Eo[nz]).max() <= 1e-5
+    g = rng.uniform(0, 1, Eg.shape).astype(np.float32)
+    ga, gp = ctx.energy_backward(st, torch.from_numpy(alb).cuda(), torch.from_numpy(pw).cuda(),
+                                 torch.from_numpy(g).cuda())
+    oa, op = O.energy_backward(fs0, ora0, alb.astype(np.float64), pw.astype(np.float64), g.astype(np.float64))
+    np.testing.assert_allclose(ga.cpu().numpy(), oa, rtol=1e-4, atol=1e-12)
+    np.testing.assert_allclose(gp.cpu().numpy(), op, rtol=1e-4, atol=1e-12)

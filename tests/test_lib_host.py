@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every declared symbol; host-only
+utilities and argument checks run without a GPU."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_06906_amd import _lib as L
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    declared = L.declared_symbols()
+    assert "pv_verify_paths" in declared and "pv_retrace_paths" in declared
+    missing = [s for s in declared if not hasattr(lib, s)]
+    assert missing == []
+
+
+def test_store_bytes_reproduce_table1():
+    # Table 1: 5 million paths of at most 7 photons, 32 B per photon
+    MiB = 1024.0 * 1024.0
+    n, B = 5_000_000, 7
+    total = L.store_bytes(n, B)
+    photon_map = n * B * 32
+    assert round(photon_map / MiB) == 1068
+    assert round(n * 4 / MiB, 2) == 19.07          # path information
+    assert round(n * 12 / MiB, 2) == 57.22         # path origin position
+    assert round((total - photon_map) / MiB, 2) == 76.29   # sub-total, reuse with objects
+    assert round(total / MiB) == 1144               # total, reuse with objects
+
+
+def test_info_word_round_trip_and_limits():
+    rng = np.random.default_rng(0)
+    for _ in range(500):
+        cell = int(rng.integers(0, 1 << 22))
+        nseg, start = int(rng.integers(0, 16)), int(rng.integers(0, 16))
+        rep, reuse = int(rng.integers(0, 2)), int(rng.integers(0, 2))
+        w = L.info_pack(cell, nseg, start, rep, reuse)
+        assert L.info_unpack(w) == (cell, nseg, start, rep, reuse)
+        assert w == O.info_make(cell, nseg, start, rep, reuse)
+    # 22 + 4 + 4 + 1 + 1 = 32 bits: the top bit is the reuse-light flag
+    assert L.info_pack(0, 0, 0, 0, 1) == 1 << 31
+    assert L.info_pack((1 << 22) - 1, 15, 15, 1, 1) == 0xFFFFFFFF
+
+
+def test_argument_errors_without_device():
+    lib = L.lib()
+    # NULL context
+    assert lib.pv_upload_scene(None, None) == L.PV_ERR_ARG
+    assert lib.pv_verify_paths(None, None, None) == L.PV_ERR_ARG
+    out = C.c_void_p()
+    code = lib.pv_create(C.byref(out), None)
+    import torch
+    if torch.cuda.is_available():
+        assert code == L.PV_OK
+        lib.pv_destroy(out)
+    else:
+        assert code == L.PV_ERR_HIP
+        assert b"HIP" in lib.pv_last_error(None) or b"device" in lib.pv_last_error(None)
+
+
+def test_declared_symbols_parse():
+    names = L.declared_symbols()
+    for n in ("pv_create", "pv_upload_scene", "pv_frame_begin", "pv_verify_paths", "pv_retrace_paths",
+              "pv_compact_photons", "pv_energy_forward", "pv_energy_backward"):
+        assert n in names
