@@ -140,7 +140,9 @@ void or_cosine_local(double u1, double u2, double out[3]) {
     r = b; phi = PI / 2.0 - (PI / 4.0) * (a / b);
   }
   double x = r * cos(phi), y = r * sin(phi);
-  double z2 = 1.0 - x * x - y * y;
+  /* height on the unit sphere above the disk point at radius |r| */
+  double ar = fabs(r);
+  double z2 = (1.0 - ar) * (1.0 + ar);
   out[0] = x; out[1] = y; out[2] = z2 > 0.0 ? sqrt(z2) : 0.0;
 }
 

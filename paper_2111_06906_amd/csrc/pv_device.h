@@ -362,7 +362,9 @@ __device__ inline float3 cosine_local(float u1, float u2) {
     phi = 2.0f * PI4 - PI4 * (a / b);
   }
   float x = r * cosf(phi), y = r * sinf(phi);
-  float z2 = 1.0f - x * x - y * y;
+  // height above the disk point at radius |r|; (1-|r|) is exact for |r| >= 1/2
+  float ar = fabsf(r);
+  float z2 = (1.0f - ar) * (1.0f + ar);
   return f3(x, y, z2 > 0.0f ? sqrtf(z2) : 0.0f);
 }
 

@@ -64,7 +64,7 @@ def test_tiny_initial_trace(E):
     ok = _amb_ok(amb)
     log("  ambiguous paths excluded: %d" % (~ok).sum())
     assert (~ok).sum() < 0.01 * sc.n_paths
-    H.compare_stores(gpu, ora, ok, "frame0")
+    H.compare_stores(gpu, ora, ok, "frame0", O.frame_scene(sc, 0).verts)
     s = ctx.stats_dict(stats)
     assert s["photons_written"] == int(((gpu["info"] >> 22) & 15).sum())
 
@@ -105,7 +105,7 @@ def test_tiny_verify_queue_and_retrace(E):
         ambr, tr = O.retrace(O.frame_scene(sc, 1, 0), ora, T, sc.seed, 1)
         ok2 = ok & _amb_ok(ambr)
         log("  retrace: excluded %d" % (~ok2).sum())
-        H.compare_stores(gpu_r, ora, ok2, "retrace T=%g" % T)
+        H.compare_stores(gpu_r, ora, ok2, "retrace T=%g" % T, O.frame_scene(sc, 1, 0).verts)
         s = ctx.stats_dict(stats)
         if ok2.all():
             assert s["rays_traced"] == int(tr.sum())
@@ -154,7 +154,7 @@ def test_max_bounces_fifteen(E):
     ctx.initial_trace(st, sc.seed, 0)
     gpu = st.to_numpy()
     ora, amb = _oracle_frame0(sc)
-    H.compare_stores(gpu, ora, _amb_ok(amb), "B=15 frame0")
+    H.compare_stores(gpu, ora, _amb_ok(amb), "B=15 frame0", O.frame_scene(sc, 0).verts)
     assert ((gpu["info"] >> 22) & 15).max() == 15
 
 
@@ -164,8 +164,7 @@ def test_max_bounces_fifteen(E):
 
 
 def _lockstep(E, sc, n_frames, T, label):
-    ora, amb0 = _oracle_frame0(sc)
-    ok_paths = _amb_ok(amb0)
+    ora, _ = _oracle_frame0(sc)
     ctx = _setup(E, sc)
     st = ctx.new_store()
     total_rep = 0
@@ -177,7 +176,7 @@ def _lockstep(E, sc, n_frames, T, label):
         gv = st.to_numpy()
         fs = O.frame_scene(sc, f, f - 1)
         ambv, _ = O.verify(fs, ora)
-        ok = ok_paths & _amb_ok(ambv)
+        ok = _amb_ok(ambv)  # both sides start this frame from the same oracle store
         assert np.array_equal(gv["info"][ok], ora.info[ok])
         assert np.abs(gv["origin"][ok] - ora.origin[ok]).max(initial=0) <= H.POS_TOL
         total_rep += int(((gv["info"] >> 30) & 1).sum())
@@ -185,10 +184,10 @@ def _lockstep(E, sc, n_frames, T, label):
         gr = st.to_numpy()
         ambr, _ = O.retrace(fs, ora, T, sc.seed, f)
         ok2 = ok & _amb_ok(ambr)
-        log("  excluded %d of %d" % ((~ok2).sum(), sc.n_paths))
-        assert (~ok2).sum() <= 0.05 * sc.n_paths
-        H.compare_stores(gr, ora, ok2, "%s frame %d" % (label, f))
-        ok_paths = ok2
+        log("  replaced %d, excluded (within a decision band) %d of %d" % (
+            ((gv["info"] >> 30) & 1).sum(), (~ok2).sum(), sc.n_paths))
+        assert (~ok2).sum() <= 0.08 * sc.n_paths
+        H.compare_stores(gr, ora, ok2, "%s frame %d" % (label, f), fs.verts)
     assert total_rep > 0
     ctx.close()
 
