@@ -51,6 +51,71 @@ def cpu_baseline(config_fn, target_s, T):
             "sample": "%d paths of the same scene, one frame (verify + error-based re-trace), %.1f s" % (n, dt)}
 
 
+def batched(args, engine, scenes, torch, np):
+    """64 uneven scenes: per-scene launches (plain) against one graph-captured
+    launch per phase (batched), from identical frame-0 stores; the stores must
+    stay bit-identical."""
+    K = args.batch_steps
+    t0 = time.perf_counter()
+    scs = scenes.make_batch(n_scenes=args.batch_scenes, frames=K + 2)
+    T, seed = 0.01, 4
+    sets = []
+    for _ in range(2):
+        ctxs = [engine.Context(s) for s in scs]
+        sts = [c.new_store() for c in ctxs]
+        for c, st in zip(ctxs, sts):
+            c.frame_begin(0)
+            c.initial_trace(st, seed, 0)
+        sets.append((ctxs, sts))
+    torch.cuda.synchronize()
+    log("batch: %d scenes, %d paths, set up in %.1f s" % (len(scs), sum(s.n_paths for s in scs),
+                                                          time.perf_counter() - t0))
+    (pc, ps), (bc, bs) = sets
+    caps = [st.n_paths * st.B for st in ps]
+    outs = [(torch.empty((c, 3), dtype=torch.float32, device="cuda"),
+             torch.empty((c, 3), dtype=torch.float32, device="cuda"),
+             torch.zeros(1, dtype=torch.int32, device="cuda")) for c in caps]
+    b = engine.Batch(bc, bs, T, seed)
+    stats_p = pc[0].new_stats()
+    stats_b = bc[0].new_stats()
+    # frame 1: warmup (graph capture for the batch)
+    for c, st, o in zip(pc, ps, outs):
+        c.frame_begin(1)
+        c.verify(st)
+        c.retrace(st, T, seed, 1)
+        c.compact_photons_into(st, *o)
+    b.frame(1, stats_b)
+    torch.cuda.synchronize()
+    stats_b.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for f in range(2, 2 + K):
+        for c, st, o in zip(pc, ps, outs):
+            c.frame_begin(f)
+            c.verify(st, stats_p)
+            c.retrace(st, T, seed, f)
+            c.compact_photons_into(st, *o)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t
+    t = time.perf_counter()
+    for f in range(2, 2 + K):
+        b.frame(f, stats_b)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t
+    same = all(np.array_equal(x.to_numpy()[k].view(np.uint32), y.to_numpy()[k].view(np.uint32))
+               for x, y in zip(ps, bs) for k in ("pos", "hit", "energy", "info", "origin"))
+    sp, sb = pc[0].stats_dict(stats_p), bc[0].stats_dict(stats_b)
+    b.close()
+    for c in pc + bc:
+        c.close()
+    return {"scenes": len(scs), "paths": int(sum(s.n_paths for s in scs)), "frames_timed": K,
+            "plain_ms_per_frame": plain_s / K * 1e3, "batched_ms_per_frame": batch_s / K * 1e3,
+            "plain_segments_per_s": sp["segments_examined"] / plain_s,
+            "batched_segments_per_s": sb["segments_examined"] / batch_s,
+            "speedup": plain_s / batch_s, "stores_bit_identical": bool(same),
+            "segments_examined_equal": sp["segments_examined"] == sb["segments_examined"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +125,9 @@ def main():
     ap.add_argument("--paths", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -173,7 +241,7 @@ def main():
         "per_frame": {"segments_examined": tot["segments_examined"] / K, "paths_invalid": tot["paths_invalid"] / K,
                       "paths_light_lost": tot["paths_light_lost"] / K, "rays_traced": tot["rays_traced"] / K,
                       "photons_written": tot["photons_written"] / K, "reuse_accepted": tot["reuse_accepted"] / K,
-                      "photons_compacted": int(out_cnt.item())},
+                      "verify_box_hits": tot["verify_box_hits"] / K, "photons_compacted": int(out_cnt.item())},
     }
     log(json.dumps(res["phases_ms_per_frame"]))
     # the paper's comparator on the same GPU: re-trace every path every frame
@@ -190,6 +258,10 @@ def main():
         base_ms.append(e0.elapsed_time(e1))
     res["baseline_retrace_all_ms"] = sum(base_ms) / len(base_ms)
     ctx.close()
+    del st, out_pos, out_en
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        res["batched"] = batched(args, engine, scenes, torch, np)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, T)
     print(json.dumps(res), flush=True)

@@ -51,6 +51,7 @@ extern "C" {
 #endif
 
 typedef struct pv_ctx pv_ctx;
+typedef struct pv_batch pv_batch;
 typedef int32_t pv_status;
 
 enum {
@@ -110,7 +111,7 @@ typedef struct {
   unsigned long long photons_written;    /* photons written by the re-trace */
   unsigned long long reuse_accepted;     /* Equation 2 acceptances (error-based walk) */
   unsigned long long paths_truncated;    /* re-traced paths ending on an escaping ray */
-  unsigned long long reserved;
+  unsigned long long verify_box_hits;    /* segments reaching a moved object's box in verify */
 } pv_stats;
 
 /* --- context ----------------------------------------------------------- */
@@ -206,11 +207,51 @@ pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const floa
                              const float* d_power, const float* d_gE, float* d_g_albedo,
                              float* d_g_power);
 
+/* --- batched form -------------------------------------------------------- */
+
+/* Group n uploaded contexts, each with its path store (the store binding of
+ * the batch is fixed), so that one call runs a whole frame of every scene with
+ * one launch per phase: transform + refit, verification, work queue (one
+ * queue over all scenes), re-trace (one persistent launch) and photon
+ * compaction into a batch-owned buffer.  d_obj_xf[i] / d_light_xf[i] are the
+ * device transform arrays of scene i (layout of pv_frame_begin) whose
+ * addresses stay fixed; the caller rewrites their contents before each frame.
+ * threshold and seed as in pv_retrace_paths.  The work runs on the stream of
+ * contexts[0]; every context must have been uploaded with pv_set_light_paths
+ * matching its store.  Results are bit-identical to the per-context calls.
+ * Synchronises.  Errors are reported through pv_last_error(contexts[0]). */
+pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path_store* stores, uint32_t n,
+                          const float* const* d_obj_xf, const float* const* d_light_xf, float threshold,
+                          uint64_t seed);
+void pv_batch_destroy(pv_batch* b);
+/* One frame of every scene.  The first call (and any call with a different
+ * d_stats) captures the frame into a HIP graph; later calls replay it, with
+ * the frame number read from device memory.  Never synchronises. */
+pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats);
+/* Point the batch at other per-scene transform arrays for the next frames
+ * (host arrays of n device pointers, copied; stream-ordered, no
+ * synchronisation, no graph re-capture: the frame reads the pointer tables
+ * from device memory). */
+pv_status pv_batch_set_transforms(pv_batch* b, const float* const* d_obj_xf, const float* const* d_light_xf);
+/* Copy the last frame's photon compaction of the batch: positions and
+ * energies (float[3] each) of every existing photon, scene by scene, each in
+ * (row, path) order (at most 'capacity' photons), and d_scene_base[0..n]: the
+ * first photon of each scene and, last, the total.  Device buffers. */
+pv_status pv_batch_copy_photons(pv_batch* b, float* d_pos, float* d_energy, uint32_t capacity,
+                                uint32_t* d_scene_base);
+
 /* --- host utilities ------------------------------------------------------ */
 
 /* Bytes of the store layout for n paths and B rows (Table 1 of the paper
  * counts 32 B per photon, 4 B path information and 12 B origin per path). */
 uint64_t pv_store_bytes(uint64_t n_paths, uint32_t max_bounces);
+/* Build, on the host, the hierarchy the library builds for n triangles
+ * (h_verts [n][9]; kind 0 = static world, binned surface-area heuristic;
+ * kind 1 = dynamic object, Morton-order radix split) and check it:
+ * out[0] internal nodes, out[1] leaves, out[2] depth of the deepest leaf,
+ * out[3] = 1 when the leaves partition the triangles, every child box
+ * contains its subtree and the depth fits the traversal stack. */
+pv_status pv_hierarchy_info(const float* h_verts, uint32_t n, int32_t kind, uint32_t* out);
 /* Pack / unpack the path-information word. */
 uint32_t pv_info_pack(uint32_t cell, uint32_t nseg, uint32_t start, uint32_t replace, uint32_t reuse);
 void pv_info_unpack(uint32_t w, uint32_t* cell, uint32_t* nseg, uint32_t* start, uint32_t* replace,

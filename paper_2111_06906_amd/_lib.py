@@ -42,7 +42,7 @@ class SceneDesc(C.Structure):
 
 
 STAT_FIELDS = ["segments_examined", "paths_invalid", "paths_light_lost", "rays_traced", "photons_written",
-               "reuse_accepted", "paths_truncated", "reserved"]
+               "reuse_accepted", "paths_truncated", "verify_box_hits"]
 
 
 class Stats(C.Structure):
@@ -85,12 +85,16 @@ def lib():
         "pv_info_pack": ([U32, U32, U32, U32, U32], U32),
         "pv_info_unpack": ([U32, P, P, P, P, P], None),
         "pv_version": ([], C.c_char_p),
+        "pv_hierarchy_info": ([P, U32, I32, P], I32),
     }
-    optional = {
-        "pv_batch_create": ([P, P, P, U32], I32),
+    optional = {}
+    sig.update({
+        "pv_batch_create": ([C.POINTER(P), P, P, U32, P, P, F, U64], I32),
         "pv_batch_destroy": ([P], None),
-        "pv_batch_frame": ([P, P, P, F, U64, U32, P], I32),
-    }
+        "pv_batch_frame": ([P, U32, P], I32),
+        "pv_batch_copy_photons": ([P, P, P, U32, P], I32),
+        "pv_batch_set_transforms": ([P, P, P], I32),
+    })
     for name, (args, res) in list(sig.items()) + list(optional.items()):
         if not hasattr(L, name):
             if name in optional:
@@ -183,7 +187,46 @@ def info_pack(cell, nseg, start, replace, reuse):
     return int(lib().pv_info_pack(cell, nseg, start, replace, reuse))
 
 
+def hierarchy_info(verts9, kind):
+    import numpy as np
+    v = np.ascontiguousarray(verts9, np.float32).reshape(-1, 9)
+    out = (C.c_uint32 * 4)()
+    check(lib().pv_hierarchy_info(v.ctypes.data_as(C.c_void_p), v.shape[0], kind, out))
+    return {"nodes": out[0], "leaves": out[1], "depth": out[2], "valid": bool(out[3])}
+
+
 def info_unpack(w):
     out = [C.c_uint32() for _ in range(5)]
     lib().pv_info_unpack(w, *[C.byref(o) for o in out])
     return tuple(o.value for o in out)
+
+
+def batch_create(ctxs, stores, d_obj_xf, d_light_xf, threshold, seed):
+    n = len(ctxs)
+    carr = (C.c_void_p * n)(*[c.value for c in ctxs])
+    sarr = (PathStore * n)(*stores)
+    oarr = (C.c_void_p * n)(*d_obj_xf)
+    larr = (C.c_void_p * n)(*d_light_xf)
+    b = C.c_void_p()
+    code = lib().pv_batch_create(C.byref(b), carr, sarr, n, oarr, larr, C.c_float(threshold), seed)
+    check(code, ctxs[0])
+    return b
+
+
+def batch_destroy(b):
+    lib().pv_batch_destroy(b)
+
+
+def batch_frame(b, frame, d_stats=None, owner=None):
+    check(lib().pv_batch_frame(b, frame, d_stats), owner)
+
+
+def batch_copy_photons(b, d_pos, d_energy, capacity, d_base, owner=None):
+    check(lib().pv_batch_copy_photons(b, d_pos, d_energy, capacity, d_base), owner)
+
+
+def batch_set_transforms(b, d_obj_xf, d_light_xf, owner=None):
+    n = len(d_obj_xf)
+    oarr = (C.c_void_p * n)(*d_obj_xf)
+    larr = (C.c_void_p * n)(*d_light_xf)
+    check(lib().pv_batch_set_transforms(b, oarr, larr), owner)

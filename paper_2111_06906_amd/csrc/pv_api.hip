@@ -68,6 +68,35 @@ struct pv_ctx {
   pv_path_store bstore{};
 };
 
+struct pv_batch {
+  pv_ctx* owner = nullptr;  // contexts[0]: stream and error message
+  hipStream_t stream = nullptr;
+  uint32_t n = 0;
+  Alloc mem;
+  SceneDev* d_scenes = nullptr;
+  uint2 *d_path_tiles = nullptr, *d_tri_tiles = nullptr, *d_leaf_tiles = nullptr;
+  uint32_t n_path_tiles = 0, n_tri_tiles = 0, n_leaf_tiles = 0;
+  uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr, *d_head = nullptr,
+           *d_gbase = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_ptotal = nullptr, *d_pbase = nullptr,
+           *d_frame = nullptr;
+  uint32_t n_counts = 0;
+  float *d_out_pos = nullptr, *d_out_en = nullptr;
+  uint32_t capacity = 0;
+  const float** d_obj_in = nullptr;
+  const float** d_light_in = nullptr;
+  float T = -1.0f;
+  uint64_t seed = 0;
+  uint32_t retrace_blocks = 0;
+  bool captured = false;
+  pv_stats* captured_stats = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~pv_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 namespace {
 
 pv_status fail(pv_ctx* c, pv_status code, const std::string& msg) {
@@ -205,6 +234,161 @@ HostBvh build_topology(const float* v9, uint32_t n, uint32_t leaf_max) {
   return h;
 }
 
+// Static world: binned surface-area-heuristic split (16 bins per axis) of
+// the centroid range, with a leaf of at most 8 triangles when splitting does
+// not pay; median split below depth 40 keeps the depth bounded.
+HostBvh build_sah(const float* v9, uint32_t n) {
+  HostBvh h;
+  constexpr int K = 16;
+  constexpr uint32_t kLeafMax = 8, kMinSplit = 2;
+  struct Box {
+    float lo[3], hi[3];
+    void reset() {
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = INFINITY;
+        hi[k] = -INFINITY;
+      }
+    }
+    void grow(const Box& b) {
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], b.lo[k]);
+        hi[k] = std::max(hi[k], b.hi[k]);
+      }
+    }
+    float area() const {
+      float d[3];
+      for (int k = 0; k < 3; ++k) d[k] = std::max(0.0f, hi[k] - lo[k]);
+      return d[0] * d[1] + d[1] * d[2] + d[2] * d[0];
+    }
+  };
+  std::vector<Box> tb(n);
+  std::vector<float> cen(3 * (size_t)n);
+  for (uint32_t i = 0; i < n; ++i) {
+    tb[i].reset();
+    for (int v = 0; v < 3; ++v)
+      for (int k = 0; k < 3; ++k) {
+        float x = v9[9 * (size_t)i + 3 * v + k];
+        tb[i].lo[k] = std::min(tb[i].lo[k], x);
+        tb[i].hi[k] = std::max(tb[i].hi[k], x);
+      }
+    for (int k = 0; k < 3; ++k) cen[3 * (size_t)i + k] = 0.5f * (tb[i].lo[k] + tb[i].hi[k]);
+  }
+  h.order.resize(n);
+  for (uint32_t i = 0; i < n; ++i) h.order[i] = i;
+  struct Item {
+    uint32_t lo, hi;  // [lo, hi)
+    int32_t parent;
+    uint32_t side, depth;
+  };
+  std::vector<Item> stack;
+  stack.push_back({0, n, -1, 0, 0});
+  auto set_child = [&](int32_t parent, uint32_t side, int32_t code) {
+    if (parent < 0)
+      h.root = code;
+    else if (side == 0)
+      h.nodes[parent].d.x = code;
+    else
+      h.nodes[parent].d.y = code;
+  };
+  while (!stack.empty()) {
+    Item it = stack.back();
+    stack.pop_back();
+    uint32_t cnt = it.hi - it.lo;
+    h.max_depth = std::max(h.max_depth, it.depth);
+    Box nb, cb;
+    nb.reset();
+    cb.reset();
+    for (uint32_t i = it.lo; i < it.hi; ++i) {
+      uint32_t t = h.order[i];
+      nb.grow(tb[t]);
+      Box c;
+      for (int k = 0; k < 3; ++k) c.lo[k] = c.hi[k] = cen[3 * (size_t)t + k];
+      cb.grow(c);
+    }
+    uint32_t mid = it.lo;
+    bool leaf = cnt < kMinSplit;
+    if (!leaf) {
+      int best_axis = -1, best_s = 0;
+      float best = INFINITY;
+      if (it.depth < 40) {
+        for (int ax = 0; ax < 3; ++ax) {
+          float ext = cb.hi[ax] - cb.lo[ax];
+          if (!(ext > 0)) continue;
+          Box bb[K];
+          uint32_t bc[K] = {0};
+          for (int b = 0; b < K; ++b) bb[b].reset();
+          for (uint32_t i = it.lo; i < it.hi; ++i) {
+            uint32_t t = h.order[i];
+            int b = std::min(K - 1, (int)((cen[3 * (size_t)t + ax] - cb.lo[ax]) / ext * K));
+            bb[b].grow(tb[t]);
+            ++bc[b];
+          }
+          float ra[K];
+          uint32_t rc[K];
+          Box acc;
+          acc.reset();
+          uint32_t c = 0;
+          for (int b = K - 1; b > 0; --b) {
+            acc.grow(bb[b]);
+            c += bc[b];
+            ra[b] = acc.area();
+            rc[b] = c;
+          }
+          acc.reset();
+          c = 0;
+          for (int b = 0; b < K - 1; ++b) {
+            acc.grow(bb[b]);
+            c += bc[b];
+            if (c == 0 || rc[b + 1] == 0) continue;
+            float cost = acc.area() * c + ra[b + 1] * rc[b + 1];
+            if (cost < best) {
+              best = cost;
+              best_axis = ax;
+              best_s = b + 1;
+            }
+          }
+        }
+      }
+      float leaf_cost = nb.area() * cnt;
+      float split_cost = best + nb.area();  // one traversal step plus the children
+      if (best_axis >= 0 && (split_cost < leaf_cost || cnt > kLeafMax)) {
+        float ext = cb.hi[best_axis] - cb.lo[best_axis];
+        auto first = h.order.begin() + it.lo, last = h.order.begin() + it.hi;
+        auto m = std::partition(first, last, [&](uint32_t t) {
+          int b = std::min(K - 1, (int)((cen[3 * (size_t)t + best_axis] - cb.lo[best_axis]) / ext * K));
+          return b < best_s;
+        });
+        mid = (uint32_t)(m - h.order.begin());
+      } else if (cnt <= kLeafMax) {
+        leaf = true;
+      }
+      if (!leaf && (mid == it.lo || mid == it.hi)) {
+        // median split along the widest centroid axis
+        int ax = 0;
+        for (int k = 1; k < 3; ++k)
+          if (cb.hi[k] - cb.lo[k] > cb.hi[ax] - cb.lo[ax]) ax = k;
+        mid = it.lo + cnt / 2;
+        std::nth_element(h.order.begin() + it.lo, h.order.begin() + mid, h.order.begin() + it.hi,
+                         [&](uint32_t a, uint32_t b) { return cen[3 * (size_t)a + ax] < cen[3 * (size_t)b + ax]; });
+      }
+    }
+    if (leaf) {
+      set_child(it.parent, it.side, pv::leaf_code(it.lo, cnt));
+      h.leaves.push_back({it.lo, cnt, it.parent, it.side});
+      continue;
+    }
+    int32_t id = (int32_t)h.nodes.size();
+    Node nd{};
+    nd.d = make_int4(0, 0, it.parent < 0 ? -1 : it.parent * 2 + (int)it.side, 0);
+    h.nodes.push_back(nd);
+    h.parent.push_back(nd.d.z);
+    set_child(it.parent, it.side, id);
+    stack.push_back({mid, it.hi, id, 1, it.depth + 1});
+    stack.push_back({it.lo, mid, id, 0, it.depth + 1});
+  }
+  return h;
+}
+
 inline float pad_lo(float x) { return x - (1e-6f + std::fabs(x) * 1e-6f); }
 inline float pad_hi(float x) { return x + (1e-6f + std::fabs(x) * 1e-6f); }
 
@@ -261,6 +445,8 @@ std::vector<uint2> make_tiles(uint32_t scene, uint32_t n) {
   return t;
 }
 
+uint32_t path_blocks(uint32_t n) { return (n + pv::kBlock - 1) / pv::kBlock; }
+
 pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
   if (!ctx->reserved) return fail(ctx, PV_ERR_STATE, "pv_reserve has not been called");
@@ -287,6 +473,9 @@ pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   ctx->hs.stride = st->stride;
   ctx->hs.n_paths = st->n_paths;
   ctx->hs.B = st->max_bounces;
+  ctx->hs.n_blocks = path_blocks(st->n_paths);
+  ctx->hs.count_base = 0;
+  ctx->hs.gpath_base = 0;
   CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
   uint32_t gb[2] = {0, st->n_paths};
   CK(hipMemcpyAsync(ctx->d_gbase, gb, sizeof(gb), hipMemcpyHostToDevice, ctx->stream));
@@ -296,12 +485,79 @@ pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   return PV_OK;
 }
 
-uint32_t path_blocks(uint32_t n) { return (n + pv::kBlock - 1) / pv::kBlock; }
-
 }  // namespace
+
+// Invariants of a hierarchy over leaf-order vertices: leaves partition the
+// triangles, every stored child box contains its subtree, depth <= bound.
+bool check_hierarchy(const HostBvh& h, const float* v9_leaf_order, uint32_t n) {
+  std::vector<uint8_t> seen(n, 0);
+  struct It {
+    int32_t code;
+    float box[6];
+  };
+  std::vector<It> st;
+  float inf_box[6] = {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY};
+  It r;
+  r.code = h.root;
+  std::memcpy(r.box, inf_box, sizeof(inf_box));
+  st.push_back(r);
+  auto inside = [](const float* inner_lo_hi, const float* outer) {
+    for (int k = 0; k < 3; ++k)
+      if (inner_lo_hi[k] < outer[k] || inner_lo_hi[3 + k] > outer[3 + k]) return false;
+    return true;
+  };
+  while (!st.empty()) {
+    It it = st.back();
+    st.pop_back();
+    if (it.code < 0) {
+      uint32_t f = pv::leaf_first(it.code), c = pv::leaf_count(it.code);
+      for (uint32_t i = f; i < f + c; ++i) {
+        if (i >= n || seen[i]) return false;
+        seen[i] = 1;
+        for (int v = 0; v < 3; ++v) {
+          const float* x = v9_leaf_order + 9 * (size_t)i + 3 * v;
+          float b[6] = {x[0], x[1], x[2], x[0], x[1], x[2]};
+          if (!inside(b, it.box)) return false;
+        }
+      }
+      continue;
+    }
+    if ((size_t)it.code >= h.nodes.size()) return false;
+    const Node& nd = h.nodes[it.code];
+    const float* f = reinterpret_cast<const float*>(&nd);
+    for (int side = 0; side < 2; ++side) {
+      It ch;
+      ch.code = side ? nd.d.y : nd.d.x;
+      std::memcpy(ch.box, f + 6 * side, 6 * sizeof(float));
+      if (!inside(ch.box, it.box)) return false;
+      st.push_back(ch);
+    }
+  }
+  for (uint32_t i = 0; i < n; ++i)
+    if (!seen[i]) return false;
+  return true;
+}
 
 // ===========================================================================
 extern "C" {
+
+pv_status pv_hierarchy_info(const float* h_verts, uint32_t n, int32_t kind, uint32_t* out) {
+  if (!h_verts || !out || n == 0 || (kind != 0 && kind != 1)) return PV_ERR_ARG;
+  try {
+    HostBvh h = kind == 0 ? build_sah(h_verts, n) : build_topology(h_verts, n, 2);
+    std::vector<float> v9(9 * (size_t)n);
+    for (uint32_t i = 0; i < n; ++i) std::memcpy(&v9[9 * (size_t)i], h_verts + 9 * (size_t)h.order[i], 36);
+    host_boxes(h, v9.data());
+    out[0] = (uint32_t)h.nodes.size();
+    out[1] = (uint32_t)h.leaves.size();
+    out[2] = h.max_depth;
+    out[3] = (check_hierarchy(h, v9.data(), n) && h.max_depth <= kMaxDepth) ? 1u : 0u;
+    return PV_OK;
+  } catch (...) {
+    return PV_ERR_OOM;
+  }
+}
+
 
 const char* pv_version(void) { return "pv-mi355x 0.1 (gfx950)"; }
 
@@ -407,7 +663,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     hs.n_static = S;
     hs.sroot = 0;
     if (S) {
-      HostBvh hb = build_topology(d->h_static_verts, S, 4);
+      HostBvh hb = build_sah(d->h_static_verts, S);
       std::vector<float> v9(9 * (size_t)S);
       stris.resize(S);
       for (uint32_t i = 0; i < S; ++i) {
@@ -529,6 +785,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
 
     CK(dalloc(A, &ctx->d_scene, 1));
     CK(dalloc(A, &ctx->d_state, 1));
+    hs.state = ctx->d_state;
     uint32_t one = 1;
     CK(hipMemcpyAsync(ctx->d_state, &one, 4, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(ctx->d_scene, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
@@ -610,7 +867,7 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
   if ((ctx->n_objects && !d_obj_xf) || !d_light_xf) return fail(ctx, PV_ERR_ARG, "transform array is NULL");
   const float* in[2] = {d_obj_xf, d_light_xf};
   CK(hipMemcpyAsync(ctx->d_in_ptrs, in, sizeof(in), hipMemcpyHostToDevice, ctx->stream));
-  CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->d_state, ctx->stream));
+  CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->stream));
   CK(pv::launch_transform(ctx->d_scene, ctx->d_tri_tiles, ctx->n_tri_tiles, ctx->stream));
   CK(pv::launch_refit(ctx->d_scene, ctx->d_leaf_tiles, ctx->n_leaf_tiles, ctx->stream));
   ctx->frame_started = true;
@@ -669,7 +926,7 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
   uint32_t blocks = (uint32_t)ctx->n_cu * 8;
   CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold, seed,
-                        frame, d_stats, blocks, ctx->stream));
+                        frame, nullptr, d_stats, blocks, ctx->stream));
   return PV_OK;
 }
 
@@ -707,6 +964,183 @@ pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const floa
   if (ctx->n_materials > 256) return fail(ctx, PV_ERR_CAPACITY, "backward supports at most 256 materials");
   CK(pv::launch_energy_bwd(ctx->d_scene, ctx->d_path_tiles, path_blocks(store->n_paths), d_albedo, d_power, d_gE,
                            ctx->n_materials, ctx->n_lights, ctx->d_partial, d_g_albedo, d_g_power, ctx->stream));
+  return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched form: every phase of a frame is one launch over all scenes
+
+static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
+  pv_ctx* ctx = b->owner;
+  hipStream_t st = b->stream;
+  CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
+  CK(pv::launch_transform(b->d_scenes, b->d_tri_tiles, b->n_tri_tiles, st));
+  CK(pv::launch_refit(b->d_scenes, b->d_leaf_tiles, b->n_leaf_tiles, st));
+  CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_block_cnt, d_stats, st));
+  CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, st));
+  CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
+  CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->d_head, b->T, b->seed, 0,
+                        b->d_frame, d_stats, b->retrace_blocks, st));
+  CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
+  CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, nullptr, st));
+  CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,
+                               b->d_out_pos, b->d_out_en, b->capacity, st));
+  CK(pv::launch_scene_photon_base(b->d_scenes, (int)b->n, b->d_poffsets, b->d_ptotal, b->d_pbase, st));
+  return PV_OK;
+}
+
+pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path_store* stores, uint32_t n,
+                          const float* const* d_obj_xf, const float* const* d_light_xf, float threshold,
+                          uint64_t seed) {
+  if (!out || !contexts || !stores || n == 0 || !d_obj_xf || !d_light_xf) return PV_ERR_ARG;
+  *out = nullptr;
+  pv_ctx* ctx = contexts[0];
+  if (!ctx) return PV_ERR_ARG;
+  if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
+  try {
+    pv_batch* b = new pv_batch();
+    b->owner = ctx;
+    b->stream = ctx->stream;
+    b->n = n;
+    b->T = threshold;
+    b->seed = seed;
+    b->retrace_blocks = (uint32_t)ctx->n_cu * 8;
+    std::vector<SceneDev> table(n);
+    std::vector<uint2> ptiles, ttiles, ltiles;
+    std::vector<uint32_t> gbase(n + 1, 0);
+    uint64_t total_paths = 0, counts = 0, cap = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      pv_ctx* c = contexts[i];
+      const pv_path_store* st = &stores[i];
+      auto bad = [&](const char* m) {
+        delete b;
+        return fail(ctx, PV_ERR_ARG, std::string("batch scene ") + std::to_string(i) + ": " + m);
+      };
+      if (!c || !c->uploaded) return bad("context without a scene");
+      if (!st->d_pos_hit || !st->d_energy || !st->d_origin || !st->d_info) return bad("store has a NULL array");
+      if (st->max_bounces < 1 || st->max_bounces > PV_MAX_BOUNCES) return bad("max_bounces out of range");
+      if (st->stride < st->n_paths || st->stride % 64 != 0) return bad("bad stride");
+      if ((c->n_objects && !d_obj_xf[i]) || !d_light_xf[i]) return bad("transform array is NULL");
+      uint32_t lp = 0;
+      for (uint32_t l = 0; l < c->n_lights; ++l) lp += c->h_light_paths[l];
+      if (lp != st->n_paths) return bad("light path counts do not add up to n_paths");
+      SceneDev hs = c->hs;
+      hs.pos = static_cast<float4*>(st->d_pos_hit);
+      hs.energy = static_cast<float4*>(st->d_energy);
+      hs.origin = st->d_origin;
+      hs.info = st->d_info;
+      hs.stride = st->stride;
+      hs.n_paths = st->n_paths;
+      hs.B = st->max_bounces;
+      hs.n_blocks = path_blocks(st->n_paths);
+      hs.count_base = (uint32_t)counts;
+      hs.gpath_base = (uint32_t)total_paths;
+      table[i] = hs;
+      gbase[i] = (uint32_t)total_paths;
+      for (uint2 t : make_tiles(i, st->n_paths)) ptiles.push_back(t);
+      for (uint2 t : make_tiles(i, c->hs.n_dyn_tris)) ttiles.push_back(t);
+      uint32_t nl = 0;
+      if (c->n_objects) {
+        std::vector<ObjDev> ob(c->n_objects);
+        CK(hipMemcpy(ob.data(), c->hs.objs, sizeof(ObjDev) * c->n_objects, hipMemcpyDeviceToHost));
+        nl = ob.back().leaf_base + ob.back().n_leaves;
+      }
+      for (uint2 t : make_tiles(i, nl)) ltiles.push_back(t);
+      total_paths += st->n_paths;
+      counts += (uint64_t)hs.n_blocks * st->max_bounces;
+      cap += (uint64_t)st->n_paths * st->max_bounces;
+    }
+    gbase[n] = (uint32_t)total_paths;
+    if (total_paths >= (1ull << 32) || cap >= (1ull << 32)) {
+      delete b;
+      return fail(ctx, PV_ERR_CAPACITY, "batch too large");
+    }
+    Alloc& A = b->mem;
+    hipStream_t s = b->stream;
+    auto chk = [&](hipError_t e) { return e == hipSuccess; };
+    bool ok = chk(upload(A, &b->d_scenes, table.data(), n, s)) && chk(upload(A, &b->d_path_tiles, ptiles.data(), ptiles.size(), s)) &&
+              chk(upload(A, &b->d_tri_tiles, ttiles.data(), ttiles.size(), s)) &&
+              chk(upload(A, &b->d_leaf_tiles, ltiles.data(), ltiles.size(), s)) &&
+              chk(upload(A, &b->d_gbase, gbase.data(), gbase.size(), s)) &&
+              chk(dalloc(A, &b->d_block_cnt, ptiles.size())) && chk(dalloc(A, &b->d_offsets, ptiles.size())) &&
+              chk(dalloc(A, &b->d_queue, total_paths)) && chk(dalloc(A, &b->d_qcount, 1)) &&
+              chk(dalloc(A, &b->d_head, 1)) && chk(dalloc(A, &b->d_pcounts, counts)) &&
+              chk(dalloc(A, &b->d_poffsets, counts)) && chk(dalloc(A, &b->d_ptotal, 1)) &&
+              chk(dalloc(A, &b->d_pbase, n + 1)) && chk(dalloc(A, &b->d_frame, 1)) &&
+              chk(dalloc(A, &b->d_out_pos, 3 * cap)) && chk(dalloc(A, &b->d_out_en, 3 * cap)) &&
+              chk(upload(A, &b->d_obj_in, const_cast<const float**>(d_obj_xf), n, s)) &&
+              chk(upload(A, &b->d_light_in, const_cast<const float**>(d_light_xf), n, s));
+    if (!ok || hipStreamSynchronize(s) != hipSuccess) {
+      delete b;
+      return fail(ctx, PV_ERR_OOM, "batch allocation failed");
+    }
+    b->n_path_tiles = (uint32_t)ptiles.size();
+    b->n_tri_tiles = (uint32_t)ttiles.size();
+    b->n_leaf_tiles = (uint32_t)ltiles.size();
+    b->n_counts = (uint32_t)counts;
+    b->capacity = (uint32_t)cap;
+    *out = b;
+    return PV_OK;
+  } catch (const std::exception& e) {
+    return fail(ctx, PV_ERR_OOM, std::string("host exception: ") + e.what());
+  }
+}
+
+void pv_batch_destroy(pv_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats) {
+  if (!b) return PV_ERR_ARG;
+  pv_ctx* ctx = b->owner;
+  CK(hipMemcpyAsync(b->d_frame, &frame, sizeof(frame), hipMemcpyHostToDevice, b->stream));
+  if (!b->captured || b->captured_stats != d_stats) {
+    if (b->exec) {
+      CK(hipGraphExecDestroy(b->exec));
+      b->exec = nullptr;
+    }
+    if (b->graph) {
+      CK(hipGraphDestroy(b->graph));
+      b->graph = nullptr;
+    }
+    CK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    pv_status st = batch_enqueue(b, d_stats);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st != PV_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    CK(e);
+    b->graph = g;
+    CK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->captured = true;
+    b->captured_stats = d_stats;
+  }
+  CK(hipGraphLaunch(b->exec, b->stream));
+  return PV_OK;
+}
+
+pv_status pv_batch_set_transforms(pv_batch* b, const float* const* d_obj_xf, const float* const* d_light_xf) {
+  if (!b || !d_obj_xf || !d_light_xf) return PV_ERR_ARG;
+  pv_ctx* ctx = b->owner;
+  CK(hipMemcpyAsync(b->d_obj_in, d_obj_xf, sizeof(float*) * b->n, hipMemcpyHostToDevice, b->stream));
+  CK(hipMemcpyAsync(b->d_light_in, d_light_xf, sizeof(float*) * b->n, hipMemcpyHostToDevice, b->stream));
+  return PV_OK;
+}
+
+pv_status pv_batch_copy_photons(pv_batch* b, float* d_pos, float* d_energy, uint32_t capacity,
+                                uint32_t* d_scene_base) {
+  if (!b || !d_scene_base || (capacity && (!d_pos || !d_energy))) return PV_ERR_ARG;
+  pv_ctx* ctx = b->owner;
+  uint32_t n = std::min(capacity, b->capacity);
+  if (n) {
+    CK(hipMemcpyAsync(d_pos, b->d_out_pos, 12 * (size_t)n, hipMemcpyDeviceToDevice, b->stream));
+    CK(hipMemcpyAsync(d_energy, b->d_out_en, 12 * (size_t)n, hipMemcpyDeviceToDevice, b->stream));
+  }
+  CK(hipMemcpyAsync(d_scene_base, b->d_pbase, 4 * (size_t)(b->n + 1), hipMemcpyDeviceToDevice, b->stream));
   return PV_OK;
 }
 

@@ -113,6 +113,9 @@ struct SceneDev {
   uint32_t stride, n_paths, B;
   float eps_end, eps_close, radius;
   uint32_t gpath_base;    // offset of this scene's paths in the work-queue id space
+  uint32_t n_blocks;      // path blocks of the bound store
+  uint32_t count_base;    // first entry of this scene's (row, block) photon counts
+  uint32_t* state;        // [1] first-frame flag of the scene
 };
 
 // ---------------------------------------------------------------------------

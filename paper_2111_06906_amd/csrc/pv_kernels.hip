@@ -34,11 +34,11 @@ __device__ inline unsigned long long block_sum_u64(unsigned long long v, unsigne
 // frame begin: one thread per (scene, object) and per (scene, light)
 
 __global__ void k_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
-                              const float* const* light_in, uint32_t* state) {
+                              const float* const* light_in) {
   int s = blockIdx.x;
   if (s >= n_scenes) return;
   SceneDev& S = scenes[s];
-  const uint32_t first = state[s];
+  const uint32_t first = S.state[0];
   for (uint32_t o = threadIdx.x; o < S.n_obj; o += blockDim.x) {
     const float* nw = obj_in[s] + 12 * o;
     float* cur = S.obj_xf_cur + 12 * o;
@@ -67,7 +67,7 @@ __global__ void k_frame_begin(SceneDev* scenes, int n_scenes, const float* const
     S.light_moved[l] = moved;
   }
   __syncthreads();
-  if (threadIdx.x == 0) state[s] = 0;
+  if (threadIdx.x == 0) S.state[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -226,10 +226,16 @@ __device__ inline bool on_moved(const MovedSet& M, uint32_t hit) {
   return false;
 }
 
-__device__ inline bool blocked_by_moved(const SceneDev& S, const MovedSet& M, const Ray& r, Stack& st) {
+__device__ inline bool blocked_by_moved(const SceneDev& S, const MovedSet& M, const Ray& r, Stack& st,
+                                        uint32_t& box_hits) {
+  bool counted = false;
   for (int i = 0; i < M.n; ++i) {
     const float* b = M.box[i];
     if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, r.tmax) == __builtin_inff()) continue;
+    if (!counted) {
+      ++box_hits;
+      counted = true;
+    }
     if (bvh_any(S.dnodes, S.dtris, M.root[i], r, st)) return true;
   }
   return false;
@@ -271,26 +277,40 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
   return true;
 }
 
+// Three phases per block of kBlock paths:
+//  A (coalesced, lane per path): origin update for moved lights, endpoint
+//    test, and one bit per segment whose ray reaches a moved object's box;
+//    scanning stops at the first segment whose end photon is on a moved
+//    object (that segment is invalid whatever lies before it);
+//  B (block-cooperative): the box-hit segments of all paths of the block are
+//    traversed as independent tasks spread over all threads, each blocked
+//    segment lowering its path's first-invalid index (LDS atomic minimum);
+//  C (lane per path): the information word.
+// The result equals the in-order test of Section 3.2: the first invalid
+// segment is the minimum over blocked segments and the first moved endpoint.
 __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
                                                    uint32_t* __restrict__ block_cnt, pv_stats* stats) {
   __shared__ uint32_t sstack[kLdsStack * kBlock];
   __shared__ MovedSet M;
   __shared__ unsigned long long sred[kBlock / 64];
+  __shared__ uint16_t task[kBlock * PV_MAX_BOUNCES];
+  __shared__ uint32_t first_bad[kBlock];
+  __shared__ float sorig[3][kBlock];
+  __shared__ uint32_t wtasks[kBlock / 64];
   uint2 tile = tiles[blockIdx.x];
   const SceneDev& S = scenes[tile.x];
   load_moved(S, M);
-  Stack st;
-  st.lds = sstack + threadIdx.x;
-  st.sp = 0;
-  uint32_t p = tile.y + threadIdx.x;
-  bool active = p < S.n_paths;
-  uint32_t ex = 0, repl = 0, lost = 0;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t p = tile.y + tid;
+  const bool active = p < S.n_paths;
+  const size_t stride = S.stride;
+  uint32_t n = 0, cell = 0, cap = 0, mask = 0, lost = 0;
+  // ---- phase A
   if (active) {
-    const size_t stride = S.stride;
     uint32_t w = S.info[p];
-    uint32_t n = min(info_nseg(w), S.B), cell = info_cell(w);
-    uint32_t out = info_pack(cell, n, 0, 0, 0);
-    bool done = false;
+    n = min(info_nseg(w), S.B);
+    cell = info_cell(w);
+    cap = n;
     float3 a = f3(S.origin[p], S.origin[stride + p], S.origin[2 * stride + p]);
     float4 row = n > 0 ? S.pos[p] : make_float4(0, 0, 0, 0);
     int l = light_of(S, p);
@@ -302,39 +322,100 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
         S.origin[stride + p] = na.y;
         S.origin[2 * stride + p] = na.z;
       } else {
-        out = info_pack(cell, n, 0, 1, 0);
-        done = true;
         lost = 1;
+        cap = 0;
       }
     }
-    for (uint32_t j = 0; j < n && !done; ++j) {
-      if (j > 0) row = S.pos[j * stride + p];
-      float3 b = xyz(row);
-      ++ex;
-      bool inv = on_moved(M, __float_as_uint(row.w));
-      if (!inv && M.n > 0) {
+    sorig[0][tid] = a.x;
+    sorig[1][tid] = a.y;
+    sorig[2][tid] = a.z;
+    if (!lost && M.n > 0) {
+      for (uint32_t j = 0; j < n; ++j) {
+        if (j > 0) row = S.pos[j * stride + p];
+        if (on_moved(M, __float_as_uint(row.w))) {
+          cap = j;
+          break;
+        }
+        float3 b = xyz(row);
         Ray r = segment_ray(a, b, S.eps_end);
-        inv = blocked_by_moved(S, M, r, st);
+        for (int i = 0; i < M.n; ++i) {
+          const float* bx = M.box[i];
+          if (box_entry(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, r.tmax) != __builtin_inff()) {
+            mask |= 1u << j;
+            break;
+          }
+        }
+        a = b;
       }
-      if (inv) {
-        out = info_pack(cell, n, j, 1, 1);
-        done = true;
+    }
+  }
+  first_bad[tid] = cap;
+  // ---- task list: block-wide exclusive prefix of the per-path task counts
+  uint32_t nt = (uint32_t)__popc(mask);
+  uint32_t x = nt;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if ((int)lane_id() >= o) x += y;
+  }
+  if (lane_id() == 63) wtasks[tid >> 6] = x;
+  __syncthreads();
+  uint32_t wbase = 0, total = 0;
+  for (uint32_t w = 0; w < kBlock / 64; ++w) {
+    if (w < (tid >> 6)) wbase += wtasks[w];
+    total += wtasks[w];
+  }
+  uint32_t pos = wbase + x - nt;
+  for (uint32_t m = mask; m; m &= m - 1) task[pos++] = (uint16_t)((tid << 4) | (uint32_t)(__ffs(m) - 1));
+  __syncthreads();
+  // ---- phase B: every thread traverses tasks of any path of the block
+  Stack st;
+  st.lds = sstack + tid;
+  st.sp = 0;
+  for (uint32_t t = tid; t < total; t += kBlock) {
+    uint32_t tk = task[t], owner = tk >> 4, j = tk & 15u;
+    if (j >= first_bad[owner]) continue;  // an earlier segment already failed
+    uint32_t q = tile.y + owner;
+    float3 a = j == 0 ? f3(sorig[0][owner], sorig[1][owner], sorig[2][owner])
+                      : xyz(S.pos[(size_t)(j - 1) * stride + q]);
+    float3 b = xyz(S.pos[(size_t)j * stride + q]);
+    Ray r = segment_ray(a, b, S.eps_end);
+    for (int i = 0; i < M.n; ++i) {
+      const float* bx = M.box[i];
+      if (box_entry(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, r.tmax) == __builtin_inff()) continue;
+      if (bvh_any(S.dnodes, S.dtris, M.root[i], r, st)) {
+        atomicMin(&first_bad[owner], j);
+        break;
       }
-      a = b;
+    }
+  }
+  __syncthreads();
+  // ---- phase C
+  uint32_t ex = 0, repl = 0;
+  if (active) {
+    uint32_t k = first_bad[tid];
+    uint32_t out;
+    if (lost) {
+      out = info_pack(cell, n, 0, 1, 0);
+    } else if (k < n) {
+      out = info_pack(cell, n, k, 1, 1);
+      ex = k + 1;
+    } else {
+      out = info_pack(cell, n, 0, 0, 0);
+      ex = n;
     }
     S.info[p] = out;
     repl = info_replace(out);
   }
-  // per-block count of replaced paths for the queue
   unsigned long long nrep = block_sum_u64(repl, sred);
-  if (threadIdx.x == 0) block_cnt[blockIdx.x] = (uint32_t)nrep;
+  if (tid == 0) block_cnt[blockIdx.x] = (uint32_t)nrep;
   if (stats) {
     unsigned long long nex = block_sum_u64(ex, sred);
     unsigned long long nlost = block_sum_u64(lost, sred);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       atomicAdd(&stats->segments_examined, nex);
       atomicAdd(&stats->paths_invalid, nrep);
       atomicAdd(&stats->paths_light_lost, nlost);
+      atomicAdd(&stats->verify_box_hits, (unsigned long long)total);
     }
   }
 }
@@ -427,20 +508,81 @@ struct Hit {
 
 constexpr float kTFar = 16.0f;
 
-__device__ inline Hit closest_hit(const SceneDev& S, float3 o, float3 w, Stack& st) {
-  Ray r = make_ray(o, w, S.eps_end, kTFar);
-  Hit h;
-  h.t = kTFar;
-  h.gid = kHitNone;
-  h.rec = 0;
-  h.set = nullptr;
-  if (S.n_static) bvh_closest(S.snodes, S.stris, S.sroot, r, st, &h.t, &h.gid, &h.rec, &h.set);
-  for (uint32_t o2 = 0; o2 < S.n_obj; ++o2) {
-    const float* b = S.obj_aabb + 6 * o2;
-    if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h.t) == __builtin_inff()) continue;
-    bvh_closest(S.dnodes, S.dtris, S.objs[o2].root, r, st, &h.t, &h.gid, &h.rec, &h.set);
+// One query over every hierarchy of a scene in a single loop: the static
+// world first (unless only moved objects are wanted), then each dynamic
+// object whose box the ray reaches.  Lanes at different hierarchies still run
+// the same loop body.  any = stop at the first crossing.
+__device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool moved_only, Stack& st, Hit* h) {
+  float t;
+  h->t = r.tmax;
+  h->gid = kHitNone;
+  h->rec = 0;
+  h->set = nullptr;
+  const Node* nodes = S.snodes;
+  const Tri* tris = S.stris;
+  int ri = (moved_only || !S.n_static) ? 0 : -1;  // -1 = static world, else object index
+  int32_t cur = ri < 0 ? S.sroot : 0;
+  bool have = ri < 0;
+  const int base = st.sp;
+  while (true) {
+    if (!have) {
+      // next dynamic object whose box the ray enters before the current best
+      if (ri < 0) ri = 0;
+      bool found = false;
+      while (ri < (int)S.n_obj) {
+        int o = ri++;
+        if (moved_only && !S.obj_moved[o]) continue;
+        const float* b = S.obj_aabb + 6 * o;
+        if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h->t) == __builtin_inff()) continue;
+        cur = S.objs[o].root;
+        nodes = S.dnodes;
+        tris = S.dtris;
+        found = true;
+        break;
+      }
+      if (!found) return h->gid != kHitNone;
+      have = true;
+    }
+    if (cur < 0) {
+      uint32_t f = leaf_first(cur), n = leaf_count(cur);
+      for (uint32_t i = 0; i < n; ++i) {
+        Tri tr = tris[f + i];
+        if (tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), h->t, &t)) {
+          h->t = t;
+          h->gid = __float_as_uint(tr.t0.w);
+          h->rec = f + i;
+          h->set = tris;
+          if (any) {
+            st.sp = base;
+            return true;
+          }
+        }
+      }
+      if (st.sp == base)
+        have = false;
+      else
+        cur = st.pop();
+      continue;
+    }
+    Node nd = nodes[cur];
+    float tb = h->t;
+    float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, tb);
+    float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, tb);
+    bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
+    if (h0 && h1) {
+      int32_t nearc = e0 <= e1 ? nd.d.x : nd.d.y, farc = e0 <= e1 ? nd.d.y : nd.d.x;
+      st.push(farc);
+      cur = nearc;
+    } else if (h0) {
+      cur = nd.d.x;
+    } else if (h1) {
+      cur = nd.d.y;
+    } else if (st.sp == base) {
+      have = false;
+    } else {
+      cur = st.pop();
+    }
   }
-  return h;
 }
 
 __device__ inline float3 hit_normal(const Hit& h) {
@@ -482,65 +624,6 @@ __device__ inline float3 reflect_energy(const SceneDev& S, float3 e, uint32_t ma
   return f3(__fmul_rn(e.x, rho[0]), __fmul_rn(e.y, rho[1]), __fmul_rn(e.z, rho[2]));
 }
 
-struct RCount {
-  uint32_t rays, photons, accepted, truncated;
-};
-
-// new bounces from the photon in 'row' (position x, arriving direction w,
-// triangle normal n_tri, material mat, energy e) up to B photons
-__device__ inline uint32_t naive_tail(const SceneDev& S, uint32_t p, uint32_t row, float3 x, float3 w, float3 ntri,
-                                      uint32_t mat, float3 e, uint64_t seed, uint32_t frame, Stack& st, RCount& rc) {
-  while (row + 1 < S.B) {
-    float3 n = dot(ntri, w) > 0.0f ? mul(ntri, -1.0f) : ntri;
-    float u[4];
-    draw4(seed, p, frame, row + 1, 1, u);
-    float3 l = cosine_local(u[0], u[1]);
-    float3 t, b;
-    onb(n, &t, &b);
-    float3 wn = add(add(mul(t, l.x), mul(b, l.y)), mul(n, l.z));
-    Hit h = closest_hit(S, x, wn, st);
-    ++rc.rays;
-    if (h.gid == kHitNone) {
-      ++rc.truncated;
-      break;
-    }
-    float3 xn = add(x, mul(wn, h.t));
-    float3 en = reflect_energy(S, e, mat);
-    ++row;
-    put_photon(S, p, row, xn, h.gid, en);
-    ++rc.photons;
-    x = xn;
-    w = wn;
-    ntri = hit_normal(h);
-    mat = hit_material(h);
-    e = en;
-  }
-  return row + 1;
-}
-
-// trace segment k from x_k along unit w, then continue naively
-__device__ inline uint32_t naive_from(const SceneDev& S, uint32_t p, uint32_t k, float3 xk, float3 w, int l,
-                                      uint64_t seed, uint32_t frame, Stack& st, RCount& rc) {
-  Hit h = closest_hit(S, xk, w, st);
-  ++rc.rays;
-  if (h.gid == kHitNone) {
-    ++rc.truncated;
-    return k;
-  }
-  float3 xn = add(xk, mul(w, h.t));
-  float3 en;
-  if (k == 0) {
-    float N = (float)S.lights[l].path_count;
-    en = f3(__fdiv_rn(S.lights[l].power[0], N), __fdiv_rn(S.lights[l].power[1], N),
-            __fdiv_rn(S.lights[l].power[2], N));
-  } else {
-    en = reflect_energy(S, energy_row(S, p, k - 1), mat_of(S, vertex_hit(S, p, k)));
-  }
-  put_photon(S, p, k, xn, h.gid, en);
-  ++rc.photons;
-  return naive_tail(S, p, k, xn, w, hit_normal(h), hit_material(h), en, seed, frame, st, rc);
-}
-
 __device__ inline bool eq2(float3 en, float3 eo, float T) {
   float d0 = __fsub_rn(en.x, eo.x), d1 = __fsub_rn(en.y, eo.y), d2 = __fsub_rn(en.z, eo.z);
   float t0 = __fmul_rn(T, eo.x), t1 = __fmul_rn(T, eo.y), t2 = __fmul_rn(T, eo.z);
@@ -556,17 +639,6 @@ __device__ inline bool on_moved_obj(const SceneDev& S, uint32_t hit) {
   return false;
 }
 
-__device__ inline bool seg_blocked_moved(const SceneDev& S, float3 a, float3 b, Stack& st) {
-  Ray r = segment_ray(a, b, S.eps_end);
-  for (uint32_t o = 0; o < S.n_obj; ++o) {
-    if (!S.obj_moved[o]) continue;
-    const float* bx = S.obj_aabb + 6 * o;
-    if (box_entry(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, r.tmax) == __builtin_inff()) continue;
-    if (bvh_any(S.dnodes, S.dtris, S.objs[o].root, r, st)) return true;
-  }
-  return false;
-}
-
 __device__ inline void clear_rows(const SceneDev& S, uint32_t p, uint32_t from) {
   for (uint32_t r = from; r < S.B; ++r) {
     size_t i = (size_t)r * S.stride + p;
@@ -576,102 +648,6 @@ __device__ inline void clear_rows(const SceneDev& S, uint32_t p, uint32_t from) 
 }
 
 __device__ inline float3 normalize3(float3 v) { return mul(v, 1.0f / length(v)); }
-
-__device__ void retrace_path(const SceneDev& S, uint32_t p, float T, uint64_t seed, uint32_t frame, Stack& st,
-                             RCount& rc) {
-  uint32_t w = S.info[p];
-  if (!info_replace(w)) return;
-  uint32_t n = min(info_nseg(w), S.B), k = info_start(w), cell = info_cell(w);
-  int l = light_of(S, p);
-  if (l < 0) return;
-  bool reuse = info_reuse(w) != 0;
-  if (k >= n) {  // nothing to keep: a new light sample
-    k = 0;
-    reuse = false;
-  }
-  uint32_t newn;
-  if (k == 0 && !reuse) {
-    // new light sample: position uniform on the rectangle, direction
-    // cosine-weighted about the light normal (one Philox draw, tag 0)
-    const float* xf = S.light_xf_cur + 12 * l;
-    float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
-    float3 nl = normalize3(f3(xf[2], xf[6], xf[10])), c = f3(xf[3], xf[7], xf[11]);
-    float u[4];
-    draw4(seed, p, frame, 0, 0, u);
-    float a = (2.0f * u[0] - 1.0f) * S.lights[l].half[0], b = (2.0f * u[1] - 1.0f) * S.lights[l].half[1];
-    float3 x0 = add(c, add(mul(eu, a), mul(ev, b)));
-    float3 lc = cosine_local(u[2], u[3]);
-    float3 w0 = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
-    const size_t stride = S.stride;
-    S.origin[p] = x0.x;
-    S.origin[stride + p] = x0.y;
-    S.origin[2 * stride + p] = x0.z;
-    newn = naive_from(S, p, 0, x0, w0, l, seed, frame, st, rc);
-  } else if (T < 0.0f) {
-    float3 xa = vertex(S, p, k), xb = vertex(S, p, k + 1);
-    newn = naive_from(S, p, k, xa, normalize3(sub(xb, xa)), l, seed, frame, st, rc);
-  } else {
-    // Algorithm 1: trace iff blocked, origin moved or end photon on a moved
-    // object; keep the rest of the path when Equation 2 holds
-    uint32_t j = k;
-    bool need = true;
-    newn = n;
-    while (j < newn) {
-      float3 xa = vertex(S, p, j), xb = vertex(S, p, j + 1);
-      if (!need) {
-        bool inv = on_moved_obj(S, vertex_hit(S, p, j + 1));
-        if (!inv) inv = seg_blocked_moved(S, xa, xb, st);
-        if (!inv) {
-          ++j;
-          continue;
-        }
-      }
-      float3 d = normalize3(sub(xb, xa));
-      Hit h = closest_hit(S, xa, d, st);
-      ++rc.rays;
-      if (h.gid == kHitNone) {
-        newn = j;
-        ++rc.truncated;
-        break;
-      }
-      float3 hp = add(xa, mul(d, h.t));
-      float3 ej = energy_row(S, p, j);
-      if (j == newn - 1) {
-        put_photon(S, p, j, hp, h.gid, ej);
-        ++rc.photons;
-        break;
-      }
-      float3 xc = vertex(S, p, j + 2);
-      float3 d2 = sub(xc, hp);
-      float3 nh = hit_normal(h);
-      float c1 = dot(d, nh), l2 = length(d2);
-      float c2 = l2 > 0.0f ? dot(d2, nh) / l2 : 0.0f;
-      uint32_t mat = hit_material(h);
-      float3 en = (c1 * c2 < 0.0f) ? reflect_energy(S, ej, mat) : f3(0.0f, 0.0f, 0.0f);
-      float3 eo = energy_row(S, p, j + 1);
-      if (!eq2(en, eo, T)) {
-        put_photon(S, p, j, hp, h.gid, ej);
-        ++rc.photons;
-        newn = naive_tail(S, p, j, hp, d, nh, mat, ej, seed, frame, st, rc);
-        break;
-      }
-      ++rc.accepted;
-      float dist = length(sub(hp, xb));
-      if (dist <= S.eps_close && !on_moved_obj(S, h.gid) && !on_moved_obj(S, vertex_hit(S, p, j + 1)) &&
-          !on_moved_obj(S, vertex_hit(S, p, j + 2)) && !seg_blocked_moved(S, xb, xc, st)) {
-        j += 2;
-        need = false;
-        continue;
-      }
-      put_photon(S, p, j, hp, h.gid, ej);
-      ++rc.photons;
-      ++j;
-      need = true;
-    }
-  }
-  clear_rows(S, p, newn);
-  S.info[p] = info_pack(cell, newn, 0, 0, 0);
-}
 
 __device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_t gp) {
   int lo = 0, hi = n_scenes;  // gbase[s] <= gp < gbase[s+1]
@@ -685,34 +661,314 @@ __device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_
   return (uint32_t)lo;
 }
 
+// Re-trace state machine: every iteration each busy lane issues exactly one
+// query (closest hit over the scene, or any hit against the moved objects),
+// then advances its path; lanes whose path is finished take the next path of
+// the work queue (persistent while-while scheme, Aila & Laine 2009).
+enum : uint32_t {
+  ST_IDLE = 0,   // needs a path
+  ST_FIRST,      // trace segment k from x (direction w), naive continuation
+  ST_TAIL,       // sample a bounce from photon 'row' and trace it
+  ST_WCHECK,     // walk: is segment j (origin unchanged) still valid?
+  ST_WTRACE,     // walk: trace segment j
+  ST_WSKIP,      // walk: accepted close re-hit; is segment j+1 clear?
+  ST_END         // queue exhausted
+};
+
+struct Lane {
+  const SceneDev* S;
+  uint32_t p, mode, n, k, cell, j, newn, row, mat, hgid;
+  int l;
+  float3 x, w, ntri, e, hp;
+};
+
+__device__ inline void finish(Lane& L) {
+  clear_rows(*L.S, L.p, L.newn);
+  L.S->info[L.p] = info_pack(L.cell, L.newn, 0, 0, 0);
+  L.mode = ST_IDLE;
+}
+
+// after writing photon 'row' (position x, triangle normal, material, energy):
+// continue sampling or finish
+__device__ inline void to_tail(Lane& L) {
+  if (L.row + 1 < L.S->B) {
+    L.mode = ST_TAIL;
+  } else {
+    L.newn = L.row + 1;
+    finish(L);
+  }
+}
+
+__device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t frame) {
+  const SceneDev& S = *L.S;
+  uint32_t w = S.info[L.p];
+  L.n = min(info_nseg(w), S.B);
+  L.k = info_start(w);
+  L.cell = info_cell(w);
+  L.l = light_of(S, L.p);
+  bool reuse = info_reuse(w) != 0;
+  if (!info_replace(w) || L.l < 0) {
+    L.mode = ST_IDLE;
+    return;
+  }
+  if (L.k >= L.n) {
+    L.k = 0;
+    reuse = false;
+  }
+  if (L.k == 0 && !reuse) {
+    // new light sample: position uniform on the rectangle, direction
+    // cosine-weighted about the light normal (one Philox draw, tag 0)
+    const float* xf = S.light_xf_cur + 12 * L.l;
+    float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
+    float3 nl = normalize3(f3(xf[2], xf[6], xf[10])), c = f3(xf[3], xf[7], xf[11]);
+    float u[4];
+    draw4(seed, L.p, frame, 0, 0, u);
+    float a = (2.0f * u[0] - 1.0f) * S.lights[L.l].half[0], b = (2.0f * u[1] - 1.0f) * S.lights[L.l].half[1];
+    float3 x0 = add(c, add(mul(eu, a), mul(ev, b)));
+    float3 lc = cosine_local(u[2], u[3]);
+    L.w = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
+    const size_t stride = S.stride;
+    S.origin[L.p] = x0.x;
+    S.origin[stride + L.p] = x0.y;
+    S.origin[2 * stride + L.p] = x0.z;
+    L.x = x0;
+    L.mode = ST_FIRST;
+  } else if (T < 0.0f) {
+    L.x = vertex(S, L.p, L.k);
+    L.w = normalize3(sub(vertex(S, L.p, L.k + 1), L.x));
+    L.mode = ST_FIRST;
+  } else {
+    L.j = L.k;
+    L.newn = L.n;
+    L.mode = ST_WTRACE;
+  }
+}
+
+template <bool kSingle>
 __global__ __launch_bounds__(kBlock) void k_retrace(const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ gbase,
                                                     int n_scenes, const uint32_t* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount, uint32_t* head, float T,
-                                                    uint64_t seed, uint32_t frame, pv_stats* stats) {
+                                                    uint64_t seed, uint32_t frame_arg, const uint32_t* frame_ptr,
+                                                    pv_stats* stats) {
   __shared__ uint32_t sstack[kLdsStack * kBlock];
   __shared__ unsigned long long sred[kBlock / 64];
   Stack st;
   st.lds = sstack + threadIdx.x;
   st.sp = 0;
-  RCount rc = {0, 0, 0, 0};
+  const uint32_t frame = frame_ptr ? *frame_ptr : frame_arg;
+  uint32_t n_rays = 0, n_photons = 0, n_acc = 0, n_trunc = 0;
   const uint32_t count = *qcount;
+  Lane L;
+  L.S = scenes;
+  L.mode = ST_IDLE;
+  L.p = 0;
   while (true) {
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(head, 64u);
-    base = __shfl(base, 0, 64);
-    if (base >= count) break;
-    uint32_t qi = base + lane_id();
-    if (qi < count) {
-      uint32_t gp = queue[qi];
-      uint32_t s = scene_of(gbase, n_scenes, gp);
-      retrace_path(scenes[s], gp - gbase[s], T, seed, frame, st, rc);
+    // refill idle lanes from the queue: one atomic per wave
+    bool want = L.mode == ST_IDLE;
+    uint64_t m = __ballot(want);
+    if (m) {
+      uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+      uint32_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(head, (uint32_t)__popcll(m));
+      base = __shfl(base, (int)leader, 64);
+      if (want) {
+        uint32_t qi = base + (uint32_t)__popcll(m & lanemask_lt());
+        if (qi < count) {
+          uint32_t gp = queue[qi];
+          if (kSingle) {
+            L.p = gp;
+          } else {
+            uint32_t s = scene_of(gbase, n_scenes, gp);
+            L.S = scenes + s;
+            L.p = gp - gbase[s];
+          }
+          start_path(L, T, seed, frame);
+          // a path without the replace bit is skipped (stays idle this round)
+        } else {
+          L.mode = ST_END;
+        }
+      }
+    }
+    if (__ballot(L.mode != ST_END && L.mode != ST_IDLE) == 0) {
+      if (__ballot(L.mode == ST_IDLE) == 0) break;
+      continue;
+    }
+    const SceneDev& S = kSingle ? scenes[0] : *L.S;
+    bool busy = L.mode != ST_IDLE && L.mode != ST_END;
+    // ---- build this lane's query
+    bool any = false, moved_only = false;
+    float3 qo = L.x, qd = L.w, wn = L.w, xa, xb;
+    float tmin = S.eps_end, tmax = kTFar;
+    if (busy) {
+      if (L.mode == ST_TAIL) {
+        float3 nrm = dot(L.ntri, L.w) > 0.0f ? mul(L.ntri, -1.0f) : L.ntri;
+        float u[4];
+        draw4(seed, L.p, frame, L.row + 1, 1, u);
+        float3 lc = cosine_local(u[0], u[1]);
+        float3 tt, bb;
+        onb(nrm, &tt, &bb);
+        wn = add(add(mul(tt, lc.x), mul(bb, lc.y)), mul(nrm, lc.z));
+        qd = wn;
+      } else if (L.mode == ST_WCHECK || L.mode == ST_WTRACE || L.mode == ST_WSKIP) {
+        uint32_t sj = L.mode == ST_WSKIP ? L.j + 1 : L.j;
+        xa = vertex(S, L.p, sj);
+        xb = vertex(S, L.p, sj + 1);
+        if (L.mode == ST_WCHECK && on_moved_obj(S, vertex_hit(S, L.p, sj + 1))) L.mode = ST_WTRACE;
+        if (L.mode == ST_WTRACE) {
+          qo = xa;
+          qd = normalize3(sub(xb, xa));
+        } else {
+          // any hit of the segment xa -> xb against the moved objects
+          any = true;
+          moved_only = true;
+          qo = xa;
+          qd = sub(xb, xa);
+          float len = length(qd);
+          tmin = len > 0.0f ? S.eps_end / len : 1.0f;
+          tmax = 1.0f - tmin;
+        }
+      }
+    }
+    Hit h;
+    h.gid = kHitNone;
+    if (busy) {
+      Ray r = make_ray(qo, qd, tmin, tmax);
+      trace(S, r, any, moved_only, st, &h);
+      if (!any) ++n_rays;
+    }
+    if (!busy) continue;
+    // ---- advance the state machine with the result
+    const bool hit = h.gid != kHitNone;
+    switch (L.mode) {
+      case ST_FIRST: {
+        if (!hit) {
+          ++n_trunc;
+          L.newn = L.k;
+          finish(L);
+          break;
+        }
+        float3 xn = add(L.x, mul(L.w, h.t));
+        float3 en;
+        if (L.k == 0) {
+          float N = (float)S.lights[L.l].path_count;
+          en = f3(__fdiv_rn(S.lights[L.l].power[0], N), __fdiv_rn(S.lights[L.l].power[1], N),
+                  __fdiv_rn(S.lights[L.l].power[2], N));
+        } else {
+          en = reflect_energy(S, energy_row(S, L.p, L.k - 1), mat_of(S, vertex_hit(S, L.p, L.k)));
+        }
+        put_photon(S, L.p, L.k, xn, h.gid, en);
+        ++n_photons;
+        L.x = xn;
+        L.ntri = hit_normal(h);
+        L.mat = hit_material(h);
+        L.e = en;
+        L.row = L.k;
+        to_tail(L);
+        break;
+      }
+      case ST_TAIL: {
+        if (!hit) {
+          ++n_trunc;
+          L.newn = L.row + 1;
+          finish(L);
+          break;
+        }
+        float3 xn = add(L.x, mul(wn, h.t));
+        float3 en = reflect_energy(S, L.e, L.mat);
+        L.row += 1;
+        put_photon(S, L.p, L.row, xn, h.gid, en);
+        ++n_photons;
+        L.x = xn;
+        L.w = wn;
+        L.ntri = hit_normal(h);
+        L.mat = hit_material(h);
+        L.e = en;
+        to_tail(L);
+        break;
+      }
+      case ST_WCHECK: {
+        if (hit) {
+          L.mode = ST_WTRACE;
+        } else if (++L.j >= L.newn) {
+          finish(L);
+        }
+        break;
+      }
+      case ST_WTRACE: {
+        if (!hit) {
+          ++n_trunc;
+          L.newn = L.j;
+          finish(L);
+          break;
+        }
+        float3 hp = add(xa, mul(qd, h.t));
+        float3 ej = energy_row(S, L.p, L.j);
+        if (L.j == L.newn - 1) {
+          put_photon(S, L.p, L.j, hp, h.gid, ej);
+          ++n_photons;
+          finish(L);
+          break;
+        }
+        float3 xc = vertex(S, L.p, L.j + 2);
+        float3 d2 = sub(xc, hp);
+        float3 nh = hit_normal(h);
+        float c1 = dot(qd, nh), l2 = length(d2);
+        float c2 = l2 > 0.0f ? dot(d2, nh) / l2 : 0.0f;
+        uint32_t mat = hit_material(h);
+        float3 en = (c1 * c2 < 0.0f) ? reflect_energy(S, ej, mat) : f3(0.0f, 0.0f, 0.0f);
+        float3 eo = energy_row(S, L.p, L.j + 1);
+        if (!eq2(en, eo, T)) {
+          // energies differ: keep the new hit and re-sample the rest
+          put_photon(S, L.p, L.j, hp, h.gid, ej);
+          ++n_photons;
+          L.x = hp;
+          L.w = qd;
+          L.ntri = nh;
+          L.mat = mat;
+          L.e = ej;
+          L.row = L.j;
+          to_tail(L);
+          break;
+        }
+        ++n_acc;
+        float dist = length(sub(hp, xb));
+        if (dist <= S.eps_close && !on_moved_obj(S, h.gid) && !on_moved_obj(S, vertex_hit(S, L.p, L.j + 1)) &&
+            !on_moved_obj(S, vertex_hit(S, L.p, L.j + 2))) {
+          L.hp = hp;
+          L.hgid = h.gid;
+          L.mode = ST_WSKIP;  // the next segment must also be clear
+          break;
+        }
+        put_photon(S, L.p, L.j, hp, h.gid, ej);
+        ++n_photons;
+        ++L.j;
+        L.mode = ST_WTRACE;
+        break;
+      }
+      case ST_WSKIP: {
+        if (!hit) {
+          L.j += 2;
+          if (L.j >= L.newn)
+            finish(L);
+          else
+            L.mode = ST_WCHECK;
+        } else {
+          put_photon(S, L.p, L.j, L.hp, L.hgid, energy_row(S, L.p, L.j));
+          ++n_photons;
+          ++L.j;
+          L.mode = ST_WTRACE;
+        }
+        break;
+      }
+      default:
+        break;
     }
   }
   if (stats) {
-    unsigned long long a = block_sum_u64(rc.rays, sred);
-    unsigned long long b = block_sum_u64(rc.photons, sred);
-    unsigned long long c = block_sum_u64(rc.accepted, sred);
-    unsigned long long d = block_sum_u64(rc.truncated, sred);
+    unsigned long long a = block_sum_u64(n_rays, sred);
+    unsigned long long b = block_sum_u64(n_photons, sred);
+    unsigned long long c = block_sum_u64(n_acc, sred);
+    unsigned long long d = block_sum_u64(n_trunc, sred);
     if (threadIdx.x == 0) {
       atomicAdd(&stats->rays_traced, a);
       atomicAdd(&stats->photons_written, b);
@@ -726,7 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_retrace(const SceneDev* __restrict__
 // compaction of existing photons: counts per (row, block), scan, scatter
 
 __global__ __launch_bounds__(kBlock) void k_photon_count(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
-                                                         uint32_t n_blocks, uint32_t* __restrict__ counts) {
+                                                         uint32_t* __restrict__ counts) {
   __shared__ uint32_t wc[PV_MAX_BOUNCES][kBlock / 64];
   uint2 tile = tiles[blockIdx.x];
   const SceneDev& S = scenes[tile.x];
@@ -740,12 +996,12 @@ __global__ __launch_bounds__(kBlock) void k_photon_count(const SceneDev* __restr
   if (threadIdx.x < S.B) {
     uint32_t c = 0;
     for (int w = 0; w < kBlock / 64; ++w) c += wc[threadIdx.x][w];
-    counts[threadIdx.x * n_blocks + blockIdx.x] = c;
+    counts[S.count_base + threadIdx.x * S.n_blocks + tile.y / kBlock] = c;
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_photon_scatter(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
-                                                           uint32_t n_blocks, const uint32_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ offsets,
                                                            float* __restrict__ out_pos, float* __restrict__ out_e,
                                                            uint32_t capacity) {
   __shared__ uint32_t wcnt[kBlock / 64];
@@ -761,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_photon_scatter(const SceneDev* __res
   uint32_t pre = 0;
   for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) pre += wcnt[w];
   if (!flag) return;
-  uint32_t idx = offsets[r * n_blocks + blockIdx.x] + pre + (uint32_t)__popcll(bal & lanemask_lt());
+  uint32_t idx = offsets[S.count_base + r * S.n_blocks + tile.y / kBlock] + pre + (uint32_t)__popcll(bal & lanemask_lt());
   if (idx >= capacity) return;
   size_t i = (size_t)r * S.stride + p;
   float4 x = S.pos[i], e = S.energy[i];
@@ -873,8 +1129,8 @@ __global__ void k_reduce_partials(const float* __restrict__ partial, uint32_t n_
 // launch wrappers (host side)
 
 hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
-                              const float* const* light_in, uint32_t* state, hipStream_t s) {
-  hipLaunchKernelGGL(k_frame_begin, dim3(n_scenes), dim3(64), 0, s, scenes, n_scenes, obj_in, light_in, state);
+                              const float* const* light_in, hipStream_t s) {
+  hipLaunchKernelGGL(k_frame_begin, dim3(n_scenes), dim3(64), 0, s, scenes, n_scenes, obj_in, light_in);
   return hipGetLastError();
 }
 
@@ -919,16 +1175,20 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
 
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
-                          pv_stats* stats, uint32_t n_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_retrace, dim3(n_blocks), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head, T,
-                     seed, frame, stats);
+                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, hipStream_t s) {
+  if (n_scenes == 1)
+    hipLaunchKernelGGL(k_retrace<true>, dim3(n_blocks), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount,
+                       head, T, seed, frame, frame_ptr, stats);
+  else
+    hipLaunchKernelGGL(k_retrace<false>, dim3(n_blocks), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount,
+                       head, T, seed, frame, frame_ptr, stats);
   return hipGetLastError();
 }
 
 hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
                                hipStream_t s) {
   if (!n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_photon_count, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, n_tiles, counts);
+  hipLaunchKernelGGL(k_photon_count, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, counts);
   return hipGetLastError();
 }
 
@@ -936,8 +1196,24 @@ hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uin
                                  const uint32_t* offsets, float* out_pos, float* out_e, uint32_t capacity,
                                  hipStream_t s) {
   if (!n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_photon_scatter, dim3(n_tiles, B), dim3(kBlock), 0, s, scenes, tiles, n_tiles, offsets, out_pos,
-                     out_e, capacity);
+  hipLaunchKernelGGL(k_photon_scatter, dim3(n_tiles, B), dim3(kBlock), 0, s, scenes, tiles, offsets, out_pos, out_e,
+                     capacity);
+  return hipGetLastError();
+}
+
+// photon ranges of the scenes of a batch: base[s] = offsets[count_base of s],
+// base[n] = total
+__global__ void k_scene_photon_base(const SceneDev* __restrict__ scenes, int n_scenes, const uint32_t* __restrict__ offsets,
+                                    const uint32_t* __restrict__ total, uint32_t* __restrict__ base) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_scenes) base[i] = offsets[scenes[i].count_base];
+  if (i == n_scenes) base[i] = *total;
+}
+
+hipError_t launch_scene_photon_base(const SceneDev* scenes, int n_scenes, const uint32_t* offsets, const uint32_t* total,
+                                    uint32_t* base, hipStream_t s) {
+  hipLaunchKernelGGL(k_scene_photon_base, dim3((n_scenes + 64) / 64), dim3(64), 0, s, scenes, n_scenes, offsets, total,
+                     base);
   return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@
 namespace pv {
 
 hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
-                              const float* const* light_in, uint32_t* state, hipStream_t s);
+                              const float* const* light_in, hipStream_t s);
 hipError_t launch_transform(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
 hipError_t launch_refit(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
 hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
@@ -20,12 +20,14 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
                            hipStream_t s);
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
-                          pv_stats* stats, uint32_t n_blocks, hipStream_t s);
+                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
                                hipStream_t s);
 hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t B,
                                  const uint32_t* offsets, float* out_pos, float* out_e, uint32_t capacity,
                                  hipStream_t s);
+hipError_t launch_scene_photon_base(const SceneDev* scenes, int n_scenes, const uint32_t* offsets, const uint32_t* total,
+                                    uint32_t* base, hipStream_t s);
 hipError_t launch_energy_fwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,
                              const float* power, float* E, hipStream_t s);
 hipError_t launch_energy_bwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,

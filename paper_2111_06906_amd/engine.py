@@ -186,3 +186,42 @@ class Context:
         """Frame-0 photon paths (every path a new light sample)."""
         self.queue_all(store)
         self.retrace(store, -1.0, seed, frame, stats)
+
+
+class Batch:
+    """Several scene contexts run as one frame: one launch per phase, the whole
+    frame captured in a HIP graph (batched form)."""
+
+    def __init__(self, contexts, stores, threshold, seed):
+        self.contexts = list(contexts)
+        self.stores = list(stores)
+        self._cs = [s.cstruct() for s in self.stores]
+        self.b = L.batch_create([c.ctx for c in self.contexts], self._cs,
+                                [c.obj_xf[0].data_ptr() for c in self.contexts],
+                                [c.light_xf[0].data_ptr() for c in self.contexts], float(threshold), int(seed))
+
+    def frame(self, f, stats=None):
+        owner = self.contexts[0].ctx
+        L.batch_set_transforms(self.b, [c.obj_xf[f].data_ptr() for c in self.contexts],
+                               [c.light_xf[f].data_ptr() for c in self.contexts], owner)
+        L.batch_frame(self.b, int(f), _ptr(stats), owner)
+
+    def photons(self):
+        """(positions [cap,3], energies [cap,3], per-scene first photon [n+1]) of the last frame."""
+        cap = sum(s.n_paths * s.B for s in self.stores)
+        pos = torch.empty((max(cap, 1), 3), dtype=F32, device="cuda")
+        en = torch.empty((max(cap, 1), 3), dtype=F32, device="cuda")
+        base = torch.empty(len(self.contexts) + 1, dtype=I32, device="cuda")
+        L.batch_copy_photons(self.b, _ptr(pos), _ptr(en), cap, _ptr(base), self.contexts[0].ctx)
+        return pos, en, base
+
+    def close(self):
+        if getattr(self, "b", None):
+            L.batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

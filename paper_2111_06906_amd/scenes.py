@@ -117,15 +117,15 @@ def _tess_quad(origin, eu, ev, nu, nv):
     o = np.asarray(origin, np.float64)
     eu = np.asarray(eu, np.float64)
     ev = np.asarray(ev, np.float64)
-    tris = []
-    for i in range(nu):
-        for j in range(nv):
-            a = o + eu * (i / nu) + ev * (j / nv)
-            b = o + eu * ((i + 1) / nu) + ev * (j / nv)
-            c = o + eu * ((i + 1) / nu) + ev * ((j + 1) / nv)
-            d = o + eu * (i / nu) + ev * ((j + 1) / nv)
-            tris += _quad(a, b, c, d)
-    return tris
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    i, j = i.reshape(-1, 1), j.reshape(-1, 1)
+    a = o + eu * (i / nu) + ev * (j / nv)
+    b = o + eu * ((i + 1) / nu) + ev * (j / nv)
+    c = o + eu * ((i + 1) / nu) + ev * ((j + 1) / nv)
+    d = o + eu * (i / nu) + ev * ((j + 1) / nv)
+    t1 = np.stack([a, b, c], axis=1)
+    t2 = np.stack([a, c, d], axis=1)
+    return list(np.stack([t1, t2], axis=1).reshape(-1, 3, 3))
 
 
 def _box(lo, hi, h=None):

@@ -233,3 +233,42 @@ def test_energy_forward_backward(E):
     oa, op = O.energy_backward(fs0, ora0, alb.astype(np.float64), pw.astype(np.float64), g.astype(np.float64))
     np.testing.assert_allclose(ga.cpu().numpy(), oa, rtol=1e-4, atol=1e-12)
     np.testing.assert_allclose(gp.cpu().numpy(), op, rtol=1e-4, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# batched form: one launch per phase over every scene, bit-identical to the
+# per-scene calls
+
+
+def test_batch_matches_plain(E):
+    import torch
+    scs = scenes.make_batch(n_scenes=6, frames=3, path_range=(2000, 30000), tri_range=(5000, 40000))
+    T, seed = 0.01, 7
+    log("batch of %d scenes, %d paths" % (len(scs), sum(s.n_paths for s in scs)))
+    plain = [E.Context(s) for s in scs]
+    batch_ctx = [E.Context(s) for s in scs]
+    sp = [c.new_store() for c in plain]
+    sb = [c.new_store() for c in batch_ctx]
+    for c, st in list(zip(plain, sp)) + list(zip(batch_ctx, sb)):
+        c.frame_begin(0)
+        c.initial_trace(st, seed, 0)
+    b = E.Batch(batch_ctx, sb, T, seed)
+    for f in (1, 2):
+        for c, st in zip(plain, sp):
+            c.frame_begin(f)
+            c.verify(st)
+            c.retrace(st, T, seed, f)
+        b.frame(f)
+        torch.cuda.synchronize()
+        for i, (x, y) in enumerate(zip(sp, sb)):
+            dx, dy = x.to_numpy(), y.to_numpy()
+            for k in dx:
+                assert np.array_equal(dx[k].view(np.uint32), dy[k].view(np.uint32)), (f, i, k)
+    # photon compaction of the batch equals the per-scene compaction
+    pos, en, base = b.photons()
+    base = base.cpu().numpy()
+    for i, (c, st) in enumerate(zip(plain, sp)):
+        p1, e1, n1 = c.compact_photons(st)
+        assert base[i + 1] - base[i] == n1
+        assert torch.equal(pos[base[i]:base[i + 1]], p1) and torch.equal(en[base[i]:base[i + 1]], e1)
+    b.close()

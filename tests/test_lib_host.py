@@ -65,3 +65,23 @@ def test_declared_symbols_parse():
     for n in ("pv_create", "pv_upload_scene", "pv_frame_begin", "pv_verify_paths", "pv_retrace_paths",
               "pv_compact_photons", "pv_energy_forward", "pv_energy_backward"):
         assert n in names
+
+
+@pytest.mark.parametrize("make,kind", [("tiny", 0), ("mid", 0), ("mid_obj", 1), ("paper", 0), ("paper_obj", 1)])
+def test_hierarchy_invariants(make, kind):
+    from paper_2111_06906_amd import scenes
+    if make == "tiny":
+        v = scenes.make_tiny().static_verts
+    elif make.startswith("mid"):
+        sc = scenes.make_mid(n_paths=10, frames=2)
+        v = sc.static_verts if kind == 0 else sc.obj_local[0]
+    else:
+        sc = scenes.make_paper(n_paths=10, frames=2)
+        v = sc.static_verts if kind == 0 else sc.obj_local[0]
+    info = L.hierarchy_info(v, kind)
+    n = v.shape[0]
+    assert info["valid"]
+    assert info["nodes"] == info["leaves"] - 1          # full binary tree
+    assert info["depth"] <= 63
+    if kind == 1:
+        assert info["leaves"] >= n // 2                  # leaves of at most 2 triangles
