@@ -47,10 +47,8 @@ struct pv_ctx {
   SceneDev hs{};               // host image of the descriptor
   SceneDev* d_scene = nullptr; // device descriptor (one entry)
   uint32_t* d_state = nullptr; // first-frame flag
-  uint2* d_tri_tiles = nullptr;
-  uint32_t n_tri_tiles = 0;
-  uint2* d_leaf_tiles = nullptr;
-  uint32_t n_leaf_tiles = 0;
+  uint2* d_obj_tiles = nullptr;  // (scene, object) for the object update kernel
+  uint32_t n_obj_tiles = 0;
   const float** d_in_ptrs = nullptr;  // [2]: object / light transform inputs of the frame
   uint32_t n_materials = 0, n_lights = 0, n_objects = 0;
   std::vector<uint32_t> h_light_paths;  // filled at binding
@@ -74,8 +72,8 @@ struct pv_batch {
   uint32_t n = 0;
   Alloc mem;
   SceneDev* d_scenes = nullptr;
-  uint2 *d_path_tiles = nullptr, *d_tri_tiles = nullptr, *d_leaf_tiles = nullptr;
-  uint32_t n_path_tiles = 0, n_tri_tiles = 0, n_leaf_tiles = 0;
+  uint2 *d_path_tiles = nullptr, *d_obj_tiles = nullptr;
+  uint32_t n_path_tiles = 0, n_obj_tiles = 0;
   uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr, *d_head = nullptr,
            *d_gbase = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_ptotal = nullptr, *d_pbase = nullptr,
            *d_frame = nullptr;
@@ -692,8 +690,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     std::vector<ObjDev> objs(d->n_objects);
     std::vector<float> dlocal(9 * n_dyn);
     std::vector<uint32_t> dgid(n_dyn);
-    std::vector<LeafRec> leaves;
-    std::vector<int32_t> nparent;
+    std::vector<uint32_t> level_nodes, level_off;
     std::vector<Node> dnodes;
     uint32_t tri_base = 0, gbase = S;
     for (uint32_t o = 0; o < d->n_objects; ++o) {
@@ -701,34 +698,43 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       const float* v = d->h_obj_verts + 9 * (size_t)tri_base;
       HostBvh hb = build_topology(v, n, 2);
       if (hb.max_depth > kMaxDepth) return fail(ctx, PV_ERR_CAPACITY, "object hierarchy too deep");
-      uint32_t node_base = (uint32_t)dnodes.size(), leaf_base = (uint32_t)leaves.size();
+      uint32_t node_base = (uint32_t)dnodes.size();
       auto rebase = [&](int32_t c) {
         return c >= 0 ? c + (int32_t)node_base
                       : pv::leaf_code(pv::leaf_first(c) + tri_base, pv::leaf_count(c));
       };
+      // depth of every internal node (parents precede children in the node order)
+      std::vector<uint32_t> depth(hb.nodes.size(), 0);
+      uint32_t maxd = 0;
+      for (size_t i = 0; i < hb.nodes.size(); ++i) {
+        int32_t par = hb.parent[i];
+        depth[i] = par < 0 ? 0 : depth[par >> 1] + 1;
+        maxd = std::max(maxd, depth[i]);
+      }
+      ObjDev& ob = objs[o];
+      ob.lvl_base = (uint32_t)level_off.size();
+      ob.n_levels = hb.nodes.empty() ? 0 : maxd + 1;
+      for (int64_t lv = (int64_t)maxd; lv >= 0 && !hb.nodes.empty(); --lv) {
+        level_off.push_back((uint32_t)level_nodes.size());
+        for (size_t i = 0; i < hb.nodes.size(); ++i)
+          if (depth[i] == (uint32_t)lv) level_nodes.push_back(node_base + (uint32_t)i);
+      }
+      level_off.push_back((uint32_t)level_nodes.size());
       for (Node nd : hb.nodes) {
         nd.d.x = rebase(nd.d.x);
         nd.d.y = rebase(nd.d.y);
         if (nd.d.z >= 0) nd.d.z += 2 * (int32_t)node_base;
         dnodes.push_back(nd);
-        nparent.push_back(nd.d.z);
-      }
-      for (LeafRec L : hb.leaves) {
-        L.first += tri_base;
-        if (L.parent >= 0) L.parent += (int32_t)node_base;
-        leaves.push_back(L);
       }
       for (uint32_t i = 0; i < n; ++i) {
         std::memcpy(&dlocal[9 * (size_t)(tri_base + i)], v + 9 * (size_t)hb.order[i], 9 * sizeof(float));
         dgid[tri_base + i] = gbase + hb.order[i];
       }
-      ObjDev& ob = objs[o];
       ob.gbase = gbase;
       ob.n_tris = n;
       ob.tri_base = tri_base;
       ob.node_base = node_base;
-      ob.n_leaves = (uint32_t)hb.leaves.size();
-      ob.leaf_base = leaf_base;
+      ob.n_nodes = (uint32_t)hb.nodes.size();
       ob.root = rebase(hb.root);
       tri_base += n;
       gbase += n;
@@ -736,25 +742,21 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     Node* d_dnodes;
     Tri* d_dtris;
     float* d_dlocal;
-    uint32_t *d_dgid, *d_counter;
-    LeafRec* d_leaves;
-    int32_t* d_nparent;
+    uint32_t *d_dgid, *d_lnodes, *d_loff;
     ObjDev* d_objs;
     CK(upload(A, &d_dnodes, dnodes.data(), dnodes.size(), s));
     CK(dalloc(A, &d_dtris, n_dyn));
     CK(upload(A, &d_dlocal, dlocal.data(), dlocal.size(), s));
     CK(upload(A, &d_dgid, dgid.data(), dgid.size(), s));
-    CK(upload(A, &d_leaves, leaves.data(), leaves.size(), s));
-    CK(upload(A, &d_nparent, nparent.data(), nparent.size(), s));
-    CK(dalloc(A, &d_counter, dnodes.size()));
+    CK(upload(A, &d_lnodes, level_nodes.data(), level_nodes.size(), s));
+    CK(upload(A, &d_loff, level_off.data(), level_off.size(), s));
     CK(upload(A, &d_objs, objs.data(), objs.size(), s));
     hs.dnodes = d_dnodes;
     hs.dtris = d_dtris;
     hs.dlocal = d_dlocal;
     hs.dtri_gid = d_dgid;
-    hs.dleaves = d_leaves;
-    hs.dnode_parent = d_nparent;
-    hs.dcounter = d_counter;
+    hs.dlevel_nodes = d_lnodes;
+    hs.dlevel_off = d_loff;
     hs.objs = d_objs;
     hs.n_obj = d->n_objects;
     hs.n_dyn_tris = (uint32_t)n_dyn;
@@ -789,11 +791,10 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     uint32_t one = 1;
     CK(hipMemcpyAsync(ctx->d_state, &one, 4, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(ctx->d_scene, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
-    std::vector<uint2> tt = make_tiles(0, (uint32_t)n_dyn), lt = make_tiles(0, (uint32_t)leaves.size());
-    CK(upload(A, &ctx->d_tri_tiles, tt.data(), tt.size(), s));
-    CK(upload(A, &ctx->d_leaf_tiles, lt.data(), lt.size(), s));
-    ctx->n_tri_tiles = (uint32_t)tt.size();
-    ctx->n_leaf_tiles = (uint32_t)lt.size();
+    std::vector<uint2> ot;
+    for (uint32_t o = 0; o < d->n_objects; ++o) ot.push_back(make_uint2(0, o));
+    CK(upload(A, &ctx->d_obj_tiles, ot.data(), ot.size(), s));
+    ctx->n_obj_tiles = (uint32_t)ot.size();
     CK(dalloc(A, &ctx->d_in_ptrs, 2));
     CK(hipStreamSynchronize(s));
     ctx->hs = hs;
@@ -868,8 +869,7 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
   const float* in[2] = {d_obj_xf, d_light_xf};
   CK(hipMemcpyAsync(ctx->d_in_ptrs, in, sizeof(in), hipMemcpyHostToDevice, ctx->stream));
   CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->stream));
-  CK(pv::launch_transform(ctx->d_scene, ctx->d_tri_tiles, ctx->n_tri_tiles, ctx->stream));
-  CK(pv::launch_refit(ctx->d_scene, ctx->d_leaf_tiles, ctx->n_leaf_tiles, ctx->stream));
+  CK(pv::launch_update_objects(ctx->d_scene, ctx->d_obj_tiles, ctx->n_obj_tiles, ctx->stream));
   ctx->frame_started = true;
   return PV_OK;
 }
@@ -974,8 +974,7 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   pv_ctx* ctx = b->owner;
   hipStream_t st = b->stream;
   CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
-  CK(pv::launch_transform(b->d_scenes, b->d_tri_tiles, b->n_tri_tiles, st));
-  CK(pv::launch_refit(b->d_scenes, b->d_leaf_tiles, b->n_leaf_tiles, st));
+  CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_block_cnt, d_stats, st));
   CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
@@ -1006,7 +1005,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
     b->seed = seed;
     b->retrace_blocks = (uint32_t)ctx->n_cu * 8;
     std::vector<SceneDev> table(n);
-    std::vector<uint2> ptiles, ttiles, ltiles;
+    std::vector<uint2> ptiles, otiles;
     std::vector<uint32_t> gbase(n + 1, 0);
     uint64_t total_paths = 0, counts = 0, cap = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -1038,14 +1037,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       table[i] = hs;
       gbase[i] = (uint32_t)total_paths;
       for (uint2 t : make_tiles(i, st->n_paths)) ptiles.push_back(t);
-      for (uint2 t : make_tiles(i, c->hs.n_dyn_tris)) ttiles.push_back(t);
-      uint32_t nl = 0;
-      if (c->n_objects) {
-        std::vector<ObjDev> ob(c->n_objects);
-        CK(hipMemcpy(ob.data(), c->hs.objs, sizeof(ObjDev) * c->n_objects, hipMemcpyDeviceToHost));
-        nl = ob.back().leaf_base + ob.back().n_leaves;
-      }
-      for (uint2 t : make_tiles(i, nl)) ltiles.push_back(t);
+      for (uint32_t o = 0; o < c->n_objects; ++o) otiles.push_back(make_uint2(i, o));
       total_paths += st->n_paths;
       counts += (uint64_t)hs.n_blocks * st->max_bounces;
       cap += (uint64_t)st->n_paths * st->max_bounces;
@@ -1059,8 +1051,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
     hipStream_t s = b->stream;
     auto chk = [&](hipError_t e) { return e == hipSuccess; };
     bool ok = chk(upload(A, &b->d_scenes, table.data(), n, s)) && chk(upload(A, &b->d_path_tiles, ptiles.data(), ptiles.size(), s)) &&
-              chk(upload(A, &b->d_tri_tiles, ttiles.data(), ttiles.size(), s)) &&
-              chk(upload(A, &b->d_leaf_tiles, ltiles.data(), ltiles.size(), s)) &&
+              chk(upload(A, &b->d_obj_tiles, otiles.data(), otiles.size(), s)) &&
               chk(upload(A, &b->d_gbase, gbase.data(), gbase.size(), s)) &&
               chk(dalloc(A, &b->d_block_cnt, ptiles.size())) && chk(dalloc(A, &b->d_offsets, ptiles.size())) &&
               chk(dalloc(A, &b->d_queue, total_paths)) && chk(dalloc(A, &b->d_qcount, 1)) &&
@@ -1075,8 +1066,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       return fail(ctx, PV_ERR_OOM, "batch allocation failed");
     }
     b->n_path_tiles = (uint32_t)ptiles.size();
-    b->n_tri_tiles = (uint32_t)ttiles.size();
-    b->n_leaf_tiles = (uint32_t)ltiles.size();
+    b->n_obj_tiles = (uint32_t)otiles.size();
     b->n_counts = (uint32_t)counts;
     b->capacity = (uint32_t)cap;
     *out = b;

@@ -55,10 +55,10 @@ struct ObjDev {
   uint32_t n_tris;
   uint32_t tri_base;   // first record in the dynamic Tri / local arrays (leaf order)
   uint32_t node_base;  // first node of its hierarchy in the dynamic node array
-  uint32_t n_leaves;   // leaves of its hierarchy
-  uint32_t leaf_base;  // first leaf record
-  int32_t root;        // root child code relative to node_base (leaf code if single leaf)
-  uint32_t pad;
+  uint32_t n_nodes;    // internal nodes of its hierarchy
+  uint32_t lvl_base;   // first entry of its level offsets (n_levels + 1 entries)
+  int32_t root;        // root child code (absolute node index, or leaf code)
+  uint32_t n_levels;   // depth levels holding internal nodes
 };
 
 struct LightDev {
@@ -68,9 +68,9 @@ struct LightDev {
   uint32_t pad;
 };
 
-struct LeafRec {          // refit bookkeeping for a leaf of a dynamic hierarchy
-  uint32_t first, count;  // triangle records (relative to the object's tri_base)
-  int32_t parent;         // parent node (relative to node_base), -1 when the leaf is the root
+struct LeafRec {          // a leaf of a hierarchy built on the host
+  uint32_t first, count;  // triangle records
+  int32_t parent;         // parent node, -1 when the leaf is the root
   uint32_t side;          // 0 = child0 of its parent, 1 = child1
 };
 
@@ -85,9 +85,8 @@ struct SceneDev {
   Tri* dtris;
   const float* dlocal;    // [n][9] object-space vertices in leaf order
   const uint32_t* dtri_gid;  // [n] global id of each leaf-order triangle
-  const LeafRec* dleaves;
-  const int32_t* dnode_parent;  // [nodes] parent*2+side (relative), -1 for roots
-  uint32_t* dcounter;     // [nodes] refit visit counters
+  const uint32_t* dlevel_nodes;  // internal nodes of each object, deepest level first
+  const uint32_t* dlevel_off;    // per object: offsets of its levels in dlevel_nodes
   const ObjDev* objs;
   uint32_t n_obj;
   uint32_t n_dyn_tris;

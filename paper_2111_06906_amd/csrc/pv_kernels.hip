@@ -1,8 +1,8 @@
 // HIP kernels of the path-verification hot path (gfx950).
 //
 //   k_frame_begin   moved flags for objects / lights, transform history
-//   k_transform     world-space triangles of moved objects (FP64 fma chain -> FP32)
-//   k_refit         bottom-up box refit of moved objects' hierarchies
+//   k_update_objects  per moved object: world-space triangles (FP64 fma chain
+//                   -> FP32) and level-by-level box refit of its hierarchy
 //   k_verify        Section 3.1 origin update + Section 3.2 dynamic occlusions,
 //                   first invalid segment, per-block replace counts
 //   k_scan          exclusive scan of per-block counts (single block)
@@ -71,19 +71,11 @@ __global__ void k_frame_begin(SceneDev* scenes, int n_scenes, const float* const
 }
 
 // ---------------------------------------------------------------------------
-// transform: one thread per dynamic triangle record; tiles = (scene, first record)
-
-__device__ inline uint32_t object_of_record(const SceneDev& S, uint32_t rec) {
-  uint32_t lo = 0, hi = S.n_obj;  // find o with tri_base[o] <= rec < tri_base[o+1]
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (S.objs[mid].tri_base <= rec)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
+// per moved object, one workgroup: world-space triangles (FP64 fma chain
+// rounded to FP32), then the hierarchy's boxes level by level from the
+// deepest internal nodes up (the topology, fixed for a rigid object, was
+// built at upload), then the object's box.  No atomics: levels are separated
+// by workgroup barriers.
 
 __device__ inline float xform_coord(const float* m, int r, float x, float y, float z) {
   double v = fma((double)m[4 * r + 0], (double)x,
@@ -91,105 +83,81 @@ __device__ inline float xform_coord(const float* m, int r, float x, float y, flo
   return (float)v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_transform(SceneDev* scenes, const uint2* tiles) {
-  uint2 tile = tiles[blockIdx.x];
-  const SceneDev& S = scenes[tile.x];
-  uint32_t rec = tile.y + threadIdx.x;
-  if (rec >= S.n_dyn_tris) return;
-  uint32_t o = object_of_record(S, rec);
-  // counters of this object's nodes are reset here, before the refit kernel
-  const ObjDev& ob = S.objs[o];
-  uint32_t local = rec - ob.tri_base;
-  if (S.obj_moved[o] && local + 1 < ob.n_leaves) S.dcounter[ob.node_base + local] = 0;
-  if (!S.obj_moved[o]) return;
-  const float* m = S.obj_xf_cur + 12 * o;
-  const float* v = S.dlocal + 9 * (size_t)rec;
-  float w[9];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) w[3 * k + r] = xform_coord(m, r, v[3 * k], v[3 * k + 1], v[3 * k + 2]);
-  uint32_t gid = S.dtri_gid[rec];
-  Tri t;
-  t.t0 = make_float4(w[0], w[1], w[2], __uint_as_float(gid));
-  t.t1 = make_float4(w[3], w[4], w[5], __uint_as_float(S.tri_mat[gid]));
-  t.t2 = make_float4(w[6], w[7], w[8], 0.0f);
-  S.dtris[rec] = t;
-}
-
-// ---------------------------------------------------------------------------
-// refit: one thread per leaf of a moved object; the second child to arrive at
-// a node computes its box and continues upwards (atomic visit counters)
-
 __device__ inline float pad_lo(float x) { return x - (1e-6f + fabsf(x) * 1e-6f); }
 __device__ inline float pad_hi(float x) { return x + (1e-6f + fabsf(x) * 1e-6f); }
 
-// Child boxes are written float by float: the two siblings of a node write
-// disjoint words (child0 = floats 0..5, child1 = floats 6..11) concurrently.
-__device__ inline void write_child_box(Node* nd, uint32_t side, const float lo[3], const float hi[3]) {
-  float* f = reinterpret_cast<float*>(nd) + 6 * side;
-  f[0] = lo[0];
-  f[1] = lo[1];
-  f[2] = lo[2];
-  f[3] = hi[0];
-  f[4] = hi[1];
-  f[5] = hi[2];
+// box (lo xyz, hi xyz) of a child: a leaf's padded triangle box, or the union
+// of an internal node's two child boxes
+__device__ inline void child_box(const SceneDev& S, int32_t code, float* b) {
+  if (code < 0) {
+    uint32_t f = leaf_first(code), c = leaf_count(code);
+    float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    for (uint32_t i = f; i < f + c; ++i) {
+      Tri t = S.dtris[i];
+      float4 vs[3] = {t.t0, t.t1, t.t2};
+      for (int k = 0; k < 3; ++k) {
+        lo[0] = fminf(lo[0], vs[k].x); hi[0] = fmaxf(hi[0], vs[k].x);
+        lo[1] = fminf(lo[1], vs[k].y); hi[1] = fmaxf(hi[1], vs[k].y);
+        lo[2] = fminf(lo[2], vs[k].z); hi[2] = fmaxf(hi[2], vs[k].z);
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      b[k] = pad_lo(lo[k]);
+      b[3 + k] = pad_hi(hi[k]);
+    }
+  } else {
+    const Node nd = S.dnodes[code];
+    const float* f = reinterpret_cast<const float*>(&nd);
+    for (int k = 0; k < 3; ++k) {
+      b[k] = fminf(f[k], f[6 + k]);
+      b[3 + k] = fmaxf(f[3 + k], f[9 + k]);
+    }
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_refit(SceneDev* scenes, const uint2* tiles) {
+__global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, const uint2* tiles) {
   uint2 tile = tiles[blockIdx.x];
   SceneDev& S = scenes[tile.x];
-  uint32_t li = tile.y + threadIdx.x;
-  uint32_t n_leaves_total = S.n_obj ? (S.objs[S.n_obj - 1].leaf_base + S.objs[S.n_obj - 1].n_leaves) : 0;
-  if (li >= n_leaves_total) return;
-  LeafRec L = S.dleaves[li];
-  uint32_t o = object_of_record(S, L.first);
+  const uint32_t o = tile.y;
   if (!S.obj_moved[o]) return;
-  float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
-  float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-  for (uint32_t i = 0; i < L.count; ++i) {
-    Tri t = S.dtris[L.first + i];
-    float4 vs[3] = {t.t0, t.t1, t.t2};
-    for (int k = 0; k < 3; ++k) {
-      lo[0] = fminf(lo[0], vs[k].x); hi[0] = fmaxf(hi[0], vs[k].x);
-      lo[1] = fminf(lo[1], vs[k].y); hi[1] = fmaxf(hi[1], vs[k].y);
-      lo[2] = fminf(lo[2], vs[k].z); hi[2] = fmaxf(hi[2], vs[k].z);
-    }
+  const ObjDev ob = S.objs[o];
+  const float* m = S.obj_xf_cur + 12 * o;
+  for (uint32_t i = threadIdx.x; i < ob.n_tris; i += blockDim.x) {
+    uint32_t rec = ob.tri_base + i;
+    const float* v = S.dlocal + 9 * (size_t)rec;
+    float w[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) w[3 * k + r] = xform_coord(m, r, v[3 * k], v[3 * k + 1], v[3 * k + 2]);
+    uint32_t gid = S.dtri_gid[rec];
+    Tri t;
+    t.t0 = make_float4(w[0], w[1], w[2], __uint_as_float(gid));
+    t.t1 = make_float4(w[3], w[4], w[5], __uint_as_float(S.tri_mat[gid]));
+    t.t2 = make_float4(w[6], w[7], w[8], 0.0f);
+    S.dtris[rec] = t;
   }
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = pad_lo(lo[k]);
-    hi[k] = pad_hi(hi[k]);
+  __syncthreads();
+  const uint32_t* off = S.dlevel_off + ob.lvl_base;
+  for (uint32_t lv = 0; lv < ob.n_levels; ++lv) {
+    const uint32_t e = off[lv + 1];
+    for (uint32_t i = off[lv] + threadIdx.x; i < e; i += blockDim.x) {
+      Node* nd = S.dnodes + S.dlevel_nodes[i];
+      int4 ch = nd->d;
+      float b[12];
+      child_box(S, ch.x, b);
+      child_box(S, ch.y, b + 6);
+      nd->a = make_float4(b[0], b[1], b[2], b[3]);
+      nd->b = make_float4(b[4], b[5], b[6], b[7]);
+      nd->c = make_float4(b[8], b[9], b[10], b[11]);
+    }
+    __syncthreads();
   }
-  int32_t parent = L.parent;
-  uint32_t side = L.side;
-  while (true) {
-    if (parent < 0) {
-      float* ob = S.obj_aabb + 6 * o;
-      for (int k = 0; k < 3; ++k) {
-        ob[k] = lo[k];
-        ob[3 + k] = hi[k];
-      }
-      return;
-    }
-    Node* nd = S.dnodes + parent;
-    write_child_box(nd, side, lo, hi);
-    __threadfence();
-    uint32_t prev = atomicAdd(&S.dcounter[parent], 1u);
-    if (prev == 0) return;  // the sibling has not arrived yet
-    __threadfence();
-    // both child boxes are now final; read them past any stale cache line
-    const volatile float* q = (const volatile float*)nd;
-    float v[12];
-    for (int k = 0; k < 12; ++k) v[k] = q[k];
-    lo[0] = fminf(v[0], v[6]); lo[1] = fminf(v[1], v[7]); lo[2] = fminf(v[2], v[8]);
-    hi[0] = fmaxf(v[3], v[9]); hi[1] = fmaxf(v[4], v[10]); hi[2] = fmaxf(v[5], v[11]);
-    int32_t pp = S.dnode_parent[parent];
-    if (pp < 0) {
-      parent = -1;
-    } else {
-      side = (uint32_t)pp & 1u;
-      parent = pp >> 1;
-    }
+  if (threadIdx.x == 0) {
+    float b[6];
+    child_box(S, ob.root, b);
+    for (int k = 0; k < 6; ++k) S.obj_aabb[6 * o + k] = b[k];
   }
 }
 
@@ -1134,15 +1102,9 @@ hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const
   return hipGetLastError();
 }
 
-hipError_t launch_transform(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s) {
+hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s) {
   if (!n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_transform, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles);
-  return hipGetLastError();
-}
-
-hipError_t launch_refit(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s) {
-  if (!n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_refit, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles);
+  hipLaunchKernelGGL(k_update_objects, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles);
   return hipGetLastError();
 }
 

@@ -8,8 +8,7 @@ namespace pv {
 
 hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
                               const float* const* light_in, hipStream_t s);
-hipError_t launch_transform(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
-hipError_t launch_refit(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
+hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
 hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
                          pv_stats* stats, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
