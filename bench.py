@@ -51,7 +51,7 @@ def cpu_baseline(config_fn, target_s, T):
             "sample": "%d paths of the same scene, one frame (verify + error-based re-trace), %.1f s" % (n, dt)}
 
 
-def batched(args, engine, scenes, torch, np):
+def batched(args, engine, scenes, torch, np, tuning=None):
     """64 uneven scenes: per-scene launches (plain) against one graph-captured
     launch per phase (batched), from identical frame-0 stores; the stores must
     stay bit-identical."""
@@ -71,6 +71,9 @@ def batched(args, engine, scenes, torch, np):
     log("batch: %d scenes, %d paths, set up in %.1f s" % (len(scs), sum(s.n_paths for s in scs),
                                                           time.perf_counter() - t0))
     (pc, ps), (bc, bs) = sets
+    if tuning:
+        for c in pc + bc:
+            c.set_tuning(tuning["retrace_variant"], tuning["retrace_blocks_per_cu"])
     caps = [st.n_paths * st.B for st in ps]
     outs = [(torch.empty((c, 3), dtype=torch.float32, device="cuda"),
              torch.empty((c, 3), dtype=torch.float32, device="cuda"),
@@ -126,6 +129,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
@@ -175,7 +179,22 @@ def main():
         ctx.compact_photons_into(st, out_pos, out_en, out_cnt)
         ev[5].record()
 
+    tuning = None
     for f in range(1, 1 + args.warmup):
+        if f == 1 and not args.no_autotune:
+            # autotuner: re-trace variant and grid on this workload (frame 1 on
+            # a snapshot of the store, which it restores)
+            ctx.frame_begin(f)
+            tuning = ctx.autotune(st, T, sc.seed, f)
+            log("autotune: %s" % tuning)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            ev[0].record()
+            ev[1].record()
+            ctx.verify(st, None, build_queue=False)
+            ctx.build_queue(st)
+            ctx.retrace(st, T, sc.seed, f)
+            ctx.compact_photons_into(st, out_pos, out_en, out_cnt)
+            continue
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         step(f, ev, None)
     torch.cuda.synchronize()
@@ -238,6 +257,7 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": "k_verify",
                      "algorithmic_bytes_per_launch": bytes_verify / K, "avg_launch_ms": avg_verify_s * 1e3},
         "phases_ms_per_frame": {k: v / K for k, v in phase.items()},
+        "tuning": tuning,
         "per_frame": {"segments_examined": tot["segments_examined"] / K, "paths_invalid": tot["paths_invalid"] / K,
                       "paths_light_lost": tot["paths_light_lost"] / K, "rays_traced": tot["rays_traced"] / K,
                       "photons_written": tot["photons_written"] / K, "reuse_accepted": tot["reuse_accepted"] / K,
@@ -261,7 +281,7 @@ def main():
     del st, out_pos, out_en
     torch.cuda.empty_cache()
     if not args.no_batch:
-        res["batched"] = batched(args, engine, scenes, torch, np)
+        res["batched"] = batched(args, engine, scenes, torch, np, tuning)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, T)
     print(json.dumps(res), flush=True)

@@ -188,6 +188,24 @@ pv_status pv_copy_queue(pv_ctx* ctx, uint32_t* d_out, uint32_t capacity, uint32_
 pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed,
                            uint32_t frame, pv_stats* d_stats);
 
+/* Kernel tuning of a context.  PV_TUNE_RETRACE_VARIANT (0..3): occupancy
+ * target of the re-trace kernel (none, 5, 6, 8 waves per SIMD; higher targets
+ * trade registers for private-memory spills); PV_TUNE_RETRACE_BLOCKS_PER_CU
+ * (1..64): persistent re-trace workgroups per compute unit.  Results do not
+ * depend on the tuning. */
+enum { PV_TUNE_RETRACE_VARIANT = 0, PV_TUNE_RETRACE_BLOCKS_PER_CU = 1 };
+pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value);
+pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
+
+/* Autotuner: with the current frame (after pv_frame_begin) and the given
+ * store, time verification + queue + re-trace for every re-trace variant and
+ * persistent grid size (2, 4, 8, 16 workgroups per CU) on a snapshot of the
+ * store, keep the fastest setting in the context and restore the store.
+ * Allocates a temporary copy of the store and synchronises.  *out_ms (host,
+ * optional) receives the best re-trace time. */
+pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed, uint32_t frame,
+                      float* out_ms);
+
 /* Existing photons in (row, path) order: d_out_pos / d_out_energy receive
  * float[3] per photon (at most 'capacity' written), *d_count the true count. */
 pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,

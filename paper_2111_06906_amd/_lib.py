@@ -86,6 +86,9 @@ def lib():
         "pv_info_unpack": ([U32, P, P, P, P, P], None),
         "pv_version": ([], C.c_char_p),
         "pv_hierarchy_info": ([P, U32, I32, P], I32),
+        "pv_set_tuning": ([P, I32, I32], I32),
+        "pv_get_tuning": ([P, I32, P], I32),
+        "pv_autotune": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
     }
     optional = {}
     sig.update({
@@ -230,3 +233,22 @@ def batch_set_transforms(b, d_obj_xf, d_light_xf, owner=None):
     oarr = (C.c_void_p * n)(*d_obj_xf)
     larr = (C.c_void_p * n)(*d_light_xf)
     check(lib().pv_batch_set_transforms(b, oarr, larr), owner)
+
+
+PV_TUNE_RETRACE_VARIANT, PV_TUNE_RETRACE_BLOCKS_PER_CU = 0, 1
+
+
+def set_tuning(ctx, key, value):
+    check(lib().pv_set_tuning(ctx, key, value), ctx)
+
+
+def get_tuning(ctx, key):
+    v = C.c_int32()
+    check(lib().pv_get_tuning(ctx, key, C.byref(v)), ctx)
+    return v.value
+
+
+def autotune(ctx, store, threshold, seed, frame):
+    ms = C.c_float()
+    check(lib().pv_autotune(ctx, C.byref(store), C.c_float(threshold), seed, frame, C.byref(ms)), ctx)
+    return ms.value

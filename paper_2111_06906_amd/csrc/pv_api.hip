@@ -60,6 +60,9 @@ struct pv_ctx {
   uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr,
            *d_head = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr;
   float* d_partial = nullptr;
+  // tuning (pv_set_tuning / pv_autotune)
+  int retrace_variant = 0;
+  int retrace_blocks_per_cu = 8;
   // bound store
   bool bound = false;
   bool counts_ready = false;   // per-block replace counts written by verify
@@ -924,9 +927,107 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   if (st) return st;
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
-  uint32_t blocks = (uint32_t)ctx->n_cu * 8;
+  uint32_t blocks = (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu);
   CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold, seed,
-                        frame, nullptr, d_stats, blocks, ctx->stream));
+                        frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value) {
+  if (!ctx) return PV_ERR_ARG;
+  if (key == PV_TUNE_RETRACE_VARIANT) {
+    if (value < 0 || value > 3) return fail(ctx, PV_ERR_ARG, "re-trace variant out of range 0..3");
+    ctx->retrace_variant = value;
+  } else if (key == PV_TUNE_RETRACE_BLOCKS_PER_CU) {
+    if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "blocks per CU out of range 1..64");
+    ctx->retrace_blocks_per_cu = value;
+  } else {
+    return fail(ctx, PV_ERR_ARG, "unknown tuning key");
+  }
+  return PV_OK;
+}
+
+pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value) {
+  if (!ctx || !value) return PV_ERR_ARG;
+  if (key == PV_TUNE_RETRACE_VARIANT)
+    *value = ctx->retrace_variant;
+  else if (key == PV_TUNE_RETRACE_BLOCKS_PER_CU)
+    *value = ctx->retrace_blocks_per_cu;
+  else
+    return PV_ERR_ARG;
+  return PV_OK;
+}
+
+pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed, uint32_t frame,
+                      float* out_ms) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
+  if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
+  const size_t rows = (size_t)store->max_bounces * store->stride;
+  const size_t b_pos = 16 * rows, b_en = 16 * rows, b_or = 12 * (size_t)store->stride, b_in = 4 * (size_t)store->stride;
+  char* backup = nullptr;
+  CK(hipMalloc(&backup, b_pos + b_en + b_or + b_in));
+  hipStream_t s = ctx->stream;
+  auto copy_store = [&](bool save) -> hipError_t {
+    void* dev[4] = {store->d_pos_hit, store->d_energy, store->d_origin, store->d_info};
+    size_t sz[4] = {b_pos, b_en, b_or, b_in};
+    size_t off = 0;
+    for (int i = 0; i < 4; ++i) {
+      hipError_t e = save ? hipMemcpyAsync(backup + off, dev[i], sz[i], hipMemcpyDeviceToDevice, s)
+                          : hipMemcpyAsync(dev[i], backup + off, sz[i], hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+      off += sz[i];
+    }
+    return hipSuccess;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = copy_store(true);
+  if (err == hipSuccess) err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  float best = INFINITY;
+  int best_v = ctx->retrace_variant, best_b = ctx->retrace_blocks_per_cu;
+  const uint32_t nb = path_blocks(store->n_paths);
+  const int grids[4] = {2, 4, 8, 16};
+  for (int v = 0; v < 4 && err == hipSuccess; ++v) {
+    for (int gi = 0; gi < 4 && err == hipSuccess; ++gi) {
+      float t_min = INFINITY;
+      for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+        err = copy_store(false);
+        if (err == hipSuccess)
+          err = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, nullptr, s);
+        if (err == hipSuccess)
+          err = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, s);
+        if (err == hipSuccess)
+          err = pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, s);
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        if (err == hipSuccess)
+          err = pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold,
+                                   seed, frame, nullptr, nullptr, (uint32_t)(ctx->n_cu * grids[gi]), v, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        t_min = std::min(t_min, ms);
+      }
+      if (t_min < best) {
+        best = t_min;
+        best_v = v;
+        best_b = grids[gi];
+      }
+    }
+  }
+  if (err == hipSuccess) err = copy_store(false);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(backup);
+  CK(err);
+  ctx->retrace_variant = best_v;
+  ctx->retrace_blocks_per_cu = best_b;
+  ctx->counts_ready = false;
+  if (out_ms) *out_ms = best;
   return PV_OK;
 }
 
@@ -979,7 +1080,8 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->d_head, b->T, b->seed, 0,
-                        b->d_frame, d_stats, b->retrace_blocks, st));
+                        b->d_frame, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
+                        st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
   CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, nullptr, st));
   CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,

@@ -712,8 +712,8 @@ __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t fram
   }
 }
 
-template <bool kSingle>
-__global__ __launch_bounds__(kBlock) void k_retrace(const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ gbase,
+template <bool kSingle, int kWaves>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_retrace(const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ gbase,
                                                     int n_scenes, const uint32_t* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount, uint32_t* head, float T,
                                                     uint64_t seed, uint32_t frame_arg, const uint32_t* frame_ptr,
@@ -1135,15 +1135,41 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
   return hipGetLastError();
 }
 
+// variant v selects the occupancy target of the re-trace kernel (waves per
+// SIMD the compiler must allow): 0 -> no target, 1 -> 5, 2 -> 6, 3 -> 8
+template <bool kSingle>
+static void retrace_variant(int v, dim3 g, hipStream_t s, const SceneDev* scenes, const uint32_t* gbase, int n_scenes,
+                            const uint32_t* queue, const uint32_t* qcount, uint32_t* head, float T, uint64_t seed,
+                            uint32_t frame, const uint32_t* frame_ptr, pv_stats* stats) {
+  switch (v) {
+    case 1:
+      hipLaunchKernelGGL((k_retrace<kSingle, 5>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+                         T, seed, frame, frame_ptr, stats);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_retrace<kSingle, 6>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+                         T, seed, frame, frame_ptr, stats);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_retrace<kSingle, 8>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+                         T, seed, frame, frame_ptr, stats);
+      break;
+    default:
+      hipLaunchKernelGGL((k_retrace<kSingle, 1>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+                         T, seed, frame, frame_ptr, stats);
+      break;
+  }
+}
+
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
-                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, hipStream_t s) {
+                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, hipStream_t s) {
   if (n_scenes == 1)
-    hipLaunchKernelGGL(k_retrace<true>, dim3(n_blocks), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount,
-                       head, T, seed, frame, frame_ptr, stats);
+    retrace_variant<true>(variant, dim3(n_blocks), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
+                          frame_ptr, stats);
   else
-    hipLaunchKernelGGL(k_retrace<false>, dim3(n_blocks), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount,
-                       head, T, seed, frame, frame_ptr, stats);
+    retrace_variant<false>(variant, dim3(n_blocks), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
+                           frame_ptr, stats);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
                            hipStream_t s);
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
-                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, hipStream_t s);
+                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, hipStream_t s);
 hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
                                hipStream_t s);
 hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t B,

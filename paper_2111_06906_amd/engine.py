@@ -182,6 +182,19 @@ class Context:
                           _ptr(gE.contiguous()), _ptr(ga), _ptr(gp))
         return ga, gp
 
+    def autotune(self, store, threshold, seed, frame):
+        """Pick the fastest re-trace kernel variant and grid on this workload."""
+        ms = L.autotune(self.ctx, store.cstruct(), float(threshold), int(seed), int(frame))
+        return {"retrace_variant": L.get_tuning(self.ctx, L.PV_TUNE_RETRACE_VARIANT),
+                "retrace_blocks_per_cu": L.get_tuning(self.ctx, L.PV_TUNE_RETRACE_BLOCKS_PER_CU),
+                "retrace_ms": ms}
+
+    def set_tuning(self, variant=None, blocks_per_cu=None):
+        if variant is not None:
+            L.set_tuning(self.ctx, L.PV_TUNE_RETRACE_VARIANT, int(variant))
+        if blocks_per_cu is not None:
+            L.set_tuning(self.ctx, L.PV_TUNE_RETRACE_BLOCKS_PER_CU, int(blocks_per_cu))
+
     def initial_trace(self, store, seed, frame=0, stats=None):
         """Frame-0 photon paths (every path a new light sample)."""
         self.queue_all(store)

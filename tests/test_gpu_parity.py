@@ -374,3 +374,29 @@ def test_paper_full_size_sampled(E):
     pos, en, cnt = ctx.compact_photons(st)
     info2 = st.info[:N].cpu().numpy().view(np.uint32)
     assert cnt == int(((info2 >> 22) & 15).sum())
+
+
+def test_autotune_restores_store_and_tuning_does_not_change_results(E):
+    import torch
+    sc = scenes.make_mid(n_paths=50000, frames=3, threshold=0.01)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    ctx.initial_trace(st, sc.seed, 0)
+    ctx.frame_begin(1)
+    before = st.to_numpy()
+    tuning = ctx.autotune(st, 0.01, sc.seed, 1)
+    log("autotune: %s" % tuning)
+    after = st.to_numpy()
+    for k in before:
+        assert np.array_equal(before[k].view(np.uint32), after[k].view(np.uint32)), k
+    results = []
+    for variant, bpc in ((0, 8), (3, 2), (1, 16), (2, 4)):
+        st.load_numpy(before)
+        ctx.set_tuning(variant, bpc)
+        ctx.verify(st)
+        ctx.retrace(st, 0.01, sc.seed, 1)
+        torch.cuda.synchronize()
+        results.append(st.to_numpy())
+    for r in results[1:]:
+        for k in r:
+            assert np.array_equal(r[k].view(np.uint32), results[0][k].view(np.uint32)), k
