@@ -189,7 +189,7 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
                            uint32_t frame, pv_stats* d_stats);
 
 /* Kernel tuning of a context.  PV_TUNE_RETRACE_VARIANT (0..3): occupancy
- * target of the re-trace kernel (none, 5, 6, 8 waves per SIMD; higher targets
+ * target of the re-trace kernel (4, 5, 6, 8 waves per SIMD; higher targets
  * trade registers for private-memory spills); PV_TUNE_RETRACE_BLOCKS_PER_CU
  * (1..64): persistent re-trace workgroups per compute unit.  Results do not
  * depend on the tuning. */

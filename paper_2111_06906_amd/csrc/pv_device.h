@@ -9,6 +9,26 @@
 
 namespace pv {
 
+// Pointers read from the scene descriptor are generic; casting them to the
+// global address space lets the compiler emit global (not flat) memory
+// instructions, which do not make LDS accesses (the traversal stack) wait for
+// outstanding memory loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PV_GLOBAL __attribute__((address_space(1)))
+#define PV_LDS __attribute__((address_space(3)))
+#else
+#define PV_GLOBAL
+#define PV_LDS
+#endif
+template <typename T>
+__device__ __forceinline__ PV_GLOBAL T* G(T* p) {
+  return (PV_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const PV_GLOBAL T* G(const T* p) {
+  return (const PV_GLOBAL T*)p;
+}
+
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kLdsStack = 16;      // traversal stack entries per lane held in LDS
 constexpr int kPrivStack = 48;     // further entries per lane in private memory
@@ -220,7 +240,7 @@ __device__ inline bool tri_hit(const Ray& r, float3 v0, float3 v1, float3 v2, fl
 // traversal stack: the top kLdsStack entries of each lane in LDS (column per
 // lane, conflict-free), deeper entries in private memory.
 struct Stack {
-  uint32_t* lds;  // &shared[0][lane]; entry i at lds[i * kBlock]
+  PV_LDS uint32_t* lds;  // &shared[0][lane]; entry i at lds[i * kBlock]
   int sp;
   int32_t priv[kPrivStack];
   __device__ inline void push(int32_t v) {
@@ -238,8 +258,10 @@ struct Stack {
 
 // Any-hit over one hierarchy; true when some triangle is crossed inside the
 // ray's open interval.  'root' is a child code relative to 'nodes'/'tris'.
-__device__ inline bool bvh_any(const Node* __restrict__ nodes, const Tri* __restrict__ tris, int32_t root,
+__device__ inline bool bvh_any(const Node* __restrict__ nodes_in, const Tri* __restrict__ tris_in, int32_t root,
                                const Ray& r, Stack& st) {
+  const PV_GLOBAL Node* nodes = G(nodes_in);
+  const PV_GLOBAL Tri* tris = G(tris_in);
   float t;
   int base = st.sp;
   int32_t cur = root;
@@ -277,9 +299,11 @@ __device__ inline bool bvh_any(const Node* __restrict__ nodes, const Tri* __rest
 }
 
 // Closest hit over one hierarchy: shrinks *tbest, records the record index.
-__device__ inline void bvh_closest(const Node* __restrict__ nodes, const Tri* __restrict__ tris, int32_t root,
+__device__ inline void bvh_closest(const Node* __restrict__ nodes_in, const Tri* __restrict__ tris_in, int32_t root,
                                    const Ray& r, Stack& st, float* tbest, uint32_t* gid_best,
                                    uint32_t* rec_best, const Tri** set_best) {
+  const PV_GLOBAL Node* nodes = G(nodes_in);
+  const PV_GLOBAL Tri* tris = G(tris_in);
   float t;
   int base = st.sp;
   int32_t cur = root;
@@ -293,7 +317,7 @@ __device__ inline void bvh_closest(const Node* __restrict__ nodes, const Tri* __
           *tbest = t;
           *gid_best = __float_as_uint(tr.t0.w);
           *rec_best = f + i;
-          *set_best = tris;
+          *set_best = tris_in;
         }
       }
       if (st.sp == base) return;

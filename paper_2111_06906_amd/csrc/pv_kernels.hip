@@ -175,10 +175,10 @@ __device__ inline void load_moved(const SceneDev& S, MovedSet& M) {
   if (threadIdx.x == 0) {
     int n = 0;
     for (uint32_t o = 0; o < S.n_obj; ++o) {
-      if (!S.obj_moved[o]) continue;
-      const ObjDev& ob = S.objs[o];
+      if (!G(S.obj_moved)[o]) continue;
+      const ObjDev ob = G(S.objs)[o];
       M.root[n] = ob.root;
-      for (int k = 0; k < 6; ++k) M.box[n][k] = S.obj_aabb[6 * o + k];
+      for (int k = 0; k < 6; ++k) M.box[n][k] = G(S.obj_aabb)[6 * o + k];
       M.glo[n] = ob.gbase;
       M.ghi[n] = ob.gbase + ob.n_tris;
       ++n;
@@ -217,15 +217,16 @@ __device__ inline Ray segment_ray(float3 a, float3 b, float eps) {
 }
 
 __device__ inline int light_of(const SceneDev& S, uint32_t p) {
+  const PV_GLOBAL LightDev* lights = G(S.lights);
   for (uint32_t l = 0; l < S.n_lights; ++l)
-    if (p - S.lights[l].path_base < S.lights[l].path_count) return (int)l;
+    if (p - lights[l].path_base < lights[l].path_count) return (int)l;
   return -1;
 }
 
 // Section 3.1 for a rectangular area light: keep the outgoing direction and
 // intersect it with the light's current plane.
 __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 x1, float3* out) {
-  const float* xf = S.light_xf_cur + 12 * l;
+  const PV_GLOBAL float* xf = G(S.light_xf_cur) + 12 * l;
   float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
   float3 n = f3(xf[2], xf[6], xf[10]), c = f3(xf[3], xf[7], xf[11]);
   n = mul(n, 1.0f / length(n));
@@ -240,7 +241,8 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
   float3 p = sub(x1, mul(w, sdist));
   float3 r = sub(p, c);
   float u = dot(r, eu), v = dot(r, ev);
-  if (!(fabsf(u) <= S.lights[l].half[0] && fabsf(v) <= S.lights[l].half[1])) return false;
+  const PV_GLOBAL LightDev* lt = G(S.lights) + l;
+  if (!(fabsf(u) <= lt->half[0] && fabsf(v) <= lt->half[1])) return false;
   *out = p;
   return true;
 }
@@ -275,20 +277,23 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
   uint32_t n = 0, cell = 0, cap = 0, mask = 0, lost = 0;
   // ---- phase A
   if (active) {
-    uint32_t w = S.info[p];
+    const PV_GLOBAL float4* pos = G(S.pos);
+    PV_GLOBAL float* org = G(S.origin);
+    uint32_t w = G(S.info)[p];
     n = min(info_nseg(w), S.B);
     cell = info_cell(w);
     cap = n;
-    float3 a = f3(S.origin[p], S.origin[stride + p], S.origin[2 * stride + p]);
-    float4 row = n > 0 ? S.pos[p] : make_float4(0, 0, 0, 0);
+    float3 a = f3(org[p], org[stride + p], org[2 * stride + p]);
+    float4 row = make_float4(0, 0, 0, 0);
+    if (n > 0) row = pos[p];
     int l = light_of(S, p);
-    if (l >= 0 && S.light_moved[l]) {
+    if (l >= 0 && G(S.light_moved)[l]) {
       float3 na;
       if (n > 0 && light_update(S, l, a, xyz(row), &na)) {
         a = na;
-        S.origin[p] = na.x;
-        S.origin[stride + p] = na.y;
-        S.origin[2 * stride + p] = na.z;
+        org[p] = na.x;
+        org[stride + p] = na.y;
+        org[2 * stride + p] = na.z;
       } else {
         lost = 1;
         cap = 0;
@@ -299,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
     sorig[2][tid] = a.z;
     if (!lost && M.n > 0) {
       for (uint32_t j = 0; j < n; ++j) {
-        if (j > 0) row = S.pos[j * stride + p];
+        if (j > 0) row = pos[j * stride + p];
         if (on_moved(M, __float_as_uint(row.w))) {
           cap = j;
           break;
@@ -337,15 +342,15 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
   __syncthreads();
   // ---- phase B: every thread traverses tasks of any path of the block
   Stack st;
-  st.lds = sstack + tid;
+  st.lds = (PV_LDS uint32_t*)(sstack + tid);
   st.sp = 0;
   for (uint32_t t = tid; t < total; t += kBlock) {
     uint32_t tk = task[t], owner = tk >> 4, j = tk & 15u;
     if (j >= first_bad[owner]) continue;  // an earlier segment already failed
     uint32_t q = tile.y + owner;
     float3 a = j == 0 ? f3(sorig[0][owner], sorig[1][owner], sorig[2][owner])
-                      : xyz(S.pos[(size_t)(j - 1) * stride + q]);
-    float3 b = xyz(S.pos[(size_t)j * stride + q]);
+                      : xyz(G(S.pos)[(size_t)(j - 1) * stride + q]);
+    float3 b = xyz(G(S.pos)[(size_t)j * stride + q]);
     Ray r = segment_ray(a, b, S.eps_end);
     for (int i = 0; i < M.n; ++i) {
       const float* bx = M.box[i];
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
       out = info_pack(cell, n, 0, 0, 0);
       ex = n;
     }
-    S.info[p] = out;
+    G(S.info)[p] = out;
     repl = info_replace(out);
   }
   unsigned long long nrep = block_sum_u64(repl, sred);
@@ -486,8 +491,9 @@ __device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool mov
   h->gid = kHitNone;
   h->rec = 0;
   h->set = nullptr;
-  const Node* nodes = S.snodes;
-  const Tri* tris = S.stris;
+  const PV_GLOBAL Node* nodes = G(S.snodes);
+  const PV_GLOBAL Tri* tris = G(S.stris);
+  const Tri* tris_generic = S.stris;
   int ri = (moved_only || !S.n_static) ? 0 : -1;  // -1 = static world, else object index
   int32_t cur = ri < 0 ? S.sroot : 0;
   bool have = ri < 0;
@@ -499,12 +505,13 @@ __device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool mov
       bool found = false;
       while (ri < (int)S.n_obj) {
         int o = ri++;
-        if (moved_only && !S.obj_moved[o]) continue;
-        const float* b = S.obj_aabb + 6 * o;
+        if (moved_only && !G(S.obj_moved)[o]) continue;
+        const PV_GLOBAL float* b = G(S.obj_aabb) + 6 * o;
         if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h->t) == __builtin_inff()) continue;
-        cur = S.objs[o].root;
-        nodes = S.dnodes;
-        tris = S.dtris;
+        cur = G(S.objs)[o].root;
+        nodes = G(S.dnodes);
+        tris = G(S.dtris);
+        tris_generic = S.dtris;
         found = true;
         break;
       }
@@ -519,7 +526,7 @@ __device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool mov
           h->t = t;
           h->gid = __float_as_uint(tr.t0.w);
           h->rec = f + i;
-          h->set = tris;
+          h->set = tris_generic;
           if (any) {
             st.sp = base;
             return true;
@@ -554,41 +561,42 @@ __device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool mov
 }
 
 __device__ inline float3 hit_normal(const Hit& h) {
-  Tri t = h.set[h.rec];
+  Tri t = G(h.set)[h.rec];
   float3 v0 = xyz(t.t0), v1 = xyz(t.t1), v2 = xyz(t.t2);
   float3 n = cross(sub(v1, v0), sub(v2, v0));
   return mul(n, 1.0f / length(n));
 }
 
-__device__ inline uint32_t hit_material(const Hit& h) { return __float_as_uint(h.set[h.rec].t1.w); }
+__device__ inline uint32_t hit_material(const Hit& h) { return __float_as_uint(G(h.set)[h.rec].t1.w); }
 
 __device__ inline float3 vertex(const SceneDev& S, uint32_t p, uint32_t j) {
   const size_t stride = S.stride;
-  if (j == 0) return f3(S.origin[p], S.origin[stride + p], S.origin[2 * stride + p]);
-  return xyz(S.pos[(size_t)(j - 1) * stride + p]);
+  const PV_GLOBAL float* org = G(S.origin);
+  if (j == 0) return f3(org[p], org[stride + p], org[2 * stride + p]);
+  return xyz(G(S.pos)[(size_t)(j - 1) * stride + p]);
 }
 
 __device__ inline uint32_t vertex_hit(const SceneDev& S, uint32_t p, uint32_t j) {
-  return __float_as_uint(S.pos[(size_t)(j - 1) * S.stride + p].w);
+  return __float_as_uint(G(S.pos)[(size_t)(j - 1) * S.stride + p].w);
 }
 
 __device__ inline float3 energy_row(const SceneDev& S, uint32_t p, uint32_t row) {
-  return xyz(S.energy[(size_t)row * S.stride + p]);
+  return xyz(G(S.energy)[(size_t)row * S.stride + p]);
 }
 
 __device__ inline void put_photon(const SceneDev& S, uint32_t p, uint32_t row, float3 x, uint32_t gid, float3 e) {
   size_t i = (size_t)row * S.stride + p;
-  S.pos[i] = make_float4(x.x, x.y, x.z, __uint_as_float(gid));
-  S.energy[i] = make_float4(e.x, e.y, e.z, S.radius);
+  G(S.pos)[i] = make_float4(x.x, x.y, x.z, __uint_as_float(gid));
+  G(S.energy)[i] = make_float4(e.x, e.y, e.z, S.radius);
 }
 
 // material of a stored hit id (ids beyond the scene map to material 0)
 __device__ inline uint32_t mat_of(const SceneDev& S, uint32_t hit) {
-  return hit < S.n_tris_total ? S.tri_mat[hit] : 0u;
+  return hit < S.n_tris_total ? G(S.tri_mat)[hit] : 0u;
 }
 
 __device__ inline float3 reflect_energy(const SceneDev& S, float3 e, uint32_t mat) {
-  const float* rho = S.albedo + 3 * mat;
+  const PV_GLOBAL float* rho = G(S.albedo) + 3 * mat;
   return f3(__fmul_rn(e.x, rho[0]), __fmul_rn(e.y, rho[1]), __fmul_rn(e.z, rho[2]));
 }
 
@@ -601,8 +609,8 @@ __device__ inline bool eq2(float3 en, float3 eo, float T) {
 __device__ inline bool on_moved_obj(const SceneDev& S, uint32_t hit) {
   if (hit == kHitNone || hit < S.n_static) return false;
   for (uint32_t o = 0; o < S.n_obj; ++o) {
-    const ObjDev& ob = S.objs[o];
-    if (hit - ob.gbase < ob.n_tris) return S.obj_moved[o] != 0;
+    const ObjDev ob = G(S.objs)[o];
+    if (hit - ob.gbase < ob.n_tris) return G(S.obj_moved)[o] != 0;
   }
   return false;
 }
@@ -610,8 +618,8 @@ __device__ inline bool on_moved_obj(const SceneDev& S, uint32_t hit) {
 __device__ inline void clear_rows(const SceneDev& S, uint32_t p, uint32_t from) {
   for (uint32_t r = from; r < S.B; ++r) {
     size_t i = (size_t)r * S.stride + p;
-    S.pos[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(kHitNone));
-    S.energy[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    G(S.pos)[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(kHitNone));
+    G(S.energy)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
 }
 
@@ -652,7 +660,7 @@ struct Lane {
 
 __device__ inline void finish(Lane& L) {
   clear_rows(*L.S, L.p, L.newn);
-  L.S->info[L.p] = info_pack(L.cell, L.newn, 0, 0, 0);
+  G(L.S->info)[L.p] = info_pack(L.cell, L.newn, 0, 0, 0);
   L.mode = ST_IDLE;
 }
 
@@ -669,7 +677,7 @@ __device__ inline void to_tail(Lane& L) {
 
 __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t frame) {
   const SceneDev& S = *L.S;
-  uint32_t w = S.info[L.p];
+  uint32_t w = G(S.info)[L.p];
   L.n = min(info_nseg(w), S.B);
   L.k = info_start(w);
   L.cell = info_cell(w);
@@ -686,19 +694,21 @@ __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t fram
   if (L.k == 0 && !reuse) {
     // new light sample: position uniform on the rectangle, direction
     // cosine-weighted about the light normal (one Philox draw, tag 0)
-    const float* xf = S.light_xf_cur + 12 * L.l;
+    const PV_GLOBAL float* xf = G(S.light_xf_cur) + 12 * L.l;
+    const PV_GLOBAL LightDev* lt = G(S.lights) + L.l;
     float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
     float3 nl = normalize3(f3(xf[2], xf[6], xf[10])), c = f3(xf[3], xf[7], xf[11]);
     float u[4];
     draw4(seed, L.p, frame, 0, 0, u);
-    float a = (2.0f * u[0] - 1.0f) * S.lights[L.l].half[0], b = (2.0f * u[1] - 1.0f) * S.lights[L.l].half[1];
+    float a = (2.0f * u[0] - 1.0f) * lt->half[0], b = (2.0f * u[1] - 1.0f) * lt->half[1];
     float3 x0 = add(c, add(mul(eu, a), mul(ev, b)));
     float3 lc = cosine_local(u[2], u[3]);
     L.w = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
     const size_t stride = S.stride;
-    S.origin[L.p] = x0.x;
-    S.origin[stride + L.p] = x0.y;
-    S.origin[2 * stride + L.p] = x0.z;
+    PV_GLOBAL float* org = G(S.origin);
+    org[L.p] = x0.x;
+    org[stride + L.p] = x0.y;
+    org[2 * stride + L.p] = x0.z;
     L.x = x0;
     L.mode = ST_FIRST;
   } else if (T < 0.0f) {
@@ -721,7 +731,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
   __shared__ uint32_t sstack[kLdsStack * kBlock];
   __shared__ unsigned long long sred[kBlock / 64];
   Stack st;
-  st.lds = sstack + threadIdx.x;
+  st.lds = (PV_LDS uint32_t*)(sstack + threadIdx.x);
   st.sp = 0;
   const uint32_t frame = frame_ptr ? *frame_ptr : frame_arg;
   uint32_t n_rays = 0, n_photons = 0, n_acc = 0, n_trunc = 0;
@@ -742,7 +752,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
       if (want) {
         uint32_t qi = base + (uint32_t)__popcll(m & lanemask_lt());
         if (qi < count) {
-          uint32_t gp = queue[qi];
+          uint32_t gp = G(queue)[qi];
           if (kSingle) {
             L.p = gp;
           } else {
@@ -818,9 +828,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         float3 xn = add(L.x, mul(L.w, h.t));
         float3 en;
         if (L.k == 0) {
-          float N = (float)S.lights[L.l].path_count;
-          en = f3(__fdiv_rn(S.lights[L.l].power[0], N), __fdiv_rn(S.lights[L.l].power[1], N),
-                  __fdiv_rn(S.lights[L.l].power[2], N));
+          const PV_GLOBAL LightDev* lt = G(S.lights) + L.l;
+          float N = (float)lt->path_count;
+          en = f3(__fdiv_rn(lt->power[0], N), __fdiv_rn(lt->power[1], N), __fdiv_rn(lt->power[2], N));
         } else {
           en = reflect_energy(S, energy_row(S, L.p, L.k - 1), mat_of(S, vertex_hit(S, L.p, L.k)));
         }
@@ -1136,7 +1146,7 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
 }
 
 // variant v selects the occupancy target of the re-trace kernel (waves per
-// SIMD the compiler must allow): 0 -> no target, 1 -> 5, 2 -> 6, 3 -> 8
+// SIMD the compiler must allow): 0 -> 4, 1 -> 5, 2 -> 6, 3 -> 8
 template <bool kSingle>
 static void retrace_variant(int v, dim3 g, hipStream_t s, const SceneDev* scenes, const uint32_t* gbase, int n_scenes,
                             const uint32_t* queue, const uint32_t* qcount, uint32_t* head, float T, uint64_t seed,
@@ -1155,7 +1165,7 @@ static void retrace_variant(int v, dim3 g, hipStream_t s, const SceneDev* scenes
                          T, seed, frame, frame_ptr, stats);
       break;
     default:
-      hipLaunchKernelGGL((k_retrace<kSingle, 1>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 4>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
                          T, seed, frame, frame_ptr, stats);
       break;
   }
