@@ -481,11 +481,29 @@ struct Hit {
 
 constexpr float kTFar = 16.0f;
 
+// Dynamic objects of a single scene staged in LDS once per workgroup.
+struct ObjTable {
+  float box[PV_MAX_OBJECTS][6];
+  int32_t root[PV_MAX_OBJECTS];
+  uint32_t moved[PV_MAX_OBJECTS];
+};
+
+__device__ inline void load_objects(const SceneDev& S, ObjTable& T) {
+  for (uint32_t o = threadIdx.x; o < S.n_obj; o += blockDim.x) {
+    for (int k = 0; k < 6; ++k) T.box[o][k] = G(S.obj_aabb)[6 * o + k];
+    T.root[o] = G(S.objs)[o].root;
+    T.moved[o] = G(S.obj_moved)[o];
+  }
+  __syncthreads();
+}
+
 // One query over every hierarchy of a scene in a single loop: the static
 // world first (unless only moved objects are wanted), then each dynamic
 // object whose box the ray reaches.  Lanes at different hierarchies still run
-// the same loop body.  any = stop at the first crossing.
-__device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool moved_only, Stack& st, Hit* h) {
+// the same loop body.  any = stop at the first crossing.  OT: the scene's
+// objects in LDS (single-scene launches) or null (read from the descriptor).
+__device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool moved_only, Stack& st, Hit* h,
+                             const PV_LDS ObjTable* OT) {
   float t;
   h->t = r.tmax;
   h->gid = kHitNone;
@@ -505,10 +523,17 @@ __device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool mov
       bool found = false;
       while (ri < (int)S.n_obj) {
         int o = ri++;
-        if (moved_only && !G(S.obj_moved)[o]) continue;
-        const PV_GLOBAL float* b = G(S.obj_aabb) + 6 * o;
-        if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h->t) == __builtin_inff()) continue;
-        cur = G(S.objs)[o].root;
+        if (OT) {
+          if (moved_only && !OT->moved[o]) continue;
+          const PV_LDS float* b = OT->box[o];
+          if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h->t) == __builtin_inff()) continue;
+          cur = OT->root[o];
+        } else {
+          if (moved_only && !G(S.obj_moved)[o]) continue;
+          const PV_GLOBAL float* b = G(S.obj_aabb) + 6 * o;
+          if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h->t) == __builtin_inff()) continue;
+          cur = G(S.objs)[o].root;
+        }
         nodes = G(S.dnodes);
         tris = G(S.dtris);
         tris_generic = S.dtris;
@@ -730,10 +755,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
                                                     pv_stats* stats) {
   __shared__ uint32_t sstack[kLdsStack * kBlock];
   __shared__ unsigned long long sred[kBlock / 64];
+  __shared__ ObjTable OTs;
   Stack st;
   st.lds = (PV_LDS uint32_t*)(sstack + threadIdx.x);
   st.sp = 0;
   const uint32_t frame = frame_ptr ? *frame_ptr : frame_arg;
+  const PV_LDS ObjTable* OT = nullptr;
+  if (kSingle) {
+    load_objects(scenes[0], OTs);
+    OT = (const PV_LDS ObjTable*)&OTs;
+  }
   uint32_t n_rays = 0, n_photons = 0, n_acc = 0, n_trunc = 0;
   const uint32_t count = *qcount;
   Lane L;
@@ -811,7 +842,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     h.gid = kHitNone;
     if (busy) {
       Ray r = make_ray(qo, qd, tmin, tmax);
-      trace(S, r, any, moved_only, st, &h);
+      trace(S, r, any, moved_only, st, &h, OT);
       if (!any) ++n_rays;
     }
     if (!busy) continue;
