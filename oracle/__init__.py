@@ -29,9 +29,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("PV_ORACLE_LIB", _build.LIB)  # mutation tests load planted variants
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        _lib = C.CDLL(_build.LIB)
+        _lib = C.CDLL(path)
         _declare(_lib)
     return _lib
 

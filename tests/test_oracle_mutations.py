@@ -1,0 +1,67 @@
+"""The pins catch planted mistakes in the oracle.
+
+Each case compiles a copy of the oracle with one plausible mistake (a dropped
+term, a wrong sign or index, a swapped constant, an off-by-one) into a
+temporary library and runs the pin tests against it in a subprocess: at least
+one pin must fail.  The oracle in the repository is never modified.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTATIONS = {
+    # Moller-Trumbore: the third barycentric bound dropped
+    "inside_without_u_plus_v": ("return u >= 0.0 && v >= 0.0 && u + v <= 1.0;", "return u >= 0.0 && v >= 0.0;",
+                                "segment_triangle or worked_case or blocker"),
+    # endpoint tolerance ignored at the start of a segment
+    "eps_start_dropped": ("return inside_uv(u, v) && s > eps && s < L - eps;",
+                          "return inside_uv(u, v) && s > 0.0 && s < L - eps;", "eps_end_interval"),
+    # a multiplier constant of Philox changed in its last digit
+    "philox_constant": ("M0 = 0xD2E7470EE14C6C93ull", "M0 = 0xD2E7470EE14C6C95ull", "philox"),
+    # reflected energy uses the green albedo for every channel
+    "albedo_channel": ("out[c] = (float)((double)e[c] * (double)rho[c]);",
+                       "out[c] = (float)((double)e[c] * (double)rho[1]);", "energies or figure1 or gradient or coloured"),
+    # origin update: wrong sign of the distance to the light plane
+    "light_plane_sign": ("double sdist = dot3(q, n) / dn;", "double sdist = -dot3(q, n) / dn;", "light_update"),
+    # Equation 2 made exclusive on the upper bound
+    "eq2_exclusive": ("if (!(mte <= d && d <= te)) return 0;", "if (!(mte <= d && d < te)) return 0;", "eq2"),
+    # Malley's lift with a dropped factor
+    "cosine_lift": ("double z2 = (1.0 - ar) * (1.0 + ar);", "double z2 = (1.0 - ar);", "cosine or concentric"),
+    # first invalid segment recorded one too late
+    "start_off_by_one": ("out = info_make(cell, n, j, 1, 1);", "out = info_make(cell, n, j + 1, 1, 1);",
+                         "worked_case or blocker or photon_on_moved"),
+    # albedo gradient without the division by the albedo
+    "gradient_term": ("g_albedo[3 * m + c] += ge / albedo[3 * m + c];", "g_albedo[3 * m + c] += ge;", "gradient"),
+    # light sample along the wrong tangent
+    "light_sample_axis": ("for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * ev[i];",
+                          "for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * eu[i];", "light_sample"),
+    # bounce sampled on the wrong side of the surface
+    "normal_not_flipped": ("    if (dot3(n, w) > 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
+                           "    if (dot3(n, w) < 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
+                           "energies or initial_trace or retrace"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_detect_planted_mistake(name):
+    old, new, select = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not unique: %s" % name
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "oracle.c")
+        open(c, "w").write(src.replace(old, new))
+        open(os.path.join(d, "oracle.h"), "w").write(open(os.path.join(ROOT, "oracle", "oracle.h")).read())
+        lib = os.path.join(d, "liboracle_mut.so")
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                               "-o", lib, c, "-lm"])
+        env = dict(os.environ, PV_ORACLE_LIB=lib)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", select],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+        assert r.returncode == 1, "mutation %s survived the pins:\n%s" % (name, r.stdout[-2000:])

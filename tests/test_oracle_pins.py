@@ -391,6 +391,21 @@ def test_energies_are_albedo_products():
     np.testing.assert_allclose(st.energy[2, walls, 0], 0.49 / 16384, rtol=1e-6)
 
 
+def test_energies_per_channel_with_coloured_albedo():
+    # RGB albedos differ per channel: every channel follows its own product
+    sc = scenes.make_tiny(n_paths=2048)
+    sc.albedo = np.array([[0.7, 0.5, 0.3], [0.2, 0.9, 0.6]], np.float32)
+    sc.light_power = np.array([[1.0, 2.0, 4.0]], np.float32)
+    fs0 = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    n = O.info_fields(st.info)["nseg"]
+    for p in range(sc.n_paths):
+        e = np.array([1.0, 2.0, 4.0]) / 2048
+        for r in range(int(n[p])):
+            np.testing.assert_allclose(st.energy[r, p], e, rtol=1e-6)
+            e = e * sc.albedo[fs0.tri_mat[st.hit[r, p]]]
+
+
 def test_initial_trace_photons_lie_on_their_triangles():
     sc = scenes.make_tiny(n_paths=2048)
     fs0 = O.frame_scene(sc, 0)
