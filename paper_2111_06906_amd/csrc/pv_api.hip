@@ -58,7 +58,8 @@ struct pv_ctx {
   uint32_t max_paths = 0, max_bounces = 0, max_blocks = 0;
   uint2* d_path_tiles = nullptr;
   uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr,
-           *d_head = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr;
+           *d_head = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr,
+           *d_scan_tmp = nullptr;
   float* d_partial = nullptr;
   // tuning (pv_set_tuning / pv_autotune)
   int retrace_variant = 0;
@@ -79,7 +80,7 @@ struct pv_batch {
   uint32_t n_path_tiles = 0, n_obj_tiles = 0;
   uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr, *d_head = nullptr,
            *d_gbase = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_ptotal = nullptr, *d_pbase = nullptr,
-           *d_frame = nullptr;
+           *d_frame = nullptr, *d_scan_tmp = nullptr;
   uint32_t n_counts = 0;
   float *d_out_pos = nullptr, *d_out_en = nullptr;
   uint32_t capacity = 0;
@@ -853,6 +854,7 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->d_poffsets, (size_t)nb * max_bounces));
     CK(dalloc(A, &ctx->d_gbase, 2));
     CK(dalloc(A, &ctx->d_partial, (size_t)nb * 3 * (256 + PV_MAX_LIGHTS)));
+    CK(dalloc(A, &ctx->d_scan_tmp, pv::scan_tmp_words(nb * max_bounces)));
     CK(hipMemsetAsync(ctx->d_qcount, 0, 4, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->max_paths = max_paths;
@@ -894,7 +896,7 @@ pv_status pv_build_queue(pv_ctx* ctx, const pv_path_store* store) {
   if (st) return st;
   if (!ctx->counts_ready) return fail(ctx, PV_ERR_STATE, "pv_verify_paths has not been called");
   uint32_t nb = path_blocks(store->n_paths);
-  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->stream));
+  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, ctx->stream));
   CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
   return PV_OK;
 }
@@ -905,7 +907,7 @@ pv_status pv_queue_all(pv_ctx* ctx, const pv_path_store* store) {
   if (st) return st;
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_mark_all(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, ctx->stream));
-  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->stream));
+  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, ctx->stream));
   CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
   return PV_OK;
 }
@@ -998,7 +1000,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
         if (err == hipSuccess)
           err = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, nullptr, s);
         if (err == hipSuccess)
-          err = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, s);
+          err = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, s);
         if (err == hipSuccess)
           err = pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, s);
         if (err == hipSuccess) err = hipEventRecord(e0, s);
@@ -1039,7 +1041,8 @@ pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_o
   if (!d_count || (capacity && (!d_out_pos || !d_out_energy))) return fail(ctx, PV_ERR_ARG, "output is NULL");
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_photon_count(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_pcounts, ctx->stream));
-  CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, nullptr, ctx->stream));
+  CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, nullptr, ctx->d_scan_tmp,
+                     ctx->stream));
   CK(pv::launch_photon_scatter(ctx->d_scene, ctx->d_path_tiles, nb, store->max_bounces, ctx->d_poffsets, d_out_pos,
                                d_out_energy, capacity, ctx->stream));
   return PV_OK;
@@ -1077,13 +1080,13 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
   CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_block_cnt, d_stats, st));
-  CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, st));
+  CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, b->d_scan_tmp, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->d_head, b->T, b->seed, 0,
                         b->d_frame, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
                         st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
-  CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, nullptr, st));
+  CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, nullptr, b->d_scan_tmp, st));
   CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,
                                b->d_out_pos, b->d_out_en, b->capacity, st));
   CK(pv::launch_scene_photon_base(b->d_scenes, (int)b->n, b->d_poffsets, b->d_ptotal, b->d_pbase, st));
@@ -1160,6 +1163,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
               chk(dalloc(A, &b->d_head, 1)) && chk(dalloc(A, &b->d_pcounts, counts)) &&
               chk(dalloc(A, &b->d_poffsets, counts)) && chk(dalloc(A, &b->d_ptotal, 1)) &&
               chk(dalloc(A, &b->d_pbase, n + 1)) && chk(dalloc(A, &b->d_frame, 1)) &&
+              chk(dalloc(A, &b->d_scan_tmp, pv::scan_tmp_words((uint32_t)std::max<uint64_t>(counts, ptiles.size())))) &&
               chk(dalloc(A, &b->d_out_pos, 3 * cap)) && chk(dalloc(A, &b->d_out_en, 3 * cap)) &&
               chk(upload(A, &b->d_obj_in, const_cast<const float**>(d_obj_xf), n, s)) &&
               chk(upload(A, &b->d_light_in, const_cast<const float**>(d_light_xf), n, s));

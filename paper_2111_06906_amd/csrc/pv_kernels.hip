@@ -436,6 +436,52 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ in, 
   }
 }
 
+// Two-level exclusive scan for long count arrays: each block scans a tile of
+// kScanTile entries (4 per thread) in place of the single-block loop, the tile
+// totals are scanned by k_scan, and k_scan_add adds each tile's offset.
+constexpr uint32_t kScanTile = 4096;
+
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                     uint32_t n, uint32_t* __restrict__ tile_sums) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * 4;
+  uint32_t v[4], loc = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0u;
+    loc += v[k];
+  }
+  uint32_t x = loc;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if ((int)lane_id() >= o) x += y;
+  }
+  if (lane_id() == 63) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    uint32_t t = wsum[threadIdx.x];
+    for (int o = 1; o < 16; o <<= 1) {
+      uint32_t y = __shfl_up(t, o, 64);
+      if ((int)threadIdx.x >= o) t += y;
+    }
+    wsum[threadIdx.x] = t;
+  }
+  __syncthreads();
+  uint32_t run = ((threadIdx.x >> 6) ? wsum[(threadIdx.x >> 6) - 1] : 0u) + x - loc;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = wsum[15];
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, uint32_t n,
+                                                  const uint32_t* __restrict__ tile_off) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_off[i / kScanTile];
+}
+
 // stable queue: ascending global path ids with the replace bit
 __global__ __launch_bounds__(kBlock) void k_scatter_queue(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
                                                           const uint32_t* __restrict__ offsets, uint32_t* __restrict__ queue) {
@@ -1157,10 +1203,20 @@ hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total, head);
+                       uint32_t* tile_tmp, hipStream_t s) {
+  if (n <= kScanTile || !tile_tmp) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total, head);
+    return hipGetLastError();
+  }
+  // tile_tmp holds 2 * ceil(n / kScanTile) words: tile sums, then their offsets
+  const uint32_t tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(1024), 0, s, in, out, n, tile_tmp);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, tile_tmp, tile_tmp + tiles, tiles, total, head);
+  hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, s, out, n, tile_tmp + tiles);
   return hipGetLastError();
 }
+
+uint32_t scan_tmp_words(uint32_t n) { return 2 * ((n + kScanTile - 1) / kScanTile) + 2; }
 
 hipError_t launch_scatter_queue(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* offsets,
                                 uint32_t* queue, hipStream_t s) {

@@ -12,7 +12,8 @@ hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t 
 hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
                          pv_stats* stats, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
-                       hipStream_t s);
+                       uint32_t* tile_tmp, hipStream_t s);
+uint32_t scan_tmp_words(uint32_t n);
 hipError_t launch_scatter_queue(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* offsets,
                                 uint32_t* queue, hipStream_t s);
 hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,

@@ -400,3 +400,24 @@ def test_autotune_restores_store_and_tuning_does_not_change_results(E):
     for r in results[1:]:
         for k in r:
             assert np.array_equal(r[k].view(np.uint32), results[0][k].view(np.uint32)), k
+
+
+def test_compaction_and_queue_properties_large(E):
+    # 200k paths x 7 rows: both scans take the two-level path; the outputs are
+    # checked as properties of the device store itself (a boolean-mask gather
+    # in (row, path) order, and the ascending list of replaced paths)
+    import torch
+    sc = scenes.make_mid(n_paths=200_000, frames=2)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    ctx.initial_trace(st, sc.seed, 0)
+    ctx.frame_begin(1)
+    ctx.verify(st)
+    q = ctx.queue()
+    d = st.to_numpy()
+    assert np.array_equal(q, np.flatnonzero((d["info"] >> 30) & 1))
+    pos, en, n = ctx.compact_photons(st)
+    cnt = (d["info"] >> 22) & 15
+    mask = np.arange(st.B)[:, None] < cnt[None, :]
+    assert n == int(mask.sum())
+    assert np.array_equal(pos.cpu().numpy(), d["pos"][mask]) and np.array_equal(en.cpu().numpy(), d["energy"][mask])
