@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
@@ -154,6 +156,13 @@ def main():
         sc.name, sc.n_static, sc.n_dynamic_tris(), sc.n_paths, sc.max_bounces, frames, time.perf_counter() - t0))
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx = engine.Context(sc)
     st = ctx.new_store()
     N, B = sc.n_paths, sc.max_bounces
@@ -231,8 +240,13 @@ def main():
     traffic = None
     tf = os.path.join(ROOT, "profiles", "verify_traffic.json")
     if os.path.exists(tf):
+        # counters only count for the kernel source they were taken with
         try:
-            traffic = json.load(open(tf)).get("bytes_per_launch")
+            import hashlib
+            rec = json.load(open(tf))
+            src = open(os.path.join(ROOT, "paper_2111_06906_amd", "csrc", "pv_kernels.hip"), "rb").read()
+            if rec.get("kernels_sha1") == hashlib.sha1(src).hexdigest():
+                traffic = rec.get("bytes_per_launch")
         except Exception:
             traffic = None
     res = {
