@@ -234,8 +234,9 @@ pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const floa
  * compaction into a batch-owned buffer.  d_obj_xf[i] / d_light_xf[i] are the
  * device transform arrays of scene i (layout of pv_frame_begin) whose
  * addresses stay fixed; the caller rewrites their contents before each frame.
- * threshold and seed as in pv_retrace_paths.  The work runs on the stream of
- * contexts[0]; every context must have been uploaded with pv_set_light_paths
+ * threshold and seed as in pv_retrace_paths.  Frames are ordered on the
+ * stream of contexts[0] (they run on a stream of the batch's own, which may
+ * be captured, fenced with events); every context must have been uploaded with pv_set_light_paths
  * matching its store.  Results are bit-identical to the per-context calls.
  * Synchronises.  Errors are reported through pv_last_error(contexts[0]). */
 pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path_store* stores, uint32_t n,

@@ -72,7 +72,9 @@ struct pv_ctx {
 
 struct pv_batch {
   pv_ctx* owner = nullptr;  // contexts[0]: stream and error message
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // the owner's stream (the caller's ordering)
+  hipStream_t cap_stream = nullptr;  // the batch's own stream: graphs cannot be captured on the null stream
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   uint32_t n = 0;
   Alloc mem;
   SceneDev* d_scenes = nullptr;
@@ -96,6 +98,9 @@ struct pv_batch {
   ~pv_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -1076,7 +1081,7 @@ pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const floa
 
 static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   pv_ctx* ctx = b->owner;
-  hipStream_t st = b->stream;
+  hipStream_t st = b->cap_stream;
   CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
   CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_block_cnt, d_stats, st));
@@ -1171,6 +1176,12 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       delete b;
       return fail(ctx, PV_ERR_OOM, "batch allocation failed");
     }
+    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+      delete b;
+      return fail(ctx, PV_ERR_HIP, "batch stream/event creation failed");
+    }
     b->n_path_tiles = (uint32_t)ptiles.size();
     b->n_obj_tiles = (uint32_t)otiles.size();
     b->n_counts = (uint32_t)counts;
@@ -1185,6 +1196,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
 void pv_batch_destroy(pv_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  if (b->cap_stream) (void)hipStreamSynchronize(b->cap_stream);
   delete b;
 }
 
@@ -1192,6 +1204,10 @@ pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats) {
   if (!b) return PV_ERR_ARG;
   pv_ctx* ctx = b->owner;
   CK(hipMemcpyAsync(b->d_frame, &frame, sizeof(frame), hipMemcpyHostToDevice, b->stream));
+  // the frame runs on the batch's stream, ordered after everything the caller
+  // enqueued on the owner's stream and before anything enqueued there later
+  CK(hipEventRecord(b->ev_in, b->stream));
+  CK(hipStreamWaitEvent(b->cap_stream, b->ev_in, 0));
   if (!b->captured || b->captured_stats != d_stats) {
     if (b->exec) {
       CK(hipGraphExecDestroy(b->exec));
@@ -1201,10 +1217,10 @@ pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats) {
       CK(hipGraphDestroy(b->graph));
       b->graph = nullptr;
     }
-    CK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    CK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     pv_status st = batch_enqueue(b, d_stats);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (st != PV_OK) {
       if (g) (void)hipGraphDestroy(g);
       return st;
@@ -1215,7 +1231,9 @@ pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats) {
     b->captured = true;
     b->captured_stats = d_stats;
   }
-  CK(hipGraphLaunch(b->exec, b->stream));
+  CK(hipGraphLaunch(b->exec, b->cap_stream));
+  CK(hipEventRecord(b->ev_out, b->cap_stream));
+  CK(hipStreamWaitEvent(b->stream, b->ev_out, 0));
   return PV_OK;
 }
 
