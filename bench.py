@@ -242,12 +242,11 @@ def main():
     if os.path.exists(tf):
         # counters only count for the kernel source they were taken with
         try:
-            import hashlib
+            from paper_2111_06906_amd.traffic import sources_sha1
             rec = json.load(open(tf))
-            src = open(os.path.join(ROOT, "paper_2111_06906_amd", "csrc", "pv_kernels.hip"), "rb").read()
-            if rec.get("kernels_sha1") == hashlib.sha1(src).hexdigest():
+            if rec.get("sources_sha1") == sources_sha1():
                 traffic = rec.get("bytes_per_launch")
-        except Exception:
+        except (OSError, ValueError):
             traffic = None
     res = {
         "metric": "verified path segments/s",
