@@ -51,6 +51,8 @@ struct pv_ctx {
   uint32_t n_obj_tiles = 0;
   const float** d_in_ptrs = nullptr;  // [2]: object / light transform inputs of the frame
   uint32_t n_materials = 0, n_lights = 0, n_objects = 0;
+  uint32_t stack_entries = 2;  // traversal stack per lane: whole-scene queries
+  uint32_t stack_moved = 2;    // traversal stack per lane: queries against the moved objects
   std::vector<uint32_t> h_light_paths;  // filled at binding
   // scratch
   bool reserved = false;
@@ -91,6 +93,7 @@ struct pv_batch {
   float T = -1.0f;
   uint64_t seed = 0;
   uint32_t retrace_blocks = 0;
+  uint32_t stack_entries = 2, stack_moved = 2;  // largest of the scenes'
   bool captured = false;
   pv_stats* captured_stats = nullptr;
   hipGraph_t graph = nullptr;
@@ -158,8 +161,15 @@ struct HostBvh {
   uint32_t max_depth = 0;        // deepest leaf (root = 0)
 };
 
-// traversal keeps at most one pending child per level
-constexpr uint32_t kMaxDepth = pv::kLdsStack + pv::kPrivStack - 1;
+constexpr uint32_t kMaxDepth = (uint32_t)pv::kMaxDepth;
+
+inline uint32_t ceil_log2(uint32_t n) { return n <= 1 ? 0u : 32u - (uint32_t)__builtin_clz(n - 1); }
+
+// Both builders split at the middle of the range once an unbalanced split
+// could push a leaf below depth kMaxDepth: a range of cnt items at depth d
+// with d + ceil_log2(cnt) <= kMaxDepth keeps that property under a middle
+// split, so every leaf stays within the bound (root: ceil_log2(n) <= kMaxDepth).
+inline bool must_halve(uint32_t depth, uint32_t cnt) { return depth + ceil_log2(cnt) + 1 > kMaxDepth; }
 
 HostBvh build_topology(const float* v9, uint32_t n, uint32_t leaf_max) {
   HostBvh h;
@@ -215,7 +225,7 @@ HostBvh build_topology(const float* v9, uint32_t n, uint32_t leaf_max) {
       continue;
     }
     uint32_t split;
-    if (sc[it.lo] == sc[it.hi]) {
+    if (sc[it.lo] == sc[it.hi] || must_halve(it.depth, cnt)) {
       split = (it.lo + it.hi) / 2;
     } else {
       int bit = 31 - __builtin_clz(sc[it.lo] ^ sc[it.hi]);
@@ -243,7 +253,7 @@ HostBvh build_topology(const float* v9, uint32_t n, uint32_t leaf_max) {
 
 // Static world: binned surface-area-heuristic split (16 bins per axis) of
 // the centroid range, with a leaf of at most 8 triangles when splitting does
-// not pay; median split below depth 40 keeps the depth bounded.
+// not pay; a median split where the depth bound requires it.
 HostBvh build_sah(const float* v9, uint32_t n) {
   HostBvh h;
   constexpr int K = 16;
@@ -317,7 +327,7 @@ HostBvh build_sah(const float* v9, uint32_t n) {
     if (!leaf) {
       int best_axis = -1, best_s = 0;
       float best = INFINITY;
-      if (it.depth < 40) {
+      if (!must_halve(it.depth, cnt)) {
         for (int ax = 0; ax < 3; ++ax) {
           float ext = cb.hi[ax] - cb.lo[ax];
           if (!(ext > 0)) continue;
@@ -665,10 +675,15 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     hs.n_tris_total = T;
 
     // static world: topology + boxes on the host
-    std::vector<Node> snodes;
+    std::vector<Node> nodes;  // static, then objects, then the top-level trees
     std::vector<Tri> stris;
     hs.n_static = S;
-    hs.sroot = 0;
+    hs.sroot = pv::kRootNone;
+    uint32_t depth = 0, obj_depth = 0;  // deepest leaf: all hierarchies, object hierarchies
+    for (int k = 0; k < 3; ++k) {
+      hs.sbox[k] = INFINITY;
+      hs.sbox[3 + k] = -INFINITY;
+    }
     if (S) {
       HostBvh hb = build_sah(d->h_static_verts, S);
       std::vector<float> v9(9 * (size_t)S);
@@ -684,33 +699,38 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
         std::memcpy(&stris[i].t1.w, &tri_mat[gid], 4);
       }
       if (hb.max_depth > kMaxDepth) return fail(ctx, PV_ERR_CAPACITY, "static hierarchy too deep");
+      depth = std::max(depth, hb.max_depth);
       host_boxes(hb, v9.data());
-      snodes = std::move(hb.nodes);
+      nodes = std::move(hb.nodes);
       hs.sroot = hb.root;
+      for (size_t i = 0; i < v9.size(); ++i) {
+        const int k = (int)(i % 3);
+        hs.sbox[k] = std::min(hs.sbox[k], v9[i]);
+        hs.sbox[3 + k] = std::max(hs.sbox[3 + k], v9[i]);
+      }
+      for (int k = 0; k < 3; ++k) {
+        hs.sbox[k] = pad_lo(hs.sbox[k]);
+        hs.sbox[3 + k] = pad_hi(hs.sbox[3 + k]);
+      }
     }
-    Node* d_snodes;
-    Tri* d_stris;
-    CK(upload(A, &d_snodes, snodes.data(), snodes.size(), s));
-    CK(upload(A, &d_stris, stris.data(), stris.size(), s));
-    hs.snodes = d_snodes;
-    hs.stris = d_stris;
 
     // dynamic objects: topology in object space, boxes refit per frame
     std::vector<ObjDev> objs(d->n_objects);
     std::vector<float> dlocal(9 * n_dyn);
     std::vector<uint32_t> dgid(n_dyn);
     std::vector<uint32_t> level_nodes, level_off;
-    std::vector<Node> dnodes;
     uint32_t tri_base = 0, gbase = S;
     for (uint32_t o = 0; o < d->n_objects; ++o) {
       uint32_t n = d->h_obj_tris[o];
       const float* v = d->h_obj_verts + 9 * (size_t)tri_base;
       HostBvh hb = build_topology(v, n, 2);
       if (hb.max_depth > kMaxDepth) return fail(ctx, PV_ERR_CAPACITY, "object hierarchy too deep");
-      uint32_t node_base = (uint32_t)dnodes.size();
+      depth = std::max(depth, hb.max_depth);
+      obj_depth = std::max(obj_depth, hb.max_depth);
+      uint32_t node_base = (uint32_t)nodes.size();
       auto rebase = [&](int32_t c) {
         return c >= 0 ? c + (int32_t)node_base
-                      : pv::leaf_code(pv::leaf_first(c) + tri_base, pv::leaf_count(c));
+                      : pv::leaf_code(pv::leaf_first(c) + S + tri_base, pv::leaf_count(c));
       };
       // depth of every internal node (parents precede children in the node order)
       std::vector<uint32_t> depth(hb.nodes.size(), 0);
@@ -733,7 +753,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
         nd.d.x = rebase(nd.d.x);
         nd.d.y = rebase(nd.d.y);
         if (nd.d.z >= 0) nd.d.z += 2 * (int32_t)node_base;
-        dnodes.push_back(nd);
+        nodes.push_back(nd);
       }
       for (uint32_t i = 0; i < n; ++i) {
         std::memcpy(&dlocal[9 * (size_t)(tri_base + i)], v + 9 * (size_t)hb.order[i], 9 * sizeof(float));
@@ -748,20 +768,27 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       tri_base += n;
       gbase += n;
     }
-    Node* d_dnodes;
-    Tri* d_dtris;
+    if (nodes.size() + 2 * (size_t)pv::kTopNodes >= (size_t)INT32_MAX)
+      return fail(ctx, PV_ERR_CAPACITY, "too many hierarchy nodes");
+    hs.top_base = (uint32_t)nodes.size();
+    nodes.resize(nodes.size() + 2 * (size_t)pv::kTopNodes, Node{});
+    Node* d_nodes;
+    Tri* d_tris;
     float* d_dlocal;
     uint32_t *d_dgid, *d_lnodes, *d_loff;
     ObjDev* d_objs;
-    CK(upload(A, &d_dnodes, dnodes.data(), dnodes.size(), s));
-    CK(dalloc(A, &d_dtris, n_dyn));
+    CK(upload(A, &d_nodes, nodes.data(), nodes.size(), s));
+    CK(dalloc(A, &d_tris, (size_t)S + n_dyn));
+    if (S) CK(hipMemcpyAsync(d_tris, stris.data(), sizeof(Tri) * S, hipMemcpyHostToDevice, s));
+    const int32_t no_roots[2] = {pv::kRootNone, pv::kRootNone};  // set per frame by the top-level build
+    CK(upload(A, &hs.top, no_roots, 2, s));
     CK(upload(A, &d_dlocal, dlocal.data(), dlocal.size(), s));
     CK(upload(A, &d_dgid, dgid.data(), dgid.size(), s));
     CK(upload(A, &d_lnodes, level_nodes.data(), level_nodes.size(), s));
     CK(upload(A, &d_loff, level_off.data(), level_off.size(), s));
     CK(upload(A, &d_objs, objs.data(), objs.size(), s));
-    hs.dnodes = d_dnodes;
-    hs.dtris = d_dtris;
+    hs.nodes = d_nodes;
+    hs.tris = d_tris;
     hs.dlocal = d_dlocal;
     hs.dtri_gid = d_dgid;
     hs.dlevel_nodes = d_lnodes;
@@ -810,6 +837,9 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     ctx->n_materials = d->n_materials;
     ctx->n_lights = d->n_lights;
     ctx->n_objects = d->n_objects;
+    // the top-level trees hold the static root and the objects, median split
+    ctx->stack_entries = pv::stack_entries(ceil_log2(d->n_objects + (S ? 1u : 0u)), depth);
+    ctx->stack_moved = pv::stack_entries(ceil_log2(d->n_objects), obj_depth);
     ctx->h_light_paths.assign(d->n_lights, 0);
     ctx->uploaded = true;
     return PV_OK;
@@ -880,6 +910,7 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
   CK(hipMemcpyAsync(ctx->d_in_ptrs, in, sizeof(in), hipMemcpyHostToDevice, ctx->stream));
   CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->stream));
   CK(pv::launch_update_objects(ctx->d_scene, ctx->d_obj_tiles, ctx->n_obj_tiles, ctx->stream));
+  CK(pv::launch_build_top(ctx->d_scene, 1, ctx->stream));
   ctx->frame_started = true;
   return PV_OK;
 }
@@ -890,7 +921,8 @@ pv_status pv_verify_paths(pv_ctx* ctx, const pv_path_store* store, pv_stats* d_s
   if (st) return st;
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   uint32_t nb = path_blocks(store->n_paths);
-  CK(pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, d_stats, ctx->stream));
+  CK(pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, d_stats, ctx->stack_moved,
+                       ctx->stream));
   ctx->counts_ready = true;
   return PV_OK;
 }
@@ -936,7 +968,7 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
   uint32_t blocks = (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu);
   CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold, seed,
-                        frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stream));
+                        frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stack_entries, ctx->stream));
   return PV_OK;
 }
 
@@ -1003,7 +1035,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
       for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
         err = copy_store(false);
         if (err == hipSuccess)
-          err = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, nullptr, s);
+          err = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, nullptr, ctx->stack_moved, s);
         if (err == hipSuccess)
           err = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, s);
         if (err == hipSuccess)
@@ -1011,7 +1043,8 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
         if (err == hipSuccess) err = hipEventRecord(e0, s);
         if (err == hipSuccess)
           err = pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold,
-                                   seed, frame, nullptr, nullptr, (uint32_t)(ctx->n_cu * grids[gi]), v, s);
+                                   seed, frame, nullptr, nullptr, (uint32_t)(ctx->n_cu * grids[gi]), v,
+                                   ctx->stack_entries, s);
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0;
@@ -1084,12 +1117,13 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   hipStream_t st = b->cap_stream;
   CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
   CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, st));
-  CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_block_cnt, d_stats, st));
+  CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
+  CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_block_cnt, d_stats, b->stack_moved, st));
   CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, b->d_scan_tmp, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->d_head, b->T, b->seed, 0,
                         b->d_frame, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
-                        st));
+                        b->stack_entries, st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
   CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, nullptr, b->d_scan_tmp, st));
   CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,
@@ -1133,6 +1167,8 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       uint32_t lp = 0;
       for (uint32_t l = 0; l < c->n_lights; ++l) lp += c->h_light_paths[l];
       if (lp != st->n_paths) return bad("light path counts do not add up to n_paths");
+      b->stack_entries = std::max(b->stack_entries, c->stack_entries);
+      b->stack_moved = std::max(b->stack_moved, c->stack_moved);
       SceneDev hs = c->hs;
       hs.pos = static_cast<float4*>(st->d_pos_hit);
       hs.energy = static_cast<float4*>(st->d_energy);

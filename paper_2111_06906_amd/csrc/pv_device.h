@@ -30,8 +30,19 @@ __device__ __forceinline__ const PV_GLOBAL T* G(const T* p) {
 }
 
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
-constexpr int kLdsStack = 16;      // traversal stack entries per lane held in LDS
-constexpr int kPrivStack = 48;     // further entries per lane in private memory
+// Traversal stack: entries per lane, all in LDS (dynamic shared memory sized
+// per launch from the scene's hierarchy depths).  A depth-first walk holds at
+// most one entry per internal ancestor of the node it visits, plus the
+// sentinel at the bottom, and writes the far child one slot above the top:
+// a walk through a top-level tree of depth t into a hierarchy of depth d needs
+// t + d + 2 entries.
+constexpr int kMaxStack = 40;
+constexpr int kTopDepth = 7;  // top-level tree depth bound (median split of <= 65 items)
+constexpr int kMaxDepth = kMaxStack - kTopDepth - 2;
+static_assert((1 << kTopDepth) >= PV_MAX_OBJECTS + 1, "top-level depth bound");
+__host__ __device__ inline uint32_t stack_entries(uint32_t top_depth, uint32_t depth) {
+  return top_depth + depth + 2;
+}
 constexpr uint32_t kHitNone = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
@@ -73,11 +84,11 @@ struct alignas(16) Tri {
 struct ObjDev {
   uint32_t gbase;      // global triangle id of its first triangle (upload order)
   uint32_t n_tris;
-  uint32_t tri_base;   // first record in the dynamic Tri / local arrays (leaf order)
-  uint32_t node_base;  // first node of its hierarchy in the dynamic node array
+  uint32_t tri_base;   // first record of the object in the object-space vertex arrays
+  uint32_t node_base;  // first node of its hierarchy in the scene's node array
   uint32_t n_nodes;    // internal nodes of its hierarchy
   uint32_t lvl_base;   // first entry of its level offsets (n_levels + 1 entries)
-  int32_t root;        // root child code (absolute node index, or leaf code)
+  int32_t root;        // root child code in the scene's node / triangle arrays
   uint32_t n_levels;   // depth levels holding internal nodes
 };
 
@@ -94,15 +105,23 @@ struct LeafRec {          // a leaf of a hierarchy built on the host
   uint32_t side;          // 0 = child0 of its parent, 1 = child1
 };
 
+// One hierarchy per scene: the static world's nodes, then every object's
+// nodes, then two top-level trees rebuilt each frame (one over the static root
+// and all object roots, one over the moved objects only).  Child codes and
+// leaf triangle indices are absolute in the scene's node and triangle arrays,
+// so one traversal loop serves every query.
+constexpr uint32_t kTopNodes = PV_MAX_OBJECTS;  // internal nodes of one top-level tree
+constexpr int32_t kRootNone = INT32_MIN;        // empty tree; never a leaf code (< 2^28 triangles)
+
 struct SceneDev {
-  // static world
-  const Node* snodes;
-  const Tri* stris;
-  int32_t sroot;          // child code of the static root
+  Node* nodes;            // [static][objects][2 x kTopNodes]
+  Tri* tris;              // [static][objects], leaf order
+  int32_t* top;           // [2] per frame: root of the whole scene, root of the moved objects
+  uint32_t top_base;      // first top-level node
   uint32_t n_static;
+  int32_t sroot;          // static root code (kRootNone without static triangles)
+  float sbox[6];          // static world box (lo, hi)
   // dynamic objects
-  Node* dnodes;
-  Tri* dtris;
   const float* dlocal;    // [n][9] object-space vertices in leaf order
   const uint32_t* dtri_gid;  // [n] global id of each leaf-order triangle
   const uint32_t* dlevel_nodes;  // internal nodes of each object, deepest level first
@@ -207,6 +226,8 @@ __device__ inline float box_entry(float lx, float ly, float lz, float hx, float 
 // Returns true with *t when the triangle is crossed at a parameter strictly
 // inside (tmin, tmax).  The edge functions are evaluated without contraction
 // so that triangles sharing an edge see the same value with opposite sign.
+// Written without early exits (the caller's loop stays one predicated block);
+// only an exactly zero edge function takes the double-precision branch.
 __device__ inline bool tri_hit(const Ray& r, float3 v0, float3 v1, float3 v2, float tmax, float* t_out) {
   float3 A = sub(v0, r.o), B = sub(v1, r.o), C = sub(v2, r.o);
   float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
@@ -222,126 +243,77 @@ __device__ inline bool tri_hit(const Ray& r, float3 v0, float3 v1, float3 v2, fl
     V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
     W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
   }
-  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+  const bool mixed = (U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f);
   float det = U + V + W;
-  if (det == 0.0f) return false;
   float Az = r.sz * Akz, Bz = r.sz * Bkz, Cz = r.sz * Ckz;
   float T = U * Az + V * Bz + W * Cz;
-  if (det < 0.0f) {
-    T = -T;
-    det = -det;
-  }
-  if (!(T > r.tmin * det) || !(T < tmax * det)) return false;
+  const bool neg = det < 0.0f;
+  T = neg ? -T : T;
+  det = neg ? -det : det;
+  const bool ok = !mixed && det != 0.0f && T > r.tmin * det && T < tmax * det;
   *t_out = T / det;
-  return true;
+  return ok;
 }
 
 // ---------------------------------------------------------------------------
-// traversal stack: the top kLdsStack entries of each lane in LDS (column per
-// lane, conflict-free), deeper entries in private memory.
-struct Stack {
-  PV_LDS uint32_t* lds;  // &shared[0][lane]; entry i at lds[i * kBlock]
-  int sp;
-  int32_t priv[kPrivStack];
-  __device__ inline void push(int32_t v) {
-    if (sp < kLdsStack)
-      lds[sp * kBlock] = (uint32_t)v;
-    else
-      priv[sp - kLdsStack] = v;
-    ++sp;
-  }
-  __device__ inline int32_t pop() {
-    --sp;
-    return sp < kLdsStack ? (int32_t)lds[sp * kBlock] : priv[sp - kLdsStack];
-  }
+// traversal stack column of one lane: entry i at col[i * kBlock] (a column per
+// lane of a kBlock-wide LDS array, conflict-free)
+using StackCol = PV_LDS int32_t*;
+
+struct Hit {
+  float t;       // ray parameter of the closest crossing (tmax when none)
+  uint32_t gid;  // its global triangle id, kHitNone when none
+  uint32_t rec;  // its record in the scene's triangle array
 };
 
-// Any-hit over one hierarchy; true when some triangle is crossed inside the
-// ray's open interval.  'root' is a child code relative to 'nodes'/'tris'.
-__device__ inline bool bvh_any(const Node* __restrict__ nodes_in, const Tri* __restrict__ tris_in, int32_t root,
-                               const Ray& r, Stack& st) {
-  const PV_GLOBAL Node* nodes = G(nodes_in);
-  const PV_GLOBAL Tri* tris = G(tris_in);
-  float t;
-  int base = st.sp;
+// Depth-first traversal of the scene hierarchy from 'root' (near child
+// first).  any = stop at the first crossing inside the ray's open interval;
+// otherwise the closest crossing.  Returns whether a triangle was crossed.
+// The inner loop over internal nodes has no branch besides its exit: the far
+// child is always written one slot above the top of the stack and the stack
+// pointer moves by +1 (both children entered), 0 (one) or -1 (none: the top
+// entry, read ahead, becomes the next node).  A sentinel at the bottom ends
+// the walk.
+__device__ inline bool traverse(const PV_GLOBAL Node* __restrict__ nodes, const PV_GLOBAL Tri* __restrict__ tris,
+                                int32_t root, const Ray& r, bool any, StackCol col, Hit* h) {
+  float tb = r.tmax;
+  uint32_t gid = kHitNone, rec = 0;
+  col[0] = kRootNone;
+  int sp = 1;  // entries in use
   int32_t cur = root;
-  while (true) {
-    if (cur < 0) {
-      uint32_t f = leaf_first(cur), n = leaf_count(cur);
-      for (uint32_t i = 0; i < n; ++i) {
-        Tri tr = tris[f + i];
-        if (tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), r.tmax, &t)) {
-          st.sp = base;
-          return true;
-        }
-      }
-      if (st.sp == base) return false;
-      cur = st.pop();
-      continue;
+  while (cur != kRootNone) {
+    while (cur >= 0) {
+      const int32_t top = col[(sp - 1) * kBlock];
+      const Node nd = nodes[cur];
+      const float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, tb);
+      const float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, tb);
+      const bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
+      const bool near0 = e0 <= e1;  // a missed child has entry +inf
+      col[sp * kBlock] = near0 ? nd.d.y : nd.d.x;
+      sp += (h0 && h1) ? 1 : ((h0 || h1) ? 0 : -1);
+      cur = (h0 || h1) ? (near0 ? nd.d.x : nd.d.y) : top;
     }
-    Node nd = nodes[cur];
-    float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, r.tmax);
-    float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, r.tmax);
-    bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
-    if (h0 && h1) {
-      int32_t nearc = e0 <= e1 ? nd.d.x : nd.d.y, farc = e0 <= e1 ? nd.d.y : nd.d.x;
-      st.push(farc);
-      cur = nearc;
-    } else if (h0) {
-      cur = nd.d.x;
-    } else if (h1) {
-      cur = nd.d.y;
-    } else {
-      if (st.sp == base) return false;
-      cur = st.pop();
+    if (cur == kRootNone) break;
+    const uint32_t f = leaf_first(cur), n = leaf_count(cur);
+    bool found = false;
+    for (uint32_t i = f; i < f + n; ++i) {
+      const Tri tr = tris[i];
+      float t;
+      // tri_hit only reports crossings strictly closer than tb
+      const bool hit = tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), tb, &t);
+      tb = hit ? t : tb;
+      gid = hit ? __float_as_uint(tr.t0.w) : gid;
+      rec = hit ? i : rec;
+      found |= hit;
     }
+    if (found && any) break;
+    --sp;
+    cur = col[sp * kBlock];
   }
-}
-
-// Closest hit over one hierarchy: shrinks *tbest, records the record index.
-__device__ inline void bvh_closest(const Node* __restrict__ nodes_in, const Tri* __restrict__ tris_in, int32_t root,
-                                   const Ray& r, Stack& st, float* tbest, uint32_t* gid_best,
-                                   uint32_t* rec_best, const Tri** set_best) {
-  const PV_GLOBAL Node* nodes = G(nodes_in);
-  const PV_GLOBAL Tri* tris = G(tris_in);
-  float t;
-  int base = st.sp;
-  int32_t cur = root;
-  while (true) {
-    if (cur < 0) {
-      uint32_t f = leaf_first(cur), n = leaf_count(cur);
-      for (uint32_t i = 0; i < n; ++i) {
-        Tri tr = tris[f + i];
-        if (tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), *tbest, &t)) {
-          // tri_hit only reports crossings strictly closer than *tbest
-          *tbest = t;
-          *gid_best = __float_as_uint(tr.t0.w);
-          *rec_best = f + i;
-          *set_best = tris_in;
-        }
-      }
-      if (st.sp == base) return;
-      cur = st.pop();
-      continue;
-    }
-    Node nd = nodes[cur];
-    float tb = *tbest;
-    float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, tb);
-    float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, tb);
-    bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
-    if (h0 && h1) {
-      int32_t nearc = e0 <= e1 ? nd.d.x : nd.d.y, farc = e0 <= e1 ? nd.d.y : nd.d.x;
-      st.push(farc);
-      cur = nearc;
-    } else if (h0) {
-      cur = nd.d.x;
-    } else if (h1) {
-      cur = nd.d.y;
-    } else {
-      if (st.sp == base) return;
-      cur = st.pop();
-    }
-  }
+  h->t = tb;
+  h->gid = gid;
+  h->rec = rec;
+  return gid != kHitNone;
 }
 
 // ---------------------------------------------------------------------------

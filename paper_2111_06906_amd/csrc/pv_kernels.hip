@@ -94,7 +94,7 @@ __device__ inline void child_box(const SceneDev& S, int32_t code, float* b) {
     float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
     for (uint32_t i = f; i < f + c; ++i) {
-      Tri t = S.dtris[i];
+      Tri t = S.tris[i];
       float4 vs[3] = {t.t0, t.t1, t.t2};
       for (int k = 0; k < 3; ++k) {
         lo[0] = fminf(lo[0], vs[k].x); hi[0] = fmaxf(hi[0], vs[k].x);
@@ -107,7 +107,7 @@ __device__ inline void child_box(const SceneDev& S, int32_t code, float* b) {
       b[3 + k] = pad_hi(hi[k]);
     }
   } else {
-    const Node nd = S.dnodes[code];
+    const Node nd = S.nodes[code];
     const float* f = reinterpret_cast<const float*>(&nd);
     for (int k = 0; k < 3; ++k) {
       b[k] = fminf(f[k], f[6 + k]);
@@ -136,14 +136,14 @@ __global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, con
     t.t0 = make_float4(w[0], w[1], w[2], __uint_as_float(gid));
     t.t1 = make_float4(w[3], w[4], w[5], __uint_as_float(S.tri_mat[gid]));
     t.t2 = make_float4(w[6], w[7], w[8], 0.0f);
-    S.dtris[rec] = t;
+    S.tris[S.n_static + rec] = t;
   }
   __syncthreads();
   const uint32_t* off = S.dlevel_off + ob.lvl_base;
   for (uint32_t lv = 0; lv < ob.n_levels; ++lv) {
     const uint32_t e = off[lv + 1];
     for (uint32_t i = off[lv] + threadIdx.x; i < e; i += blockDim.x) {
-      Node* nd = S.dnodes + S.dlevel_nodes[i];
+      Node* nd = S.nodes + S.dlevel_nodes[i];
       int4 ch = nd->d;
       float b[12];
       child_box(S, ch.x, b);
@@ -162,11 +162,104 @@ __global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, con
 }
 
 // ---------------------------------------------------------------------------
+// top-level trees, rebuilt each frame once the object boxes are current: one
+// over the static root and every object root, one over the moved objects
+// only (the set that verification and the walk's clearance tests query).
+// The trees hold at most PV_MAX_OBJECTS + 1 items, so one thread per scene
+// builds them: median split of the items along the widest axis of their box
+// centres, ranges taken from an explicit stack, node 0 the root.
+
+__global__ void k_build_top(SceneDev* scenes) {
+  constexpr int kItems = PV_MAX_OBJECTS + 1;
+  __shared__ float ibox[kItems][6];
+  __shared__ float icen[kItems][3];
+  __shared__ int32_t icode[kItems];
+  __shared__ uint8_t idx[kItems];
+  SceneDev& S = scenes[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  for (int which = 0; which < 2; ++which) {
+    int n = 0;
+    if (which == 0 && S.sroot != kRootNone) {
+      for (int k = 0; k < 6; ++k) ibox[n][k] = S.sbox[k];
+      icode[n++] = S.sroot;
+    }
+    for (uint32_t o = 0; o < S.n_obj; ++o) {
+      if (which == 1 && !S.obj_moved[o]) continue;
+      for (int k = 0; k < 6; ++k) ibox[n][k] = S.obj_aabb[6 * o + k];
+      icode[n++] = S.objs[o].root;
+    }
+    for (int i = 0; i < n; ++i) {
+      idx[i] = (uint8_t)i;
+      for (int k = 0; k < 3; ++k) icen[i][k] = 0.5f * (ibox[i][k] + ibox[i][3 + k]);
+    }
+    const uint32_t first = S.top_base + (uint32_t)which * kTopNodes;
+    int32_t root = n == 0 ? kRootNone : (n == 1 ? icode[0] : (int32_t)first);
+    if (n >= 2) {
+      struct Range {
+        uint8_t lo, hi, node;
+      };
+      Range stack[kTopNodes];
+      int sp = 0, next = 1;
+      stack[sp++] = {0, (uint8_t)n, 0};
+      while (sp > 0) {
+        const Range rg = stack[--sp];
+        float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+        float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+        for (int i = rg.lo; i < rg.hi; ++i)
+          for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], icen[idx[i]][k]);
+            hi[k] = fmaxf(hi[k], icen[idx[i]][k]);
+          }
+        int ax = 0;
+        for (int k = 1; k < 3; ++k)
+          if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+        for (int i = rg.lo + 1; i < rg.hi; ++i) {  // insertion sort by centre
+          const uint8_t v = idx[i];
+          int j = i - 1;
+          while (j >= rg.lo && icen[idx[j]][ax] > icen[v][ax]) {
+            idx[j + 1] = idx[j];
+            --j;
+          }
+          idx[j + 1] = v;
+        }
+        const int mid = (rg.lo + rg.hi) / 2;
+        float cb[2][6];
+        int32_t ch[2];
+        for (int side = 0; side < 2; ++side) {
+          const int a = side ? mid : rg.lo, b = side ? rg.hi : mid;
+          for (int k = 0; k < 3; ++k) {
+            cb[side][k] = __builtin_inff();
+            cb[side][3 + k] = -__builtin_inff();
+          }
+          for (int i = a; i < b; ++i)
+            for (int k = 0; k < 3; ++k) {
+              cb[side][k] = fminf(cb[side][k], ibox[idx[i]][k]);
+              cb[side][3 + k] = fmaxf(cb[side][3 + k], ibox[idx[i]][3 + k]);
+            }
+          if (b - a == 1) {
+            ch[side] = icode[idx[a]];
+          } else {
+            const int id = next++;
+            ch[side] = (int32_t)(first + (uint32_t)id);
+            stack[sp++] = {(uint8_t)a, (uint8_t)b, (uint8_t)id};
+          }
+        }
+        Node& nd = S.nodes[first + rg.node];
+        nd.a = make_float4(cb[0][0], cb[0][1], cb[0][2], cb[0][3]);
+        nd.b = make_float4(cb[0][4], cb[0][5], cb[1][0], cb[1][1]);
+        nd.c = make_float4(cb[1][2], cb[1][3], cb[1][4], cb[1][5]);
+        nd.d = make_int4(ch[0], ch[1], -1, 0);
+      }
+    }
+    S.top[which] = root;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // verification (Sections 3.1 and 3.2)
 
 struct MovedSet {
   int n;
-  int32_t root[PV_MAX_OBJECTS];
   float box[PV_MAX_OBJECTS][6];
   uint32_t glo[PV_MAX_OBJECTS], ghi[PV_MAX_OBJECTS];
 };
@@ -177,7 +270,6 @@ __device__ inline void load_moved(const SceneDev& S, MovedSet& M) {
     for (uint32_t o = 0; o < S.n_obj; ++o) {
       if (!G(S.obj_moved)[o]) continue;
       const ObjDev ob = G(S.objs)[o];
-      M.root[n] = ob.root;
       for (int k = 0; k < 6; ++k) M.box[n][k] = G(S.obj_aabb)[6 * o + k];
       M.glo[n] = ob.gbase;
       M.ghi[n] = ob.gbase + ob.n_tris;
@@ -191,21 +283,6 @@ __device__ inline void load_moved(const SceneDev& S, MovedSet& M) {
 __device__ inline bool on_moved(const MovedSet& M, uint32_t hit) {
   for (int i = 0; i < M.n; ++i)
     if (hit >= M.glo[i] && hit < M.ghi[i]) return true;
-  return false;
-}
-
-__device__ inline bool blocked_by_moved(const SceneDev& S, const MovedSet& M, const Ray& r, Stack& st,
-                                        uint32_t& box_hits) {
-  bool counted = false;
-  for (int i = 0; i < M.n; ++i) {
-    const float* b = M.box[i];
-    if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, r.tmax) == __builtin_inff()) continue;
-    if (!counted) {
-      ++box_hits;
-      counted = true;
-    }
-    if (bvh_any(S.dnodes, S.dtris, M.root[i], r, st)) return true;
-  }
   return false;
 }
 
@@ -260,7 +337,7 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
 // segment is the minimum over blocked segments and the first moved endpoint.
 __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
                                                    uint32_t* __restrict__ block_cnt, pv_stats* stats) {
-  __shared__ uint32_t sstack[kLdsStack * kBlock];
+  extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   __shared__ MovedSet M;
   __shared__ unsigned long long sred[kBlock / 64];
   __shared__ uint16_t task[kBlock * PV_MAX_BOUNCES];
@@ -341,9 +418,10 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
   for (uint32_t m = mask; m; m &= m - 1) task[pos++] = (uint16_t)((tid << 4) | (uint32_t)(__ffs(m) - 1));
   __syncthreads();
   // ---- phase B: every thread traverses tasks of any path of the block
-  Stack st;
-  st.lds = (PV_LDS uint32_t*)(sstack + tid);
-  st.sp = 0;
+  const StackCol col = (StackCol)(sstack + tid);
+  const PV_GLOBAL Node* nodes = G(S.nodes);
+  const PV_GLOBAL Tri* tris = G(S.tris);
+  const int32_t moved_root = G(S.top)[1];
   for (uint32_t t = tid; t < total; t += kBlock) {
     uint32_t tk = task[t], owner = tk >> 4, j = tk & 15u;
     if (j >= first_bad[owner]) continue;  // an earlier segment already failed
@@ -352,14 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
                       : xyz(G(S.pos)[(size_t)(j - 1) * stride + q]);
     float3 b = xyz(G(S.pos)[(size_t)j * stride + q]);
     Ray r = segment_ray(a, b, S.eps_end);
-    for (int i = 0; i < M.n; ++i) {
-      const float* bx = M.box[i];
-      if (box_entry(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, r.tmax) == __builtin_inff()) continue;
-      if (bvh_any(S.dnodes, S.dtris, M.root[i], r, st)) {
-        atomicMin(&first_bad[owner], j);
-        break;
-      }
-    }
+    Hit h;
+    if (traverse(nodes, tris, moved_root, r, true, col, &h)) atomicMin(&first_bad[owner], j);
   }
   __syncthreads();
   // ---- phase C
@@ -518,127 +590,18 @@ __global__ __launch_bounds__(kBlock) void k_mark_all(const SceneDev* __restrict_
 // ---------------------------------------------------------------------------
 // re-tracing (Section 3.2 naive, Section 3.3 / Algorithm 1 error-based)
 
-struct Hit {
-  float t;
-  uint32_t gid;
-  uint32_t rec;
-  const Tri* set;
-};
-
 constexpr float kTFar = 16.0f;
 
-// Dynamic objects of a single scene staged in LDS once per workgroup.
-struct ObjTable {
-  float box[PV_MAX_OBJECTS][6];
-  int32_t root[PV_MAX_OBJECTS];
-  uint32_t moved[PV_MAX_OBJECTS];
-};
-
-__device__ inline void load_objects(const SceneDev& S, ObjTable& T) {
-  for (uint32_t o = threadIdx.x; o < S.n_obj; o += blockDim.x) {
-    for (int k = 0; k < 6; ++k) T.box[o][k] = G(S.obj_aabb)[6 * o + k];
-    T.root[o] = G(S.objs)[o].root;
-    T.moved[o] = G(S.obj_moved)[o];
-  }
-  __syncthreads();
-}
-
-// One query over every hierarchy of a scene in a single loop: the static
-// world first (unless only moved objects are wanted), then each dynamic
-// object whose box the ray reaches.  Lanes at different hierarchies still run
-// the same loop body.  any = stop at the first crossing.  OT: the scene's
-// objects in LDS (single-scene launches) or null (read from the descriptor).
-__device__ inline bool trace(const SceneDev& S, const Ray& r, bool any, bool moved_only, Stack& st, Hit* h,
-                             const PV_LDS ObjTable* OT) {
-  float t;
-  h->t = r.tmax;
-  h->gid = kHitNone;
-  h->rec = 0;
-  h->set = nullptr;
-  const PV_GLOBAL Node* nodes = G(S.snodes);
-  const PV_GLOBAL Tri* tris = G(S.stris);
-  const Tri* tris_generic = S.stris;
-  int ri = (moved_only || !S.n_static) ? 0 : -1;  // -1 = static world, else object index
-  int32_t cur = ri < 0 ? S.sroot : 0;
-  bool have = ri < 0;
-  const int base = st.sp;
-  while (true) {
-    if (!have) {
-      // next dynamic object whose box the ray enters before the current best
-      if (ri < 0) ri = 0;
-      bool found = false;
-      while (ri < (int)S.n_obj) {
-        int o = ri++;
-        if (OT) {
-          if (moved_only && !OT->moved[o]) continue;
-          const PV_LDS float* b = OT->box[o];
-          if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h->t) == __builtin_inff()) continue;
-          cur = OT->root[o];
-        } else {
-          if (moved_only && !G(S.obj_moved)[o]) continue;
-          const PV_GLOBAL float* b = G(S.obj_aabb) + 6 * o;
-          if (box_entry(b[0], b[1], b[2], b[3], b[4], b[5], r, h->t) == __builtin_inff()) continue;
-          cur = G(S.objs)[o].root;
-        }
-        nodes = G(S.dnodes);
-        tris = G(S.dtris);
-        tris_generic = S.dtris;
-        found = true;
-        break;
-      }
-      if (!found) return h->gid != kHitNone;
-      have = true;
-    }
-    if (cur < 0) {
-      uint32_t f = leaf_first(cur), n = leaf_count(cur);
-      for (uint32_t i = 0; i < n; ++i) {
-        Tri tr = tris[f + i];
-        if (tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), h->t, &t)) {
-          h->t = t;
-          h->gid = __float_as_uint(tr.t0.w);
-          h->rec = f + i;
-          h->set = tris_generic;
-          if (any) {
-            st.sp = base;
-            return true;
-          }
-        }
-      }
-      if (st.sp == base)
-        have = false;
-      else
-        cur = st.pop();
-      continue;
-    }
-    Node nd = nodes[cur];
-    float tb = h->t;
-    float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, tb);
-    float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, tb);
-    bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
-    if (h0 && h1) {
-      int32_t nearc = e0 <= e1 ? nd.d.x : nd.d.y, farc = e0 <= e1 ? nd.d.y : nd.d.x;
-      st.push(farc);
-      cur = nearc;
-    } else if (h0) {
-      cur = nd.d.x;
-    } else if (h1) {
-      cur = nd.d.y;
-    } else if (st.sp == base) {
-      have = false;
-    } else {
-      cur = st.pop();
-    }
-  }
-}
-
-__device__ inline float3 hit_normal(const Hit& h) {
-  Tri t = G(h.set)[h.rec];
+__device__ inline float3 hit_normal(const SceneDev& S, const Hit& h) {
+  Tri t = G(S.tris)[h.rec];
   float3 v0 = xyz(t.t0), v1 = xyz(t.t1), v2 = xyz(t.t2);
   float3 n = cross(sub(v1, v0), sub(v2, v0));
   return mul(n, 1.0f / length(n));
 }
 
-__device__ inline uint32_t hit_material(const Hit& h) { return __float_as_uint(G(h.set)[h.rec].t1.w); }
+__device__ inline uint32_t hit_material(const SceneDev& S, const Hit& h) {
+  return __float_as_uint(G(S.tris)[h.rec].t1.w);
+}
 
 __device__ inline float3 vertex(const SceneDev& S, uint32_t p, uint32_t j) {
   const size_t stride = S.stride;
@@ -799,18 +762,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
                                                     const uint32_t* __restrict__ qcount, uint32_t* head, float T,
                                                     uint64_t seed, uint32_t frame_arg, const uint32_t* frame_ptr,
                                                     pv_stats* stats) {
-  __shared__ uint32_t sstack[kLdsStack * kBlock];
+  extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   __shared__ unsigned long long sred[kBlock / 64];
-  __shared__ ObjTable OTs;
-  Stack st;
-  st.lds = (PV_LDS uint32_t*)(sstack + threadIdx.x);
-  st.sp = 0;
+  const StackCol col = (StackCol)(sstack + threadIdx.x);
   const uint32_t frame = frame_ptr ? *frame_ptr : frame_arg;
-  const PV_LDS ObjTable* OT = nullptr;
-  if (kSingle) {
-    load_objects(scenes[0], OTs);
-    OT = (const PV_LDS ObjTable*)&OTs;
-  }
   uint32_t n_rays = 0, n_photons = 0, n_acc = 0, n_trunc = 0;
   const uint32_t count = *qcount;
   Lane L;
@@ -851,7 +806,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     const SceneDev& S = kSingle ? scenes[0] : *L.S;
     bool busy = L.mode != ST_IDLE && L.mode != ST_END;
     // ---- build this lane's query
-    bool any = false, moved_only = false;
+    bool any = false;
     float3 qo = L.x, qd = L.w, wn = L.w, xa, xb;
     float tmin = S.eps_end, tmax = kTFar;
     if (busy) {
@@ -875,7 +830,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         } else {
           // any hit of the segment xa -> xb against the moved objects
           any = true;
-          moved_only = true;
           qo = xa;
           qd = sub(xb, xa);
           float len = length(qd);
@@ -888,7 +842,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     h.gid = kHitNone;
     if (busy) {
       Ray r = make_ray(qo, qd, tmin, tmax);
-      trace(S, r, any, moved_only, st, &h, OT);
+      const int32_t root = G(S.top)[any ? 1 : 0];
+      traverse(G(S.nodes), G(S.tris), root, r, any, col, &h);
       if (!any) ++n_rays;
     }
     if (!busy) continue;
@@ -914,8 +869,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         put_photon(S, L.p, L.k, xn, h.gid, en);
         ++n_photons;
         L.x = xn;
-        L.ntri = hit_normal(h);
-        L.mat = hit_material(h);
+        L.ntri = hit_normal(S, h);
+        L.mat = hit_material(S, h);
         L.e = en;
         L.row = L.k;
         to_tail(L);
@@ -935,8 +890,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         ++n_photons;
         L.x = xn;
         L.w = wn;
-        L.ntri = hit_normal(h);
-        L.mat = hit_material(h);
+        L.ntri = hit_normal(S, h);
+        L.mat = hit_material(S, h);
         L.e = en;
         to_tail(L);
         break;
@@ -966,10 +921,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         }
         float3 xc = vertex(S, L.p, L.j + 2);
         float3 d2 = sub(xc, hp);
-        float3 nh = hit_normal(h);
+        float3 nh = hit_normal(S, h);
         float c1 = dot(qd, nh), l2 = length(d2);
         float c2 = l2 > 0.0f ? dot(d2, nh) / l2 : 0.0f;
-        uint32_t mat = hit_material(h);
+        uint32_t mat = hit_material(S, h);
         float3 en = (c1 * c2 < 0.0f) ? reflect_energy(S, ej, mat) : f3(0.0f, 0.0f, 0.0f);
         float3 eo = energy_row(S, L.p, L.j + 1);
         if (!eq2(en, eo, T)) {
@@ -1195,10 +1150,19 @@ hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t 
   return hipGetLastError();
 }
 
+hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s) {
+  if (n_scenes <= 0) return hipSuccess;
+  k_build_top<<<n_scenes, 64, 0, s>>>(scenes);
+  return hipGetLastError();
+}
+
+static size_t stack_bytes(uint32_t entries) { return (size_t)entries * kBlock * sizeof(int32_t); }
+
 hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
-                         pv_stats* stats, hipStream_t s) {
+                         pv_stats* stats, uint32_t stack, hipStream_t s) {
   if (!n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_verify, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, block_cnt, stats);
+  if (stack < 2 || stack > (uint32_t)kMaxStack) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_verify, dim3(n_tiles), dim3(kBlock), stack_bytes(stack), s, scenes, tiles, block_cnt, stats);
   return hipGetLastError();
 }
 
@@ -1235,24 +1199,24 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
 // variant v selects the occupancy target of the re-trace kernel (waves per
 // SIMD the compiler must allow): 0 -> 4, 1 -> 5, 2 -> 6, 3 -> 8
 template <bool kSingle>
-static void retrace_variant(int v, dim3 g, hipStream_t s, const SceneDev* scenes, const uint32_t* gbase, int n_scenes,
+static void retrace_variant(int v, dim3 g, size_t lds, hipStream_t s, const SceneDev* scenes, const uint32_t* gbase, int n_scenes,
                             const uint32_t* queue, const uint32_t* qcount, uint32_t* head, float T, uint64_t seed,
                             uint32_t frame, const uint32_t* frame_ptr, pv_stats* stats) {
   switch (v) {
     case 1:
-      hipLaunchKernelGGL((k_retrace<kSingle, 5>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 5>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
                          T, seed, frame, frame_ptr, stats);
       break;
     case 2:
-      hipLaunchKernelGGL((k_retrace<kSingle, 6>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 6>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
                          T, seed, frame, frame_ptr, stats);
       break;
     case 3:
-      hipLaunchKernelGGL((k_retrace<kSingle, 8>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 8>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
                          T, seed, frame, frame_ptr, stats);
       break;
     default:
-      hipLaunchKernelGGL((k_retrace<kSingle, 4>), g, dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 4>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
                          T, seed, frame, frame_ptr, stats);
       break;
   }
@@ -1260,12 +1224,14 @@ static void retrace_variant(int v, dim3 g, hipStream_t s, const SceneDev* scenes
 
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
-                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, hipStream_t s) {
+                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
+                          hipStream_t s) {
+  if (stack < 2 || stack > (uint32_t)kMaxStack) return hipErrorInvalidValue;
   if (n_scenes == 1)
-    retrace_variant<true>(variant, dim3(n_blocks), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
+    retrace_variant<true>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
                           frame_ptr, stats);
   else
-    retrace_variant<false>(variant, dim3(n_blocks), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
+    retrace_variant<false>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
                            frame_ptr, stats);
   return hipGetLastError();
 }

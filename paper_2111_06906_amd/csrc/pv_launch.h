@@ -9,8 +9,11 @@ namespace pv {
 hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
                               const float* const* light_in, hipStream_t s);
 hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
+hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s);
+// 'stack': traversal stack entries per lane (stack_entries of the scenes'
+// hierarchy depths, at most kMaxStack)
 hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
-                         pv_stats* stats, hipStream_t s);
+                         pv_stats* stats, uint32_t stack, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
                        uint32_t* tile_tmp, hipStream_t s);
 uint32_t scan_tmp_words(uint32_t n);
@@ -20,7 +23,8 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
                            hipStream_t s);
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
-                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, hipStream_t s);
+                          const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
+                          hipStream_t s);
 hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
                                hipStream_t s);
 hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t B,
