@@ -73,7 +73,7 @@ def batched(args, engine, scenes, torch, np, tuning=None):
     (pc, ps), (bc, bs) = sets
     if tuning:
         for c in pc + bc:
-            c.set_tuning(tuning["retrace_variant"], tuning["retrace_blocks_per_cu"])
+            c.set_tuning(tuning["retrace_variant"], tuning["retrace_blocks_per_cu"], tuning["walk_min_active"])
     caps = [st.n_paths * st.B for st in ps]
     outs = [(torch.empty((c, 3), dtype=torch.float32, device="cuda"),
              torch.empty((c, 3), dtype=torch.float32, device="cuda"),
@@ -267,7 +267,8 @@ def main():
                                    sc.light_half.shape[0], "moving" if sc.meta.get("lights_move") else "static", T),
                    "paths": N, "max_bounces": B, "frames_timed": K},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": "k_verify",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "verify: k_verify_begin + k_verify_scan + k_verify_trace + k_verify_finish",
                      "algorithmic_bytes_per_launch": bytes_verify / K, "avg_launch_ms": avg_verify_s * 1e3},
         "phases_ms_per_frame": {k: v / K for k, v in phase.items()},
         "tuning": tuning,

@@ -135,9 +135,10 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* desc);
  * afterwards. */
 pv_status pv_set_light_paths(pv_ctx* ctx, const uint32_t* h_counts);
 
-/* Reserve scratch (work queue, per-block counters) for stores of up to
- * max_paths paths and max_bounces rows.  Synchronises.  Must precede
- * verify/queue/retrace/compact calls. */
+/* Reserve scratch (work queue, per-block counters, verification task lists:
+ * about 4 * max_paths * (max_bounces + 4) bytes) for stores of up to
+ * max_paths paths (1 .. 2^28) and max_bounces rows.  Synchronises.  Must
+ * precede verify/queue/retrace/compact calls. */
 pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces);
 
 /* --- per frame --------------------------------------------------------- */
@@ -191,9 +192,11 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
 /* Kernel tuning of a context.  PV_TUNE_RETRACE_VARIANT (0..3): occupancy
  * target of the re-trace kernel (4, 5, 6, 8 waves per SIMD; higher targets
  * trade registers for private-memory spills); PV_TUNE_RETRACE_BLOCKS_PER_CU
- * (1..64): persistent re-trace workgroups per compute unit.  Results do not
+ * (1..64): persistent re-trace workgroups per compute unit;
+ * PV_TUNE_WALK_MIN_ACTIVE (1..64): a wave's hierarchy walk yields to take new
+ * queries once fewer of its 64 lanes are still walking.  Results do not
  * depend on the tuning. */
-enum { PV_TUNE_RETRACE_VARIANT = 0, PV_TUNE_RETRACE_BLOCKS_PER_CU = 1 };
+enum { PV_TUNE_RETRACE_VARIANT = 0, PV_TUNE_RETRACE_BLOCKS_PER_CU = 1, PV_TUNE_WALK_MIN_ACTIVE = 2 };
 pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value);
 pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
 

@@ -63,9 +63,11 @@ struct pv_ctx {
            *d_head = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr,
            *d_scan_tmp = nullptr;
   float* d_partial = nullptr;
+  pv::VerifyWork vw{};  // verification task lists
   // tuning (pv_set_tuning / pv_autotune)
   int retrace_variant = 0;
   int retrace_blocks_per_cu = 8;
+  int walk_min_active = 16;  // a wave's walk yields once fewer lanes are still walking
   // bound store
   bool bound = false;
   bool counts_ready = false;   // per-block replace counts written by verify
@@ -86,6 +88,7 @@ struct pv_batch {
            *d_gbase = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_ptotal = nullptr, *d_pbase = nullptr,
            *d_frame = nullptr, *d_scan_tmp = nullptr;
   uint32_t n_counts = 0;
+  pv::VerifyWork vw{};
   float *d_out_pos = nullptr, *d_out_en = nullptr;
   uint32_t capacity = 0;
   const float** d_obj_in = nullptr;
@@ -162,6 +165,8 @@ struct HostBvh {
 };
 
 constexpr uint32_t kMaxDepth = (uint32_t)pv::kMaxDepth;
+// paths per context or batch: verification tasks carry a path index in 28 bits
+constexpr uint32_t kMaxPaths = 1u << 28;
 
 inline uint32_t ceil_log2(uint32_t n) { return n <= 1 ? 0u : 32u - (uint32_t)__builtin_clz(n - 1); }
 
@@ -464,6 +469,9 @@ std::vector<uint2> make_tiles(uint32_t scene, uint32_t n) {
 
 uint32_t path_blocks(uint32_t n) { return (n + pv::kBlock - 1) / pv::kBlock; }
 
+// grid of the verification traversal kernel (persistent, grid-stride)
+uint32_t verify_blocks(const pv_ctx* ctx) { return (uint32_t)ctx->n_cu * 8u; }
+
 pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
   if (!ctx->reserved) return fail(ctx, PV_ERR_STATE, "pv_reserve has not been called");
@@ -493,6 +501,8 @@ pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   ctx->hs.n_blocks = path_blocks(st->n_paths);
   ctx->hs.count_base = 0;
   ctx->hs.gpath_base = 0;
+  ctx->hs.tile_base = 0;
+  ctx->hs.task_base = 0;
   CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
   uint32_t gb[2] = {0, st->n_paths};
   CK(hipMemcpyAsync(ctx->d_gbase, gb, sizeof(gb), hipMemcpyHostToDevice, ctx->stream));
@@ -870,7 +880,7 @@ pv_status pv_set_light_paths(pv_ctx* ctx, const uint32_t* h_counts) {
 
 pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
   if (!ctx) return PV_ERR_ARG;
-  if (max_paths == 0 || max_paths > (1u << 30)) return fail(ctx, PV_ERR_ARG, "max_paths out of range");
+  if (max_paths == 0 || max_paths > kMaxPaths) return fail(ctx, PV_ERR_ARG, "max_paths out of range");
   if (max_bounces < 1 || max_bounces > PV_MAX_BOUNCES) return fail(ctx, PV_ERR_ARG, "max_bounces out of range");
   try {
     CK(hipStreamSynchronize(ctx->stream));
@@ -890,6 +900,14 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->d_gbase, 2));
     CK(dalloc(A, &ctx->d_partial, (size_t)nb * 3 * (256 + PV_MAX_LIGHTS)));
     CK(dalloc(A, &ctx->d_scan_tmp, pv::scan_tmp_words(nb * max_bounces)));
+    const size_t task_cap = (size_t)nb * pv::kBlock * max_bounces;  // a region of kBlock * B per tile
+    CK(dalloc(A, &ctx->vw.tmp, task_cap));
+    CK(dalloc(A, &ctx->vw.tasks, task_cap));
+    CK(dalloc(A, &ctx->vw.tcount, nb));
+    CK(dalloc(A, &ctx->vw.toff, nb));
+    CK(dalloc(A, &ctx->vw.total, 1));
+    CK(dalloc(A, &ctx->vw.first, max_paths));
+    CK(dalloc(A, &ctx->vw.part, 4 * (size_t)nb + 2 * (size_t)pv::verify_finish_blocks(verify_blocks(ctx))));
     CK(hipMemsetAsync(ctx->d_qcount, 0, 4, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->max_paths = max_paths;
@@ -921,8 +939,8 @@ pv_status pv_verify_paths(pv_ctx* ctx, const pv_path_store* store, pv_stats* d_s
   if (st) return st;
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   uint32_t nb = path_blocks(store->n_paths);
-  CK(pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, d_stats, ctx->stack_moved,
-                       ctx->stream));
+  CK(pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt, d_stats,
+                       ctx->stack_moved, verify_blocks(ctx), ctx->d_scan_tmp, ctx->stream));
   ctx->counts_ready = true;
   return PV_OK;
 }
@@ -968,7 +986,8 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
   uint32_t blocks = (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu);
   CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold, seed,
-                        frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stack_entries, ctx->stream));
+                        frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stack_entries,
+                        ctx->walk_min_active, ctx->stream));
   return PV_OK;
 }
 
@@ -980,6 +999,9 @@ pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value) {
   } else if (key == PV_TUNE_RETRACE_BLOCKS_PER_CU) {
     if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "blocks per CU out of range 1..64");
     ctx->retrace_blocks_per_cu = value;
+  } else if (key == PV_TUNE_WALK_MIN_ACTIVE) {
+    if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "walk minimum active lanes out of range 1..64");
+    ctx->walk_min_active = value;
   } else {
     return fail(ctx, PV_ERR_ARG, "unknown tuning key");
   }
@@ -992,6 +1014,8 @@ pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value) {
     *value = ctx->retrace_variant;
   else if (key == PV_TUNE_RETRACE_BLOCKS_PER_CU)
     *value = ctx->retrace_blocks_per_cu;
+  else if (key == PV_TUNE_WALK_MIN_ACTIVE)
+    *value = ctx->walk_min_active;
   else
     return PV_ERR_ARG;
   return PV_OK;
@@ -1025,37 +1049,56 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   hipError_t err = copy_store(true);
   if (err == hipSuccess) err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
-  float best = INFINITY;
-  int best_v = ctx->retrace_variant, best_b = ctx->retrace_blocks_per_cu;
   const uint32_t nb = path_blocks(store->n_paths);
+  // one trial: restore the store, verify + queue, time the re-trace (best of 2)
+  auto trial = [&](int v, int bpc, int min_active, float* ms_out) -> hipError_t {
+    float t_min = INFINITY;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      e = copy_store(false);
+      if (e == hipSuccess)
+        e = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt,
+                              nullptr, ctx->stack_moved, verify_blocks(ctx), ctx->d_scan_tmp, s);
+      if (e == hipSuccess)
+        e = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, s);
+      if (e == hipSuccess)
+        e = pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        e = pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold,
+                               seed, frame, nullptr, nullptr, (uint32_t)(ctx->n_cu * bpc), v, ctx->stack_entries,
+                               min_active, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      t_min = std::min(t_min, ms);
+    }
+    *ms_out = t_min;
+    return e;
+  };
+  // occupancy variant x grid at the current yield threshold, then the threshold
+  float best = INFINITY;
+  int best_v = ctx->retrace_variant, best_b = ctx->retrace_blocks_per_cu, best_m = ctx->walk_min_active;
   const int grids[4] = {2, 4, 8, 16};
   for (int v = 0; v < 4 && err == hipSuccess; ++v) {
     for (int gi = 0; gi < 4 && err == hipSuccess; ++gi) {
-      float t_min = INFINITY;
-      for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
-        err = copy_store(false);
-        if (err == hipSuccess)
-          err = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, nullptr, ctx->stack_moved, s);
-        if (err == hipSuccess)
-          err = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, s);
-        if (err == hipSuccess)
-          err = pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, s);
-        if (err == hipSuccess) err = hipEventRecord(e0, s);
-        if (err == hipSuccess)
-          err = pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold,
-                                   seed, frame, nullptr, nullptr, (uint32_t)(ctx->n_cu * grids[gi]), v,
-                                   ctx->stack_entries, s);
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        t_min = std::min(t_min, ms);
-      }
-      if (t_min < best) {
-        best = t_min;
+      float ms = INFINITY;
+      err = trial(v, grids[gi], best_m, &ms);
+      if (ms < best) {
+        best = ms;
         best_v = v;
         best_b = grids[gi];
       }
+    }
+  }
+  const int mins[6] = {8, 16, 24, 32, 40, 48};
+  for (int mi = 0; mi < 6 && err == hipSuccess; ++mi) {
+    float ms = INFINITY;
+    err = trial(best_v, best_b, mins[mi], &ms);
+    if (ms < best) {
+      best = ms;
+      best_m = mins[mi];
     }
   }
   if (err == hipSuccess) err = copy_store(false);
@@ -1066,6 +1109,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   CK(err);
   ctx->retrace_variant = best_v;
   ctx->retrace_blocks_per_cu = best_b;
+  ctx->walk_min_active = best_m;
   ctx->counts_ready = false;
   if (out_ms) *out_ms = best;
   return PV_OK;
@@ -1118,12 +1162,13 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
   CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, st));
   CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
-  CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_block_cnt, d_stats, b->stack_moved, st));
+  CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_gbase, (int)b->n, b->vw, b->d_block_cnt,
+                       d_stats, b->stack_moved, verify_blocks(ctx), b->d_scan_tmp, st));
   CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, b->d_scan_tmp, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->d_head, b->T, b->seed, 0,
                         b->d_frame, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
-                        b->stack_entries, st));
+                        b->stack_entries, ctx->walk_min_active, st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
   CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, nullptr, b->d_scan_tmp, st));
   CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,
@@ -1151,7 +1196,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
     std::vector<SceneDev> table(n);
     std::vector<uint2> ptiles, otiles;
     std::vector<uint32_t> gbase(n + 1, 0);
-    uint64_t total_paths = 0, counts = 0, cap = 0;
+    uint64_t total_paths = 0, counts = 0, cap = 0, task_cap = 0;
     for (uint32_t i = 0; i < n; ++i) {
       pv_ctx* c = contexts[i];
       const pv_path_store* st = &stores[i];
@@ -1180,6 +1225,8 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       hs.n_blocks = path_blocks(st->n_paths);
       hs.count_base = (uint32_t)counts;
       hs.gpath_base = (uint32_t)total_paths;
+      hs.tile_base = (uint32_t)ptiles.size();
+      hs.task_base = (uint32_t)task_cap;
       table[i] = hs;
       gbase[i] = (uint32_t)total_paths;
       for (uint2 t : make_tiles(i, st->n_paths)) ptiles.push_back(t);
@@ -1187,9 +1234,10 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       total_paths += st->n_paths;
       counts += (uint64_t)hs.n_blocks * st->max_bounces;
       cap += (uint64_t)st->n_paths * st->max_bounces;
+      task_cap += (uint64_t)hs.n_blocks * pv::kBlock * st->max_bounces;
     }
     gbase[n] = (uint32_t)total_paths;
-    if (total_paths >= (1ull << 32) || cap >= (1ull << 32)) {
+    if (total_paths > kMaxPaths || cap >= (1ull << 32) || task_cap >= (1ull << 32)) {
       delete b;
       return fail(ctx, PV_ERR_CAPACITY, "batch too large");
     }
@@ -1206,6 +1254,10 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
               chk(dalloc(A, &b->d_pbase, n + 1)) && chk(dalloc(A, &b->d_frame, 1)) &&
               chk(dalloc(A, &b->d_scan_tmp, pv::scan_tmp_words((uint32_t)std::max<uint64_t>(counts, ptiles.size())))) &&
               chk(dalloc(A, &b->d_out_pos, 3 * cap)) && chk(dalloc(A, &b->d_out_en, 3 * cap)) &&
+              chk(dalloc(A, &b->vw.tmp, task_cap)) && chk(dalloc(A, &b->vw.tasks, task_cap)) &&
+              chk(dalloc(A, &b->vw.tcount, ptiles.size())) && chk(dalloc(A, &b->vw.toff, ptiles.size())) &&
+              chk(dalloc(A, &b->vw.total, 1)) && chk(dalloc(A, &b->vw.first, total_paths)) &&
+              chk(dalloc(A, &b->vw.part, 4 * ptiles.size() + 2 * (size_t)pv::verify_finish_blocks(verify_blocks(ctx)))) &&
               chk(upload(A, &b->d_obj_in, const_cast<const float**>(d_obj_xf), n, s)) &&
               chk(upload(A, &b->d_light_in, const_cast<const float**>(d_light_xf), n, s));
     if (!ok || hipStreamSynchronize(s) != hipSuccess) {

@@ -153,7 +153,24 @@ struct SceneDev {
   uint32_t gpath_base;    // offset of this scene's paths in the work-queue id space
   uint32_t n_blocks;      // path blocks of the bound store
   uint32_t count_base;    // first entry of this scene's (row, block) photon counts
+  uint32_t tile_base;     // first path tile (block of kBlock paths) of this scene
+  uint32_t task_base;     // first entry of this scene's tile regions of verification tasks
   uint32_t* state;        // [1] first-frame flag of the scene
+};
+
+// Verification work lists (device scratch).  A task is one segment whose ray
+// reaches a moved object's box: (global path id << 4) | segment.  Each path
+// tile first writes its tasks into a region of its own; a scan of the
+// per-tile counts and a gather make them one list.  No atomics are needed:
+// device-wide atomics on one word from thousands of blocks serialise.
+struct VerifyWork {
+  uint32_t* tmp;     // tasks by tile: region of a tile = kBlock * B entries
+  uint32_t* tasks;   // compacted tasks
+  uint32_t* tcount;  // [tiles] tasks of each tile
+  uint32_t* toff;    // [tiles] their offsets in the compacted list
+  uint32_t* total;   // [1] tasks in all
+  uint32_t* first;   // [paths] first invalid segment found so far (global path id)
+  uint32_t* part;    // per-block statistics: [scan blocks][4], then [finish blocks][2]
 };
 
 // ---------------------------------------------------------------------------
@@ -174,6 +191,7 @@ __device__ inline float comp(float3 v, int k) { return k == 0 ? v.x : (k == 1 ? 
 // ray / segment query state
 struct Ray {
   float3 o, d, inv;   // origin, direction (not necessarily unit), 1/direction
+  float3 oi;          // -o / d per axis: slab parameters are fma(bound, inv, oi)
   float tmin, tmax;   // open interval of the parameter
   int kx, ky, kz;     // watertight-test axis permutation
   float sx, sy, sz;   // shear constants
@@ -188,6 +206,7 @@ __device__ inline Ray make_ray(float3 o, float3 d, float tmin, float tmax) {
   float dy = fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y);
   float dz = fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z);
   r.inv = f3(1.0f / dx, 1.0f / dy, 1.0f / dz);
+  r.oi = f3(-(o.x * r.inv.x), -(o.y * r.inv.y), -(o.z * r.inv.z));
   r.tmin = tmin;
   r.tmax = tmax;
   // Woop, Benthin, Wald 2013: largest |d| component becomes z
@@ -211,12 +230,15 @@ __device__ inline Ray make_ray(float3 o, float3 d, float tmin, float tmax) {
 }
 
 // Slab test of one box against the ray's current [tmin, tmax]; returns the
-// entry parameter or +inf.
+// entry parameter or +inf.  A slab parameter is one fused multiply-add,
+// bound * (1/d) - o/d; its error (relative 2^-24 of o/d, i.e. about 6e-8 of
+// the origin's coordinates in distance) stays far inside the 1e-6 padding of
+// every stored box, so the test remains conservative.
 __device__ inline float box_entry(float lx, float ly, float lz, float hx, float hy, float hz, const Ray& r,
                                   float tmax) {
-  float tx0 = (lx - r.o.x) * r.inv.x, tx1 = (hx - r.o.x) * r.inv.x;
-  float ty0 = (ly - r.o.y) * r.inv.y, ty1 = (hy - r.o.y) * r.inv.y;
-  float tz0 = (lz - r.o.z) * r.inv.z, tz1 = (hz - r.o.z) * r.inv.z;
+  float tx0 = fmaf(lx, r.inv.x, r.oi.x), tx1 = fmaf(hx, r.inv.x, r.oi.x);
+  float ty0 = fmaf(ly, r.inv.y, r.oi.y), ty1 = fmaf(hy, r.inv.y, r.oi.y);
+  float tz0 = fmaf(lz, r.inv.z, r.oi.z), tz1 = fmaf(hz, r.inv.z, r.oi.z);
   float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
   float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
   return t0 <= t1 ? t0 : __builtin_inff();
@@ -266,21 +288,43 @@ struct Hit {
   uint32_t rec;  // its record in the scene's triangle array
 };
 
-// Depth-first traversal of the scene hierarchy from 'root' (near child
-// first).  any = stop at the first crossing inside the ray's open interval;
-// otherwise the closest crossing.  Returns whether a triangle was crossed.
+// Depth-first walk of the scene hierarchy from a root (near child first), in
+// resumable form for persistent kernels.  any = stop at the first crossing
+// inside the ray's open interval; otherwise the closest crossing.  The state
+// of one lane's query survives between calls, and a call returns as soon as
+// this lane's walk is finished or fewer than 'min_active' lanes of the wave
+// are still walking, so that finished lanes can take new work instead of
+// idling until the longest walk of the wave ends (Aila and Laine 2009,
+// dynamic ray fetch).
+//
 // The inner loop over internal nodes has no branch besides its exit: the far
 // child is always written one slot above the top of the stack and the stack
 // pointer moves by +1 (both children entered), 0 (one) or -1 (none: the top
 // entry, read ahead, becomes the next node).  A sentinel at the bottom ends
 // the walk.
-__device__ inline bool traverse(const PV_GLOBAL Node* __restrict__ nodes, const PV_GLOBAL Tri* __restrict__ tris,
-                                int32_t root, const Ray& r, bool any, StackCol col, Hit* h) {
-  float tb = r.tmax;
-  uint32_t gid = kHitNone, rec = 0;
+struct Walk {
+  int32_t cur;    // next node or leaf; kRootNone once finished
+  int sp;         // stack entries in use
+  float tb;       // closest crossing so far (the ray's tmax initially)
+  uint32_t gid;   // its global triangle id, kHitNone when none
+  uint32_t rec;   // its record in the scene's triangle array
+};
+
+__device__ inline void walk_start(Walk& w, int32_t root, float tmax, StackCol col) {
   col[0] = kRootNone;
-  int sp = 1;  // entries in use
-  int32_t cur = root;
+  w.sp = 1;
+  w.cur = root;
+  w.tb = tmax;
+  w.gid = kHitNone;
+  w.rec = 0;
+}
+
+__device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const PV_GLOBAL Tri* __restrict__ tris,
+                                const Ray& r, bool any, StackCol col, Walk& w, int min_active) {
+  int32_t cur = w.cur;
+  int sp = w.sp;
+  float tb = w.tb;
+  uint32_t gid = w.gid, rec = w.rec;
   while (cur != kRootNone) {
     while (cur >= 0) {
       const int32_t top = col[(sp - 1) * kBlock];
@@ -288,7 +332,7 @@ __device__ inline bool traverse(const PV_GLOBAL Node* __restrict__ nodes, const 
       const float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, tb);
       const float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, tb);
       const bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
-      const bool near0 = e0 <= e1;  // a missed child has entry +inf
+      const bool near0 = e0 <= e1;
       col[sp * kBlock] = near0 ? nd.d.y : nd.d.x;
       sp += (h0 && h1) ? 1 : ((h0 || h1) ? 0 : -1);
       cur = (h0 || h1) ? (near0 ? nd.d.x : nd.d.y) : top;
@@ -299,21 +343,21 @@ __device__ inline bool traverse(const PV_GLOBAL Node* __restrict__ nodes, const 
     for (uint32_t i = f; i < f + n; ++i) {
       const Tri tr = tris[i];
       float t;
-      // tri_hit only reports crossings strictly closer than tb
       const bool hit = tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), tb, &t);
       tb = hit ? t : tb;
       gid = hit ? __float_as_uint(tr.t0.w) : gid;
       rec = hit ? i : rec;
       found |= hit;
     }
-    if (found && any) break;
     --sp;
-    cur = col[sp * kBlock];
+    cur = (found && any) ? kRootNone : col[sp * kBlock];
+    if (cur != kRootNone && __popcll(__ballot(1)) < min_active) break;
   }
-  h->t = tb;
-  h->gid = gid;
-  h->rec = rec;
-  return gid != kHitNone;
+  w.cur = cur;
+  w.sp = sp;
+  w.tb = tb;
+  w.gid = gid;
+  w.rec = rec;
 }
 
 // ---------------------------------------------------------------------------

@@ -258,32 +258,50 @@ __global__ void k_build_top(SceneDev* scenes) {
 // ---------------------------------------------------------------------------
 // verification (Sections 3.1 and 3.2)
 
+// Moved objects of a scene in LDS: box corners with the object's global
+// triangle id range in the w components (lo.w = first id, hi.w = count).
 struct MovedSet {
   int n;
-  float box[PV_MAX_OBJECTS][6];
-  uint32_t glo[PV_MAX_OBJECTS], ghi[PV_MAX_OBJECTS];
+  float4 lo[PV_MAX_OBJECTS], hi[PV_MAX_OBJECTS];
 };
 
+// the moved objects of the scene, compacted in object order by the first wave
+// (at most PV_MAX_OBJECTS = 64 objects: one lane each)
 __device__ inline void load_moved(const SceneDev& S, MovedSet& M) {
-  if (threadIdx.x == 0) {
-    int n = 0;
-    for (uint32_t o = 0; o < S.n_obj; ++o) {
-      if (!G(S.obj_moved)[o]) continue;
+  static_assert(PV_MAX_OBJECTS <= 64, "one lane per object");
+  if (threadIdx.x < 64) {
+    const uint32_t o = threadIdx.x;
+    const bool mv = o < S.n_obj && G(S.obj_moved)[o] != 0;
+    const uint64_t m = __ballot(mv);
+    if (mv) {
+      const uint32_t i = (uint32_t)__popcll(m & lanemask_lt());
       const ObjDev ob = G(S.objs)[o];
-      for (int k = 0; k < 6; ++k) M.box[n][k] = G(S.obj_aabb)[6 * o + k];
-      M.glo[n] = ob.gbase;
-      M.ghi[n] = ob.gbase + ob.n_tris;
-      ++n;
+      const PV_GLOBAL float* b = G(S.obj_aabb) + 6 * o;
+      M.lo[i] = make_float4(b[0], b[1], b[2], __uint_as_float(ob.gbase));
+      M.hi[i] = make_float4(b[3], b[4], b[5], __uint_as_float(ob.n_tris));
     }
-    M.n = n;
+    if (o == 0) M.n = (int)__popcll(m);
   }
   __syncthreads();
 }
 
+// whether a stored hit id lies on a moved object (no early exit: the loop
+// count is uniform over the block)
 __device__ inline bool on_moved(const MovedSet& M, uint32_t hit) {
+  bool mv = false;
   for (int i = 0; i < M.n; ++i)
-    if (hit >= M.glo[i] && hit < M.ghi[i]) return true;
-  return false;
+    mv |= hit - __float_as_uint(M.lo[i].w) < __float_as_uint(M.hi[i].w);
+  return mv;
+}
+
+// whether a ray reaches any moved object's box within its interval
+__device__ inline bool reaches_moved_box(const MovedSet& M, const Ray& r) {
+  bool h = false;
+  for (int i = 0; i < M.n; ++i) {
+    const float4 lo = M.lo[i], hi = M.hi[i];
+    h |= box_entry(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, r, r.tmax) != __builtin_inff();
+  }
+  return h;
 }
 
 __device__ inline Ray segment_ray(float3 a, float3 b, float eps) {
@@ -324,26 +342,44 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
   return true;
 }
 
-// Three phases per block of kBlock paths:
-//  A (coalesced, lane per path): origin update for moved lights, endpoint
-//    test, and one bit per segment whose ray reaches a moved object's box;
-//    scanning stops at the first segment whose end photon is on a moved
-//    object (that segment is invalid whatever lies before it);
-//  B (block-cooperative): the box-hit segments of all paths of the block are
-//    traversed as independent tasks spread over all threads, each blocked
-//    segment lowering its path's first-invalid index (LDS atomic minimum);
-//  C (lane per path): the information word.
+// scene of a global path id: gbase[s] <= gp < gbase[s + 1]
+__device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_t gp) {
+  int lo = 0, hi = n_scenes;  // gbase[s] <= gp < gbase[s+1]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (gbase[mid] <= gp)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
+// Verification runs as a short chain of kernels without atomics.
+//  k_verify_scan (coalesced, lane per path, no traversal): origin update for
+//    moved lights, the bounce rows read up front, endpoint test, and one task
+//    per segment whose ray reaches a moved object's box, written into the
+//    tile's own region; scanning stops at the first segment whose end photon
+//    is on a moved object (that segment is invalid whatever lies before it).
+//    Writes the information word as if no task were blocked (final for paths
+//    without tasks).
+//  scan of the per-tile task counts, k_verify_gather: one compact task list.
+//  k_verify_trace: the tasks as independent any-hit queries against the
+//    moved objects, every lane busy; a blocked segment lowers its path's
+//    first invalid segment (atomic minimum on that path's own word).
+//  k_verify_finish: information words of the paths with tasks.
+//  k_replace_count: replace bits per tile for the work queue.
 // The result equals the in-order test of Section 3.2: the first invalid
 // segment is the minimum over blocked segments and the first moved endpoint.
-__global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
-                                                   uint32_t* __restrict__ block_cnt, pv_stats* stats) {
-  extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
+
+constexpr int kPreRows = 8;  // bounce rows a lane loads before testing
+
+__global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restrict__ scenes,
+                                                        const uint2* __restrict__ tiles, VerifyWork W,
+                                                        pv_stats* stats) {
   __shared__ MovedSet M;
   __shared__ unsigned long long sred[kBlock / 64];
-  __shared__ uint16_t task[kBlock * PV_MAX_BOUNCES];
-  __shared__ uint32_t first_bad[kBlock];
-  __shared__ float sorig[3][kBlock];
-  __shared__ uint32_t wtasks[kBlock / 64];
+  __shared__ uint32_t swt[kBlock / 64];
   uint2 tile = tiles[blockIdx.x];
   const SceneDev& S = scenes[tile.x];
   load_moved(S, M);
@@ -352,7 +388,6 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
   const bool active = p < S.n_paths;
   const size_t stride = S.stride;
   uint32_t n = 0, cell = 0, cap = 0, mask = 0, lost = 0;
-  // ---- phase A
   if (active) {
     const PV_GLOBAL float4* pos = G(S.pos);
     PV_GLOBAL float* org = G(S.origin);
@@ -360,13 +395,20 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
     n = min(info_nseg(w), S.B);
     cell = info_cell(w);
     cap = n;
+    // the path's rows (up to kPreRows) are all requested before the first
+    // is used, so their loads are in flight together
+    float4 rows[kPreRows];
+    const uint32_t nload = M.n > 0 ? n : min(n, 1u);  // the light update needs the first hit only
+#pragma unroll
+    for (int j = 0; j < kPreRows; ++j) {
+      rows[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if ((uint32_t)j < nload) rows[j] = pos[(size_t)j * stride + p];
+    }
     float3 a = f3(org[p], org[stride + p], org[2 * stride + p]);
-    float4 row = make_float4(0, 0, 0, 0);
-    if (n > 0) row = pos[p];
     int l = light_of(S, p);
     if (l >= 0 && G(S.light_moved)[l]) {
       float3 na;
-      if (n > 0 && light_update(S, l, a, xyz(row), &na)) {
+      if (n > 0 && light_update(S, l, a, xyz(rows[0]), &na)) {
         a = na;
         org[p] = na.x;
         org[stride + p] = na.y;
@@ -376,92 +418,240 @@ __global__ __launch_bounds__(kBlock) void k_verify(const SceneDev* __restrict__ 
         cap = 0;
       }
     }
-    sorig[0][tid] = a.x;
-    sorig[1][tid] = a.y;
-    sorig[2][tid] = a.z;
     if (!lost && M.n > 0) {
-      for (uint32_t j = 0; j < n; ++j) {
-        if (j > 0) row = pos[j * stride + p];
-        if (on_moved(M, __float_as_uint(row.w))) {
-          cap = j;
-          break;
+      // every segment of the path is tested (no early exit); the first
+      // segment whose end photon lies on a moved object caps the scan
+      uint32_t first_mv = n;
+#pragma unroll
+      for (int j = 0; j < kPreRows; ++j) {
+        if ((uint32_t)j < n) {
+          const float4 row = rows[j];
+          const float3 b = xyz(row);
+          if (on_moved(M, __float_as_uint(row.w))) first_mv = min(first_mv, (uint32_t)j);
+          if (reaches_moved_box(M, segment_ray(a, b, S.eps_end))) mask |= 1u << j;
+          a = b;
         }
-        float3 b = xyz(row);
-        Ray r = segment_ray(a, b, S.eps_end);
-        for (int i = 0; i < M.n; ++i) {
-          const float* bx = M.box[i];
-          if (box_entry(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], r, r.tmax) != __builtin_inff()) {
-            mask |= 1u << j;
-            break;
-          }
-        }
+      }
+      for (uint32_t j = kPreRows; j < n; ++j) {
+        const float4 row = pos[(size_t)j * stride + p];
+        const float3 b = xyz(row);
+        if (on_moved(M, __float_as_uint(row.w))) first_mv = min(first_mv, j);
+        if (reaches_moved_box(M, segment_ray(a, b, S.eps_end))) mask |= 1u << j;
         a = b;
       }
+      cap = first_mv;
+      mask &= (1u << cap) - 1u;
     }
   }
-  first_bad[tid] = cap;
-  // ---- task list: block-wide exclusive prefix of the per-path task counts
-  uint32_t nt = (uint32_t)__popc(mask);
-  uint32_t x = nt;
+  // ---- tasks into the tile's region, in lane order
+  const uint32_t nt = (uint32_t)__popc(mask);
+  uint32_t x = nt;  // inclusive wave prefix of the task counts
   for (int o = 1; o < 64; o <<= 1) {
     uint32_t y = __shfl_up(x, o, 64);
     if ((int)lane_id() >= o) x += y;
   }
-  if (lane_id() == 63) wtasks[tid >> 6] = x;
+  const uint32_t wave = tid >> 6;
+  if (lane_id() == 63) swt[wave] = x;
   __syncthreads();
-  uint32_t wbase = 0, total = 0;
+  uint32_t before = 0, all = 0;
   for (uint32_t w = 0; w < kBlock / 64; ++w) {
-    if (w < (tid >> 6)) wbase += wtasks[w];
-    total += wtasks[w];
+    before += w < wave ? swt[w] : 0u;
+    all += swt[w];
   }
-  uint32_t pos = wbase + x - nt;
-  for (uint32_t m = mask; m; m &= m - 1) task[pos++] = (uint16_t)((tid << 4) | (uint32_t)(__ffs(m) - 1));
-  __syncthreads();
-  // ---- phase B: every thread traverses tasks of any path of the block
-  const StackCol col = (StackCol)(sstack + tid);
-  const PV_GLOBAL Node* nodes = G(S.nodes);
-  const PV_GLOBAL Tri* tris = G(S.tris);
-  const int32_t moved_root = G(S.top)[1];
-  for (uint32_t t = tid; t < total; t += kBlock) {
-    uint32_t tk = task[t], owner = tk >> 4, j = tk & 15u;
-    if (j >= first_bad[owner]) continue;  // an earlier segment already failed
-    uint32_t q = tile.y + owner;
-    float3 a = j == 0 ? f3(sorig[0][owner], sorig[1][owner], sorig[2][owner])
-                      : xyz(G(S.pos)[(size_t)(j - 1) * stride + q]);
-    float3 b = xyz(G(S.pos)[(size_t)j * stride + q]);
-    Ray r = segment_ray(a, b, S.eps_end);
-    Hit h;
-    if (traverse(nodes, tris, moved_root, r, true, col, &h)) atomicMin(&first_bad[owner], j);
+  if (tid == 0) W.tcount[blockIdx.x] = all;
+  if (nt > 0) {
+    const uint32_t gp = S.gpath_base + p;
+    W.first[gp] = cap;
+    PV_GLOBAL uint32_t* region =
+        G(W.tmp) + S.task_base + (size_t)(blockIdx.x - S.tile_base) * kBlock * S.B;
+    uint32_t t = before + x - nt;
+    for (uint32_t m = mask; m; m &= m - 1) region[t++] = (gp << 4) | (uint32_t)(__ffs(m) - 1);
   }
-  __syncthreads();
-  // ---- phase C
-  uint32_t ex = 0, repl = 0;
+  // ---- information word as if no task were blocked
+  uint32_t ex = 0, inv = 0;
   if (active) {
-    uint32_t k = first_bad[tid];
     uint32_t out;
     if (lost) {
       out = info_pack(cell, n, 0, 1, 0);
-    } else if (k < n) {
-      out = info_pack(cell, n, k, 1, 1);
-      ex = k + 1;
+    } else if (cap < n) {
+      out = info_pack(cell, n, cap, 1, 1);
+      ex = cap + 1;
     } else {
       out = info_pack(cell, n, 0, 0, 0);
       ex = n;
     }
     G(S.info)[p] = out;
-    repl = info_replace(out);
+    inv = info_replace(out);
+    if (nt > 0) ex = inv = 0;  // counted by k_verify_finish
   }
-  unsigned long long nrep = block_sum_u64(repl, sred);
-  if (tid == 0) block_cnt[blockIdx.x] = (uint32_t)nrep;
+  if (stats) {
+    // per-block counts (at most kBlock * 15 each) go to their own slots and
+    // are summed by k_verify_stats: one counter word shared by every block
+    // would serialise thousands of atomics
+    unsigned long long nex = block_sum_u64(ex, sred);
+    unsigned long long ninv = block_sum_u64(inv, sred);
+    unsigned long long nlost = block_sum_u64(lost, sred);
+    unsigned long long ntask = block_sum_u64(nt, sred);
+    if (tid == 0) {
+      uint32_t* o = W.part + 4 * (size_t)blockIdx.x;
+      o[0] = (uint32_t)nex;
+      o[1] = (uint32_t)ninv;
+      o[2] = (uint32_t)nlost;
+      o[3] = (uint32_t)ntask;
+    }
+  }
+}
+
+// one block per path tile: its tasks to their place in the compacted list
+__global__ __launch_bounds__(kBlock) void k_verify_gather(const SceneDev* __restrict__ scenes,
+                                                          const uint2* __restrict__ tiles, VerifyWork W) {
+  const SceneDev& S = scenes[tiles[blockIdx.x].x];
+  const uint32_t n = W.tcount[blockIdx.x];
+  const PV_GLOBAL uint32_t* src = G(W.tmp) + S.task_base + (size_t)(blockIdx.x - S.tile_base) * kBlock * S.B;
+  PV_GLOBAL uint32_t* dst = G(W.tasks) + W.toff[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
+}
+
+// Persistent: each wave owns a contiguous range of the task list; a lane
+// whose walk has finished takes the next task of the range while the other
+// lanes of its wave continue.
+constexpr int kMinActive = 16;
+
+template <bool kSingle>
+__global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restrict__ scenes,
+                                                         const uint32_t* __restrict__ gbase, int n_scenes,
+                                                         VerifyWork W) {
+  extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
+  const StackCol col = (StackCol)(sstack + threadIdx.x);
+  const uint32_t total = *W.total;
+  const uint32_t n_waves = gridDim.x * (kBlock / 64);
+  const uint32_t chunk = (total + n_waves - 1) / n_waves;
+  const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  uint32_t next = min(total, wave * chunk);  // wave-uniform cursor
+  const uint32_t end = min(total, next + chunk);
+  Walk w;
+  w.cur = kRootNone;
+  Ray r;
+  uint32_t gp = 0, j = 0;
+  bool busy = false, drained = false;
+  const SceneDev* S = scenes;
+  while (true) {
+    // lanes without a task take the next ones; a task whose path already
+    // failed at an earlier segment is dropped (the minimum only decreases)
+    const bool want = !busy && !drained;
+    const uint64_t m = __ballot(want);
+    if (m) {
+      const uint32_t base = next;
+      next += (uint32_t)__popcll(m);
+      if (want) {
+        const uint32_t t = base + (uint32_t)__popcll(m & lanemask_lt());
+        if (t >= end) {
+          drained = true;
+        } else {
+          const uint32_t tk = G(W.tasks)[t];
+          gp = tk >> 4;
+          j = tk & 15u;
+          if (j < __hip_atomic_load(&W.first[gp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            S = scenes + (kSingle ? 0u : scene_of(gbase, n_scenes, gp));
+            const uint32_t q = gp - S->gpath_base;
+            const size_t stride = S->stride;
+            const PV_GLOBAL float* org = G(S->origin);
+            const float3 a = j == 0 ? f3(org[q], org[stride + q], org[2 * stride + q])
+                                    : xyz(G(S->pos)[(size_t)(j - 1) * stride + q]);
+            const float3 b = xyz(G(S->pos)[(size_t)j * stride + q]);
+            r = segment_ray(a, b, S->eps_end);
+            walk_start(w, G(S->top)[1], r.tmax, col);
+            busy = true;
+          }
+        }
+      }
+    }
+    if (__ballot(busy) == 0) {
+      if (__ballot(!drained) == 0) break;
+      continue;
+    }
+    if (busy) {
+      walk_run(G(S->nodes), G(S->tris), r, true, col, w, kMinActive);
+      if (w.cur == kRootNone) {
+        if (w.gid != kHitNone) atomicMin(&W.first[gp], j);
+        busy = false;
+      }
+    }
+  }
+}
+
+// The tasks of a path are adjacent in the list: the thread holding a path's
+// first task writes its information word.
+template <bool kSingle>
+__global__ __launch_bounds__(kBlock) void k_verify_finish(const SceneDev* __restrict__ scenes,
+                                                          const uint32_t* __restrict__ gbase, int n_scenes,
+                                                          VerifyWork W, uint32_t n_scan_blocks, pv_stats* stats) {
+  __shared__ unsigned long long sred[kBlock / 64];
+  const uint32_t total = *W.total;
+  uint32_t ex = 0, inv = 0;
+  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
+    const uint32_t gp = G(W.tasks)[t] >> 4;
+    if (t > 0 && (G(W.tasks)[t - 1] >> 4) == gp) continue;
+    uint32_t s = 0;
+    if (!kSingle) s = scene_of(gbase, n_scenes, gp);
+    const SceneDev& S = scenes[s];
+    const uint32_t q = gp - S.gpath_base;
+    const uint32_t w = G(S.info)[q];  // as written by the scan
+    const uint32_t n = info_nseg(w), k = G(W.first)[gp];
+    if (k < n) {
+      G(S.info)[q] = info_pack(info_cell(w), n, k, 1, 1);
+      ex += k + 1;
+      inv += 1;
+    } else {
+      ex += n;
+    }
+  }
   if (stats) {
     unsigned long long nex = block_sum_u64(ex, sred);
-    unsigned long long nlost = block_sum_u64(lost, sred);
-    if (tid == 0) {
-      atomicAdd(&stats->segments_examined, nex);
-      atomicAdd(&stats->paths_invalid, nrep);
-      atomicAdd(&stats->paths_light_lost, nlost);
-      atomicAdd(&stats->verify_box_hits, (unsigned long long)total);
+    unsigned long long ninv = block_sum_u64(inv, sred);
+    if (threadIdx.x == 0) {
+      uint32_t* o = W.part + 4 * (size_t)n_scan_blocks + 2 * (size_t)blockIdx.x;
+      o[0] = (uint32_t)min(nex, 0xffffffffull);
+      o[1] = (uint32_t)ninv;
     }
+  }
+}
+
+// replace bits per path tile (the work queue's block counts)
+__global__ __launch_bounds__(kBlock) void k_replace_count(const SceneDev* __restrict__ scenes,
+                                                          const uint2* __restrict__ tiles,
+                                                          uint32_t* __restrict__ block_cnt) {
+  __shared__ unsigned long long sred[kBlock / 64];
+  const uint2 tile = tiles[blockIdx.x];
+  const SceneDev& S = scenes[tile.x];
+  const uint32_t p = tile.y + threadIdx.x;
+  const uint32_t rep = p < S.n_paths ? info_replace(G(S.info)[p]) : 0u;
+  const unsigned long long n = block_sum_u64(rep, sred);
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = (uint32_t)n;
+}
+
+// sum of the per-block statistics of one verification call into pv_stats
+__global__ __launch_bounds__(1024) void k_verify_stats(const uint32_t* __restrict__ part, uint32_t n_scan,
+                                                       uint32_t n_fin, pv_stats* stats) {
+  __shared__ unsigned long long sh[4][1024 / 64];
+  unsigned long long a[4] = {0, 0, 0, 0};
+  for (uint32_t b = threadIdx.x; b < n_scan; b += blockDim.x)
+    for (int k = 0; k < 4; ++k) a[k] += part[4 * (size_t)b + k];
+  for (uint32_t b = threadIdx.x; b < n_fin; b += blockDim.x)
+    for (int k = 0; k < 2; ++k) a[k] += part[4 * (size_t)n_scan + 2 * (size_t)b + k];
+  for (int k = 0; k < 4; ++k) {
+    for (int o = 32; o > 0; o >>= 1) a[k] += __shfl_down(a[k], o, 64);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = a[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k)
+      for (uint32_t w = 0; w < blockDim.x / 64; ++w) t[k] += sh[k][w];
+    atomicAdd(&stats->segments_examined, t[0]);
+    atomicAdd(&stats->paths_invalid, t[1]);
+    atomicAdd(&stats->paths_light_lost, t[2]);
+    atomicAdd(&stats->verify_box_hits, t[3]);
   }
 }
 
@@ -659,17 +849,6 @@ __device__ inline void clear_rows(const SceneDev& S, uint32_t p, uint32_t from) 
 
 __device__ inline float3 normalize3(float3 v) { return mul(v, 1.0f / length(v)); }
 
-__device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_t gp) {
-  int lo = 0, hi = n_scenes;  // gbase[s] <= gp < gbase[s+1]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (gbase[mid] <= gp)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return (uint32_t)lo;
-}
 
 // Re-trace state machine: every iteration each busy lane issues exactly one
 // query (closest hit over the scene, or any hit against the moved objects),
@@ -761,7 +940,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
                                                     int n_scenes, const uint32_t* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount, uint32_t* head, float T,
                                                     uint64_t seed, uint32_t frame_arg, const uint32_t* frame_ptr,
-                                                    pv_stats* stats) {
+                                                    pv_stats* stats, int min_active) {
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   __shared__ unsigned long long sred[kBlock / 64];
   const StackCol col = (StackCol)(sstack + threadIdx.x);
@@ -772,6 +951,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
   L.S = scenes;
   L.mode = ST_IDLE;
   L.p = 0;
+  Ray r;             // the lane's current query
+  Walk wk;           // its walk through the hierarchy
+  wk.cur = kRootNone;
+  bool tracing = false, any = false;
   while (true) {
     // refill idle lanes from the queue: one atomic per wave
     bool want = L.mode == ST_IDLE;
@@ -804,12 +987,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
       continue;
     }
     const SceneDev& S = kSingle ? scenes[0] : *L.S;
-    bool busy = L.mode != ST_IDLE && L.mode != ST_END;
-    // ---- build this lane's query
-    bool any = false;
-    float3 qo = L.x, qd = L.w, wn = L.w, xa, xb;
-    float tmin = S.eps_end, tmax = kTFar;
-    if (busy) {
+    const bool busy = L.mode != ST_IDLE && L.mode != ST_END;
+    // ---- a lane with a path and no walk in progress starts its next query
+    if (busy && !tracing) {
+      any = false;
+      float3 qo = L.x, qd = L.w;
+      float tmin = S.eps_end, tmax = kTFar;
       if (L.mode == ST_TAIL) {
         float3 nrm = dot(L.ntri, L.w) > 0.0f ? mul(L.ntri, -1.0f) : L.ntri;
         float u[4];
@@ -817,36 +1000,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         float3 lc = cosine_local(u[0], u[1]);
         float3 tt, bb;
         onb(nrm, &tt, &bb);
-        wn = add(add(mul(tt, lc.x), mul(bb, lc.y)), mul(nrm, lc.z));
-        qd = wn;
+        qd = add(add(mul(tt, lc.x), mul(bb, lc.y)), mul(nrm, lc.z));
       } else if (L.mode == ST_WCHECK || L.mode == ST_WTRACE || L.mode == ST_WSKIP) {
         uint32_t sj = L.mode == ST_WSKIP ? L.j + 1 : L.j;
-        xa = vertex(S, L.p, sj);
-        xb = vertex(S, L.p, sj + 1);
+        const float3 xa = vertex(S, L.p, sj), xb = vertex(S, L.p, sj + 1);
         if (L.mode == ST_WCHECK && on_moved_obj(S, vertex_hit(S, L.p, sj + 1))) L.mode = ST_WTRACE;
+        qo = xa;
         if (L.mode == ST_WTRACE) {
-          qo = xa;
           qd = normalize3(sub(xb, xa));
         } else {
           // any hit of the segment xa -> xb against the moved objects
           any = true;
-          qo = xa;
           qd = sub(xb, xa);
           float len = length(qd);
           tmin = len > 0.0f ? S.eps_end / len : 1.0f;
           tmax = 1.0f - tmin;
         }
       }
-    }
-    Hit h;
-    h.gid = kHitNone;
-    if (busy) {
-      Ray r = make_ray(qo, qd, tmin, tmax);
-      const int32_t root = G(S.top)[any ? 1 : 0];
-      traverse(G(S.nodes), G(S.tris), root, r, any, col, &h);
+      r = make_ray(qo, qd, tmin, tmax);
+      walk_start(wk, G(S.top)[any ? 1 : 0], tmax, col);
+      tracing = true;
       if (!any) ++n_rays;
     }
-    if (!busy) continue;
+    if (tracing) walk_run(G(S.nodes), G(S.tris), r, any, col, wk, min_active);
+    if (!tracing || wk.cur != kRootNone) continue;
+    // ---- the walk is finished: its query's ray is r (origin xa of a walk
+    // segment, direction of a sampled bounce)
+    tracing = false;
+    Hit h;
+    h.t = wk.tb;
+    h.gid = wk.gid;
+    h.rec = wk.rec;
+    const float3 wn = r.d, qd = r.d, xa = r.o;
     // ---- advance the state machine with the result
     const bool hit = h.gid != kHitNone;
     switch (L.mode) {
@@ -941,7 +1126,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
           break;
         }
         ++n_acc;
-        float dist = length(sub(hp, xb));
+        float dist = length(sub(hp, vertex(S, L.p, L.j + 1)));
         if (dist <= S.eps_close && !on_moved_obj(S, h.gid) && !on_moved_obj(S, vertex_hit(S, L.p, L.j + 1)) &&
             !on_moved_obj(S, vertex_hit(S, L.p, L.j + 2))) {
           L.hp = hp;
@@ -1158,11 +1343,27 @@ hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s) {
 
 static size_t stack_bytes(uint32_t entries) { return (size_t)entries * kBlock * sizeof(int32_t); }
 
-hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
-                         pv_stats* stats, uint32_t stack, hipStream_t s) {
+uint32_t verify_finish_blocks(uint32_t trace_blocks) { return std::max(1u, trace_blocks / 2); }
+
+hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* gbase,
+                         int n_scenes, VerifyWork W, uint32_t* block_cnt, pv_stats* stats, uint32_t stack,
+                         uint32_t trace_blocks, uint32_t* scan_tmp, hipStream_t s) {
   if (!n_tiles) return hipSuccess;
-  if (stack < 2 || stack > (uint32_t)kMaxStack) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_verify, dim3(n_tiles), dim3(kBlock), stack_bytes(stack), s, scenes, tiles, block_cnt, stats);
+  if (stack < 2 || stack > (uint32_t)kMaxStack || trace_blocks == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_verify_scan, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W, stats);
+  hipError_t e = launch_scan(W.tcount, W.toff, n_tiles, W.total, nullptr, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_verify_gather, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W);
+  const dim3 gt(trace_blocks), gf(verify_finish_blocks(trace_blocks));
+  if (n_scenes == 1) {
+    hipLaunchKernelGGL(k_verify_trace<true>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W);
+    hipLaunchKernelGGL(k_verify_finish<true>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, n_tiles, stats);
+  } else {
+    hipLaunchKernelGGL(k_verify_trace<false>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W);
+    hipLaunchKernelGGL(k_verify_finish<false>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, n_tiles, stats);
+  }
+  hipLaunchKernelGGL(k_replace_count, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, block_cnt);
+  if (stats) hipLaunchKernelGGL(k_verify_stats, dim3(1), dim3(1024), 0, s, W.part, n_tiles, gf.x, stats);
   return hipGetLastError();
 }
 
@@ -1201,23 +1402,23 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
 template <bool kSingle>
 static void retrace_variant(int v, dim3 g, size_t lds, hipStream_t s, const SceneDev* scenes, const uint32_t* gbase, int n_scenes,
                             const uint32_t* queue, const uint32_t* qcount, uint32_t* head, float T, uint64_t seed,
-                            uint32_t frame, const uint32_t* frame_ptr, pv_stats* stats) {
+                            uint32_t frame, const uint32_t* frame_ptr, pv_stats* stats, int min_active) {
   switch (v) {
     case 1:
       hipLaunchKernelGGL((k_retrace<kSingle, 5>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
-                         T, seed, frame, frame_ptr, stats);
+                         T, seed, frame, frame_ptr, stats, min_active);
       break;
     case 2:
       hipLaunchKernelGGL((k_retrace<kSingle, 6>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
-                         T, seed, frame, frame_ptr, stats);
+                         T, seed, frame, frame_ptr, stats, min_active);
       break;
     case 3:
       hipLaunchKernelGGL((k_retrace<kSingle, 8>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
-                         T, seed, frame, frame_ptr, stats);
+                         T, seed, frame, frame_ptr, stats, min_active);
       break;
     default:
       hipLaunchKernelGGL((k_retrace<kSingle, 4>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
-                         T, seed, frame, frame_ptr, stats);
+                         T, seed, frame, frame_ptr, stats, min_active);
       break;
   }
 }
@@ -1225,14 +1426,14 @@ static void retrace_variant(int v, dim3 g, size_t lds, hipStream_t s, const Scen
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
                           const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
-                          hipStream_t s) {
-  if (stack < 2 || stack > (uint32_t)kMaxStack) return hipErrorInvalidValue;
+                          int min_active, hipStream_t s) {
+  if (stack < 2 || stack > (uint32_t)kMaxStack || min_active < 1 || min_active > 64) return hipErrorInvalidValue;
   if (n_scenes == 1)
     retrace_variant<true>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
-                          frame_ptr, stats);
+                          frame_ptr, stats, min_active);
   else
     retrace_variant<false>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
-                           frame_ptr, stats);
+                           frame_ptr, stats, min_active);
   return hipGetLastError();
 }
 

@@ -10,10 +10,18 @@ hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const
                               const float* const* light_in, hipStream_t s);
 hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
 hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s);
-// 'stack': traversal stack entries per lane (stack_entries of the scenes'
-// hierarchy depths, at most kMaxStack)
-hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
-                         pv_stats* stats, uint32_t stack, hipStream_t s);
+// Verification of every path of the tiles: scan, task list, traversal of the
+// box-hit segments, information words of the paths with tasks, per-tile
+// replace counts into block_cnt.  'gbase' / 'n_scenes': scene path ranges
+// (global path ids); 'stack': traversal stack entries per lane (stack_entries
+// of the moved objects' hierarchy depths, at most kMaxStack); 'trace_blocks':
+// grid of the traversal kernel; 'scan_tmp': scan_tmp_words(n_tiles) words.
+hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* gbase,
+                         int n_scenes, VerifyWork W, uint32_t* block_cnt, pv_stats* stats, uint32_t stack,
+                         uint32_t trace_blocks, uint32_t* scan_tmp, hipStream_t s);
+// blocks of the finishing kernel for a traversal grid (sizes W.part: 4 words
+// per path tile plus 2 per finishing block)
+uint32_t verify_finish_blocks(uint32_t trace_blocks);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
                        uint32_t* tile_tmp, hipStream_t s);
 uint32_t scan_tmp_words(uint32_t n);
@@ -24,7 +32,7 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
                           const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
                           const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
-                          hipStream_t s);
+                          int min_active, hipStream_t s);
 hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
                                hipStream_t s);
 hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t B,

@@ -187,13 +187,16 @@ class Context:
         ms = L.autotune(self.ctx, store.cstruct(), float(threshold), int(seed), int(frame))
         return {"retrace_variant": L.get_tuning(self.ctx, L.PV_TUNE_RETRACE_VARIANT),
                 "retrace_blocks_per_cu": L.get_tuning(self.ctx, L.PV_TUNE_RETRACE_BLOCKS_PER_CU),
+                "walk_min_active": L.get_tuning(self.ctx, L.PV_TUNE_WALK_MIN_ACTIVE),
                 "retrace_ms": ms}
 
-    def set_tuning(self, variant=None, blocks_per_cu=None):
+    def set_tuning(self, variant=None, blocks_per_cu=None, walk_min_active=None):
         if variant is not None:
             L.set_tuning(self.ctx, L.PV_TUNE_RETRACE_VARIANT, int(variant))
         if blocks_per_cu is not None:
             L.set_tuning(self.ctx, L.PV_TUNE_RETRACE_BLOCKS_PER_CU, int(blocks_per_cu))
+        if walk_min_active is not None:
+            L.set_tuning(self.ctx, L.PV_TUNE_WALK_MIN_ACTIVE, int(walk_min_active))
 
     def initial_trace(self, store, seed, frame=0, stats=None):
         """Frame-0 photon paths (every path a new light sample)."""

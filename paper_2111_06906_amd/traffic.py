@@ -1,13 +1,13 @@
 """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) into HBM bytes per
-launch of the verify kernel, scaled by what the same counters read for a plain
+verification call (the sum over its kernels), scaled by what the same counters read for a plain
 device-to-device copy of known size, and store them with the hash of the kernel
 sources they were taken on.
 
     python -m paper_2111_06906_amd.traffic <fetch_dir> <write_dir> <copy_MiB> [out.json]
 
 Both runs profile ``bench.py --calib-copy-mib <copy_MiB>``, which enqueues one
-copy of that size before the timed frames.  The first verify launch of a run
-is a warm-up and is dropped.
+copy of that size before the timed frames.  Per kernel the first launch of a
+run is a warm-up and is dropped.
 """
 from __future__ import annotations
 
@@ -54,6 +54,20 @@ def _pick(d, key):
     raise SystemExit("kernel %r not in counter output" % key)
 
 
+def _per_call(d):
+    """Mean over launches (the first, a warm-up, dropped) summed over the
+    kernels of one verification call."""
+    tot, n = 0.0, 0
+    for k, v in d.items():
+        if "k_verify" in k:
+            v = v[1:] or v
+            tot += sum(v) / len(v)
+            n = max(n, len(v))
+    if not n:
+        raise SystemExit("no verification kernels in counter output")
+    return tot, n
+
+
 def summarize(fetch_dir, write_dir, copy_mib):
     fetch = _per_kernel(_rows(fetch_dir), "FETCH_SIZE")
     write = _per_kernel(_rows(write_dir), "WRITE_SIZE")
@@ -61,15 +75,13 @@ def summarize(fetch_dir, write_dir, copy_mib):
     # the largest copy dispatch is the calibration copy
     sf = max(_pick(fetch, "copyBuffer")) / copy_kib
     sw = max(_pick(write, "copyBuffer")) / copy_kib
-    vf = _pick(fetch, "k_verify")
-    vw = _pick(write, "k_verify")
-    vf = vf[1:] or vf
-    vw = vw[1:] or vw
-    fb = sum(vf) / len(vf) * 1024.0 / sf
-    wb = sum(vw) / len(vw) * 1024.0 / sw
-    return {"kernel": "k_verify", "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-            "bytes_per_launch": fb + wb, "copy_scale_fetch": sf, "copy_scale_write": sw,
-            "launches": [len(vf), len(vw)], "calibration": "%g MiB device-to-device copy" % copy_mib,
+    vf, nf = _per_call(fetch)
+    vw, nw = _per_call(write)
+    fb = vf * 1024.0 / sf
+    wb = vw * 1024.0 / sw
+    return {"kernel": "verify (k_verify_begin/scan/trace/finish)", "fetch_bytes_per_launch": fb,
+            "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb, "copy_scale_fetch": sf,
+            "copy_scale_write": sw, "launches": [nf, nw], "calibration": "%g MiB device-to-device copy" % copy_mib,
             "sources_sha1": sources_sha1()}
 
 
