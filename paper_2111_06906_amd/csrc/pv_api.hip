@@ -49,8 +49,11 @@ struct pv_ctx {
   uint32_t* d_state = nullptr; // first-frame flag
   uint2* d_obj_tiles = nullptr;  // (scene, object) for the object update kernel
   uint32_t n_obj_tiles = 0;
+  uint2* d_xf_tiles = nullptr;   // (scene << 8 | object, first triangle) for the transform kernel
+  uint32_t n_xf_tiles = 0;
   const float** d_in_ptrs = nullptr;  // [2]: object / light transform inputs of the frame
   uint32_t n_materials = 0, n_lights = 0, n_objects = 0;
+  std::vector<uint32_t> h_obj_tris;  // triangles per object
   uint32_t stack_entries = 2;  // traversal stack per lane: whole-scene queries
   uint32_t stack_moved = 2;    // traversal stack per lane: queries against the moved objects
   std::vector<uint32_t> h_light_paths;  // filled at binding
@@ -82,8 +85,8 @@ struct pv_batch {
   uint32_t n = 0;
   Alloc mem;
   SceneDev* d_scenes = nullptr;
-  uint2 *d_path_tiles = nullptr, *d_obj_tiles = nullptr;
-  uint32_t n_path_tiles = 0, n_obj_tiles = 0;
+  uint2 *d_path_tiles = nullptr, *d_obj_tiles = nullptr, *d_xf_tiles = nullptr;
+  uint32_t n_path_tiles = 0, n_obj_tiles = 0, n_xf_tiles = 0;
   uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr, *d_head = nullptr,
            *d_gbase = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_ptotal = nullptr, *d_pbase = nullptr,
            *d_frame = nullptr, *d_scan_tmp = nullptr;
@@ -469,6 +472,14 @@ std::vector<uint2> make_tiles(uint32_t scene, uint32_t n) {
 
 uint32_t path_blocks(uint32_t n) { return (n + pv::kBlock - 1) / pv::kBlock; }
 
+// transform tiles of a scene's objects: (scene << 8 | object, first triangle)
+std::vector<uint2> xf_tiles(uint32_t scene, const uint32_t* obj_tris, uint32_t n_objects) {
+  std::vector<uint2> t;
+  for (uint32_t o = 0; o < n_objects; ++o)
+    for (uint32_t f = 0; f < obj_tris[o]; f += pv::kBlock) t.push_back(make_uint2((scene << 8) | o, f));
+  return t;
+}
+
 // grid of the verification traversal kernel (persistent, grid-stride)
 uint32_t verify_blocks(const pv_ctx* ctx) { return (uint32_t)ctx->n_cu * 8u; }
 
@@ -733,7 +744,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     for (uint32_t o = 0; o < d->n_objects; ++o) {
       uint32_t n = d->h_obj_tris[o];
       const float* v = d->h_obj_verts + 9 * (size_t)tri_base;
-      HostBvh hb = build_topology(v, n, 2);
+      HostBvh hb = build_sah(v, n);  // topology in object space, boxes refit each frame
       if (hb.max_depth > kMaxDepth) return fail(ctx, PV_ERR_CAPACITY, "object hierarchy too deep");
       depth = std::max(depth, hb.max_depth);
       obj_depth = std::max(obj_depth, hb.max_depth);
@@ -841,12 +852,16 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     for (uint32_t o = 0; o < d->n_objects; ++o) ot.push_back(make_uint2(0, o));
     CK(upload(A, &ctx->d_obj_tiles, ot.data(), ot.size(), s));
     ctx->n_obj_tiles = (uint32_t)ot.size();
+    std::vector<uint2> xt = xf_tiles(0, d->h_obj_tris, d->n_objects);
+    CK(upload(A, &ctx->d_xf_tiles, xt.data(), xt.size(), s));
+    ctx->n_xf_tiles = (uint32_t)xt.size();
     CK(dalloc(A, &ctx->d_in_ptrs, 2));
     CK(hipStreamSynchronize(s));
     ctx->hs = hs;
     ctx->n_materials = d->n_materials;
     ctx->n_lights = d->n_lights;
     ctx->n_objects = d->n_objects;
+    ctx->h_obj_tris.assign(d->h_obj_tris, d->h_obj_tris + d->n_objects);
     // the top-level trees hold the static root and the objects, median split
     ctx->stack_entries = pv::stack_entries(ceil_log2(d->n_objects + (S ? 1u : 0u)), depth);
     ctx->stack_moved = pv::stack_entries(ceil_log2(d->n_objects), obj_depth);
@@ -927,7 +942,8 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
   const float* in[2] = {d_obj_xf, d_light_xf};
   CK(hipMemcpyAsync(ctx->d_in_ptrs, in, sizeof(in), hipMemcpyHostToDevice, ctx->stream));
   CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->stream));
-  CK(pv::launch_update_objects(ctx->d_scene, ctx->d_obj_tiles, ctx->n_obj_tiles, ctx->stream));
+  CK(pv::launch_update_objects(ctx->d_scene, ctx->d_obj_tiles, ctx->n_obj_tiles, ctx->d_xf_tiles, ctx->n_xf_tiles,
+                               ctx->stream));
   CK(pv::launch_build_top(ctx->d_scene, 1, ctx->stream));
   ctx->frame_started = true;
   return PV_OK;
@@ -1160,7 +1176,7 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   pv_ctx* ctx = b->owner;
   hipStream_t st = b->cap_stream;
   CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
-  CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, st));
+  CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, b->d_xf_tiles, b->n_xf_tiles, st));
   CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_gbase, (int)b->n, b->vw, b->d_block_cnt,
                        d_stats, b->stack_moved, verify_blocks(ctx), b->d_scan_tmp, st));
@@ -1194,7 +1210,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
     b->seed = seed;
     b->retrace_blocks = (uint32_t)ctx->n_cu * 8;
     std::vector<SceneDev> table(n);
-    std::vector<uint2> ptiles, otiles;
+    std::vector<uint2> ptiles, otiles, xtiles;
     std::vector<uint32_t> gbase(n + 1, 0);
     uint64_t total_paths = 0, counts = 0, cap = 0, task_cap = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -1231,6 +1247,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       gbase[i] = (uint32_t)total_paths;
       for (uint2 t : make_tiles(i, st->n_paths)) ptiles.push_back(t);
       for (uint32_t o = 0; o < c->n_objects; ++o) otiles.push_back(make_uint2(i, o));
+      for (uint2 t : xf_tiles(i, c->h_obj_tris.data(), c->n_objects)) xtiles.push_back(t);
       total_paths += st->n_paths;
       counts += (uint64_t)hs.n_blocks * st->max_bounces;
       cap += (uint64_t)st->n_paths * st->max_bounces;
@@ -1246,6 +1263,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
     auto chk = [&](hipError_t e) { return e == hipSuccess; };
     bool ok = chk(upload(A, &b->d_scenes, table.data(), n, s)) && chk(upload(A, &b->d_path_tiles, ptiles.data(), ptiles.size(), s)) &&
               chk(upload(A, &b->d_obj_tiles, otiles.data(), otiles.size(), s)) &&
+              chk(upload(A, &b->d_xf_tiles, xtiles.data(), xtiles.size(), s)) &&
               chk(upload(A, &b->d_gbase, gbase.data(), gbase.size(), s)) &&
               chk(dalloc(A, &b->d_block_cnt, ptiles.size())) && chk(dalloc(A, &b->d_offsets, ptiles.size())) &&
               chk(dalloc(A, &b->d_queue, total_paths)) && chk(dalloc(A, &b->d_qcount, 1)) &&
@@ -1272,6 +1290,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
     }
     b->n_path_tiles = (uint32_t)ptiles.size();
     b->n_obj_tiles = (uint32_t)otiles.size();
+    b->n_xf_tiles = (uint32_t)xtiles.size();
     b->n_counts = (uint32_t)counts;
     b->capacity = (uint32_t)cap;
     *out = b;

@@ -116,14 +116,17 @@ __device__ inline void child_box(const SceneDev& S, int32_t code, float* b) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, const uint2* tiles) {
-  uint2 tile = tiles[blockIdx.x];
-  SceneDev& S = scenes[tile.x];
-  const uint32_t o = tile.y;
+// world-space triangles of moved objects: one thread per triangle; a tile is
+// (scene << 8 | object, first triangle of the object) for kBlock triangles
+__global__ __launch_bounds__(kBlock) void k_transform(SceneDev* scenes, const uint2* tiles) {
+  const uint2 tile = tiles[blockIdx.x];
+  SceneDev& S = scenes[tile.x >> 8];
+  const uint32_t o = tile.x & 0xffu;
   if (!S.obj_moved[o]) return;
   const ObjDev ob = S.objs[o];
-  const float* m = S.obj_xf_cur + 12 * o;
-  for (uint32_t i = threadIdx.x; i < ob.n_tris; i += blockDim.x) {
+  const uint32_t i = tile.y + threadIdx.x;
+  if (i < ob.n_tris) {
+    const float* m = S.obj_xf_cur + 12 * o;
     uint32_t rec = ob.tri_base + i;
     const float* v = S.dlocal + 9 * (size_t)rec;
     float w[9];
@@ -138,7 +141,16 @@ __global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, con
     t.t2 = make_float4(w[6], w[7], w[8], 0.0f);
     S.tris[S.n_static + rec] = t;
   }
-  __syncthreads();
+}
+
+// per moved object, one workgroup: the hierarchy's boxes level by level from
+// the deepest internal nodes up, then the object's box
+__global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, const uint2* tiles) {
+  uint2 tile = tiles[blockIdx.x];
+  SceneDev& S = scenes[tile.x];
+  const uint32_t o = tile.y;
+  if (!S.obj_moved[o]) return;
+  const ObjDev ob = S.objs[o];
   const uint32_t* off = S.dlevel_off + ob.lvl_base;
   for (uint32_t lv = 0; lv < ob.n_levels; ++lv) {
     const uint32_t e = off[lv + 1];
@@ -1329,8 +1341,10 @@ hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const
   return hipGetLastError();
 }
 
-hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s) {
+hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint2* xf_tiles,
+                                 uint32_t n_xf_tiles, hipStream_t s) {
   if (!n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_transform, dim3(n_xf_tiles), dim3(kBlock), 0, s, scenes, xf_tiles);
   hipLaunchKernelGGL(k_update_objects, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles);
   return hipGetLastError();
 }

@@ -8,7 +8,11 @@ namespace pv {
 
 hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
                               const float* const* light_in, hipStream_t s);
-hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, hipStream_t s);
+// moved objects: world triangles (xf_tiles: (scene << 8 | object, first
+// triangle) per kBlock triangles), then their hierarchies' boxes (tiles:
+// (scene, object))
+hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint2* xf_tiles,
+                                 uint32_t n_xf_tiles, hipStream_t s);
 hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s);
 // Verification of every path of the tiles: scan, task list, traversal of the
 // box-hit segments, information words of the paths with tasks, per-tile
