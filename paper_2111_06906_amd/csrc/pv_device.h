@@ -303,57 +303,91 @@ struct Hit {
 // entry, read ahead, becomes the next node).  A sentinel at the bottom ends
 // the walk.
 struct Walk {
-  int32_t cur;    // next node or leaf; kRootNone once finished
+  int32_t cur;    // next node or leaf; kRootNone once the stack is exhausted
+  int32_t leaf;   // a reached leaf whose test is postponed, 0 when none
   int sp;         // stack entries in use
   float tb;       // closest crossing so far (the ray's tmax initially)
   uint32_t gid;   // its global triangle id, kHitNone when none
   uint32_t rec;   // its record in the scene's triangle array
 };
 
+__device__ inline bool is_leaf(int32_t c) { return (uint32_t)c > 0x80000000u; }  // c < 0, c != kRootNone
+
+__device__ inline bool walk_done(const Walk& w) { return w.cur == kRootNone && w.leaf == 0; }
+
 __device__ inline void walk_start(Walk& w, int32_t root, float tmax, StackCol col) {
   col[0] = kRootNone;
   w.sp = 1;
   w.cur = root;
+  w.leaf = 0;
   w.tb = tmax;
   w.gid = kHitNone;
   w.rec = 0;
 }
 
+// Speculative traversal (Aila and Laine 2009): a lane that reaches a leaf
+// while holding none keeps it pending and continues with the next stack
+// entry, until every lane still walking holds a leaf; then the wave tests
+// leaves together.  Leaves are tested in the same depth-first order as
+// without postponement and culling only uses an older (larger) closest
+// distance, so the result is the same.
 __device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const PV_GLOBAL Tri* __restrict__ tris,
                                 const Ray& r, bool any, StackCol col, Walk& w, int min_active) {
-  int32_t cur = w.cur;
+  int32_t cur = w.cur, leaf = w.leaf;
   int sp = w.sp;
   float tb = w.tb;
   uint32_t gid = w.gid, rec = w.rec;
-  while (cur != kRootNone) {
+  while (true) {
     while (cur >= 0) {
       const int32_t top = col[(sp - 1) * kBlock];
       const Node nd = nodes[cur];
       const float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, tb);
       const float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, tb);
       const bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
-      const bool near0 = e0 <= e1;
+      const bool near0 = e0 <= e1;  // a missed child has entry +inf
       col[sp * kBlock] = near0 ? nd.d.y : nd.d.x;
       sp += (h0 && h1) ? 1 : ((h0 || h1) ? 0 : -1);
       cur = (h0 || h1) ? (near0 ? nd.d.x : nd.d.y) : top;
+      // postpone a reached leaf and go on with the next stack entry (sp is 0
+      // only once the sentinel itself was taken: then nothing is postponed)
+      const int32_t next = col[max(sp - 1, 0) * kBlock];
+      const bool post = leaf == 0 && is_leaf(cur);
+      leaf = post ? cur : leaf;
+      cur = post ? next : cur;
+      sp -= post ? 1 : 0;
+      if (__ballot(leaf == 0) == 0) break;  // every lane still here holds a leaf
     }
-    if (cur == kRootNone) break;
-    const uint32_t f = leaf_first(cur), n = leaf_count(cur);
+    if (leaf == 0 && is_leaf(cur)) {
+      leaf = cur;
+      --sp;
+      cur = col[sp * kBlock];
+    }
     bool found = false;
-    for (uint32_t i = f; i < f + n; ++i) {
-      const Tri tr = tris[i];
-      float t;
-      const bool hit = tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), tb, &t);
-      tb = hit ? t : tb;
-      gid = hit ? __float_as_uint(tr.t0.w) : gid;
-      rec = hit ? i : rec;
-      found |= hit;
+    while (leaf != 0) {
+      const uint32_t f = leaf_first(leaf), n = leaf_count(leaf);
+      for (uint32_t i = f; i < f + n; ++i) {
+        const Tri tr = tris[i];
+        float t;
+        const bool hit = tri_hit(r, xyz(tr.t0), xyz(tr.t1), xyz(tr.t2), tb, &t);
+        tb = hit ? t : tb;
+        gid = hit ? __float_as_uint(tr.t0.w) : gid;
+        rec = hit ? i : rec;
+        found |= hit;
+      }
+      // the current entry may itself be a leaf: test it next
+      const bool again = is_leaf(cur) && !(found && any);
+      leaf = again ? cur : 0;
+      if (again) {
+        --sp;
+        cur = col[sp * kBlock];
+      }
     }
-    --sp;
-    cur = (found && any) ? kRootNone : col[sp * kBlock];
-    if (cur != kRootNone && __popcll(__ballot(1)) < min_active) break;
+    if (found && any) cur = kRootNone;
+    if (cur == kRootNone) break;
+    if (__popcll(__ballot(1)) < min_active) break;
   }
   w.cur = cur;
+  w.leaf = leaf;
   w.sp = sp;
   w.tb = tb;
   w.gid = gid;

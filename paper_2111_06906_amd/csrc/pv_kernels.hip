@@ -183,29 +183,53 @@ __global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, con
 
 __global__ void k_build_top(SceneDev* scenes) {
   constexpr int kItems = PV_MAX_OBJECTS + 1;
-  __shared__ float ibox[kItems][6];
+  __shared__ float ibox[2][kItems][6];
+  __shared__ int32_t icode[2][kItems];
+  __shared__ int nitems[2];
   __shared__ float icen[kItems][3];
-  __shared__ int32_t icode[kItems];
   __shared__ uint8_t idx[kItems];
   SceneDev& S = scenes[blockIdx.x];
+  // the items of both trees, one lane per object (compacted by ballot)
+  static_assert(PV_MAX_OBJECTS <= 64, "one lane per object");
+  if (threadIdx.x < 64) {
+    const uint32_t o = threadIdx.x;
+    const int first_obj = S.sroot != kRootNone ? 1 : 0;  // the static root is item 0 of the whole-scene tree
+    const bool have = o < S.n_obj;
+    const bool mv = have && S.obj_moved[o] != 0;
+    const uint64_t mm = __ballot(mv);
+    if (have) {
+      float b[6];
+      for (int k = 0; k < 6; ++k) b[k] = S.obj_aabb[6 * o + k];
+      const int32_t root = S.objs[o].root;
+      for (int k = 0; k < 6; ++k) ibox[0][first_obj + o][k] = b[k];
+      icode[0][first_obj + o] = root;
+      if (mv) {
+        const uint32_t i = (uint32_t)__popcll(mm & ((1ull << o) - 1ull));
+        for (int k = 0; k < 6; ++k) ibox[1][i][k] = b[k];
+        icode[1][i] = root;
+      }
+    }
+    if (o == 0) {
+      if (first_obj) {
+        for (int k = 0; k < 6; ++k) ibox[0][0][k] = S.sbox[k];
+        icode[0][0] = S.sroot;
+      }
+      nitems[0] = first_obj + (int)S.n_obj;
+      nitems[1] = (int)__popcll(mm);
+    }
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   for (int which = 0; which < 2; ++which) {
-    int n = 0;
-    if (which == 0 && S.sroot != kRootNone) {
-      for (int k = 0; k < 6; ++k) ibox[n][k] = S.sbox[k];
-      icode[n++] = S.sroot;
-    }
-    for (uint32_t o = 0; o < S.n_obj; ++o) {
-      if (which == 1 && !S.obj_moved[o]) continue;
-      for (int k = 0; k < 6; ++k) ibox[n][k] = S.obj_aabb[6 * o + k];
-      icode[n++] = S.objs[o].root;
-    }
+    const int n = nitems[which];
+    float(*ib)[6] = ibox[which];
+    const int32_t* ic = icode[which];
     for (int i = 0; i < n; ++i) {
       idx[i] = (uint8_t)i;
-      for (int k = 0; k < 3; ++k) icen[i][k] = 0.5f * (ibox[i][k] + ibox[i][3 + k]);
+      for (int k = 0; k < 3; ++k) icen[i][k] = 0.5f * (ib[i][k] + ib[i][3 + k]);
     }
     const uint32_t first = S.top_base + (uint32_t)which * kTopNodes;
-    int32_t root = n == 0 ? kRootNone : (n == 1 ? icode[0] : (int32_t)first);
+    int32_t root = n == 0 ? kRootNone : (n == 1 ? ic[0] : (int32_t)first);
     if (n >= 2) {
       struct Range {
         uint8_t lo, hi, node;
@@ -245,11 +269,11 @@ __global__ void k_build_top(SceneDev* scenes) {
           }
           for (int i = a; i < b; ++i)
             for (int k = 0; k < 3; ++k) {
-              cb[side][k] = fminf(cb[side][k], ibox[idx[i]][k]);
-              cb[side][3 + k] = fmaxf(cb[side][3 + k], ibox[idx[i]][3 + k]);
+              cb[side][k] = fminf(cb[side][k], ib[idx[i]][k]);
+              cb[side][3 + k] = fmaxf(cb[side][3 + k], ib[idx[i]][3 + k]);
             }
           if (b - a == 1) {
-            ch[side] = icode[idx[a]];
+            ch[side] = ic[idx[a]];
           } else {
             const int id = next++;
             ch[side] = (int32_t)(first + (uint32_t)id);
@@ -543,6 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
   const uint32_t end = min(total, next + chunk);
   Walk w;
   w.cur = kRootNone;
+  w.leaf = 0;
   Ray r;
   uint32_t gp = 0, j = 0;
   bool busy = false, drained = false;
@@ -584,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
     }
     if (busy) {
       walk_run(G(S->nodes), G(S->tris), r, true, col, w, kMinActive);
-      if (w.cur == kRootNone) {
+      if (walk_done(w)) {
         if (w.gid != kHitNone) atomicMin(&W.first[gp], j);
         busy = false;
       }
@@ -966,6 +991,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
   Ray r;             // the lane's current query
   Walk wk;           // its walk through the hierarchy
   wk.cur = kRootNone;
+  wk.leaf = 0;
   bool tracing = false, any = false;
   while (true) {
     // refill idle lanes from the queue: one atomic per wave
@@ -1035,7 +1061,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
       if (!any) ++n_rays;
     }
     if (tracing) walk_run(G(S.nodes), G(S.tris), r, any, col, wk, min_active);
-    if (!tracing || wk.cur != kRootNone) continue;
+    if (!tracing || !walk_done(wk)) continue;
     // ---- the walk is finished: its query's ray is r (origin xa of a walk
     // segment, direction of a sampled bounce)
     tracing = false;
