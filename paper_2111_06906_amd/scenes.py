@@ -220,6 +220,31 @@ def make_tiny(n_paths=16384, max_bounces=3, frames=2, threshold=-1.0, seed=1):
         meta={"static_tris": 10, "dynamic_tris": 12})
 
 
+def make_objects_only(n_paths=4096, max_bounces=4, frames=3, threshold=-1.0, seed=5):
+    """The tiny box as a rigid object that never moves (no static triangles),
+    with the tiny configuration's cube moving inside it."""
+    walls = []
+    walls += _quad([0, 0, 0], [1, 0, 0], [1, 0, 1], [0, 0, 1])      # floor y=0
+    walls += _quad([0, 1, 0], [0, 1, 1], [1, 1, 1], [1, 1, 0])      # ceiling y=1
+    walls += _quad([0, 0, 0], [0, 0, 1], [0, 1, 1], [0, 1, 0])      # left x=0
+    walls += _quad([1, 0, 0], [1, 1, 0], [1, 1, 1], [1, 0, 1])      # right x=1
+    walls += _quad([0, 0, 0], [0, 1, 0], [1, 1, 0], [1, 0, 0])      # back z=0
+    box = _as_f32_tris(walls)
+    cube = _as_f32_tris(_box([-0.1, -0.1, -0.1], [0.1, 0.1, 0.1]))
+    albedo = np.array([[0.7, 0.7, 0.7], [0.5, 0.5, 0.5]], F32)
+    xf = np.stack([np.stack([_xf(np.eye(3), [0, 0, 0]), _xf(np.eye(3), [0.3 + 0.05 * f, 0.5, 0.5])])
+                   for f in range(frames)])
+    lxf = np.stack([_xf(R_DOWN, [0.5, 0.999, 0.5])[None] for _ in range(frames)])
+    return Scene(
+        name="objects_only", static_verts=np.zeros((0, 3, 3), F32), static_mat=np.zeros(0, U32),
+        obj_local=[box, cube], obj_mat=[np.zeros(10, U32), np.ones(12, U32)], obj_xforms=xf.astype(F32),
+        albedo=albedo, light_half=np.array([[0.1, 0.1]], F32),
+        light_power=np.ones((1, 3), F32), light_xforms=lxf.astype(F32),
+        light_paths=np.array([n_paths], np.int64), max_bounces=max_bounces,
+        threshold=threshold, seed=seed,
+        meta={"static_tris": 0, "dynamic_tris": 22})
+
+
 # ----------------------------------------------------------------------------
 # procedural room grids
 

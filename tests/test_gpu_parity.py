@@ -207,6 +207,26 @@ def test_paper_rooms_moving_lights(E):
     _lockstep(E, sc, 3, 0.01, "paper")
 
 
+def test_objects_only_scene(E):
+    # no static triangles: the whole-scene top-level tree holds objects only
+    sc = scenes.make_objects_only(n_paths=4096 + 7, frames=3)
+    _lockstep(E, sc, 3, -1.0, "objects only naive")
+    sc = scenes.make_objects_only(n_paths=4096 + 7, frames=3, threshold=0.01)
+    _lockstep(E, sc, 3, 0.01, "objects only error-based")
+
+
+def test_static_only_scene_moving_lights(E):
+    # no dynamic objects: the moved-object tree is empty, only the lights move
+    sc = scenes.make_rooms("static_only", 2, 2, 5000, 0, (8, 4), 3001, 5, 3, 0.01, 11, lights_move=True)
+    _lockstep(E, sc, 3, 0.01, "static only")
+
+
+def test_sixty_four_objects(E):
+    # the largest object count: deepest top-level tree and traversal stack
+    sc = scenes.make_rooms("many", 3, 3, 20000, 64, (8, 4), 6000 + 5, 7, 3, 0.01, 12, lights_move=True)
+    _lockstep(E, sc, 3, 0.01, "64 objects")
+
+
 # ---------------------------------------------------------------------------
 # differentiation form
 

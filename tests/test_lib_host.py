@@ -67,6 +67,37 @@ def test_declared_symbols_parse():
         assert n in names
 
 
+# traversal stack: 40 entries per lane hold a top-level tree of depth 7 plus
+# a hierarchy of depth 31 (one entry per internal ancestor, the sentinel and
+# the slot above the top)
+MAX_DEPTH = 31
+
+
+def _degenerate(kind, n, rng):
+    """Triangle sets that unbalance a surface-area split."""
+    if kind == "identical":
+        t = np.tile(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), (n, 1, 1))
+    elif kind == "exponential":
+        # centres spread over many orders of magnitude along x
+        x = np.exp(np.linspace(0, 40, n)).astype(np.float64)
+        t = np.zeros((n, 3, 3))
+        t[:, :, 0] = x[:, None]
+        t[:, 1, 1] = 1e-3 * x
+        t[:, 2, 2] = 1e-3 * x
+    else:  # one big triangle among many tiny ones
+        t = rng.uniform(0, 1e-3, (n, 3, 3))
+        t[0] = [[0, 0, 0], [1e3, 0, 0], [0, 1e3, 0]]
+    return np.ascontiguousarray(t, np.float32)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("dist", ["identical", "exponential", "one_big"])
+def test_hierarchy_depth_bound_on_degenerate_inputs(kind, dist):
+    info = L.hierarchy_info(_degenerate(dist, 20000, np.random.default_rng(3)), kind)
+    assert info["valid"]
+    assert info["depth"] <= MAX_DEPTH
+
+
 @pytest.mark.parametrize("make,kind", [("tiny", 0), ("mid", 0), ("mid_obj", 1), ("paper", 0), ("paper_obj", 1)])
 def test_hierarchy_invariants(make, kind):
     from paper_2111_06906_amd import scenes
@@ -82,6 +113,6 @@ def test_hierarchy_invariants(make, kind):
     n = v.shape[0]
     assert info["valid"]
     assert info["nodes"] == info["leaves"] - 1          # full binary tree
-    assert info["depth"] <= 63
+    assert info["depth"] <= MAX_DEPTH
     if kind == 1:
         assert info["leaves"] >= n // 2                  # leaves of at most 2 triangles
