@@ -73,7 +73,8 @@ def batched(args, engine, scenes, torch, np, tuning=None):
     (pc, ps), (bc, bs) = sets
     if tuning:
         for c in pc + bc:
-            c.set_tuning(tuning["retrace_variant"], tuning["retrace_blocks_per_cu"], tuning["walk_min_active"])
+            c.set_tuning(tuning["retrace_variant"], tuning["retrace_blocks_per_cu"], tuning["walk_min_active"],
+                         tuning["verify_blocks_per_cu"], tuning["verify_min_active"])
     caps = [st.n_paths * st.B for st in ps]
     outs = [(torch.empty((c, 3), dtype=torch.float32, device="cuda"),
              torch.empty((c, 3), dtype=torch.float32, device="cuda"),

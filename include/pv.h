@@ -193,19 +193,30 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
  * target of the re-trace kernel (4, 5, 6, 8 waves per SIMD; higher targets
  * trade registers for private-memory spills); PV_TUNE_RETRACE_BLOCKS_PER_CU
  * (1..64): persistent re-trace workgroups per compute unit;
- * PV_TUNE_WALK_MIN_ACTIVE (1..64): a wave's hierarchy walk yields to take new
- * queries once fewer of its 64 lanes are still walking.  Results do not
+ * PV_TUNE_WALK_MIN_ACTIVE (1..64): a wave's re-trace walk yields to take new
+ * queries once fewer of its 64 lanes are still walking;
+ * PV_TUNE_VERIFY_BLOCKS_PER_CU (1..16) and PV_TUNE_VERIFY_MIN_ACTIVE (1..64):
+ * the same two choices for the verification traversal.  Results do not
  * depend on the tuning. */
-enum { PV_TUNE_RETRACE_VARIANT = 0, PV_TUNE_RETRACE_BLOCKS_PER_CU = 1, PV_TUNE_WALK_MIN_ACTIVE = 2 };
+enum {
+  PV_TUNE_RETRACE_VARIANT = 0,
+  PV_TUNE_RETRACE_BLOCKS_PER_CU = 1,
+  PV_TUNE_WALK_MIN_ACTIVE = 2,
+  PV_TUNE_VERIFY_BLOCKS_PER_CU = 3,
+  PV_TUNE_VERIFY_MIN_ACTIVE = 4
+};
 pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value);
 pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
 
 /* Autotuner: with the current frame (after pv_frame_begin) and the given
- * store, time verification + queue + re-trace for every re-trace variant and
- * persistent grid size (2, 4, 8, 16 workgroups per CU) on a snapshot of the
- * store, keep the fastest setting in the context and restore the store.
- * Allocates a temporary copy of the store and synchronises.  *out_ms (host,
- * optional) receives the best re-trace time. */
+ * store, on a snapshot of the store: time verification for every traversal
+ * grid (2, 4, 8, 16 workgroups per CU) and yield threshold (8, 16, 32, 48);
+ * then, after verification and queue building, time the re-trace for every
+ * re-trace variant and persistent grid size (2, 4, 8, 16 workgroups per CU),
+ * then for yield thresholds 8..48.  Keeps the fastest settings in the
+ * context and restores the store.  Allocates a temporary copy of the store
+ * and synchronises.  *out_ms (host, optional) receives the best re-trace
+ * time. */
 pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed, uint32_t frame,
                       float* out_ms);
 

@@ -235,7 +235,8 @@ def batch_set_transforms(b, d_obj_xf, d_light_xf, owner=None):
     check(lib().pv_batch_set_transforms(b, oarr, larr), owner)
 
 
-PV_TUNE_RETRACE_VARIANT, PV_TUNE_RETRACE_BLOCKS_PER_CU, PV_TUNE_WALK_MIN_ACTIVE = 0, 1, 2
+(PV_TUNE_RETRACE_VARIANT, PV_TUNE_RETRACE_BLOCKS_PER_CU, PV_TUNE_WALK_MIN_ACTIVE, PV_TUNE_VERIFY_BLOCKS_PER_CU,
+ PV_TUNE_VERIFY_MIN_ACTIVE) = 0, 1, 2, 3, 4
 
 
 def set_tuning(ctx, key, value):

@@ -70,7 +70,9 @@ struct pv_ctx {
   // tuning (pv_set_tuning / pv_autotune)
   int retrace_variant = 0;
   int retrace_blocks_per_cu = 8;
-  int walk_min_active = 16;  // a wave's walk yields once fewer lanes are still walking
+  int walk_min_active = 16;  // a wave's re-trace walk yields once fewer lanes are still walking
+  int verify_blocks_per_cu = 8;  // persistent verification traversal workgroups per compute unit
+  int verify_min_active = 16;    // yield threshold of the verification walks
   // bound store
   bool bound = false;
   bool counts_ready = false;   // per-block replace counts written by verify
@@ -481,7 +483,10 @@ std::vector<uint2> xf_tiles(uint32_t scene, const uint32_t* obj_tris, uint32_t n
 }
 
 // grid of the verification traversal kernel (persistent, grid-stride)
-uint32_t verify_blocks(const pv_ctx* ctx) { return (uint32_t)ctx->n_cu * 8u; }
+constexpr int kMaxVerifyBlocksPerCu = 16;
+uint32_t verify_blocks(const pv_ctx* ctx) { return (uint32_t)(ctx->n_cu * ctx->verify_blocks_per_cu); }
+// the largest traversal grid any tuning can pick (sizes the statistics slots)
+uint32_t verify_blocks_max(const pv_ctx* ctx) { return (uint32_t)(ctx->n_cu * kMaxVerifyBlocksPerCu); }
 
 pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
@@ -922,7 +927,7 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->vw.toff, nb));
     CK(dalloc(A, &ctx->vw.total, 1));
     CK(dalloc(A, &ctx->vw.first, max_paths));
-    CK(dalloc(A, &ctx->vw.part, 4 * (size_t)nb + 2 * (size_t)pv::verify_finish_blocks(verify_blocks(ctx))));
+    CK(dalloc(A, &ctx->vw.part, 4 * (size_t)nb + 2 * (size_t)pv::verify_finish_blocks(verify_blocks_max(ctx))));
     CK(hipMemsetAsync(ctx->d_qcount, 0, 4, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->max_paths = max_paths;
@@ -956,7 +961,7 @@ pv_status pv_verify_paths(pv_ctx* ctx, const pv_path_store* store, pv_stats* d_s
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt, d_stats,
-                       ctx->stack_moved, verify_blocks(ctx), ctx->d_scan_tmp, ctx->stream));
+                       ctx->stack_moved, verify_blocks(ctx), ctx->verify_min_active, ctx->d_scan_tmp, ctx->stream));
   ctx->counts_ready = true;
   return PV_OK;
 }
@@ -1018,6 +1023,12 @@ pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value) {
   } else if (key == PV_TUNE_WALK_MIN_ACTIVE) {
     if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "walk minimum active lanes out of range 1..64");
     ctx->walk_min_active = value;
+  } else if (key == PV_TUNE_VERIFY_BLOCKS_PER_CU) {
+    if (value < 1 || value > kMaxVerifyBlocksPerCu) return fail(ctx, PV_ERR_ARG, "verify blocks per CU out of range 1..16");
+    ctx->verify_blocks_per_cu = value;
+  } else if (key == PV_TUNE_VERIFY_MIN_ACTIVE) {
+    if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "verify minimum active lanes out of range 1..64");
+    ctx->verify_min_active = value;
   } else {
     return fail(ctx, PV_ERR_ARG, "unknown tuning key");
   }
@@ -1032,6 +1043,10 @@ pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value) {
     *value = ctx->retrace_blocks_per_cu;
   else if (key == PV_TUNE_WALK_MIN_ACTIVE)
     *value = ctx->walk_min_active;
+  else if (key == PV_TUNE_VERIFY_BLOCKS_PER_CU)
+    *value = ctx->verify_blocks_per_cu;
+  else if (key == PV_TUNE_VERIFY_MIN_ACTIVE)
+    *value = ctx->verify_min_active;
   else
     return PV_ERR_ARG;
   return PV_OK;
@@ -1074,7 +1089,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
       e = copy_store(false);
       if (e == hipSuccess)
         e = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt,
-                              nullptr, ctx->stack_moved, verify_blocks(ctx), ctx->d_scan_tmp, s);
+                              nullptr, ctx->stack_moved, verify_blocks(ctx), ctx->verify_min_active, ctx->d_scan_tmp, s);
       if (e == hipSuccess)
         e = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, s);
       if (e == hipSuccess)
@@ -1093,7 +1108,40 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
     *ms_out = t_min;
     return e;
   };
-  // occupancy variant x grid at the current yield threshold, then the threshold
+  // verification: traversal grid x yield threshold, each timed on the restored store
+  float best_verify = INFINITY;
+  {
+    int bv_b = ctx->verify_blocks_per_cu, bv_m = ctx->verify_min_active;
+    const int vgrids[4] = {2, 4, 8, 16}, vmins[4] = {8, 16, 32, 48};
+    for (int gi = 0; gi < 4 && err == hipSuccess; ++gi) {
+      for (int mi = 0; mi < 4 && err == hipSuccess; ++mi) {
+        ctx->verify_blocks_per_cu = vgrids[gi];
+        ctx->verify_min_active = vmins[mi];
+        float t_min = INFINITY;
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+          err = copy_store(false);
+          if (err == hipSuccess) err = hipEventRecord(e0, s);
+          if (err == hipSuccess)
+            err = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt,
+                                    nullptr, ctx->stack_moved, verify_blocks(ctx), ctx->verify_min_active,
+                                    ctx->d_scan_tmp, s);
+          if (err == hipSuccess) err = hipEventRecord(e1, s);
+          if (err == hipSuccess) err = hipEventSynchronize(e1);
+          float ms = 0;
+          if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+          t_min = std::min(t_min, ms);
+        }
+        if (t_min < best_verify) {
+          best_verify = t_min;
+          bv_b = vgrids[gi];
+          bv_m = vmins[mi];
+        }
+      }
+    }
+    ctx->verify_blocks_per_cu = bv_b;
+    ctx->verify_min_active = bv_m;
+  }
+  // re-trace: occupancy variant x grid at the current yield threshold, then the threshold
   float best = INFINITY;
   int best_v = ctx->retrace_variant, best_b = ctx->retrace_blocks_per_cu, best_m = ctx->walk_min_active;
   const int grids[4] = {2, 4, 8, 16};
@@ -1179,7 +1227,7 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, b->d_xf_tiles, b->n_xf_tiles, st));
   CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_gbase, (int)b->n, b->vw, b->d_block_cnt,
-                       d_stats, b->stack_moved, verify_blocks(ctx), b->d_scan_tmp, st));
+                       d_stats, b->stack_moved, verify_blocks(ctx), ctx->verify_min_active, b->d_scan_tmp, st));
   CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, b->d_scan_tmp, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->d_head, b->T, b->seed, 0,
@@ -1275,7 +1323,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
               chk(dalloc(A, &b->vw.tmp, task_cap)) && chk(dalloc(A, &b->vw.tasks, task_cap)) &&
               chk(dalloc(A, &b->vw.tcount, ptiles.size())) && chk(dalloc(A, &b->vw.toff, ptiles.size())) &&
               chk(dalloc(A, &b->vw.total, 1)) && chk(dalloc(A, &b->vw.first, total_paths)) &&
-              chk(dalloc(A, &b->vw.part, 4 * ptiles.size() + 2 * (size_t)pv::verify_finish_blocks(verify_blocks(ctx)))) &&
+              chk(dalloc(A, &b->vw.part, 4 * ptiles.size() + 2 * (size_t)pv::verify_finish_blocks(verify_blocks_max(ctx)))) &&
               chk(upload(A, &b->d_obj_in, const_cast<const float**>(d_obj_xf), n, s)) &&
               chk(upload(A, &b->d_light_in, const_cast<const float**>(d_light_xf), n, s));
     if (!ok || hipStreamSynchronize(s) != hipSuccess) {

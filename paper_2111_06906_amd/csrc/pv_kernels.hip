@@ -347,6 +347,26 @@ __device__ inline Ray segment_ray(float3 a, float3 b, float eps) {
   return make_ray(a, d, tmin, 1.0f - tmin);
 }
 
+// The box-test part of segment_ray, for filters only: 1/d from the hardware
+// reciprocal (1 ulp) and the end tolerance shortened by 1e-5 relative.  Both
+// move slab parameters by about 1e-7 of the segment or widen the tested
+// interval, far inside the 1e-6 padding of every stored box, so a segment that
+// crosses a triangle inside a box always reaches that box.
+__device__ inline Ray segment_box_ray(float3 a, float3 b, float eps) {
+  Ray r;
+  const float3 d = sub(b, a);
+  const float tiny = 1e-30f;
+  const float dx = fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x);
+  const float dy = fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y);
+  const float dz = fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z);
+  r.inv = f3(__builtin_amdgcn_rcpf(dx), __builtin_amdgcn_rcpf(dy), __builtin_amdgcn_rcpf(dz));
+  r.oi = f3(-(a.x * r.inv.x), -(a.y * r.inv.y), -(a.z * r.inv.z));
+  const float L2 = dot(d, d);
+  r.tmin = L2 > 0.0f ? eps * __builtin_amdgcn_rsqf(L2) * (1.0f - 1e-5f) : 1.0f;
+  r.tmax = 1.0f - r.tmin;
+  return r;
+}
+
 __device__ inline int light_of(const SceneDev& S, uint32_t p) {
   const PV_GLOBAL LightDev* lights = G(S.lights);
   for (uint32_t l = 0; l < S.n_lights; ++l)
@@ -464,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
           const float4 row = rows[j];
           const float3 b = xyz(row);
           if (on_moved(M, __float_as_uint(row.w))) first_mv = min(first_mv, (uint32_t)j);
-          if (reaches_moved_box(M, segment_ray(a, b, S.eps_end))) mask |= 1u << j;
+          if (reaches_moved_box(M, segment_box_ray(a, b, S.eps_end))) mask |= 1u << j;
           a = b;
         }
       }
@@ -472,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
         const float4 row = pos[(size_t)j * stride + p];
         const float3 b = xyz(row);
         if (on_moved(M, __float_as_uint(row.w))) first_mv = min(first_mv, j);
-        if (reaches_moved_box(M, segment_ray(a, b, S.eps_end))) mask |= 1u << j;
+        if (reaches_moved_box(M, segment_box_ray(a, b, S.eps_end))) mask |= 1u << j;
         a = b;
       }
       cap = first_mv;
@@ -551,12 +571,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_gather(const SceneDev* __rest
 // Persistent: each wave owns a contiguous range of the task list; a lane
 // whose walk has finished takes the next task of the range while the other
 // lanes of its wave continue.
-constexpr int kMinActive = 16;
 
 template <bool kSingle>
 __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restrict__ scenes,
                                                          const uint32_t* __restrict__ gbase, int n_scenes,
-                                                         VerifyWork W) {
+                                                         VerifyWork W, int min_active) {
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   const StackCol col = (StackCol)(sstack + threadIdx.x);
   const uint32_t total = *W.total;
@@ -608,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
       continue;
     }
     if (busy) {
-      walk_run(G(S->nodes), G(S->tris), r, true, col, w, kMinActive);
+      walk_run(G(S->nodes), G(S->tris), r, true, col, w, min_active);
       if (walk_done(w)) {
         if (w.gid != kHitNone) atomicMin(&W.first[gp], j);
         busy = false;
@@ -1387,19 +1406,22 @@ uint32_t verify_finish_blocks(uint32_t trace_blocks) { return std::max(1u, trace
 
 hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* gbase,
                          int n_scenes, VerifyWork W, uint32_t* block_cnt, pv_stats* stats, uint32_t stack,
-                         uint32_t trace_blocks, uint32_t* scan_tmp, hipStream_t s) {
+                         uint32_t trace_blocks, int min_active, uint32_t* scan_tmp, hipStream_t s) {
   if (!n_tiles) return hipSuccess;
-  if (stack < 2 || stack > (uint32_t)kMaxStack || trace_blocks == 0) return hipErrorInvalidValue;
+  if (stack < 2 || stack > (uint32_t)kMaxStack || trace_blocks == 0 || min_active < 1 || min_active > 64)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_verify_scan, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W, stats);
   hipError_t e = launch_scan(W.tcount, W.toff, n_tiles, W.total, nullptr, scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_verify_gather, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W);
   const dim3 gt(trace_blocks), gf(verify_finish_blocks(trace_blocks));
   if (n_scenes == 1) {
-    hipLaunchKernelGGL(k_verify_trace<true>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W);
+    hipLaunchKernelGGL(k_verify_trace<true>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W,
+                       min_active);
     hipLaunchKernelGGL(k_verify_finish<true>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, n_tiles, stats);
   } else {
-    hipLaunchKernelGGL(k_verify_trace<false>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W);
+    hipLaunchKernelGGL(k_verify_trace<false>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W,
+                       min_active);
     hipLaunchKernelGGL(k_verify_finish<false>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, n_tiles, stats);
   }
   hipLaunchKernelGGL(k_replace_count, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, block_cnt);

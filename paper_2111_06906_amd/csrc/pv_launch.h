@@ -19,10 +19,11 @@ hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s);
 // replace counts into block_cnt.  'gbase' / 'n_scenes': scene path ranges
 // (global path ids); 'stack': traversal stack entries per lane (stack_entries
 // of the moved objects' hierarchy depths, at most kMaxStack); 'trace_blocks':
-// grid of the traversal kernel; 'scan_tmp': scan_tmp_words(n_tiles) words.
+// grid of the traversal kernel; 'min_active': its walk yield threshold;
+// 'scan_tmp': scan_tmp_words(n_tiles) words.
 hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* gbase,
                          int n_scenes, VerifyWork W, uint32_t* block_cnt, pv_stats* stats, uint32_t stack,
-                         uint32_t trace_blocks, uint32_t* scan_tmp, hipStream_t s);
+                         uint32_t trace_blocks, int min_active, uint32_t* scan_tmp, hipStream_t s);
 // blocks of the finishing kernel for a traversal grid (sizes W.part: 4 words
 // per path tile plus 2 per finishing block)
 uint32_t verify_finish_blocks(uint32_t trace_blocks);

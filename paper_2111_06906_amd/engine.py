@@ -183,20 +183,23 @@ class Context:
         return ga, gp
 
     def autotune(self, store, threshold, seed, frame):
-        """Pick the fastest re-trace kernel variant and grid on this workload."""
+        """Pick the fastest verification and re-trace grids, thresholds and variant on this workload."""
         ms = L.autotune(self.ctx, store.cstruct(), float(threshold), int(seed), int(frame))
         return {"retrace_variant": L.get_tuning(self.ctx, L.PV_TUNE_RETRACE_VARIANT),
                 "retrace_blocks_per_cu": L.get_tuning(self.ctx, L.PV_TUNE_RETRACE_BLOCKS_PER_CU),
                 "walk_min_active": L.get_tuning(self.ctx, L.PV_TUNE_WALK_MIN_ACTIVE),
+                "verify_blocks_per_cu": L.get_tuning(self.ctx, L.PV_TUNE_VERIFY_BLOCKS_PER_CU),
+                "verify_min_active": L.get_tuning(self.ctx, L.PV_TUNE_VERIFY_MIN_ACTIVE),
                 "retrace_ms": ms}
 
-    def set_tuning(self, variant=None, blocks_per_cu=None, walk_min_active=None):
-        if variant is not None:
-            L.set_tuning(self.ctx, L.PV_TUNE_RETRACE_VARIANT, int(variant))
-        if blocks_per_cu is not None:
-            L.set_tuning(self.ctx, L.PV_TUNE_RETRACE_BLOCKS_PER_CU, int(blocks_per_cu))
-        if walk_min_active is not None:
-            L.set_tuning(self.ctx, L.PV_TUNE_WALK_MIN_ACTIVE, int(walk_min_active))
+    def set_tuning(self, variant=None, blocks_per_cu=None, walk_min_active=None, verify_blocks_per_cu=None,
+                   verify_min_active=None):
+        for key, v in ((L.PV_TUNE_RETRACE_VARIANT, variant), (L.PV_TUNE_RETRACE_BLOCKS_PER_CU, blocks_per_cu),
+                       (L.PV_TUNE_WALK_MIN_ACTIVE, walk_min_active),
+                       (L.PV_TUNE_VERIFY_BLOCKS_PER_CU, verify_blocks_per_cu),
+                       (L.PV_TUNE_VERIFY_MIN_ACTIVE, verify_min_active)):
+            if v is not None:
+                L.set_tuning(self.ctx, key, int(v))
 
     def initial_trace(self, store, seed, frame=0, stats=None):
         """Frame-0 photon paths (every path a new light sample)."""

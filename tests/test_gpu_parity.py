@@ -410,9 +410,10 @@ def test_autotune_restores_store_and_tuning_does_not_change_results(E):
     for k in before:
         assert np.array_equal(before[k].view(np.uint32), after[k].view(np.uint32)), k
     results = []
-    for variant, bpc, min_active in ((0, 8, 16), (3, 2, 1), (1, 16, 64), (2, 4, 40)):
+    for variant, bpc, min_active, vbpc, vmin in ((0, 8, 16, 8, 16), (3, 2, 1, 1, 64), (1, 16, 64, 16, 1),
+                                                 (2, 4, 40, 3, 24)):
         st.load_numpy(before)
-        ctx.set_tuning(variant, bpc, min_active)
+        ctx.set_tuning(variant, bpc, min_active, vbpc, vmin)
         ctx.verify(st)
         ctx.retrace(st, 0.01, sc.seed, 1)
         torch.cuda.synchronize()
