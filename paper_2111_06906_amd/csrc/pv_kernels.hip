@@ -895,6 +895,46 @@ __device__ inline bool on_moved_obj(const SceneDev& S, uint32_t hit) {
   return false;
 }
 
+// Object id ranges, moved flags and light path ranges of the scene of a
+// single-scene launch, staged in LDS once per workgroup for the state
+// machine's lookups.
+struct SceneTab {
+  uint32_t obj_lo[PV_MAX_OBJECTS], obj_n[PV_MAX_OBJECTS], obj_mv[PV_MAX_OBJECTS];
+  uint32_t light_base[PV_MAX_LIGHTS], light_n[PV_MAX_LIGHTS];
+  uint32_t n_obj, n_lights;
+};
+
+__device__ inline void load_tab(const SceneDev& S, SceneTab& T) {
+  const uint32_t i = threadIdx.x;
+  if (i < S.n_obj) {
+    const ObjDev ob = G(S.objs)[i];
+    T.obj_lo[i] = ob.gbase;
+    T.obj_n[i] = ob.n_tris;
+    T.obj_mv[i] = G(S.obj_moved)[i];
+  }
+  if (i < S.n_lights) {
+    T.light_base[i] = G(S.lights)[i].path_base;
+    T.light_n[i] = G(S.lights)[i].path_count;
+  }
+  if (i == 0) {
+    T.n_obj = S.n_obj;
+    T.n_lights = S.n_lights;
+  }
+  __syncthreads();
+}
+
+__device__ inline bool on_moved_obj(const PV_LDS SceneTab& T, uint32_t hit) {
+  bool mv = false;  // no early exit: the loop count is uniform
+  for (uint32_t o = 0; o < T.n_obj; ++o) mv |= (hit - T.obj_lo[o] < T.obj_n[o]) && T.obj_mv[o] != 0;
+  return mv;  // kHitNone and static ids lie in no object range
+}
+
+__device__ inline int light_of(const PV_LDS SceneTab& T, uint32_t p) {
+  int l = -1;
+  for (uint32_t i = 0; i < T.n_lights; ++i) l = (p - T.light_base[i] < T.light_n[i]) ? (int)i : l;
+  return l;
+}
+
 __device__ inline void clear_rows(const SceneDev& S, uint32_t p, uint32_t from) {
   for (uint32_t r = from; r < S.B; ++r) {
     size_t i = (size_t)r * S.stride + p;
@@ -944,13 +984,13 @@ __device__ inline void to_tail(Lane& L) {
   }
 }
 
-__device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t frame) {
+__device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t frame, const PV_LDS SceneTab* tab) {
   const SceneDev& S = *L.S;
   uint32_t w = G(S.info)[L.p];
   L.n = min(info_nseg(w), S.B);
   L.k = info_start(w);
   L.cell = info_cell(w);
-  L.l = light_of(S, L.p);
+  L.l = tab ? light_of(*tab, L.p) : light_of(S, L.p);
   bool reuse = info_reuse(w) != 0;
   if (!info_replace(w) || L.l < 0) {
     L.mode = ST_IDLE;
@@ -999,10 +1039,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
                                                     pv_stats* stats, int min_active) {
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   __shared__ unsigned long long sred[kBlock / 64];
+  __shared__ SceneTab stab;
   const StackCol col = (StackCol)(sstack + threadIdx.x);
   const uint32_t frame = frame_ptr ? *frame_ptr : frame_arg;
   uint32_t n_rays = 0, n_photons = 0, n_acc = 0, n_trunc = 0;
+  const PV_LDS SceneTab* tab = nullptr;
+  if (kSingle) {
+    load_tab(scenes[0], stab);
+    tab = (const PV_LDS SceneTab*)&stab;
+  }
+  // each wave owns a contiguous range of the work queue (no atomics: device
+  // atomics on one word from thousands of waves serialise)
   const uint32_t count = *qcount;
+  const uint32_t n_waves = gridDim.x * (kBlock / 64);
+  const uint32_t chunk = (count + n_waves - 1) / n_waves;
+  const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  uint32_t next = min(count, wave * chunk);  // wave-uniform cursor
+  const uint32_t qend = min(count, next + chunk);
   Lane L;
   L.S = scenes;
   L.mode = ST_IDLE;
@@ -1013,17 +1066,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
   wk.leaf = 0;
   bool tracing = false, any = false;
   while (true) {
-    // refill idle lanes from the queue: one atomic per wave
+    // refill idle lanes from the wave's range of the queue
     bool want = L.mode == ST_IDLE;
     uint64_t m = __ballot(want);
     if (m) {
-      uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-      uint32_t base = 0;
-      if (lane_id() == leader) base = atomicAdd(head, (uint32_t)__popcll(m));
-      base = __shfl(base, (int)leader, 64);
+      const uint32_t base = next;
+      next += (uint32_t)__popcll(m);
       if (want) {
         uint32_t qi = base + (uint32_t)__popcll(m & lanemask_lt());
-        if (qi < count) {
+        if (qi < qend) {
           uint32_t gp = G(queue)[qi];
           if (kSingle) {
             L.p = gp;
@@ -1032,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
             L.S = scenes + s;
             L.p = gp - gbase[s];
           }
-          start_path(L, T, seed, frame);
+          start_path(L, T, seed, frame, tab);
           // a path without the replace bit is skipped (stays idle this round)
         } else {
           L.mode = ST_END;
@@ -1061,7 +1112,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
       } else if (L.mode == ST_WCHECK || L.mode == ST_WTRACE || L.mode == ST_WSKIP) {
         uint32_t sj = L.mode == ST_WSKIP ? L.j + 1 : L.j;
         const float3 xa = vertex(S, L.p, sj), xb = vertex(S, L.p, sj + 1);
-        if (L.mode == ST_WCHECK && on_moved_obj(S, vertex_hit(S, L.p, sj + 1))) L.mode = ST_WTRACE;
+        if (L.mode == ST_WCHECK && (tab ? on_moved_obj(*tab, vertex_hit(S, L.p, sj + 1))
+                                        : on_moved_obj(S, vertex_hit(S, L.p, sj + 1))))
+          L.mode = ST_WTRACE;
         qo = xa;
         if (L.mode == ST_WTRACE) {
           qd = normalize3(sub(xb, xa));
@@ -1184,8 +1237,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         }
         ++n_acc;
         float dist = length(sub(hp, vertex(S, L.p, L.j + 1)));
-        if (dist <= S.eps_close && !on_moved_obj(S, h.gid) && !on_moved_obj(S, vertex_hit(S, L.p, L.j + 1)) &&
-            !on_moved_obj(S, vertex_hit(S, L.p, L.j + 2))) {
+        auto moved = [&](uint32_t hit) { return tab ? on_moved_obj(*tab, hit) : on_moved_obj(S, hit); };
+        if (dist <= S.eps_close && !moved(h.gid) && !moved(vertex_hit(S, L.p, L.j + 1)) &&
+            !moved(vertex_hit(S, L.p, L.j + 2))) {
           L.hp = hp;
           L.hgid = h.gid;
           L.mode = ST_WSKIP;  // the next segment must also be clear
