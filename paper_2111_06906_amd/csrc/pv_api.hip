@@ -63,7 +63,7 @@ struct pv_ctx {
   uint32_t max_paths = 0, max_bounces = 0, max_blocks = 0;
   uint2* d_path_tiles = nullptr;
   uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr,
-           *d_head = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr,
+           *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr,
            *d_scan_tmp = nullptr;
   float* d_partial = nullptr;
   pv::VerifyWork vw{};  // verification task lists
@@ -89,7 +89,7 @@ struct pv_batch {
   SceneDev* d_scenes = nullptr;
   uint2 *d_path_tiles = nullptr, *d_obj_tiles = nullptr, *d_xf_tiles = nullptr;
   uint32_t n_path_tiles = 0, n_obj_tiles = 0, n_xf_tiles = 0;
-  uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr, *d_head = nullptr,
+  uint32_t *d_block_cnt = nullptr, *d_offsets = nullptr, *d_queue = nullptr, *d_qcount = nullptr,
            *d_gbase = nullptr, *d_pcounts = nullptr, *d_poffsets = nullptr, *d_ptotal = nullptr, *d_pbase = nullptr,
            *d_frame = nullptr, *d_scan_tmp = nullptr;
   uint32_t n_counts = 0;
@@ -914,7 +914,6 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->d_offsets, nb));
     CK(dalloc(A, &ctx->d_queue, max_paths));
     CK(dalloc(A, &ctx->d_qcount, 1));
-    CK(dalloc(A, &ctx->d_head, 1));
     CK(dalloc(A, &ctx->d_pcounts, (size_t)nb * max_bounces));
     CK(dalloc(A, &ctx->d_poffsets, (size_t)nb * max_bounces));
     CK(dalloc(A, &ctx->d_gbase, 2));
@@ -972,7 +971,7 @@ pv_status pv_build_queue(pv_ctx* ctx, const pv_path_store* store) {
   if (st) return st;
   if (!ctx->counts_ready) return fail(ctx, PV_ERR_STATE, "pv_verify_paths has not been called");
   uint32_t nb = path_blocks(store->n_paths);
-  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, ctx->stream));
+  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_scan_tmp, ctx->stream));
   CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
   return PV_OK;
 }
@@ -983,7 +982,7 @@ pv_status pv_queue_all(pv_ctx* ctx, const pv_path_store* store) {
   if (st) return st;
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_mark_all(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, ctx->stream));
-  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, ctx->stream));
+  CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_scan_tmp, ctx->stream));
   CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
   return PV_OK;
 }
@@ -1006,7 +1005,7 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
   uint32_t blocks = (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu);
-  CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold, seed,
+  CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, threshold, seed,
                         frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stack_entries,
                         ctx->walk_min_active, ctx->stream));
   return PV_OK;
@@ -1091,12 +1090,12 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
         e = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt,
                               nullptr, ctx->stack_moved, verify_blocks(ctx), ctx->verify_min_active, ctx->d_scan_tmp, s);
       if (e == hipSuccess)
-        e = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_head, ctx->d_scan_tmp, s);
+        e = pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_scan_tmp, s);
       if (e == hipSuccess)
         e = pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, s);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       if (e == hipSuccess)
-        e = pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, ctx->d_head, threshold,
+        e = pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, threshold,
                                seed, frame, nullptr, nullptr, (uint32_t)(ctx->n_cu * bpc), v, ctx->stack_entries,
                                min_active, s);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -1187,7 +1186,7 @@ pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_o
   if (!d_count || (capacity && (!d_out_pos || !d_out_energy))) return fail(ctx, PV_ERR_ARG, "output is NULL");
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_photon_count(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_pcounts, ctx->stream));
-  CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, nullptr, ctx->d_scan_tmp,
+  CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, ctx->d_scan_tmp,
                      ctx->stream));
   CK(pv::launch_photon_scatter(ctx->d_scene, ctx->d_path_tiles, nb, store->max_bounces, ctx->d_poffsets, d_out_pos,
                                d_out_energy, capacity, ctx->stream));
@@ -1228,13 +1227,13 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_gbase, (int)b->n, b->vw, b->d_block_cnt,
                        d_stats, b->stack_moved, verify_blocks(ctx), ctx->verify_min_active, b->d_scan_tmp, st));
-  CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_head, b->d_scan_tmp, st));
+  CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_scan_tmp, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
-  CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->d_head, b->T, b->seed, 0,
+  CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->T, b->seed, 0,
                         b->d_frame, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
                         b->stack_entries, ctx->walk_min_active, st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
-  CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, nullptr, b->d_scan_tmp, st));
+  CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, b->d_scan_tmp, st));
   CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,
                                b->d_out_pos, b->d_out_en, b->capacity, st));
   CK(pv::launch_scene_photon_base(b->d_scenes, (int)b->n, b->d_poffsets, b->d_ptotal, b->d_pbase, st));
@@ -1315,7 +1314,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
               chk(upload(A, &b->d_gbase, gbase.data(), gbase.size(), s)) &&
               chk(dalloc(A, &b->d_block_cnt, ptiles.size())) && chk(dalloc(A, &b->d_offsets, ptiles.size())) &&
               chk(dalloc(A, &b->d_queue, total_paths)) && chk(dalloc(A, &b->d_qcount, 1)) &&
-              chk(dalloc(A, &b->d_head, 1)) && chk(dalloc(A, &b->d_pcounts, counts)) &&
+              chk(dalloc(A, &b->d_pcounts, counts)) &&
               chk(dalloc(A, &b->d_poffsets, counts)) && chk(dalloc(A, &b->d_ptotal, 1)) &&
               chk(dalloc(A, &b->d_pbase, n + 1)) && chk(dalloc(A, &b->d_frame, 1)) &&
               chk(dalloc(A, &b->d_scan_tmp, pv::scan_tmp_words((uint32_t)std::max<uint64_t>(counts, ptiles.size())))) &&

@@ -145,7 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_transform(SceneDev* scenes, const ui
 
 // per moved object, one workgroup: the hierarchy's boxes level by level from
 // the deepest internal nodes up, then the object's box
-__global__ __launch_bounds__(kBlock) void k_update_objects(SceneDev* scenes, const uint2* tiles) {
+constexpr int kRefitBlock = 1024;  // the deepest levels of an object hold thousands of nodes
+
+__global__ __launch_bounds__(kRefitBlock) void k_update_objects(SceneDev* scenes, const uint2* tiles) {
   uint2 tile = tiles[blockIdx.x];
   SceneDev& S = scenes[tile.x];
   const uint32_t o = tile.y;
@@ -712,11 +714,10 @@ __global__ __launch_bounds__(1024) void k_verify_stats(const uint32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of n counts by one block of 1024 threads; total -> *total,
-// and the work-queue head reset
+// exclusive scan of n counts by one block of 1024 threads; total -> *total
 
 __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint32_t n,
-                                               uint32_t* total, uint32_t* head) {
+                                               uint32_t* total) {
   __shared__ uint32_t wsum[16];
   __shared__ uint32_t carry_sh;
   if (threadIdx.x == 0) carry_sh = 0;
@@ -750,7 +751,6 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ in, 
   }
   if (threadIdx.x == 0) {
     *total = carry_sh;
-    if (head) *head = 0;
   }
 }
 
@@ -1034,7 +1034,7 @@ __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t fram
 template <bool kSingle, int kWaves>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_retrace(const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ gbase,
                                                     int n_scenes, const uint32_t* __restrict__ queue,
-                                                    const uint32_t* __restrict__ qcount, uint32_t* head, float T,
+                                                    const uint32_t* __restrict__ qcount, float T,
                                                     uint64_t seed, uint32_t frame_arg, const uint32_t* frame_ptr,
                                                     pv_stats* stats, int min_active) {
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
@@ -1444,7 +1444,7 @@ hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t 
                                  uint32_t n_xf_tiles, hipStream_t s) {
   if (!n_tiles) return hipSuccess;
   hipLaunchKernelGGL(k_transform, dim3(n_xf_tiles), dim3(kBlock), 0, s, scenes, xf_tiles);
-  hipLaunchKernelGGL(k_update_objects, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles);
+  hipLaunchKernelGGL(k_update_objects, dim3(n_tiles), dim3(kRefitBlock), 0, s, scenes, tiles);
   return hipGetLastError();
 }
 
@@ -1465,7 +1465,7 @@ hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_
   if (stack < 2 || stack > (uint32_t)kMaxStack || trace_blocks == 0 || min_active < 1 || min_active > 64)
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_verify_scan, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W, stats);
-  hipError_t e = launch_scan(W.tcount, W.toff, n_tiles, W.total, nullptr, scan_tmp, s);
+  hipError_t e = launch_scan(W.tcount, W.toff, n_tiles, W.total, scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_verify_gather, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W);
   const dim3 gt(trace_blocks), gf(verify_finish_blocks(trace_blocks));
@@ -1483,16 +1483,16 @@ hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
                        uint32_t* tile_tmp, hipStream_t s) {
   if (n <= kScanTile || !tile_tmp) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total, head);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total);
     return hipGetLastError();
   }
   // tile_tmp holds 2 * ceil(n / kScanTile) words: tile sums, then their offsets
   const uint32_t tiles = (n + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(1024), 0, s, in, out, n, tile_tmp);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, tile_tmp, tile_tmp + tiles, tiles, total, head);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, tile_tmp, tile_tmp + tiles, tiles, total);
   hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, s, out, n, tile_tmp + tiles);
   return hipGetLastError();
 }
@@ -1517,38 +1517,38 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
 // SIMD the compiler must allow): 0 -> 4, 1 -> 5, 2 -> 6, 3 -> 8
 template <bool kSingle>
 static void retrace_variant(int v, dim3 g, size_t lds, hipStream_t s, const SceneDev* scenes, const uint32_t* gbase, int n_scenes,
-                            const uint32_t* queue, const uint32_t* qcount, uint32_t* head, float T, uint64_t seed,
+                            const uint32_t* queue, const uint32_t* qcount, float T, uint64_t seed,
                             uint32_t frame, const uint32_t* frame_ptr, pv_stats* stats, int min_active) {
   switch (v) {
     case 1:
-      hipLaunchKernelGGL((k_retrace<kSingle, 5>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 5>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
                          T, seed, frame, frame_ptr, stats, min_active);
       break;
     case 2:
-      hipLaunchKernelGGL((k_retrace<kSingle, 6>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 6>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
                          T, seed, frame, frame_ptr, stats, min_active);
       break;
     case 3:
-      hipLaunchKernelGGL((k_retrace<kSingle, 8>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 8>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
                          T, seed, frame, frame_ptr, stats, min_active);
       break;
     default:
-      hipLaunchKernelGGL((k_retrace<kSingle, 4>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount, head,
+      hipLaunchKernelGGL((k_retrace<kSingle, 4>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
                          T, seed, frame, frame_ptr, stats, min_active);
       break;
   }
 }
 
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
-                          const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
+                          const uint32_t* qcount, float T, uint64_t seed, uint32_t frame,
                           const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
                           int min_active, hipStream_t s) {
   if (stack < 2 || stack > (uint32_t)kMaxStack || min_active < 1 || min_active > 64) return hipErrorInvalidValue;
   if (n_scenes == 1)
-    retrace_variant<true>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
+    retrace_variant<true>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, T, seed, frame,
                           frame_ptr, stats, min_active);
   else
-    retrace_variant<false>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, head, T, seed, frame,
+    retrace_variant<false>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, T, seed, frame,
                            frame_ptr, stats, min_active);
   return hipGetLastError();
 }

@@ -27,7 +27,7 @@ hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_
 // blocks of the finishing kernel for a traversal grid (sizes W.part: 4 words
 // per path tile plus 2 per finishing block)
 uint32_t verify_finish_blocks(uint32_t trace_blocks);
-hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* head,
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
                        uint32_t* tile_tmp, hipStream_t s);
 uint32_t scan_tmp_words(uint32_t n);
 hipError_t launch_scatter_queue(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint32_t* offsets,
@@ -35,7 +35,7 @@ hipError_t launch_scatter_queue(const SceneDev* scenes, const uint2* tiles, uint
 hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
                            hipStream_t s);
 hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
-                          const uint32_t* qcount, uint32_t* head, float T, uint64_t seed, uint32_t frame,
+                          const uint32_t* qcount, float T, uint64_t seed, uint32_t frame,
                           const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
                           int min_active, hipStream_t s);
 hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
