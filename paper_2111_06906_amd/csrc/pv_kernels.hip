@@ -413,6 +413,15 @@ __device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_
   return (uint32_t)lo;
 }
 
+// Work lists are dealt to the waves of a persistent grid in interleaved chunks
+// of kChunk entries (chunk c to wave c mod waves): no atomics, and each wave's
+// share spans the whole list, so uneven regions of it (the scenes of a batch,
+// expensive paths) are spread over all waves.  A wave's n-th entry:
+constexpr uint32_t kChunk = 64;
+__device__ inline uint32_t wave_entry(uint32_t wave, uint32_t n_waves, uint32_t n) {
+  return ((n / kChunk) * n_waves + wave) * kChunk + n % kChunk;
+}
+
 // Verification runs as a short chain of kernels without atomics.
 //  k_verify_scan (coalesced, lane per path, no traversal): origin update for
 //    moved lights, the bounce rows read up front, endpoint test, and one task
@@ -570,9 +579,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_gather(const SceneDev* __rest
   for (uint32_t i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
 }
 
-// Persistent: each wave owns a contiguous range of the task list; a lane
-// whose walk has finished takes the next task of the range while the other
-// lanes of its wave continue.
+// Persistent: a lane whose walk has finished takes the wave's next task
+// (interleaved chunks, see wave_entry) while the other lanes continue.
 
 template <bool kSingle>
 __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restrict__ scenes,
@@ -582,10 +590,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
   const StackCol col = (StackCol)(sstack + threadIdx.x);
   const uint32_t total = *W.total;
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
-  const uint32_t chunk = (total + n_waves - 1) / n_waves;
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  uint32_t next = min(total, wave * chunk);  // wave-uniform cursor
-  const uint32_t end = min(total, next + chunk);
+  uint32_t next = 0;  // wave-uniform count of entries taken
   Walk w;
   w.cur = kRootNone;
   w.leaf = 0;
@@ -602,8 +608,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
       const uint32_t base = next;
       next += (uint32_t)__popcll(m);
       if (want) {
-        const uint32_t t = base + (uint32_t)__popcll(m & lanemask_lt());
-        if (t >= end) {
+        const uint32_t t = wave_entry(wave, n_waves, base + (uint32_t)__popcll(m & lanemask_lt()));
+        if (t >= total) {
           drained = true;
         } else {
           const uint32_t tk = G(W.tasks)[t];
@@ -1048,14 +1054,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     load_tab(scenes[0], stab);
     tab = (const PV_LDS SceneTab*)&stab;
   }
-  // each wave owns a contiguous range of the work queue (no atomics: device
-  // atomics on one word from thousands of waves serialise)
+  // the wave's share of the work queue in interleaved chunks (no atomics:
+  // device atomics on one word from thousands of waves serialise)
   const uint32_t count = *qcount;
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
-  const uint32_t chunk = (count + n_waves - 1) / n_waves;
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  uint32_t next = min(count, wave * chunk);  // wave-uniform cursor
-  const uint32_t qend = min(count, next + chunk);
+  uint32_t next = 0;  // wave-uniform count of entries taken
   Lane L;
   L.S = scenes;
   L.mode = ST_IDLE;
@@ -1066,15 +1070,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
   wk.leaf = 0;
   bool tracing = false, any = false;
   while (true) {
-    // refill idle lanes from the wave's range of the queue
+    // refill idle lanes from the wave's share of the queue
     bool want = L.mode == ST_IDLE;
     uint64_t m = __ballot(want);
     if (m) {
       const uint32_t base = next;
       next += (uint32_t)__popcll(m);
       if (want) {
-        uint32_t qi = base + (uint32_t)__popcll(m & lanemask_lt());
-        if (qi < qend) {
+        const uint32_t qi = wave_entry(wave, n_waves, base + (uint32_t)__popcll(m & lanemask_lt()));
+        if (qi < count) {
           uint32_t gp = G(queue)[qi];
           if (kSingle) {
             L.p = gp;
