@@ -69,10 +69,12 @@ struct pv_ctx {
   pv::VerifyWork vw{};  // verification task lists
   // tuning (pv_set_tuning / pv_autotune)
   int retrace_variant = 0;
-  int retrace_blocks_per_cu = 8;
-  int walk_min_active = 16;  // a wave's re-trace walk yields once fewer lanes are still walking
-  int verify_blocks_per_cu = 8;  // persistent verification traversal workgroups per compute unit
-  int verify_min_active = 16;    // yield threshold of the verification walks
+  // defaults: the settings the autotuner picks on the 3M-path, 380k-triangle
+  // interior (one persistent wave per SIMD slot that 127 VGPRs allow)
+  int retrace_blocks_per_cu = 4;
+  int walk_min_active = 40;  // a wave's re-trace walk yields once fewer lanes are still walking
+  int verify_blocks_per_cu = 4;  // persistent verification traversal workgroups per compute unit
+  int verify_min_active = 32;    // yield threshold of the verification walks
   // bound store
   bool bound = false;
   bool counts_ready = false;   // per-block replace counts written by verify
@@ -867,8 +869,10 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     ctx->n_lights = d->n_lights;
     ctx->n_objects = d->n_objects;
     ctx->h_obj_tris.assign(d->h_obj_tris, d->h_obj_tris + d->n_objects);
-    // the top-level trees hold the static root and the objects, median split
-    ctx->stack_entries = pv::stack_entries(ceil_log2(d->n_objects + (S ? 1u : 0u)), depth);
+    // the whole-scene top-level tree: the static root beside a median split
+    // of the objects (or either alone); the moved-object tree: a median split
+    const uint32_t top_depth = S && d->n_objects ? 1u + ceil_log2(d->n_objects) : ceil_log2(d->n_objects);
+    ctx->stack_entries = pv::stack_entries(top_depth, depth);
     ctx->stack_moved = pv::stack_entries(ceil_log2(d->n_objects), obj_depth);
     ctx->h_light_paths.assign(d->n_lights, 0);
     ctx->uploaded = true;

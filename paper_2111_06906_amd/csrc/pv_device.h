@@ -37,9 +37,9 @@ constexpr int kBlock = 256;        // threads per block of the streaming kernels
 // a walk through a top-level tree of depth t into a hierarchy of depth d needs
 // t + d + 2 entries.
 constexpr int kMaxStack = 40;
-constexpr int kTopDepth = 7;  // top-level tree depth bound (median split of <= 65 items)
+constexpr int kTopDepth = 7;  // top-level tree depth bound (the static root beside a median split of <= 64 objects)
 constexpr int kMaxDepth = kMaxStack - kTopDepth - 2;
-static_assert((1 << kTopDepth) >= PV_MAX_OBJECTS + 1, "top-level depth bound");
+static_assert((1 << (kTopDepth - 1)) >= PV_MAX_OBJECTS, "top-level depth bound");
 __host__ __device__ inline uint32_t stack_entries(uint32_t top_depth, uint32_t depth) {
   return top_depth + depth + 2;
 }

@@ -179,118 +179,126 @@ __global__ __launch_bounds__(kRefitBlock) void k_update_objects(SceneDev* scenes
 // top-level trees, rebuilt each frame once the object boxes are current: one
 // over the static root and every object root, one over the moved objects
 // only (the set that verification and the walk's clearance tests query).
-// The trees hold at most PV_MAX_OBJECTS + 1 items, so one thread per scene
-// builds them: median split of the items along the widest axis of their box
-// centres, ranges taken from an explicit stack, node 0 the root.
+// The objects of a tree are split at their median along the widest axis of
+// their box centres, recursively; the static hierarchy, whose box spans the
+// scene and would widen every node above it, is the root's first child and
+// the objects' tree the second (nearly every query enters the static side
+// first).  One wave per tree, one lane per position of the item order, one
+// level of the recursion per step: every range of the level is stably sorted
+// by rank along its own axis, at once.  A range [lo, hi) splits at
+// mid = (lo + hi) / 2, and each split position belongs to exactly one
+// internal node, so node mid - 1 of the tree's block holds that range (node
+// n - 1 the root above the static hierarchy).
 
-__global__ void k_build_top(SceneDev* scenes) {
-  constexpr int kItems = PV_MAX_OBJECTS + 1;
-  __shared__ float ibox[2][kItems][6];
-  __shared__ int32_t icode[2][kItems];
-  __shared__ int nitems[2];
-  __shared__ float icen[kItems][3];
-  __shared__ uint8_t idx[kItems];
-  SceneDev& S = scenes[blockIdx.x];
-  // the items of both trees, one lane per object (compacted by ballot)
+constexpr int kTopLevels = kTopDepth - 1;  // median levels over <= PV_MAX_OBJECTS objects
+
+__global__ __launch_bounds__(128) void k_build_top(SceneDev* scenes) {
   static_assert(PV_MAX_OBJECTS <= 64, "one lane per object");
-  if (threadIdx.x < 64) {
-    const uint32_t o = threadIdx.x;
-    const int first_obj = S.sroot != kRootNone ? 1 : 0;  // the static root is item 0 of the whole-scene tree
-    const bool have = o < S.n_obj;
-    const bool mv = have && S.obj_moved[o] != 0;
-    const uint64_t mm = __ballot(mv);
-    if (have) {
-      float b[6];
-      for (int k = 0; k < 6; ++k) b[k] = S.obj_aabb[6 * o + k];
-      const int32_t root = S.objs[o].root;
-      for (int k = 0; k < 6; ++k) ibox[0][first_obj + o][k] = b[k];
-      icode[0][first_obj + o] = root;
-      if (mv) {
-        const uint32_t i = (uint32_t)__popcll(mm & ((1ull << o) - 1ull));
-        for (int k = 0; k < 6; ++k) ibox[1][i][k] = b[k];
-        icode[1][i] = root;
-      }
-    }
-    if (o == 0) {
-      if (first_obj) {
-        for (int k = 0; k < 6; ++k) ibox[0][0][k] = S.sbox[k];
-        icode[0][0] = S.sroot;
-      }
-      nitems[0] = first_obj + (int)S.n_obj;
-      nitems[1] = (int)__popcll(mm);
-    }
+  static_assert((1 << kTopLevels) >= PV_MAX_OBJECTS, "median levels");
+  __shared__ float sbx[2][2][6][64];  // [tree][buffer][box component][position]
+  __shared__ int32_t scode[2][2][64];
+  SceneDev& S = scenes[blockIdx.x];
+  const int which = threadIdx.x >> 6;  // tree of this wave
+  const uint32_t lane = threadIdx.x & 63u;
+  // items of the tree in object order (moved objects compacted by ballot)
+  const bool have = lane < S.n_obj;
+  const bool take = have && (which == 0 || S.obj_moved[lane] != 0);
+  const uint64_t mm = __ballot(take);
+  const uint32_t n = (uint32_t)__popcll(mm);
+  if (take) {
+    const uint32_t i = (uint32_t)__popcll(mm & lanemask_lt());
+    for (int k = 0; k < 6; ++k) sbx[which][0][k][i] = S.obj_aabb[6 * lane + k];
+    scode[which][0][i] = S.objs[lane].root;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int which = 0; which < 2; ++which) {
-    const int n = nitems[which];
-    float(*ib)[6] = ibox[which];
-    const int32_t* ic = icode[which];
-    for (int i = 0; i < n; ++i) {
-      idx[i] = (uint8_t)i;
-      for (int k = 0; k < 3; ++k) icen[i][k] = 0.5f * (ib[i][k] + ib[i][3 + k]);
-    }
-    const uint32_t first = S.top_base + (uint32_t)which * kTopNodes;
-    int32_t root = n == 0 ? kRootNone : (n == 1 ? ic[0] : (int32_t)first);
-    if (n >= 2) {
-      struct Range {
-        uint8_t lo, hi, node;
-      };
-      Range stack[kTopNodes];
-      int sp = 0, next = 1;
-      stack[sp++] = {0, (uint8_t)n, 0};
-      while (sp > 0) {
-        const Range rg = stack[--sp];
-        float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
-        float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-        for (int i = rg.lo; i < rg.hi; ++i)
-          for (int k = 0; k < 3; ++k) {
-            lo[k] = fminf(lo[k], icen[idx[i]][k]);
-            hi[k] = fmaxf(hi[k], icen[idx[i]][k]);
-          }
-        int ax = 0;
-        for (int k = 1; k < 3; ++k)
-          if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
-        for (int i = rg.lo + 1; i < rg.hi; ++i) {  // insertion sort by centre
-          const uint8_t v = idx[i];
-          int j = i - 1;
-          while (j >= rg.lo && icen[idx[j]][ax] > icen[v][ax]) {
-            idx[j + 1] = idx[j];
-            --j;
-          }
-          idx[j + 1] = v;
+  const uint32_t first = S.top_base + (uint32_t)which * kTopNodes;
+  uint32_t lo = 0, hi = n;  // range of this lane's position
+  int buf = 0;
+  for (int level = 0; level < kTopLevels; ++level) {
+    const float(*bx)[64] = sbx[which][buf];
+    const bool live = lane < n && hi - lo >= 2;
+    uint32_t dst = lane;
+    if (live) {
+      // widest axis of the range's box centres
+      float clo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+      float chi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+      for (uint32_t q = lo; q < hi; ++q)
+        for (int k = 0; k < 3; ++k) {
+          const float c = 0.5f * (bx[k][q] + bx[3 + k][q]);
+          clo[k] = fminf(clo[k], c);
+          chi[k] = fmaxf(chi[k], c);
         }
-        const int mid = (rg.lo + rg.hi) / 2;
+      int ax = 0;
+      for (int k = 1; k < 3; ++k)
+        if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+      // stable rank along that axis
+      const float mine = 0.5f * (bx[ax][lane] + bx[3 + ax][lane]);
+      uint32_t rank = 0;
+      for (uint32_t q = lo; q < hi; ++q) {
+        const float c = 0.5f * (bx[ax][q] + bx[3 + ax][q]);
+        rank += (c < mine || (c == mine && q < lane)) ? 1u : 0u;
+      }
+      dst = lo + rank;
+    }
+    float mb[6];
+    for (int k = 0; k < 6; ++k) mb[k] = bx[k][lane];
+    const int32_t mc = scode[which][buf][lane];
+    if (lane < n) {
+      for (int k = 0; k < 6; ++k) sbx[which][buf ^ 1][k][dst] = mb[k];
+      scode[which][buf ^ 1][dst] = mc;
+    }
+    __syncthreads();
+    buf ^= 1;
+    if (live) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (lane == lo) {  // one lane per range writes its node
+        const float(*nb)[64] = sbx[which][buf];
         float cb[2][6];
         int32_t ch[2];
         for (int side = 0; side < 2; ++side) {
-          const int a = side ? mid : rg.lo, b = side ? rg.hi : mid;
+          const uint32_t a = side ? mid : lo, b = side ? hi : mid;
           for (int k = 0; k < 3; ++k) {
             cb[side][k] = __builtin_inff();
             cb[side][3 + k] = -__builtin_inff();
           }
-          for (int i = a; i < b; ++i)
+          for (uint32_t q = a; q < b; ++q)
             for (int k = 0; k < 3; ++k) {
-              cb[side][k] = fminf(cb[side][k], ib[idx[i]][k]);
-              cb[side][3 + k] = fmaxf(cb[side][3 + k], ib[idx[i]][3 + k]);
+              cb[side][k] = fminf(cb[side][k], nb[k][q]);
+              cb[side][3 + k] = fmaxf(cb[side][3 + k], nb[3 + k][q]);
             }
-          if (b - a == 1) {
-            ch[side] = ic[idx[a]];
-          } else {
-            const int id = next++;
-            ch[side] = (int32_t)(first + (uint32_t)id);
-            stack[sp++] = {(uint8_t)a, (uint8_t)b, (uint8_t)id};
-          }
+          ch[side] = b - a == 1 ? scode[which][buf][a] : (int32_t)(first + (a + b) / 2 - 1);
         }
-        Node& nd = S.nodes[first + rg.node];
+        Node& nd = S.nodes[first + mid - 1];
         nd.a = make_float4(cb[0][0], cb[0][1], cb[0][2], cb[0][3]);
         nd.b = make_float4(cb[0][4], cb[0][5], cb[1][0], cb[1][1]);
         nd.c = make_float4(cb[1][2], cb[1][3], cb[1][4], cb[1][5]);
         nd.d = make_int4(ch[0], ch[1], -1, 0);
       }
+      if (lane < mid) hi = mid;
+      else lo = mid;
     }
-    S.top[which] = root;
   }
+  if (lane != 0) return;
+  // root of the objects' tree: its node, the single object, or none
+  int32_t root = n == 0 ? kRootNone : (n == 1 ? scode[which][buf][0] : (int32_t)(first + n / 2 - 1));
+  if (which == 0 && S.sroot != kRootNone && n > 0) {
+    float ob[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                   -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    for (uint32_t q = 0; q < n; ++q)
+      for (int k = 0; k < 3; ++k) {
+        ob[k] = fminf(ob[k], sbx[0][buf][k][q]);
+        ob[3 + k] = fmaxf(ob[3 + k], sbx[0][buf][3 + k][q]);
+      }
+    Node& nd = S.nodes[first + n - 1];
+    nd.a = make_float4(S.sbox[0], S.sbox[1], S.sbox[2], S.sbox[3]);
+    nd.b = make_float4(S.sbox[4], S.sbox[5], ob[0], ob[1]);
+    nd.c = make_float4(ob[2], ob[3], ob[4], ob[5]);
+    nd.d = make_int4(S.sroot, root, -1, 0);
+    root = (int32_t)(first + n - 1);
+  } else if (which == 0 && S.sroot != kRootNone) {
+    root = S.sroot;
+  }
+  S.top[which] = root;
 }
 
 // ---------------------------------------------------------------------------
@@ -1454,7 +1462,7 @@ hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t 
 
 hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s) {
   if (n_scenes <= 0) return hipSuccess;
-  k_build_top<<<n_scenes, 64, 0, s>>>(scenes);
+  k_build_top<<<n_scenes, 128, 0, s>>>(scenes);
   return hipGetLastError();
 }
 
