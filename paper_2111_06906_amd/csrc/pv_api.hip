@@ -796,7 +796,8 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       tri_base += n;
       gbase += n;
     }
-    if (nodes.size() + 2 * (size_t)pv::kTopNodes >= (size_t)INT32_MAX)
+    // traversal addresses node records by a 32-bit byte offset
+    if ((nodes.size() + 2 * (size_t)pv::kTopNodes) * sizeof(Node) > (size_t)UINT32_MAX)
       return fail(ctx, PV_ERR_CAPACITY, "too many hierarchy nodes");
     hs.top_base = (uint32_t)nodes.size();
     nodes.resize(nodes.size() + 2 * (size_t)pv::kTopNodes, Node{});

@@ -334,33 +334,54 @@ __device__ inline void walk_start(Walk& w, int32_t root, float tmax, StackCol co
 __device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const PV_GLOBAL Tri* __restrict__ tris,
                                 const Ray& r, bool any, StackCol col, Walk& w, int min_active) {
   int32_t cur = w.cur, leaf = w.leaf;
-  int sp = w.sp;
+  // top: the stack's top entry (entry sp - 1); the far child goes one entry
+  // above it.  Once the sentinel itself is taken top points one entry below
+  // the column's first, which every launch allocates and nothing uses.
+  StackCol top = col + (w.sp - 1) * kBlock;
   float tb = w.tb;
   uint32_t gid = w.gid, rec = w.rec;
+  const float tmin = r.tmin;
   while (true) {
     while (cur >= 0) {
-      const int32_t top = col[(sp - 1) * kBlock];
-      const Node nd = nodes[cur];
-      const float e0 = box_entry(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, r, tb);
-      const float e1 = box_entry(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, r, tb);
-      const bool h0 = e0 != __builtin_inff(), h1 = e1 != __builtin_inff();
-      const bool near0 = e0 <= e1;  // a missed child has entry +inf
-      col[sp * kBlock] = near0 ? nd.d.y : nd.d.x;
-      sp += (h0 && h1) ? 1 : ((h0 || h1) ? 0 : -1);
-      cur = (h0 || h1) ? (near0 ? nd.d.x : nd.d.y) : top;
-      // postpone a reached leaf and go on with the next stack entry (sp is 0
-      // only once the sentinel itself was taken: then nothing is postponed)
-      const int32_t next = col[max(sp - 1, 0) * kBlock];
-      const bool post = leaf == 0 && is_leaf(cur);
+      const int32_t below = top[0];
+      // node records are addressed by a 32-bit byte offset (arrays < 4 GiB)
+      const Node nd = *(const PV_GLOBAL Node*)((const PV_GLOBAL char*)nodes + ((uint32_t)cur << 6));
+      // slab entry and exit of both children; the query interval enters by
+      // comparisons only (min/max with it would need canonical operands)
+      float tx0 = fmaf(nd.a.x, r.inv.x, r.oi.x), tx1 = fmaf(nd.a.w, r.inv.x, r.oi.x);
+      float ty0 = fmaf(nd.a.y, r.inv.y, r.oi.y), ty1 = fmaf(nd.b.x, r.inv.y, r.oi.y);
+      float tz0 = fmaf(nd.a.z, r.inv.z, r.oi.z), tz1 = fmaf(nd.b.y, r.inv.z, r.oi.z);
+      const float e0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
+      const float x0 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+      tx0 = fmaf(nd.b.z, r.inv.x, r.oi.x), tx1 = fmaf(nd.c.y, r.inv.x, r.oi.x);
+      ty0 = fmaf(nd.b.w, r.inv.y, r.oi.y), ty1 = fmaf(nd.c.z, r.inv.y, r.oi.y);
+      tz0 = fmaf(nd.c.x, r.inv.z, r.oi.z), tz1 = fmaf(nd.c.w, r.inv.z, r.oi.z);
+      const float e1 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
+      const float x1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+      // the slab interval meets [tmin, tb]
+      const bool a0 = e0 <= x0, b0 = e0 <= tb, c0 = x0 >= tmin;
+      const bool a1 = e1 <= x1, b1 = e1 <= tb, c1 = x1 >= tmin;
+      const bool le = e0 <= e1;
+      const bool h0 = a0 && b0 && c0, h1 = a1 && b1 && c1;
+      const bool near0 = h0 && (!h1 || le);  // a missed child comes last
+      top[kBlock] = near0 ? nd.d.y : nd.d.x;
+      const StackCol up = top + kBlock, down = top - kBlock;
+      top = (h0 && h1) ? up : ((h0 || h1) ? top : down);
+      cur = (h0 || h1) ? (near0 ? nd.d.x : nd.d.y) : below;
+      // postpone a reached leaf and go on with the next stack entry (once the
+      // sentinel itself was taken, cur is kRootNone and nothing is postponed)
+      const int32_t next = top[0];
+      const bool lf = is_leaf(cur), em = leaf == 0;
+      const bool post = em && lf;
       leaf = post ? cur : leaf;
       cur = post ? next : cur;
-      sp -= post ? 1 : 0;
+      top = post ? top - kBlock : top;
       if (__ballot(leaf == 0) == 0) break;  // every lane still here holds a leaf
     }
     if (leaf == 0 && is_leaf(cur)) {
       leaf = cur;
-      --sp;
-      cur = col[sp * kBlock];
+      cur = top[0];
+      top -= kBlock;
     }
     bool found = false;
     while (leaf != 0) {
@@ -378,8 +399,8 @@ __device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const 
       const bool again = is_leaf(cur) && !(found && any);
       leaf = again ? cur : 0;
       if (again) {
-        --sp;
-        cur = col[sp * kBlock];
+        cur = top[0];
+        top -= kBlock;
       }
     }
     if (found && any) cur = kRootNone;
@@ -388,7 +409,7 @@ __device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const 
   }
   w.cur = cur;
   w.leaf = leaf;
-  w.sp = sp;
+  w.sp = (int)(top - col) / kBlock + 1;
   w.tb = tb;
   w.gid = gid;
   w.rec = rec;

@@ -595,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
                                                          const uint32_t* __restrict__ gbase, int n_scenes,
                                                          VerifyWork W, int min_active) {
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
-  const StackCol col = (StackCol)(sstack + threadIdx.x);
+  const StackCol col = (StackCol)(sstack + kBlock + threadIdx.x);  // entry 0 of the column; entry -1 spare
   const uint32_t total = *W.total;
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -1054,7 +1054,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   __shared__ unsigned long long sred[kBlock / 64];
   __shared__ SceneTab stab;
-  const StackCol col = (StackCol)(sstack + threadIdx.x);
+  const StackCol col = (StackCol)(sstack + kBlock + threadIdx.x);  // entry 0 of the column; entry -1 spare
   const uint32_t frame = frame_ptr ? *frame_ptr : frame_arg;
   uint32_t n_rays = 0, n_photons = 0, n_acc = 0, n_trunc = 0;
   const PV_LDS SceneTab* tab = nullptr;
@@ -1466,7 +1466,9 @@ hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s) {
   return hipGetLastError();
 }
 
-static size_t stack_bytes(uint32_t entries) { return (size_t)entries * kBlock * sizeof(int32_t); }
+// the stack columns of a block, plus one spare entry below each column (a walk
+// whose sentinel was taken points there)
+static size_t stack_bytes(uint32_t entries) { return (size_t)(entries + 1) * kBlock * sizeof(int32_t); }
 
 uint32_t verify_finish_blocks(uint32_t trace_blocks) { return std::max(1u, trace_blocks / 2); }
 
