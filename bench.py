@@ -293,6 +293,22 @@ def main():
         torch.cuda.synchronize()
         base_ms.append(e0.elapsed_time(e1))
     res["baseline_retrace_all_ms"] = sum(base_ms) / len(base_ms)
+    # frame begin (object transforms, hierarchies, top-level trees) with the
+    # objects' hierarchies refit, then with every object's hierarchy rebuilt on
+    # the device as a linear BVH (last: the mode keeps larger traversal stacks)
+    fb = {}
+    for mode in (0, 1):
+        ctx.set_tuning(object_rebuild=mode)
+        ms = []
+        for i in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.frame_begin(1 + (i % max(1, sc.n_frames - 1)))
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        fb["rebuild_ms" if mode else "refit_ms"] = sum(ms[1:]) / len(ms[1:])
+    res["frame_begin_objects"] = fb
     ctx.close()
     del st, out_pos, out_en
     torch.cuda.empty_cache()

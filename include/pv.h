@@ -196,14 +196,23 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
  * PV_TUNE_WALK_MIN_ACTIVE (1..64): a wave's re-trace walk yields to take new
  * queries once fewer of its 64 lanes are still walking;
  * PV_TUNE_VERIFY_BLOCKS_PER_CU (1..16) and PV_TUNE_VERIFY_MIN_ACTIVE (1..64):
- * the same two choices for the verification traversal.  Results do not
- * depend on the tuning. */
+ * the same two choices for the verification traversal;
+ * PV_TUNE_OBJECT_REBUILD (0 or 1): 0 (default) refits each moved object's
+ * upload-time topology (binned surface-area heuristic, object space) in
+ * pv_frame_begin; 1 also rebuilds every object's hierarchy on the device each
+ * frame, as a linear BVH (30-bit Morton codes of the triangle centroids, radix
+ * sort, radix tree by Karras 2012, boxes bottom-up), which becomes the
+ * object's hierarchy unless it is deeper than 31 levels (then the refit
+ * topology serves that frame).  Once mode 1 was set, the traversal stacks stay
+ * sized for 31-level object hierarchies.  Results do not depend on the
+ * tuning. */
 enum {
   PV_TUNE_RETRACE_VARIANT = 0,
   PV_TUNE_RETRACE_BLOCKS_PER_CU = 1,
   PV_TUNE_WALK_MIN_ACTIVE = 2,
   PV_TUNE_VERIFY_BLOCKS_PER_CU = 3,
-  PV_TUNE_VERIFY_MIN_ACTIVE = 4
+  PV_TUNE_VERIFY_MIN_ACTIVE = 4,
+  PV_TUNE_OBJECT_REBUILD = 5
 };
 pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value);
 pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
@@ -285,6 +294,16 @@ uint64_t pv_store_bytes(uint64_t n_paths, uint32_t max_bounces);
  * out[3] = 1 when the leaves partition the triangles, every child box
  * contains its subtree and the depth fits the traversal stack. */
 pv_status pv_hierarchy_info(const float* h_verts, uint32_t n, int32_t kind, uint32_t* out);
+/* Check the current hierarchy of dynamic object 'obj' on the device (after
+ * pv_frame_begin; synchronises the context's stream and copies the scene's
+ * nodes and the object's triangles to the host): out[0] internal nodes,
+ * out[1] leaves, out[2] depth of the deepest leaf, out[3] = 1 when the leaves
+ * partition the object's triangles, every box on the way to a leaf contains
+ * its triangles and the depth fits the traversal stack, out[4] = 1 when the
+ * hierarchy is the per-frame rebuilt one (PV_TUNE_OBJECT_REBUILD), 0 for the
+ * refit upload-time topology.  PV_ERR_ARG for an object index out of range,
+ * PV_ERR_STATE before a scene upload. */
+pv_status pv_object_hierarchy_info(pv_ctx* ctx, uint32_t obj, uint32_t* out);
 /* Pack / unpack the path-information word. */
 uint32_t pv_info_pack(uint32_t cell, uint32_t nseg, uint32_t start, uint32_t replace, uint32_t reuse);
 void pv_info_unpack(uint32_t w, uint32_t* cell, uint32_t* nseg, uint32_t* start, uint32_t* replace,

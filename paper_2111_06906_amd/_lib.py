@@ -86,6 +86,7 @@ def lib():
         "pv_info_unpack": ([U32, P, P, P, P, P], None),
         "pv_version": ([], C.c_char_p),
         "pv_hierarchy_info": ([P, U32, I32, P], I32),
+        "pv_object_hierarchy_info": ([P, U32, P], I32),
         "pv_set_tuning": ([P, I32, I32], I32),
         "pv_get_tuning": ([P, I32, P], I32),
         "pv_autotune": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
@@ -236,7 +237,13 @@ def batch_set_transforms(b, d_obj_xf, d_light_xf, owner=None):
 
 
 (PV_TUNE_RETRACE_VARIANT, PV_TUNE_RETRACE_BLOCKS_PER_CU, PV_TUNE_WALK_MIN_ACTIVE, PV_TUNE_VERIFY_BLOCKS_PER_CU,
- PV_TUNE_VERIFY_MIN_ACTIVE) = 0, 1, 2, 3, 4
+ PV_TUNE_VERIFY_MIN_ACTIVE, PV_TUNE_OBJECT_REBUILD) = 0, 1, 2, 3, 4, 5
+
+
+def object_hierarchy_info(ctx, obj):
+    out = (C.c_uint32 * 5)()
+    check(lib().pv_object_hierarchy_info(ctx, obj, out), ctx)
+    return {"nodes": out[0], "leaves": out[1], "depth": out[2], "valid": bool(out[3]), "rebuilt": bool(out[4])}
 
 
 def set_tuning(ctx, key, value):

@@ -56,6 +56,12 @@ struct pv_ctx {
   std::vector<uint32_t> h_obj_tris;  // triangles per object
   uint32_t stack_entries = 2;  // traversal stack per lane: whole-scene queries
   uint32_t stack_moved = 2;    // traversal stack per lane: queries against the moved objects
+  // deepest leaves: static world, upload-time object topologies, rebuilt
+  // object hierarchies (bound), whole-scene top-level tree
+  uint32_t static_depth = 0, obj_depth = 0, lbvh_depth = 0, top_depth = 0;
+  pv::LbvhWork lw{};          // scratch of the per-frame object rebuild
+  bool object_rebuild = false;  // PV_TUNE_OBJECT_REBUILD
+  bool lbvh_used = false;       // a rebuilt hierarchy may be current: stacks sized for it
   std::vector<uint32_t> h_light_paths;  // filled at binding
   // scratch
   bool reserved = false;
@@ -532,6 +538,15 @@ pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
 
 }  // namespace
 
+// Traversal stack entries per lane: the top-level tree above the deepest
+// hierarchy a query can enter (a rebuilt object hierarchy once one may be
+// current: objects that did not move since keep theirs).
+static void size_stacks(pv_ctx* ctx) {
+  const uint32_t od = ctx->lbvh_used ? std::max(ctx->obj_depth, ctx->lbvh_depth) : ctx->obj_depth;
+  ctx->stack_entries = pv::stack_entries(ctx->top_depth, std::max(ctx->static_depth, od));
+  ctx->stack_moved = pv::stack_entries(ceil_log2(ctx->n_objects), od);
+}
+
 // Invariants of a hierarchy over leaf-order vertices: leaves partition the
 // triangles, every stored child box contains its subtree, depth <= bound.
 bool check_hierarchy(const HostBvh& h, const float* v9_leaf_order, uint32_t n) {
@@ -742,6 +757,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       }
     }
 
+    const uint32_t static_depth = depth;
     // dynamic objects: topology in object space, boxes refit per frame
     std::vector<ObjDev> objs(d->n_objects);
     std::vector<float> dlocal(9 * n_dyn);
@@ -796,6 +812,15 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       tri_base += n;
       gbase += n;
     }
+    // regions of the per-frame rebuilt hierarchies (a radix tree over an
+    // object's n triangles has n - 1 internal nodes), after the topologies
+    const uint32_t lbvh_first = (uint32_t)nodes.size();
+    for (uint32_t o = 0; o < d->n_objects; ++o) {
+      objs[o].sah_root = objs[o].root;
+      objs[o].lbvh_base = (uint32_t)nodes.size();
+      nodes.resize(nodes.size() + (objs[o].n_tris - 1), Node{});
+    }
+    const uint32_t lbvh_nodes = (uint32_t)nodes.size() - lbvh_first;
     // traversal addresses node records by a 32-bit byte offset
     if ((nodes.size() + 2 * (size_t)pv::kTopNodes) * sizeof(Node) > (size_t)UINT32_MAX)
       return fail(ctx, PV_ERR_CAPACITY, "too many hierarchy nodes");
@@ -816,6 +841,26 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     CK(upload(A, &d_lnodes, level_nodes.data(), level_nodes.size(), s));
     CK(upload(A, &d_loff, level_off.data(), level_off.size(), s));
     CK(upload(A, &d_objs, objs.data(), objs.size(), s));
+    pv::LbvhWork lw{};
+    if (n_dyn) {
+      const uint32_t nd = (uint32_t)n_dyn, tiles = pv::lbvh_sort_tiles(nd);
+      for (int b = 0; b < 2; ++b) {
+        CK(dalloc(A, &lw.key[b], nd));
+        CK(dalloc(A, &lw.val[b], nd));
+      }
+      CK(dalloc(A, &lw.hist, 256 * (size_t)tiles));
+      CK(dalloc(A, &lw.hoff, 256 * (size_t)tiles));
+      CK(dalloc(A, &lw.htotal, 1));
+      CK(dalloc(A, &lw.scan_tmp, pv::scan_tmp_words(256 * tiles)));
+      CK(dalloc(A, &lw.parent_leaf, nd));
+      CK(dalloc(A, &lw.parent_node, std::max(lbvh_nodes, 1u)));
+      CK(dalloc(A, &lw.flag, std::max(lbvh_nodes, 1u)));
+      CK(dalloc(A, &lw.height, std::max(lbvh_nodes, 1u)));
+      CK(dalloc(A, &lw.cbox, 6 * (size_t)d->n_objects));
+      lw.n_dyn = nd;
+      lw.first_node = lbvh_first;
+      lw.n_nodes = lbvh_nodes;
+    }
     hs.nodes = d_nodes;
     hs.tris = d_tris;
     hs.dlocal = d_dlocal;
@@ -872,9 +917,13 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     ctx->h_obj_tris.assign(d->h_obj_tris, d->h_obj_tris + d->n_objects);
     // the whole-scene top-level tree: the static root beside a median split
     // of the objects (or either alone); the moved-object tree: a median split
-    const uint32_t top_depth = S && d->n_objects ? 1u + ceil_log2(d->n_objects) : ceil_log2(d->n_objects);
-    ctx->stack_entries = pv::stack_entries(top_depth, depth);
-    ctx->stack_moved = pv::stack_entries(ceil_log2(d->n_objects), obj_depth);
+    ctx->top_depth = S && d->n_objects ? 1u + ceil_log2(d->n_objects) : ceil_log2(d->n_objects);
+    ctx->static_depth = static_depth;
+    ctx->obj_depth = obj_depth;
+    ctx->lbvh_depth = d->n_objects ? (uint32_t)kMaxDepth : 0;
+    ctx->lw = lw;
+    ctx->lbvh_used = ctx->object_rebuild;
+    size_stacks(ctx);
     ctx->h_light_paths.assign(d->n_lights, 0);
     ctx->uploaded = true;
     return PV_OK;
@@ -953,6 +1002,11 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
   CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->stream));
   CK(pv::launch_update_objects(ctx->d_scene, ctx->d_obj_tiles, ctx->n_obj_tiles, ctx->d_xf_tiles, ctx->n_xf_tiles,
                                ctx->stream));
+  // rebuild mode: every object's hierarchy rebuilt from its current
+  // triangles; the refit topology (kept current above) stays the hierarchy of
+  // an object whose rebuilt tree is too deep for the traversal stacks
+  if (ctx->object_rebuild)
+    CK(pv::launch_rebuild_objects(ctx->d_scene, ctx->lw, ctx->n_objects, ctx->lbvh_depth, ctx->stream));
   CK(pv::launch_build_top(ctx->d_scene, 1, ctx->stream));
   ctx->frame_started = true;
   return PV_OK;
@@ -1033,10 +1087,106 @@ pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value) {
   } else if (key == PV_TUNE_VERIFY_MIN_ACTIVE) {
     if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "verify minimum active lanes out of range 1..64");
     ctx->verify_min_active = value;
+  } else if (key == PV_TUNE_OBJECT_REBUILD) {
+    if (value != 0 && value != 1) return fail(ctx, PV_ERR_ARG, "object rebuild is 0 or 1");
+    ctx->object_rebuild = value == 1;
+    if (ctx->object_rebuild && !ctx->lbvh_used) {
+      ctx->lbvh_used = true;
+      size_stacks(ctx);
+    }
   } else {
     return fail(ctx, PV_ERR_ARG, "unknown tuning key");
   }
   return PV_OK;
+}
+
+pv_status pv_object_hierarchy_info(pv_ctx* ctx, uint32_t obj, uint32_t* out) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!out) return fail(ctx, PV_ERR_ARG, "out is NULL");
+  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
+  if (obj >= ctx->n_objects) return fail(ctx, PV_ERR_ARG, "object index out of range");
+  try {
+    CK(hipStreamSynchronize(ctx->stream));
+    const SceneDev& hs = ctx->hs;
+    ObjDev ob;
+    CK(hipMemcpy(&ob, hs.objs + obj, sizeof(ObjDev), hipMemcpyDeviceToHost));
+    std::vector<Node> nodes(hs.top_base);
+    CK(hipMemcpy(nodes.data(), hs.nodes, sizeof(Node) * nodes.size(), hipMemcpyDeviceToHost));
+    const uint32_t first = hs.n_static + ob.tri_base;
+    std::vector<Tri> tris(ob.n_tris);
+    CK(hipMemcpy(tris.data(), hs.tris + first, sizeof(Tri) * tris.size(), hipMemcpyDeviceToHost));
+    // walk the current hierarchy from the object's root: its internal nodes
+    // lie in the object's topology or rebuild region, its leaves partition the
+    // object's triangle records, every box on the way to a leaf contains that
+    // leaf's triangles, and no leaf is deeper than the stack allows
+    const bool in_rebuild = ob.root >= 0 && (uint32_t)ob.root >= ob.lbvh_base;
+    const uint32_t lo = in_rebuild ? ob.lbvh_base : ob.node_base;
+    const uint32_t hi = in_rebuild ? ob.lbvh_base + (ob.n_tris - 1) : ob.node_base + ob.n_nodes;
+    struct It {
+      int32_t code;
+      uint32_t depth;
+      float box[6];
+    };
+    std::vector<It> st;
+    std::vector<uint8_t> seen(ob.n_tris, 0);
+    st.push_back({ob.root, 0, {-INFINITY, -INFINITY, -INFINITY, INFINITY, INFINITY, INFINITY}});
+    uint32_t n_int = 0, n_leaf = 0, max_depth = 0;
+    bool ok = true;
+    auto inside = [](const float* in6, const float* out6) {
+      for (int k = 0; k < 3; ++k)
+        if (in6[k] < out6[k] || in6[3 + k] > out6[3 + k]) return false;
+      return true;
+    };
+    while (!st.empty() && ok) {
+      const It it = st.back();
+      st.pop_back();
+      max_depth = std::max(max_depth, it.depth);
+      if (it.code < 0) {
+        ++n_leaf;
+        const uint32_t f = pv::leaf_first(it.code), c = pv::leaf_count(it.code);
+        for (uint32_t i = f; i < f + c && ok; ++i) {
+          if (i < first || i - first >= ob.n_tris || seen[i - first]) {
+            ok = false;
+            break;
+          }
+          seen[i - first] = 1;
+          const Tri& t = tris[i - first];
+          const float4 v[3] = {t.t0, t.t1, t.t2};
+          for (int q = 0; q < 3; ++q) {
+            const float b[6] = {v[q].x, v[q].y, v[q].z, v[q].x, v[q].y, v[q].z};
+            if (!inside(b, it.box)) ok = false;
+          }
+        }
+        continue;
+      }
+      if ((uint32_t)it.code < lo || (uint32_t)it.code >= hi || n_int > ob.n_tris) {
+        ok = false;
+        break;
+      }
+      ++n_int;
+      const Node& nd = nodes[it.code];
+      const float* f = reinterpret_cast<const float*>(&nd);
+      for (int side = 0; side < 2; ++side) {
+        It ch;
+        ch.code = side ? nd.d.y : nd.d.x;
+        ch.depth = it.depth + 1;
+        std::memcpy(ch.box, f + 6 * side, sizeof(ch.box));
+        if (!inside(ch.box, it.box)) ok = false;
+        st.push_back(ch);
+      }
+    }
+    for (uint32_t i = 0; i < ob.n_tris && ok; ++i)
+      if (!seen[i]) ok = false;
+    const uint32_t allowed = ctx->lbvh_used ? std::max(ctx->obj_depth, ctx->lbvh_depth) : ctx->obj_depth;
+    out[0] = n_int;
+    out[1] = n_leaf;
+    out[2] = max_depth;
+    out[3] = (ok && max_depth <= allowed) ? 1u : 0u;
+    out[4] = in_rebuild ? 1u : 0u;
+    return PV_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, PV_ERR_OOM, "host allocation failed");
+  }
 }
 
 pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value) {
@@ -1051,6 +1201,8 @@ pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value) {
     *value = ctx->verify_blocks_per_cu;
   else if (key == PV_TUNE_VERIFY_MIN_ACTIVE)
     *value = ctx->verify_min_active;
+  else if (key == PV_TUNE_OBJECT_REBUILD)
+    *value = ctx->object_rebuild ? 1 : 0;
   else
     return PV_ERR_ARG;
   return PV_OK;

@@ -88,8 +88,10 @@ struct ObjDev {
   uint32_t node_base;  // first node of its hierarchy in the scene's node array
   uint32_t n_nodes;    // internal nodes of its hierarchy
   uint32_t lvl_base;   // first entry of its level offsets (n_levels + 1 entries)
-  int32_t root;        // root child code in the scene's node / triangle arrays
+  int32_t root;        // root child code in the scene's node / triangle arrays (current hierarchy)
   uint32_t n_levels;   // depth levels holding internal nodes
+  int32_t sah_root;    // root of the upload-time topology (refit each frame)
+  uint32_t lbvh_base;  // first node of its region for the per-frame rebuilt radix tree
 };
 
 struct LightDev {
@@ -156,6 +158,29 @@ struct SceneDev {
   uint32_t tile_base;     // first path tile (block of kBlock paths) of this scene
   uint32_t task_base;     // first entry of this scene's tile regions of verification tasks
   uint32_t* state;        // [1] first-frame flag of the scene
+};
+
+// Device scratch of the per-frame object hierarchy rebuild (linear BVH over
+// 30-bit Morton codes): sort keys (object << 30 | Morton code of the
+// triangle's centroid) and values (dynamic triangle record) in two buffers,
+// per-tile digit histograms and their scan, parent links and arrival counters
+// of the rebuilt nodes (indexed from the scene's first rebuilt node), and the
+// objects' centroid boxes.
+struct LbvhWork {
+  uint64_t* key[2];
+  uint32_t* val[2];
+  uint32_t* hist;        // [256][tiles] digit counts of a sort pass
+  uint32_t* hoff;        // their exclusive scan
+  uint32_t* htotal;      // [1]
+  uint32_t* scan_tmp;    // scan_tmp_words(256 * tiles)
+  int32_t* parent_leaf;  // [n_dyn] by sorted position: parent node, -1 for a one-triangle object
+  int32_t* parent_node;  // [nodes] parent node, -1 at an object's root
+  uint32_t* flag;        // [nodes] children completed so far
+  uint32_t* height;      // [nodes] levels below each node
+  float* cbox;           // [n_obj][6] centroid bounds
+  uint32_t n_dyn;        // dynamic triangles of the scene
+  uint32_t first_node;   // scene node index of the first rebuilt node
+  uint32_t n_nodes;      // rebuilt nodes of all objects
 };
 
 // Verification work lists (device scratch).  A task is one segment whose ray

@@ -170,8 +170,9 @@ __global__ __launch_bounds__(kRefitBlock) void k_update_objects(SceneDev* scenes
   }
   if (threadIdx.x == 0) {
     float b[6];
-    child_box(S, ob.root, b);
+    child_box(S, ob.sah_root, b);
     for (int k = 0; k < 6; ++k) S.obj_aabb[6 * o + k] = b[k];
+    const_cast<ObjDev*>(S.objs)[o].root = ob.sah_root;  // the refit topology is the current one
   }
 }
 
@@ -1457,6 +1458,12 @@ hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t 
   if (!n_tiles) return hipSuccess;
   hipLaunchKernelGGL(k_transform, dim3(n_xf_tiles), dim3(kBlock), 0, s, scenes, xf_tiles);
   hipLaunchKernelGGL(k_update_objects, dim3(n_tiles), dim3(kRefitBlock), 0, s, scenes, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_transform_objects(SceneDev* scenes, const uint2* xf_tiles, uint32_t n_xf_tiles, hipStream_t s) {
+  if (!n_xf_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_transform, dim3(n_xf_tiles), dim3(kBlock), 0, s, scenes, xf_tiles);
   return hipGetLastError();
 }
 

@@ -13,6 +13,14 @@ hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const
 // (scene, object))
 hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const uint2* xf_tiles,
                                  uint32_t n_xf_tiles, hipStream_t s);
+// world triangles of the moved objects only (xf_tiles as above)
+hipError_t launch_transform_objects(SceneDev* scenes, const uint2* xf_tiles, uint32_t n_xf_tiles, hipStream_t s);
+// every object's hierarchy rebuilt from its current world triangles (one
+// scene): linear BVH over Morton codes, into the objects' rebuild regions; an
+// object whose tree is deeper than max_depth keeps its current hierarchy
+hipError_t launch_rebuild_objects(SceneDev* scenes, LbvhWork W, uint32_t n_obj, uint32_t max_depth, hipStream_t s);
+// sort tiles of the rebuild for n_dyn triangles (W.hist holds 256 per tile)
+uint32_t lbvh_sort_tiles(uint32_t n_dyn);
 hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s);
 // Verification of every path of the tiles: scan, task list, traversal of the
 // box-hit segments, information words of the paths with tasks, per-tile

@@ -193,13 +193,18 @@ class Context:
                 "retrace_ms": ms}
 
     def set_tuning(self, variant=None, blocks_per_cu=None, walk_min_active=None, verify_blocks_per_cu=None,
-                   verify_min_active=None):
+                   verify_min_active=None, object_rebuild=None):
         for key, v in ((L.PV_TUNE_RETRACE_VARIANT, variant), (L.PV_TUNE_RETRACE_BLOCKS_PER_CU, blocks_per_cu),
                        (L.PV_TUNE_WALK_MIN_ACTIVE, walk_min_active),
                        (L.PV_TUNE_VERIFY_BLOCKS_PER_CU, verify_blocks_per_cu),
-                       (L.PV_TUNE_VERIFY_MIN_ACTIVE, verify_min_active)):
+                       (L.PV_TUNE_VERIFY_MIN_ACTIVE, verify_min_active),
+                       (L.PV_TUNE_OBJECT_REBUILD, object_rebuild)):
             if v is not None:
                 L.set_tuning(self.ctx, key, int(v))
+
+    def object_hierarchy_info(self, obj):
+        """Check of dynamic object obj's current device hierarchy (synchronises)."""
+        return L.object_hierarchy_info(self.ctx, int(obj))
 
     def initial_trace(self, store, seed, frame=0, stats=None):
         """Frame-0 photon paths (every path a new light sample)."""

@@ -163,9 +163,12 @@ def test_max_bounces_fifteen(E):
 # the oracle's store of the previous frame)
 
 
-def _lockstep(E, sc, n_frames, T, label):
+def _lockstep(E, sc, n_frames, T, label, tuning=None):
     ora, _ = _oracle_frame0(sc)
-    ctx = _setup(E, sc)
+    ctx = E.Context(sc)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    ctx.frame_begin(0)
     st = ctx.new_store()
     total_rep = 0
     for f in range(1, n_frames):
@@ -225,6 +228,97 @@ def test_sixty_four_objects(E):
     # the largest object count: deepest top-level tree and traversal stack
     sc = scenes.make_rooms("many", 3, 3, 20000, 64, (8, 4), 6000 + 5, 7, 3, 0.01, 12, lights_move=True)
     _lockstep(E, sc, 3, 0.01, "64 objects")
+
+
+def test_object_rebuild_lockstep(E):
+    # every object's hierarchy rebuilt on the device each frame (Morton codes,
+    # radix sort, radix tree, bottom-up boxes) instead of refit: same results
+    sc = scenes.make_paper(n_paths=4096 + 13, frames=3)
+    _lockstep(E, sc, 3, 0.01, "paper, rebuilt objects", tuning=dict(object_rebuild=1))
+    sc = scenes.make_rooms("many", 3, 3, 20000, 64, (8, 4), 6000 + 5, 7, 3, 0.01, 12, lights_move=True)
+    _lockstep(E, sc, 3, 0.01, "64 objects, rebuilt", tuning=dict(object_rebuild=1))
+
+
+DEPTH_ALLOWANCE = 31  # object hierarchies deeper than this keep the refit topology
+
+
+def test_object_hierarchies_in_both_modes(E):
+    # the device hierarchy of every object after refit, after a rebuild, and
+    # after switching back (objects that did not move keep the rebuilt one)
+    sc = scenes.make_paper(n_paths=1024, frames=4)
+    ctx = E.Context(sc)
+    n_obj = sc.n_dynamic
+    ctx.frame_begin(0)
+    for o in range(n_obj):
+        h = ctx.object_hierarchy_info(o)
+        assert h["valid"] and not h["rebuilt"] and h["nodes"] + 1 == h["leaves"], (o, h)
+    ctx.set_tuning(object_rebuild=1)
+    ctx.frame_begin(1)
+    for o in range(n_obj):
+        n = sc.obj_local[o].shape[0]
+        h = ctx.object_hierarchy_info(o)
+        log("object %d rebuilt: %s" % (o, h))
+        assert h["valid"] and h["rebuilt"] and h["leaves"] == n and h["nodes"] == n - 1, (o, h)
+        assert h["depth"] <= DEPTH_ALLOWANCE
+    ctx.set_tuning(object_rebuild=0)
+    ctx.frame_begin(2)
+    moved = [not np.array_equal(sc.obj_xforms[2, o], sc.obj_xforms[1, o]) for o in range(n_obj)]
+    for o in range(n_obj):
+        h = ctx.object_hierarchy_info(o)
+        assert h["valid"] and h["rebuilt"] == (not moved[o]), (o, h, moved[o])
+    with pytest.raises(Exception):
+        ctx.object_hierarchy_info(n_obj)
+    ctx.close()
+
+
+def _chain_object(m):
+    # small triangles at 2^-k along each axis (k = 1..10) and m copies at the
+    # origin, in a unit centroid box: the radix tree's path to the copies
+    # splits off one Morton bit per level (30 levels), then ceil(log2 m)
+    tri = np.array([[0.0, 0.0, 0.0], [1e-7, 0.0, 0.0], [0.0, 1e-7, 0.0]], np.float32)
+    pts = [np.zeros(3), np.ones(3)]
+    for a in range(3):
+        for k in range(1, 11):
+            p = np.zeros(3)
+            p[a] = 2.0 ** -k
+            pts.append(p)
+    tris = [tri + p.astype(np.float32) for p in pts] + [tri] * m
+    return np.stack(tris).astype(np.float32)
+
+
+def test_object_rebuild_degenerate_objects(E):
+    # equal Morton codes (copies of one triangle, a cluster far below the
+    # quantisation step), a one-triangle object, and an object whose radix
+    # tree is deeper than the allowance (it keeps the refit topology)
+    import dataclasses
+    sc = scenes.make_tiny(n_paths=1024, frames=3)
+    rng = np.random.default_rng(7)
+    tri = np.array([[0.0, 0.0, 0.0], [0.01, 0.0, 0.0], [0.0, 0.01, 0.0]], np.float32)
+    copies = np.repeat(tri[None], 300, axis=0)
+    cluster = (rng.random((200, 3, 3)) * 1e-6).astype(np.float32)
+    spread = (rng.random((97, 3, 3)) * 0.05 - 0.025).astype(np.float32)
+    deg = np.concatenate([copies, cluster, spread]).astype(np.float32)
+    one = tri[None].copy()
+    chain = _chain_object(4096)
+    objs = [sc.obj_local[0], deg, one, chain]
+    xf = np.concatenate([sc.obj_xforms] * len(objs), axis=1)
+    for o, x in ((1, 0.6), (2, 0.2), (3, 0.8)):
+        xf[:, o, 3] = x
+    sc = dataclasses.replace(sc, obj_local=objs, obj_mat=[np.ones(len(t), np.uint32) for t in objs], obj_xforms=xf)
+    ctx = E.Context(sc)
+    ctx.set_tuning(object_rebuild=1)
+    for f in range(3):
+        ctx.frame_begin(f)
+        for o in range(len(objs)):
+            n = objs[o].shape[0]
+            h = ctx.object_hierarchy_info(o)
+            log("frame %d object %d (%d triangles): %s" % (f, o, n, h))
+            assert h["valid"] and h["depth"] <= DEPTH_ALLOWANCE, (f, o, h)
+            if o < 3:  # a one-triangle object's hierarchy is its leaf
+                assert h["leaves"] == n and h["rebuilt"] == (n > 1), (f, o, h)
+            else:
+                assert not h["rebuilt"], (f, o, h)
+    ctx.close()
 
 
 # ---------------------------------------------------------------------------
