@@ -854,8 +854,8 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       CK(dalloc(A, &lw.scan_tmp, pv::scan_tmp_words(256 * tiles)));
       CK(dalloc(A, &lw.parent_leaf, nd));
       CK(dalloc(A, &lw.parent_node, std::max(lbvh_nodes, 1u)));
-      CK(dalloc(A, &lw.flag, std::max(lbvh_nodes, 1u)));
-      CK(dalloc(A, &lw.height, std::max(lbvh_nodes, 1u)));
+      CK(dalloc(A, &lw.pyr, 2 * (size_t)pv::lbvh_pyramid_entries(nd)));
+      CK(dalloc(A, &lw.odepth, d->n_objects));
       CK(dalloc(A, &lw.cbox, 6 * (size_t)d->n_objects));
       lw.n_dyn = nd;
       lw.first_node = lbvh_first;

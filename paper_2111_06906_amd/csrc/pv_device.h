@@ -163,25 +163,45 @@ struct SceneDev {
 // Device scratch of the per-frame object hierarchy rebuild (linear BVH over
 // 30-bit Morton codes): sort keys (object << 30 | Morton code of the
 // triangle's centroid) and values (dynamic triangle record) in two buffers,
-// per-tile digit histograms and their scan, parent links and arrival counters
-// of the rebuilt nodes (indexed from the scene's first rebuilt node), and the
-// objects' centroid boxes.
+// per-tile digit counts (and their scan for large sorts), parent links of the
+// radix trees, a pyramid of box unions over the sorted triangles (level l
+// entry k: positions [k 2^l, (k+1) 2^l)), each object's tree depth and
+// centroid box.
 struct LbvhWork {
   uint64_t* key[2];
   uint32_t* val[2];
   uint32_t* hist;        // [256][tiles] digit counts of a sort pass
-  uint32_t* hoff;        // their exclusive scan
+  uint32_t* hoff;        // their exclusive scan (sorts of more than kFusedTiles tiles)
   uint32_t* htotal;      // [1]
   uint32_t* scan_tmp;    // scan_tmp_words(256 * tiles)
-  int32_t* parent_leaf;  // [n_dyn] by sorted position: parent node, -1 for a one-triangle object
+  int32_t* parent_leaf;  // [n_dyn] by sorted position: parent node (scene index)
   int32_t* parent_node;  // [nodes] parent node, -1 at an object's root
-  uint32_t* flag;        // [nodes] children completed so far
-  uint32_t* height;      // [nodes] levels below each node
+  float4* pyr;           // [2 * pyr_entries]: lo, hi of each pyramid entry
+  uint32_t* odepth;      // [n_obj] deepest leaf of each rebuilt tree
   float* cbox;           // [n_obj][6] centroid bounds
   uint32_t n_dyn;        // dynamic triangles of the scene
   uint32_t first_node;   // scene node index of the first rebuilt node
   uint32_t n_nodes;      // rebuilt nodes of all objects
 };
+
+// first entry of pyramid level l over n positions (level sizes n, ceil(n/2), ...)
+__host__ __device__ inline uint32_t pyr_level(uint32_t n, int l) {
+  uint32_t off = 0, m = n;
+  for (int i = 0; i < l; ++i) {
+    off += m;
+    m = (m + 1) / 2;
+  }
+  return off;
+}
+// entries of the whole pyramid (levels down to a single entry)
+__host__ __device__ inline uint32_t pyr_entries(uint32_t n) {
+  uint32_t off = 0, m = n;
+  while (m > 1) {
+    off += m;
+    m = (m + 1) / 2;
+  }
+  return off + m;
+}
 
 // Verification work lists (device scratch).  A task is one segment whose ray
 // reaches a moved object's box: (global path id << 4) | segment.  Each path

@@ -21,6 +21,8 @@ hipError_t launch_transform_objects(SceneDev* scenes, const uint2* xf_tiles, uin
 hipError_t launch_rebuild_objects(SceneDev* scenes, LbvhWork W, uint32_t n_obj, uint32_t max_depth, hipStream_t s);
 // sort tiles of the rebuild for n_dyn triangles (W.hist holds 256 per tile)
 uint32_t lbvh_sort_tiles(uint32_t n_dyn);
+// entries of W.pyr (two float4 each) for n_dyn triangles
+uint32_t lbvh_pyramid_entries(uint32_t n_dyn);
 hipError_t launch_build_top(SceneDev* scenes, int n_scenes, hipStream_t s);
 // Verification of every path of the tiles: scan, task list, traversal of the
 // box-hit segments, information words of the paths with tasks, per-tile

@@ -6,23 +6,29 @@
 //   k_lbvh_bounds   one workgroup per object: centroid box of its triangles
 //   k_lbvh_keys     one thread per dynamic triangle: key (object << 30 |
 //                   Morton code), value (its record)
-//   k_lbvh_hist /   stable least-significant-digit radix sort of the keys,
-//   launch_scan /   8 bits per pass: digit counts per tile, their scan, and a
-//   k_lbvh_scatter  scatter that keeps the order of equal digits (wave ballots
-//                   rank the keys of one digit inside a wave)
+//   k_lbvh_hist /   stable least-significant-digit radix sort of the keys, 8
+//   k_lbvh_scatter  bits per pass: digit counts per tile, then a scatter that
+//                   keeps the order of equal digits (wave ballots rank the keys
+//                   of one digit inside a wave); the scatter scans the counts
+//                   itself when there are few tiles
+//   k_lbvh_leaves / padded triangle boxes in sorted order and a pyramid of
+//   k_lbvh_pyramid  their unions over aligned power-of-two blocks
 //   k_lbvh_nodes    one thread per internal node of each object's radix tree:
 //                   its key range and split (the object's keys are contiguous
-//                   after the sort); equal keys are ordered by position
-//   k_lbvh_boxes    one thread per leaf climbs towards the root; at each node
-//                   the second child to finish computes the node's boxes and
-//                   height (an arrival counter per node; no thread ever waits)
+//                   after the sort; equal keys are ordered by position), and
+//                   its two child boxes as unions over the children's position
+//                   ranges, each assembled from O(log n) pyramid entries: no
+//                   node waits for another
+//   k_lbvh_depth    one thread per leaf counts its ancestors
+//   k_lbvh_finish   one thread per object: the rebuilt tree becomes the
+//                   object's hierarchy unless it is deeper than the traversal
+//                   stacks allow (up to 30 + ceil(log2 n) levels are possible:
+//                   the common prefix of a node's keys grows from a node to its
+//                   children); the refit upload-time topology serves otherwise
 //
 // Leaves hold one triangle and name its record directly, so triangles are
-// never moved.  A radix tree can be deeper than the traversal stack allows
-// (up to 30 + ceil(log2 n) levels: the common prefix of a node's keys grows
-// from a node to its children, and the varying key bits are the Morton code
-// and the position); an object whose rebuilt tree is deeper than the depth
-// allowance keeps its refit upload-time topology for the frame.
+// never moved.  The boxes are the same unions of the same padded triangle
+// boxes that a bottom-up refit computes.
 #include "pv_launch.h"
 
 namespace pv {
@@ -33,8 +39,12 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems;  // keys per sort tile
 constexpr int kDigits = 256;
-constexpr int kSortPasses = 5;  // 8-bit digits over the 36 key bits (6 object + 30 Morton)
+constexpr int kSortPasses = 5;          // 8-bit digits over the 36 key bits (6 object + 30 Morton)
+constexpr uint32_t kFusedTiles = 256;   // up to this many tiles the scatter scans the counts itself
+constexpr int kLowLevels = 8;           // pyramid levels built inside one 256-entry workgroup
+constexpr uint32_t kDepthGuard = 64;    // > 30 + 28: no radix tree here is that deep
 static_assert(kSortThreads == kDigits, "one thread per digit in the tile histograms");
+static_assert(kBlock == (1 << kLowLevels), "one workgroup of the leaf kernel spans the low pyramid levels");
 static_assert(PV_MAX_OBJECTS <= 64, "object ids fit the 6 key bits above the Morton code");
 
 __device__ inline uint32_t lane_of() { return threadIdx.x & 63u; }
@@ -78,6 +88,63 @@ __device__ inline uint32_t quantise(float c, float lo, float hi) {
   return min((uint32_t)fmaxf(u * 1024.0f, 0.0f), 1023u);
 }
 
+struct Box {
+  float3 lo, hi;
+};
+
+__device__ inline Box empty_box() {
+  return {make_float3(__builtin_inff(), __builtin_inff(), __builtin_inff()),
+          make_float3(-__builtin_inff(), -__builtin_inff(), -__builtin_inff())};
+}
+
+__device__ inline Box join(const Box& a, const Box& b) {
+  return {make_float3(fminf(a.lo.x, b.lo.x), fminf(a.lo.y, b.lo.y), fminf(a.lo.z, b.lo.z)),
+          make_float3(fmaxf(a.hi.x, b.hi.x), fmaxf(a.hi.y, b.hi.y), fmaxf(a.hi.z, b.hi.z))};
+}
+
+// a leaf's box: the padded box of its triangle (as the refit computes it)
+__device__ inline Box tri_box(const Tri& t) {
+  return {make_float3(pad_lo(fminf(fminf(t.t0.x, t.t1.x), t.t2.x)), pad_lo(fminf(fminf(t.t0.y, t.t1.y), t.t2.y)),
+                      pad_lo(fminf(fminf(t.t0.z, t.t1.z), t.t2.z))),
+          make_float3(pad_hi(fmaxf(fmaxf(t.t0.x, t.t1.x), t.t2.x)), pad_hi(fmaxf(fmaxf(t.t0.y, t.t1.y), t.t2.y)),
+                      pad_hi(fmaxf(fmaxf(t.t0.z, t.t1.z), t.t2.z)))};
+}
+
+__device__ inline Box pyr_get(const float4* pyr, uint32_t i) {
+  const float4 a = pyr[2 * i], b = pyr[2 * i + 1];
+  return {make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z)};
+}
+
+__device__ inline void pyr_put(float4* pyr, uint32_t i, const Box& v) {
+  pyr[2 * i] = make_float4(v.lo.x, v.lo.y, v.lo.z, 0.0f);
+  pyr[2 * i + 1] = make_float4(v.hi.x, v.hi.y, v.hi.z, 0.0f);
+}
+
+// union of the boxes at sorted positions [a, b) from the pyramid: at each
+// level the blocks at the range's ragged ends, then one level up
+__device__ inline Box range_box(const float4* pyr, uint32_t n, uint32_t a, uint32_t b) {
+  Box r = empty_box();
+  uint32_t off = 0, m = n;
+  while (a < b) {
+    if (a & 1u) r = join(r, pyr_get(pyr, off + a++));
+    if (b & 1u) r = join(r, pyr_get(pyr, off + --b));
+    a >>= 1;
+    b >>= 1;
+    off += m;
+    m = (m + 1) / 2;
+  }
+  return r;
+}
+
+// length of the common prefix of the keys at positions i and j of an object's
+// sorted range (ties broken by position); -1 outside the range
+__device__ inline int prefix(const uint64_t* __restrict__ key, uint32_t start, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  const uint64_t a = key[start + (uint32_t)i], b = key[start + (uint32_t)j];
+  if (a != b) return __clzll((long long)(a ^ b));
+  return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(1024) void k_lbvh_bounds(const SceneDev* __restrict__ scenes, LbvhWork W) {
@@ -110,6 +177,7 @@ __global__ __launch_bounds__(1024) void k_lbvh_bounds(const SceneDev* __restrict
     for (uint32_t q = 1; q < blockDim.x / 64; ++q) v = k < 3 ? fminf(v, red[k][q]) : fmaxf(v, red[k][q]);
     W.cbox[6 * o + k] = v;
   }
+  if (threadIdx.x == 0) W.odepth[o] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_lbvh_keys(const SceneDev* __restrict__ scenes, LbvhWork W) {
@@ -142,22 +210,44 @@ __global__ __launch_bounds__(kSortThreads) void k_lbvh_hist(const uint64_t* __re
 }
 
 // Stable scatter of one tile: keys are taken in index order, kSortThreads at
-// a time; a key's slot is the scanned start of its (digit, tile), plus the
-// keys of its digit placed by earlier rounds, by lower waves of this round and
-// by lower lanes of its wave (lanes of equal digit found by ballots over the
-// digit's bits).
+// a time; a key's slot is the first slot of its (digit, tile), plus the keys
+// of its digit placed by earlier rounds, by lower waves of this round and by
+// lower lanes of its wave (lanes of equal digit found by ballots over the
+// digit's bits).  hoff == nullptr: the first slots are computed here from the
+// raw counts (all digits' totals, scanned, plus this digit's count in the
+// earlier tiles).
 __global__ __launch_bounds__(kSortThreads) void k_lbvh_scatter(const uint64_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                               uint32_t n, int shift, const uint32_t* __restrict__ hoff,
-                                                               uint32_t tiles) {
+                                                               uint32_t n, int shift, const uint32_t* __restrict__ hist,
+                                                               const uint32_t* __restrict__ hoff, uint32_t tiles) {
   constexpr int kWaves = kSortThreads / 64;
   __shared__ uint32_t run[kDigits];
   __shared__ uint32_t wc[kWaves][kDigits];
   const uint32_t tid = threadIdx.x, w = tid >> 6;
-  run[tid] = hoff[tid * tiles + blockIdx.x];
+  if (hoff) {
+    run[tid] = hoff[tid * tiles + blockIdx.x];
+  } else {
+    uint32_t tot = 0, mine = 0;
+    for (uint32_t t = 0; t < tiles; ++t) {
+      const uint32_t c = hist[tid * tiles + t];
+      tot += c;
+      mine += t < blockIdx.x ? c : 0u;
+    }
+    uint32_t x = tot;  // inclusive scan of the digit totals: waves, then wave sums
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if ((int)lane_of() >= o) x += y;
+    }
+    if (lane_of() == 63) wc[0][w] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < w; ++q) before += wc[0][q];
+    run[tid] = before + x - tot + mine;
+  }
   const uint32_t base = blockIdx.x * kSortTile;
   for (int s = 0; s < kSortItems; ++s) {
+    __syncthreads();
     for (int q = 0; q < kWaves; ++q) wc[q][tid] = 0;
     __syncthreads();
     const uint32_t e = base + (uint32_t)s * kSortThreads + tid;
@@ -192,18 +282,53 @@ __global__ __launch_bounds__(kSortThreads) void k_lbvh_scatter(const uint64_t* _
   }
 }
 
-namespace {
-
-// length of the common prefix of the keys at positions i and j of an object's
-// sorted range (ties broken by position); -1 outside the range
-__device__ inline int prefix(const uint64_t* __restrict__ key, uint32_t start, int n, int i, int j) {
-  if (j < 0 || j >= n) return -1;
-  const uint64_t a = key[start + (uint32_t)i], b = key[start + (uint32_t)j];
-  if (a != b) return __clzll((long long)(a ^ b));
-  return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+// level 0 of the pyramid (padded triangle boxes in sorted order) and the
+// levels 1..kLowLevels of each aligned 256-position block
+__global__ __launch_bounds__(kBlock) void k_lbvh_leaves(const SceneDev* __restrict__ scenes, LbvhWork W,
+                                                        const uint32_t* __restrict__ val) {
+  __shared__ float3 slo[kBlock], shi[kBlock];
+  const SceneDev& S = scenes[0];
+  const uint32_t n = W.n_dyn;
+  const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+  Box b = empty_box();
+  if (g < n) {
+    b = tri_box(S.tris[S.n_static + val[g]]);
+    pyr_put(W.pyr, g, b);
+  }
+  uint32_t off = 0, m = n;
+  for (int l = 1; l <= kLowLevels; ++l) {
+    off += m;
+    m = (m + 1) / 2;
+    slo[threadIdx.x] = b.lo;
+    shi[threadIdx.x] = b.hi;
+    __syncthreads();
+    const uint32_t cnt = (uint32_t)kBlock >> l;
+    if (threadIdx.x < cnt) {
+      const uint32_t i = 2 * threadIdx.x;
+      b = join(Box{slo[i], shi[i]}, Box{slo[i + 1], shi[i + 1]});
+      const uint32_t k = (blockIdx.x * kBlock >> l) + threadIdx.x;
+      if (k < m) pyr_put(W.pyr, off + k, b);
+    }
+    __syncthreads();
+  }
 }
 
-}  // namespace
+// the pyramid levels above kLowLevels, one workgroup
+__global__ __launch_bounds__(1024) void k_lbvh_pyramid(LbvhWork W) {
+  const uint32_t n = W.n_dyn;
+  uint32_t off = pyr_level(n, kLowLevels), m = (n + (1u << kLowLevels) - 1) >> kLowLevels;
+  while (m > 1) {
+    const uint32_t up = (m + 1) / 2;
+    for (uint32_t k = threadIdx.x; k < up; k += blockDim.x) {
+      Box b = pyr_get(W.pyr, off + 2 * k);
+      if (2 * k + 1 < m) b = join(b, pyr_get(W.pyr, off + 2 * k + 1));
+      pyr_put(W.pyr, off + m + k, b);
+    }
+    __syncthreads();
+    off += m;
+    m = up;
+  }
+}
 
 __global__ __launch_bounds__(kBlock) void k_lbvh_nodes(SceneDev* __restrict__ scenes, LbvhWork W,
                                                        const uint64_t* __restrict__ key,
@@ -234,11 +359,12 @@ __global__ __launch_bounds__(kBlock) void k_lbvh_nodes(SceneDev* __restrict__ sc
     if (t == 1) break;
   }
   const int split = i + s * d + min(d, 0);
+  const int first = min(i, j), last = max(i, j);
   const uint32_t node = ob.lbvh_base + (uint32_t)i;
   int32_t ch[2];
   for (int side = 0; side < 2; ++side) {
     const int c = split + side;
-    const bool leaf = side == 0 ? min(i, j) == c : max(i, j) == c;
+    const bool leaf = side == 0 ? first == c : last == c;
     if (leaf) {
       ch[side] = leaf_code(S.n_static + val[start + (uint32_t)c], 1);
       W.parent_leaf[start + (uint32_t)c] = (int32_t)node;
@@ -247,97 +373,80 @@ __global__ __launch_bounds__(kBlock) void k_lbvh_nodes(SceneDev* __restrict__ sc
       W.parent_node[ob.lbvh_base + (uint32_t)c - W.first_node] = (int32_t)node;
     }
   }
-  S.nodes[node].d = make_int4(ch[0], ch[1], -1, 0);
-  W.flag[node - W.first_node] = 0;
+  const Box b0 = range_box(W.pyr, W.n_dyn, start + (uint32_t)first, start + (uint32_t)split + 1);
+  const Box b1 = range_box(W.pyr, W.n_dyn, start + (uint32_t)split + 1, start + (uint32_t)last + 1);
+  Node& nd = S.nodes[node];
+  nd.a = make_float4(b0.lo.x, b0.lo.y, b0.lo.z, b0.hi.x);
+  nd.b = make_float4(b0.hi.y, b0.hi.z, b1.lo.x, b1.lo.y);
+  nd.c = make_float4(b1.lo.z, b1.hi.x, b1.hi.y, b1.hi.z);
+  nd.d = make_int4(ch[0], ch[1], -1, 0);
   if (i == 0) W.parent_node[node - W.first_node] = -1;
 }
 
-namespace {
-
-__device__ inline void tri_box(const Tri& t, float* b) {
-  b[0] = pad_lo(fminf(fminf(t.t0.x, t.t1.x), t.t2.x));
-  b[1] = pad_lo(fminf(fminf(t.t0.y, t.t1.y), t.t2.y));
-  b[2] = pad_lo(fminf(fminf(t.t0.z, t.t1.z), t.t2.z));
-  b[3] = pad_hi(fmaxf(fmaxf(t.t0.x, t.t1.x), t.t2.x));
-  b[4] = pad_hi(fmaxf(fmaxf(t.t0.y, t.t1.y), t.t2.y));
-  b[5] = pad_hi(fmaxf(fmaxf(t.t0.z, t.t1.z), t.t2.z));
+// depth of every leaf (its internal ancestors), maximum per object
+__global__ __launch_bounds__(kBlock) void k_lbvh_depth(const SceneDev* __restrict__ scenes, LbvhWork W,
+                                                       const uint64_t* __restrict__ key) {
+  const SceneDev& S = scenes[0];
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = g < W.n_dyn;
+  uint32_t o = 0, depth = 0;
+  if (valid) {
+    o = (uint32_t)(key[g] >> 30);
+    // every non-root node has one parent and the root none, so the climb
+    // ends at the root; the step bound (above any radix tree's depth over
+    // 2^28 triangles) only keeps a damaged tree from looping
+    if (S.objs[o].n_tris > 1)
+      for (int32_t p = W.parent_leaf[g]; p >= 0 && depth < kDepthGuard; p = W.parent_node[(uint32_t)p - W.first_node])
+        ++depth;
+  }
+  // one atomic per wave when the wave's leaves share an object
+  const uint64_t act = __ballot(valid);
+  if (!act) return;
+  const uint32_t lead = (uint32_t)__ffsll((long long)act) - 1u;
+  const uint32_t o0 = __shfl(o, (int)lead, 64);
+  if (__ballot(valid && o != o0) == 0) {
+    uint32_t m = valid ? depth : 0u;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor(m, off, 64));
+    if (lane_of() == lead) atomicMax(&W.odepth[o0], m);
+  } else if (valid) {
+    atomicMax(&W.odepth[o], depth);
+  }
 }
 
-// box of a child while the hierarchy is being built: a leaf's padded triangle
-// box, or the union of a node's two child boxes, which another thread of this
-// launch wrote (read at device scope, past this compute unit's cache)
-__device__ inline void rebuilt_child_box(const SceneDev& S, int32_t code, float* b) {
-  if (code < 0) {
-    tri_box(S.tris[leaf_first(code)], b);
-    return;
-  }
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(S.nodes + code);
-  float f[12];
-  for (int k = 0; k < 12; ++k)
-    f[k] = __uint_as_float(__hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  for (int k = 0; k < 3; ++k) {
-    b[k] = fminf(f[k], f[6 + k]);
-    b[3 + k] = fmaxf(f[3 + k], f[9 + k]);
-  }
-}
-
-}  // namespace
-
-__global__ __launch_bounds__(kBlock) void k_lbvh_boxes(SceneDev* __restrict__ scenes, LbvhWork W,
-                                                       const uint64_t* __restrict__ key,
-                                                       const uint32_t* __restrict__ val, uint32_t max_depth) {
+__global__ void k_lbvh_finish(SceneDev* __restrict__ scenes, LbvhWork W, const uint32_t* __restrict__ val,
+                              uint32_t max_depth) {
   SceneDev& S = scenes[0];
   ObjDev* objs = const_cast<ObjDev*>(S.objs);
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= W.n_dyn) return;
-  const uint32_t o = (uint32_t)(key[g] >> 30);
-  if (S.objs[o].n_tris == 1) {
-    const int32_t leaf = leaf_code(S.n_static + val[g], 1);
-    float b[6];
-    tri_box(S.tris[leaf_first(leaf)], b);
-    for (int k = 0; k < 6; ++k) S.obj_aabb[6 * o + k] = b[k];
-    objs[o].root = leaf;
-    return;
+  const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= S.n_obj) return;
+  const ObjDev ob = S.objs[o];
+  Box b;
+  int32_t root;
+  if (ob.n_tris == 1) {
+    root = leaf_code(S.n_static + val[ob.tri_base], 1);
+    b = tri_box(S.tris[leaf_first(root)]);
+  } else {
+    // the rebuilt tree replaces the refit topology only within the depth the
+    // traversal stacks were sized for
+    if (W.odepth[o] > max_depth) return;
+    root = (int32_t)ob.lbvh_base;
+    b = range_box(W.pyr, W.n_dyn, ob.tri_base, ob.tri_base + ob.n_tris);
   }
-  int32_t p = W.parent_leaf[g];
-  while (true) {
-    // the first child to arrive stops; the second builds the node: every
-    // node is completed exactly once, after both of its children
-    __threadfence();
-    if (atomicAdd(&W.flag[(uint32_t)p - W.first_node], 1u) == 0u) return;
-    __threadfence();
-    Node& nd = S.nodes[p];
-    const int4 ch = nd.d;
-    float b[12];
-    rebuilt_child_box(S, ch.x, b);
-    rebuilt_child_box(S, ch.y, b + 6);
-    nd.a = make_float4(b[0], b[1], b[2], b[3]);
-    nd.b = make_float4(b[4], b[5], b[6], b[7]);
-    nd.c = make_float4(b[8], b[9], b[10], b[11]);
-    uint32_t h = 0;  // levels below this node
-    for (int side = 0; side < 2; ++side) {
-      const int32_t c = side ? ch.y : ch.x;
-      const uint32_t hc = c < 0 ? 0u
-                                : __hip_atomic_load(&W.height[(uint32_t)c - W.first_node], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-      h = max(h, hc + 1);
-    }
-    W.height[(uint32_t)p - W.first_node] = h;
-    const int32_t up = W.parent_node[(uint32_t)p - W.first_node];
-    if (up < 0) {
-      // the rebuilt tree replaces the refit topology only within the depth
-      // the traversal stacks were sized for
-      if (h <= max_depth) {
-        for (int k = 0; k < 3; ++k) {
-          S.obj_aabb[6 * o + k] = fminf(b[k], b[6 + k]);
-          S.obj_aabb[6 * o + 3 + k] = fmaxf(b[3 + k], b[9 + k]);
-        }
-        objs[o].root = p;
-      }
-      return;
-    }
-    p = up;
-  }
+  S.obj_aabb[6 * o + 0] = b.lo.x;
+  S.obj_aabb[6 * o + 1] = b.lo.y;
+  S.obj_aabb[6 * o + 2] = b.lo.z;
+  S.obj_aabb[6 * o + 3] = b.hi.x;
+  S.obj_aabb[6 * o + 4] = b.hi.y;
+  S.obj_aabb[6 * o + 5] = b.hi.z;
+  objs[o].root = root;
+}
+
+uint32_t lbvh_sort_tiles(uint32_t n_dyn) { return (n_dyn + kSortTile - 1) / kSortTile; }
+
+// the leaf kernel writes levels 1..kLowLevels even where the pyramid has
+// fewer levels (their entries past the top are never read)
+uint32_t lbvh_pyramid_entries(uint32_t n_dyn) {
+  return std::max(pyr_entries(n_dyn), pyr_level(n_dyn, kLowLevels + 1));
 }
 
 hipError_t launch_rebuild_objects(SceneDev* scenes, LbvhWork W, uint32_t n_obj, uint32_t max_depth, hipStream_t s) {
@@ -350,17 +459,22 @@ hipError_t launch_rebuild_objects(SceneDev* scenes, LbvhWork W, uint32_t n_obj, 
   for (int pass = 0; pass < kSortPasses; ++pass) {
     const int shift = 8 * pass;
     hipLaunchKernelGGL(k_lbvh_hist, dim3(tiles), dim3(kSortThreads), 0, s, W.key[src], W.n_dyn, shift, W.hist, tiles);
-    hipError_t e = launch_scan(W.hist, W.hoff, kDigits * tiles, W.htotal, W.scan_tmp, s);
-    if (e != hipSuccess) return e;
+    const uint32_t* hoff = nullptr;
+    if (tiles > kFusedTiles) {
+      hipError_t e = launch_scan(W.hist, W.hoff, kDigits * tiles, W.htotal, W.scan_tmp, s);
+      if (e != hipSuccess) return e;
+      hoff = W.hoff;
+    }
     hipLaunchKernelGGL(k_lbvh_scatter, dim3(tiles), dim3(kSortThreads), 0, s, W.key[src], W.val[src], W.key[src ^ 1],
-                       W.val[src ^ 1], W.n_dyn, shift, W.hoff, tiles);
+                       W.val[src ^ 1], W.n_dyn, shift, W.hist, hoff, tiles);
     src ^= 1;
   }
+  hipLaunchKernelGGL(k_lbvh_leaves, dim3(nb), dim3(kBlock), 0, s, scenes, W, W.val[src]);
+  if (W.n_dyn > (1u << kLowLevels)) hipLaunchKernelGGL(k_lbvh_pyramid, dim3(1), dim3(1024), 0, s, W);
   hipLaunchKernelGGL(k_lbvh_nodes, dim3(nb), dim3(kBlock), 0, s, scenes, W, W.key[src], W.val[src]);
-  hipLaunchKernelGGL(k_lbvh_boxes, dim3(nb), dim3(kBlock), 0, s, scenes, W, W.key[src], W.val[src], max_depth);
+  hipLaunchKernelGGL(k_lbvh_depth, dim3(nb), dim3(kBlock), 0, s, scenes, W, W.key[src]);
+  hipLaunchKernelGGL(k_lbvh_finish, dim3((n_obj + 63) / 64), dim3(64), 0, s, scenes, W, W.val[src], max_depth);
   return hipGetLastError();
 }
-
-uint32_t lbvh_sort_tiles(uint32_t n_dyn) { return (n_dyn + kSortTile - 1) / kSortTile; }
 
 }  // namespace pv
