@@ -596,7 +596,19 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
                                                          const uint32_t* __restrict__ gbase, int n_scenes,
                                                          VerifyWork W, int min_active) {
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
+  __shared__ MovedSet M;                // single scene: the moved objects' boxes
+  __shared__ int32_t mroot[PV_MAX_OBJECTS];  // and their hierarchies' roots
   const StackCol col = (StackCol)(sstack + kBlock + threadIdx.x);  // entry 0 of the column; entry -1 spare
+  if (kSingle) {
+    if (threadIdx.x < 64) {
+      const SceneDev& S0 = scenes[0];
+      const uint32_t o = threadIdx.x;
+      const bool mv = o < S0.n_obj && G(S0.obj_moved)[o] != 0;
+      const uint64_t mm = __ballot(mv);
+      if (mv) mroot[__popcll(mm & lanemask_lt())] = G(S0.objs)[o].root;
+    }
+    load_moved(scenes[0], M);  // ends with a barrier
+  }
   const uint32_t total = *W.total;
   const uint32_t n_waves = gridDim.x * (kBlock / 64);
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -633,8 +645,24 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
                                     : xyz(G(S->pos)[(size_t)(j - 1) * stride + q]);
             const float3 b = xyz(G(S->pos)[(size_t)j * stride + q]);
             r = segment_ray(a, b, S->eps_end);
-            walk_start(w, G(S->top)[1], r.tmax, col);
-            busy = true;
+            int32_t root = G(S->top)[1];
+            if (kSingle) {
+              // the objects whose boxes the segment reaches, from LDS: one
+              // object is walked from its own root (its box is the only one
+              // of the moved-object tree the ray enters); several, through
+              // the moved-object tree; none, not at all
+              uint32_t nh = 0;
+              int32_t only = kRootNone;
+              for (int i = 0; i < M.n; ++i) {
+                const float4 lo = M.lo[i], hi = M.hi[i];
+                const bool h = box_entry(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, r, r.tmax) != __builtin_inff();
+                nh += h ? 1u : 0u;
+                only = h ? mroot[i] : only;
+              }
+              root = nh == 0 ? kRootNone : (nh == 1 ? only : root);
+            }
+            walk_start(w, root, r.tmax, col);
+            busy = root != kRootNone;
           }
         }
       }
