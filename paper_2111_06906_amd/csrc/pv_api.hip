@@ -73,6 +73,7 @@ struct pv_ctx {
            *d_scan_tmp = nullptr;
   float* d_partial = nullptr;
   pv::VerifyWork vw{};  // verification task lists
+  pv::OrderWork ow{};   // re-trace work order
   // tuning (pv_set_tuning / pv_autotune)
   int retrace_variant = 0;
   // defaults: the settings the autotuner picks on the 3M-path, 380k-triangle
@@ -102,6 +103,7 @@ struct pv_batch {
            *d_frame = nullptr, *d_scan_tmp = nullptr;
   uint32_t n_counts = 0;
   pv::VerifyWork vw{};
+  pv::OrderWork ow{};
   float *d_out_pos = nullptr, *d_out_en = nullptr;
   uint32_t capacity = 0;
   const float** d_obj_in = nullptr;
@@ -967,6 +969,12 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->d_block_cnt, nb));
     CK(dalloc(A, &ctx->d_offsets, nb));
     CK(dalloc(A, &ctx->d_queue, max_paths));
+    ctx->ow.tiles = pv::order_tiles(max_paths);
+    CK(dalloc(A, &ctx->ow.queue, max_paths));
+    CK(dalloc(A, &ctx->ow.hist, 8 * (size_t)ctx->ow.tiles));
+    CK(dalloc(A, &ctx->ow.hoff, 8 * (size_t)ctx->ow.tiles));
+    CK(dalloc(A, &ctx->ow.htotal, 1));
+    CK(dalloc(A, &ctx->ow.scan_tmp, pv::scan_tmp_words(8 * ctx->ow.tiles)));
     CK(dalloc(A, &ctx->d_qcount, 1));
     CK(dalloc(A, &ctx->d_pcounts, (size_t)nb * max_bounces));
     CK(dalloc(A, &ctx->d_poffsets, (size_t)nb * max_bounces));
@@ -1066,7 +1074,7 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   uint32_t blocks = (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu);
   CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, threshold, seed,
                         frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stack_entries,
-                        ctx->walk_min_active, ctx->stream));
+                        ctx->walk_min_active, ctx->ow, ctx->stream));
   return PV_OK;
 }
 
@@ -1254,7 +1262,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
       if (e == hipSuccess)
         e = pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, threshold,
                                seed, frame, nullptr, nullptr, (uint32_t)(ctx->n_cu * bpc), v, ctx->stack_entries,
-                               min_active, s);
+                               min_active, ctx->ow, s);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0;
@@ -1388,7 +1396,7 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->T, b->seed, 0,
                         b->d_frame, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
-                        b->stack_entries, ctx->walk_min_active, st));
+                        b->stack_entries, ctx->walk_min_active, b->ow, st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
   CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, b->d_scan_tmp, st));
   CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,
@@ -1479,6 +1487,10 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
               chk(dalloc(A, &b->vw.tmp, task_cap)) && chk(dalloc(A, &b->vw.tasks, task_cap)) &&
               chk(dalloc(A, &b->vw.tcount, ptiles.size())) && chk(dalloc(A, &b->vw.toff, ptiles.size())) &&
               chk(dalloc(A, &b->vw.total, 1)) && chk(dalloc(A, &b->vw.first, total_paths)) &&
+              (b->ow.tiles = pv::order_tiles((uint32_t)total_paths), true) &&
+              chk(dalloc(A, &b->ow.queue, total_paths)) && chk(dalloc(A, &b->ow.hist, 8 * (size_t)b->ow.tiles)) &&
+              chk(dalloc(A, &b->ow.hoff, 8 * (size_t)b->ow.tiles)) && chk(dalloc(A, &b->ow.htotal, 1)) &&
+              chk(dalloc(A, &b->ow.scan_tmp, pv::scan_tmp_words(8 * b->ow.tiles))) &&
               chk(dalloc(A, &b->vw.part, 4 * ptiles.size() + 2 * (size_t)pv::verify_finish_blocks(verify_blocks_max(ctx)))) &&
               chk(upload(A, &b->d_obj_in, const_cast<const float**>(d_obj_xf), n, s)) &&
               chk(upload(A, &b->d_light_in, const_cast<const float**>(d_light_xf), n, s));

@@ -1473,6 +1473,95 @@ __global__ void k_reduce_partials(const float* __restrict__ partial, uint32_t n_
 }
 
 // ---------------------------------------------------------------------------
+// Re-trace work order.  A path's re-trace costs up to one ray per segment from
+// its first invalid one on, so the queue (ascending path ids, as the caller
+// sees it) is handed to the persistent re-trace kernel reordered by that
+// segment, smallest first (a stable counting sort over kOrderBuckets
+// buckets): every wave's interleaved share then starts with its long paths
+// and ends with short ones, and the waves finish closer together.
+
+constexpr uint32_t kOrderTile = 2048;  // queue entries per tile of the reorder
+constexpr int kOrderBuckets = 8;
+
+__device__ inline uint32_t order_bucket(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, uint32_t gp) {
+  const uint32_t s = scene_of(gbase, n_scenes, gp);
+  const SceneDev& S = scenes[s];
+  const uint32_t w = G(S.info)[gp - gbase[s]];
+  const uint32_t n = min(info_nseg(w), S.B), k = info_start(w);
+  return min(k < n ? k : 0u, (uint32_t)kOrderBuckets - 1u);  // k >= n: a new light sample, a full path
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_hist(const SceneDev* __restrict__ scenes,
+                                                       const uint32_t* __restrict__ gbase, int n_scenes,
+                                                       const uint32_t* __restrict__ queue,
+                                                       const uint32_t* __restrict__ qcount, uint32_t* __restrict__ hist,
+                                                       uint32_t tiles) {
+  __shared__ uint32_t h[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t count = *qcount, base = blockIdx.x * kOrderTile;
+  const uint32_t end = min(base + kOrderTile, count);
+  for (uint32_t e = base + threadIdx.x; e < end; e += kBlock)
+    atomicAdd(&h[order_bucket(scenes, gbase, n_scenes, queue[e])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets) hist[threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// stable scatter of one tile: entries in index order, kBlock at a time; an
+// entry's slot is its (bucket, tile) start plus the entries of its bucket
+// placed by earlier rounds, lower waves and lower lanes (ballots over the
+// bucket's bits)
+__global__ __launch_bounds__(kBlock) void k_order_scatter(const SceneDev* __restrict__ scenes,
+                                                          const uint32_t* __restrict__ gbase, int n_scenes,
+                                                          const uint32_t* __restrict__ queue,
+                                                          const uint32_t* __restrict__ qcount,
+                                                          const uint32_t* __restrict__ hoff, uint32_t tiles,
+                                                          uint32_t* __restrict__ out) {
+  constexpr int kWaves = kBlock / 64;
+  static_assert(kOrderBuckets == 8, "three bucket bits");
+  __shared__ uint32_t run[kOrderBuckets];
+  __shared__ uint32_t wc[kWaves][kOrderBuckets];
+  const uint32_t count = *qcount, base = blockIdx.x * kOrderTile;
+  if (base >= count) return;  // uniform over the block
+  const uint32_t tid = threadIdx.x, w = tid >> 6;
+  if (tid < kOrderBuckets) run[tid] = hoff[tid * tiles + blockIdx.x];
+  for (uint32_t r = 0; r < kOrderTile / kBlock; ++r) {
+    __syncthreads();
+    if (tid < kWaves * kOrderBuckets) wc[tid / kOrderBuckets][tid % kOrderBuckets] = 0;
+    __syncthreads();
+    const uint32_t e = base + r * kBlock + tid;
+    const bool valid = e < count;
+    uint32_t gp = 0, b = 0;
+    if (valid) {
+      gp = queue[e];
+      b = order_bucket(scenes, gbase, n_scenes, gp);
+    }
+    uint64_t peers = __ballot(valid);
+    for (int bit = 0; bit < 3; ++bit) {
+      const bool set = ((b >> bit) & 1u) != 0;
+      const uint64_t m = __ballot(valid && set);
+      peers &= set ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+    if (valid && rank == 0) wc[w][b] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t before = 0;
+      for (uint32_t q = 0; q < w; ++q) before += wc[q][b];
+      out[run[b] + before + rank] = gp;
+    }
+    __syncthreads();
+    if (tid < kOrderBuckets) {
+      uint32_t add = 0;
+      for (int q = 0; q < kWaves; ++q) add += wc[q][tid];
+      run[tid] += add;
+    }
+  }
+}
+
+uint32_t order_tiles(uint32_t max_entries) { return (max_entries + kOrderTile - 1) / kOrderTile; }
+
+// ---------------------------------------------------------------------------
 // launch wrappers (host side)
 
 hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
@@ -1588,11 +1677,19 @@ static void retrace_variant(int v, dim3 g, size_t lds, hipStream_t s, const Scen
   }
 }
 
-hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
+hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue_in,
                           const uint32_t* qcount, float T, uint64_t seed, uint32_t frame,
                           const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
-                          int min_active, hipStream_t s) {
+                          int min_active, const OrderWork& O, hipStream_t s) {
   if (stack < 2 || stack > (uint32_t)kMaxStack || min_active < 1 || min_active > 64) return hipErrorInvalidValue;
+  // the queue reordered by first invalid segment (see k_order_hist)
+  hipLaunchKernelGGL(k_order_hist, dim3(O.tiles), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue_in, qcount, O.hist,
+                     O.tiles);
+  hipError_t e = launch_scan(O.hist, O.hoff, kOrderBuckets * O.tiles, O.htotal, O.scan_tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_order_scatter, dim3(O.tiles), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue_in, qcount,
+                     O.hoff, O.tiles, O.queue);
+  const uint32_t* queue = O.queue;
   if (n_scenes == 1)
     retrace_variant<true>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, T, seed, frame,
                           frame_ptr, stats, min_active);

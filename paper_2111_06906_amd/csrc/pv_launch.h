@@ -44,10 +44,23 @@ hipError_t launch_scatter_queue(const SceneDev* scenes, const uint2* tiles, uint
                                 uint32_t* queue, hipStream_t s);
 hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* block_cnt,
                            hipStream_t s);
-hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue,
+// Scratch of the re-trace's work order: the reordered queue (as many entries
+// as the queue can hold), bucket counts per tile and their scan.
+struct OrderWork {
+  uint32_t* queue;     // [max entries]
+  uint32_t* hist;      // [8 * tiles]
+  uint32_t* hoff;      // [8 * tiles]
+  uint32_t* htotal;    // [1]
+  uint32_t* scan_tmp;  // scan_tmp_words(8 * tiles)
+  uint32_t tiles;      // order_tiles(max entries)
+};
+uint32_t order_tiles(uint32_t max_entries);
+// queue_in / qcount: the work queue (ascending path ids) and its length; the
+// paths are re-traced in the order of their first invalid segment
+hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_scenes, const uint32_t* queue_in,
                           const uint32_t* qcount, float T, uint64_t seed, uint32_t frame,
                           const uint32_t* frame_ptr, pv_stats* stats, uint32_t n_blocks, int variant, uint32_t stack,
-                          int min_active, hipStream_t s);
+                          int min_active, const OrderWork& O, hipStream_t s);
 hipError_t launch_photon_count(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t* counts,
                                hipStream_t s);
 hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t B,
