@@ -975,6 +975,7 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->ow.hoff, 8 * (size_t)ctx->ow.tiles));
     CK(dalloc(A, &ctx->ow.htotal, 1));
     CK(dalloc(A, &ctx->ow.scan_tmp, pv::scan_tmp_words(8 * ctx->ow.tiles)));
+    CK(dalloc(A, &ctx->ow.deal, (size_t)pv::kDealGroups * pv::kDealStride));
     CK(dalloc(A, &ctx->d_qcount, 1));
     CK(dalloc(A, &ctx->d_pcounts, (size_t)nb * max_bounces));
     CK(dalloc(A, &ctx->d_poffsets, (size_t)nb * max_bounces));
@@ -987,6 +988,7 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->vw.tcount, nb));
     CK(dalloc(A, &ctx->vw.toff, nb));
     CK(dalloc(A, &ctx->vw.total, 1));
+    CK(dalloc(A, &ctx->vw.deal, (size_t)pv::kDealGroups * pv::kDealStride));
     CK(dalloc(A, &ctx->vw.first, max_paths));
     CK(dalloc(A, &ctx->vw.part, 4 * (size_t)nb + 2 * (size_t)pv::verify_finish_blocks(verify_blocks_max(ctx))));
     CK(hipMemsetAsync(ctx->d_qcount, 0, 4, ctx->stream));
@@ -1491,6 +1493,8 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
               chk(dalloc(A, &b->ow.queue, total_paths)) && chk(dalloc(A, &b->ow.hist, 8 * (size_t)b->ow.tiles)) &&
               chk(dalloc(A, &b->ow.hoff, 8 * (size_t)b->ow.tiles)) && chk(dalloc(A, &b->ow.htotal, 1)) &&
               chk(dalloc(A, &b->ow.scan_tmp, pv::scan_tmp_words(8 * b->ow.tiles))) &&
+              chk(dalloc(A, &b->ow.deal, (size_t)pv::kDealGroups * pv::kDealStride)) &&
+              chk(dalloc(A, &b->vw.deal, (size_t)pv::kDealGroups * pv::kDealStride)) &&
               chk(dalloc(A, &b->vw.part, 4 * ptiles.size() + 2 * (size_t)pv::verify_finish_blocks(verify_blocks_max(ctx)))) &&
               chk(upload(A, &b->d_obj_in, const_cast<const float**>(d_obj_xf), n, s)) &&
               chk(upload(A, &b->d_light_in, const_cast<const float**>(d_light_xf), n, s));

@@ -216,7 +216,15 @@ struct VerifyWork {
   uint32_t* total;   // [1] tasks in all
   uint32_t* first;   // [paths] first invalid segment found so far (global path id)
   uint32_t* part;    // per-block statistics: [scan blocks][4], then [finish blocks][2]
+  uint32_t* deal;    // [kDealGroups * kDealStride] refill counters of the traversal
 };
+
+// Persistent kernels take their work lists a refill at a time from one of
+// kDealGroups counters (a wave uses counter wave mod kDealGroups, each
+// counter on its own 128-byte line); counter g deals the list's chunks
+// g, g + kDealGroups, ... in order.
+constexpr uint32_t kDealGroups = 64;
+constexpr uint32_t kDealStride = 32;
 
 // ---------------------------------------------------------------------------
 // small vector helpers (FP32)

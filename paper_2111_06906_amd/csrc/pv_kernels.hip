@@ -422,13 +422,42 @@ __device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_
   return (uint32_t)lo;
 }
 
-// Work lists are dealt to the waves of a persistent grid in interleaved chunks
-// of kChunk entries (chunk c to wave c mod waves): no atomics, and each wave's
-// share spans the whole list, so uneven regions of it (the scenes of a batch,
-// expensive paths) are spread over all waves.  A wave's n-th entry:
+// Work lists are dealt to the waves of a persistent grid dynamically, a
+// refill at a time: a wave whose idle lanes want work adds their number to its
+// group's counter (one device atomic per refill) and takes that many entries
+// of the group's share, chunks g, g + kDealGroups, ... of kChunk entries, in
+// list order.  Static shares per wave left a wave idle for 12% of a re-trace
+// launch on average (the sums of ~340 path costs differ from wave to wave);
+// one counter for all waves serialised the atomics on one word; with 64
+// groups each counter sees a few hundred refills per launch.  The group's
+// n-th entry (groups: kDealGroups, or one per wave for grids of fewer waves):
 constexpr uint32_t kChunk = 64;
-__device__ inline uint32_t wave_entry(uint32_t wave, uint32_t n_waves, uint32_t n) {
-  return ((n / kChunk) * n_waves + wave) * kChunk + n % kChunk;
+__device__ inline uint32_t group_entry(uint32_t g, uint32_t groups, uint32_t n) {
+  return ((n / kChunk) * groups + g) * kChunk + n % kChunk;
+}
+
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;
+
+// The entry a lane that wants work takes (kNoEntry once its group's share is
+// exhausted).  Called by every lane of the wave.
+__device__ inline uint32_t deal(uint32_t* __restrict__ ctrs, uint32_t wave, uint32_t count, bool want) {
+  const uint64_t m = __ballot(want);
+  if (!m) return kNoEntry;
+  const uint32_t groups = min(kDealGroups, gridDim.x * (blockDim.x / 64));
+  const uint32_t g = wave % groups;
+  const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctrs + g * kDealStride, (uint32_t)__popcll(m));
+  base = __shfl(base, (int)leader, 64);
+  if (!want) return kNoEntry;
+  const uint32_t idx = group_entry(g, groups, base + (uint32_t)__popcll(m & lanemask_lt()));
+  return idx < count ? idx : kNoEntry;
+}
+
+// the counters start at zero for a launch (cleared by a kernel that precedes
+// it in the stream, so that the sequence can be captured in a graph)
+__device__ inline void deal_reset(uint32_t* ctrs) {
+  if (blockIdx.x == 0 && threadIdx.x < kDealGroups) ctrs[threadIdx.x * kDealStride] = 0;
 }
 
 // Verification runs as a short chain of kernels without atomics.
@@ -586,10 +615,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_gather(const SceneDev* __rest
   const PV_GLOBAL uint32_t* src = G(W.tmp) + S.task_base + (size_t)(blockIdx.x - S.tile_base) * kBlock * S.B;
   PV_GLOBAL uint32_t* dst = G(W.tasks) + W.toff[blockIdx.x];
   for (uint32_t i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
+  deal_reset(W.deal);
 }
 
 // Persistent: a lane whose walk has finished takes the wave's next task
-// (interleaved chunks, see wave_entry) while the other lanes continue.
+// (dealt by deal()) while the other lanes continue.
 
 template <bool kSingle>
 __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restrict__ scenes,
@@ -610,9 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
     load_moved(scenes[0], M);  // ends with a barrier
   }
   const uint32_t total = *W.total;
-  const uint32_t n_waves = gridDim.x * (kBlock / 64);
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  uint32_t next = 0;  // wave-uniform count of entries taken
   Walk w;
   w.cur = kRootNone;
   w.leaf = 0;
@@ -624,13 +652,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
     // lanes without a task take the next ones; a task whose path already
     // failed at an earlier segment is dropped (the minimum only decreases)
     const bool want = !busy && !drained;
-    const uint64_t m = __ballot(want);
-    if (m) {
-      const uint32_t base = next;
-      next += (uint32_t)__popcll(m);
+    if (__ballot(want)) {
+      const uint32_t t = deal(W.deal, wave, total, want);
       if (want) {
-        const uint32_t t = wave_entry(wave, n_waves, base + (uint32_t)__popcll(m & lanemask_lt()));
-        if (t >= total) {
+        if (t == kNoEntry) {
           drained = true;
         } else {
           const uint32_t tk = G(W.tasks)[t];
@@ -1079,7 +1104,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
                                                     int n_scenes, const uint32_t* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount, float T,
                                                     uint64_t seed, uint32_t frame_arg, const uint32_t* frame_ptr,
-                                                    pv_stats* stats, int min_active) {
+                                                    pv_stats* stats, int min_active, uint32_t* __restrict__ deal_ctr) {
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   __shared__ unsigned long long sred[kBlock / 64];
   __shared__ SceneTab stab;
@@ -1091,12 +1116,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     load_tab(scenes[0], stab);
     tab = (const PV_LDS SceneTab*)&stab;
   }
-  // the wave's share of the work queue in interleaved chunks (no atomics:
-  // device atomics on one word from thousands of waves serialise)
+  // the work queue, dealt by deal() from the counters 'deal_ctr'
   const uint32_t count = *qcount;
-  const uint32_t n_waves = gridDim.x * (kBlock / 64);
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  uint32_t next = 0;  // wave-uniform count of entries taken
   Lane L;
   L.S = scenes;
   L.mode = ST_IDLE;
@@ -1107,15 +1129,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
   wk.leaf = 0;
   bool tracing = false, any = false;
   while (true) {
-    // refill idle lanes from the wave's share of the queue
-    bool want = L.mode == ST_IDLE;
-    uint64_t m = __ballot(want);
-    if (m) {
-      const uint32_t base = next;
-      next += (uint32_t)__popcll(m);
+    // refill idle lanes from the queue
+    const bool want = L.mode == ST_IDLE;
+    if (__ballot(want)) {
+      const uint32_t qi = deal(deal_ctr, wave, count, want);
       if (want) {
-        const uint32_t qi = wave_entry(wave, n_waves, base + (uint32_t)__popcll(m & lanemask_lt()));
-        if (qi < count) {
+        if (qi != kNoEntry) {
           uint32_t gp = G(queue)[qi];
           if (kSingle) {
             L.p = gp;
@@ -1516,11 +1535,12 @@ __global__ __launch_bounds__(kBlock) void k_order_scatter(const SceneDev* __rest
                                                           const uint32_t* __restrict__ queue,
                                                           const uint32_t* __restrict__ qcount,
                                                           const uint32_t* __restrict__ hoff, uint32_t tiles,
-                                                          uint32_t* __restrict__ out) {
+                                                          uint32_t* __restrict__ out, uint32_t* __restrict__ deal_ctr) {
   constexpr int kWaves = kBlock / 64;
   static_assert(kOrderBuckets == 8, "three bucket bits");
   __shared__ uint32_t run[kOrderBuckets];
   __shared__ uint32_t wc[kWaves][kOrderBuckets];
+  deal_reset(deal_ctr);  // the re-trace that follows deals from these
   const uint32_t count = *qcount, base = blockIdx.x * kOrderTile;
   if (base >= count) return;  // uniform over the block
   const uint32_t tid = threadIdx.x, w = tid >> 6;
@@ -1656,23 +1676,24 @@ hipError_t launch_mark_all(const SceneDev* scenes, const uint2* tiles, uint32_t 
 template <bool kSingle>
 static void retrace_variant(int v, dim3 g, size_t lds, hipStream_t s, const SceneDev* scenes, const uint32_t* gbase, int n_scenes,
                             const uint32_t* queue, const uint32_t* qcount, float T, uint64_t seed,
-                            uint32_t frame, const uint32_t* frame_ptr, pv_stats* stats, int min_active) {
+                            uint32_t frame, const uint32_t* frame_ptr, pv_stats* stats, int min_active,
+                            uint32_t* deal_ctr) {
   switch (v) {
     case 1:
       hipLaunchKernelGGL((k_retrace<kSingle, 5>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
-                         T, seed, frame, frame_ptr, stats, min_active);
+                         T, seed, frame, frame_ptr, stats, min_active, deal_ctr);
       break;
     case 2:
       hipLaunchKernelGGL((k_retrace<kSingle, 6>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
-                         T, seed, frame, frame_ptr, stats, min_active);
+                         T, seed, frame, frame_ptr, stats, min_active, deal_ctr);
       break;
     case 3:
       hipLaunchKernelGGL((k_retrace<kSingle, 8>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
-                         T, seed, frame, frame_ptr, stats, min_active);
+                         T, seed, frame, frame_ptr, stats, min_active, deal_ctr);
       break;
     default:
       hipLaunchKernelGGL((k_retrace<kSingle, 4>), g, dim3(kBlock), lds, s, scenes, gbase, n_scenes, queue, qcount,
-                         T, seed, frame, frame_ptr, stats, min_active);
+                         T, seed, frame, frame_ptr, stats, min_active, deal_ctr);
       break;
   }
 }
@@ -1688,14 +1709,14 @@ hipError_t launch_retrace(const SceneDev* scenes, const uint32_t* gbase, int n_s
   hipError_t e = launch_scan(O.hist, O.hoff, kOrderBuckets * O.tiles, O.htotal, O.scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_order_scatter, dim3(O.tiles), dim3(kBlock), 0, s, scenes, gbase, n_scenes, queue_in, qcount,
-                     O.hoff, O.tiles, O.queue);
+                     O.hoff, O.tiles, O.queue, O.deal);
   const uint32_t* queue = O.queue;
   if (n_scenes == 1)
     retrace_variant<true>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, T, seed, frame,
-                          frame_ptr, stats, min_active);
+                          frame_ptr, stats, min_active, O.deal);
   else
     retrace_variant<false>(variant, dim3(n_blocks), stack_bytes(stack), s, scenes, gbase, n_scenes, queue, qcount, T, seed, frame,
-                           frame_ptr, stats, min_active);
+                           frame_ptr, stats, min_active, O.deal);
   return hipGetLastError();
 }
 

@@ -52,6 +52,7 @@ struct OrderWork {
   uint32_t* hoff;      // [8 * tiles]
   uint32_t* htotal;    // [1]
   uint32_t* scan_tmp;  // scan_tmp_words(8 * tiles)
+  uint32_t* deal;      // [kDealGroups * kDealStride] refill counters of the re-trace
   uint32_t tiles;      // order_tiles(max entries)
 };
 uint32_t order_tiles(uint32_t max_entries);
