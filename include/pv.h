@@ -195,7 +195,7 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
  * (1..64): persistent re-trace workgroups per compute unit;
  * PV_TUNE_WALK_MIN_ACTIVE (1..64): a wave's re-trace walk yields to take new
  * queries once fewer of its 64 lanes are still walking;
- * PV_TUNE_VERIFY_BLOCKS_PER_CU (1..16) and PV_TUNE_VERIFY_MIN_ACTIVE (1..64):
+ * PV_TUNE_VERIFY_BLOCKS_PER_CU (1..32) and PV_TUNE_VERIFY_MIN_ACTIVE (1..64):
  * the same two choices for the verification traversal;
  * PV_TUNE_OBJECT_REBUILD (0 or 1): 0 (default) refits each moved object's
  * upload-time topology (binned surface-area heuristic, object space) in
@@ -219,9 +219,9 @@ pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
 
 /* Autotuner: with the current frame (after pv_frame_begin) and the given
  * store, on a snapshot of the store: time verification for every traversal
- * grid (2, 4, 8, 16 workgroups per CU) and yield threshold (8, 16, 32, 48);
+ * grid (4, 8, 16, 32 workgroups per CU) and yield threshold (8, 16, 32, 48);
  * then, after verification and queue building, time the re-trace for every
- * re-trace variant and persistent grid size (2, 4, 8, 16 workgroups per CU),
+ * re-trace variant and persistent grid size (4, 8, 16, 32 workgroups per CU),
  * then for yield thresholds 8..48.  Keeps the fastest settings in the
  * context and restores the store.  Allocates a temporary copy of the store
  * and synchronises.  *out_ms (host, optional) receives the best re-trace

@@ -77,11 +77,12 @@ struct pv_ctx {
   // tuning (pv_set_tuning / pv_autotune)
   int retrace_variant = 0;
   // defaults: the settings the autotuner picks on the 3M-path, 380k-triangle
-  // interior (one persistent wave per SIMD slot that 127 VGPRs allow)
-  int retrace_blocks_per_cu = 4;
+  // interior (twice the workgroups that fit at once: the later ones take
+  // what is left of the dealt work lists)
+  int retrace_blocks_per_cu = 8;
   int walk_min_active = 40;  // a wave's re-trace walk yields once fewer lanes are still walking
-  int verify_blocks_per_cu = 4;  // persistent verification traversal workgroups per compute unit
-  int verify_min_active = 32;    // yield threshold of the verification walks
+  int verify_blocks_per_cu = 8;  // persistent verification traversal workgroups per compute unit
+  int verify_min_active = 16;    // yield threshold of the verification walks
   // bound store
   bool bound = false;
   bool counts_ready = false;   // per-block replace counts written by verify
@@ -493,7 +494,7 @@ std::vector<uint2> xf_tiles(uint32_t scene, const uint32_t* obj_tris, uint32_t n
 }
 
 // grid of the verification traversal kernel (persistent, grid-stride)
-constexpr int kMaxVerifyBlocksPerCu = 16;
+constexpr int kMaxVerifyBlocksPerCu = 32;
 uint32_t verify_blocks(const pv_ctx* ctx) { return (uint32_t)(ctx->n_cu * ctx->verify_blocks_per_cu); }
 // the largest traversal grid any tuning can pick (sizes the statistics slots)
 uint32_t verify_blocks_max(const pv_ctx* ctx) { return (uint32_t)(ctx->n_cu * kMaxVerifyBlocksPerCu); }
@@ -1092,7 +1093,7 @@ pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value) {
     if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "walk minimum active lanes out of range 1..64");
     ctx->walk_min_active = value;
   } else if (key == PV_TUNE_VERIFY_BLOCKS_PER_CU) {
-    if (value < 1 || value > kMaxVerifyBlocksPerCu) return fail(ctx, PV_ERR_ARG, "verify blocks per CU out of range 1..16");
+    if (value < 1 || value > kMaxVerifyBlocksPerCu) return fail(ctx, PV_ERR_ARG, "verify blocks per CU out of range 1..32");
     ctx->verify_blocks_per_cu = value;
   } else if (key == PV_TUNE_VERIFY_MIN_ACTIVE) {
     if (value < 1 || value > 64) return fail(ctx, PV_ERR_ARG, "verify minimum active lanes out of range 1..64");
@@ -1278,7 +1279,9 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   float best_verify = INFINITY;
   {
     int bv_b = ctx->verify_blocks_per_cu, bv_m = ctx->verify_min_active;
-    const int vgrids[4] = {2, 4, 8, 16}, vmins[4] = {8, 16, 32, 48};
+    // (with work dealt a refill at a time, workgroups beyond residency simply
+    // start later and take what is left)
+    const int vgrids[4] = {4, 8, 16, 32}, vmins[4] = {8, 16, 32, 48};
     for (int gi = 0; gi < 4 && err == hipSuccess; ++gi) {
       for (int mi = 0; mi < 4 && err == hipSuccess; ++mi) {
         ctx->verify_blocks_per_cu = vgrids[gi];
@@ -1310,7 +1313,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   // re-trace: occupancy variant x grid at the current yield threshold, then the threshold
   float best = INFINITY;
   int best_v = ctx->retrace_variant, best_b = ctx->retrace_blocks_per_cu, best_m = ctx->walk_min_active;
-  const int grids[4] = {2, 4, 8, 16};
+  const int grids[4] = {4, 8, 16, 32};
   for (int v = 0; v < 4 && err == hipSuccess; ++v) {
     for (int gi = 0; gi < 4 && err == hipSuccess; ++gi) {
       float ms = INFINITY;
