@@ -1275,6 +1275,10 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
     *ms_out = t_min;
     return e;
   };
+  // a later candidate (larger grid, higher occupancy target or threshold)
+  // replaces the best one only when it is clearly faster: near-ties between
+  // grids measured on one frame did not carry over to later frames
+  constexpr float kTuneMargin = 0.99f;
   // verification: traversal grid x yield threshold, each timed on the restored store
   float best_verify = INFINITY;
   {
@@ -1300,7 +1304,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
           if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
           t_min = std::min(t_min, ms);
         }
-        if (t_min < best_verify) {
+        if (t_min < best_verify * kTuneMargin) {
           best_verify = t_min;
           bv_b = vgrids[gi];
           bv_m = vmins[mi];
@@ -1318,7 +1322,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
     for (int gi = 0; gi < 4 && err == hipSuccess; ++gi) {
       float ms = INFINITY;
       err = trial(v, grids[gi], best_m, &ms);
-      if (ms < best) {
+      if (ms < best * kTuneMargin) {
         best = ms;
         best_v = v;
         best_b = grids[gi];
@@ -1329,7 +1333,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   for (int mi = 0; mi < 6 && err == hipSuccess; ++mi) {
     float ms = INFINITY;
     err = trial(best_v, best_b, mins[mi], &ms);
-    if (ms < best) {
+    if (ms < best * kTuneMargin) {
       best = ms;
       best_m = mins[mi];
     }

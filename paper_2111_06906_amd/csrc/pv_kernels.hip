@@ -590,19 +590,20 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
     if (nt > 0) ex = inv = 0;  // counted by k_verify_finish
   }
   if (stats) {
-    // per-block counts (at most kBlock * 15 each) go to their own slots and
-    // are summed by k_verify_stats: one counter word shared by every block
-    // would serialise thousands of atomics
-    unsigned long long nex = block_sum_u64(ex, sred);
-    unsigned long long ninv = block_sum_u64(inv, sred);
-    unsigned long long nlost = block_sum_u64(lost, sred);
-    unsigned long long ntask = block_sum_u64(nt, sred);
+    // per-block counts go to their own slots and are summed by
+    // k_verify_stats: one counter word shared by every block would serialise
+    // thousands of atomics.  Each count is at most kBlock * 15 < 2^16 per
+    // block, so the four travel as 16-bit fields of one sum.
+    static_assert(kBlock * 15 < (1 << 16), "16-bit fields");
+    const unsigned long long packed = (unsigned long long)ex | ((unsigned long long)inv << 16) |
+                                      ((unsigned long long)lost << 32) | ((unsigned long long)nt << 48);
+    const unsigned long long sum = block_sum_u64(packed, sred);
     if (tid == 0) {
       uint32_t* o = W.part + 4 * (size_t)blockIdx.x;
-      o[0] = (uint32_t)nex;
-      o[1] = (uint32_t)ninv;
-      o[2] = (uint32_t)nlost;
-      o[3] = (uint32_t)ntask;
+      o[0] = (uint32_t)(sum & 0xffffu);
+      o[1] = (uint32_t)((sum >> 16) & 0xffffu);
+      o[2] = (uint32_t)((sum >> 32) & 0xffffu);
+      o[3] = (uint32_t)(sum >> 48);
     }
   }
 }
@@ -733,12 +734,12 @@ __global__ __launch_bounds__(kBlock) void k_verify_finish(const SceneDev* __rest
     }
   }
   if (stats) {
-    unsigned long long nex = block_sum_u64(ex, sred);
-    unsigned long long ninv = block_sum_u64(inv, sred);
+    // both counts of a block fit 32 bits (at most 15 and 1 per path): one sum
+    const unsigned long long sum = block_sum_u64((unsigned long long)ex | ((unsigned long long)inv << 32), sred);
     if (threadIdx.x == 0) {
       uint32_t* o = W.part + 4 * (size_t)n_scan_blocks + 2 * (size_t)blockIdx.x;
-      o[0] = (uint32_t)min(nex, 0xffffffffull);
-      o[1] = (uint32_t)ninv;
+      o[0] = (uint32_t)(sum & 0xffffffffull);
+      o[1] = (uint32_t)(sum >> 32);
     }
   }
 }
