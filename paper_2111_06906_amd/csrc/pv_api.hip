@@ -766,6 +766,9 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     std::vector<float> dlocal(9 * n_dyn);
     std::vector<uint32_t> dgid(n_dyn);
     std::vector<uint32_t> level_nodes, level_off;
+    std::vector<uint4> dspan;          // per object node: its children's record ranges
+    std::vector<uint32_t> dspan_obj;   // and its object
+    const uint32_t obj_node_first = (uint32_t)nodes.size();
     uint32_t tri_base = 0, gbase = S;
     for (uint32_t o = 0; o < d->n_objects; ++o) {
       uint32_t n = d->h_obj_tris[o];
@@ -801,6 +804,24 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
         nd.d.y = rebase(nd.d.y);
         if (nd.d.z >= 0) nd.d.z += 2 * (int32_t)node_base;
         nodes.push_back(nd);
+      }
+      // children's leaf-order ranges, children before parents (a parent
+      // precedes its children in the node order)
+      {
+        std::vector<uint2> span(hb.nodes.size());
+        auto child_span = [&](int32_t c) {
+          if (c < 0) return make_uint2(pv::leaf_first(c), pv::leaf_first(c) + pv::leaf_count(c));
+          return span[(size_t)c];
+        };
+        const size_t at = dspan.size();
+        dspan.resize(at + hb.nodes.size());
+        dspan_obj.resize(at + hb.nodes.size(), o);
+        for (size_t k = hb.nodes.size(); k-- > 0;) {
+          const uint2 a = child_span(hb.nodes[k].d.x), b = child_span(hb.nodes[k].d.y);
+          if (a.y != b.x) return fail(ctx, PV_ERR_STATE, "object topology is not in leaf order");
+          span[k] = make_uint2(a.x, b.y);
+          dspan[at + k] = make_uint4(tri_base + a.x, tri_base + a.y, tri_base + b.x, tri_base + b.y);
+        }
       }
       for (uint32_t i = 0; i < n; ++i) {
         std::memcpy(&dlocal[9 * (size_t)(tri_base + i)], v + 9 * (size_t)hb.order[i], 9 * sizeof(float));
@@ -844,6 +865,16 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     CK(upload(A, &d_lnodes, level_nodes.data(), level_nodes.size(), s));
     CK(upload(A, &d_loff, level_off.data(), level_off.size(), s));
     CK(upload(A, &d_objs, objs.data(), objs.size(), s));
+    hs.obj_node_first = obj_node_first;
+    hs.n_obj_nodes = (uint32_t)dspan.size();
+    if (!dspan.empty()) {
+      uint4* d_span;
+      uint32_t* d_span_obj;
+      CK(upload(A, &d_span, dspan.data(), dspan.size(), s));
+      CK(upload(A, &d_span_obj, dspan_obj.data(), dspan_obj.size(), s));
+      hs.dspan = d_span;
+      hs.dspan_obj = d_span_obj;
+    }
     pv::LbvhWork lw{};
     if (n_dyn) {
       const uint32_t nd = (uint32_t)n_dyn, tiles = pv::lbvh_sort_tiles(nd);
@@ -1011,8 +1042,10 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
   const float* in[2] = {d_obj_xf, d_light_xf};
   CK(hipMemcpyAsync(ctx->d_in_ptrs, in, sizeof(in), hipMemcpyHostToDevice, ctx->stream));
   CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->stream));
-  CK(pv::launch_update_objects(ctx->d_scene, ctx->d_obj_tiles, ctx->n_obj_tiles, ctx->d_xf_tiles, ctx->n_xf_tiles,
-                               ctx->stream));
+  // world triangles of the moved objects, then their topologies' boxes as
+  // unions over leaf-order ranges
+  CK(pv::launch_transform_objects(ctx->d_scene, ctx->d_xf_tiles, ctx->n_xf_tiles, ctx->stream));
+  CK(pv::launch_refit_objects(ctx->d_scene, ctx->lw, ctx->n_objects, ctx->hs.n_obj_nodes, ctx->stream));
   // rebuild mode: every object's hierarchy rebuilt from its current
   // triangles; the refit topology (kept current above) stays the hierarchy of
   // an object whose rebuilt tree is too deep for the traversal stacks

@@ -135,6 +135,13 @@ struct SceneDev {
   float* obj_xf_cur;      // [n_obj][12]
   float* obj_xf_prev;
   uint32_t* obj_moved;    // [n_obj]
+  // per internal node of the objects' upload-time topologies (nodes
+  // [obj_node_first, obj_node_first + n_obj_nodes) of the scene): the
+  // dynamic-record ranges of its two children (a subtree holds a contiguous
+  // run of the leaf order), and its object
+  const uint4* dspan;
+  const uint32_t* dspan_obj;
+  uint32_t obj_node_first, n_obj_nodes;
   // lights
   const LightDev* lights;
   float* light_xf_cur;    // [L][12]

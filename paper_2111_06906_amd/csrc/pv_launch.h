@@ -15,6 +15,9 @@ hipError_t launch_update_objects(SceneDev* scenes, const uint2* tiles, uint32_t 
                                  uint32_t n_xf_tiles, hipStream_t s);
 // world triangles of the moved objects only (xf_tiles as above)
 hipError_t launch_transform_objects(SceneDev* scenes, const uint2* xf_tiles, uint32_t n_xf_tiles, hipStream_t s);
+// boxes of the moved objects' upload-time topologies (one scene) as unions
+// over leaf-order ranges (the box pyramid of W), their object boxes and roots
+hipError_t launch_refit_objects(SceneDev* scenes, LbvhWork W, uint32_t n_obj, uint32_t n_obj_nodes, hipStream_t s);
 // every object's hierarchy rebuilt from its current world triangles (one
 // scene): linear BVH over Morton codes, into the objects' rebuild regions; an
 // object whose tree is deeper than max_depth keeps its current hierarchy

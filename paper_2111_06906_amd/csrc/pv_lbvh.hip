@@ -282,8 +282,9 @@ __global__ __launch_bounds__(kSortThreads) void k_lbvh_scatter(const uint64_t* _
   }
 }
 
-// level 0 of the pyramid (padded triangle boxes in sorted order) and the
-// levels 1..kLowLevels of each aligned 256-position block
+// level 0 of the pyramid (padded triangle boxes in sorted order, or in record
+// order when val is null) and the levels 1..kLowLevels of each aligned
+// 256-position block
 __global__ __launch_bounds__(kBlock) void k_lbvh_leaves(const SceneDev* __restrict__ scenes, LbvhWork W,
                                                         const uint32_t* __restrict__ val) {
   __shared__ float3 slo[kBlock], shi[kBlock];
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_lbvh_leaves(const SceneDev* __restri
   const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
   Box b = empty_box();
   if (g < n) {
-    b = tri_box(S.tris[S.n_static + val[g]]);
+    b = tri_box(S.tris[S.n_static + (val ? val[g] : g)]);
     pyr_put(W.pyr, g, b);
   }
   uint32_t off = 0, m = n;
@@ -439,6 +440,53 @@ __global__ void k_lbvh_finish(SceneDev* __restrict__ scenes, LbvhWork W, const u
   S.obj_aabb[6 * o + 4] = b.hi.y;
   S.obj_aabb[6 * o + 5] = b.hi.z;
   objs[o].root = root;
+}
+
+// Per-frame refit of the upload-time topologies of the moved objects: every
+// node's two child boxes are unions over the children's leaf-order record
+// ranges, read from the pyramid over the records (a subtree holds a
+// contiguous run of the leaf order), so no node waits for its children.
+// The unions equal those of a level-by-level refit bit for bit: the padding
+// is monotone, so the padded box of a union is the union of padded boxes.
+__global__ __launch_bounds__(kBlock) void k_refit_nodes(SceneDev* __restrict__ scenes, LbvhWork W) {
+  SceneDev& S = scenes[0];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n_obj_nodes || !S.obj_moved[S.dspan_obj[i]]) return;
+  const uint4 r = S.dspan[i];
+  const Box b0 = range_box(W.pyr, W.n_dyn, r.x, r.y), b1 = range_box(W.pyr, W.n_dyn, r.z, r.w);
+  Node& nd = S.nodes[S.obj_node_first + i];
+  nd.a = make_float4(b0.lo.x, b0.lo.y, b0.lo.z, b0.hi.x);
+  nd.b = make_float4(b0.hi.y, b0.hi.z, b1.lo.x, b1.lo.y);
+  nd.c = make_float4(b1.lo.z, b1.hi.x, b1.hi.y, b1.hi.z);
+}
+
+// each moved object's box (the union of its records) and its refit topology
+// as its current hierarchy
+__global__ void k_refit_objects(SceneDev* __restrict__ scenes, LbvhWork W) {
+  SceneDev& S = scenes[0];
+  ObjDev* objs = const_cast<ObjDev*>(S.objs);
+  const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= S.n_obj || !S.obj_moved[o]) return;
+  const ObjDev ob = S.objs[o];
+  const Box b = range_box(W.pyr, W.n_dyn, ob.tri_base, ob.tri_base + ob.n_tris);
+  S.obj_aabb[6 * o + 0] = b.lo.x;
+  S.obj_aabb[6 * o + 1] = b.lo.y;
+  S.obj_aabb[6 * o + 2] = b.lo.z;
+  S.obj_aabb[6 * o + 3] = b.hi.x;
+  S.obj_aabb[6 * o + 4] = b.hi.y;
+  S.obj_aabb[6 * o + 5] = b.hi.z;
+  objs[o].root = ob.sah_root;
+}
+
+hipError_t launch_refit_objects(SceneDev* scenes, LbvhWork W, uint32_t n_obj, uint32_t n_obj_nodes, hipStream_t s) {
+  if (!W.n_dyn || !n_obj) return hipSuccess;
+  const uint32_t nb = (W.n_dyn + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_lbvh_leaves, dim3(nb), dim3(kBlock), 0, s, scenes, W, nullptr);
+  if (W.n_dyn > (1u << kLowLevels)) hipLaunchKernelGGL(k_lbvh_pyramid, dim3(1), dim3(1024), 0, s, W);
+  if (n_obj_nodes)
+    hipLaunchKernelGGL(k_refit_nodes, dim3((n_obj_nodes + kBlock - 1) / kBlock), dim3(kBlock), 0, s, scenes, W);
+  hipLaunchKernelGGL(k_refit_objects, dim3((n_obj + 63) / 64), dim3(64), 0, s, scenes, W);
+  return hipGetLastError();
 }
 
 uint32_t lbvh_sort_tiles(uint32_t n_dyn) { return (n_dyn + kSortTile - 1) / kSortTile; }
