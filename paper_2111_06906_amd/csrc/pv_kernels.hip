@@ -1497,8 +1497,8 @@ __global__ void k_reduce_partials(const float* __restrict__ partial, uint32_t n_
 // its first invalid one on, so the queue (ascending path ids, as the caller
 // sees it) is handed to the persistent re-trace kernel reordered by that
 // segment, smallest first (a stable counting sort over kOrderBuckets
-// buckets): every wave's interleaved share then starts with its long paths
-// and ends with short ones, and the waves finish closer together.
+// buckets): the refills deal the long paths first and the last refills of a
+// launch are short paths, so the waves finish closer together.
 
 constexpr uint32_t kOrderTile = 2048;  // queue entries per tile of the reorder
 constexpr int kOrderBuckets = 8;
