@@ -270,7 +270,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "verification call (k_verify_scan, task scan + k_verify_gather, k_verify_trace, "
-                               "k_verify_finish, k_replace_count, k_verify_stats)",
+                               "k_verify_finish, k_verify_stats)",
                      "algorithmic_bytes_per_launch": bytes_verify / K, "avg_launch_ms": avg_verify_s * 1e3},
         "phases_ms_per_frame": {k: v / K for k, v in phase.items()},
         "tuning": tuning,

@@ -306,10 +306,13 @@ __global__ __launch_bounds__(128) void k_build_top(SceneDev* scenes) {
 // verification (Sections 3.1 and 3.2)
 
 // Moved objects of a scene in LDS: box corners with the object's global
-// triangle id range in the w components (lo.w = first id, hi.w = count).
+// triangle id range in the w components (lo.w = first id, hi.w = count), and
+// the same id ranges merged where consecutive moved objects' ids adjoin
+// (run[k] = {first id, count}; one run when every object moves).
 struct MovedSet {
-  int n;
+  int n, nr;
   float4 lo[PV_MAX_OBJECTS], hi[PV_MAX_OBJECTS];
+  uint2 run[PV_MAX_OBJECTS];
 };
 
 // the moved objects of the scene, compacted in object order by the first wave
@@ -318,16 +321,32 @@ __device__ inline void load_moved(const SceneDev& S, MovedSet& M) {
   static_assert(PV_MAX_OBJECTS <= 64, "one lane per object");
   if (threadIdx.x < 64) {
     const uint32_t o = threadIdx.x;
-    const bool mv = o < S.n_obj && G(S.obj_moved)[o] != 0;
+    const bool have = o < S.n_obj;
+    const bool mv = have && G(S.obj_moved)[o] != 0;
     const uint64_t m = __ballot(mv);
+    ObjDev ob{};
+    if (have) ob = G(S.objs)[o];
     if (mv) {
       const uint32_t i = (uint32_t)__popcll(m & lanemask_lt());
-      const ObjDev ob = G(S.objs)[o];
       const PV_GLOBAL float* b = G(S.obj_aabb) + 6 * o;
       M.lo[i] = make_float4(b[0], b[1], b[2], __uint_as_float(ob.gbase));
       M.hi[i] = make_float4(b[3], b[4], b[5], __uint_as_float(ob.n_tris));
     }
-    if (o == 0) M.n = (int)__popcll(m);
+    // runs: a moved object continues the run of the object before it when
+    // that one moved too and its ids end where this one's begin
+    const uint32_t end = ob.gbase + ob.n_tris;
+    const uint32_t prev_end = __shfl_up(end, 1, 64);
+    const bool cont = mv && o > 0 && ((m >> (o - 1)) & 1ull) && prev_end == ob.gbase;
+    const bool start = mv && !cont;
+    const uint64_t cm = __ballot(cont), sm = __ballot(start);
+    const uint64_t after = o < 63 ? ~cm >> (o + 1) : 0ull;  // lanes past o that end a run
+    const uint32_t last = o + (after ? (uint32_t)__ffsll((long long)after) - 1u : 63u - o);
+    const uint32_t run_end = __shfl(end, (int)last, 64);
+    if (start) M.run[__popcll(sm & lanemask_lt())] = make_uint2(ob.gbase, run_end - ob.gbase);
+    if (o == 0) {
+      M.n = (int)__popcll(m);
+      M.nr = (int)__popcll(sm);
+    }
   }
   __syncthreads();
 }
@@ -336,9 +355,21 @@ __device__ inline void load_moved(const SceneDev& S, MovedSet& M) {
 // count is uniform over the block)
 __device__ inline bool on_moved(const MovedSet& M, uint32_t hit) {
   bool mv = false;
-  for (int i = 0; i < M.n; ++i)
-    mv |= hit - __float_as_uint(M.lo[i].w) < __float_as_uint(M.hi[i].w);
+  for (int k = 0; k < M.nr; ++k) mv |= hit - M.run[k].x < M.run[k].y;
   return mv;
+}
+
+// whether a segment's query reaches box [lo, hi] within its interval: the
+// same decision as box_entry(...) != inf when tmin <= tmax, with the interval
+// entering by comparisons (the slab parameters are fma results, so the
+// min/max need no operand canonicalisation)
+__device__ inline bool slab_hit(float4 lo, float4 hi, const Ray& r) {
+  const float x0 = fmaf(lo.x, r.inv.x, r.oi.x), x1 = fmaf(hi.x, r.inv.x, r.oi.x);
+  const float y0 = fmaf(lo.y, r.inv.y, r.oi.y), y1 = fmaf(hi.y, r.inv.y, r.oi.y);
+  const float z0 = fmaf(lo.z, r.inv.z, r.oi.z), z1 = fmaf(hi.z, r.inv.z, r.oi.z);
+  const float e = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), r.tmin));
+  const float x = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), r.tmax));
+  return e <= x;
 }
 
 // whether a ray reaches any moved object's box within its interval
@@ -467,13 +498,13 @@ __device__ inline void deal_reset(uint32_t* ctrs) {
 //    tile's own region; scanning stops at the first segment whose end photon
 //    is on a moved object (that segment is invalid whatever lies before it).
 //    Writes the information word as if no task were blocked (final for paths
-//    without tasks).
+//    without tasks) and the tile's replace count over those paths.
 //  scan of the per-tile task counts, k_verify_gather: one compact task list.
 //  k_verify_trace: the tasks as independent any-hit queries against the
 //    moved objects, every lane busy; a blocked segment lowers its path's
 //    first invalid segment (atomic minimum on that path's own word).
-//  k_verify_finish: information words of the paths with tasks.
-//  k_replace_count: replace bits per tile for the work queue.
+//  k_verify_finish: information words of the paths with tasks, whose replace
+//    bits it adds to their tiles' counts (the work queue's block counts).
 // The result equals the in-order test of Section 3.2: the first invalid
 // segment is the minimum over blocked segments and the first moved endpoint.
 
@@ -481,7 +512,7 @@ constexpr int kPreRows = 8;  // bounce rows a lane loads before testing
 
 __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restrict__ scenes,
                                                         const uint2* __restrict__ tiles, VerifyWork W,
-                                                        pv_stats* stats) {
+                                                        uint32_t* __restrict__ block_cnt, pv_stats* stats) {
   __shared__ MovedSet M;
   __shared__ unsigned long long sred[kBlock / 64];
   __shared__ uint32_t swt[kBlock / 64];
@@ -525,18 +556,37 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
     }
     if (!lost && M.n > 0) {
       // every segment of the path is tested (no early exit); the first
-      // segment whose end photon lies on a moved object caps the scan
-      uint32_t first_mv = n;
+      // segment whose end photon lies on a moved object caps the scan.  The
+      // loaded rows' segments are set up first, then each moved box is read
+      // once and tested against all of them (rows past n are masked off).
+      // Rows are tested up to the scene's bounce limit (uniform), not the
+      // path's own count, so that no lane-dependent branch splits the loop.
+      // Box hits are collected as wave masks (one per row, scalar registers).
+      Ray rs[kPreRows];
+      uint64_t hit[kPreRows];
+      uint32_t mv = 0;
 #pragma unroll
       for (int j = 0; j < kPreRows; ++j) {
-        if ((uint32_t)j < n) {
-          const float4 row = rows[j];
-          const float3 b = xyz(row);
-          if (on_moved(M, __float_as_uint(row.w))) first_mv = min(first_mv, (uint32_t)j);
-          if (reaches_moved_box(M, segment_box_ray(a, b, S.eps_end))) mask |= 1u << j;
+        hit[j] = 0;
+        if ((uint32_t)j < S.B) {
+          const float3 b = xyz(rows[j]);
+          rs[j] = segment_box_ray(a, b, S.eps_end);
+          if (!(rs[j].tmin <= rs[j].tmax)) rs[j].tmin = __builtin_inff();  // nothing to test
+          rs[j].tmin = __builtin_canonicalizef(rs[j].tmin);
+          rs[j].tmax = __builtin_canonicalizef(rs[j].tmax);
+          if (on_moved(M, __float_as_uint(rows[j].w))) mv |= 1u << j;
           a = b;
         }
       }
+      for (int i = 0; i < M.n; ++i) {
+        const float4 lo = M.lo[i], hi = M.hi[i];
+#pragma unroll
+        for (int j = 0; j < kPreRows; ++j)
+          if ((uint32_t)j < S.B) hit[j] |= __builtin_amdgcn_ballot_w64(slab_hit(lo, hi, rs[j]));
+      }
+#pragma unroll
+      for (int j = 0; j < kPreRows; ++j) mask |= (uint32_t)((hit[j] >> lane_id()) & 1ull) << j;
+      uint32_t first_mv = min(n, mv ? (uint32_t)__ffs(mv) - 1u : n);
       for (uint32_t j = kPreRows; j < n; ++j) {
         const float4 row = pos[(size_t)j * stride + p];
         const float3 b = xyz(row);
@@ -589,16 +639,18 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
     inv = info_replace(out);
     if (nt > 0) ex = inv = 0;  // counted by k_verify_finish
   }
-  if (stats) {
+  {
     // per-block counts go to their own slots and are summed by
     // k_verify_stats: one counter word shared by every block would serialise
     // thousands of atomics.  Each count is at most kBlock * 15 < 2^16 per
-    // block, so the four travel as 16-bit fields of one sum.
+    // block, so the four travel as 16-bit fields of one sum.  The replace
+    // count of the tile is one of them.
     static_assert(kBlock * 15 < (1 << 16), "16-bit fields");
     const unsigned long long packed = (unsigned long long)ex | ((unsigned long long)inv << 16) |
                                       ((unsigned long long)lost << 32) | ((unsigned long long)nt << 48);
     const unsigned long long sum = block_sum_u64(packed, sred);
-    if (tid == 0) {
+    if (tid == 0) block_cnt[blockIdx.x] = (uint32_t)((sum >> 16) & 0xffffu);
+    if (stats && tid == 0) {
       uint32_t* o = W.part + 4 * (size_t)blockIdx.x;
       o[0] = (uint32_t)(sum & 0xffffu);
       o[1] = (uint32_t)((sum >> 16) & 0xffffu);
@@ -709,28 +761,45 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
 
 // The tasks of a path are adjacent in the list: the thread holding a path's
 // first task writes its information word.
+// The replace bits are added to the tiles' counts with one atomic per tile a
+// wave's lanes reach (a wave's tasks belong to one or two tiles of paths).
 template <bool kSingle>
 __global__ __launch_bounds__(kBlock) void k_verify_finish(const SceneDev* __restrict__ scenes,
                                                           const uint32_t* __restrict__ gbase, int n_scenes,
-                                                          VerifyWork W, uint32_t n_scan_blocks, pv_stats* stats) {
+                                                          VerifyWork W, uint32_t* __restrict__ block_cnt,
+                                                          uint32_t n_scan_blocks, pv_stats* stats) {
   __shared__ unsigned long long sred[kBlock / 64];
   const uint32_t total = *W.total;
   uint32_t ex = 0, inv = 0;
+  // the lanes of a wave hold consecutive tasks: they stay in step and leave
+  // the loop together except in its last round
   for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
     const uint32_t gp = G(W.tasks)[t] >> 4;
-    if (t > 0 && (G(W.tasks)[t - 1] >> 4) == gp) continue;
-    uint32_t s = 0;
-    if (!kSingle) s = scene_of(gbase, n_scenes, gp);
-    const SceneDev& S = scenes[s];
-    const uint32_t q = gp - S.gpath_base;
-    const uint32_t w = G(S.info)[q];  // as written by the scan
-    const uint32_t n = info_nseg(w), k = G(W.first)[gp];
-    if (k < n) {
-      G(S.info)[q] = info_pack(info_cell(w), n, k, 1, 1);
-      ex += k + 1;
-      inv += 1;
-    } else {
-      ex += n;
+    uint32_t tile = kNoEntry;  // the tile whose count this lane raises
+    if (!(t > 0 && (G(W.tasks)[t - 1] >> 4) == gp)) {
+      uint32_t s = 0;
+      if (!kSingle) s = scene_of(gbase, n_scenes, gp);
+      const SceneDev& S = scenes[s];
+      const uint32_t q = gp - S.gpath_base;
+      const uint32_t w = G(S.info)[q];  // as written by the scan
+      const uint32_t n = info_nseg(w), k = G(W.first)[gp];
+      if (k < n) {
+        G(S.info)[q] = info_pack(info_cell(w), n, k, 1, 1);
+        ex += k + 1;
+        inv += 1;
+        tile = S.tile_base + q / kBlock;
+      } else {
+        ex += n;
+      }
+    }
+    while (true) {
+      const uint64_t m = __ballot(tile != kNoEntry);
+      if (!m) break;
+      const int leader = __ffsll((long long)m) - 1;
+      const uint32_t lt = __shfl(tile, leader, 64);
+      const uint64_t same = __ballot(tile == lt);
+      if ((int)lane_id() == leader) atomicAdd(block_cnt + lt, (uint32_t)__popcll(same));
+      if (tile == lt) tile = kNoEntry;
     }
   }
   if (stats) {
@@ -744,27 +813,22 @@ __global__ __launch_bounds__(kBlock) void k_verify_finish(const SceneDev* __rest
   }
 }
 
-// replace bits per path tile (the work queue's block counts)
-__global__ __launch_bounds__(kBlock) void k_replace_count(const SceneDev* __restrict__ scenes,
-                                                          const uint2* __restrict__ tiles,
-                                                          uint32_t* __restrict__ block_cnt) {
-  __shared__ unsigned long long sred[kBlock / 64];
-  const uint2 tile = tiles[blockIdx.x];
-  const SceneDev& S = scenes[tile.x];
-  const uint32_t p = tile.y + threadIdx.x;
-  const uint32_t rep = p < S.n_paths ? info_replace(G(S.info)[p]) : 0u;
-  const unsigned long long n = block_sum_u64(rep, sred);
-  if (threadIdx.x == 0) block_cnt[blockIdx.x] = (uint32_t)n;
-}
-
 // sum of the per-block statistics of one verification call into pv_stats
+// (a few blocks, each adding its part with one atomic per counter)
 __global__ __launch_bounds__(1024) void k_verify_stats(const uint32_t* __restrict__ part, uint32_t n_scan,
                                                        uint32_t n_fin, pv_stats* stats) {
   __shared__ unsigned long long sh[4][1024 / 64];
   unsigned long long a[4] = {0, 0, 0, 0};
-  for (uint32_t b = threadIdx.x; b < n_scan; b += blockDim.x)
-    for (int k = 0; k < 4; ++k) a[k] += part[4 * (size_t)b + k];
-  for (uint32_t b = threadIdx.x; b < n_fin; b += blockDim.x)
+  const uint4* __restrict__ p4 = reinterpret_cast<const uint4*>(part);  // one record per scan block
+  const uint32_t step = gridDim.x * blockDim.x;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_scan; b += step) {
+    const uint4 r = p4[b];
+    a[0] += r.x;
+    a[1] += r.y;
+    a[2] += r.z;
+    a[3] += r.w;
+  }
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_fin; b += step)
     for (int k = 0; k < 2; ++k) a[k] += part[4 * (size_t)n_scan + 2 * (size_t)b + k];
   for (int k = 0; k < 4; ++k) {
     for (int o = 32; o > 0; o >>= 1) a[k] += __shfl_down(a[k], o, 64);
@@ -823,44 +887,65 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ in, 
   }
 }
 
-// Two-level exclusive scan for long count arrays: each block scans a tile of
-// kScanTile entries (4 per thread) in place of the single-block loop, the tile
-// totals are scanned by k_scan, and k_scan_add adds each tile's offset.
-constexpr uint32_t kScanTile = 4096;
+// Exclusive scan of count arrays: each block scans a tile of kScanTile
+// entries, kScanPer rows of 1024 read and written coalesced (row k of the tile
+// is entries k * 1024 .. k * 1024 + 1023).  Every row is scanned within its
+// waves, then one pass over the (row, wave) totals in entry order gives each
+// wave its offset.  One tile (the per-tile counts of a few million paths) is
+// the whole scan in one launch; longer arrays add k_scan over the tile totals
+// and k_scan_add.
+constexpr uint32_t kScanPer = 16;
+constexpr uint32_t kScanTile = 1024 * kScanPer;
 
 __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                      uint32_t n, uint32_t* __restrict__ tile_sums) {
-  __shared__ uint32_t wsum[16];
-  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * 4;
-  uint32_t v[4], loc = 0;
+  static_assert(kScanPer * 16 == 256, "four waves scan the (row, wave) totals");
+  __shared__ uint32_t part[kScanPer * 16];  // (row, wave) totals, then their exclusive offsets
+  __shared__ uint32_t qsum[4];
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  const uint32_t base = blockIdx.x * kScanTile + tid;
+  uint32_t v[kScanPer], x[kScanPer];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0u;
-    loc += v[k];
+  for (uint32_t k = 0; k < kScanPer; ++k) {
+    const uint32_t i = base + k * 1024;
+    v[k] = i < n ? in[i] : 0u;
+    x[k] = v[k];
   }
-  uint32_t x = loc;
   for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if ((int)lane_id() >= o) x += y;
-  }
-  if (lane_id() == 63) wsum[threadIdx.x >> 6] = x;
-  __syncthreads();
-  if (threadIdx.x < 16) {
-    uint32_t t = wsum[threadIdx.x];
-    for (int o = 1; o < 16; o <<= 1) {
-      uint32_t y = __shfl_up(t, o, 64);
-      if ((int)threadIdx.x >= o) t += y;
-    }
-    wsum[threadIdx.x] = t;
-  }
-  __syncthreads();
-  uint32_t run = ((threadIdx.x >> 6) ? wsum[(threadIdx.x >> 6) - 1] : 0u) + x - loc;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
+    for (uint32_t k = 0; k < kScanPer; ++k) {
+      const uint32_t y = __shfl_up(x[k], o, 64);
+      if ((int)lane >= o) x[k] += y;
+    }
   }
-  if (threadIdx.x == 0) tile_sums[blockIdx.x] = wsum[15];
+  if (lane == 63) {
+#pragma unroll
+    for (uint32_t k = 0; k < kScanPer; ++k) part[k * 16 + wave] = x[k];
+  }
+  __syncthreads();
+  uint32_t a = 0, q = 0;
+  if (tid < 256) {
+    a = part[tid];
+    q = a;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(q, o, 64);
+      if ((int)lane >= o) q += y;
+    }
+    if (lane == 63) qsum[wave] = q;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint32_t pre = 0;
+    for (uint32_t w = 0; w < wave; ++w) pre += qsum[w];
+    part[tid] = pre + q - a;
+  }
+  if (tid == 0) tile_sums[blockIdx.x] = qsum[0] + qsum[1] + qsum[2] + qsum[3];
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < kScanPer; ++k) {
+    const uint32_t i = base + k * 1024;
+    if (i < n) out[i] = part[k * 16 + wave] + x[k] - v[k];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, uint32_t n,
@@ -1623,7 +1708,7 @@ hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_
   if (!n_tiles) return hipSuccess;
   if (stack < 2 || stack > (uint32_t)kMaxStack || trace_blocks == 0 || min_active < 1 || min_active > 64)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_verify_scan, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W, stats);
+  hipLaunchKernelGGL(k_verify_scan, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W, block_cnt, stats);
   hipError_t e = launch_scan(W.tcount, W.toff, n_tiles, W.total, scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_verify_gather, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, W);
@@ -1631,20 +1716,28 @@ hipError_t launch_verify(const SceneDev* scenes, const uint2* tiles, uint32_t n_
   if (n_scenes == 1) {
     hipLaunchKernelGGL(k_verify_trace<true>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W,
                        min_active);
-    hipLaunchKernelGGL(k_verify_finish<true>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, n_tiles, stats);
+    hipLaunchKernelGGL(k_verify_finish<true>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, block_cnt, n_tiles,
+                       stats);
   } else {
     hipLaunchKernelGGL(k_verify_trace<false>, gt, dim3(kBlock), stack_bytes(stack), s, scenes, gbase, n_scenes, W,
                        min_active);
-    hipLaunchKernelGGL(k_verify_finish<false>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, n_tiles, stats);
+    hipLaunchKernelGGL(k_verify_finish<false>, gf, dim3(kBlock), 0, s, scenes, gbase, n_scenes, W, block_cnt, n_tiles,
+                       stats);
   }
-  hipLaunchKernelGGL(k_replace_count, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, block_cnt);
-  if (stats) hipLaunchKernelGGL(k_verify_stats, dim3(1), dim3(1024), 0, s, W.part, n_tiles, gf.x, stats);
+  if (stats) {
+    const uint32_t sb = std::min(16u, (std::max(n_tiles, gf.x) + 1023) / 1024);
+    hipLaunchKernelGGL(k_verify_stats, dim3(sb), dim3(1024), 0, s, W.part, n_tiles, gf.x, stats);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
                        uint32_t* tile_tmp, hipStream_t s) {
-  if (n <= kScanTile || !tile_tmp) {
+  if (n <= kScanTile) {  // one tile: its total is the scan's
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, in, out, n, total);
+    return hipGetLastError();
+  }
+  if (!tile_tmp) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, total);
     return hipGetLastError();
   }

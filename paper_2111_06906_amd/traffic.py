@@ -66,8 +66,7 @@ def _pick(d, key):
 
 # kernels launched once per verification call (the shared scan kernels that
 # also serve queue building and photon compaction are not attributed)
-VERIFY_KERNELS = ("k_verify_scan", "k_verify_gather", "k_verify_trace", "k_verify_finish", "k_replace_count",
-                  "k_verify_stats")
+VERIFY_KERNELS = ("k_verify_scan", "k_verify_gather", "k_verify_trace", "k_verify_finish", "k_verify_stats")
 
 
 def _per_call(d):

@@ -230,6 +230,22 @@ def test_sixty_four_objects(E):
     _lockstep(E, sc, 3, 0.01, "64 objects")
 
 
+def test_some_objects_still(E):
+    # objects 1, 2 and 5 never move and object 7 stops in frame 2: the moved
+    # objects' triangle id ranges form several runs with gaps between them
+    sc = scenes.make_paper(n_paths=4096 + 13, frames=3)
+    for o in (1, 2, 5):
+        sc.obj_xforms[:, o] = sc.obj_xforms[0, o]
+    sc.obj_xforms[2, 7] = sc.obj_xforms[1, 7]
+    _lockstep(E, sc, 3, 0.01, "paper, some objects still")
+    # a single moved object between still ones
+    sc = scenes.make_paper(n_paths=4096 + 13, frames=2)
+    for o in range(sc.n_dynamic):
+        if o != 4:
+            sc.obj_xforms[:, o] = sc.obj_xforms[0, o]
+    _lockstep(E, sc, 2, -1.0, "paper, one object moves")
+
+
 def test_object_rebuild_lockstep(E):
     # every object's hierarchy rebuilt on the device each frame (Morton codes,
     # radix sort, radix tree, bottom-up boxes) instead of refit: same results
