@@ -217,6 +217,21 @@ enum {
 pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value);
 pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
 
+/* Test of the dynamic-occlusion step (Section 3.2) used by pv_verify_paths.
+ * PV_VERIFY_TRIANGLES (default): a segment is invalid when a triangle of a
+ * moved object crosses it within (eps_end, L - eps_end).  PV_VERIFY_BOXES: the
+ * paper's conservative test, a segment is invalid once that part of it
+ * reaches the bounding box of a moved object (the box is the object's stored
+ * world box, padded by 1e-6 + 1e-6 |x| per coordinate); it invalidates every
+ * path the triangle test does, at the same or an earlier segment, and traces
+ * nothing.  Both tests take the first moved end photon and the origin update
+ * of Section 3.1 alike; Algorithm 1's own checks in pv_retrace_paths stay
+ * triangle-exact.  Takes effect for the context's next verification (a batch
+ * takes each context's mode when it is created).  PV_ERR_ARG for any other
+ * value. */
+enum { PV_VERIFY_TRIANGLES = 0, PV_VERIFY_BOXES = 1 };
+pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode);
+
 /* Autotuner: with the current frame (after pv_frame_begin) and the given
  * store, on a snapshot of the store: time verification for every traversal
  * grid (4, 8, 16, 32 workgroups per CU) and yield threshold (8, 16, 32, 48);

@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 HIT_NONE = 0xFFFFFFFF
-AMB_EDGE, AMB_END, AMB_LIGHT, AMB_TIE, AMB_HEMI, AMB_CLOSE = 1, 2, 4, 8, 16, 32
+AMB_EDGE, AMB_END, AMB_LIGHT, AMB_TIE, AMB_HEMI, AMB_CLOSE, AMB_BOX = 1, 2, 4, 8, 16, 32, 64
 
 _lib = None
 
@@ -45,6 +45,7 @@ class CScene(C.Structure):
         ("light_half", C.c_void_p), ("light_power", C.c_void_p), ("light_moved", C.c_void_p),
         ("light_base", C.c_void_p), ("eps_end", C.c_double), ("eps_close", C.c_double),
         ("band_verify", C.c_double), ("band_trace", C.c_double), ("radius", C.c_float),
+        ("verify_boxes", C.c_int32), ("band_box", C.c_double),
     ]
 
 
@@ -129,6 +130,8 @@ class FrameScene:
     band_verify: float = 1e-6
     band_trace: float = 1e-5
     radius: float = 0.01
+    verify_boxes: int = 0     # 1: Section 3.2's box test instead of the triangles
+    band_box: float = 1e-5    # ambiguity band of the box test (covers the kernels' box padding)
 
     def cstruct(self):
         self._keep = [_c(self.verts, np.float32), _c(self.tri_obj, np.uint32), _c(self.tri_mat, np.uint32),
@@ -138,7 +141,8 @@ class FrameScene:
         k = self._keep
         return CScene(k[0].shape[0], _p(k[0]), _p(k[1]), _p(k[2]), k[3].shape[0], _p(k[3]), _p(k[4]),
                       k[5].shape[0], _p(k[5]), _p(k[6]), _p(k[7]), _p(k[8]), _p(k[9]),
-                      self.eps_end, self.eps_close, self.band_verify, self.band_trace, self.radius)
+                      self.eps_end, self.eps_close, self.band_verify, self.band_trace, self.radius,
+                      int(self.verify_boxes), self.band_box)
 
 
 def transform(local_verts, m12):

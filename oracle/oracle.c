@@ -12,6 +12,9 @@
  *    the open interval (eps_end, L - eps_end) of its length L;
  *  - only objects whose transform changed are tested; a segment whose end
  *    photon lies on a moved object is invalid;
+ *  - the box mode (Section 3.2's own, conservative test) uses the exact box
+ *    of each moved object's current world triangles and the same interval
+ *    (eps_end, L - eps_end) of the segment;
  *  - world vertices are fp32(fma(m0,x,fma(m1,y,fma(m2,z,t)))) evaluated in FP64;
  *  - random numbers come from Philox4x64-10 keyed (seed, 0) with counter
  *    (path, frame, vertex, tag); uniforms are the top 24 bits times 2^-24;
@@ -257,10 +260,27 @@ typedef struct {
   const or_scene* s;
   chunk_t* ch;
   int64_t n_ch;
+  double* obox;  /* [n_obj][6] box (lo, hi) of each object's world triangles */
 } accel_t;
 
 static void accel_build(accel_t* a, const or_scene* s) {
   a->s = s;
+  a->obox = (double*)malloc(sizeof(double) * 6 * (size_t)(s->n_obj > 0 ? s->n_obj : 1));
+  for (int32_t o = 0; o < s->n_obj; ++o)
+    for (int k = 0; k < 3; ++k) {
+      a->obox[6 * o + k] = INFINITY;
+      a->obox[6 * o + 3 + k] = -INFINITY;
+    }
+  for (int64_t t = 0; t < s->n_tris; ++t) {
+    const uint32_t o = s->tri_obj[t];
+    if (o == 0 || (int32_t)o >= s->n_obj) continue;
+    for (int v = 0; v < 3; ++v)
+      for (int k = 0; k < 3; ++k) {
+        const double x = s->verts[9 * t + 3 * v + k];
+        if (x < a->obox[6 * o + k]) a->obox[6 * o + k] = x;
+        if (x > a->obox[6 * o + 3 + k]) a->obox[6 * o + 3 + k] = x;
+      }
+  }
   a->ch = (chunk_t*)malloc(sizeof(chunk_t) * (size_t)(s->n_tris / 1 + 1));
   a->n_ch = 0;
   int64_t t = 0;
@@ -283,13 +303,17 @@ static void accel_build(accel_t* a, const or_scene* s) {
   }
 }
 
-static void accel_free(accel_t* a) { free(a->ch); }
+static void accel_free(accel_t* a) {
+  free(a->ch);
+  free(a->obox);
+}
 
 /* does o + t d, t in [t0, t1], come within pad of the box? (slab test)      */
 static int seg_box(const double o[3], const double d[3], double t0, double t1, const double lo[3],
                    const double hi[3], double pad) {
   for (int k = 0; k < 3; ++k) {
     double l = lo[k] - pad, h = hi[k] + pad;
+    if (l > h) return 0; /* a box shrunk to nothing */
     if (d[k] == 0.0) {
       if (o[k] < l || o[k] > h) return 0;
     } else {
@@ -353,6 +377,34 @@ static int seg_blocked_moved(const accel_t* A, const double a[3], const double b
   }
   if (!certain) *amb |= local_amb;
   return blocked;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3.2's own test: does segment a->b, over the part (eps_end,         */
+/* L - eps_end) of its length L, reach the bounding box of a moved object?     */
+/* The decision is taken on the exact boxes and interval; *amb gets           */
+/* OR_AMB_BOX when growing, or shrinking, every box and the interval by the   */
+/* band would change it.                                                      */
+
+static int seg_reaches_moved_box(const accel_t* A, const double a[3], const double b[3], double band,
+                                 uint32_t* amb) {
+  const or_scene* s = A->s;
+  double d[3];
+  sub3(b, a, d);
+  double L = norm3(d);
+  if (L <= 0.0) return 0;
+  double e = s->eps_end;
+  int hit = 0, grown = 0, shrunk = 0;
+  for (int32_t o = 1; o < s->n_obj; ++o) {
+    if (!s->obj_moved[o]) continue;
+    const double* lo = A->obox + 6 * o;
+    const double* hi = lo + 3;
+    if (e <= L - e) hit |= seg_box(a, d, e / L, (L - e) / L, lo, hi, 0.0);
+    grown |= seg_box(a, d, (e - band) / L, (L - e + band) / L, lo, hi, band);
+    if (e + band <= L - e - band) shrunk |= seg_box(a, d, (e + band) / L, (L - e - band) / L, lo, hi, -band);
+  }
+  if (grown != shrunk) *amb |= OR_AMB_BOX;
+  return hit;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -518,7 +570,9 @@ static void verify_path(const or_scene* s, const accel_t* A, or_store* st, int64
     vtx(st, p, (int)j + 1, xb);
     ++ex;
     int inv = hit_on_moved(s, vhit(st, p, (int)j + 1));
-    if (!inv) inv = seg_blocked_moved(A, xa, xb, band, &a);
+    if (!inv)
+      inv = s->verify_boxes ? seg_reaches_moved_box(A, xa, xb, s->band_box, &a)
+                            : seg_blocked_moved(A, xa, xb, band, &a);
     if (inv) {
       out = info_make(cell, n, j, 1, 1);
       done = 1;

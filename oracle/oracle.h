@@ -44,6 +44,8 @@ typedef struct {
   double band_verify;        /* ambiguity band for verification decisions */
   double band_trace;         /* ambiguity band for traced rays */
   float radius;              /* radius written on new photons */
+  int32_t verify_boxes;      /* 1: a segment is invalid once it reaches a moved object's box */
+  double band_box;           /* ambiguity band of that box decision */
 } or_scene;
 
 typedef struct {
@@ -64,5 +66,6 @@ typedef struct {
 #define OR_AMB_TIE 8u
 #define OR_AMB_HEMI 16u
 #define OR_AMB_CLOSE 32u
+#define OR_AMB_BOX 64u
 
 #endif

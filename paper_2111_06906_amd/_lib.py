@@ -88,6 +88,7 @@ def lib():
         "pv_hierarchy_info": ([P, U32, I32, P], I32),
         "pv_object_hierarchy_info": ([P, U32, P], I32),
         "pv_set_tuning": ([P, I32, I32], I32),
+        "pv_set_verify_mode": ([P, I32], I32),
         "pv_get_tuning": ([P, I32, P], I32),
         "pv_autotune": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
     }
@@ -248,6 +249,13 @@ def object_hierarchy_info(ctx, obj):
 
 def set_tuning(ctx, key, value):
     check(lib().pv_set_tuning(ctx, key, value), ctx)
+
+
+PV_VERIFY_TRIANGLES, PV_VERIFY_BOXES = 0, 1
+
+
+def set_verify_mode(ctx, mode):
+    check(lib().pv_set_verify_mode(ctx, mode), ctx)
 
 
 def get_tuning(ctx, key):

@@ -61,6 +61,7 @@ struct pv_ctx {
   uint32_t static_depth = 0, obj_depth = 0, lbvh_depth = 0, top_depth = 0;
   pv::LbvhWork lw{};          // scratch of the per-frame object rebuild
   bool object_rebuild = false;  // PV_TUNE_OBJECT_REBUILD
+  bool verify_boxes = false;    // pv_set_verify_mode
   bool lbvh_used = false;       // a rebuilt hierarchy may be current: stacks sized for it
   std::vector<uint32_t> h_light_paths;  // filled at binding
   // scratch
@@ -924,6 +925,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     CK(dalloc(A, &hs.light_xf_cur, 12 * (size_t)d->n_lights));
     CK(dalloc(A, &hs.light_xf_prev, 12 * (size_t)d->n_lights));
     CK(dalloc(A, &hs.light_moved, d->n_lights));
+    hs.verify_boxes = ctx->verify_boxes ? 1u : 0u;
     hs.eps_end = d->eps_end;
     hs.eps_close = d->eps_close;
     hs.radius = d->photon_radius;
@@ -1141,6 +1143,17 @@ pv_status pv_set_tuning(pv_ctx* ctx, int32_t key, int32_t value) {
   } else {
     return fail(ctx, PV_ERR_ARG, "unknown tuning key");
   }
+  return PV_OK;
+}
+
+pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode) {
+  if (!ctx) return PV_ERR_ARG;
+  if (mode != PV_VERIFY_TRIANGLES && mode != PV_VERIFY_BOXES)
+    return fail(ctx, PV_ERR_ARG, "verify mode is PV_VERIFY_TRIANGLES or PV_VERIFY_BOXES");
+  ctx->verify_boxes = mode == PV_VERIFY_BOXES;
+  ctx->hs.verify_boxes = ctx->verify_boxes ? 1u : 0u;
+  if (ctx->uploaded)  // stream-ordered after the work already enqueued
+    CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
   return PV_OK;
 }
 

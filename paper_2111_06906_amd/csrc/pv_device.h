@@ -158,6 +158,7 @@ struct SceneDev {
   float* origin;
   uint32_t* info;
   uint32_t stride, n_paths, B;
+  uint32_t verify_boxes;  // 1: a segment that reaches a moved object's box is invalid (no triangle test)
   float eps_end, eps_close, radius;
   uint32_t gpath_base;    // offset of this scene's paths in the work-queue id space
   uint32_t n_blocks;      // path blocks of the bound store

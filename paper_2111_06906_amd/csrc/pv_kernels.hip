@@ -594,8 +594,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
         if (reaches_moved_box(M, segment_box_ray(a, b, S.eps_end))) mask |= 1u << j;
         a = b;
       }
-      cap = first_mv;
-      mask &= (1u << cap) - 1u;
+      if (S.verify_boxes) {
+        // Section 3.2's own test: the first segment that reaches a moved
+        // box is invalid, no triangle is tested (rows past n masked off)
+        mask &= (1u << n) - 1u;
+        cap = min(first_mv, mask ? (uint32_t)__ffs(mask) - 1u : n);
+        mask = 0;
+      } else {
+        cap = first_mv;
+        mask &= (1u << cap) - 1u;
+      }
     }
   }
   // ---- tasks into the tile's region, in lane order

@@ -202,6 +202,10 @@ class Context:
             if v is not None:
                 L.set_tuning(self.ctx, key, int(v))
 
+    def set_verify_mode(self, boxes):
+        """Section 3.2's conservative box test (True) or the triangle test (False)."""
+        L.set_verify_mode(self.ctx, L.PV_VERIFY_BOXES if boxes else L.PV_VERIFY_TRIANGLES)
+
     def object_hierarchy_info(self, obj):
         """Check of dynamic object obj's current device hierarchy (synchronises)."""
         return L.object_hierarchy_info(self.ctx, int(obj))

@@ -40,20 +40,22 @@ LIGHT_DOWN = np.array([1, 0, 0, 0.5, 0, 0, -1, 0.999, 0, 1, 0, 0.5], np.float32)
 
 
 def box_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_paths=1, light_moved=False,
-              light_xf=LIGHT_DOWN):
-    """Box plus optional cube blockers (each its own object), as a FrameScene."""
+              light_xf=LIGHT_DOWN, tri_blockers=()):
+    """Box plus optional cube blockers and single-triangle blockers (each its
+    own object, cubes first), as a FrameScene."""
     tris = [BOX]
     obj = [np.zeros(10, np.uint32)]
     mat = [np.zeros(10, np.uint32)]
-    for i, (center, side) in enumerate(blockers):
-        t = cube_tris(center, side)
+    parts = [cube_tris(center, side) for center, side in blockers]
+    parts += [np.asarray(t, np.float32).reshape(1, 3, 3) for t in tri_blockers]
+    for i, t in enumerate(parts):
         tris.append(t)
-        obj.append(np.full(12, i + 1, np.uint32))
-        mat.append(np.ones(12, np.uint32))
+        obj.append(np.full(t.shape[0], i + 1, np.uint32))
+        mat.append(np.ones(t.shape[0], np.uint32))
     verts = np.concatenate(tris).reshape(-1, 9)
     return O.FrameScene(
         verts=verts, tri_obj=np.concatenate(obj), tri_mat=np.concatenate(mat),
-        obj_moved=np.array([0] + [1 if moved else 0] * len(blockers), np.uint8),
+        obj_moved=np.array([0] + [1 if moved else 0] * len(parts), np.uint8),
         albedo=np.array([[albedo_box] * 3, [albedo_blocker] * 3], np.float32),
         light_xf=np.asarray(light_xf, np.float32)[None], light_half=np.array([[0.1, 0.1]], np.float32),
         light_power=np.ones((1, 3), np.float32), light_moved=np.array([1 if light_moved else 0], np.uint8),

@@ -163,11 +163,13 @@ def test_max_bounces_fifteen(E):
 # the oracle's store of the previous frame)
 
 
-def _lockstep(E, sc, n_frames, T, label, tuning=None):
+def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False):
     ora, _ = _oracle_frame0(sc)
     ctx = E.Context(sc)
     if tuning:
         ctx.set_tuning(**tuning)
+    if boxes:
+        ctx.set_verify_mode(True)
     ctx.frame_begin(0)
     st = ctx.new_store()
     total_rep = 0
@@ -178,6 +180,7 @@ def _lockstep(E, sc, n_frames, T, label, tuning=None):
         ctx.verify(st)
         gv = st.to_numpy()
         fs = O.frame_scene(sc, f, f - 1)
+        fs.verify_boxes = int(boxes)
         ambv, _ = O.verify(fs, ora)
         ok = _amb_ok(ambv)  # both sides start this frame from the same oracle store
         assert np.array_equal(gv["info"][ok], ora.info[ok])
@@ -244,6 +247,38 @@ def test_some_objects_still(E):
         if o != 4:
             sc.obj_xforms[:, o] = sc.obj_xforms[0, o]
     _lockstep(E, sc, 2, -1.0, "paper, one object moves")
+
+
+def test_box_mode_lockstep(E):
+    # Section 3.2's own conservative test: a segment reaching a moved object's
+    # box is invalid; then the usual re-trace
+    sc = scenes.make_mid(n_paths=6000 + 19, frames=3, threshold=0.01)
+    _lockstep(E, sc, 3, 0.01, "mid, box test", boxes=True)
+    sc = scenes.make_paper(n_paths=4096 + 13, frames=2)
+    _lockstep(E, sc, 2, -1.0, "paper, box test, naive", boxes=True)
+
+
+def test_box_mode_invalidates_a_superset(E):
+    # on the device: every path the triangle test replaces is replaced by the
+    # box test at the same or an earlier segment (same store, same frame)
+    sc = scenes.make_mid(n_paths=20000, frames=2)
+    ora, _ = _oracle_frame0(sc)
+    starts = {}
+    for boxes in (False, True):
+        ctx = E.Context(sc)
+        ctx.set_verify_mode(boxes)
+        ctx.frame_begin(0)
+        st = ctx.new_store()
+        st.load_numpy(H.from_oracle(ora))
+        ctx.frame_begin(1)
+        ctx.verify(st)
+        info = st.to_numpy()["info"].astype(np.int64)
+        starts[boxes] = np.where((info >> 30) & 1, (info >> 26) & 15, 99)
+        ctx.close()
+    tri, box = starts[False], starts[True]
+    assert np.all(box <= tri)
+    assert (box < tri).sum() > 0
+    log("box test replaces %d paths, triangle test %d" % ((box < 99).sum(), (tri < 99).sum()))
 
 
 def test_object_rebuild_lockstep(E):

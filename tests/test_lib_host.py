@@ -49,6 +49,7 @@ def test_argument_errors_without_device():
     # NULL context
     assert lib.pv_upload_scene(None, None) == L.PV_ERR_ARG
     assert lib.pv_verify_paths(None, None, None) == L.PV_ERR_ARG
+    assert lib.pv_set_verify_mode(None, L.PV_VERIFY_BOXES) == L.PV_ERR_ARG
     out = C.c_void_p()
     code = lib.pv_create(C.byref(out), None)
     import torch

@@ -228,6 +228,107 @@ def test_segment_near_edge_is_flagged():
 
 
 # ---------------------------------------------------------------------------
+# Section 3.2's own test: a segment that reaches a moved object's bounding box
+# is invalid (conservative); the triangle-exact mode is the default
+
+# a tilted triangle whose box segment 1 of the worked path crosses (over
+# t in [0.56, 0.64]) while its plane is crossed outside the triangle
+# (barycentric u = -0.175)
+_TRI_NEAR_SEG1 = [[0.75, 0.28, 0.45], [0.85, 0.28, 0.45], [0.75, 0.32, 0.53]]
+
+
+def test_box_mode_invalidates_segment_through_box_missing_triangle():
+    st = H.store_from_paths([_worked_path()], 3)
+    fs = H.box_scene(tri_blockers=[_TRI_NEAR_SEG1])
+    amb, ex = O.verify(fs, st)
+    assert O.info_fields(st.info)["replace"][0] == 0 and amb[0] == 0 and ex[0] == 3
+    st = H.store_from_paths([_worked_path()], 3)
+    fs.verify_boxes = 1
+    amb, ex = O.verify(fs, st)
+    f = O.info_fields(st.info)
+    assert (f["replace"][0], f["start"][0], f["reuse"][0]) == (1, 1, 1) and amb[0] == 0 and ex[0] == 2
+
+
+def test_box_mode_unmoved_object_and_far_box_keep_the_path():
+    st = H.store_from_paths([_worked_path()], 3)
+    fs = H.box_scene(tri_blockers=[_TRI_NEAR_SEG1], moved=False)
+    fs.verify_boxes = 1
+    O.verify(fs, st)
+    assert O.info_fields(st.info)["replace"][0] == 0
+    st = H.store_from_paths([_worked_path()], 3)
+    fs = H.box_scene(tri_blockers=[[[0.1, 0.8, 0.8], [0.2, 0.8, 0.8], [0.1, 0.9, 0.9]]])
+    fs.verify_boxes = 1
+    amb, _ = O.verify(fs, st)
+    assert O.info_fields(st.info)["replace"][0] == 0 and amb[0] == 0
+
+
+def test_box_mode_grazing_a_face_is_flagged():
+    # segment 0 runs down x = 0.5; a box face 1e-7 beside it is within the band
+    tri = [[0.5 + 1e-7, 0.4, 0.45], [0.6, 0.4, 0.55], [0.6, 0.6, 0.45]]
+    st = H.store_from_paths([_worked_path()], 3)
+    fs = H.box_scene(tri_blockers=[tri])
+    fs.verify_boxes = 1
+    amb, _ = O.verify(fs, st)
+    assert amb[0] & O.AMB_BOX
+
+
+def test_box_mode_matches_dense_sampling():
+    # one-segment paths against three moved triangles' boxes: where the oracle
+    # reports no ambiguity, its decision equals whether a point sampled every
+    # 5e-6 along the tested part (eps_end, L - eps_end) lies inside a box (a
+    # decision clear of the 1e-5 band has a chord longer than 2e-5 in the box)
+    rng = np.random.default_rng(11)
+    tris = [rng.uniform(0.2, 0.8, (3, 3)) for _ in range(3)]
+    boxes = [(t.astype(np.float32).astype(np.float64).min(0), t.astype(np.float32).astype(np.float64).max(0))
+             for t in tris]
+    n = 300
+    a = rng.uniform(0.05, 0.95, (n, 3))
+    b = rng.uniform(0.05, 0.95, (n, 3))
+    paths = [(a[i], [(b[i], 0)]) for i in range(n)]
+    st = H.store_from_paths(paths, 1)
+    fs = H.box_scene(tri_blockers=tris, n_paths=n)
+    fs.verify_boxes = 1
+    amb, _ = O.verify(fs, st)
+    rep = O.info_fields(st.info)["replace"]
+    eps = fs.eps_end
+    checked = hits = 0
+    for i in range(n):
+        if amb[i]:
+            continue
+        A = st.origin[i].astype(np.float64)
+        Bp = st.pos[0, i].astype(np.float64)
+        L = np.linalg.norm(Bp - A)
+        t = np.arange(eps, L - eps, 5e-6) / L
+        pts = A + t[:, None] * (Bp - A)
+        inside = any(np.any(np.all((pts >= lo) & (pts <= hi), 1)) for lo, hi in boxes)
+        assert bool(rep[i]) == inside, i
+        checked += 1
+        hits += int(inside)
+    assert checked > 0.95 * n and 0.1 * checked < hits < 0.9 * checked
+
+
+def test_box_mode_is_conservative_on_a_traced_scene():
+    # every path the triangle test invalidates is invalidated by the box test
+    # at the same or an earlier segment; paths the box test keeps are kept
+    # (rooms with tori: a torus fills only part of its box)
+    sc = scenes.make_mid(n_paths=2048, frames=2)
+    fs0 = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    fs = O.frame_scene(sc, 1, 0)
+    se, sb = st.copy(), st.copy()
+    amb_e, _ = O.verify(fs, se)
+    fs.verify_boxes = 1
+    amb_b, _ = O.verify(fs, sb)
+    ok = (amb_e == 0) & (amb_b == 0)
+    fe, fb = O.info_fields(se.info), O.info_fields(sb.info)
+    assert ok.sum() > 0.95 * sc.n_paths
+    assert np.all(fb["replace"][ok] >= fe["replace"][ok])
+    both = ok & (fe["replace"] == 1)
+    assert np.all(fb["start"][both] <= fe["start"][both])
+    assert (fb["replace"][ok] > fe["replace"][ok]).sum() > 0  # the box test is looser here
+
+
+# ---------------------------------------------------------------------------
 # light origin update closed forms (Section 3.1)
 
 
