@@ -293,6 +293,28 @@ def main():
         torch.cuda.synchronize()
         base_ms.append(e0.elapsed_time(e1))
     res["baseline_retrace_all_ms"] = sum(base_ms) / len(base_ms)
+    # the paper's own dynamic-occlusion test (moved objects' bounding boxes,
+    # PV_VERIFY_BOXES) on the frames that follow: cheaper verification, more
+    # paths to re-trace
+    ctx.set_verify_mode(True)
+    bx = {"verify": [], "retrace": [], "frame": [], "paths_invalid": [], "rays_traced": []}
+    for i in range(5):
+        f = 1 + (3 + args.warmup + i) % max(1, sc.n_frames - 1)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        s = ctx.new_stats()
+        step(f, ev, s)
+        torch.cuda.synchronize()
+        d = ctx.stats_dict(s)
+        if i == 0:
+            continue  # first frame after the full re-trace baseline
+        bx["verify"].append(ev[1].elapsed_time(ev[2]))
+        bx["retrace"].append(ev[3].elapsed_time(ev[4]))
+        bx["frame"].append(ev[0].elapsed_time(ev[5]))
+        bx["paths_invalid"].append(d["paths_invalid"])
+        bx["rays_traced"].append(d["rays_traced"])
+    ctx.set_verify_mode(False)
+    res["box_test_mode"] = {k + ("" if k in ("paths_invalid", "rays_traced") else "_ms"): sum(v) / len(v)
+                            for k, v in bx.items()}
     # frame begin (object transforms, hierarchies, top-level trees) with the
     # objects' hierarchies refit, then with every object's hierarchy rebuilt on
     # the device as a linear BVH (last: the mode keeps larger traversal stacks)
