@@ -92,8 +92,10 @@ typedef struct {
   const uint32_t* h_obj_mat;     /* [sum obj_tris] material ids */
   uint32_t n_materials;
   const float* h_albedo;         /* [n_materials][3] diffuse albedo rho */
-  uint32_t n_lights;             /* rectangular area lights, <= PV_MAX_LIGHTS */
-  const float* h_light_half;     /* [n_lights][2] half extents along local u, v */
+  uint32_t n_lights;             /* lights, <= PV_MAX_LIGHTS */
+  const float* h_light_half;     /* [n_lights][2] half extents along local u, v: both > 0 for a
+                                    rectangular area light, both 0 for a point light (PV_ERR_ARG
+                                    otherwise); both emit cosine-weighted about the local z axis */
   const float* h_light_power;    /* [n_lights][3] radiant power Phi */
   float eps_end;                 /* segment endpoint tolerance (scene units) */
   float eps_close;               /* AreClose tolerance of Algorithm 1 (scene units) */
@@ -147,7 +149,7 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces);
  * transforms.  d_obj_xf: [n_objects][12] device floats, row-major 3x4 [R|t]
  * (world = R p + t); d_light_xf: [n_lights][12] rigid light transforms (light
  * local z = emitting normal, the light is the rectangle |u|<=hu, |v|<=hv of
- * its local z=0 plane).  An object or light is "moved" when any of its 12
+ * its local z=0 plane, or its local origin for a point light).  An object or light is "moved" when any of its 12
  * floats differs bitwise from the previous frame's; the first call marks
  * everything moved.  Then transforms the moved objects' triangles to world
  * space (each coordinate the FP64 evaluation of fma(r0,x,fma(r1,y,fma(r2,z,t)))
@@ -157,7 +159,11 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
 /* Sections 3.1 and 3.2 (update path origins, dynamic occlusions): for each
  * path of a moved light, keep the outgoing direction and move x_0 onto the
  * light's new plane (invalid when outside the rectangle or behind the light:
- * replace=1, start=0, reuse_light=0); then test the segments in order from the
+ * replace=1, start=0, reuse_light=0); for a point light, x_0 becomes the
+ * light's new position and segment 0 is re-aimed at the first photon (invalid
+ * as above when that is not farther than eps_end on the emitting side), and
+ * segment 0 is then tested against every triangle, static ones included (a
+ * visibility ray in place of the paper's shadow map); then test the segments in order from the
  * light against every triangle of the moved objects (two-sided, hit strictly
  * inside (eps_end, L-eps_end)), a segment also being invalid when its end
  * photon lies on a moved object; the first invalid segment k gives replace=1,

@@ -12,6 +12,11 @@
  *    the open interval (eps_end, L - eps_end) of its length L;
  *  - only objects whose transform changed are tested; a segment whose end
  *    photon lies on a moved object is invalid;
+ *  - a light with both half extents 0 is a point light emitting cosine-
+ *    weighted about its normal; Section 3.1's point-light update moves the
+ *    origin to the light's new position, re-aims segment 0 at the first
+ *    photon (lost when that leaves the emitting side) and replaces the
+ *    shadow-map test by a visibility segment against every triangle;
  *  - the box mode (Section 3.2's own, conservative test) uses the exact box
  *    of each moved object's current world triangles and the same interval
  *    (eps_end, L - eps_end) of the segment;
@@ -332,13 +337,14 @@ static void tri_verts(const or_scene* s, int64_t t, double v[9]) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Section 3.2: is segment a->b blocked by a triangle of a moved object?      */
+/* Section 3.2: is segment a->b blocked by a triangle of a moved object (of   */
+/* any object and the static world when 'all': a point light's visibility)?  */
 /* Result: 0 clear, 1 blocked.  *amb |= flags when some triangle lies within  */
 /* the band of the decision (edge or endpoint) and no triangle blocks it      */
 /* with margin.                                                               */
 
-static int seg_blocked_moved(const accel_t* A, const double a[3], const double b[3], double band,
-                             uint32_t* amb) {
+static int seg_blocked(const accel_t* A, const double a[3], const double b[3], double band, int all,
+                       uint32_t* amb) {
   const or_scene* s = A->s;
   double d[3];
   sub3(b, a, d);
@@ -355,7 +361,7 @@ static int seg_blocked_moved(const accel_t* A, const double a[3], const double b
   uint32_t local_amb = 0;
   for (int64_t c = 0; c < A->n_ch && !certain; ++c) {
     const chunk_t* ch = &A->ch[c];
-    if (ch->obj == 0 || !s->obj_moved[ch->obj]) continue;
+    if (!all && (ch->obj == 0 || !s->obj_moved[ch->obj])) continue;
     if (!seg_box(a, d, tlo, thi, ch->lo, ch->hi, band + 1e-9)) continue;
     for (int64_t t = ch->first; t < ch->first + ch->count; ++t) {
       double v[9], tt, u, w;
@@ -486,6 +492,20 @@ int or_light_update(const float* xf, const float* half, const double x0[3], cons
                     double eps, double band, double out[3], uint32_t* amb) {
   double c[3], eu[3], ev[3], n[3], w[3];
   light_frame(xf, c, eu, ev, n);
+  if (half[0] == 0.0f && half[1] == 0.0f) {
+    /* point light: the sample is the light's new position and segment 0 is */
+    /* re-aimed at the first photon; it must leave on the emitting side and  */
+    /* be longer than eps (its visibility is tested by the caller)           */
+    sub3(x1, c, w);
+    double len = norm3(w);
+    if (fabs(len - eps) <= band) *amb |= OR_AMB_LIGHT;
+    if (!(len > eps)) return 0;
+    double dn = dot3(w, n) / len;
+    if (fabs(dn) <= band) *amb |= OR_AMB_LIGHT;
+    if (!(dn > 0.0)) return 0;
+    for (int i = 0; i < 3; ++i) out[i] = c[i];
+    return 1;
+  }
   sub3(x1, x0, w);
   double len = norm3(w);
   if (len <= 0.0) return 0;
@@ -549,6 +569,7 @@ static void verify_path(const or_scene* s, const accel_t* A, or_store* st, int64
   int ex = 0, done = 0;
   int l = light_of(s, p);
   uint32_t out = info_make(cell, n, 0, 0, 0);
+  int visibility = 0; /* segment 0 is tested against every triangle */
   if (l >= 0 && s->light_moved[l]) {
     double x0[3], x1[3], nx[3];
     if (n == 0) {
@@ -557,10 +578,12 @@ static void verify_path(const or_scene* s, const accel_t* A, or_store* st, int64
       vtx(st, p, 0, x0);
       vtx(st, p, 1, x1);
       if (or_light_update(s->light_xf + 12 * l, s->light_half + 2 * l, x0, x1, s->eps_end, band,
-                          nx, &a))
+                          nx, &a)) {
         store3f(st->origin + 3 * p, nx);
-      else
+        visibility = s->light_half[2 * l] == 0.0f && s->light_half[2 * l + 1] == 0.0f;
+      } else {
         done = 1;
+      }
     }
     if (done) out = info_make(cell, n, 0, 1, 0);
   }
@@ -570,9 +593,13 @@ static void verify_path(const or_scene* s, const accel_t* A, or_store* st, int64
     vtx(st, p, (int)j + 1, xb);
     ++ex;
     int inv = hit_on_moved(s, vhit(st, p, (int)j + 1));
-    if (!inv)
-      inv = s->verify_boxes ? seg_reaches_moved_box(A, xa, xb, s->band_box, &a)
-                            : seg_blocked_moved(A, xa, xb, band, &a);
+    if (!inv && s->verify_boxes) inv = seg_reaches_moved_box(A, xa, xb, s->band_box, &a);
+    if (!inv) {
+      if (j == 0 && visibility)
+        inv = seg_blocked(A, xa, xb, band, 1, &a); /* every triangle: the point light's visibility */
+      else if (!s->verify_boxes)
+        inv = seg_blocked(A, xa, xb, band, 0, &a); /* the moved objects' triangles */
+    }
     if (inv) {
       out = info_make(cell, n, j, 1, 1);
       done = 1;
@@ -606,7 +633,7 @@ void or_verify_list(const or_scene* s, or_store* st, const int64_t* list, int64_
 int or_segment_query(const or_scene* s, const double a[3], const double b[3], uint32_t* amb) {
   accel_t A;
   accel_build(&A, s);
-  int r = seg_blocked_moved(&A, a, b, s->band_verify, amb);
+  int r = seg_blocked(&A, a, b, s->band_verify, 0, amb);
   accel_free(&A);
   return r;
 }
@@ -787,7 +814,7 @@ static void retrace_path(rctx* c, int64_t p, uint32_t* amb, int* traces) {
       vtx(st, p, j + 1, xb);
       if (!need) {
         int inv = hit_on_moved(s, vhit(st, p, j + 1));
-        if (!inv) inv = seg_blocked_moved(c->A, xa, xb, s->band_trace, amb);
+        if (!inv) inv = seg_blocked(c->A, xa, xb, s->band_trace, 0, amb);
         if (!inv) { ++j; continue; }
       }
       double d[3];
@@ -835,7 +862,7 @@ static void retrace_path(rctx* c, int64_t p, uint32_t* amb, int* traces) {
       uint32_t old_hit = vhit(st, p, j + 1);
       if (dist <= s->eps_close && !hit_on_moved(s, (uint32_t)h.tri) && !hit_on_moved(s, old_hit) &&
           !hit_on_moved(s, vhit(st, p, j + 2)) &&
-          !seg_blocked_moved(c->A, xb, xc, s->band_trace, amb)) {
+          !seg_blocked(c->A, xb, xc, s->band_trace, 0, amb)) {
         j += 2;
         need = 0;
         continue;

@@ -62,6 +62,7 @@ struct pv_ctx {
   pv::LbvhWork lw{};          // scratch of the per-frame object rebuild
   bool object_rebuild = false;  // PV_TUNE_OBJECT_REBUILD
   bool verify_boxes = false;    // pv_set_verify_mode
+  bool point_lights = false;    // a light of zero extent: verification walks the whole scene
   bool lbvh_used = false;       // a rebuilt hierarchy may be current: stacks sized for it
   std::vector<uint32_t> h_light_paths;  // filled at binding
   // scratch
@@ -549,6 +550,8 @@ static void size_stacks(pv_ctx* ctx) {
   const uint32_t od = ctx->lbvh_used ? std::max(ctx->obj_depth, ctx->lbvh_depth) : ctx->obj_depth;
   ctx->stack_entries = pv::stack_entries(ctx->top_depth, std::max(ctx->static_depth, od));
   ctx->stack_moved = pv::stack_entries(ceil_log2(ctx->n_objects), od);
+  // a point light's visibility test walks the whole scene during verification
+  if (ctx->point_lights) ctx->stack_moved = std::max(ctx->stack_moved, ctx->stack_entries);
 }
 
 // Invariants of a hierarchy over leaf-order vertices: leaves partition the
@@ -684,6 +687,11 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     if (d->n_materials < 1 || !d->h_albedo) return fail(ctx, PV_ERR_ARG, "no materials");
     if (d->n_static && (!d->h_static_verts || !d->h_static_mat)) return fail(ctx, PV_ERR_ARG, "static arrays NULL");
     if (!d->h_light_half || !d->h_light_power) return fail(ctx, PV_ERR_ARG, "light arrays NULL");
+    for (uint32_t l = 0; l < d->n_lights; ++l) {
+      const float hu = d->h_light_half[2 * l], hv = d->h_light_half[2 * l + 1];
+      if (!((hu > 0.0f && hv > 0.0f) || (hu == 0.0f && hv == 0.0f)))
+        return fail(ctx, PV_ERR_ARG, "light half extents must both be positive (rectangle) or both 0 (point light)");
+    }
     if (!(d->eps_end > 0.0f) || !(d->eps_close >= 0.0f)) return fail(ctx, PV_ERR_ARG, "bad tolerances");
     uint64_t n_dyn = 0;
     for (uint32_t o = 0; o < d->n_objects; ++o) {
@@ -959,6 +967,9 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     ctx->lbvh_depth = d->n_objects ? (uint32_t)kMaxDepth : 0;
     ctx->lw = lw;
     ctx->lbvh_used = ctx->object_rebuild;
+    ctx->point_lights = false;
+    for (uint32_t l = 0; l < d->n_lights; ++l)
+      ctx->point_lights |= d->h_light_half[2 * l] == 0.0f && d->h_light_half[2 * l + 1] == 0.0f;
     size_stacks(ctx);
     ctx->h_light_paths.assign(d->n_lights, 0);
     ctx->uploaded = true;

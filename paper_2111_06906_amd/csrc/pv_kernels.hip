@@ -417,11 +417,23 @@ __device__ inline int light_of(const SceneDev& S, uint32_t p) {
 }
 
 // Section 3.1 for a rectangular area light: keep the outgoing direction and
-// intersect it with the light's current plane.
-__device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 x1, float3* out) {
+// intersect it with the light's current plane.  A light with both half
+// extents 0 is a point light: the sample becomes the light's new position and
+// segment 0 is re-aimed at the first photon, which must lie on the emitting
+// side farther than eps_end; *vis then asks for segment 0 to be tested
+// against every triangle (the visibility the paper reads from a shadow map).
+__device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 x1, float3* out, bool* vis) {
   const PV_GLOBAL float* xf = G(S.light_xf_cur) + 12 * l;
   float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
   float3 n = f3(xf[2], xf[6], xf[10]), c = f3(xf[3], xf[7], xf[11]);
+  const PV_GLOBAL LightDev* lt = G(S.lights) + l;
+  if (lt->half[0] == 0.0f && lt->half[1] == 0.0f) {
+    const float3 w = sub(x1, c);
+    if (!(length(w) > S.eps_end) || !(dot(w, n) > 0.0f)) return false;
+    *out = c;
+    *vis = true;
+    return true;
+  }
   n = mul(n, 1.0f / length(n));
   float3 w = sub(x1, x0);
   float len = length(w);
@@ -434,7 +446,6 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
   float3 p = sub(x1, mul(w, sdist));
   float3 r = sub(p, c);
   float u = dot(r, eu), v = dot(r, ev);
-  const PV_GLOBAL LightDev* lt = G(S.lights) + l;
   if (!(fabsf(u) <= lt->half[0] && fabsf(v) <= lt->half[1])) return false;
   *out = p;
   return true;
@@ -509,6 +520,10 @@ __device__ inline void deal_reset(uint32_t* ctrs) {
 // segment is the minimum over blocked segments and the first moved endpoint.
 
 constexpr int kPreRows = 8;  // bounce rows a lane loads before testing
+// task segment field of a point light's visibility test of segment 0 (real
+// segments are 0..14)
+constexpr uint32_t kVisTask = 15;
+static_assert(PV_MAX_BOUNCES <= 15, "segment indices below kVisTask");
 
 __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restrict__ scenes,
                                                         const uint2* __restrict__ tiles, VerifyWork W,
@@ -524,6 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
   const bool active = p < S.n_paths;
   const size_t stride = S.stride;
   uint32_t n = 0, cell = 0, cap = 0, mask = 0, lost = 0;
+  bool vis = false;  // a point light moved: segment 0 against every triangle
   if (active) {
     const PV_GLOBAL float4* pos = G(S.pos);
     PV_GLOBAL float* org = G(S.origin);
@@ -544,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
     int l = light_of(S, p);
     if (l >= 0 && G(S.light_moved)[l]) {
       float3 na;
-      if (n > 0 && light_update(S, l, a, xyz(rows[0]), &na)) {
+      if (n > 0 && light_update(S, l, a, xyz(rows[0]), &na, &vis)) {
         a = na;
         org[p] = na.x;
         org[stride + p] = na.y;
@@ -605,6 +621,9 @@ __global__ __launch_bounds__(kBlock) void k_verify_scan(const SceneDev* __restri
         mask &= (1u << cap) - 1u;
       }
     }
+    // the visibility task (segment index kVisTask) replaces segment 0's own
+    // test, which it covers; none when segment 0 is already invalid
+    if (vis && cap > 0) mask = (mask & ~1u) | (1u << kVisTask);
   }
   // ---- tasks into the tile's region, in lane order
   const uint32_t nt = (uint32_t)__popc(mask);
@@ -722,6 +741,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
           const uint32_t tk = G(W.tasks)[t];
           gp = tk >> 4;
           j = tk & 15u;
+          const bool vis = j == kVisTask;  // segment 0 against the whole scene
+          if (vis) j = 0;
           if (j < __hip_atomic_load(&W.first[gp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             S = scenes + (kSingle ? 0u : scene_of(gbase, n_scenes, gp));
             const uint32_t q = gp - S->gpath_base;
@@ -747,6 +768,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
               }
               root = nh == 0 ? kRootNone : (nh == 1 ? only : root);
             }
+            if (vis) root = G(S->top)[0];
             walk_start(w, root, r.tmax, col);
             busy = root != kRootNone;
           }

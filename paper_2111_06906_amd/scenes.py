@@ -311,7 +311,7 @@ def _tess_count(panels, boxes, h):
 
 def make_rooms(name, nx, nz, static_target, n_dyn, torus_segs, n_paths, max_bounces,
                frames, threshold, seed, n_lights=2, lights_move=False,
-               torus_size=(0.16, 0.055), clutter_per_room=2):
+               torus_size=(0.16, 0.055), clutter_per_room=2, point_lights=False):
     rng = np.random.default_rng(seed)
     panels, wx, wz = _room_panels(nx, nz, rng)
     boxes = _clutter(nx, nz, clutter_per_room, rng)
@@ -346,7 +346,8 @@ def make_rooms(name, nx, nz, static_target, n_dyn, torus_segs, n_paths, max_boun
     order = rng.permutation(len(rooms))
     light_rooms = [rooms[j] for j in order[:n_lights]]
     y_light = 0.25 - (0.02 if lights_move else 0.001)
-    light_half = np.full((n_lights, 2), 0.05, F32)
+    # rectangles of 0.1 x 0.1, or points (both half extents 0)
+    light_half = np.full((n_lights, 2), 0.0 if point_lights else 0.05, F32)
     light_power = np.ones((n_lights, 3), F32)
     lpos = np.array([[-1 + (i + 0.5) * wx, y_light, -1 + (k + 0.5) * wz] for i, k in light_rooms])
     ltilt = np.zeros((n_lights, 2))

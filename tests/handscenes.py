@@ -40,7 +40,7 @@ LIGHT_DOWN = np.array([1, 0, 0, 0.5, 0, 0, -1, 0.999, 0, 1, 0, 0.5], np.float32)
 
 
 def box_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_paths=1, light_moved=False,
-              light_xf=LIGHT_DOWN, tri_blockers=()):
+              light_xf=LIGHT_DOWN, tri_blockers=(), light_half=(0.1, 0.1)):
     """Box plus optional cube blockers and single-triangle blockers (each its
     own object, cubes first), as a FrameScene."""
     tris = [BOX]
@@ -57,7 +57,7 @@ def box_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_pat
         verts=verts, tri_obj=np.concatenate(obj), tri_mat=np.concatenate(mat),
         obj_moved=np.array([0] + [1 if moved else 0] * len(parts), np.uint8),
         albedo=np.array([[albedo_box] * 3, [albedo_blocker] * 3], np.float32),
-        light_xf=np.asarray(light_xf, np.float32)[None], light_half=np.array([[0.1, 0.1]], np.float32),
+        light_xf=np.asarray(light_xf, np.float32)[None], light_half=np.array([light_half], np.float32),
         light_power=np.ones((1, 3), np.float32), light_moved=np.array([1 if light_moved else 0], np.uint8),
         light_base=np.array([0, n_paths], np.int64))
 

@@ -281,6 +281,17 @@ def test_box_mode_invalidates_a_superset(E):
     log("box test replaces %d paths, triangle test %d" % ((box < 99).sum(), (tri < 99).sum()))
 
 
+def test_point_lights_lockstep(E):
+    # moving point lights (both half extents 0): the origin follows the light,
+    # segment 0 is re-aimed at the first photon and tested against every
+    # triangle, static ones included (Section 3.1's point-light update)
+    sc = scenes.make_rooms("points", 3, 3, 20000, 4, (24, 12), 6000 + 11, 5, 3, 0.01, 21,
+                           lights_move=True, point_lights=True)
+    _lockstep(E, sc, 3, 0.01, "point lights")
+    _lockstep(E, sc, 3, -1.0, "point lights, naive")
+    _lockstep(E, sc, 2, -1.0, "point lights, box test", boxes=True)
+
+
 def test_object_rebuild_lockstep(E):
     # every object's hierarchy rebuilt on the device each frame (Morton codes,
     # radix sort, radix tree, bottom-up boxes) instead of refit: same results

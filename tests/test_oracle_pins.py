@@ -346,6 +346,63 @@ def test_light_update_in_plane_translation():
     assert not ok2
 
 
+# point lights (both half extents 0): Section 3.1's point-light update
+
+
+def test_point_light_update_moves_origin_to_the_light():
+    # the sample becomes the light's new position; no direction test beyond the
+    # emitting side and no plane intersection
+    x0 = np.array([0.5, 0.999, 0.5])
+    x1 = np.array([0.3, 0.0, 0.8])
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(0.03)
+    xf[7] -= np.float32(0.01)
+    ok, nx, amb = O.light_update(xf, [0.0, 0.0], x0, x1)
+    assert ok and amb == 0
+    assert np.array_equal(nx, np.array([xf[3], xf[7], xf[11]], np.float64))
+    # a first photon above the light's plane is on its non-emitting side: lost
+    ok2, _, _ = O.light_update(xf, [0.0, 0.0], x0, np.array([0.3, 0.9999, 0.8]))
+    assert not ok2
+    # grazing the plane is flagged
+    _, _, amb3 = O.light_update(xf, [0.0, 0.0], x0, np.array([0.9, float(xf[7]) - 1e-8, 0.5]))
+    assert amb3 & O.AMB_LIGHT
+
+
+def test_point_light_sample_is_the_light_position():
+    xf = H.LIGHT_DOWN.copy()
+    for path in range(50):
+        x0, w = O.light_sample(xf, [0.0, 0.0], 7, path, 3)
+        assert np.array_equal(x0, np.array([xf[3], xf[7], xf[11]], np.float64))
+        assert w[1] < 0 and abs(np.linalg.norm(w) - 1) < 1e-12   # emitted downwards
+
+
+def _point_light_frame(dx, blockers=(), moved=True):
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(dx)
+    return H.box_scene(blockers=blockers, moved=moved, light_moved=True, light_xf=xf, light_half=(0.0, 0.0))
+
+
+def test_point_light_visibility_ray_uses_every_triangle():
+    # the light moves +0.05 in x: segment 0 now runs from (0.55, 0.999, 0.5) to
+    # the floor photon; an object that did not move sits across it
+    occluder = [((0.53, 0.5, 0.5), 0.1)]
+    st = H.store_from_paths([_worked_path()], 3)
+    amb, ex = O.verify(_point_light_frame(0.05, occluder, moved=False), st)
+    f = O.info_fields(st.info)
+    assert (f["replace"][0], f["start"][0], f["reuse"][0]) == (1, 0, 1) and amb[0] == 0 and ex[0] == 1
+    assert abs(st.origin[0, 0] - 0.55) < 1e-7
+    # without the occluder the moved path is kept
+    st = H.store_from_paths([_worked_path()], 3)
+    amb, _ = O.verify(_point_light_frame(0.05), st)
+    assert O.info_fields(st.info)["replace"][0] == 0 and amb[0] == 0
+    # an area light that moved the same way does not test static geometry
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(0.05)
+    st = H.store_from_paths([_worked_path()], 3)
+    O.verify(H.box_scene(blockers=occluder, moved=False, light_moved=True, light_xf=xf), st)
+    assert O.info_fields(st.info)["replace"][0] == 0
+
+
 def test_light_update_normal_shift():
     x0 = np.array([0.52, 0.999, 0.47])
     x1 = np.array([0.3, 0.0, 0.8])
