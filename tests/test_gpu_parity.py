@@ -417,12 +417,29 @@ def test_energy_forward_backward(E):
 
 
 def test_batch_matches_plain(E):
-    import torch
     scs = scenes.make_batch(n_scenes=6, frames=3, path_range=(2000, 30000), tri_range=(5000, 40000))
+    _batch_vs_plain(E, scs, [False] * len(scs))
+
+
+def test_batch_mixed_modes_matches_plain(E):
+    # scenes with point lights (visibility tasks in the multi-scene traversal)
+    # and contexts on the box test, batched together with ordinary ones
+    scs = scenes.make_batch(n_scenes=2, frames=3, path_range=(2000, 20000), tri_range=(5000, 30000))
+    scs.append(scenes.make_rooms("bpoints", 2, 2, 8000, 3, (20, 10), 7000 + 3, 5, 3, 0.01, 31,
+                                 lights_move=True, point_lights=True))
+    scs.append(scenes.make_rooms("bboxes", 2, 2, 8000, 3, (20, 10), 5000 + 1, 6, 3, 0.01, 32,
+                                 lights_move=True, point_lights=True))
+    _batch_vs_plain(E, scs, [False, True, False, True])
+
+
+def _batch_vs_plain(E, scs, boxes):
+    import torch
     T, seed = 0.01, 7
     log("batch of %d scenes, %d paths" % (len(scs), sum(s.n_paths for s in scs)))
     plain = [E.Context(s) for s in scs]
     batch_ctx = [E.Context(s) for s in scs]
+    for c, bx in list(zip(plain, boxes)) + list(zip(batch_ctx, boxes)):
+        c.set_verify_mode(bx)
     sp = [c.new_store() for c in plain]
     sb = [c.new_store() for c in batch_ctx]
     for c, st in list(zip(plain, sp)) + list(zip(batch_ctx, sb)):
