@@ -115,6 +115,7 @@ struct pv_batch {
   uint64_t seed = 0;
   uint32_t retrace_blocks = 0;
   uint32_t stack_entries = 2, stack_moved = 2;  // largest of the scenes'
+  uint32_t max_bounces = 1;                      // largest B of the scenes' stores (photon rows)
   bool captured = false;
   pv_stats* captured_stats = nullptr;
   hipGraph_t graph = nullptr;
@@ -1465,7 +1466,7 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
                         b->stack_entries, ctx->walk_min_active, b->ow, st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
   CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, b->d_scan_tmp, st));
-  CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, PV_MAX_BOUNCES, b->d_poffsets,
+  CK(pv::launch_photon_scatter(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->max_bounces, b->d_poffsets,
                                b->d_out_pos, b->d_out_en, b->capacity, st));
   CK(pv::launch_scene_photon_base(b->d_scenes, (int)b->n, b->d_poffsets, b->d_ptotal, b->d_pbase, st));
   return PV_OK;
@@ -1507,6 +1508,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       for (uint32_t l = 0; l < c->n_lights; ++l) lp += c->h_light_paths[l];
       if (lp != st->n_paths) return bad("light path counts do not add up to n_paths");
       b->stack_entries = std::max(b->stack_entries, c->stack_entries);
+      b->max_bounces = std::max(b->max_bounces, st->max_bounces);
       b->stack_moved = std::max(b->stack_moved, c->stack_moved);
       SceneDev hs = c->hs;
       hs.pos = static_cast<float4*>(st->d_pos_hit);
