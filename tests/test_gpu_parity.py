@@ -292,6 +292,21 @@ def test_point_lights_lockstep(E):
     _lockstep(E, sc, 2, -1.0, "point lights, box test", boxes=True)
 
 
+def test_point_lights_edge_cases(E):
+    # fifteen bounces: a path can hold fourteen segment tasks beside its
+    # visibility task
+    sc = scenes.make_rooms("points15", 2, 2, 8000, 3, (20, 10), 3000 + 7, 15, 3, 0.01, 41,
+                           lights_move=True, point_lights=True)
+    _lockstep(E, sc, 3, -1.0, "point lights, B=15")
+    _lockstep(E, sc, 2, -1.0, "point lights, B=15, box test", boxes=True)
+    # no static triangles: the visibility walk runs over the objects' tree only
+    sc = scenes.make_objects_only(n_paths=4096 + 5, frames=3, threshold=0.01)
+    sc.light_half[:] = 0.0
+    for f in range(3):
+        sc.light_xforms[f, :, 3] += np.float32(0.004 * f)
+    _lockstep(E, sc, 3, 0.01, "objects only, point light")
+
+
 def test_object_rebuild_lockstep(E):
     # every object's hierarchy rebuilt on the device each frame (Morton codes,
     # radix sort, radix tree, bottom-up boxes) instead of refit: same results
