@@ -113,7 +113,8 @@ typedef struct {
   unsigned long long photons_written;    /* photons written by the re-trace */
   unsigned long long reuse_accepted;     /* Equation 2 acceptances (error-based walk) */
   unsigned long long paths_truncated;    /* re-traced paths ending on an escaping ray */
-  unsigned long long verify_box_hits;    /* segments reaching a moved object's box in verify */
+  unsigned long long verify_box_hits;    /* segments traversed by verify: those reaching a moved object's box
+                                            (none in the box mode), and point-light visibility segments */
 } pv_stats;
 
 /* --- context ----------------------------------------------------------- */
