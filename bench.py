@@ -193,6 +193,10 @@ def main():
     torch.cuda.synchronize()
     log("frame 0 traced")
 
+    # the photon compaction runs on the context's stream in the timed frames
+    # (clean per-phase events); a later section overlaps it with the next frame
+    cstream = None
+
     def step(f, ev, stats):
         ev[0].record()
         ctx.frame_begin(f)
@@ -203,8 +207,14 @@ def main():
         ev[3].record()
         ctx.retrace(st, T, sc.seed, f, stats)
         ev[4].record()
-        ctx.compact_photons_into(st, out_pos, out_en, out_cnt)
-        ev[5].record()
+        if cstream is None:
+            ctx.compact_photons_into(st, out_pos, out_en, out_cnt)
+            ev[5].record()
+        else:
+            # overlapped with the next frame's begin, verification and queue
+            # (the next re-trace waits for it)
+            ctx.compact_photons_into(st, out_pos, out_en, out_cnt, stream=cstream)
+            ev[5].record(cstream)
 
     tuning = None
     for f in range(1, 1 + args.warmup):
@@ -334,6 +344,25 @@ def main():
         bx["paths_invalid"].append(d["paths_invalid"])
         bx["rays_traced"].append(d["rays_traced"])
     ctx.set_verify_mode(False)
+    # the overlap form of the compaction (side stream, beside the next frame's
+    # begin, verification and queue): whole frames, wall clock
+    cstream = torch.cuda.Stream()
+    ov_frames = [1 + (8 + args.warmup + i) % max(1, sc.n_frames - 1) for i in range(11)]
+    ov_seg = 0
+    ov_stats = [ctx.new_stats() for _ in ov_frames]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    step(ov_frames[0], ev, None)  # warm-up
+    torch.cuda.synchronize()
+    t_ov = time.perf_counter()
+    for f, s in zip(ov_frames[1:], ov_stats[1:]):
+        step(f, ev, s)
+    torch.cuda.synchronize()
+    t_ov = time.perf_counter() - t_ov
+    ov_seg = sum(ctx.stats_dict(s)["segments_examined"] for s in ov_stats[1:])
+    res["overlapped_compaction"] = {"frames": len(ov_frames) - 1,
+                                    "ms_per_step": t_ov / (len(ov_frames) - 1) * 1e3,
+                                    "segments_per_s": ov_seg / t_ov}
+    cstream = None
     if not args.no_box_test:
         res["box_test_mode"] = {k + ("" if k in ("paths_invalid", "rays_traced") else "_ms"): sum(v) / len(v)
                                 for k, v in bx.items()}

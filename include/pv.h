@@ -256,6 +256,19 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
 pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
                              float* d_out_energy, uint32_t capacity, uint32_t* d_count);
 
+/* The same compaction, overlapped with the next frame: enqueued on the
+ * caller's 'hip_stream' behind everything already on the context's stream (an
+ * event), with scan scratch of its own, so that it runs beside the next
+ * frame's pv_frame_begin, pv_verify_paths and pv_build_queue (they write no
+ * photon row, no segment count and no scratch it uses).  The context's next
+ * pv_retrace_paths, pv_queue_all, compaction, autotuning, verify-mode change,
+ * store rebinding, pv_reserve or pv_upload_scene waits for it on the context's
+ * stream (an event); consumers of d_out_pos / d_out_energy / d_count order
+ * themselves after 'hip_stream'.  Same outputs and errors as
+ * pv_compact_photons. */
+pv_status pv_compact_photons_async(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
+                                   float* d_out_energy, uint32_t capacity, uint32_t* d_count, void* hip_stream);
+
 /* --- differentiation form ------------------------------------------------ */
 
 /* Deposited energy of every photon recomputed from the path's materials:

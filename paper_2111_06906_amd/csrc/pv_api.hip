@@ -74,6 +74,11 @@ struct pv_ctx {
            *d_pcounts = nullptr, *d_poffsets = nullptr, *d_gbase = nullptr,
            *d_scan_tmp = nullptr;
   float* d_partial = nullptr;
+  uint32_t* d_scan_tmp_c = nullptr;  // scan scratch of the overlapped photon compaction
+  // overlapped compaction (pv_compact_photons_async): the event its stream
+  // records when done, waited for by the next work that conflicts with it
+  hipEvent_t ev_store = nullptr, ev_compact = nullptr;
+  bool compact_pending = false;
   pv::VerifyWork vw{};  // verification task lists
   pv::OrderWork ow{};   // re-trace work order
   // tuning (pv_set_tuning / pv_autotune)
@@ -502,6 +507,16 @@ uint32_t verify_blocks(const pv_ctx* ctx) { return (uint32_t)(ctx->n_cu * ctx->v
 // the largest traversal grid any tuning can pick (sizes the statistics slots)
 uint32_t verify_blocks_max(const pv_ctx* ctx) { return (uint32_t)(ctx->n_cu * kMaxVerifyBlocksPerCu); }
 
+// Work that writes what an overlapped compaction reads (the photon rows and
+// segment counts, the scene descriptor) or reuses its scratch is ordered
+// after it on the context's stream.
+pv_status wait_compaction(pv_ctx* ctx) {
+  if (!ctx->compact_pending) return PV_OK;
+  ctx->compact_pending = false;
+  CK(hipStreamWaitEvent(ctx->stream, ctx->ev_compact, 0));
+  return PV_OK;
+}
+
 pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
   if (!ctx->reserved) return fail(ctx, PV_ERR_STATE, "pv_reserve has not been called");
@@ -517,6 +532,7 @@ pv_status bind_store(pv_ctx* ctx, const pv_path_store* st) {
   if (((uintptr_t)st->d_pos_hit | (uintptr_t)st->d_energy) & 15u)
     return fail(ctx, PV_ERR_ARG, "pos_hit / energy must be 16-byte aligned");
   if (ctx->bound && std::memcmp(&ctx->bstore, st, sizeof(*st)) == 0) return PV_OK;
+  if (pv_status w = wait_compaction(ctx)) return w;
   // light path ranges must cover the store exactly
   uint32_t total = 0;
   for (uint32_t l = 0; l < ctx->n_lights; ++l) total += ctx->h_light_paths[l];
@@ -676,6 +692,9 @@ pv_status pv_create(pv_ctx** out, void* hip_stream) {
 void pv_destroy(pv_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ev_compact) (void)hipEventSynchronize(ctx->ev_compact);
+  if (ctx->ev_store) (void)hipEventDestroy(ctx->ev_store);
+  if (ctx->ev_compact) (void)hipEventDestroy(ctx->ev_compact);
   delete ctx;
 }
 
@@ -709,6 +728,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     for (uint64_t i = 0; i < n_dyn; ++i)
       if (d->h_obj_mat[i] >= d->n_materials) return fail(ctx, PV_ERR_ARG, "object material id out of range");
 
+    if (pv_status w = wait_compaction(ctx)) return w;
     CK(hipStreamSynchronize(ctx->stream));
     ctx->scene_mem.release();
     ctx->uploaded = ctx->frame_started = ctx->bound = false;
@@ -1005,6 +1025,7 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
   if (max_paths == 0 || max_paths > kMaxPaths) return fail(ctx, PV_ERR_ARG, "max_paths out of range");
   if (max_bounces < 1 || max_bounces > PV_MAX_BOUNCES) return fail(ctx, PV_ERR_ARG, "max_bounces out of range");
   try {
+    if (pv_status w = wait_compaction(ctx)) return w;
     CK(hipStreamSynchronize(ctx->stream));
     ctx->res_mem.release();
     ctx->reserved = ctx->bound = false;
@@ -1028,6 +1049,7 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(dalloc(A, &ctx->d_gbase, 2));
     CK(dalloc(A, &ctx->d_partial, (size_t)nb * 3 * (256 + PV_MAX_LIGHTS)));
     CK(dalloc(A, &ctx->d_scan_tmp, pv::scan_tmp_words(nb * max_bounces)));
+    CK(dalloc(A, &ctx->d_scan_tmp_c, pv::scan_tmp_words(nb * max_bounces)));
     const size_t task_cap = (size_t)nb * pv::kBlock * max_bounces;  // a region of kBlock * B per tile
     CK(dalloc(A, &ctx->vw.tmp, task_cap));
     CK(dalloc(A, &ctx->vw.tasks, task_cap));
@@ -1097,6 +1119,7 @@ pv_status pv_queue_all(pv_ctx* ctx, const pv_path_store* store) {
   if (!ctx) return PV_ERR_ARG;
   pv_status st = bind_store(ctx, store);
   if (st) return st;
+  if ((st = wait_compaction(ctx))) return st;
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_mark_all(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, ctx->stream));
   CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_scan_tmp, ctx->stream));
@@ -1121,6 +1144,7 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   if (st) return st;
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
+  if ((st = wait_compaction(ctx))) return st;
   uint32_t blocks = (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu);
   CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, threshold, seed,
                         frame, nullptr, d_stats, blocks, ctx->retrace_variant, ctx->stack_entries,
@@ -1164,6 +1188,7 @@ pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode) {
     return fail(ctx, PV_ERR_ARG, "verify mode is PV_VERIFY_TRIANGLES or PV_VERIFY_BOXES");
   ctx->verify_boxes = mode == PV_VERIFY_BOXES;
   ctx->hs.verify_boxes = ctx->verify_boxes ? 1u : 0u;
+  if (pv_status w = wait_compaction(ctx)) return w;
   if (ctx->uploaded)  // stream-ordered after the work already enqueued
     CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
   return PV_OK;
@@ -1284,6 +1309,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   if (st) return st;
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
+  if ((st = wait_compaction(ctx))) return st;
   const size_t rows = (size_t)store->max_bounces * store->stride;
   const size_t b_pos = 16 * rows, b_en = 16 * rows, b_or = 12 * (size_t)store->stride, b_in = 4 * (size_t)store->stride;
   char* backup = nullptr;
@@ -1416,12 +1442,36 @@ pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_o
   pv_status st = bind_store(ctx, store);
   if (st) return st;
   if (!d_count || (capacity && (!d_out_pos || !d_out_energy))) return fail(ctx, PV_ERR_ARG, "output is NULL");
+  if ((st = wait_compaction(ctx))) return st;
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_photon_count(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_pcounts, ctx->stream));
   CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, ctx->d_scan_tmp,
                      ctx->stream));
   CK(pv::launch_photon_scatter(ctx->d_scene, ctx->d_path_tiles, nb, store->max_bounces, ctx->d_poffsets, d_out_pos,
                                d_out_energy, capacity, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_compact_photons_async(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
+                                   float* d_out_energy, uint32_t capacity, uint32_t* d_count, void* hip_stream) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!d_count || (capacity && (!d_out_pos || !d_out_energy))) return fail(ctx, PV_ERR_ARG, "output is NULL");
+  if ((st = wait_compaction(ctx))) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (!ctx->ev_store) CK(hipEventCreateWithFlags(&ctx->ev_store, hipEventDisableTiming));
+  if (!ctx->ev_compact) CK(hipEventCreateWithFlags(&ctx->ev_compact, hipEventDisableTiming));
+  // after everything enqueued on the context's stream so far
+  CK(hipEventRecord(ctx->ev_store, ctx->stream));
+  CK(hipStreamWaitEvent(s, ctx->ev_store, 0));
+  uint32_t nb = path_blocks(store->n_paths);
+  CK(pv::launch_photon_count(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_pcounts, s));
+  CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, ctx->d_scan_tmp_c, s));
+  CK(pv::launch_photon_scatter(ctx->d_scene, ctx->d_path_tiles, nb, store->max_bounces, ctx->d_poffsets, d_out_pos,
+                               d_out_energy, capacity, s));
+  CK(hipEventRecord(ctx->ev_compact, s));
+  ctx->compact_pending = true;
   return PV_OK;
 }
 
@@ -1500,6 +1550,10 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
         return fail(ctx, PV_ERR_ARG, std::string("batch scene ") + std::to_string(i) + ": " + m);
       };
       if (!c || !c->uploaded) return bad("context without a scene");
+      if (c->compact_pending) {  // an overlapped compaction still reads this store
+        if (hipEventSynchronize(c->ev_compact) != hipSuccess) return bad("overlapped compaction failed");
+        c->compact_pending = false;
+      }
       if (!st->d_pos_hit || !st->d_energy || !st->d_origin || !st->d_info) return bad("store has a NULL array");
       if (st->max_bounces < 1 || st->max_bounces > PV_MAX_BOUNCES) return bad("max_bounces out of range");
       if (st->stride < st->n_paths || st->stride % 64 != 0) return bad("bad stride");

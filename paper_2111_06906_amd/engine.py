@@ -166,9 +166,15 @@ class Context:
         n = int(cnt.item())
         return pos[:min(n, cap)], en[:min(n, cap)], n
 
-    def compact_photons_into(self, store, pos, en, cnt):
-        """Compaction into preallocated outputs; no host synchronisation."""
-        L.compact_photons(self.ctx, store.cstruct(), _ptr(pos), _ptr(en), pos.shape[0], _ptr(cnt))
+    def compact_photons_into(self, store, pos, en, cnt, stream=None):
+        """Compaction into preallocated outputs; no host synchronisation.  With
+        a torch stream, the overlap form: it runs there beside the next frame's
+        begin and verification, and the next re-trace waits for it."""
+        if stream is None:
+            L.compact_photons(self.ctx, store.cstruct(), _ptr(pos), _ptr(en), pos.shape[0], _ptr(cnt))
+        else:
+            L.compact_photons_async(self.ctx, store.cstruct(), _ptr(pos), _ptr(en), pos.shape[0], _ptr(cnt),
+                                    stream.cuda_stream)
 
     def energy_forward(self, store, albedo, power):
         E = torch.empty((store.B, store.n_paths, 3), dtype=F32, device="cuda")

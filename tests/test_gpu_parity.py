@@ -611,6 +611,45 @@ def test_autotune_restores_store_and_tuning_does_not_change_results(E):
             assert np.array_equal(r[k].view(np.uint32), results[0][k].view(np.uint32)), k
 
 
+def test_overlapped_compaction_matches_serial(E):
+    # the photon compaction on a side stream, overlapped with the next frame's
+    # begin, verification and queue: every frame's photon list and the final
+    # store equal the serial sequence's bit for bit
+    import torch
+    sc = scenes.make_mid(n_paths=60000 + 3, frames=5, threshold=0.01)
+    T, seed = 0.01, 3
+    cap = sc.n_paths * sc.max_bounces
+    runs = []
+    for overlap in (False, True):
+        ctx = E.Context(sc)
+        st = ctx.new_store()
+        ctx.frame_begin(0)
+        ctx.initial_trace(st, seed, 0)
+        side = torch.cuda.Stream() if overlap else None
+        outs = []
+        for f in range(1, 5):
+            o = (torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
+                 torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
+                 torch.zeros(1, dtype=torch.int32, device="cuda"))
+            ctx.frame_begin(f)
+            ctx.verify(st)
+            ctx.retrace(st, T, seed, f)
+            ctx.compact_photons_into(st, *o, stream=side)
+            outs.append(o)
+        torch.cuda.synchronize()
+        lists = []
+        for p, e, c in outs:
+            n = int(c.item())
+            lists.append((p[:n].cpu().numpy(), e[:n].cpu().numpy()))
+        runs.append((lists, st.to_numpy()))
+        ctx.close()
+    (l0, s0), (l1, s1) = runs
+    for f, (a, b) in enumerate(zip(l0, l1)):
+        assert a[0].shape == b[0].shape and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), f
+    for k in s0:
+        assert np.array_equal(s0[k].view(np.uint32), s1[k].view(np.uint32)), k
+
+
 def test_compaction_and_queue_properties_large(E):
     # 200k paths x 7 rows: both scans take the two-level path; the outputs are
     # checked as properties of the device store itself (a boolean-mask gather
