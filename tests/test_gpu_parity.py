@@ -307,6 +307,19 @@ def test_point_lights_edge_cases(E):
     _lockstep(E, sc, 3, 0.01, "objects only, point light")
 
 
+def test_light_extents_and_verify_mode_checked(E):
+    # a light with one zero half extent is neither a rectangle nor a point
+    from paper_2111_06906_amd import _lib as L
+    sc = scenes.make_tiny(n_paths=1024)
+    sc.light_half[0] = (0.1, 0.0)
+    with pytest.raises(RuntimeError, match="half extents"):
+        E.Context(sc)
+    sc = scenes.make_tiny(n_paths=1024)
+    ctx = E.Context(sc)
+    assert L.lib().pv_set_verify_mode(ctx.ctx, 2) == L.PV_ERR_ARG
+    ctx.close()
+
+
 def test_object_rebuild_lockstep(E):
     # every object's hierarchy rebuilt on the device each frame (Morton codes,
     # radix sort, radix tree, bottom-up boxes) instead of refit: same results
