@@ -398,9 +398,10 @@ __device__ inline Ray segment_box_ray(float3 a, float3 b, float eps) {
   Ray r;
   const float3 d = sub(b, a);
   const float tiny = 1e-30f;
-  const float dx = fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x);
-  const float dy = fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y);
-  const float dz = fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z);
+  // |d| raised to at least tiny, sign kept (the same values as a select)
+  const float dx = copysignf(fmaxf(fabsf(d.x), tiny), d.x);
+  const float dy = copysignf(fmaxf(fabsf(d.y), tiny), d.y);
+  const float dz = copysignf(fmaxf(fabsf(d.z), tiny), d.z);
   r.inv = f3(__builtin_amdgcn_rcpf(dx), __builtin_amdgcn_rcpf(dy), __builtin_amdgcn_rcpf(dz));
   r.oi = f3(-(a.x * r.inv.x), -(a.y * r.inv.y), -(a.z * r.inv.z));
   const float L2 = dot(d, d);
@@ -429,19 +430,22 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
   const PV_GLOBAL LightDev* lt = G(S.lights) + l;
   if (lt->half[0] == 0.0f && lt->half[1] == 0.0f) {
     const float3 w = sub(x1, c);
-    if (!(length(w) > S.eps_end) || !(dot(w, n) > 0.0f)) return false;
+    if (!(dot(w, w) > S.eps_end * S.eps_end) || !(dot(w, n) > 0.0f)) return false;
     *out = c;
     *vis = true;
     return true;
   }
-  n = mul(n, 1.0f / length(n));
+  // hardware reciprocal and reciprocal square root (about 1 ulp): the
+  // decisions match the FP64 update outside its 1e-6 band, the new origin
+  // within the position tolerance
+  n = mul(n, __builtin_amdgcn_rsqf(dot(n, n)));
   float3 w = sub(x1, x0);
-  float len = length(w);
-  if (!(len > 0.0f)) return false;
-  w = mul(w, 1.0f / len);
-  float dn = dot(w, n);
+  const float l2 = dot(w, w);
+  if (!(l2 > 0.0f)) return false;
+  w = mul(w, __builtin_amdgcn_rsqf(l2));
+  const float dn = dot(w, n);
   if (!(dn > 0.0f)) return false;
-  float sdist = dot(sub(x1, c), n) / dn;
+  const float sdist = dot(sub(x1, c), n) * __builtin_amdgcn_rcpf(dn);
   if (!(sdist > S.eps_end)) return false;
   float3 p = sub(x1, mul(w, sdist));
   float3 r = sub(p, c);
