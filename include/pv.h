@@ -4,7 +4,7 @@
  * Implements the per-frame hot path of Moreau, Doggett and Sintorn, "Path
  * Verification for Dynamic Indirect Illumination": photon paths stored by the
  * previous frame are verified against the current frame's dynamic geometry
- * and moving area lights, and each invalidated path is re-traced from its
+ * and moving area or point lights, and each invalidated path is re-traced from its
  * first invalid segment, optionally keeping path tails whose reflected energy
  * stays within the error threshold of Equation 2.
  *
@@ -14,8 +14,9 @@
  *    copied; the path store and outputs stay caller-owned and must remain
  *    valid until the context's stream has completed the call.
  *  - All work is enqueued on the context's stream (the one given to
- *    pv_create); no call synchronises the stream except pv_upload_scene,
- *    pv_set_light_paths and pv_reserve.
+ *    pv_create; pv_compact_photons_async also uses the caller's stream); no
+ *    call synchronises the stream except pv_upload_scene, pv_set_light_paths
+ *    and pv_reserve.
  *  - Return value: PV_OK (0) or a negative PV_ERR_* code.  Argument errors are
  *    detected on the host before anything is enqueued; pv_last_error() then
  *    describes the problem.  Faults of enqueued work surface as PV_ERR_HIP on
@@ -34,7 +35,8 @@
  *   energy  [B][stride] float4 {r, g, b, radius}: flux arriving at the photon
  *   origin  [3][stride] float: world-space light sample x_0 (x row, y row, z row)
  *   info    [stride] uint32 (Section 4 path-information word):
- *           bits 0..21 distribution-map cell, 22..25 segment count n (0..15),
+ *           bits 0..21 distribution-map cell (reserved, kept unchanged),
+ *           22..25 segment count n (0..15),
  *           26..29 first segment to re-trace, 30 replace, 31 reuse light
  *   Paths [light_base[l], light_base[l+1]) belong to light l.
  *
