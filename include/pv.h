@@ -253,8 +253,9 @@ pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode);
 pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed, uint32_t frame,
                       float* out_ms);
 
-/* Existing photons in (row, path) order: d_out_pos / d_out_energy receive
- * float[3] per photon (at most 'capacity' written), *d_count the true count. */
+/* Section 4 (the photon map a splatting renderer consumes): existing photons
+ * in (row, path) order; d_out_pos / d_out_energy receive float[3] per photon
+ * (at most 'capacity' written), *d_count the true count. */
 pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
                              float* d_out_energy, uint32_t capacity, uint32_t* d_count);
 
