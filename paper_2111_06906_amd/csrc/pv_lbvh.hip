@@ -121,17 +121,30 @@ __device__ inline void pyr_put(float4* pyr, uint32_t i, const Box& v) {
 }
 
 // union of the boxes at sorted positions [a, b) from the pyramid: at each
-// level the blocks at the range's ragged ends, then one level up
+// level the blocks at the range's ragged ends, then one level up.  The
+// entries of four levels are loaded before any of them is joined, so their
+// loads are in flight together (min and max: the order of the joins does not
+// change the box).
 __device__ inline Box range_box(const float4* pyr, uint32_t n, uint32_t a, uint32_t b) {
   Box r = empty_box();
   uint32_t off = 0, m = n;
   while (a < b) {
-    if (a & 1u) r = join(r, pyr_get(pyr, off + a++));
-    if (b & 1u) r = join(r, pyr_get(pyr, off + --b));
-    a >>= 1;
-    b >>= 1;
-    off += m;
-    m = (m + 1) / 2;
+    Box e[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool ta = a < b && (a & 1u) != 0u;
+      e[2 * k] = ta ? pyr_get(pyr, off + a) : empty_box();
+      a += ta ? 1u : 0u;
+      const bool tb = a < b && (b & 1u) != 0u;
+      e[2 * k + 1] = tb ? pyr_get(pyr, off + b - 1u) : empty_box();
+      b -= tb ? 1u : 0u;
+      a >>= 1;
+      b >>= 1;
+      off += m;
+      m = (m + 1) / 2;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r = join(r, e[k]);
   }
   return r;
 }
