@@ -140,7 +140,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only; multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs a path store on one device "
+              "(stores would shard by path range across GPUs, each with its own replica of the scene)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
