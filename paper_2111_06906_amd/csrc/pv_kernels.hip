@@ -455,6 +455,18 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
   return true;
 }
 
+// The scene bases of a multi-scene launch (gbase[0..n_scenes]) copied to LDS
+// by the whole block, so that the binary search of scene_of reads LDS (up to
+// kLdsScenes scenes; larger batches keep reading global memory).  Ends with a
+// barrier.
+constexpr int kLdsScenes = 256;
+__device__ inline const uint32_t* stage_gbase(const uint32_t* gbase, int n_scenes, uint32_t* sg) {
+  if (n_scenes > kLdsScenes) return gbase;
+  for (int i = (int)threadIdx.x; i <= n_scenes; i += (int)blockDim.x) sg[i] = gbase[i];
+  __syncthreads();
+  return sg;
+}
+
 // scene of a global path id: gbase[s] <= gp < gbase[s + 1]
 __device__ inline uint32_t scene_of(const uint32_t* gbase, int n_scenes, uint32_t gp) {
   int lo = 0, hi = n_scenes;  // gbase[s] <= gp < gbase[s+1]
@@ -723,6 +735,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
     }
     load_moved(scenes[0], M);  // ends with a barrier
   }
+  __shared__ uint32_t sgb[kSingle ? 1 : kLdsScenes + 1];
+  if (!kSingle) gbase = stage_gbase(gbase, n_scenes, sgb);
   const uint32_t total = *W.total;
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   Walk w;
@@ -803,6 +817,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_finish(const SceneDev* __rest
                                                           VerifyWork W, uint32_t* __restrict__ block_cnt,
                                                           uint32_t n_scan_blocks, pv_stats* stats) {
   __shared__ unsigned long long sred[kBlock / 64];
+  __shared__ uint32_t sgb[kSingle ? 1 : kLdsScenes + 1];
+  if (!kSingle) gbase = stage_gbase(gbase, n_scenes, sgb);
   const uint32_t total = *W.total;
   uint32_t ex = 0, inv = 0;
   // the lanes of a wave hold consecutive tasks: they stay in step and leave
@@ -1236,6 +1252,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     load_tab(scenes[0], stab);
     tab = (const PV_LDS SceneTab*)&stab;
   }
+  __shared__ uint32_t sgb[kSingle ? 1 : kLdsScenes + 1];
+  if (!kSingle) gbase = stage_gbase(gbase, n_scenes, sgb);
   // the work queue, dealt by deal() from the counters 'deal_ctr'
   const uint32_t count = *qcount;
   const uint32_t wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -1636,6 +1654,8 @@ __global__ __launch_bounds__(kBlock) void k_order_hist(const SceneDev* __restric
                                                        const uint32_t* __restrict__ qcount, uint32_t* __restrict__ hist,
                                                        uint32_t tiles) {
   __shared__ uint32_t h[kOrderBuckets];
+  __shared__ uint32_t sgb[kLdsScenes + 1];
+  if (n_scenes > 1) gbase = stage_gbase(gbase, n_scenes, sgb);  // uniform
   if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t count = *qcount, base = blockIdx.x * kOrderTile;
@@ -1660,7 +1680,9 @@ __global__ __launch_bounds__(kBlock) void k_order_scatter(const SceneDev* __rest
   static_assert(kOrderBuckets == 8, "three bucket bits");
   __shared__ uint32_t run[kOrderBuckets];
   __shared__ uint32_t wc[kWaves][kOrderBuckets];
+  __shared__ uint32_t sgb[kLdsScenes + 1];
   deal_reset(deal_ctr);  // the re-trace that follows deals from these
+  if (n_scenes > 1) gbase = stage_gbase(gbase, n_scenes, sgb);  // uniform
   const uint32_t count = *qcount, base = blockIdx.x * kOrderTile;
   if (base >= count) return;  // uniform over the block
   const uint32_t tid = threadIdx.x, w = tid >> 6;
