@@ -19,7 +19,10 @@
  *    shadow-map test by a visibility segment against every triangle;
  *  - the box mode (Section 3.2's own, conservative test) uses the exact box
  *    of each moved object's current world triangles and the same interval
- *    (eps_end, L - eps_end) of the segment;
+ *    (eps_end, L - eps_end) of the segment; the error-based walk after it
+ *    tests the first invalid segment against the moved triangles before
+ *    tracing it, unless its origin moved (Section 3.3's box-without-triangle
+ *    case);
  *  - world vertices are fp32(fma(m0,x,fma(m1,y,fma(m2,z,t)))) evaluated in FP64;
  *  - random numbers come from Philox4x64-10 keyed (seed, 0) with counter
  *    (path, frame, vertex, tag); uniforms are the top 24 bits times 2^-24;
@@ -805,8 +808,15 @@ static void retrace_path(rctx* c, int64_t p, uint32_t* amb, int* traces) {
     /* Algorithm 1 with the readings: trace iff blocked, origin moved, or end
        photon on a moved object; after an accepted re-hit that lands within
        eps_close of the old vertex, the following segment is kept without a
-       trace when it is itself clear */
-    int j = (int)k, need = 1;
+       trace when it is itself clear.  Segment k itself is known to be
+       blocked after the triangle test; after the box test (Section 3.2's
+       own) it only reached a moved object's box, and Section 3.3 casts no
+       visibility ray for a segment that the object's box crosses but none of
+       its triangles: when segment k's origin is unchanged (k > 0, or the
+       light did not move) the walk first checks it against the triangles. */
+    int l = light_of(s, p);
+    int origin_moved = k == 0 && l >= 0 && s->light_moved[l];
+    int j = (int)k, need = !(s->verify_boxes && !origin_moved);
     newn = (int)n;
     while (j < newn) {
       double xa[3], xb[3];

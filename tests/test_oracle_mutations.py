@@ -45,6 +45,34 @@ MUTATIONS = {
     "normal_not_flipped": ("    if (dot3(n, w) > 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
                            "    if (dot3(n, w) < 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
                            "energies or initial_trace or retrace"),
+    # equal-distance hits: the later triangle wins instead of the lowest id
+    "tie_rule": ("if (tt < h.t || (tt == h.t && t < h.tri)) { h.t = tt; h.tri = t; }",
+                 "if (tt <= h.t) { h.t = tt; h.tri = t; }", "tie"),
+    # closest hit forgets the moved objects (re-traced rays pass through them)
+    "closest_hit_skips_moved": ("    double tmax = h.tri >= 0 ? h.t : T_FAR;",
+                                "    if (ch->obj != 0 && s->obj_moved[ch->obj]) continue;\n"
+                                "    double tmax = h.tri >= 0 ? h.t : T_FAR;", "valid_at_new_frame"),
+    # pre-reject chunk boxes built from the first vertex of each triangle only
+    "chunk_box_one_vertex": ("      for (int v = 0; v < 3; ++v)\n        for (int k = 0; k < 3; ++k) {\n"
+                             "          double x = s->verts[9 * t + 3 * v + k];",
+                             "      for (int v = 0; v < 1; ++v)\n        for (int k = 0; k < 3; ++k) {\n"
+                             "          double x = s->verts[9 * t + 3 * v + k];", "multi_chunk"),
+    # the last triangle of every chunk skipped by the closest-hit search
+    "closest_hit_chunk_tail": ("    for (int64_t t = ch->first; t < ch->first + ch->count; ++t) {\n"
+                               "      double v[9], tt, u, vv;\n      tri_verts(s, t, v);\n      if (!mt_plane",
+                               "    for (int64_t t = ch->first; t < ch->first + ch->count - 1; ++t) {\n"
+                               "      double v[9], tt, u, vv;\n      tri_verts(s, t, v);\n      if (!mt_plane",
+                               "multi_chunk or valid_at_new_frame"),
+    # box test: the walk traces the first invalid segment even when only a box was reached
+    "box_walk_always_traces": ("int j = (int)k, need = !(s->verify_boxes && !origin_moved);",
+                               "int j = (int)k, need = 1;", "box_mode_walk"),
+    # box test: a moved light's segment 0 is checked instead of traced
+    "box_walk_ignores_moved_light": ("int origin_moved = k == 0 && l >= 0 && s->light_moved[l];",
+                                     "int origin_moved = 0;", "box_mode_walk"),
+    # a sampled bounce's photon placed along the incoming direction
+    "tail_photon_direction": ("for (int i = 0; i < 3; ++i) xn[i] = x[i] + h.t * wn[i];",
+                              "for (int i = 0; i < 3; ++i) xn[i] = x[i] + h.t * w[i];",
+                              "photons_lie or valid_at_new_frame"),
 }
 
 

@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 from paper_2111_06906_amd import scenes
+from tests import brute as B
 from tests import handscenes as H
 
 # ---------------------------------------------------------------------------
@@ -328,6 +329,69 @@ def test_box_mode_is_conservative_on_a_traced_scene():
     assert (fb["replace"][ok] > fe["replace"][ok]).sum() > 0  # the box test is looser here
 
 
+# the worked path with its first photon moved off the floor's diagonal (a ray
+# re-traced along segment 0 must not land on a shared edge)
+def _path_off_diagonal():
+    return ([0.52, 0.999, 0.47], [([0.52, 0, 0.47], 0), ([1, 0.5, 0.5], 7), ([0, 0.5, 0.25], 4)])
+
+
+# a tilted triangle whose box that path's segment 0 (x = 0.52, z = 0.47)
+# crosses for y in [0.5, 0.6], while its plane is crossed at y = 0.5625 outside
+# the triangle (barycentric u + v = 1.125)
+_TRI_NEAR_SEG0 = [[0.47, 0.5, 0.42], [0.57, 0.5, 0.42], [0.47, 0.6, 0.50]]
+
+
+def test_box_mode_walk_casts_no_ray_for_box_without_triangle():
+    # Section 3.3: no visibility ray for a segment that a dynamic object's box
+    # crosses but none of its triangles (origin unchanged, endpoints not on a
+    # moved object): after the box test the error-based walk checks the
+    # segment against the triangles, finds every segment clear and keeps the
+    # whole path, tracing nothing
+    fs = H.box_scene(tri_blockers=[_TRI_NEAR_SEG1])
+    fs.verify_boxes = 1
+    st = H.store_from_paths([_worked_path()], 3)
+    O.verify(fs, st)
+    assert O.info_fields(st.info)["start"][0] == 1 and O.info_fields(st.info)["replace"][0] == 1
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert amb[0] == 0 and tr[0] == 0
+    f = O.info_fields(st.info)
+    assert (f["replace"][0], f["nseg"][0]) == (0, 3)
+    for k in ("pos", "hit", "energy", "origin"):
+        assert np.array_equal(getattr(st, k), getattr(before, k)), k
+    # the naive method re-traces from the first invalid segment regardless
+    st = before.copy()
+    _, tr = O.retrace(fs, st, -1.0, 1, 1)
+    assert tr[0] == 2
+    # the same through segment 0 with the light still: no ray
+    fs0 = H.box_scene(tri_blockers=[_TRI_NEAR_SEG0])
+    fs0.verify_boxes = 1
+    st = H.store_from_paths([_path_off_diagonal()], 3)
+    O.verify(fs0, st)
+    assert O.info_fields(st.info)["start"][0] == 0 and O.info_fields(st.info)["reuse"][0] == 1
+    _, tr = O.retrace(fs0, st, 0.001, 1, 1)
+    assert tr[0] == 0 and O.info_fields(st.info)["replace"][0] == 0
+
+
+def test_box_mode_walk_traces_a_segment_whose_origin_moved():
+    # the light translates in its plane (the origin update keeps x_0): segment
+    # 0's origin counts as moved, so it is traced; its new hit coincides with
+    # the old photon and the rest of the path is kept (one ray)
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(0.01)
+    fs = H.box_scene(tri_blockers=[_TRI_NEAR_SEG0], light_moved=True, light_xf=xf)
+    fs.verify_boxes = 1
+    st = H.store_from_paths([_path_off_diagonal()], 3)
+    O.verify(fs, st)
+    f = O.info_fields(st.info)
+    assert (f["replace"][0], f["start"][0], f["reuse"][0]) == (1, 0, 1)
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert amb[0] == 0 and tr[0] == 1
+    assert O.info_fields(st.info)["replace"][0] == 0
+    assert np.array_equal(st.pos, before.pos) and np.array_equal(st.hit, before.hit)
+
+
 # ---------------------------------------------------------------------------
 # light origin update closed forms (Section 3.1)
 
@@ -460,6 +524,76 @@ def test_closest_hit_prefers_nearer_blocker():
     assert 10 <= tri < 22 and t == pytest.approx(0.25, abs=1e-7)
 
 
+def _torus_scene(moved=True):
+    # the open box plus one 2000-triangle torus (50 x 20 segments, the mid
+    # scene's objects) as a single object: its triangles span 63 pre-reject
+    # chunks of the oracle
+    loc = np.asarray(scenes._torus(0.2, 0.06, 50, 20), np.float64).reshape(-1, 3, 3)
+    R = scenes._rot_axis_angle([0.3, 1.0, 0.2], 0.7)
+    tor = (loc @ R.T + np.array([0.5, 0.45, 0.5])).astype(np.float32)
+    fs = H.box_scene(n_paths=1)
+    fs.verts = np.concatenate([fs.verts, tor.reshape(-1, 9)])
+    fs.tri_obj = np.concatenate([fs.tri_obj, np.ones(tor.shape[0], np.uint32)])
+    fs.tri_mat = np.concatenate([fs.tri_mat, np.ones(tor.shape[0], np.uint32)])
+    fs.obj_moved = np.array([0, 1 if moved else 0], np.uint8)
+    return fs
+
+
+def test_segment_query_on_multi_chunk_object_matches_per_triangle_loop():
+    # the chunked, pre-rejected segment test equals a plain loop of the
+    # per-triangle predicate (itself pinned by exact orientations) over every
+    # triangle of the moved torus, and the numpy brute force
+    fs = _torus_scene()
+    tor = np.flatnonzero(fs.tri_obj == 1)
+    assert tor.size == 2000
+    rng = np.random.default_rng(31)
+    c = np.array([0.5, 0.45, 0.5])
+    n_blocked = n_checked = 0
+    for _ in range(150):
+        a = c + rng.uniform(-0.35, 0.35, 3)
+        b = c + rng.uniform(-0.35, 0.35, 3)
+        got, amb = O.segment_query(fs, a, b)
+        if amb:
+            continue
+        loop = any(O.segment_blocked_tri(a, b, fs.verts[t].astype(np.float64), fs.eps_end) for t in tor)
+        assert got == loop
+        assert got == B.segment_blocked(fs.verts, a, b, fs.eps_end, tor)
+        n_checked += 1
+        n_blocked += got
+    assert n_checked > 130 and 20 < n_blocked < n_checked - 20
+
+
+def test_closest_hit_on_multi_chunk_object_matches_brute_force():
+    fs = _torus_scene()
+    rng = np.random.default_rng(32)
+    n_tor = n_checked = 0
+    for _ in range(150):
+        o = rng.uniform(0.1, 0.9, 3)
+        w = np.array([0.5, 0.45, 0.5]) + rng.uniform(-0.25, 0.25, 3) - o  # towards the torus
+        w /= np.linalg.norm(w)
+        tri, t, amb = O.closest_query(fs, o, w)
+        if amb:
+            continue
+        bt, btt = B.closest_hit(fs.verts, o, w, fs.eps_end)
+        assert tri == bt
+        if tri >= 0:
+            assert t == pytest.approx(btt, abs=1e-12)
+        n_checked += 1
+        n_tor += tri >= 10
+    assert n_checked > 130 and n_tor > 20
+
+
+def test_closest_hit_tie_takes_lowest_id():
+    # two coincident triangles (the second with the opposite winding) across
+    # the ray: equal distances, the lower id wins and the tie is flagged
+    tri = [[0.7, 0.2, 0.4], [0.7, 0.5, 0.4], [0.7, 0.3, 0.8]]
+    rev = [tri[0], tri[2], tri[1]]
+    for pair in ((tri, rev), (rev, tri)):
+        fs = H.box_scene(tri_blockers=list(pair), moved=False)
+        t_id, t, amb = O.closest_query(fs, [0.5, 0.3, 0.5], [1, 0, 0])
+        assert t_id == 10 and t == pytest.approx(float(np.float32(0.7)) - 0.5, abs=1e-15) and amb & O.AMB_TIE
+
+
 # ---------------------------------------------------------------------------
 # sampling: concentric map and tangent frame
 
@@ -578,8 +712,14 @@ def test_initial_trace_photons_lie_on_their_triangles():
         nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
         dist = np.abs(np.einsum("ij,ij->i", p - tri[:, 0], nrm))
         assert dist.max() < 1e-6
-    # consecutive photons see each other (no triangle strictly between them)
+    # paths without photons store none
     assert np.all(st.hit[:, n == 0] == O.HIT_NONE)
+    # consecutive vertices see each other: no triangle crosses a segment
+    # strictly inside it (brute force over every triangle)
+    for p in range(0, sc.n_paths, 17):
+        pts = [st.origin[p].astype(np.float64)] + [st.pos[r, p].astype(np.float64) for r in range(n[p])]
+        for j in range(n[p]):
+            assert not B.segment_blocked(fs0.verts, pts[j], pts[j + 1], fs0.eps_end), (p, j)
 
 
 # ---------------------------------------------------------------------------
@@ -606,16 +746,44 @@ def test_retrace_never_traces_more_than_full_invalidation():
         assert np.all(tr[~rep] == 0)
 
 
+def _moved_tri_ids(fs):
+    return np.flatnonzero(fs.obj_moved[fs.tri_obj] != 0)
+
+
 def test_retrace_result_is_valid_at_new_frame():
+    # frame 1 of the tiny scene (the cube moved): after the naive re-trace
+    # every photon from the first invalid segment on is the brute-force
+    # closest hit over all frame-1 triangles from the previous vertex along
+    # the segment; after either re-trace no segment of any path crosses a
+    # moved triangle (the store is valid at the new frame)
     sc, fs1, st = _frame_pair()
-    s2 = st.copy()
-    amb, _ = O.retrace(fs1, s2, -1.0, sc.seed, 1)
-    assert O.info_fields(s2.info)["replace"].sum() == 0
-    s3 = s2.copy()
-    # a second verification against the same frame (nothing moves) keeps every path
-    fs_static = O.frame_scene(sc, 1, 1)
-    O.verify(fs_static, s3)
-    assert O.info_fields(s3.info)["replace"].sum() == 0
+    f0 = O.info_fields(st.info)
+    rep = np.flatnonzero(f0["replace"])
+    assert rep.size > 100
+    moved = _moved_tri_ids(fs1)
+    assert moved.size == 12
+    for T in (-1.0, 0.01):
+        s2 = st.copy()
+        amb, _ = O.retrace(fs1, s2, T, sc.seed, 1)
+        n = O.info_fields(s2.info)["nseg"]
+        assert O.info_fields(s2.info)["replace"].sum() == 0
+        checked = 0
+        for p in range(0, st.n_paths, 7):
+            if amb[p]:
+                continue
+            pts = [s2.origin[p].astype(np.float64)] + [s2.pos[r, p].astype(np.float64) for r in range(n[p])]
+            for j in range(n[p]):
+                assert not B.segment_blocked(fs1.verts, pts[j], pts[j + 1], fs1.eps_end, moved), (T, p, j)
+            if T < 0 and f0["replace"][p]:
+                for j in range(int(f0["start"][p]), int(n[p])):
+                    d = pts[j + 1] - pts[j]
+                    w = d / np.linalg.norm(d)
+                    tri, t = B.closest_hit(fs1.verts, pts[j], w, fs1.eps_end)
+                    assert tri == s2.hit[j, p], (p, j)
+                    assert np.abs(pts[j] + t * w - pts[j + 1]).max() < 1e-6, (p, j)
+                checked += 1
+        if T < 0:
+            assert checked > 20
 
 
 def test_figure1_last_segment_only_new_hit():
