@@ -28,27 +28,163 @@ def light_moved(sc, f):
     return [not np.array_equal(a[l].view(np.uint32), b[l].view(np.uint32)) for l in range(a.shape[0])]
 
 
-def cpu_baseline(config_fn, target_s, T):
-    """The oracle (untuned) on a bounded sample of the same workload."""
+def cpu_baseline(sc, engine, torch, T, target_s):
+    """The oracle (untuned) timed on a bounded sample of the same workload:
+    sampled paths of the full-size store, frame 1, verification and re-trace
+    timed apart (median of 3 runs each).  The same sampled paths, loaded from
+    the oracle's frame-0 store into a full-size device store, are verified and
+    re-traced on the GPU too, and compared with the oracle outside its
+    decision bands (excluded paths counted)."""
     import numpy as np
     import oracle as O
-    n = 512
+    N, B = sc.n_paths, sc.max_bounces
+    rng = np.random.default_rng(17)
+    fs0 = O.frame_scene(sc, 0)
+    fs1 = O.frame_scene(sc, 1, 0)
+    n = 2048
     while True:
-        sc = config_fn(n_paths=n, frames=2)
-        fs0 = O.frame_scene(sc, 0)
-        st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
-        fs1 = O.frame_scene(sc, 1, 0)
-        t0 = time.perf_counter()
-        _, ex = O.verify(fs1, st)
-        O.retrace(fs1, st, T, sc.seed, 1)
-        dt = time.perf_counter() - t0
-        log("cpu baseline: %d paths, %.2f s" % (n, dt))
-        if dt >= target_s * 0.5 or n >= 1 << 19:
+        cols = np.unique(rng.choice(N, n, replace=False))
+        ora, amb0, _ = O.initial_trace(fs0, N, B, sc.seed, paths=cols)
+        snap = ora.select(cols)
+        tv, tr = [], []
+        for rep in range(3):
+            for k in ("pos", "hit", "energy", "radius"):
+                getattr(ora, k)[:, cols] = getattr(snap, k)
+            ora.origin[cols] = snap.origin
+            ora.info[cols] = snap.info
+            t0 = time.perf_counter()
+            ambv, ex = O.verify(fs1, ora, paths=cols)
+            t1 = time.perf_counter()
+            replaced = int(((ora.info[cols] >> 30) & 1).sum())
+            ambr, rays = O.retrace(fs1, ora, T, sc.seed, 1, paths=cols)
+            t2 = time.perf_counter()
+            tv.append(t1 - t0)
+            tr.append(t2 - t1)
+        total = sum(tv) + sum(tr)
+        log("cpu baseline: %d sampled paths, %.2f s (3 runs)" % (cols.size, total))
+        if total >= target_s * 0.4 or n >= 1 << 18:
             break
-        n = int(min(1 << 19, n * max(2.0, min(16.0, target_s / max(dt, 1e-3)))))
+        n = int(min(1 << 18, n * max(2.0, min(8.0, target_s / max(total, 1e-3)))))
+    mv, mr = sorted(tv)[1], sorted(tr)[1]
+    seg = float(ex.sum())
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": float(ex.sum()) / dt, "unit": "segments/s", "cores": cores, "kind": "oracle",
-            "sample": "%d paths of the same scene, one frame (verify + error-based re-trace), %.1f s" % (n, dt)}
+    res = {"value": seg / (mv + mr), "unit": "segments/s", "cores": cores, "kind": "oracle",
+           "sample": "%d sampled paths of the full-size store, frame 1 (verify + error-based re-trace), "
+                     "median of 3 runs, %.1f s in all" % (cols.size, total),
+           "verify_s": mv, "retrace_s": mr, "verify_segments_per_s": seg / mv,
+           "retrace_rays_per_s": float(rays.sum()) / mr, "replaced_paths": replaced}
+    # parity of the GPU on the same sampled paths, frame 1
+    ctx = engine.Context(sc)
+    st = ctx.new_store()
+    ctx.frame_begin(0)
+    ctx.initial_trace(st, sc.seed, 0)
+    st.load_numpy(dict(pos=snap.pos, hit=snap.hit, energy=snap.energy, radius=snap.radius, origin=snap.origin,
+                       info=snap.info), cols=cols)
+    ctx.frame_begin(1)
+    ctx.verify(st)
+    ctx.retrace(st, T, sc.seed, 1)
+    torch.cuda.synchronize()
+    g = st.to_numpy(cols)
+    ctx.close()
+    o = ora.select(cols)
+    ok = (amb0 == 0) & (ambv == 0) & (ambr == 0)
+    nrow = (o.info >> 22) & 15
+    rows = np.arange(B)[:, None] < nrow[None, :]
+    info_bad = int((g["info"][ok] != o.info[ok]).sum())
+    hit_bad = int(((g["hit"] != o.hit) & rows)[:, ok].sum())
+    dp = np.abs(g["pos"] - o.pos).max(-1)[rows & ok[None, :]]
+    res["parity_sample"] = {"paths": int(cols.size), "excluded": int((~ok).sum()), "compared": int(ok.sum()),
+                            "info_mismatches": info_bad, "hit_mismatches": hit_bad,
+                            "max_position_diff": float(dp.max()) if dp.size else 0.0}
+    return res
+
+
+def set_tuning(ctx, tuning):
+    if tuning:
+        ctx.set_tuning(tuning["retrace_variant"], tuning["retrace_blocks_per_cu"], tuning["walk_min_active"],
+                       tuning["verify_blocks_per_cu"], tuning["verify_min_active"])
+
+
+def headline_graph(args, engine, sc, torch, np, T, tuning):
+    """The measured workload itself in the batched form: the whole frame of
+    the one scene captured in a HIP graph and replayed, against the plain
+    per-frame calls, from identical frame-0 stores (stores compared bit for
+    bit after the timed frames)."""
+    K = args.headline_graph_frames
+    seed = sc.seed
+    runs = []
+    for graph in (False, True):
+        ctx = engine.Context(sc)
+        set_tuning(ctx, tuning)
+        st = ctx.new_store()
+        ctx.frame_begin(0)
+        ctx.initial_trace(st, seed, 0)
+        b = engine.Batch([ctx], [st], T, seed) if graph else None
+        cap = sc.n_paths * sc.max_bounces
+        o = (torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
+             torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
+             torch.zeros(1, dtype=torch.int32, device="cuda"))
+        stats = ctx.new_stats()
+
+        def frame(f, s=None):
+            if graph:
+                b.frame(f, s)
+            else:
+                ctx.frame_begin(f)
+                ctx.verify(st, s)
+                ctx.retrace(st, T, seed, f)
+                ctx.compact_photons_into(st, *o)
+
+        frame(1, stats)  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        stats.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for f in range(2, 2 + K):
+            frame(f, stats)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        seg = ctx.stats_dict(stats)["segments_examined"]
+        runs.append((dt / K * 1e3, seg / dt, st.to_numpy()))
+        if b is not None:
+            b.close()
+        ctx.close()
+    (pm, ps, sp), (bm, bs, sb) = runs
+    same = all(np.array_equal(sp[k].view(np.uint32), sb[k].view(np.uint32)) for k in sp)
+    return {"frames_timed": K, "plain_ms_per_frame": pm, "graph_ms_per_frame": bm, "plain_segments_per_s": ps,
+            "graph_segments_per_s": bs, "speedup": pm / bm, "stores_bit_identical": bool(same)}
+
+
+def cache_resident_mid(engine, scenes, torch, tuning):
+    """The mid workload (1M paths x 7 bounces, 3 moving objects): its
+    verification reads (about 130 MB) fit in the 256 MB Infinity Cache, so
+    its rate is the cache-resident one, not an HBM figure."""
+    sc = scenes.make_mid(frames=8, threshold=0.01)
+    ctx = engine.Context(sc)
+    set_tuning(ctx, tuning)
+    st = ctx.new_store()
+    ctx.frame_begin(0)
+    ctx.initial_trace(st, sc.seed, 0)
+    ms, byts = [], []
+    for f in range(1, 8):
+        s = ctx.new_stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.frame_begin(f)
+        e0.record()
+        ctx.verify(st, s, build_queue=False)
+        e1.record()
+        ctx.retrace(st, 0.01, sc.seed, f)
+        torch.cuda.synchronize()
+        if f > 2:
+            ms.append(e0.elapsed_time(e1))
+            byts.append(20 * sc.n_paths + 16 * ctx.stats_dict(s)["segments_examined"])
+    ctx.close()
+    v = sum(ms) / len(ms)
+    gbs = sum(byts) / len(byts) / (v / 1e3) / 1e9
+    return {"workload": "mid: %d paths x %d bounces, %d static + %d dynamic triangles" % (
+        sc.n_paths, sc.max_bounces, sc.n_static, sc.n_dynamic_tris()), "verify_ms": v,
+        "algorithmic_bytes_per_launch": sum(byts) / len(byts), "achieved_gbs": gbs,
+        "frac_of_hbm_peak": gbs / PEAK_HBM_GBS, "note": "cache-resident (verification set below the 256 MB MALL)"}
 
 
 def batched(args, engine, scenes, torch, np, tuning=None):
@@ -71,10 +207,8 @@ def batched(args, engine, scenes, torch, np, tuning=None):
     log("batch: %d scenes, %d paths, set up in %.1f s" % (len(scs), sum(s.n_paths for s in scs),
                                                           time.perf_counter() - t0))
     (pc, ps), (bc, bs) = sets
-    if tuning:
-        for c in pc + bc:
-            c.set_tuning(tuning["retrace_variant"], tuning["retrace_blocks_per_cu"], tuning["walk_min_active"],
-                         tuning["verify_blocks_per_cu"], tuning["verify_min_active"])
+    for c in pc + bc:
+        set_tuning(c, tuning)
     caps = [st.n_paths * st.B for st in ps]
     outs = [(torch.empty((c, 3), dtype=torch.float32, device="cuda"),
              torch.empty((c, 3), dtype=torch.float32, device="cuda"),
@@ -135,6 +269,9 @@ def main():
                     help="skip the frames with the paper's box test (counter runs of the triangle test)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (counter calibration under rocprofv3 --pmc)")
+    ap.add_argument("--no-headline-graph", action="store_true")
+    ap.add_argument("--no-cache-resident", action="store_true")
+    ap.add_argument("--headline-graph-frames", type=int, default=10)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
@@ -312,6 +449,12 @@ def main():
                       "photons_written": tot["photons_written"] / K, "reuse_accepted": tot["reuse_accepted"] / K,
                       "verify_box_hits": tot["verify_box_hits"] / K, "photons_compacted": int(out_cnt.item())},
     }
+    rt_s = phase["retrace"] / K / 1e3
+    rays = tot["rays_traced"] / K
+    res["retrace"] = {"rays_per_s": rays / rt_s, "ms": rt_s * 1e3,
+                      "algorithmic_gbs": (48.0 * rays + 4.0 * tot["paths_invalid"] / K) / rt_s / 1e9,
+                      "note": "latency-bound traversal; algorithmic bytes: 16 B origin vertex read + 32 B photon "
+                              "written per ray, 4 B information word per queued path"}
     log(json.dumps(res["phases_ms_per_frame"]))
     # the paper's comparator on the same GPU: re-trace every path every frame
     base_ms = []
@@ -389,8 +532,12 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batch:
         res["batched"] = batched(args, engine, scenes, torch, np, tuning)
+    if not args.no_headline_graph:
+        res["batched_headline"] = headline_graph(args, engine, sc, torch, np, T, tuning)
+    if not args.no_cache_resident and args.config == "paper":
+        res["cache_resident_mid"] = cache_resident_mid(engine, scenes, torch, tuning)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, T)
+        res["cpu_baseline"] = cpu_baseline(sc, engine, torch, T, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

@@ -124,6 +124,21 @@ typedef struct {
 /* Create a context on the current HIP device; all work goes to 'hip_stream'
  * (a hipStream_t; NULL = the null stream). */
 pv_status pv_create(pv_ctx** out, void* hip_stream);
+
+/* Options fixed when a context is created (pv_create_config). */
+typedef struct {
+  uint32_t max_paths;     /* > 0: scratch reserved now, as by pv_reserve(max_paths, max_bounces);
+                             0: call pv_reserve before the first store */
+  uint32_t max_bounces;   /* rows of the stores (1..PV_MAX_BOUNCES) when max_paths > 0 */
+  int32_t verify_mode;    /* PV_VERIFY_TRIANGLES or PV_VERIFY_BOXES (pv_set_verify_mode) */
+  int32_t object_rebuild; /* 0 or 1 (PV_TUNE_OBJECT_REBUILD) */
+} pv_config;
+
+/* pv_create followed by the settings of *cfg (host pointer, read during the
+ * call).  On any error no context is returned (*out = NULL) and
+ * pv_last_error(NULL) describes it; PV_ERR_ARG for an option out of range,
+ * PV_ERR_OOM when the reservation fails.  Synchronises when it reserves. */
+pv_status pv_create_config(pv_ctx** out, const pv_config* cfg, void* hip_stream);
 void pv_destroy(pv_ctx* ctx);
 /* Last error message of the context (or of the last failed pv_create when ctx
  * is NULL).  Valid until the next call on the context. */
@@ -158,6 +173,24 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces);
  * space (each coordinate the FP64 evaluation of fma(r0,x,fma(r1,y,fma(r2,z,t)))
  * rounded to FP32) and refits their hierarchies. */
 pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_light_xf);
+/* (With both arrays NULL, pv_frame_begin starts the frame with the context's
+ * staged transforms below.) */
+
+/* Section 3 (dynamic objects, dynamic lights) by id: stage new rigid
+ * transforms for some objects (lights) of the next frame.  d_obj_ids /
+ * d_light_ids: n DEVICE uint32 ids; d_m3x4: n DEVICE float[12] matrices in the
+ * layout of pv_frame_begin.  Entries whose id is not below the scene's object
+ * (light) count are skipped; of a repeated id the last entry is taken.  Ids
+ * not named keep their staged transform: the last one given by this call or
+ * by pv_frame_begin, identity before any.  n <= PV_MAX_OBJECTS
+ * (PV_MAX_LIGHTS), else PV_ERR_ARG; PV_ERR_STATE before pv_upload_scene.
+ * Stream-ordered, allocates nothing, may be captured.  The next
+ * pv_verify_paths, pv_retrace_paths, pv_autotune or pv_object_hierarchy_info
+ * first begins the frame with the staged transforms, as pv_frame_begin(ctx,
+ * NULL, NULL) would; an object or light counts as moved when its staged
+ * matrix differs bitwise from the previous frame's. */
+pv_status pv_update_transforms(pv_ctx* ctx, uint32_t n, const uint32_t* d_obj_ids, const float* d_m3x4);
+pv_status pv_update_lights(pv_ctx* ctx, uint32_t n, const uint32_t* d_light_ids, const float* d_m3x4);
 
 /* Sections 3.1 and 3.2 (update path origins, dynamic occlusions): for each
  * path of a moved light, keep the outgoing direction and move x_0 onto the
@@ -194,7 +227,9 @@ pv_status pv_copy_queue(pv_ctx* ctx, uint32_t* d_out, uint32_t capacity, uint32_
  * the albedo at each bounce, E_1 = Phi_l / N_l).  threshold >= 0: the
  * error-based walk of Algorithm 1 with Equation 2 evaluated per channel in
  * FP32 against the stored energies.  Random numbers: Philox4x64-10 keyed
- * (seed, 0), counter (path, frame, vertex, tag). */
+ * (seed, 0), counter (path, frame, vertex, tag).  When pv_verify_paths ran
+ * after the last pv_build_queue / pv_queue_all, the queue of its replaced
+ * paths is built first (as pv_build_queue would). */
 pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed,
                            uint32_t frame, pv_stats* d_stats);
 
@@ -242,8 +277,9 @@ enum { PV_VERIFY_TRIANGLES = 0, PV_VERIFY_BOXES = 1 };
 pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode);
 
 /* Autotuner: with the current frame (after pv_frame_begin) and the given
- * store, on a snapshot of the store: time verification for every traversal
- * grid (4, 8, 16, 32 workgroups per CU) and yield threshold (8, 16, 32, 48);
+ * store, on a snapshot of the store: time verification (median of three runs
+ * each) for every traversal grid (4, 8, 16, 32 workgroups per CU) and yield
+ * threshold (8, 16, 32, 48);
  * then, after verification and queue building, time the re-trace for every
  * re-trace variant and persistent grid size (4, 8, 16, 32 workgroups per CU),
  * then for yield thresholds 8..48.  Keeps the fastest settings in the
@@ -252,10 +288,20 @@ pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode);
  * time. */
 pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, uint64_t seed, uint32_t frame,
                       float* out_ms);
+/* Timings of the context's last pv_autotune (every trial is timed three
+ * times; its median decides): h_out[7] (host) receives the chosen
+ * verification setting's median ms, its spread (max - min) / median, the
+ * largest spread of any verification trial, the chosen re-trace setting's
+ * median ms, its spread, the largest spread of any re-trace trial, and the
+ * number of trials.  Zeros before the first autotuning. */
+pv_status pv_autotune_report(const pv_ctx* ctx, float* h_out);
 
 /* Section 4 (the photon map a splatting renderer consumes): existing photons
  * in (row, path) order; d_out_pos / d_out_energy receive float[3] per photon
- * (at most 'capacity' written), *d_count the true count. */
+ * (at most 'capacity' written), *d_count the true count.  The call never
+ * synchronises, so it cannot know the count when it returns: an output too
+ * small for the photons is reported only through *d_count > capacity (the
+ * first 'capacity' photons are written), never as PV_ERR_CAPACITY. */
 pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
                              float* d_out_energy, uint32_t capacity, uint32_t* d_count);
 

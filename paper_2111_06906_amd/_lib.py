@@ -45,6 +45,11 @@ STAT_FIELDS = ["segments_examined", "paths_invalid", "paths_light_lost", "rays_t
                "reuse_accepted", "paths_truncated", "verify_box_hits"]
 
 
+class Config(C.Structure):
+    _fields_ = [("max_paths", C.c_uint32), ("max_bounces", C.c_uint32), ("verify_mode", C.c_int32),
+                ("object_rebuild", C.c_int32)]
+
+
 class Stats(C.Structure):
     _fields_ = [(n, C.c_ulonglong) for n in STAT_FIELDS]
 
@@ -72,7 +77,10 @@ def lib():
         "pv_upload_scene": ([P, C.POINTER(SceneDesc)], I32),
         "pv_set_light_paths": ([P, P], I32),
         "pv_reserve": ([P, U32, U32], I32),
+        "pv_create_config": ([C.POINTER(P), C.POINTER(Config), P], I32),
         "pv_frame_begin": ([P, P, P], I32),
+        "pv_update_transforms": ([P, U32, P, P], I32),
+        "pv_update_lights": ([P, U32, P, P], I32),
         "pv_verify_paths": ([P, C.POINTER(PathStore), P], I32),
         "pv_build_queue": ([P, C.POINTER(PathStore)], I32),
         "pv_queue_all": ([P, C.POINTER(PathStore)], I32),
@@ -92,6 +100,7 @@ def lib():
         "pv_set_verify_mode": ([P, I32], I32),
         "pv_get_tuning": ([P, I32, P], I32),
         "pv_autotune": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
+        "pv_autotune_report": ([P, P], I32),
     }
     optional = {}
     sig.update({
@@ -131,6 +140,21 @@ def create(stream=None):
     ctx = C.c_void_p()
     check(lib().pv_create(C.byref(ctx), stream))
     return ctx
+
+
+def create_config(max_paths=0, max_bounces=1, verify_mode=0, object_rebuild=0, stream=None):
+    ctx = C.c_void_p()
+    cfg = Config(max_paths, max_bounces, verify_mode, object_rebuild)
+    check(lib().pv_create_config(C.byref(ctx), C.byref(cfg), stream))
+    return ctx
+
+
+def update_transforms(ctx, n, d_ids, d_m3x4):
+    return check(lib().pv_update_transforms(ctx, n, d_ids, d_m3x4), ctx)
+
+
+def update_lights(ctx, n, d_ids, d_m3x4):
+    return check(lib().pv_update_lights(ctx, n, d_ids, d_m3x4), ctx)
 
 
 def destroy(ctx):
@@ -273,3 +297,13 @@ def autotune(ctx, store, threshold, seed, frame):
     ms = C.c_float()
     check(lib().pv_autotune(ctx, C.byref(store), C.c_float(threshold), seed, frame, C.byref(ms)), ctx)
     return ms.value
+
+
+AUTOTUNE_REPORT = ["verify_ms", "verify_spread", "verify_max_spread", "retrace_ms", "retrace_spread",
+                   "retrace_max_spread", "trials"]
+
+
+def autotune_report(ctx):
+    out = (C.c_float * len(AUTOTUNE_REPORT))()
+    check(lib().pv_autotune_report(ctx, out), ctx)
+    return dict(zip(AUTOTUNE_REPORT, [float(x) for x in out]))

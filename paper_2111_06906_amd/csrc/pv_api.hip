@@ -52,6 +52,11 @@ struct pv_ctx {
   uint2* d_xf_tiles = nullptr;   // (scene << 8 | object, first triangle) for the transform kernel
   uint32_t n_xf_tiles = 0;
   const float** d_in_ptrs = nullptr;  // [2]: object / light transform inputs of the frame
+  // transforms of the next frame, written sparsely by pv_update_transforms /
+  // pv_update_lights (and densely by pv_frame_begin); a pending update begins
+  // the frame at the next call that reads the scene
+  float *d_obj_staged = nullptr, *d_light_staged = nullptr;
+  bool xf_pending = false;
   uint32_t n_materials = 0, n_lights = 0, n_objects = 0;
   std::vector<uint32_t> h_obj_tris;  // triangles per object
   uint32_t stack_entries = 2;  // traversal stack per lane: whole-scene queries
@@ -90,9 +95,11 @@ struct pv_ctx {
   int walk_min_active = 40;  // a wave's re-trace walk yields once fewer lanes are still walking
   int verify_blocks_per_cu = 8;  // persistent verification traversal workgroups per compute unit
   int verify_min_active = 16;    // yield threshold of the verification walks
+  float tune_report[7] = {0, 0, 0, 0, 0, 0, 0};  // pv_autotune_report
   // bound store
   bool bound = false;
   bool counts_ready = false;   // per-block replace counts written by verify
+  bool queue_stale = false;    // verify ran after the last queue build
   pv_path_store bstore{};
 };
 
@@ -438,8 +445,15 @@ HostBvh build_sah(const float* v9, uint32_t n) {
 inline float pad_lo(float x) { return x - (1e-6f + std::fabs(x) * 1e-6f); }
 inline float pad_hi(float x) { return x + (1e-6f + std::fabs(x) * 1e-6f); }
 
-// child boxes of every node from leaf-order world vertices (static world)
-void host_boxes(HostBvh& h, const float* v9_leaf_order) {
+// Extra padding of the object-space boxes: a world segment mapped into object
+// space in FP32 (inverse transform) is off by a few units of 2^-24 of its
+// distance from the object's origin, at most about 4e-6 for coordinates up
+// to 10 scene units; 1e-5 keeps every object-space box conservative.
+constexpr float kObjSpacePad = 1e-5f;
+
+// child boxes of every node from leaf-order vertices (static world, or an
+// object in its own space with 'extra' added to the padding)
+void host_boxes(HostBvh& h, const float* v9_leaf_order, float extra = 0.0f) {
   auto leaf_box = [&](int32_t code, float* b) {
     uint32_t f = pv::leaf_first(code), c = pv::leaf_count(code);
     for (int k = 0; k < 3; ++k) {
@@ -454,8 +468,8 @@ void host_boxes(HostBvh& h, const float* v9_leaf_order) {
           b[3 + k] = std::max(b[3 + k], x);
         }
     for (int k = 0; k < 3; ++k) {
-      b[k] = pad_lo(b[k]);
-      b[3 + k] = pad_hi(b[3 + k]);
+      b[k] = pad_lo(b[k]) - extra;
+      b[3 + k] = pad_hi(b[3 + k]) + extra;
     }
   };
   std::vector<float> nb(6 * h.nodes.size());
@@ -689,6 +703,31 @@ pv_status pv_create(pv_ctx** out, void* hip_stream) {
   return PV_OK;
 }
 
+pv_status pv_create_config(pv_ctx** out, const pv_config* cfg, void* hip_stream) {
+  if (!cfg) {
+    if (out) *out = nullptr;
+    g_create_error = "cfg is NULL";
+    return PV_ERR_ARG;
+  }
+  if (cfg->verify_mode != PV_VERIFY_TRIANGLES && cfg->verify_mode != PV_VERIFY_BOXES) {
+    if (out) *out = nullptr;
+    g_create_error = "verify_mode out of range";
+    return PV_ERR_ARG;
+  }
+  pv_status st = pv_create(out, hip_stream);
+  if (st) return st;
+  pv_ctx* ctx = *out;
+  if (!st) st = pv_set_verify_mode(ctx, cfg->verify_mode);
+  if (!st) st = pv_set_tuning(ctx, PV_TUNE_OBJECT_REBUILD, cfg->object_rebuild);
+  if (!st && cfg->max_paths) st = pv_reserve(ctx, cfg->max_paths, cfg->max_bounces);
+  if (st) {
+    g_create_error = ctx->err;
+    pv_destroy(ctx);
+    *out = nullptr;
+  }
+  return st;
+}
+
 void pv_destroy(pv_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
@@ -798,6 +837,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     std::vector<uint32_t> level_nodes, level_off;
     std::vector<uint4> dspan;          // per object node: its children's record ranges
     std::vector<uint32_t> dspan_obj;   // and its object
+    std::vector<Node> onodes;          // the objects' topologies with object-space boxes
     const uint32_t obj_node_first = (uint32_t)nodes.size();
     uint32_t tri_base = 0, gbase = S;
     for (uint32_t o = 0; o < d->n_objects; ++o) {
@@ -863,6 +903,24 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       ob.node_base = node_base;
       ob.n_nodes = (uint32_t)hb.nodes.size();
       ob.root = rebase(hb.root);
+      {
+        // the same topology with fixed object-space boxes; internal child
+        // codes count from the region's start until it is placed below
+        std::vector<float> lv9(9 * (size_t)n);
+        for (uint32_t i = 0; i < n; ++i)
+          std::memcpy(&lv9[9 * (size_t)i], v + 9 * (size_t)hb.order[i], 9 * sizeof(float));
+        HostBvh os = hb;
+        host_boxes(os, lv9.data(), kObjSpacePad);
+        const int32_t obase = (int32_t)onodes.size();
+        auto orebase = [&](int32_t c) { return c >= 0 ? c + obase : rebase(c); };
+        for (Node nd : os.nodes) {
+          nd.d.x = orebase(nd.d.x);
+          nd.d.y = orebase(nd.d.y);
+          nd.d.z = -1;
+          onodes.push_back(nd);
+        }
+        ob.oroot = orebase(hb.root);
+      }
       tri_base += n;
       gbase += n;
     }
@@ -880,6 +938,16 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       return fail(ctx, PV_ERR_CAPACITY, "too many hierarchy nodes");
     hs.top_base = (uint32_t)nodes.size();
     nodes.resize(nodes.size() + 2 * (size_t)pv::kTopNodes, Node{});
+    // the object-space copies after the top-level trees
+    hs.onode_first = (uint32_t)nodes.size();
+    for (Node nd : onodes) {
+      if (nd.d.x >= 0) nd.d.x += (int32_t)hs.onode_first;
+      if (nd.d.y >= 0) nd.d.y += (int32_t)hs.onode_first;
+      nodes.push_back(nd);
+    }
+    for (ObjDev& ob : objs)
+      if (ob.oroot >= 0) ob.oroot += (int32_t)hs.onode_first;
+    if (nodes.size() * sizeof(Node) > (size_t)UINT32_MAX) return fail(ctx, PV_ERR_CAPACITY, "too many hierarchy nodes");
     Node* d_nodes;
     Tri* d_tris;
     float* d_dlocal;
@@ -974,6 +1042,14 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     CK(upload(A, &ctx->d_xf_tiles, xt.data(), xt.size(), s));
     ctx->n_xf_tiles = (uint32_t)xt.size();
     CK(dalloc(A, &ctx->d_in_ptrs, 2));
+    // staged transforms start as identities (every object and light moves at
+    // the first frame anyway); the host copy lives until the synchronisation
+    const float id12[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+    std::vector<float> ident(12 * (size_t)std::max(std::max(d->n_objects, d->n_lights), 1u));
+    for (size_t i = 0; i < ident.size(); ++i) ident[i] = id12[i % 12];
+    CK(upload(A, &ctx->d_obj_staged, ident.data(), 12 * (size_t)std::max(d->n_objects, 1u), s));
+    CK(upload(A, &ctx->d_light_staged, ident.data(), 12 * (size_t)d->n_lights, s));
+    ctx->xf_pending = false;
     CK(hipStreamSynchronize(s));
     ctx->hs = hs;
     ctx->n_materials = d->n_materials;
@@ -1071,10 +1147,24 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
   }
 }
 
-pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_light_xf) {
-  if (!ctx) return PV_ERR_ARG;
-  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
-  if ((ctx->n_objects && !d_obj_xf) || !d_light_xf) return fail(ctx, PV_ERR_ARG, "transform array is NULL");
+namespace {
+
+// Start a frame with the given transform arrays (the staged ones when both
+// are NULL): moved flags, world triangles of the moved objects, their boxes,
+// the top-level trees.
+pv_status begin_frame(pv_ctx* ctx, const float* d_obj_xf, const float* d_light_xf) {
+  if (!d_obj_xf && !d_light_xf) {
+    d_obj_xf = ctx->d_obj_staged;
+    d_light_xf = ctx->d_light_staged;
+  } else {
+    // the staged arrays follow the dense ones, for later sparse updates
+    if (ctx->n_objects)
+      CK(hipMemcpyAsync(ctx->d_obj_staged, d_obj_xf, 48 * (size_t)ctx->n_objects, hipMemcpyDeviceToDevice,
+                        ctx->stream));
+    CK(hipMemcpyAsync(ctx->d_light_staged, d_light_xf, 48 * (size_t)ctx->n_lights, hipMemcpyDeviceToDevice,
+                      ctx->stream));
+  }
+  ctx->xf_pending = false;
   const float* in[2] = {d_obj_xf, d_light_xf};
   CK(hipMemcpyAsync(ctx->d_in_ptrs, in, sizeof(in), hipMemcpyHostToDevice, ctx->stream));
   CK(pv::launch_frame_begin(ctx->d_scene, 1, ctx->d_in_ptrs, ctx->d_in_ptrs + 1, ctx->stream));
@@ -1092,15 +1182,55 @@ pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_ligh
   return PV_OK;
 }
 
+// A sparse transform update since the last frame begins the next frame.
+pv_status commit_pending(pv_ctx* ctx) {
+  if (!ctx->xf_pending) return PV_OK;
+  return begin_frame(ctx, nullptr, nullptr);
+}
+
+pv_status update_staged(pv_ctx* ctx, float* staged, uint32_t n_rows, uint32_t max_n, uint32_t n,
+                        const uint32_t* d_ids, const float* d_m3x4, const char* what) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
+  if (n > max_n) return fail(ctx, PV_ERR_ARG, std::string("more ") + what + " updates than " + what + "s");
+  if (n && (!d_ids || !d_m3x4)) return fail(ctx, PV_ERR_ARG, "id or matrix array is NULL");
+  if (n) CK(pv::launch_scatter_xf(staged, n_rows, d_ids, d_m3x4, n, ctx->stream));
+  ctx->xf_pending = true;
+  return PV_OK;
+}
+
+}  // namespace
+
+pv_status pv_frame_begin(pv_ctx* ctx, const float* d_obj_xf, const float* d_light_xf) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
+  const bool staged = !d_obj_xf && !d_light_xf;
+  if (!staged && ((ctx->n_objects && !d_obj_xf) || !d_light_xf))
+    return fail(ctx, PV_ERR_ARG, "transform array is NULL");
+  return begin_frame(ctx, d_obj_xf, d_light_xf);
+}
+
+pv_status pv_update_transforms(pv_ctx* ctx, uint32_t n, const uint32_t* d_obj_ids, const float* d_m3x4) {
+  return update_staged(ctx, ctx ? ctx->d_obj_staged : nullptr, ctx ? ctx->n_objects : 0, PV_MAX_OBJECTS, n,
+                       d_obj_ids, d_m3x4, "object");
+}
+
+pv_status pv_update_lights(pv_ctx* ctx, uint32_t n, const uint32_t* d_light_ids, const float* d_m3x4) {
+  return update_staged(ctx, ctx ? ctx->d_light_staged : nullptr, ctx ? ctx->n_lights : 0, PV_MAX_LIGHTS, n,
+                       d_light_ids, d_m3x4, "light");
+}
+
 pv_status pv_verify_paths(pv_ctx* ctx, const pv_path_store* store, pv_stats* d_stats) {
   if (!ctx) return PV_ERR_ARG;
   pv_status st = bind_store(ctx, store);
   if (st) return st;
-  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
+  if ((st = commit_pending(ctx))) return st;
+  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "no transforms given (pv_frame_begin or pv_update_*)");
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt, d_stats,
                        ctx->stack_moved, verify_blocks(ctx), ctx->verify_min_active, ctx->d_scan_tmp, ctx->stream));
   ctx->counts_ready = true;
+  ctx->queue_stale = true;
   return PV_OK;
 }
 
@@ -1112,6 +1242,7 @@ pv_status pv_build_queue(pv_ctx* ctx, const pv_path_store* store) {
   uint32_t nb = path_blocks(store->n_paths);
   CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_scan_tmp, ctx->stream));
   CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
+  ctx->queue_stale = false;
   return PV_OK;
 }
 
@@ -1124,6 +1255,7 @@ pv_status pv_queue_all(pv_ctx* ctx, const pv_path_store* store) {
   CK(pv::launch_mark_all(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_block_cnt, ctx->stream));
   CK(pv::launch_scan(ctx->d_block_cnt, ctx->d_offsets, nb, ctx->d_qcount, ctx->d_scan_tmp, ctx->stream));
   CK(pv::launch_scatter_queue(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_offsets, ctx->d_queue, ctx->stream));
+  ctx->queue_stale = false;
   return PV_OK;
 }
 
@@ -1142,8 +1274,11 @@ pv_status pv_retrace_paths(pv_ctx* ctx, const pv_path_store* store, float thresh
   if (!ctx) return PV_ERR_ARG;
   pv_status st = bind_store(ctx, store);
   if (st) return st;
-  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
+  if ((st = commit_pending(ctx))) return st;
+  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "no transforms given (pv_frame_begin or pv_update_*)");
+  // the paths the last verification replaced, unless the queue was built since
+  if (ctx->queue_stale && (st = pv_build_queue(ctx, store))) return st;
   if ((st = wait_compaction(ctx))) return st;
   uint32_t blocks = (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu);
   CK(pv::launch_retrace(ctx->d_scene, ctx->d_gbase, 1, ctx->d_queue, ctx->d_qcount, threshold, seed,
@@ -1200,6 +1335,7 @@ pv_status pv_object_hierarchy_info(pv_ctx* ctx, uint32_t obj, uint32_t* out) {
   if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
   if (obj >= ctx->n_objects) return fail(ctx, PV_ERR_ARG, "object index out of range");
   try {
+    if (pv_status st = commit_pending(ctx)) return st;
     CK(hipStreamSynchronize(ctx->stream));
     const SceneDev& hs = ctx->hs;
     ObjDev ob;
@@ -1307,8 +1443,11 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   if (!ctx) return PV_ERR_ARG;
   pv_status st = bind_store(ctx, store);
   if (st) return st;
-  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "pv_frame_begin has not been called");
   if (std::isnan(threshold)) return fail(ctx, PV_ERR_ARG, "threshold is NaN");
+  if ((st = commit_pending(ctx))) return st;
+  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "no transforms given (pv_frame_begin or pv_update_*)");
+  // the paths the last verification replaced, unless the queue was built since
+  if (ctx->queue_stale && (st = pv_build_queue(ctx, store))) return st;
   if ((st = wait_compaction(ctx))) return st;
   const size_t rows = (size_t)store->max_bounces * store->stride;
   const size_t b_pos = 16 * rows, b_en = 16 * rows, b_or = 12 * (size_t)store->stride, b_in = 4 * (size_t)store->stride;
@@ -1332,11 +1471,23 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   if (err == hipSuccess) err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
   const uint32_t nb = path_blocks(store->n_paths);
-  // one trial: restore the store, verify + queue, time the re-trace (best of 2)
+  // every trial is timed kTuneReps times on the restored store; the median
+  // decides, and the spread (max - min) / median of each trial is recorded
+  constexpr int kTuneReps = 3;
+  float rep_ms[kTuneReps];
+  auto median_spread = [&](float* spread) {
+    float a = rep_ms[0], b = rep_ms[1], c = rep_ms[2];
+    const float lo = std::min(a, std::min(b, c)), hi = std::max(a, std::max(b, c));
+    const float med = a + b + c - lo - hi;
+    *spread = med > 0.0f ? (hi - lo) / med : 0.0f;
+    return med;
+  };
+  float rep_spread = 0.0f;
+  std::memset(ctx->tune_report, 0, sizeof(ctx->tune_report));
+  // one trial: restore the store, verify + queue, time the re-trace
   auto trial = [&](int v, int bpc, int min_active, float* ms_out) -> hipError_t {
-    float t_min = INFINITY;
     hipError_t e = hipSuccess;
-    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+    for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
       e = copy_store(false);
       if (e == hipSuccess)
         e = pv::launch_verify(ctx->d_scene, ctx->d_path_tiles, nb, ctx->d_gbase, 1, ctx->vw, ctx->d_block_cnt,
@@ -1354,9 +1505,11 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      t_min = std::min(t_min, ms);
+      rep_ms[rep] = ms;
     }
-    *ms_out = t_min;
+    *ms_out = e == hipSuccess ? median_spread(&rep_spread) : INFINITY;
+    ctx->tune_report[6] += 1.0f;
+    ctx->tune_report[5] = std::max(ctx->tune_report[5], rep_spread);
     return e;
   };
   // a later candidate (larger grid, higher occupancy target or threshold)
@@ -1374,8 +1527,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
       for (int mi = 0; mi < 4 && err == hipSuccess; ++mi) {
         ctx->verify_blocks_per_cu = vgrids[gi];
         ctx->verify_min_active = vmins[mi];
-        float t_min = INFINITY;
-        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+        for (int rep = 0; rep < kTuneReps && err == hipSuccess; ++rep) {
           err = copy_store(false);
           if (err == hipSuccess) err = hipEventRecord(e0, s);
           if (err == hipSuccess)
@@ -1386,10 +1538,16 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
           if (err == hipSuccess) err = hipEventSynchronize(e1);
           float ms = 0;
           if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-          t_min = std::min(t_min, ms);
+          rep_ms[rep] = ms;
         }
-        if (t_min < best_verify * kTuneMargin) {
-          best_verify = t_min;
+        if (err != hipSuccess) break;
+        float spread = 0.0f;
+        const float t_med = median_spread(&spread);
+        ctx->tune_report[6] += 1.0f;
+        ctx->tune_report[2] = std::max(ctx->tune_report[2], spread);
+        if (t_med < best_verify * kTuneMargin) {
+          best_verify = t_med;
+          ctx->tune_report[1] = spread;
           bv_b = vgrids[gi];
           bv_m = vmins[mi];
         }
@@ -1408,6 +1566,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
       err = trial(v, grids[gi], best_m, &ms);
       if (ms < best * kTuneMargin) {
         best = ms;
+        ctx->tune_report[4] = rep_spread;
         best_v = v;
         best_b = grids[gi];
       }
@@ -1419,6 +1578,7 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
     err = trial(best_v, best_b, mins[mi], &ms);
     if (ms < best * kTuneMargin) {
       best = ms;
+      ctx->tune_report[4] = rep_spread;
       best_m = mins[mi];
     }
   }
@@ -1432,7 +1592,15 @@ pv_status pv_autotune(pv_ctx* ctx, const pv_path_store* store, float threshold, 
   ctx->retrace_blocks_per_cu = best_b;
   ctx->walk_min_active = best_m;
   ctx->counts_ready = false;
+  ctx->tune_report[0] = best_verify;
+  ctx->tune_report[3] = best;
   if (out_ms) *out_ms = best;
+  return PV_OK;
+}
+
+pv_status pv_autotune_report(const pv_ctx* ctx, float* h_out) {
+  if (!ctx || !h_out) return PV_ERR_ARG;
+  std::memcpy(h_out, ctx->tune_report, sizeof(ctx->tune_report));
   return PV_OK;
 }
 

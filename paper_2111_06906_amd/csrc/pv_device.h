@@ -92,6 +92,8 @@ struct ObjDev {
   uint32_t n_levels;   // depth levels holding internal nodes
   int32_t sah_root;    // root of the upload-time topology (refit each frame)
   uint32_t lbvh_base;  // first node of its region for the per-frame rebuilt radix tree
+  int32_t oroot;       // root of the upload-time topology with object-space boxes
+  uint32_t pad_;
 };
 
 struct LightDev {
@@ -142,6 +144,10 @@ struct SceneDev {
   const uint4* dspan;
   const uint32_t* dspan_obj;
   uint32_t obj_node_first, n_obj_nodes;
+  // the same topologies with fixed object-space boxes (padded for the error
+  // of mapping a world segment into object space), nodes [onode_first,
+  // onode_first + n_obj_nodes); ObjDev::oroot is an object's root among them
+  uint32_t onode_first;
   // lights
   const LightDev* lights;
   float* light_xf_cur;    // [L][12]
@@ -392,8 +398,14 @@ __device__ inline void walk_start(Walk& w, int32_t root, float tmax, StackCol co
 // leaves together.  Leaves are tested in the same depth-first order as
 // without postponement and culling only uses an older (larger) closest
 // distance, so the result is the same.
+//
+// Boxes are tested with the slab parameters (binv, boi) and triangles with
+// the ray r itself: a walk through a rigid object's hierarchy in its own
+// object space passes the object-space ray's parameters for the boxes, with
+// the same parameter interval, while triangles stay in world space.
 __device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const PV_GLOBAL Tri* __restrict__ tris,
-                                const Ray& r, bool any, StackCol col, Walk& w, int min_active) {
+                                const Ray& r, float3 binv, float3 boi, bool any, StackCol col, Walk& w,
+                                int min_active) {
   int32_t cur = w.cur, leaf = w.leaf;
   // top: the stack's top entry (entry sp - 1); the far child goes one entry
   // above it.  Once the sentinel itself is taken top points one entry below
@@ -409,14 +421,14 @@ __device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const 
       const Node nd = *(const PV_GLOBAL Node*)((const PV_GLOBAL char*)nodes + ((uint32_t)cur << 6));
       // slab entry and exit of both children; the query interval enters by
       // comparisons only (min/max with it would need canonical operands)
-      float tx0 = fmaf(nd.a.x, r.inv.x, r.oi.x), tx1 = fmaf(nd.a.w, r.inv.x, r.oi.x);
-      float ty0 = fmaf(nd.a.y, r.inv.y, r.oi.y), ty1 = fmaf(nd.b.x, r.inv.y, r.oi.y);
-      float tz0 = fmaf(nd.a.z, r.inv.z, r.oi.z), tz1 = fmaf(nd.b.y, r.inv.z, r.oi.z);
+      float tx0 = fmaf(nd.a.x, binv.x, boi.x), tx1 = fmaf(nd.a.w, binv.x, boi.x);
+      float ty0 = fmaf(nd.a.y, binv.y, boi.y), ty1 = fmaf(nd.b.x, binv.y, boi.y);
+      float tz0 = fmaf(nd.a.z, binv.z, boi.z), tz1 = fmaf(nd.b.y, binv.z, boi.z);
       const float e0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
       const float x0 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
-      tx0 = fmaf(nd.b.z, r.inv.x, r.oi.x), tx1 = fmaf(nd.c.y, r.inv.x, r.oi.x);
-      ty0 = fmaf(nd.b.w, r.inv.y, r.oi.y), ty1 = fmaf(nd.c.z, r.inv.y, r.oi.y);
-      tz0 = fmaf(nd.c.x, r.inv.z, r.oi.z), tz1 = fmaf(nd.c.w, r.inv.z, r.oi.z);
+      tx0 = fmaf(nd.b.z, binv.x, boi.x), tx1 = fmaf(nd.c.y, binv.x, boi.x);
+      ty0 = fmaf(nd.b.w, binv.y, boi.y), ty1 = fmaf(nd.c.z, binv.y, boi.y);
+      tz0 = fmaf(nd.c.x, binv.z, boi.z), tz1 = fmaf(nd.c.w, binv.z, boi.z);
       const float e1 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
       const float x1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
       // the slab interval meets [tmin, tb]
@@ -474,6 +486,12 @@ __device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const 
   w.tb = tb;
   w.gid = gid;
   w.rec = rec;
+}
+
+// the same walk with world-space boxes
+__device__ inline void walk_run(const PV_GLOBAL Node* __restrict__ nodes, const PV_GLOBAL Tri* __restrict__ tris,
+                                const Ray& r, bool any, StackCol col, Walk& w, int min_active) {
+  walk_run(nodes, tris, r, r.inv, r.oi, any, col, w, min_active);
 }
 
 // ---------------------------------------------------------------------------

@@ -71,6 +71,33 @@ __global__ void k_frame_begin(SceneDev* scenes, int n_scenes, const float* const
 }
 
 // ---------------------------------------------------------------------------
+// sparse transform update (one wave, n <= 64): row ids[i] of dst takes the 12
+// floats m[i]; when an id repeats, its last entry wins; ids >= n_rows are
+// skipped
+
+__global__ __launch_bounds__(64) void k_scatter_xf(float* __restrict__ dst, uint32_t n_rows,
+                                                   const uint32_t* __restrict__ ids,
+                                                   const float* __restrict__ m, uint32_t n) {
+  __shared__ uint32_t sid[64];
+  const uint32_t i = threadIdx.x;
+  const uint32_t id = i < n ? ids[i] : 0xFFFFFFFFu;
+  sid[i] = id;
+  __syncthreads();
+  if (i >= n || id >= n_rows) return;
+  for (uint32_t j = i + 1; j < n; ++j)
+    if (sid[j] == id) return;
+  for (int c = 0; c < 12; ++c) dst[12 * (size_t)id + c] = m[12 * (size_t)i + c];
+}
+
+hipError_t launch_scatter_xf(float* dst, uint32_t n_rows, const uint32_t* ids, const float* m, uint32_t n,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (n > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scatter_xf, dim3(1), dim3(64), 0, s, dst, n_rows, ids, m, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // per moved object, one workgroup: world-space triangles (FP64 fma chain
 // rounded to FP32), then the hierarchy's boxes level by level from the
 // deepest internal nodes up (the topology, fixed for a rigid object, was
@@ -724,6 +751,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
   extern __shared__ int32_t sstack[];  // traversal stacks, launch-time size
   __shared__ MovedSet M;                // single scene: the moved objects' boxes
   __shared__ int32_t mroot[PV_MAX_OBJECTS];  // and their hierarchies' roots
+  // their upload-time topologies with object-space boxes (kRootNone: walk in
+  // world space) and the inverse of their current transforms (rows of the
+  // inverse 3x3, then the translation)
+  __shared__ int32_t moroot[PV_MAX_OBJECTS];
+  __shared__ float minv[PV_MAX_OBJECTS][12];
   const StackCol col = (StackCol)(sstack + kBlock + threadIdx.x);  // entry 0 of the column; entry -1 spare
   if (kSingle) {
     if (threadIdx.x < 64) {
@@ -731,7 +763,32 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
       const uint32_t o = threadIdx.x;
       const bool mv = o < S0.n_obj && G(S0.obj_moved)[o] != 0;
       const uint64_t mm = __ballot(mv);
-      if (mv) mroot[__popcll(mm & lanemask_lt())] = G(S0.objs)[o].root;
+      if (mv) {
+        const uint32_t i = (uint32_t)__popcll(mm & lanemask_lt());
+        const ObjDev ob = G(S0.objs)[o];
+        mroot[i] = ob.root;
+        // inverse of the 3x3 part by cofactors in FP64
+        const PV_GLOBAL float* x = G(S0.obj_xf_cur) + 12 * o;
+        const double m0 = x[0], m1 = x[1], m2 = x[2], m4 = x[4], m5 = x[5], m6 = x[6];
+        const double m8 = x[8], m9 = x[9], m10 = x[10];
+        const double c00 = m5 * m10 - m6 * m9, c01 = m2 * m9 - m1 * m10, c02 = m1 * m6 - m2 * m5;
+        const double det = m0 * c00 + m4 * c01 + m8 * c02;
+        const bool ok = fabs(det) > 1e-12 && isfinite(det);
+        const double id = ok ? 1.0 / det : 0.0;
+        minv[i][0] = (float)(c00 * id);
+        minv[i][1] = (float)(c01 * id);
+        minv[i][2] = (float)(c02 * id);
+        minv[i][3] = (float)((m6 * m8 - m4 * m10) * id);
+        minv[i][4] = (float)((m0 * m10 - m2 * m8) * id);
+        minv[i][5] = (float)((m2 * m4 - m0 * m6) * id);
+        minv[i][6] = (float)((m4 * m9 - m5 * m8) * id);
+        minv[i][7] = (float)((m1 * m8 - m0 * m9) * id);
+        minv[i][8] = (float)((m0 * m5 - m1 * m4) * id);
+        minv[i][9] = x[3];
+        minv[i][10] = x[7];
+        minv[i][11] = x[11];
+        moroot[i] = ok ? ob.oroot : kRootNone;
+      }
     }
     load_moved(scenes[0], M);  // ends with a barrier
   }
@@ -743,6 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
   w.cur = kRootNone;
   w.leaf = 0;
   Ray r;
+  float3 binv = f3(0.0f, 0.0f, 0.0f), boi = binv;  // slab parameters of the walk's boxes
   uint32_t gp = 0, j = 0;
   bool busy = false, drained = false;
   const SceneDev* S = scenes;
@@ -770,21 +828,46 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
                                     : xyz(G(S->pos)[(size_t)(j - 1) * stride + q]);
             const float3 b = xyz(G(S->pos)[(size_t)j * stride + q]);
             r = segment_ray(a, b, S->eps_end);
+            binv = r.inv;
+            boi = r.oi;
             int32_t root = G(S->top)[1];
-            if (kSingle) {
+            if (kSingle && !vis) {
               // the objects whose boxes the segment reaches, from LDS: one
               // object is walked from its own root (its box is the only one
               // of the moved-object tree the ray enters); several, through
               // the moved-object tree; none, not at all
               uint32_t nh = 0;
-              int32_t only = kRootNone;
+              int only = 0;
               for (int i = 0; i < M.n; ++i) {
                 const float4 lo = M.lo[i], hi = M.hi[i];
                 const bool h = box_entry(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, r, r.tmax) != __builtin_inff();
                 nh += h ? 1u : 0u;
-                only = h ? mroot[i] : only;
+                only = h ? i : only;
               }
-              root = nh == 0 ? kRootNone : (nh == 1 ? only : root);
+              root = nh == 0 ? kRootNone : (nh == 1 ? mroot[only] : root);
+              if (nh == 1 && moroot[only] != kRootNone) {
+                // a rigid object is walked in its own space: the segment
+                // mapped by the inverse transform (same parameter interval)
+                // meets the fixed object-space boxes, which are tighter than
+                // the world boxes of the rotated nodes; triangles are still
+                // tested in world space
+                const float* mi = minv[only];
+                const float3 ta = sub(a, f3(mi[9], mi[10], mi[11])), tb = sub(b, f3(mi[9], mi[10], mi[11]));
+                const float3 oa = f3(mi[0] * ta.x + mi[1] * ta.y + mi[2] * ta.z,
+                                     mi[3] * ta.x + mi[4] * ta.y + mi[5] * ta.z,
+                                     mi[6] * ta.x + mi[7] * ta.y + mi[8] * ta.z);
+                const float3 ob = f3(mi[0] * tb.x + mi[1] * tb.y + mi[2] * tb.z,
+                                     mi[3] * tb.x + mi[4] * tb.y + mi[5] * tb.z,
+                                     mi[6] * tb.x + mi[7] * tb.y + mi[8] * tb.z);
+                const float3 od = sub(ob, oa);
+                const float tiny = 1e-30f;
+                const float dx = copysignf(fmaxf(fabsf(od.x), tiny), od.x);
+                const float dy = copysignf(fmaxf(fabsf(od.y), tiny), od.y);
+                const float dz = copysignf(fmaxf(fabsf(od.z), tiny), od.z);
+                binv = f3(__builtin_amdgcn_rcpf(dx), __builtin_amdgcn_rcpf(dy), __builtin_amdgcn_rcpf(dz));
+                boi = f3(-(oa.x * binv.x), -(oa.y * binv.y), -(oa.z * binv.z));
+                root = moroot[only];
+              }
             }
             if (vis) root = G(S->top)[0];
             walk_start(w, root, r.tmax, col);
@@ -798,7 +881,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_trace(const SceneDev* __restr
       continue;
     }
     if (busy) {
-      walk_run(G(S->nodes), G(S->tris), r, true, col, w, min_active);
+      walk_run(G(S->nodes), G(S->tris), r, binv, boi, true, col, w, min_active);
       if (walk_done(w)) {
         if (w.gid != kHitNone) atomicMin(&W.first[gp], j);
         busy = false;
@@ -1231,7 +1314,12 @@ __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t fram
   } else {
     L.j = L.k;
     L.newn = L.n;
-    L.mode = ST_WTRACE;
+    // After the triangle test segment k is known to be blocked.  After the
+    // box test it only reached a moved object's box, and Section 3.3 casts no
+    // ray for a segment that the box crosses but no triangle: with its origin
+    // unchanged the walk first checks it against the moved triangles.
+    const bool origin_moved = L.k == 0 && G(S.light_moved)[L.l] != 0;
+    L.mode = (S.verify_boxes && !origin_moved) ? ST_WCHECK : ST_WTRACE;
   }
 }
 

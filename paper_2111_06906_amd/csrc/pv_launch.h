@@ -6,6 +6,10 @@
 
 namespace pv {
 
+// rows ids[i] of dst (n_rows rows of 12 floats) take m[i] (n <= 64; the last
+// entry of a repeated id wins, ids >= n_rows are skipped)
+hipError_t launch_scatter_xf(float* dst, uint32_t n_rows, const uint32_t* ids, const float* m, uint32_t n,
+                             hipStream_t s);
 hipError_t launch_frame_begin(SceneDev* scenes, int n_scenes, const float* const* obj_in,
                               const float* const* light_in, hipStream_t s);
 // moved objects: world triangles (xf_tiles: (scene << 8 | object, first

@@ -78,18 +78,26 @@ class Store:
 class Context:
     """One scene on the device: upload, per-frame transforms, the method's calls."""
 
-    def __init__(self, scene: Scene, max_paths=None, max_bounces=None, stream=None):
+    def __init__(self, scene: Scene, max_paths=None, max_bounces=None, stream=None, config=None):
+        """config: None, or a dict of pv_config fields other than the sizes
+        (verify_mode, object_rebuild): the context is then made by
+        pv_create_config, which also reserves the scratch."""
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device available")
         self.scene = scene
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.ctx = L.create(C.c_void_p(self.stream.cuda_stream))
+        self.max_paths = int(max_paths or scene.n_paths)
+        self.max_bounces = int(max_bounces or scene.max_bounces)
+        if config is None:
+            self.ctx = L.create(C.c_void_p(self.stream.cuda_stream))
+        else:
+            self.ctx = L.create_config(self.max_paths, self.max_bounces, int(config.get("verify_mode", 0)),
+                                       int(config.get("object_rebuild", 0)), C.c_void_p(self.stream.cuda_stream))
         self._upload(scene)
         counts = np.ascontiguousarray(scene.light_paths, np.uint32)
         L.set_light_paths(self.ctx, _np_ptr(counts))
-        self.max_paths = int(max_paths or scene.n_paths)
-        self.max_bounces = int(max_bounces or scene.max_bounces)
-        L.reserve(self.ctx, self.max_paths, self.max_bounces)
+        if config is None:
+            L.reserve(self.ctx, self.max_paths, self.max_bounces)
         self.obj_xf = torch.from_numpy(np.ascontiguousarray(scene.obj_xforms, np.float32)).cuda()
         self.light_xf = torch.from_numpy(np.ascontiguousarray(scene.light_xforms, np.float32)).cuda()
         if self.obj_xf.numel() == 0:
@@ -135,6 +143,25 @@ class Context:
     # --- the method's calls ---------------------------------------------
     def frame_begin(self, frame):
         L.frame_begin(self.ctx, _ptr(self.obj_xf[frame]), _ptr(self.light_xf[frame]))
+
+    def frame_begin_staged(self):
+        """Begin a frame with the staged transforms (pv_frame_begin(ctx, NULL, NULL))."""
+        L.frame_begin(self.ctx, None, None)
+
+    def update_transforms(self, ids, m3x4):
+        """Stage transforms of the objects 'ids' (pv_update_transforms); returns
+        the device arrays, which must live until the stream has used them."""
+        d_ids = torch.as_tensor(np.asarray(ids, np.int64).astype(np.int32), device="cuda")
+        d_m = torch.as_tensor(np.asarray(m3x4, np.float32).reshape(-1, 12), device="cuda").contiguous()
+        L.update_transforms(self.ctx, int(d_ids.numel()), _ptr(d_ids), _ptr(d_m))
+        return d_ids, d_m
+
+    def update_lights(self, ids, m3x4):
+        """Stage transforms of the lights 'ids' (pv_update_lights)."""
+        d_ids = torch.as_tensor(np.asarray(ids, np.int64).astype(np.int32), device="cuda")
+        d_m = torch.as_tensor(np.asarray(m3x4, np.float32).reshape(-1, 12), device="cuda").contiguous()
+        L.update_lights(self.ctx, int(d_ids.numel()), _ptr(d_ids), _ptr(d_m))
+        return d_ids, d_m
 
     def verify(self, store, stats=None, build_queue=True):
         L.verify_paths(self.ctx, store.cstruct(), _ptr(stats))
@@ -196,7 +223,7 @@ class Context:
                 "walk_min_active": L.get_tuning(self.ctx, L.PV_TUNE_WALK_MIN_ACTIVE),
                 "verify_blocks_per_cu": L.get_tuning(self.ctx, L.PV_TUNE_VERIFY_BLOCKS_PER_CU),
                 "verify_min_active": L.get_tuning(self.ctx, L.PV_TUNE_VERIFY_MIN_ACTIVE),
-                "retrace_ms": ms}
+                "retrace_ms": ms, "report": L.autotune_report(self.ctx)}
 
     def set_tuning(self, variant=None, blocks_per_cu=None, walk_min_active=None, verify_blocks_per_cu=None,
                    verify_min_active=None, object_rebuild=None):

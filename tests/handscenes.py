@@ -76,3 +76,34 @@ def store_from_paths(paths, B):
             e = np.float32(e * np.float32(0.7))
         st.info[p] = O.info_make(0, len(photons), 0, 0, 0)
     return st
+
+
+IDENTITY = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], np.float32)
+PARKED = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 5], np.float32)   # frame-0 place of a moved blocker
+
+
+def device_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_paths=1, light_moved=False,
+                 light_xf=LIGHT_DOWN, tri_blockers=(), light_half=(0.1, 0.1), max_bounces=3):
+    """The scene of box_scene(...) with the same arguments as a two-frame
+    Scene for the device context: frame 1 holds the blockers at their world
+    positions (identity transforms, so the world vertices are the given ones
+    bit for bit); in frame 0 a moved blocker is parked elsewhere and a moved
+    light holds LIGHT_DOWN.  O.frame_scene(scene, 1, 0) equals box_scene(...)."""
+    from paper_2111_06906_amd import scenes
+    parts = [cube_tris(center, side) for center, side in blockers]
+    parts += [np.asarray(t, np.float32).reshape(1, 3, 3) for t in tri_blockers]
+    D = len(parts)
+    xf1 = np.tile(IDENTITY, (D, 1))
+    xf0 = np.tile(PARKED if moved else IDENTITY, (D, 1))
+    lxf1 = np.asarray(light_xf, np.float32)[None]
+    lxf0 = LIGHT_DOWN[None] if light_moved else lxf1
+    if light_moved:
+        assert not np.array_equal(lxf0, lxf1), "a moved light needs a transform other than LIGHT_DOWN"
+    return scenes.Scene(
+        name="hand", static_verts=BOX.copy(), static_mat=np.zeros(10, np.uint32),
+        obj_local=parts, obj_mat=[np.ones(p.shape[0], np.uint32) for p in parts],
+        obj_xforms=np.stack([xf0, xf1]).reshape(2, D, 12).astype(np.float32),
+        albedo=np.array([[albedo_box] * 3, [albedo_blocker] * 3], np.float32),
+        light_half=np.array([light_half], np.float32), light_power=np.ones((1, 3), np.float32),
+        light_xforms=np.stack([lxf0, lxf1]).astype(np.float32),
+        light_paths=np.array([n_paths], np.int64), max_bounces=max_bounces, threshold=-1.0, seed=1)

@@ -4,16 +4,27 @@ store and the oracle's plain store, and the comparison rules.
 Tolerances (derived in the design notes):
   * verification decisions (info words, first-invalid index, queue): bit-exact,
     except paths the oracle flags within 1e-6 of a decision boundary;
-  * photon positions after re-tracing: 1e-5 scene units (FP32 rounding along
-    up to 15 traced bounces), hit ids exact, energies 1e-5 relative;
+  * photon positions after re-tracing: 1e-5 scene units plus four times the
+    first-order FP32 error bound propagated along the path, capped at 1e-4;
+    a photon whose bound exceeds the cap and whose difference lies between
+    the cap and the bound (a grazing hit) is flagged, counted and reported,
+    at most 0.5% of the compared paths; hit ids exact, energies 1e-5
+    relative;
   * paths whose traced rays pass within 1e-5 of a triangle edge, of eps_end,
-    of another surface or of eps_close are excluded and counted.
+    of another surface or of eps_close are excluded and counted (at most 5%
+    of the paths of a frame).
+
+Every comparison is recorded in REPORT (label -> list of records); the test
+session writes it as JSON (conftest.py).
 """
 import numpy as np
 
 import oracle as O
 
 POS_TOL = 1e-5
+POS_CAP = 1e-4     # largest position tolerance applied
+FLAG_FRAC = 0.005  # largest fraction of compared paths with a flagged (grazing) photon
+EXCL_FRAC = 0.05   # largest fraction of a frame's paths inside a decision band
 E_RTOL = 1e-5
 EPS_POS = 2e-7   # FP32 rounding of a computed position (coordinates within [-1, 1])
 EPS_DIR = 4e-7   # FP32 error of a sampled or normalised unit direction
@@ -49,6 +60,22 @@ def photon_tolerance(ora, verts9):
     return tol
 
 
+REPORT = {}
+
+
+def record(label, **fields):
+    """Keep one comparison's counts for the session report."""
+    REPORT.setdefault(label, []).append({k: (float(v) if isinstance(v, (float, np.floating)) else
+                                             int(v) if isinstance(v, (bool, int, np.integer, np.bool_)) else v)
+                                         for k, v in fields.items()})
+
+
+def check_excluded(excluded, total, label, frac=EXCL_FRAC):
+    """Assert and record the paths left out of an element-wise comparison."""
+    record(label + " [exclusions]", excluded=int(excluded), paths=int(total), budget=float(frac))
+    assert excluded <= frac * total, "%s: %d of %d paths inside a decision band" % (label, excluded, total)
+
+
 def to_oracle(d):
     return O.Store(pos=d["pos"].astype(np.float32).copy(), hit=d["hit"].astype(np.uint32).copy(),
                    energy=d["energy"].astype(np.float32).copy(), radius=d["radius"].astype(np.float32).copy(),
@@ -59,10 +86,13 @@ def from_oracle(st):
     return dict(pos=st.pos, hit=st.hit, energy=st.energy, radius=st.radius, origin=st.origin, info=st.info)
 
 
-def compare_stores(gpu, ora, mask, label="", verts9=None):
+def compare_stores(gpu, ora, mask, label="", verts9=None, excluded=None):
     """Element-wise comparison of the columns selected by mask (bool [N]).
 
-    Positions use the per-photon tolerance when the frame's vertices are given."""
+    Positions use the per-photon tolerance, capped at POS_CAP, when the
+    frame's vertices are given.  Returns the counts it also records: paths
+    compared, paths excluded (when given), largest position difference,
+    largest tolerance applied, photons and paths flagged as grazing."""
     idx = np.flatnonzero(mask)
     g_info, o_info = gpu["info"][idx], ora.info[idx]
     bad = np.flatnonzero(g_info != o_info)
@@ -76,10 +106,15 @@ def compare_stores(gpu, ora, mask, label="", verts9=None):
     assert not diff.any(), "%s hit ids differ at %d photons (first path %d)" % (
         label, diff.sum(), idx[np.flatnonzero(diff.any(0))[0]])
     dp = np.abs(gpu["pos"][:, idx] - ora.pos[:, idx]).max(axis=-1)
-    tol = photon_tolerance(ora, verts9)[:, idx] if verts9 is not None else np.full(dp.shape, POS_TOL)
-    over = rows & (dp > tol)
+    bound = photon_tolerance(ora, verts9)[:, idx] if verts9 is not None else np.full(dp.shape, POS_TOL)
+    tol = np.minimum(bound, POS_CAP)
+    flagged = rows & (dp > tol) & (dp <= bound)
+    over = rows & (dp > bound)
     assert not over.any(), "%s positions differ at %d photons: worst %g (tolerance %g)" % (
-        label, over.sum(), dp[over].max(), tol[over][np.argmax(dp[over])])
+        label, over.sum(), dp[over].max(), bound[over][np.argmax(dp[over])])
+    n_flag_paths = int(flagged.any(0).sum())
+    assert n_flag_paths <= FLAG_FRAC * max(idx.size, 1), "%s: %d paths with photons beyond %g" % (
+        label, n_flag_paths, POS_CAP)
     ge, oe = gpu["energy"][:, idx], ora.energy[:, idx]
     rel = np.abs(ge - oe) / np.maximum(np.abs(oe), 1e-30)
     assert (rel[rows] <= E_RTOL).all(), "%s energies differ by up to %g rel" % (label, rel[rows].max())
@@ -87,3 +122,12 @@ def compare_stores(gpu, ora, mask, label="", verts9=None):
     assert (gh[~rows] == O.HIT_NONE).all() and (oh[~rows] == O.HIT_NONE).all()
     do = np.abs(gpu["origin"][idx] - ora.origin[idx]).max() if idx.size else 0.0
     assert do <= POS_TOL, "%s origins differ by %g" % (label, do)
+    counts = dict(compared=idx.size, photons=int(rows.sum()),
+                  max_pos_diff=float(dp[rows].max()) if rows.any() else 0.0,
+                  max_tol_applied=float(tol[rows].max()) if rows.any() else 0.0,
+                  max_energy_rel=float(rel[rows].max()) if rows.any() else 0.0,
+                  flagged_photons=int(flagged.sum()), flagged_paths=n_flag_paths)
+    if excluded is not None:
+        counts["excluded"] = int(excluded)
+    record(label, **counts)
+    return counts
