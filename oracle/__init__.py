@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 HIT_NONE = 0xFFFFFFFF
-AMB_EDGE, AMB_END, AMB_LIGHT, AMB_TIE, AMB_HEMI, AMB_CLOSE, AMB_BOX = 1, 2, 4, 8, 16, 32, 64
+AMB_EDGE, AMB_END, AMB_LIGHT, AMB_TIE, AMB_HEMI, AMB_CLOSE, AMB_BOX, AMB_CELL = 1, 2, 4, 8, 16, 32, 64, 128
 
 _lib = None
 
@@ -45,7 +45,7 @@ class CScene(C.Structure):
         ("light_half", C.c_void_p), ("light_power", C.c_void_p), ("light_moved", C.c_void_p),
         ("light_base", C.c_void_p), ("eps_end", C.c_double), ("eps_close", C.c_double),
         ("band_verify", C.c_double), ("band_trace", C.c_double), ("radius", C.c_float),
-        ("verify_boxes", C.c_int32), ("band_box", C.c_double),
+        ("verify_boxes", C.c_int32), ("band_box", C.c_double), ("dm", C.c_void_p),
     ]
 
 
@@ -86,6 +86,13 @@ def _declare(L):
     L.or_energy_backward.argtypes = [P, C.c_int64, C.c_int32, P, P, P, P, P, C.c_int32, P, P]
     L.or_info_make.argtypes = [C.c_uint32] * 5
     L.or_info_make.restype = C.c_uint32
+    L.or_dm_cells.argtypes = [P, P]
+    L.or_dm_cells.restype = C.c_int64
+    L.or_dm_target.argtypes = [C.c_int64, C.c_int64, P]
+    L.or_dm_cell.argtypes = [P, P, P, P, P, C.c_double, P]
+    L.or_dm_cell.restype = C.c_int64
+    L.or_dm_sample.argtypes = [P, P, P, C.c_int64, C.c_uint64, C.c_uint64, C.c_uint64, P, P]
+    L.or_dm_update.argtypes = [P, P, C.c_uint64, C.c_uint64, P, P, P]
 
 
 def _p(a):
@@ -132,17 +139,24 @@ class FrameScene:
     radius: float = 0.01
     verify_boxes: int = 0     # 1: Section 3.2's box test instead of the triangles
     band_box: float = 1e-5    # ambiguity band of the box test (covers the kernels' box padding)
+    dm: object = None         # None, or the distribution-map grid (gu, gv, rings, sectors)
 
     def cstruct(self):
         self._keep = [_c(self.verts, np.float32), _c(self.tri_obj, np.uint32), _c(self.tri_mat, np.uint32),
                       _c(self.obj_moved, np.uint8), _c(self.albedo, np.float32), _c(self.light_xf, np.float32),
                       _c(self.light_half, np.float32), _c(self.light_power, np.float32),
-                      _c(self.light_moved, np.uint8), _c(self.light_base, np.int64)]
+                      _c(self.light_moved, np.uint8), _c(self.light_base, np.int64),
+                      None if self.dm is None else _c(self.dm, np.int32)]
         k = self._keep
         return CScene(k[0].shape[0], _p(k[0]), _p(k[1]), _p(k[2]), k[3].shape[0], _p(k[3]), _p(k[4]),
                       k[5].shape[0], _p(k[5]), _p(k[6]), _p(k[7]), _p(k[8]), _p(k[9]),
                       self.eps_end, self.eps_close, self.band_verify, self.band_trace, self.radius,
-                      int(self.verify_boxes), self.band_box)
+                      int(self.verify_boxes), self.band_box, None if k[10] is None else _p(k[10]))
+
+    def dm_offsets(self):
+        """First cell of each light in the maps of all lights, and the total."""
+        sizes = [dm_cells(self.light_half[l], self.dm) for l in range(self.light_half.shape[0])]
+        return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
 
 
 def transform(local_verts, m12):
@@ -266,11 +280,55 @@ def retrace(fs: FrameScene, store: Store, T, seed, frame, paths=None):
 
 
 def initial_trace(fs: FrameScene, n_paths, B, seed, frame=0, paths=None):
-    """Frame-0 photon paths: every path a new light sample traced to B photons."""
+    """Frame-0 photon paths: every path a new light sample traced to B photons
+    (with distribution maps, the fill first gives every path its cell)."""
     st = Store.empty(n_paths, B)
     st.info[:] = info_make(0, 0, 0, 1, 0)
+    if fs.dm is not None:
+        dm_update(fs, st, seed, frame)
     amb, tr = retrace(fs, st, -1.0, seed, frame, paths)
     return st, amb, tr
+
+
+# ---------------------------------------------------------------------------
+# distribution maps (Section 3.1)
+
+def dm_cells(half, dm):
+    return int(lib().or_dm_cells(_p(_c(half, np.float32)), _p(_c(dm, np.int32))))
+
+
+def dm_target(n_cells, n_paths):
+    out = np.zeros(n_cells, np.uint32)
+    lib().or_dm_target(n_cells, n_paths, _p(out))
+    return out
+
+
+def dm_cell(xf, half, dm, x0, w, band=1e-6):
+    """(cell or -1, ambiguity flags) of a light sample."""
+    amb = np.zeros(1, np.uint32)
+    c = lib().or_dm_cell(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), _p(_c(dm, np.int32)),
+                         _p(_c(x0, np.float64)), _p(_c(w, np.float64)), band, _p(amb))
+    return int(c), int(amb[0])
+
+
+def dm_sample(xf, half, dm, cell, seed, path, frame):
+    x0 = np.zeros(3)
+    w = np.zeros(3)
+    lib().or_dm_sample(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), _p(_c(dm, np.int32)), int(cell), seed,
+                       path, frame, _p(x0), _p(w))
+    return x0, w
+
+
+def dm_update(fs: FrameScene, store: Store, seed, frame):
+    """Compute DM_C, prune (Equation 1), fill, in place; returns (DM_C before
+    pruning, pruned per cell, ambiguity flags per path)."""
+    total = int(fs.dm_offsets()[-1])
+    dm_c = np.zeros(total, np.uint32)
+    pruned = np.zeros(total, np.uint32)
+    amb = np.zeros(store.n_paths, np.uint32)
+    lib().or_dm_update(C.byref(fs.cstruct()), C.byref(store.cstruct()), seed, frame, _p(dm_c), _p(pruned),
+                       _p(amb))
+    return dm_c, pruned, amb
 
 
 def queue(info):

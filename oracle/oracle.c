@@ -767,6 +767,204 @@ void or_light_sample(const float* xf, const float* half, uint64_t seed, uint64_t
   for (int i = 0; i < 3; ++i) w[i] = l[0] * eu[i] + l[1] * ev[i] + l[2] * n[i];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Distribution maps (Section 3.1).  The light's surface and its set of       */
+/* outgoing directions are partitioned into cells; DM_T holds the targeted     */
+/* number of paths per cell, DM_C the number of existing paths.  Reading of    */
+/* the parametrisation the paper leaves open: a rectangle's cell is a          */
+/* position cell of a gu x gv grid over its local (u, v), times a direction    */
+/* cell of the unit disk of the direction's local (x, y) components, cut into  */
+/* 'rings' rings of equal area (equal steps of x^2 + y^2) and 'sectors'       */
+/* sectors of equal angle.  Cosine-weighted emission is uniform on that disk   */
+/* (Malley's method), so every cell of a light is equally likely; a point      */
+/* light has the direction cells only.  Cell index:                            */
+/* ((iu * gv + iv) * rings + ring) * sectors + sector.                         */
+
+static const double PI_D = 3.14159265358979323846;
+
+static int dm_point(const float* half) { return half[0] == 0.0f && half[1] == 0.0f; }
+
+int64_t or_dm_cells(const float* half, const int32_t* dm) {
+  return (int64_t)(dm_point(half) ? 1 : dm[0] * dm[1]) * dm[2] * dm[3];
+}
+
+/* DM_T: the light's paths spread evenly, the first N mod C cells one more */
+static int64_t dm_target_of(int64_t n_paths, int64_t n_cells, int64_t c) {
+  return n_paths / n_cells + (c < n_paths % n_cells ? 1 : 0);
+}
+void or_dm_target(int64_t n_cells, int64_t n_paths, uint32_t* target) {
+  for (int64_t c = 0; c < n_cells; ++c) target[c] = (uint32_t)dm_target_of(n_paths, n_cells, c);
+}
+
+/* distance of x to the nearest integer */
+static double frac_dist(double x) { return fabs(x - floor(x + 0.5)); }
+
+/* The cell of a light sample (origin x0 on the light, unit direction w), or  */
+/* -1 when the parametrisation has no value for it (origin off the rectangle, */
+/* direction not on the emitting side).  Decisions within 'band' of a cell    */
+/* boundary (in scene units on the light, in disk units for the direction)    */
+/* set OR_AMB_CELL.                                                           */
+int64_t or_dm_cell(const float* xf, const float* half, const int32_t* dm, const double x0[3],
+                   const double w[3], double band, uint32_t* amb) {
+  double c[3], eu[3], ev[3], n[3];
+  light_frame(xf, c, eu, ev, n);
+  const int point = dm_point(half);
+  const int gu = point ? 1 : dm[0], gv = point ? 1 : dm[1], nr = dm[2], ns = dm[3];
+  int64_t iu = 0, iv = 0;
+  if (!point) {
+    double r[3];
+    sub3(x0, c, r);
+    const double u = dot3(r, eu), v = dot3(r, ev);
+    const double fu = (u + half[0]) / (2.0 * half[0]) * gu, fv = (v + half[1]) / (2.0 * half[1]) * gv;
+    if (!(fu >= 0.0 && fu <= gu && fv >= 0.0 && fv <= gv)) return -1;
+    if (frac_dist(fu) * (2.0 * half[0] / gu) <= band || frac_dist(fv) * (2.0 * half[1] / gv) <= band)
+      *amb |= OR_AMB_CELL;
+    iu = (int64_t)floor(fu);
+    iv = (int64_t)floor(fv);
+    if (iu > gu - 1) iu = gu - 1;
+    if (iv > gv - 1) iv = gv - 1;
+  }
+  const double x = dot3(w, eu), y = dot3(w, ev), z = dot3(w, n);
+  if (fabs(z) <= band) *amb |= OR_AMB_CELL;
+  if (!(z > 0.0)) return -1;
+  const double rho2 = x * x + y * y, rho = sqrt(rho2);
+  const double fr = rho2 * nr;
+  if (frac_dist(fr) / nr <= band) *amb |= OR_AMB_CELL;
+  int64_t ring = (int64_t)floor(fr);
+  if (ring > nr - 1) ring = nr - 1;
+  const double phi = atan2(y, x);  /* (-pi, pi] */
+  const double fs = (phi + PI_D) / (2.0 * PI_D) * ns;
+  if (rho <= band || rho * frac_dist(fs) * (2.0 * PI_D / ns) <= band) *amb |= OR_AMB_CELL;
+  int64_t sector = (int64_t)floor(fs);
+  if (sector > ns - 1) sector = ns - 1;
+  if (sector < 0) sector = 0;
+  return ((iu * gv + iv) * nr + ring) * ns + sector;
+}
+
+/* A new light sample inside cell 'cell' (Section 3.1, "Fill DM_C": sampling */
+/* restricted to the cell): position uniform in the cell's part of the        */
+/* rectangle, disk point uniform in the cell's ring and sector (uniform in     */
+/* x^2 + y^2 and in angle), lifted to the hemisphere; one Philox draw, tag 0. */
+void or_dm_sample(const float* xf, const float* half, const int32_t* dm, int64_t cell, uint64_t seed,
+                  uint64_t path, uint64_t frame, double x0[3], double w[3]) {
+  double u[4], c[3], eu[3], ev[3], n[3];
+  draw4(seed, path, frame, 0, 0, u);
+  light_frame(xf, c, eu, ev, n);
+  const int point = dm_point(half);
+  const int64_t gv = point ? 1 : dm[1], nr = dm[2], ns = dm[3];
+  const int64_t gu = point ? 1 : dm[0];
+  const int64_t sector = cell % ns, ring = (cell / ns) % nr, pc = cell / (ns * nr);
+  const int64_t iv = pc % gv, iu = pc / gv;
+  if (point) {
+    for (int i = 0; i < 3; ++i) x0[i] = c[i];
+  } else {
+    const double a = -half[0] + ((double)iu + u[0]) * (2.0 * half[0] / (double)gu);
+    const double b = -half[1] + ((double)iv + u[1]) * (2.0 * half[1] / (double)gv);
+    for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * ev[i];
+  }
+  const double rho2 = ((double)ring + u[2]) / (double)nr, rho = sqrt(rho2);
+  const double phi = -PI_D + ((double)sector + u[3]) * (2.0 * PI_D / (double)ns);
+  const double lx = rho * cos(phi), ly = rho * sin(phi), lz = sqrt(1.0 - rho2 > 0.0 ? 1.0 - rho2 : 0.0);
+  for (int i = 0; i < 3; ++i) w[i] = lx * eu[i] + ly * ev[i] + lz * n[i];
+}
+
+/* offset of light l's cells in the maps of all lights */
+static int64_t dm_offset(const or_scene* s, int l) {
+  int64_t off = 0;
+  for (int i = 0; i < l; ++i) off += or_dm_cells(s->light_half + 2 * i, s->dm);
+  return off;
+}
+
+/* The three distribution-map steps of Section 3.1 after the origin update,  */
+/* in the paper's order, on the whole store:                                  */
+/*  Compute DM_C: every path whose light sample survived the update counts in */
+/*    its cell (a moved light's sample gets its cell from its updated origin  */
+/*    and its kept direction; a path the parametrisation cannot place is      */
+/*    marked for re-sampling; otherwise the stored cell);                     */
+/*  Prune paths: in a cell with DM_C > DM_T each path is pruned with          */
+/*    probability (DM_C - DM_T) / DM_C (Equation 1), decided in FP32 against  */
+/*    one Philox uniform (vertex 0, tag 2), all decisions taken with the      */
+/*    counts before any pruning and the counts lowered afterwards (the two    */
+/*    passes of Section 4);                                                   */
+/*  Fill DM_C: the paths to re-sample (replace without reuse-light: lost by  */
+/*    the update, pruned, or all of them at the first frame), in path order,  */
+/*    are given the cells still below target: the i-th re-sampled path of a   */
+/*    light takes the cell where the running sum of the deficits              */
+/*    max(0, DM_T - DM_C) passes i.                                           */
+/* dm_c / dm_pruned (all lights' cells) receive the counts of the first step  */
+/* and the pruned paths per cell.                                             */
+void or_dm_update(const or_scene* s, or_store* st, uint64_t seed, uint64_t frame, uint32_t* dm_c,
+                  uint32_t* dm_pruned, uint32_t* amb) {
+  const int32_t* dm = s->dm;
+  const int64_t total = dm_offset(s, s->n_lights);
+  memset(dm_c, 0, sizeof(uint32_t) * total);
+  memset(dm_pruned, 0, sizeof(uint32_t) * total);
+  /* Compute DM_C */
+  for (int64_t p = 0; p < st->n_paths; ++p) {
+    const int l = light_of(s, p);
+    if (l < 0) continue;
+    uint32_t w = st->info[p];
+    if (info_replace(w) && !info_reuse(w)) continue;
+    int64_t cell = info_cell(w);
+    if (s->light_moved[l]) {
+      double x0[3], x1[3], d[3];
+      vtx(st, p, 0, x0);
+      vtx(st, p, 1, x1);
+      sub3(x1, x0, d);
+      const double len = norm3(d);
+      for (int i = 0; i < 3; ++i) d[i] /= len;
+      cell = or_dm_cell(s->light_xf + 12 * l, s->light_half + 2 * l, dm, x0, d, s->band_verify, &amb[p]);
+      if (cell < 0) {
+        st->info[p] = info_make(0, info_nseg(w), 0, 1, 0);
+        continue;
+      }
+      st->info[p] = info_make((uint32_t)cell, info_nseg(w), info_start(w), info_replace(w), info_reuse(w));
+    }
+    dm_c[dm_offset(s, l) + cell] += 1;
+  }
+  /* Prune paths (Equation 1) */
+  for (int64_t p = 0; p < st->n_paths; ++p) {
+    const int l = light_of(s, p);
+    if (l < 0) continue;
+    const uint32_t w = st->info[p];
+    if (info_replace(w) && !info_reuse(w)) continue;
+    const int64_t at = dm_offset(s, l) + info_cell(w);
+    const int64_t cells = or_dm_cells(s->light_half + 2 * l, dm);
+    const uint32_t tgt = (uint32_t)dm_target_of(s->light_base[l + 1] - s->light_base[l], cells, info_cell(w));
+    const uint32_t C = dm_c[at];
+    if (C <= tgt) continue;
+    double u[4];
+    draw4(seed, (uint64_t)p, frame, 0, 2, u);
+    const float prob = (float)(C - tgt) / (float)C;
+    if ((float)u[0] < prob) {
+      st->info[p] = info_make(info_cell(w), info_nseg(w), 0, 1, 0);
+      dm_pruned[at] += 1;
+    }
+  }
+  /* Fill DM_C */
+  for (int l = 0; l < s->n_lights; ++l) {
+    const int64_t off = dm_offset(s, l), cells = or_dm_cells(s->light_half + 2 * l, dm);
+    const int64_t Nl = s->light_base[l + 1] - s->light_base[l];
+    int64_t c = 0, run = 0, i = 0;
+    for (int64_t p = s->light_base[l]; p < s->light_base[l + 1]; ++p) {
+      const uint32_t w = st->info[p];
+      if (!(info_replace(w) && !info_reuse(w))) continue;
+      /* advance to the cell whose running deficit sum passes i */
+      while (c < cells) {
+        const int64_t tgt = dm_target_of(Nl, cells, c);
+        const int64_t have = (int64_t)dm_c[off + c] - (int64_t)dm_pruned[off + c];
+        const int64_t def = tgt > have ? tgt - have : 0;
+        if (run + def > i) break;
+        run += def;
+        ++c;
+      }
+      const int64_t cell = c < cells ? c : i % cells;
+      st->info[p] = info_make((uint32_t)cell, info_nseg(w), info_start(w), 1, 0);
+      ++i;
+    }
+  }
+}
+
 /* Section 3.3 energy test, Equation 2, per channel, inclusive, evaluated in */
 /* FP32 (the precision of the stored energies).                              */
 int or_eq2(const float en[3], const float eo[3], float T) {
@@ -790,8 +988,12 @@ static void retrace_path(rctx* c, int64_t p, uint32_t* amb, int* traces) {
   if (k == 0 && !info_reuse(w)) {
     int l = light_of(s, p);
     double x0[3], w0[3];
-    or_light_sample(s->light_xf + 12 * l, s->light_half + 2 * l, c->seed, (uint64_t)p, c->frame, x0,
-                    w0);
+    if (s->dm)
+      or_dm_sample(s->light_xf + 12 * l, s->light_half + 2 * l, s->dm, info_cell(w), c->seed, (uint64_t)p,
+                   c->frame, x0, w0);
+    else
+      or_light_sample(s->light_xf + 12 * l, s->light_half + 2 * l, c->seed, (uint64_t)p, c->frame, x0,
+                      w0);
     store3f(st->origin + 3 * p, x0);
     double x0f[3];
     vtx(st, p, 0, x0f);

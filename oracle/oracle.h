@@ -46,6 +46,8 @@ typedef struct {
   float radius;              /* radius written on new photons */
   int32_t verify_boxes;      /* 1: a segment is invalid once it reaches a moved object's box */
   double band_box;           /* ambiguity band of that box decision */
+  const int32_t* dm;         /* NULL, or the distribution-map grid {gu, gv, rings, sectors}: new
+                                light samples are drawn inside the cell of their path */
 } or_scene;
 
 typedef struct {
@@ -67,5 +69,6 @@ typedef struct {
 #define OR_AMB_HEMI 16u
 #define OR_AMB_CLOSE 32u
 #define OR_AMB_BOX 64u
+#define OR_AMB_CELL 128u
 
 #endif

@@ -73,6 +73,20 @@ MUTATIONS = {
     "tail_photon_direction": ("for (int i = 0; i < 3; ++i) xn[i] = x[i] + h.t * wn[i];",
                               "for (int i = 0; i < 3; ++i) xn[i] = x[i] + h.t * w[i];",
                               "photons_lie or valid_at_new_frame"),
+    # Equation 1 with the kept share in place of the pruned share
+    "dm_prune_share": ("const float prob = (float)(C - tgt) / (float)C;", "const float prob = (float)tgt / (float)C;",
+                       "dm_prune"),
+    # the fill spreads re-sampled paths by the targets instead of the deficits
+    "dm_fill_targets": ("const int64_t def = tgt > have ? tgt - have : 0;", "const int64_t def = tgt;",
+                        "dm_fill or dm_static"),
+    # rings of equal radius steps instead of equal area
+    "dm_ring_radius": ("const double fr = rho2 * nr;", "const double fr = rho * nr;", "dm_cell or dm_cells"),
+    # restricted sampling with the position cell's row and column swapped
+    "dm_sample_swapped": ("const int64_t iv = pc % gv, iu = pc / gv;", "const int64_t iu = pc % gv, iv = pc / gv;",
+                          "dm_restricted or dm_initial"),
+    # a moved light's paths keep their old cells
+    "dm_stale_cells": ("    if (s->light_moved[l]) {\n      double x0[3], x1[3], d[3];",
+                       "    if (0) {\n      double x0[3], x1[3], d[3];", "dm_moving"),
 }
 
 

@@ -887,3 +887,222 @@ def test_energy_gradient_matches_finite_differences():
         fd = (np.sum(g * O.energy_forward(fs0, st, alb, p1)) - np.sum(g * O.energy_forward(fs0, st, alb, p2))) / (2 * h)
         assert gp[0, c] == pytest.approx(fd, rel=1e-9)
     assert np.sum(E) > 0
+
+
+# ---------------------------------------------------------------------------
+# distribution maps (Section 3.1): the parametrisation, Equation 1's pruning,
+# the fill, the cell-restricted light sampling
+
+DM_GRID = np.array([2, 2, 4, 8], np.int32)   # 2 x 2 position cells, 4 rings, 8 sectors: 128 cells
+
+
+def test_dm_cell_closed_forms():
+    xf, half = H.LIGHT_DOWN, np.array([0.1, 0.1], np.float32)
+    # LIGHT_DOWN: local u = world x, local v = world z, normal = -y
+    c = np.array([0.5, 0.999, 0.5])
+    w = np.array([0.3, -1.0, 0.1])
+    w /= np.linalg.norm(w)
+    x0 = c + np.array([0.03, 0.0, -0.07])
+    cell, amb = O.dm_cell(xf, half, DM_GRID, x0, w)
+    # u = 0.03 -> column 1 of 2; v = -0.07 -> row 0; x^2 + y^2 = 0.1/1.1 -> ring 0 of 4;
+    # angle atan2(0.1, 0.3) = 0.3218 rad -> sector floor(8 (0.3218 + pi) / 2pi) = 4
+    assert amb == 0
+    assert cell == ((1 * 2 + 0) * 4 + 0) * 8 + 4
+    # ring and sector move with the direction: x^2 + y^2 = 0.6 -> ring 2; angle
+    # -pi/2 + 0.2 -> sector floor(8 (pi/2 + 0.2) / 2pi) = 2
+    a = -np.pi / 2 + 0.2
+    w2 = np.array([np.sqrt(0.6) * np.cos(a), -np.sqrt(0.4), np.sqrt(0.6) * np.sin(a)])
+    cell2, amb2 = O.dm_cell(xf, half, DM_GRID, x0, w2)
+    assert amb2 == 0 and cell2 == ((1 * 2 + 0) * 4 + 2) * 8 + 2
+    # no value on the back side of the light or off the rectangle
+    assert O.dm_cell(xf, half, DM_GRID, x0, -w)[0] == -1
+    assert O.dm_cell(xf, half, DM_GRID, c + np.array([0.2, 0, 0]), w)[0] == -1
+    # a point light has the direction cells only (32 of them)
+    assert O.dm_cells(np.zeros(2, np.float32), DM_GRID) == 32
+    cp, _ = O.dm_cell(xf, np.zeros(2, np.float32), DM_GRID, c, w)
+    assert cp == 0 * 8 + 4
+    # a direction on a sector boundary is flagged
+    _, amb3 = O.dm_cell(xf, half, DM_GRID, x0, np.array([0.3, -1.0, 0.0]) / np.sqrt(1.09))
+    assert amb3 & O.AMB_CELL
+
+
+def test_dm_cells_are_equally_likely_under_cosine_emission():
+    # unrestricted light samples (position uniform on the rectangle, direction
+    # cosine-weighted) land in every cell with the same probability: the cell
+    # histogram of 64k samples passes a chi-square test against uniform
+    xf, half = H.LIGHT_DOWN, np.array([0.1, 0.1], np.float32)
+    n, cells = 65536, 128
+    counts = np.zeros(cells)
+    for p in range(n):
+        x0, w = O.light_sample(xf, half, 3, p, 0)
+        c, _ = O.dm_cell(xf, half, DM_GRID, x0, w)
+        counts[c] += 1
+    e = n / cells
+    chi2 = ((counts - e) ** 2 / e).sum()
+    # 127 degrees of freedom: mean 127, sd 15.9; the bound is about 6 sd
+    assert chi2 < 127 + 6 * 15.9, chi2
+    assert counts.min() > 0
+
+
+def test_dm_restricted_sample_maps_back_to_its_cell():
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(0.013)
+    for half in (np.array([0.1, 0.05], np.float32), np.zeros(2, np.float32)):
+        n_cells = O.dm_cells(half, DM_GRID)
+        checked = 0
+        for cell in range(n_cells):
+            for path in range(6):
+                x0, w = O.dm_sample(xf, half, DM_GRID, cell, 9, path * 131 + cell, 2)
+                assert abs(np.linalg.norm(w) - 1.0) < 1e-12
+                c, amb = O.dm_cell(xf, half, DM_GRID, x0, w)
+                if amb == 0:
+                    assert c == cell, (cell, path, c)
+                    checked += 1
+        assert checked > 0.95 * n_cells * 6
+
+
+def _dm_scene(n_paths, light_moved=False, xf=None):
+    fs = H.box_scene(n_paths=n_paths, light_moved=light_moved,
+                     light_xf=H.LIGHT_DOWN if xf is None else xf)
+    fs.dm = DM_GRID
+    return fs
+
+
+def _store_with_cells(cells, B=2):
+    """One path per entry, each with one photon on the floor below the light
+    and the given cell, reuse kept (a valid path of a light that did not move)."""
+    N = len(cells)
+    st = O.Store.empty(N, B)
+    st.pos[0, :] = [0.5, 0.0, 0.5]
+    st.hit[0, :] = 0
+    st.energy[0, :] = 1.0 / N
+    st.origin[:] = [0.5, 0.999, 0.5]
+    st.info[:] = [O.info_make(int(c), 1, 0, 0, 0) for c in cells]
+    return st
+
+
+def test_dm_prune_expectation_of_equation_1():
+    # N = 1536 paths over 128 cells (target 12 each): cells 0..31 hold three
+    # times their target (36 paths), cells 32..127 four paths each.  Equation 1
+    # prunes each path of an over-full cell with probability (36 - 12) / 36 =
+    # 2/3: the pruned count per cell is Binomial(36, 2/3), so over 32 cells it
+    # is 768 +- 5 sd (sd = 16); nothing is pruned elsewhere, and the pruned
+    # paths are marked for re-sampling
+    cells = np.concatenate([np.repeat(np.arange(32), 36), np.repeat(np.arange(32, 128), 4)])
+    st = _store_with_cells(cells)
+    fs = _dm_scene(1536)
+    tgt = O.dm_target(128, 1536)
+    assert (tgt == 12).all()
+    dm_c, pruned, amb = O.dm_update(fs, st, 5, 1)
+    assert (dm_c[:32] == 36).all() and (dm_c[32:] == 4).all()
+    assert (pruned[32:] == 0).all()
+    assert abs(int(pruned.sum()) - 768) <= 5 * 16
+    f = O.info_fields(st.info)
+    res = (f["replace"] == 1) & (f["reuse"] == 0)
+    assert res.sum() == pruned.sum()
+    # a cell at its target loses nothing
+    st2 = _store_with_cells(np.repeat(np.arange(128), 12))
+    _, pruned2, _ = O.dm_update(fs, st2, 5, 1)
+    assert pruned2.sum() == 0
+
+
+def test_dm_fill_by_brute_force():
+    # the re-sampled paths, in path order, fill the cells below target from the
+    # first cell on: expanding every cell's deficit into a list gives each
+    # re-sampled path's cell
+    rng = np.random.default_rng(3)
+    N = 1024
+    cells = rng.integers(0, 128, N)
+    st = _store_with_cells(cells)
+    lost = rng.random(N) < 0.2
+    for p in np.flatnonzero(lost):
+        st.info[p] = O.info_make(0, 1, 0, 1, 0)
+    fs = _dm_scene(N)
+    before = st.copy()
+    dm_c, pruned, _ = O.dm_update(fs, st, 11, 4)
+    kept = ~lost
+    have = np.bincount(cells[kept], minlength=128)
+    assert np.array_equal(dm_c, have)
+    tgt = O.dm_target(128, N)
+    left = have - pruned
+    slots = [c for c in range(128) for _ in range(max(0, int(tgt[c]) - int(left[c])))]
+    f0 = O.info_fields(before.info)
+    f = O.info_fields(st.info)
+    res = np.flatnonzero((f["replace"] == 1) & (f["reuse"] == 0))
+    assert res.size <= len(slots)
+    for i, p in enumerate(res):
+        assert f["cell"][p] == slots[i], (i, p)
+    # paths that stay keep their cell; conservation: kept + re-sampled = N
+    stay = np.flatnonzero(~((f["replace"] == 1) & (f["reuse"] == 0)))
+    assert np.array_equal(f["cell"][stay], f0["cell"][stay])
+    assert stay.size + res.size == N
+
+
+def test_dm_static_light_reaches_its_target():
+    # frame 0: every path is re-sampled, so the fill gives each cell exactly
+    # its target; a later frame with nothing moving counts DM_C = DM_T and
+    # neither prunes nor re-samples anything
+    sc = scenes.make_tiny(n_paths=4096)
+    fs0 = O.frame_scene(sc, 0)
+    fs0.dm = DM_GRID
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    tgt = O.dm_target(128, 4096)
+    assert np.array_equal(np.bincount(O.info_fields(st.info)["cell"], minlength=128), tgt)
+    fs1 = O.frame_scene(sc, 0, 0)
+    fs1.dm = DM_GRID
+    st2 = st.copy()
+    O.verify(fs1, st2)
+    dm_c, pruned, amb = O.dm_update(fs1, st2, sc.seed, 1)
+    assert np.array_equal(dm_c, tgt) and pruned.sum() == 0
+    assert np.array_equal(st2.info, st.info)
+
+
+def test_dm_initial_samples_lie_in_their_cells():
+    # the re-trace samples each new path inside its cell: the cell of the
+    # stored origin and first segment direction is the path's cell
+    sc = scenes.make_tiny(n_paths=2048)
+    fs0 = O.frame_scene(sc, 0)
+    fs0.dm = DM_GRID
+    st, _, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    f = O.info_fields(st.info)
+    checked = 0
+    for p in range(0, sc.n_paths, 3):
+        if f["nseg"][p] == 0:
+            continue
+        x0 = st.origin[p].astype(np.float64)
+        d = st.pos[0, p].astype(np.float64) - x0
+        c, amb = O.dm_cell(sc.light_xforms[0, 0], sc.light_half[0], DM_GRID, x0, d / np.linalg.norm(d), band=1e-5)
+        if amb == 0:
+            assert c == f["cell"][p], p
+            checked += 1
+    assert checked > 500
+
+
+def test_dm_moving_light_converges_and_conserves():
+    # a light sliding along its plane keeps its directions; positions drift
+    # across cells.  Every frame: the kept paths plus the re-sampled ones are
+    # N, and the distance to the target after the fill shrinks from the
+    # counted DM_C
+    xf = H.LIGHT_DOWN.copy()
+    N = 4096
+    fs = _dm_scene(N)
+    st, _, _ = O.initial_trace(fs, N, 2, 7)
+    tgt = O.dm_target(128, N)
+    for f in range(1, 4):
+        xf[3] += np.float32(0.01)
+        fsf = _dm_scene(N, light_moved=True, xf=xf)
+        O.verify(fsf, st)
+        dm_c, pruned, amb = O.dm_update(fsf, st, 7, f)
+        fl = O.info_fields(st.info)
+        res = (fl["replace"] == 1) & (fl["reuse"] == 0)
+        assert int(dm_c.sum()) - int(pruned.sum()) + int(res.sum()) == N
+        after = np.bincount(fl["cell"][~res], minlength=128) + np.bincount(fl["cell"][res], minlength=128)
+        assert np.abs(after.astype(int) - tgt.astype(int)).sum() <= np.abs(dm_c.astype(int) - tgt.astype(int)).sum()
+        # a kept path's cell is the cell of its updated origin and kept direction
+        for p in np.flatnonzero(~res)[::9]:
+            x0 = st.origin[p].astype(np.float64)
+            d = st.pos[0, p].astype(np.float64) - x0
+            c, a = O.dm_cell(xf, fsf.light_half[0], DM_GRID, x0, d / np.linalg.norm(d))
+            if a == 0:
+                assert c == fl["cell"][p], (f, p)
+        O.retrace(fsf, st, -1.0, 7, f)
