@@ -39,8 +39,10 @@ MUTATIONS = {
     # albedo gradient without the division by the albedo
     "gradient_term": ("g_albedo[3 * m + c] += ge / albedo[3 * m + c];", "g_albedo[3 * m + c] += ge;", "gradient"),
     # light sample along the wrong tangent
-    "light_sample_axis": ("for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * ev[i];",
-                          "for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * eu[i];", "light_sample"),
+    "light_sample_axis": ("double a = (2.0 * u[0] - 1.0) * half[0], b = (2.0 * u[1] - 1.0) * half[1];\n"
+                          "  for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * ev[i];",
+                          "double a = (2.0 * u[0] - 1.0) * half[0], b = (2.0 * u[1] - 1.0) * half[1];\n"
+                          "  for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * eu[i];", "light_sample"),
     # bounce sampled on the wrong side of the surface
     "normal_not_flipped": ("    if (dot3(n, w) > 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
                            "    if (dot3(n, w) < 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
