@@ -12,7 +12,11 @@ Tolerances (derived in the design notes):
     relative;
   * paths whose traced rays pass within 1e-5 of a triangle edge, of eps_end,
     of another surface or of eps_close are excluded and counted (at most 5%
-    of the paths of a frame).
+    of the paths of a frame; for a full trace, where every path casts all of
+    its rays, the rate the oracle itself shows on an independent sample of the
+    scene plus three binomial standard deviations of the compared sample).
+    The oracle alone decides what is excluded, so a budget bounds how much of
+    a frame is left uncompared, never how far the kernels may be off.
 
 Every comparison is recorded in REPORT (label -> list of records); the test
 session writes it as JSON (conftest.py).
@@ -68,6 +72,18 @@ def record(label, **fields):
     REPORT.setdefault(label, []).append({k: (float(v) if isinstance(v, (float, np.floating)) else
                                              int(v) if isinstance(v, (bool, int, np.integer, np.bool_)) else v)
                                          for k, v in fields.items()})
+
+
+def sampled_budget(rate, n):
+    """Exclusion budget of n compared paths when the oracle flags a fraction
+    'rate' of the scene's paths: rate plus three binomial standard deviations."""
+    return rate + 3.0 * np.sqrt(rate * (1.0 - rate) / max(n, 1))
+
+
+# Oracle-flagged share of full 7-ray traces of the paper-scale scene: 1279 of
+# 20000 independent paths (seed 5), 6.4%, almost all within 1e-5 of an edge of
+# its finely tessellated walls (about 0.94% per traced ray).
+PAPER_FULL_TRACE_RATE = 0.064
 
 
 def check_excluded(excluded, total, label, frac=EXCL_FRAC):

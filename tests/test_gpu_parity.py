@@ -606,7 +606,8 @@ def test_paper_full_size_sampled(E):
     # the GPU's own frame-0 trace of the sampled columns against the oracle's
     g0 = st.to_numpy(cols)
     o0 = ora.select(cols)
-    H.check_excluded((amb0 != 0).sum(), cols.size, "paper full size frame0 (sampled)")
+    H.check_excluded((amb0 != 0).sum(), cols.size, "paper full size frame0 (sampled)",
+                     H.sampled_budget(H.PAPER_FULL_TRACE_RATE, cols.size))
     H.compare_stores(g0, o0, amb0 == 0, "paper full size frame0 (sampled)", fs0.verts, (amb0 != 0).sum())
     # every path: rows beyond the count are empty, counts agree with the stats
     info = st.info[:N].cpu().numpy().view(np.uint32)
