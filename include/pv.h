@@ -305,6 +305,23 @@ pv_status pv_autotune_report(const pv_ctx* ctx, float* h_out);
 pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
                              float* d_out_energy, uint32_t capacity, uint32_t* d_count);
 
+/* For callers that cannot allocate device memory at all (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * compaction, same outputs and argument errors as pv_compact_photons, with
+ * its scratch (photon counts per bounce row and 256-path block, their
+ * offsets, the scan's tile sums) in a fixed 1 MiB array of the library
+ * instead of the context's reserved scratch.  The call allocates nothing.
+ * Limit: path blocks x bounce rows, ceil(n_paths / 256) * max_bounces, at most
+ * PV_NOALLOC_MAX_COUNTS (e.g. 4.79 M paths of 7 rows); a larger store returns
+ * PV_ERR_CAPACITY before anything is enqueued.  The array is one per device,
+ * shared by every context and call on that device and held until the process
+ * ends; each call overwrites what it reads, so nothing needs clearing, but
+ * calls that overlap on one device (other streams, other threads) race on it
+ * and must be ordered by the caller. */
+#define PV_NOALLOC_MAX_COUNTS 131008u
+pv_status pv_compact_photons_noalloc(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
+                                     float* d_out_energy, uint32_t capacity, uint32_t* d_count);
+
 /* The same compaction, overlapped with the next frame: enqueued on the
  * caller's 'hip_stream' behind everything already on the context's stream (an
  * event), with scan scratch of its own, so that it runs beside the next

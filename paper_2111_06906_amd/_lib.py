@@ -88,6 +88,7 @@ def lib():
         "pv_retrace_paths": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
         "pv_compact_photons": ([P, C.POINTER(PathStore), P, P, U32, P], I32),
         "pv_compact_photons_async": ([P, C.POINTER(PathStore), P, P, U32, P, P], I32),
+        "pv_compact_photons_noalloc": ([P, C.POINTER(PathStore), P, P, U32, P], I32),
         "pv_energy_forward": ([P, C.POINTER(PathStore), P, P, P], I32),
         "pv_energy_backward": ([P, C.POINTER(PathStore), P, P, P, P, P], I32),
         "pv_store_bytes": ([U64, U32], U64),
@@ -199,6 +200,13 @@ def retrace_paths(ctx, store, threshold, seed, frame, d_stats=None):
 
 def compact_photons(ctx, store, d_pos, d_energy, capacity, d_count):
     check(lib().pv_compact_photons(ctx, C.byref(store), d_pos, d_energy, capacity, d_count), ctx)
+
+
+PV_NOALLOC_MAX_COUNTS = 131008  # path blocks x bounce rows the fixed scratch of the no-allocation form holds
+
+
+def compact_photons_noalloc(ctx, store, d_pos, d_energy, capacity, d_count):
+    check(lib().pv_compact_photons_noalloc(ctx, C.byref(store), d_pos, d_energy, capacity, d_count), ctx)
 
 
 def compact_photons_async(ctx, store, d_pos, d_energy, capacity, d_count, stream):

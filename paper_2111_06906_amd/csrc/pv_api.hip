@@ -7,12 +7,21 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "pv_device.h"
 #include "pv_launch.h"
+
+// Fixed device scratch of pv_compact_photons_noalloc: the photon counts per
+// (bounce row, path block), their exclusive offsets and the scan's tile sums.
+// Each device holds its own copy until the process ends.  Host code never
+// uses this name as an address: it takes the current device's address from
+// hipGetSymbolAddress (fixed_scratch below) and passes that to the kernels.
+constexpr uint32_t kFixedScratchWords = (1u << 20) / 4;  // 1 MiB
+static __device__ __align__(256) uint32_t scratch[kFixedScratchWords];
 
 using pv::LeafRec;
 using pv::LightDev;
@@ -39,6 +48,8 @@ struct Alloc {
 struct pv_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
+  uint32_t* fixed_scratch = nullptr;  // this device's copy of 'scratch'
+
   int n_cu = 256;
   std::string err;
   // scene
@@ -142,6 +153,33 @@ struct pv_batch {
 };
 
 namespace {
+
+// Device address of 'scratch' on device 'dev', which must be current: looked
+// up once per device and kept (every context of a device shares the array).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t fixed_scratch(int dev, uint32_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Layout of the fixed scratch for n = path blocks x bounce rows counts:
+// counts [0, a), offsets [a, 2a), scan tile sums [2a, 2a + scan_tmp_words(n))
+// with a = n rounded up to 64 words; returns the words it needs.
+uint64_t fixed_layout(uint64_t n, uint64_t* a) {
+  *a = (n + 63) / 64 * 64;
+  return 2 * *a + pv::scan_tmp_words((uint32_t)std::min<uint64_t>(n, 0xFFFFFFFFull));
+}
 
 pv_status fail(pv_ctx* c, pv_status code, const std::string& msg) {
   if (c) c->err = msg;
@@ -699,6 +737,12 @@ pv_status pv_create(pv_ctx** out, void* hip_stream) {
     return PV_ERR_HIP;
   }
   ctx->n_cu = prop.multiProcessorCount;
+  // the library's fixed scratch on this (current) device
+  if ((e = fixed_scratch(ctx->device, &ctx->fixed_scratch)) != hipSuccess) {
+    g_create_error = std::string("fixed scratch: hipGetSymbolAddress: ") + hipGetErrorString(e);
+    delete ctx;
+    return PV_ERR_HIP;
+  }
   *out = ctx;
   return PV_OK;
 }
@@ -1616,6 +1660,39 @@ pv_status pv_compact_photons(pv_ctx* ctx, const pv_path_store* store, float* d_o
   CK(pv::launch_scan(ctx->d_pcounts, ctx->d_poffsets, nb * store->max_bounces, d_count, ctx->d_scan_tmp,
                      ctx->stream));
   CK(pv::launch_photon_scatter(ctx->d_scene, ctx->d_path_tiles, nb, store->max_bounces, ctx->d_poffsets, d_out_pos,
+                               d_out_energy, capacity, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_compact_photons_noalloc(pv_ctx* ctx, const pv_path_store* store, float* d_out_pos,
+                                     float* d_out_energy, uint32_t capacity, uint32_t* d_count) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!store) return fail(ctx, PV_ERR_ARG, "store is NULL");
+  if (store->max_bounces < 1 || store->max_bounces > PV_MAX_BOUNCES)
+    return fail(ctx, PV_ERR_ARG, "max_bounces out of range 1..15");
+  // the size check comes first: a store too large for the fixed scratch is
+  // rejected before anything is bound or enqueued
+  const uint64_t n = (uint64_t)path_blocks(store->n_paths) * store->max_bounces;
+  uint64_t a = 0;
+  if (fixed_layout(n, &a) > kFixedScratchWords)
+    return fail(ctx, PV_ERR_CAPACITY,
+                "store too large for the fixed compaction scratch: " + std::to_string(n) +
+                    " (path blocks of 256) x (bounce rows) counts, at most " +
+                    std::to_string(PV_NOALLOC_MAX_COUNTS));
+  if (!ctx->fixed_scratch) return fail(ctx, PV_ERR_STATE, "fixed scratch unavailable");
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!d_count || (capacity && (!d_out_pos || !d_out_energy))) return fail(ctx, PV_ERR_ARG, "output is NULL");
+  if ((st = wait_compaction(ctx))) return st;
+  // every word the kernels read is written earlier in the same call, so
+  // nothing is cleared; the scratch keeps the last call's contents
+  uint32_t* counts = ctx->fixed_scratch;
+  uint32_t* offsets = counts + a;
+  uint32_t* tmp = offsets + a;
+  const uint32_t nb = path_blocks(store->n_paths);
+  CK(pv::launch_photon_count(ctx->d_scene, ctx->d_path_tiles, nb, counts, ctx->stream));
+  CK(pv::launch_scan(counts, offsets, (uint32_t)n, d_count, tmp, ctx->stream));
+  CK(pv::launch_photon_scatter(ctx->d_scene, ctx->d_path_tiles, nb, store->max_bounces, offsets, d_out_pos,
                                d_out_energy, capacity, ctx->stream));
   return PV_OK;
 }
