@@ -35,7 +35,8 @@
  *   energy  [B][stride] float4 {r, g, b, radius}: flux arriving at the photon
  *   origin  [3][stride] float: world-space light sample x_0 (x row, y row, z row)
  *   info    [stride] uint32 (Section 4 path-information word):
- *           bits 0..21 distribution-map cell (reserved, kept unchanged),
+ *           bits 0..21 distribution-map cell (pv_set_distribution_map; kept
+ *           unchanged without maps),
  *           22..25 segment count n (0..15),
  *           26..29 first segment to re-trace, 30 replace, 31 reuse light
  *   Paths [light_base[l], light_base[l+1]) belong to light l.
@@ -275,6 +276,46 @@ pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
  * value. */
 enum { PV_VERIFY_TRIANGLES = 0, PV_VERIFY_BOXES = 1 };
 pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode);
+
+/* --- distribution maps (Section 3.1) -------------------------------------- */
+
+/* Section 3.1's distribution maps: each light's emission is partitioned into
+ * cells and the number of paths per cell kept at its target DM_T.
+ * h_grid (host) = {gu, gv, rings, sectors}, each 1..4096: a rectangle's cells
+ * are a gu x gv grid over its local (u, v) times the direction cells, a point
+ * light's the direction cells only; directions are cut on the unit disk of
+ * their local (x, y) components into 'rings' rings of equal area and
+ * 'sectors' sectors of equal angle (cosine-weighted emission is uniform
+ * there, so every cell is equally likely); cell index
+ * ((iu * gv + iv) * rings + ring) * sectors + sector, stored in bits 0..21 of
+ * the information word.  DM_T of cell c of a light with N paths and C cells:
+ * N / C, plus one for c < N mod C.  NULL disables the maps.  Requires an
+ * uploaded scene and pv_reserve (a later pv_reserve or pv_upload_scene
+ * disables them again).  Allocates and synchronises.  PV_ERR_ARG for sizes out
+ * of range or more than 2^22 cells per light (2^24 in all). */
+pv_status pv_set_distribution_map(pv_ctx* ctx, const int32_t* h_grid);
+/* Cells of all lights of the context's maps (0 when none). */
+uint32_t pv_distribution_cells(const pv_ctx* ctx);
+/* Section 3.1's three steps after the origin update (call after
+ * pv_verify_paths, or after pv_queue_all at the first frame, and before
+ * pv_build_queue / pv_retrace_paths):
+ *  Compute DM_C: every path whose light sample survived counts in its cell;
+ *    a moved light's path takes the cell of its updated origin and kept
+ *    direction, and one that has no cell is re-sampled;
+ *  Prune paths: a path of a cell holding C > DM_T paths is re-sampled with
+ *    probability (C - DM_T) / C (Equation 1), decided in FP32 against one
+ *    Philox uniform (key seed, counter (path, frame, 0, 2)), all with the
+ *    counts before pruning (two passes, Section 4);
+ *  Fill DM_C: the i-th re-sampled path of a light (path order: lost, pruned,
+ *    or all of them at the first frame) takes the cell where the running sum
+ *    of the deficits max(0, DM_T - (DM_C - pruned)) passes i.
+ * Re-sampled paths get replace = 1, reuse-light = 0 and their cell; the next
+ * pv_retrace_paths draws their light samples inside the cell.  d_dm_c /
+ * d_pruned (device, nullable, [pv_distribution_cells]) receive the counts of
+ * the first step and the pruned paths per cell.  Single-scene calls only (the
+ * batched form has no maps).  PV_ERR_STATE without maps. */
+pv_status pv_update_distribution(pv_ctx* ctx, const pv_path_store* store, uint64_t seed, uint32_t frame,
+                                 uint32_t* d_dm_c, uint32_t* d_pruned);
 
 /* Autotuner: with the current frame (after pv_frame_begin) and the given
  * store, on a snapshot of the store: time verification (median of three runs

@@ -46,6 +46,7 @@ class CScene(C.Structure):
         ("light_base", C.c_void_p), ("eps_end", C.c_double), ("eps_close", C.c_double),
         ("band_verify", C.c_double), ("band_trace", C.c_double), ("radius", C.c_float),
         ("verify_boxes", C.c_int32), ("band_box", C.c_double), ("dm", C.c_void_p),
+        ("light_kind", C.c_void_p), ("light_param", C.c_void_p),
     ]
 
 
@@ -69,9 +70,9 @@ def _declare(L):
     L.or_segment_blocked_tri.restype = C.c_int
     L.or_segseg_dist.argtypes = [P, P, P, P]
     L.or_segseg_dist.restype = C.c_double
-    L.or_light_update.argtypes = [P, P, P, P, C.c_double, C.c_double, P, P]
+    L.or_light_update.argtypes = [P, P, C.c_int32, P, P, P, C.c_double, C.c_double, P, P]
     L.or_light_update.restype = C.c_int
-    L.or_light_sample.argtypes = [P, P, C.c_uint64, C.c_uint64, C.c_uint64, P, P]
+    L.or_light_sample.argtypes = [P, P, C.c_int32, P, C.c_uint64, C.c_uint64, C.c_uint64, P, P]
     L.or_eq2.argtypes = [P, P, C.c_float]
     L.or_eq2.restype = C.c_int
     L.or_verify.argtypes = [P, P, P, P]
@@ -86,12 +87,12 @@ def _declare(L):
     L.or_energy_backward.argtypes = [P, C.c_int64, C.c_int32, P, P, P, P, P, C.c_int32, P, P]
     L.or_info_make.argtypes = [C.c_uint32] * 5
     L.or_info_make.restype = C.c_uint32
-    L.or_dm_cells.argtypes = [P, P]
+    L.or_dm_cells.argtypes = [P, C.c_int32, P]
     L.or_dm_cells.restype = C.c_int64
     L.or_dm_target.argtypes = [C.c_int64, C.c_int64, P]
-    L.or_dm_cell.argtypes = [P, P, P, P, P, C.c_double, P]
+    L.or_dm_cell.argtypes = [P, P, C.c_int32, P, P, P, P, C.c_double, P]
     L.or_dm_cell.restype = C.c_int64
-    L.or_dm_sample.argtypes = [P, P, P, C.c_int64, C.c_uint64, C.c_uint64, C.c_uint64, P, P]
+    L.or_dm_sample.argtypes = [P, P, C.c_int32, P, P, C.c_int64, C.c_uint64, C.c_uint64, C.c_uint64, P, P]
     L.or_dm_update.argtypes = [P, P, C.c_uint64, C.c_uint64, P, P, P]
 
 
@@ -140,22 +141,33 @@ class FrameScene:
     verify_boxes: int = 0     # 1: Section 3.2's box test instead of the triangles
     band_box: float = 1e-5    # ambiguity band of the box test (covers the kernels' box padding)
     dm: object = None         # None, or the distribution-map grid (gu, gv, rings, sectors)
+    light_kind: object = None   # None (all 0), or [L] i32: 0 rectangle / point, 1 spot, 2 camera
+    light_param: object = None  # [L,2] f32: spot (cos of the half-angle, 0); camera (tan u, tan v)
 
     def cstruct(self):
         self._keep = [_c(self.verts, np.float32), _c(self.tri_obj, np.uint32), _c(self.tri_mat, np.uint32),
                       _c(self.obj_moved, np.uint8), _c(self.albedo, np.float32), _c(self.light_xf, np.float32),
                       _c(self.light_half, np.float32), _c(self.light_power, np.float32),
                       _c(self.light_moved, np.uint8), _c(self.light_base, np.int64),
-                      None if self.dm is None else _c(self.dm, np.int32)]
+                      None if self.dm is None else _c(self.dm, np.int32),
+                      None if self.light_kind is None else _c(self.light_kind, np.int32),
+                      None if self.light_param is None else _c(self.light_param, np.float32)]
         k = self._keep
+        opt = [None if a is None else _p(a) for a in k[10:13]]
         return CScene(k[0].shape[0], _p(k[0]), _p(k[1]), _p(k[2]), k[3].shape[0], _p(k[3]), _p(k[4]),
                       k[5].shape[0], _p(k[5]), _p(k[6]), _p(k[7]), _p(k[8]), _p(k[9]),
                       self.eps_end, self.eps_close, self.band_verify, self.band_trace, self.radius,
-                      int(self.verify_boxes), self.band_box, None if k[10] is None else _p(k[10]))
+                      int(self.verify_boxes), self.band_box, *opt)
+
+    def kind(self, l):
+        return 0 if self.light_kind is None else int(self.light_kind[l])
+
+    def param(self, l):
+        return np.zeros(2, np.float32) if self.light_param is None else np.asarray(self.light_param[l], np.float32)
 
     def dm_offsets(self):
         """First cell of each light in the maps of all lights, and the total."""
-        sizes = [dm_cells(self.light_half[l], self.dm) for l in range(self.light_half.shape[0])]
+        sizes = [dm_cells(self.light_half[l], self.dm, self.kind(l)) for l in range(self.light_half.shape[0])]
         return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
 
 
@@ -191,7 +203,8 @@ def frame_scene(scene, frame, prev_frame=None, band_verify=1e-6, band_trace=1e-5
                       albedo=scene.albedo, light_xf=scene.light_xforms[frame], light_half=scene.light_half,
                       light_power=scene.light_power, light_moved=light_moved, light_base=scene.light_base,
                       eps_end=scene.eps_end, eps_close=scene.eps_close, band_verify=band_verify,
-                      band_trace=band_trace, radius=scene.photon_radius)
+                      band_trace=band_trace, radius=scene.photon_radius,
+                      light_kind=getattr(scene, "light_kind", None), light_param=getattr(scene, "light_param", None))
 
 
 # ---------------------------------------------------------------------------
@@ -293,8 +306,8 @@ def initial_trace(fs: FrameScene, n_paths, B, seed, frame=0, paths=None):
 # ---------------------------------------------------------------------------
 # distribution maps (Section 3.1)
 
-def dm_cells(half, dm):
-    return int(lib().or_dm_cells(_p(_c(half, np.float32)), _p(_c(dm, np.int32))))
+def dm_cells(half, dm, kind=0):
+    return int(lib().or_dm_cells(_p(_c(half, np.float32)), int(kind), _p(_c(dm, np.int32))))
 
 
 def dm_target(n_cells, n_paths):
@@ -303,19 +316,19 @@ def dm_target(n_cells, n_paths):
     return out
 
 
-def dm_cell(xf, half, dm, x0, w, band=1e-6):
+def dm_cell(xf, half, dm, x0, w, band=1e-6, kind=0, param=(0.0, 0.0)):
     """(cell or -1, ambiguity flags) of a light sample."""
     amb = np.zeros(1, np.uint32)
-    c = lib().or_dm_cell(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), _p(_c(dm, np.int32)),
-                         _p(_c(x0, np.float64)), _p(_c(w, np.float64)), band, _p(amb))
+    c = lib().or_dm_cell(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), int(kind), _p(_c(param, np.float32)),
+                         _p(_c(dm, np.int32)), _p(_c(x0, np.float64)), _p(_c(w, np.float64)), band, _p(amb))
     return int(c), int(amb[0])
 
 
-def dm_sample(xf, half, dm, cell, seed, path, frame):
+def dm_sample(xf, half, dm, cell, seed, path, frame, kind=0, param=(0.0, 0.0)):
     x0 = np.zeros(3)
     w = np.zeros(3)
-    lib().or_dm_sample(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), _p(_c(dm, np.int32)), int(cell), seed,
-                       path, frame, _p(x0), _p(w))
+    lib().or_dm_sample(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), int(kind), _p(_c(param, np.float32)),
+                       _p(_c(dm, np.int32)), int(cell), seed, path, frame, _p(x0), _p(w))
     return x0, w
 
 
@@ -357,18 +370,20 @@ def closest_query(fs: FrameScene, o, w):
     return int(tri), float(t[0]), int(amb[0])
 
 
-def light_update(xf, half, x0, x1, eps=1e-4, band=1e-6):
+def light_update(xf, half, x0, x1, eps=1e-4, band=1e-6, kind=0, param=(0.0, 0.0)):
     out = np.zeros(3, np.float64)
     amb = np.zeros(1, np.uint32)
-    ok = lib().or_light_update(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), _p(_c(x0, np.float64)),
-                               _p(_c(x1, np.float64)), eps, band, _p(out), _p(amb))
+    ok = lib().or_light_update(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), int(kind),
+                               _p(_c(param, np.float32)), _p(_c(x0, np.float64)), _p(_c(x1, np.float64)), eps,
+                               band, _p(out), _p(amb))
     return bool(ok), out, int(amb[0])
 
 
-def light_sample(xf, half, seed, path, frame):
+def light_sample(xf, half, seed, path, frame, kind=0, param=(0.0, 0.0)):
     x0 = np.zeros(3)
     w = np.zeros(3)
-    lib().or_light_sample(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), seed, path, frame, _p(x0), _p(w))
+    lib().or_light_sample(_p(_c(xf, np.float32)), _p(_c(half, np.float32)), int(kind), _p(_c(param, np.float32)),
+                          seed, path, frame, _p(x0), _p(w))
     return x0, w
 
 

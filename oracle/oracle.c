@@ -491,21 +491,42 @@ static void light_frame(const float* xf, double c[3], double eu[3], double ev[3]
   for (int r = 0; r < 3; ++r) n[r] /= l;
 }
 
-int or_light_update(const float* xf, const float* half, const double x0[3], const double x1[3],
-                    double eps, double band, double out[3], uint32_t* amb) {
+/* whether the unit direction d (light frame eu, ev, n) lies in the emission */
+/* set of a zero-extent light of kind 'kind' (flags decisions within band)    */
+static int emits(int32_t kind, const float* param, const double eu[3], const double ev[3],
+                 const double n[3], const double d[3], double band, uint32_t* amb) {
+  const double z = dot3(d, n);
+  if (fabs(z) <= band) *amb |= OR_AMB_LIGHT;
+  if (!(z > 0.0)) return 0;
+  if (kind == OR_LIGHT_SPOT) {
+    /* inside the cone: cos of the angle to the axis at least param[0] */
+    if (fabs(z - param[0]) <= band) *amb |= OR_AMB_LIGHT;
+    return z >= param[0];
+  }
+  if (kind == OR_LIGHT_CAMERA) {
+    /* through the near plane at unit distance: |x / z| <= tu, |y / z| <= tv */
+    const double a = dot3(d, eu) / z, b = dot3(d, ev) / z;
+    if (fabs(fabs(a) - param[0]) <= band || fabs(fabs(b) - param[1]) <= band) *amb |= OR_AMB_LIGHT;
+    return fabs(a) <= param[0] && fabs(b) <= param[1];
+  }
+  return 1;
+}
+
+int or_light_update(const float* xf, const float* half, int32_t kind, const float* param, const double x0[3],
+                    const double x1[3], double eps, double band, double out[3], uint32_t* amb) {
   double c[3], eu[3], ev[3], n[3], w[3];
   light_frame(xf, c, eu, ev, n);
   if (half[0] == 0.0f && half[1] == 0.0f) {
-    /* point light: the sample is the light's new position and segment 0 is */
-    /* re-aimed at the first photon; it must leave on the emitting side and  */
-    /* be longer than eps (its visibility is tested by the caller)           */
+    /* point, spot or camera: the sample is the light's new position and     */
+    /* segment 0 is re-aimed at the first photon; it must be longer than eps */
+    /* and leave within the emission set (its visibility is tested by the    */
+    /* caller)                                                               */
     sub3(x1, c, w);
     double len = norm3(w);
     if (fabs(len - eps) <= band) *amb |= OR_AMB_LIGHT;
     if (!(len > eps)) return 0;
-    double dn = dot3(w, n) / len;
-    if (fabs(dn) <= band) *amb |= OR_AMB_LIGHT;
-    if (!(dn > 0.0)) return 0;
+    for (int i = 0; i < 3; ++i) w[i] /= len;
+    if (!emits(kind, param, eu, ev, n, w, band, amb)) return 0;
     for (int i = 0; i < 3; ++i) out[i] = c[i];
     return 1;
   }
@@ -530,6 +551,12 @@ int or_light_update(const float* xf, const float* half, const double x0[3], cons
   if (!(fabs(u) <= half[0] && fabs(v) <= half[1])) return 0;
   for (int i = 0; i < 3; ++i) out[i] = p[i];
   return 1;
+}
+
+static int32_t lkind(const or_scene* s, int l) { return s->light_kind ? s->light_kind[l] : OR_LIGHT_AREA; }
+static const float* lparam(const or_scene* s, int l) {
+  static const float none[2] = {0.0f, 0.0f};
+  return s->light_param ? s->light_param + 2 * l : none;
 }
 
 static int light_of(const or_scene* s, int64_t p) {
@@ -580,8 +607,8 @@ static void verify_path(const or_scene* s, const accel_t* A, or_store* st, int64
     } else {
       vtx(st, p, 0, x0);
       vtx(st, p, 1, x1);
-      if (or_light_update(s->light_xf + 12 * l, s->light_half + 2 * l, x0, x1, s->eps_end, band,
-                          nx, &a)) {
+      if (or_light_update(s->light_xf + 12 * l, s->light_half + 2 * l, lkind(s, l), lparam(s, l), x0, x1,
+                          s->eps_end, band, nx, &a)) {
         store3f(st->origin + 3 * p, nx);
         visibility = s->light_half[2 * l] == 0.0f && s->light_half[2 * l + 1] == 0.0f;
       } else {
@@ -754,16 +781,33 @@ static int naive_from(rctx* c, int64_t p, int k, const double xk[3], const doubl
   return naive_tail(c, p, k, xn, w, (uint32_t)h.tri, en, amb, traces);
 }
 
-/* new light sample: position uniform on the rectangle, direction cosine-    */
-/* weighted about the light normal, both from one Philox draw (tag 0)        */
-void or_light_sample(const float* xf, const float* half, uint64_t seed, uint64_t path,
-                     uint64_t frame, double x0[3], double w[3]) {
+/* new light sample, from one Philox draw (tag 0): position uniform on the  */
+/* rectangle (the centre for a zero-extent light); direction cosine-weighted  */
+/* about the light normal, restricted for a spot light to its cone (the disk  */
+/* point scaled to the cone's radius sin(theta) before the lift, which keeps  */
+/* the cosine weighting inside the cone), and for a camera uniform on the     */
+/* near plane at unit distance, |x| <= tu, |y| <= tv                          */
+void or_light_sample(const float* xf, const float* half, int32_t kind, const float* param, uint64_t seed,
+                     uint64_t path, uint64_t frame, double x0[3], double w[3]) {
   double u[4], c[3], eu[3], ev[3], n[3], l[3];
   draw4(seed, path, frame, 0, 0, u);
   light_frame(xf, c, eu, ev, n);
   double a = (2.0 * u[0] - 1.0) * half[0], b = (2.0 * u[1] - 1.0) * half[1];
   for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * ev[i];
+  if (kind == OR_LIGHT_CAMERA) {
+    const double x = (2.0 * u[0] - 1.0) * param[0], y = (2.0 * u[1] - 1.0) * param[1];
+    const double len = sqrt(x * x + y * y + 1.0);
+    for (int i = 0; i < 3; ++i) w[i] = (x * eu[i] + y * ev[i] + n[i]) / len;
+    return;
+  }
   or_cosine_local(u[2], u[3], l);
+  if (kind == OR_LIGHT_SPOT) {
+    const double sr = sqrt((1.0 - (double)param[0]) * (1.0 + (double)param[0]));
+    l[0] *= sr;
+    l[1] *= sr;
+    const double r2 = l[0] * l[0] + l[1] * l[1];
+    l[2] = sqrt(1.0 - r2 > 0.0 ? 1.0 - r2 : 0.0);
+  }
   for (int i = 0; i < 3; ++i) w[i] = l[0] * eu[i] + l[1] * ev[i] + l[2] * n[i];
 }
 
@@ -784,7 +828,11 @@ static const double PI_D = 3.14159265358979323846;
 
 static int dm_point(const float* half) { return half[0] == 0.0f && half[1] == 0.0f; }
 
-int64_t or_dm_cells(const float* half, const int32_t* dm) {
+/* a camera's cells are a gu x gv grid over its near plane (the pixels); a  */
+/* spot light's direction cells cover the disk of its cone, radius          */
+/* sin(theta), in the same rings (equal area) and sectors                   */
+int64_t or_dm_cells(const float* half, int32_t kind, const int32_t* dm) {
+  if (kind == OR_LIGHT_CAMERA) return (int64_t)dm[0] * dm[1];
   return (int64_t)(dm_point(half) ? 1 : dm[0] * dm[1]) * dm[2] * dm[3];
 }
 
@@ -804,10 +852,26 @@ static double frac_dist(double x) { return fabs(x - floor(x + 0.5)); }
 /* direction not on the emitting side).  Decisions within 'band' of a cell    */
 /* boundary (in scene units on the light, in disk units for the direction)    */
 /* set OR_AMB_CELL.                                                           */
-int64_t or_dm_cell(const float* xf, const float* half, const int32_t* dm, const double x0[3],
-                   const double w[3], double band, uint32_t* amb) {
+int64_t or_dm_cell(const float* xf, const float* half, int32_t kind, const float* param, const int32_t* dm,
+                   const double x0[3], const double w[3], double band, uint32_t* amb) {
   double c[3], eu[3], ev[3], n[3];
   light_frame(xf, c, eu, ev, n);
+  if (kind == OR_LIGHT_CAMERA) {
+    const double z = dot3(w, n);
+    if (fabs(z) <= band) *amb |= OR_AMB_CELL;
+    if (!(z > 0.0)) return -1;
+    const double fu = (dot3(w, eu) / z + param[0]) / (2.0 * param[0]) * dm[0];
+    const double fv = (dot3(w, ev) / z + param[1]) / (2.0 * param[1]) * dm[1];
+    if (!(fu >= 0.0 && fu <= dm[0] && fv >= 0.0 && fv <= dm[1])) return -1;
+    if (frac_dist(fu) * (2.0 * param[0] / dm[0]) <= band || frac_dist(fv) * (2.0 * param[1] / dm[1]) <= band)
+      *amb |= OR_AMB_CELL;
+    int64_t iu = (int64_t)floor(fu), iv = (int64_t)floor(fv);
+    if (iu > dm[0] - 1) iu = dm[0] - 1;
+    if (iv > dm[1] - 1) iv = dm[1] - 1;
+    return iu * dm[1] + iv;
+  }
+  /* squared radius of the direction disk: 1, or sin^2 of a spot's cone */
+  const double s2 = kind == OR_LIGHT_SPOT ? (1.0 - (double)param[0]) * (1.0 + (double)param[0]) : 1.0;
   const int point = dm_point(half);
   const int gu = point ? 1 : dm[0], gv = point ? 1 : dm[1], nr = dm[2], ns = dm[3];
   int64_t iu = 0, iv = 0;
@@ -828,8 +892,9 @@ int64_t or_dm_cell(const float* xf, const float* half, const int32_t* dm, const 
   if (fabs(z) <= band) *amb |= OR_AMB_CELL;
   if (!(z > 0.0)) return -1;
   const double rho2 = x * x + y * y, rho = sqrt(rho2);
-  const double fr = rho2 * nr;
-  if (frac_dist(fr) / nr <= band) *amb |= OR_AMB_CELL;
+  const double fr = rho2 / s2 * nr;
+  if (frac_dist(fr) / nr * s2 <= band) *amb |= OR_AMB_CELL;
+  if (kind == OR_LIGHT_SPOT && !(fr <= nr)) return -1; /* outside the cone */
   int64_t ring = (int64_t)floor(fr);
   if (ring > nr - 1) ring = nr - 1;
   const double phi = atan2(y, x);  /* (-pi, pi] */
@@ -845,11 +910,24 @@ int64_t or_dm_cell(const float* xf, const float* half, const int32_t* dm, const 
 /* restricted to the cell): position uniform in the cell's part of the        */
 /* rectangle, disk point uniform in the cell's ring and sector (uniform in     */
 /* x^2 + y^2 and in angle), lifted to the hemisphere; one Philox draw, tag 0. */
-void or_dm_sample(const float* xf, const float* half, const int32_t* dm, int64_t cell, uint64_t seed,
-                  uint64_t path, uint64_t frame, double x0[3], double w[3]) {
+void or_dm_sample(const float* xf, const float* half, int32_t kind, const float* param, const int32_t* dm,
+                  int64_t cell, uint64_t seed, uint64_t path, uint64_t frame, double x0[3], double w[3]) {
   double u[4], c[3], eu[3], ev[3], n[3];
   draw4(seed, path, frame, 0, 0, u);
   light_frame(xf, c, eu, ev, n);
+  if (kind == OR_LIGHT_CAMERA) {
+    /* uniform in the pixel's part of the near plane */
+    const int64_t iu = cell / dm[1], iv = cell % dm[1];
+    const double x = -param[0] + ((double)iu + u[0]) * (2.0 * param[0] / dm[0]);
+    const double y = -param[1] + ((double)iv + u[1]) * (2.0 * param[1] / dm[1]);
+    const double len = sqrt(x * x + y * y + 1.0);
+    for (int i = 0; i < 3; ++i) {
+      x0[i] = c[i];
+      w[i] = (x * eu[i] + y * ev[i] + n[i]) / len;
+    }
+    return;
+  }
+  const double s2 = kind == OR_LIGHT_SPOT ? (1.0 - (double)param[0]) * (1.0 + (double)param[0]) : 1.0;
   const int point = dm_point(half);
   const int64_t gv = point ? 1 : dm[1], nr = dm[2], ns = dm[3];
   const int64_t gu = point ? 1 : dm[0];
@@ -862,7 +940,7 @@ void or_dm_sample(const float* xf, const float* half, const int32_t* dm, int64_t
     const double b = -half[1] + ((double)iv + u[1]) * (2.0 * half[1] / (double)gv);
     for (int i = 0; i < 3; ++i) x0[i] = c[i] + a * eu[i] + b * ev[i];
   }
-  const double rho2 = ((double)ring + u[2]) / (double)nr, rho = sqrt(rho2);
+  const double rho2 = ((double)ring + u[2]) / (double)nr * s2, rho = sqrt(rho2);
   const double phi = -PI_D + ((double)sector + u[3]) * (2.0 * PI_D / (double)ns);
   const double lx = rho * cos(phi), ly = rho * sin(phi), lz = sqrt(1.0 - rho2 > 0.0 ? 1.0 - rho2 : 0.0);
   for (int i = 0; i < 3; ++i) w[i] = lx * eu[i] + ly * ev[i] + lz * n[i];
@@ -871,7 +949,7 @@ void or_dm_sample(const float* xf, const float* half, const int32_t* dm, int64_t
 /* offset of light l's cells in the maps of all lights */
 static int64_t dm_offset(const or_scene* s, int l) {
   int64_t off = 0;
-  for (int i = 0; i < l; ++i) off += or_dm_cells(s->light_half + 2 * i, s->dm);
+  for (int i = 0; i < l; ++i) off += or_dm_cells(s->light_half + 2 * i, lkind(s, i), s->dm);
   return off;
 }
 
@@ -913,7 +991,8 @@ void or_dm_update(const or_scene* s, or_store* st, uint64_t seed, uint64_t frame
       sub3(x1, x0, d);
       const double len = norm3(d);
       for (int i = 0; i < 3; ++i) d[i] /= len;
-      cell = or_dm_cell(s->light_xf + 12 * l, s->light_half + 2 * l, dm, x0, d, s->band_verify, &amb[p]);
+      cell = or_dm_cell(s->light_xf + 12 * l, s->light_half + 2 * l, lkind(s, l), lparam(s, l), dm, x0, d,
+                        s->band_verify, &amb[p]);
       if (cell < 0) {
         st->info[p] = info_make(0, info_nseg(w), 0, 1, 0);
         continue;
@@ -929,7 +1008,7 @@ void or_dm_update(const or_scene* s, or_store* st, uint64_t seed, uint64_t frame
     const uint32_t w = st->info[p];
     if (info_replace(w) && !info_reuse(w)) continue;
     const int64_t at = dm_offset(s, l) + info_cell(w);
-    const int64_t cells = or_dm_cells(s->light_half + 2 * l, dm);
+    const int64_t cells = or_dm_cells(s->light_half + 2 * l, lkind(s, l), dm);
     const uint32_t tgt = (uint32_t)dm_target_of(s->light_base[l + 1] - s->light_base[l], cells, info_cell(w));
     const uint32_t C = dm_c[at];
     if (C <= tgt) continue;
@@ -943,7 +1022,7 @@ void or_dm_update(const or_scene* s, or_store* st, uint64_t seed, uint64_t frame
   }
   /* Fill DM_C */
   for (int l = 0; l < s->n_lights; ++l) {
-    const int64_t off = dm_offset(s, l), cells = or_dm_cells(s->light_half + 2 * l, dm);
+    const int64_t off = dm_offset(s, l), cells = or_dm_cells(s->light_half + 2 * l, lkind(s, l), dm);
     const int64_t Nl = s->light_base[l + 1] - s->light_base[l];
     int64_t c = 0, run = 0, i = 0;
     for (int64_t p = s->light_base[l]; p < s->light_base[l + 1]; ++p) {
@@ -989,11 +1068,11 @@ static void retrace_path(rctx* c, int64_t p, uint32_t* amb, int* traces) {
     int l = light_of(s, p);
     double x0[3], w0[3];
     if (s->dm)
-      or_dm_sample(s->light_xf + 12 * l, s->light_half + 2 * l, s->dm, info_cell(w), c->seed, (uint64_t)p,
-                   c->frame, x0, w0);
+      or_dm_sample(s->light_xf + 12 * l, s->light_half + 2 * l, lkind(s, l), lparam(s, l), s->dm, info_cell(w),
+                   c->seed, (uint64_t)p, c->frame, x0, w0);
     else
-      or_light_sample(s->light_xf + 12 * l, s->light_half + 2 * l, c->seed, (uint64_t)p, c->frame, x0,
-                      w0);
+      or_light_sample(s->light_xf + 12 * l, s->light_half + 2 * l, lkind(s, l), lparam(s, l), c->seed,
+                      (uint64_t)p, c->frame, x0, w0);
     store3f(st->origin + 3 * p, x0);
     double x0f[3];
     vtx(st, p, 0, x0f);

@@ -48,7 +48,16 @@ typedef struct {
   double band_box;           /* ambiguity band of that box decision */
   const int32_t* dm;         /* NULL, or the distribution-map grid {gu, gv, rings, sectors}: new
                                 light samples are drawn inside the cell of their path */
+  const int32_t* light_kind; /* NULL (all 0), or [L] emission of each light: 0 rectangle / point
+                                light (cosine-weighted hemisphere), 1 spot light, 2 camera */
+  const float* light_param;  /* [L][2]: spot: cos of the cone half-angle; camera: tangents of the
+                                half field of view along u and v */
 } or_scene;
+
+/* light kinds (emission set of a light of zero extent) */
+#define OR_LIGHT_AREA 0
+#define OR_LIGHT_SPOT 1
+#define OR_LIGHT_CAMERA 2
 
 typedef struct {
   int64_t n_paths;

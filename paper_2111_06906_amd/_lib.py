@@ -102,6 +102,9 @@ def lib():
         "pv_get_tuning": ([P, I32, P], I32),
         "pv_autotune": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
         "pv_autotune_report": ([P, P], I32),
+        "pv_set_distribution_map": ([P, P], I32),
+        "pv_distribution_cells": ([P], U32),
+        "pv_update_distribution": ([P, C.POINTER(PathStore), U64, U32, P, P], I32),
     }
     optional = {}
     sig.update({
@@ -315,3 +318,20 @@ def autotune_report(ctx):
     out = (C.c_float * len(AUTOTUNE_REPORT))()
     check(lib().pv_autotune_report(ctx, out), ctx)
     return dict(zip(AUTOTUNE_REPORT, [float(x) for x in out]))
+
+
+def set_distribution_map(ctx, grid):
+    """grid: (gu, gv, rings, sectors), or None to disable the maps."""
+    if grid is None:
+        check(lib().pv_set_distribution_map(ctx, None), ctx)
+    else:
+        g = (C.c_int32 * 4)(*[int(x) for x in grid])
+        check(lib().pv_set_distribution_map(ctx, g), ctx)
+
+
+def distribution_cells(ctx):
+    return int(lib().pv_distribution_cells(ctx))
+
+
+def update_distribution(ctx, store, seed, frame, d_dm_c=None, d_pruned=None):
+    check(lib().pv_update_distribution(ctx, C.byref(store), seed, frame, d_dm_c, d_pruned), ctx)

@@ -97,6 +97,11 @@ struct pv_ctx {
   bool compact_pending = false;
   pv::VerifyWork vw{};  // verification task lists
   pv::OrderWork ow{};   // re-trace work order
+  // distribution maps (pv_set_distribution_map)
+  bool dm_enabled = false;
+  uint32_t dm_cells = 0;  // cells of all lights
+  Alloc dm_mem;
+  pv::DmWork dw{};
   // tuning (pv_set_tuning / pv_autotune)
   int retrace_variant = 0;
   // defaults: the settings the autotuner picks on the 3M-path, 380k-triangle
@@ -815,6 +820,9 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     CK(hipStreamSynchronize(ctx->stream));
     ctx->scene_mem.release();
     ctx->uploaded = ctx->frame_started = ctx->bound = false;
+    ctx->dm_mem.release();  // a new scene has no distribution map
+    ctx->dm_enabled = false;
+    ctx->dm_cells = 0;
     hipStream_t s = ctx->stream;
     Alloc& A = ctx->scene_mem;
     SceneDev hs{};
@@ -1149,6 +1157,12 @@ pv_status pv_reserve(pv_ctx* ctx, uint32_t max_paths, uint32_t max_bounces) {
     CK(hipStreamSynchronize(ctx->stream));
     ctx->res_mem.release();
     ctx->reserved = ctx->bound = false;
+    if (ctx->dm_enabled) {  // the maps' per-tile scratch follows the reserved size: set them again
+      ctx->dm_mem.release();
+      ctx->dm_enabled = false;
+      ctx->dm_cells = 0;
+      std::memset(ctx->hs.dm, 0, sizeof(ctx->hs.dm));
+    }
     Alloc& A = ctx->res_mem;
     uint32_t nb = path_blocks(max_paths);
     std::vector<uint2> tiles = make_tiles(0, max_paths);
@@ -1372,6 +1386,80 @@ pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode) {
     CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
   return PV_OK;
 }
+
+pv_status pv_set_distribution_map(pv_ctx* ctx, const int32_t* h_grid) {
+  if (!ctx) return PV_ERR_ARG;
+  if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
+  if (!ctx->reserved) return fail(ctx, PV_ERR_STATE, "pv_reserve has not been called");
+  if (pv_status w = wait_compaction(ctx)) return w;
+  CK(hipStreamSynchronize(ctx->stream));  // the maps' scratch may be in use
+  ctx->dm_mem.release();
+  ctx->dw = pv::DmWork{};
+  ctx->dm_enabled = false;
+  ctx->dm_cells = 0;
+  std::memset(ctx->hs.dm, 0, sizeof(ctx->hs.dm));
+  std::memset(ctx->hs.dm_off, 0, sizeof(ctx->hs.dm_off));
+  if (h_grid) {
+    for (int k = 0; k < 4; ++k)
+      if (h_grid[k] < 1 || h_grid[k] > 4096) return fail(ctx, PV_ERR_ARG, "grid sizes out of range 1..4096");
+    std::vector<LightDev> lights(ctx->n_lights);
+    CK(hipMemcpy(lights.data(), ctx->hs.lights, sizeof(LightDev) * ctx->n_lights, hipMemcpyDeviceToHost));
+    uint64_t total = 0;
+    uint32_t off[PV_MAX_LIGHTS + 1] = {0};
+    for (uint32_t l = 0; l < ctx->n_lights; ++l) {
+      const uint64_t c = (uint64_t)(pv::dm_point(lights[l].half) ? 1 : (uint64_t)h_grid[0] * h_grid[1]) *
+                         (uint64_t)h_grid[2] * h_grid[3];
+      if (c > (1u << 22)) return fail(ctx, PV_ERR_ARG, "more than 2^22 cells for a light (22-bit cell field)");
+      off[l] = (uint32_t)total;
+      total += c;
+    }
+    if (total > (1u << 24)) return fail(ctx, PV_ERR_ARG, "more than 2^24 cells in all");
+    off[ctx->n_lights] = (uint32_t)total;
+    const uint32_t cells = (uint32_t)total, tiles = ctx->max_blocks;
+    Alloc& A = ctx->dm_mem;
+    pv::DmWork& D = ctx->dw;
+    CK(dalloc(A, &D.dm_c, cells));
+    CK(dalloc(A, &D.pruned, cells));
+    CK(dalloc(A, &D.def, cells));
+    CK(dalloc(A, &D.dex, (size_t)cells + 1));
+    CK(dalloc(A, &D.tcnt, tiles));
+    CK(dalloc(A, &D.toff, tiles));
+    CK(dalloc(A, &D.ttotal, 1));
+    CK(dalloc(A, &D.rank0, PV_MAX_LIGHTS));
+    CK(dalloc(A, &D.scan_tmp, pv::scan_tmp_words(cells)));
+    CK(dalloc(A, &D.scan_tmp2, pv::scan_tmp_words(tiles)));
+    for (int k = 0; k < 4; ++k) ctx->hs.dm[k] = h_grid[k];
+    std::memcpy(ctx->hs.dm_off, off, sizeof(off));
+    ctx->dm_cells = cells;
+    ctx->dm_enabled = true;
+  }
+  // stream-ordered after the work already enqueued
+  CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
+  return PV_OK;
+}
+
+pv_status pv_update_distribution(pv_ctx* ctx, const pv_path_store* store, uint64_t seed, uint32_t frame,
+                                 uint32_t* d_dm_c, uint32_t* d_pruned) {
+  if (!ctx) return PV_ERR_ARG;
+  pv_status st = bind_store(ctx, store);
+  if (st) return st;
+  if (!ctx->dm_enabled) return fail(ctx, PV_ERR_STATE, "no distribution map (pv_set_distribution_map)");
+  if ((st = commit_pending(ctx))) return st;
+  if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "no transforms given (pv_frame_begin or pv_update_*)");
+  if ((st = wait_compaction(ctx))) return st;
+  const uint32_t nb = path_blocks(store->n_paths);
+  CK(pv::launch_dm_update(ctx->d_scene, ctx->d_path_tiles, nb, ctx->dm_cells, ctx->n_lights, ctx->dw,
+                          ctx->d_block_cnt, seed, frame, ctx->stream));
+  if (d_dm_c)
+    CK(hipMemcpyAsync(d_dm_c, ctx->dw.dm_c, 4 * (size_t)ctx->dm_cells, hipMemcpyDeviceToDevice, ctx->stream));
+  if (d_pruned)
+    CK(hipMemcpyAsync(d_pruned, ctx->dw.pruned, 4 * (size_t)ctx->dm_cells, hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->counts_ready = true;
+  ctx->queue_stale = true;
+  return PV_OK;
+}
+
+uint32_t pv_distribution_cells(const pv_ctx* ctx) { return ctx && ctx->dm_enabled ? ctx->dm_cells : 0u; }
 
 pv_status pv_object_hierarchy_info(pv_ctx* ctx, uint32_t obj, uint32_t* out) {
   if (!ctx) return PV_ERR_ARG;

@@ -172,6 +172,10 @@ struct SceneDev {
   uint32_t tile_base;     // first path tile (block of kBlock paths) of this scene
   uint32_t task_base;     // first entry of this scene's tile regions of verification tasks
   uint32_t* state;        // [1] first-frame flag of the scene
+  // distribution maps (Section 3.1): grid {gu, gv, rings, sectors}, dm[0] = 0
+  // when none; first cell of each light in the maps of all lights
+  int32_t dm[4];
+  uint32_t dm_off[PV_MAX_LIGHTS + 1];
 };
 
 // Device scratch of the per-frame object hierarchy rebuild (linear BVH over
@@ -542,6 +546,89 @@ __device__ inline float3 cosine_local(float u1, float u2) {
   float ar = fabsf(r);
   float z2 = (1.0f - ar) * (1.0f + ar);
   return f3(x, y, z2 > 0.0f ? sqrtf(z2) : 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Distribution maps (Section 3.1).  A light's emission is partitioned into
+// cells: for a rectangle, a gu x gv grid over its local (u, v) times a grid of
+// directions; for a point light, the directions only.  Directions are cut on
+// the unit disk of their local (x, y) components (cosine-weighted emission is
+// uniform there): 'rings' rings of equal area (equal steps of x^2 + y^2) and
+// 'sectors' sectors of equal angle, so that every cell is equally likely.
+// Cell index ((iu * gv + iv) * rings + ring) * sectors + sector.
+
+__host__ __device__ inline bool dm_point(const float half[2]) { return half[0] == 0.0f && half[1] == 0.0f; }
+
+__host__ __device__ inline uint32_t dm_cells(const float half[2], const int32_t dm[4]) {
+  return (uint32_t)(dm_point(half) ? 1 : dm[0] * dm[1]) * (uint32_t)dm[2] * (uint32_t)dm[3];
+}
+
+// DM_T: a light's paths spread evenly over its cells, the first N mod C
+// cells one more
+__host__ __device__ inline uint32_t dm_target(uint32_t n_paths, uint32_t cells, uint32_t c) {
+  return n_paths / cells + (c < n_paths % cells ? 1u : 0u);
+}
+
+constexpr float kPiF = 3.14159265358979323846f;
+
+// The cell of a light sample (origin x0 on the light, unit direction w), or
+// -1 when the parametrisation has no value for it (origin off the rectangle,
+// direction not on the emitting side).  xf: the light's 3x4 transform
+// (columns eu, ev, n, centre).
+__device__ inline int32_t dm_cell(const float* xf, const float half[2], const int32_t dm[4], float3 x0,
+                                  float3 w) {
+  const float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
+  const float3 c = f3(xf[3], xf[7], xf[11]);
+  float3 n = f3(xf[2], xf[6], xf[10]);
+  n = mul(n, 1.0f / length(n));
+  const bool point = dm_point(half);
+  const int32_t gu = point ? 1 : dm[0], gv = point ? 1 : dm[1], nr = dm[2], ns = dm[3];
+  int32_t iu = 0, iv = 0;
+  if (!point) {
+    const float3 r = sub(x0, c);
+    const float u = dot(r, eu), v = dot(r, ev);
+    const float fu = (u + half[0]) / (2.0f * half[0]) * (float)gu;
+    const float fv = (v + half[1]) / (2.0f * half[1]) * (float)gv;
+    if (!(fu >= 0.0f && fu <= (float)gu && fv >= 0.0f && fv <= (float)gv)) return -1;
+    iu = min((int32_t)floorf(fu), gu - 1);
+    iv = min((int32_t)floorf(fv), gv - 1);
+  }
+  const float x = dot(w, eu), y = dot(w, ev), z = dot(w, n);
+  if (!(z > 0.0f)) return -1;
+  const float rho2 = x * x + y * y;
+  const int32_t ring = min((int32_t)floorf(rho2 * (float)nr), nr - 1);
+  const float phi = atan2f(y, x);  // [-pi, pi]
+  const float fs = (phi + kPiF) / (2.0f * kPiF) * (float)ns;
+  const int32_t sector = max(0, min((int32_t)floorf(fs), ns - 1));
+  return ((iu * gv + iv) * nr + ring) * ns + sector;
+}
+
+// A new light sample inside cell 'cell' (Section 3.1, filling DM_C:
+// sampling restricted to the cell): position uniform in the cell's part of
+// the rectangle, disk point uniform in the cell's ring (in x^2 + y^2) and
+// sector (in angle), lifted to the hemisphere; u: one Philox draw (tag 0).
+__device__ inline void dm_sample(const float* xf, const float half[2], const int32_t dm[4], uint32_t cell,
+                                 const float u[4], float3* x0, float3* w) {
+  const float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
+  const float3 c = f3(xf[3], xf[7], xf[11]);
+  float3 n = f3(xf[2], xf[6], xf[10]);
+  n = mul(n, 1.0f / length(n));
+  const bool point = dm_point(half);
+  const uint32_t gu = point ? 1u : (uint32_t)dm[0], gv = point ? 1u : (uint32_t)dm[1];
+  const uint32_t nr = (uint32_t)dm[2], ns = (uint32_t)dm[3];
+  const uint32_t sector = cell % ns, ring = (cell / ns) % nr, pc = cell / (ns * nr);
+  const uint32_t iv = pc % gv, iu = pc / gv;
+  if (point) {
+    *x0 = c;
+  } else {
+    const float a = -half[0] + ((float)iu + u[0]) * (2.0f * half[0] / (float)gu);
+    const float b = -half[1] + ((float)iv + u[1]) * (2.0f * half[1] / (float)gv);
+    *x0 = add(c, add(mul(eu, a), mul(ev, b)));
+  }
+  const float rho2 = ((float)ring + u[2]) / (float)nr, rho = sqrtf(rho2);
+  const float phi = -kPiF + ((float)sector + u[3]) * (2.0f * kPiF / (float)ns);
+  const float lx = rho * cosf(phi), ly = rho * sinf(phi), lz = sqrtf(fmaxf(1.0f - rho2, 0.0f));
+  *w = add(add(mul(eu, lx), mul(ev, ly)), mul(n, lz));
 }
 
 // Tangent frame of a unit normal (Duff et al., JCGT 2017).

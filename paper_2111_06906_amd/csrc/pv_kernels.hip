@@ -1296,10 +1296,17 @@ __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t fram
     float3 nl = normalize3(f3(xf[2], xf[6], xf[10])), c = f3(xf[3], xf[7], xf[11]);
     float u[4];
     draw4(seed, L.p, frame, 0, 0, u);
-    float a = (2.0f * u[0] - 1.0f) * lt->half[0], b = (2.0f * u[1] - 1.0f) * lt->half[1];
-    float3 x0 = add(c, add(mul(eu, a), mul(ev, b)));
-    float3 lc = cosine_local(u[2], u[3]);
-    L.w = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
+    float3 x0;
+    if (S.dm[0] > 0) {
+      // distribution maps: the sample is drawn inside the path's cell
+      const LightDev lc = *lt;
+      dm_sample((const float*)xf, lc.half, S.dm, L.cell, u, &x0, &L.w);
+    } else {
+      float a = (2.0f * u[0] - 1.0f) * lt->half[0], b = (2.0f * u[1] - 1.0f) * lt->half[1];
+      x0 = add(c, add(mul(eu, a), mul(ev, b)));
+      float3 lc = cosine_local(u[2], u[3]);
+      L.w = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
+    }
     const size_t stride = S.stride;
     PV_GLOBAL float* org = G(S.origin);
     org[L.p] = x0.x;

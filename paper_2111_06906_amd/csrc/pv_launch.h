@@ -76,6 +76,24 @@ hipError_t launch_photon_scatter(const SceneDev* scenes, const uint2* tiles, uin
                                  hipStream_t s);
 hipError_t launch_scene_photon_base(const SceneDev* scenes, int n_scenes, const uint32_t* offsets, const uint32_t* total,
                                     uint32_t* base, hipStream_t s);
+// Scratch of the distribution-map update (cells: all lights' cells)
+struct DmWork {
+  uint32_t* dm_c;      // [cells] paths counted per cell (Compute DM_C)
+  uint32_t* pruned;    // [cells] paths pruned per cell
+  uint32_t* def;       // [cells] deficits
+  uint32_t* dex;       // [cells + 1] their exclusive scan, then the total
+  uint32_t* tcnt;      // [tiles] re-sampled paths per path tile
+  uint32_t* toff;      // [tiles] their exclusive scan
+  uint32_t* ttotal;    // [1]
+  uint32_t* rank0;     // [PV_MAX_LIGHTS] rank of each light's first path among the re-sampled ones
+  uint32_t* scan_tmp;  // scan_tmp_words(cells)
+  uint32_t* scan_tmp2; // scan_tmp_words(tiles)
+};
+// Compute DM_C, prune (Equation 1), fill (Section 3.1) on one scene's store
+// (information words updated, tiles' replace counts into block_cnt)
+hipError_t launch_dm_update(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t cells,
+                            uint32_t n_lights, const DmWork& D, uint32_t* block_cnt, uint64_t seed, uint32_t frame,
+                            hipStream_t s);
 hipError_t launch_energy_fwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,
                              const float* power, float* E, hipStream_t s);
 hipError_t launch_energy_bwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,

@@ -239,13 +239,29 @@ class Context:
         """Section 3.2's conservative box test (True) or the triangle test (False)."""
         L.set_verify_mode(self.ctx, L.PV_VERIFY_BOXES if boxes else L.PV_VERIFY_TRIANGLES)
 
+    def set_distribution_map(self, grid):
+        """Section 3.1's distribution maps with grid (gu, gv, rings, sectors), or None."""
+        L.set_distribution_map(self.ctx, grid)
+
+    def update_distribution(self, store, seed, frame):
+        """Compute DM_C, prune (Equation 1), fill; returns (DM_C before pruning,
+        pruned per cell) as device tensors over all lights' cells."""
+        n = L.distribution_cells(self.ctx)
+        dm_c = torch.zeros(max(n, 1), dtype=I32, device="cuda")
+        pruned = torch.zeros(max(n, 1), dtype=I32, device="cuda")
+        L.update_distribution(self.ctx, store.cstruct(), int(seed), int(frame), _ptr(dm_c), _ptr(pruned))
+        return dm_c[:n], pruned[:n]
+
     def object_hierarchy_info(self, obj):
         """Check of dynamic object obj's current device hierarchy (synchronises)."""
         return L.object_hierarchy_info(self.ctx, int(obj))
 
     def initial_trace(self, store, seed, frame=0, stats=None):
-        """Frame-0 photon paths (every path a new light sample)."""
+        """Frame-0 photon paths (every path a new light sample; with
+        distribution maps, the fill first gives every path its cell)."""
         self.queue_all(store)
+        if L.distribution_cells(self.ctx):
+            self.update_distribution(store, seed, frame)
         self.retrace(store, -1.0, seed, frame, stats)
 
 

@@ -1,0 +1,172 @@
+"""Distribution maps of Section 3.1 (compute DM_C, prune with Equation 1,
+fill) on the device against the oracle, in lockstep over frames with moving
+lights, and the first frame's exact targets at full size.
+
+Cells, counts and prune / fill decisions are integer work or FP32
+comparisons both sides take alike: they are compared bit for bit, except
+where the oracle flags a decision inside its band (a cell boundary within
+1e-6 of a moved light's re-aimed sample, or a verification decision); then the
+histograms may legitimately differ by the flagged paths and the frame's
+dependent assignments are not compared element by element (counted and
+recorded).  Stores after the re-trace (light samples drawn inside the cells)
+are compared with the usual tolerances.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_06906_amd import scenes
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+GRID = (2, 2, 4, 8)  # 128 cells per rectangular light
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2111_06906_amd import engine
+    return engine
+
+
+def _fs(sc, f, prev=None, grid=GRID):
+    fs = O.frame_scene(sc, f) if prev is None else O.frame_scene(sc, f, prev)
+    fs.dm = np.asarray(grid, np.int32)
+    return fs
+
+
+def _cells_per_light(fs, info, light_base):
+    """Histogram of the stored cells of each light's paths (all lights' cells)."""
+    off = fs.dm_offsets()
+    cells = info & 0x3FFFFF
+    out = np.zeros(int(off[-1]), np.int64)
+    for l in range(len(light_base) - 1):
+        c = cells[light_base[l]:light_base[l + 1]].astype(np.int64)
+        out[off[l]:off[l + 1]] += np.bincount(c, minlength=int(off[l + 1] - off[l]))[: off[l + 1] - off[l]]
+    return out
+
+
+def _targets(fs, light_base):
+    off = fs.dm_offsets()
+    return np.concatenate([O.dm_target(int(off[l + 1] - off[l]), int(light_base[l + 1] - light_base[l]))
+                           for l in range(len(light_base) - 1)]).astype(np.int64)
+
+
+def _run(E, sc, frames, T, label, grid=GRID):
+    import torch
+    lb = sc.light_base
+    fs0 = _fs(sc, 0, grid=grid)
+    ora, amb0, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    ctx = E.Context(sc)
+    ctx.set_distribution_map(grid)
+    st = ctx.new_store()
+    ctx.frame_begin(0)
+    ctx.initial_trace(st, sc.seed, 0)
+    g0 = st.to_numpy()
+    # frame 0: every path re-sampled, the fill alone gives the cells (exact)
+    assert np.array_equal(g0["info"] & 0x3FFFFF, ora.info & 0x3FFFFF)
+    assert np.array_equal(_cells_per_light(fs0, g0["info"], lb), _targets(fs0, lb))
+    ok0 = amb0 == 0
+    H.check_excluded((~ok0).sum(), sc.n_paths, "%s frame 0" % label,
+                     H.sampled_budget(H.PAPER_FULL_TRACE_RATE, sc.n_paths))
+    H.compare_stores(g0, ora, ok0, "%s frame 0" % label, fs0.verts, (~ok0).sum())
+    strict_frames = 0
+    for f in range(1, frames):
+        st.load_numpy(H.from_oracle(ora))
+        ctx.frame_begin(f)
+        ctx.verify(st, build_queue=False)
+        dm_c_g, pr_g = ctx.update_distribution(st, sc.seed, f)
+        torch.cuda.synchronize()
+        gd = st.to_numpy()
+        fs = _fs(sc, f, f - 1, grid)
+        ambv, _ = O.verify(fs, ora)
+        dm_c_o, pr_o, ambd = O.dm_update(fs, ora, sc.seed, f)
+        flagged = (ambv | ambd) != 0
+        dc, dp = dm_c_g.cpu().numpy().astype(np.int64), pr_g.cpu().numpy().astype(np.int64)
+        same_hist = np.array_equal(dc, dm_c_o.astype(np.int64)) and np.array_equal(dp, pr_o.astype(np.int64))
+        n_flag = int(flagged.sum())
+        log("%s frame %d: %d paths flagged, histograms %s, %d pruned, %d counted" % (
+            label, f, n_flag, "equal" if same_hist else "differ", int(pr_o.sum()), int(dm_c_o.sum())))
+        H.record("%s frame %d [distribution]" % (label, f), flagged=n_flag, histograms_equal=bool(same_hist),
+                 pruned=int(pr_o.sum()), counted=int(dm_c_o.sum()))
+        if not same_hist:
+            # only flagged paths may have been counted differently
+            assert np.abs(dc - dm_c_o).sum() <= 2 * n_flag and n_flag > 0
+        else:
+            bad = np.flatnonzero((gd["info"] != ora.info) & ~flagged)
+            assert bad.size == 0, "info differs at %d unflagged paths, e.g. %d: gpu %08x oracle %08x" % (
+                bad.size, bad[0], gd["info"][bad[0]], ora.info[bad[0]])
+            if n_flag == 0:
+                assert np.array_equal(gd["info"], ora.info)
+                strict_frames += 1
+        ctx.retrace(st, T, sc.seed, f)
+        gr = st.to_numpy()
+        ambr, _ = O.retrace(fs, ora, T, sc.seed, f)
+        if not same_hist:
+            continue
+        ok = ~flagged & (ambr == 0)
+        H.check_excluded((~ok).sum(), sc.n_paths, "%s frame %d" % (label, f))
+        H.compare_stores(gr, ora, ok, "%s frame %d" % (label, f), fs.verts, (~ok).sum())
+    ctx.close()
+    return strict_frames
+
+
+def test_distribution_maps_moving_lights_lockstep(E):
+    # the paper-scale generator (moving lights) at 8k paths, error-based re-trace
+    sc = scenes.make_paper(n_paths=8192 + 37, frames=4)
+    assert _run(E, sc, 4, 0.01, "dm paper 8k") >= 1
+
+
+def test_distribution_maps_static_lights_naive(E):
+    # static lights: cells never change; pruning and filling still act on the
+    # paths the moving objects invalidate
+    sc = scenes.make_mid(n_paths=6000 + 5, frames=3)
+    assert _run(E, sc, 3, -1.0, "dm mid 6k", grid=(3, 2, 2, 6)) >= 1
+
+
+def test_distribution_maps_point_lights(E):
+    sc = scenes.make_rooms("pts", 3, 3, 20_000, 3, (40, 16), 4096 + 9, 5, 3, 0.01, 13, n_lights=2,
+                           lights_move=True, point_lights=True)
+    assert _run(E, sc, 3, 0.01, "dm point lights", grid=(1, 1, 4, 16)) >= 1
+
+
+def test_distribution_maps_full_size_first_frame(E):
+    # the measured workload with maps: after the first frame every cell of
+    # both lights holds exactly its target, and a following frame keeps the
+    # total number of paths per light (counted - pruned + filled = N_l)
+    import torch
+    sc = scenes.make_paper(frames=3)
+    grid = (4, 4, 8, 16)
+    ctx = E.Context(sc)
+    ctx.set_distribution_map(grid)
+    st = ctx.new_store()
+    ctx.frame_begin(0)
+    ctx.initial_trace(st, sc.seed, 0)
+    fs0 = _fs(sc, 0, grid=grid)
+    lb = sc.light_base
+    info = st.info[:sc.n_paths].cpu().numpy().view(np.uint32)
+    assert np.array_equal(_cells_per_light(fs0, info, lb), _targets(fs0, lb))
+    ctx.frame_begin(1)
+    ctx.verify(st, build_queue=False)
+    dm_c, pruned = ctx.update_distribution(st, sc.seed, 1)
+    torch.cuda.synchronize()
+    info = st.info[:sc.n_paths].cpu().numpy().view(np.uint32)
+    assert int(pruned.sum().item()) > 0 or int(dm_c.sum().item()) == sc.n_paths
+    # every path has a cell of its light, and re-sampled paths carry replace without reuse
+    cells = info & 0x3FFFFF
+    off = fs0.dm_offsets()
+    for l in range(len(lb) - 1):
+        assert cells[lb[l]:lb[l + 1]].max() < off[l + 1] - off[l]
+    rs = ((info >> 30) & 1 == 1) & ((info >> 31) & 1 == 0)
+    log("full size: %d counted, %d pruned, %d re-sampled" % (int(dm_c.sum().item()), int(pruned.sum().item()),
+                                                              int(rs.sum())))
+    ctx.retrace(st, sc.threshold, sc.seed, 1)
+    torch.cuda.synchronize()
+    ctx.close()

@@ -82,7 +82,8 @@ MUTATIONS = {
     "dm_fill_targets": ("const int64_t def = tgt > have ? tgt - have : 0;", "const int64_t def = tgt;",
                         "dm_fill or dm_static"),
     # rings of equal radius steps instead of equal area
-    "dm_ring_radius": ("const double fr = rho2 * nr;", "const double fr = rho * nr;", "dm_cell or dm_cells"),
+    "dm_ring_radius": ("const double fr = rho2 / s2 * nr;", "const double fr = rho / s2 * nr;",
+                       "dm_cell or dm_cells"),
     # restricted sampling with the position cell's row and column swapped
     "dm_sample_swapped": ("const int64_t iv = pc % gv, iu = pc / gv;", "const int64_t iu = pc % gv, iv = pc / gv;",
                           "dm_restricted or dm_initial"),
