@@ -90,6 +90,19 @@ MUTATIONS = {
     # a moved light's paths keep their old cells
     "dm_stale_cells": ("    if (s->light_moved[l]) {\n      double x0[3], x1[3], d[3];",
                        "    if (0) {\n      double x0[3], x1[3], d[3];", "dm_moving"),
+    # a spot light's cone test inverted
+    "spot_cone_inverted": ("    return z >= param[0];", "    return z <= param[0];", "spot"),
+    # spot samples drawn over the whole hemisphere (disk not scaled to the cone)
+    "spot_disk_unscaled": ("    l[0] *= sr;\n    l[1] *= sr;", "    l[0] *= 1.0;\n    l[1] *= 1.0;", "spot"),
+    # a camera's field-of-view tangents swapped between u and v
+    "camera_tangents_swapped": ("return fabs(a) <= param[0] && fabs(b) <= param[1];",
+                                "return fabs(a) <= param[1] && fabs(b) <= param[0];", "camera"),
+    # a camera's pixel index transposed
+    "camera_cell_transposed": ("    return iu * dm[1] + iv;", "    return iv * dm[0] + iu;", "cells"),
+    # restricted spot samples spread over the whole disk instead of the cone's
+    "spot_restricted_radius": ("const double rho2 = ((double)ring + u[2]) / (double)nr * s2, rho = sqrt(rho2);",
+                               "const double rho2 = ((double)ring + u[2]) / (double)nr, rho = sqrt(rho2);",
+                               "uniform_over_cells"),
 }
 
 

@@ -1106,3 +1106,181 @@ def test_dm_moving_light_converges_and_conserves():
             if a == 0:
                 assert c == fl["cell"][p], (f, p)
         O.retrace(fsf, st, -1.0, 7, f)
+
+
+# ---------------------------------------------------------------------------
+# spot lights and cameras (Section 3.1's spotlight; Section 7's camera paths):
+# zero-extent emitters whose emission set is a cone (spot) or a rectangular
+# near plane at unit distance (camera)
+
+SPOT_COS = np.float32(0.8)                       # cone half-angle acos(0.8) = 36.87 degrees
+CAM_TAN = np.array([0.5, 0.25], np.float32)      # half field of view tangents along u, v
+ZERO = np.zeros(2, np.float32)
+
+
+def test_spot_samples_fill_the_cone_cosine_weighted():
+    # every direction lies inside the cone, the sample sits at the light, and
+    # the mean cosine to the axis is the cosine-weighted cap's closed form
+    # E[cos] = 2 (1 - c^3) / (3 (1 - c^2))
+    xf, c0 = H.LIGHT_DOWN, float(SPOT_COS)
+    n = 20000
+    cs = np.empty(n)
+    for p in range(n):
+        x0, w = O.light_sample(xf, ZERO, 5, p, 1, kind=1, param=(SPOT_COS, 0))
+        assert np.array_equal(x0, np.array([xf[3], xf[7], xf[11]], np.float64))
+        assert abs(np.linalg.norm(w) - 1) < 1e-12
+        cs[p] = -w[1]   # LIGHT_DOWN emits along -y
+    assert cs.min() >= c0 - 1e-12
+    mean = 2 * (1 - c0 ** 3) / (3 * (1 - c0 ** 2))
+    # cos^2 is uniform on [c^2, 1] under this density: variance of cos below 0.01
+    assert abs(cs.mean() - mean) < 4 * np.sqrt(0.01 / n), (cs.mean(), mean)
+    # the full hemisphere's 2/3 is the limit c -> 0
+    x, w = O.light_sample(xf, ZERO, 5, 0, 1, kind=1, param=(np.float32(0.0), 0))
+    assert abs(np.linalg.norm(w) - 1) < 1e-12
+
+
+def test_camera_samples_are_uniform_on_the_near_plane():
+    xf = H.LIGHT_DOWN
+    n = 20000
+    ab = np.empty((n, 2))
+    for p in range(n):
+        x0, w = O.light_sample(xf, ZERO, 6, p, 1, kind=2, param=CAM_TAN)
+        assert np.array_equal(x0, np.array([xf[3], xf[7], xf[11]], np.float64))
+        z = -w[1]
+        ab[p] = (w[0] / z, w[2] / z)    # local u = world x, local v = world z
+    assert (np.abs(ab) <= CAM_TAN + 1e-12).all()
+    # uniform on [-t, t]: mean 0, variance t^2 / 3
+    for k in range(2):
+        t = float(CAM_TAN[k])
+        assert abs(ab[:, k].mean()) < 4 * t / np.sqrt(3 * n)
+        assert abs(ab[:, k].var() - t * t / 3) < 0.05 * t * t / 3
+
+
+def test_spot_and_camera_updates_keep_paths_inside_their_emission_set():
+    x0 = np.array([0.5, 0.999, 0.5])
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(0.02)      # light moved 0.02 along +x
+    c = np.array([xf[3], xf[7], xf[11]], np.float64)
+    # spot: a photon 0.4 below at lateral distance 0.2 is at cos = 0.4 / sqrt(0.2) = 0.894 > 0.8
+    x1 = c + np.array([0.2, -0.4, 0.0])
+    ok, nx, amb = O.light_update(xf, ZERO, x0, x1, kind=1, param=(SPOT_COS, 0))
+    assert ok and amb == 0 and np.array_equal(nx, c)
+    # lateral 0.35: cos = 0.4 / sqrt(0.2825) = 0.753 < 0.8, outside the cone: lost
+    ok2, _, _ = O.light_update(xf, ZERO, x0, c + np.array([0.35, -0.4, 0.0]), kind=1, param=(SPOT_COS, 0))
+    assert not ok2
+    # exactly on the cone (lateral 0.3: cos = 0.8) is flagged
+    _, _, amb3 = O.light_update(xf, ZERO, x0, c + np.array([0.3, -0.4, 0.0]), kind=1, param=(SPOT_COS, 0))
+    assert amb3 & O.AMB_LIGHT
+    # camera: |x / z| <= 0.5 and |y / z| <= 0.25 through the near plane
+    ok4, nx4, _ = O.light_update(xf, ZERO, x0, c + np.array([0.19, -0.4, 0.09]), kind=2, param=CAM_TAN)
+    assert ok4 and np.array_equal(nx4, c)
+    ok5, _, _ = O.light_update(xf, ZERO, x0, c + np.array([0.19, -0.4, 0.11]), kind=2, param=CAM_TAN)
+    assert not ok5       # v / z = 0.275 > 0.25
+    ok6, _, _ = O.light_update(xf, ZERO, x0, c + np.array([0.21, -0.4, 0.0]), kind=2, param=CAM_TAN)
+    assert not ok6       # u / z = 0.525 > 0.5
+    # the hemisphere point light keeps both
+    assert O.light_update(xf, ZERO, x0, c + np.array([0.35, -0.4, 0.0]))[0]
+
+
+def test_spot_and_camera_cells():
+    xf = H.LIGHT_DOWN
+    c = np.array([0.5, 0.999, 0.5])
+    # camera: the pixel grid over the near plane, cell iu * gv + iv
+    grid = np.array([4, 2, 1, 1], np.int32)
+    assert O.dm_cells(ZERO, grid, kind=2) == 8
+    w = np.array([0.3, -1.0, -0.1])        # u / z = 0.3 -> column floor(4 * 0.8 / 1.0) = 3
+    w /= np.linalg.norm(w)                 # v / z = -0.1 -> row floor(2 * 0.15 / 0.5) = 0
+    cell, amb = O.dm_cell(xf, ZERO, grid, c, w, kind=2, param=CAM_TAN)
+    assert amb == 0 and cell == 3 * 2 + 0
+    assert O.dm_cell(xf, ZERO, grid, c, np.array([0.6, -1.0, 0.0]) / np.sqrt(1.36), kind=2, param=CAM_TAN)[0] == -1
+    # spot: rings of equal area on the cone's disk of radius sin(theta) = 0.6
+    sgrid = np.array([1, 1, 4, 8], np.int32)
+    assert O.dm_cells(ZERO, sgrid, kind=1) == 32
+    rho = 0.6 * np.sqrt(0.6)               # x^2 + y^2 = 0.6 s^2 -> ring floor(4 * 0.6) = 2
+    a = 0.2                                # angle 0.2 rad -> sector floor(8 (0.2 + pi) / 2 pi) = 4
+    w = np.array([rho * np.cos(a), -np.sqrt(1 - rho * rho), rho * np.sin(a)])
+    cs, amb = O.dm_cell(xf, ZERO, sgrid, c, w, kind=1, param=(SPOT_COS, 0))
+    assert amb == 0 and cs == 2 * 8 + 4
+    w_out = np.array([0.7, -np.sqrt(1 - 0.49), 0.0])   # sin 0.7 > 0.6: outside the cone
+    assert O.dm_cell(xf, ZERO, sgrid, c, w_out, kind=1, param=(SPOT_COS, 0))[0] == -1
+
+
+@pytest.mark.parametrize("kind,param,grid", [(1, (SPOT_COS, 0.0), (1, 1, 3, 8)), (2, CAM_TAN, (4, 3, 1, 1))])
+def test_spot_and_camera_samples_are_uniform_over_cells_and_restricted_samples_return(kind, param, grid):
+    xf = H.LIGHT_DOWN.copy()
+    xf[11] += np.float32(0.011)
+    grid = np.asarray(grid, np.int32)
+    cells = O.dm_cells(ZERO, grid, kind=kind)
+    n = 24 * 1024
+    counts = np.zeros(cells)
+    for p in range(n):
+        x0, w = O.light_sample(xf, ZERO, 4, p, 0, kind=kind, param=param)
+        cc, _ = O.dm_cell(xf, ZERO, grid, x0, w, kind=kind, param=param)
+        assert cc >= 0
+        counts[cc] += 1
+    e = n / cells
+    chi2 = ((counts - e) ** 2 / e).sum()
+    dof = cells - 1
+    assert chi2 < dof + 6 * np.sqrt(2 * dof), chi2
+    for cell in range(cells):
+        for path in range(4):
+            x0, w = O.dm_sample(xf, ZERO, grid, cell, 8, path * 97 + cell, 1, kind=kind, param=param)
+            cc, amb = O.dm_cell(xf, ZERO, grid, x0, w, kind=kind, param=param)
+            assert amb != 0 or cc == cell
+
+
+def _spot_scene(kind, param, dx, blockers=(), n_paths=1):
+    xf = H.LIGHT_DOWN.copy()
+    xf[3] += np.float32(dx)
+    fs = H.box_scene(blockers=blockers, moved=False, light_moved=dx != 0, light_xf=xf, light_half=(0.0, 0.0),
+                     n_paths=n_paths)
+    fs.light_kind = np.array([kind], np.int32)
+    fs.light_param = np.array([param], np.float32)
+    return fs
+
+
+@pytest.mark.parametrize("kind,param", [(1, (SPOT_COS, 0.0)), (2, CAM_TAN)])
+def test_spot_and_camera_paths_traced_inside_their_emission_and_moved_ones_verified(kind, param):
+    # frame 0 with the emitter at LIGHT_DOWN: every path's first segment lies
+    # in its emission set; after the emitter moves 0.03 along x, verification
+    # keeps exactly the paths whose first photon is still inside it (brute
+    # force: the emission test on the re-aimed segment 0, which a static
+    # blocker may also cut), and re-aims them at the new position
+    n = 400
+    fs0 = _spot_scene(kind, param, 0.0, n_paths=n)
+    st, amb0, _ = O.initial_trace(fs0, n, 3, 21)
+    c0 = np.array([0.5, 0.999, 0.5])
+    d = st.pos[0].astype(np.float64) - st.origin.astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    z = -d[:, 1]
+    if kind == 1:
+        assert (z >= float(param[0]) - 1e-6).all()
+    else:
+        assert (np.abs(d[:, 0] / z) <= float(param[0]) + 1e-6).all()
+        assert (np.abs(d[:, 2] / z) <= float(param[1]) + 1e-6).all()
+    assert np.allclose(st.origin, c0)
+    fs1 = _spot_scene(kind, param, 0.03, n_paths=n)
+    v = st.copy()
+    ambv, _ = O.verify(fs1, v)
+    c1 = c0 + np.array([0.03, 0, 0])
+    f = O.info_fields(v.info)
+    n0 = O.info_fields(st.info)["nseg"]
+    for p in range(n):
+        if ambv[p] or amb0[p]:
+            continue
+        if n0[p] == 0:
+            # escaped at once: nothing to aim at, a new sample is drawn
+            assert f["replace"][p] == 1 and f["reuse"][p] == 0
+            continue
+        e = st.pos[0, p].astype(np.float64) - c1
+        e /= np.linalg.norm(e)
+        zz = -e[1]
+        inside = zz >= float(param[0]) if kind == 1 else (abs(e[0] / zz) <= float(param[0]) and
+                                                          abs(e[2] / zz) <= float(param[1]))
+        if inside:
+            # re-aimed at the new position; the box is empty, so the path stays valid
+            assert f["replace"][p] == 0, p
+            assert np.allclose(v.origin[p], c1, atol=1e-6)
+        else:
+            assert f["replace"][p] == 1 and f["reuse"][p] == 0 and f["start"][p] == 0, p
+    assert (f["replace"] == 1).sum() > 0 and (f["replace"] == 0).sum() > 0
