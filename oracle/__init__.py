@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 HIT_NONE = 0xFFFFFFFF
-AMB_EDGE, AMB_END, AMB_LIGHT, AMB_TIE, AMB_HEMI, AMB_CLOSE, AMB_BOX, AMB_CELL = 1, 2, 4, 8, 16, 32, 64, 128
+AMB_EDGE, AMB_END, AMB_LIGHT, AMB_TIE, AMB_HEMI, AMB_CLOSE, AMB_BOX, AMB_CELL, AMB_EQ2 = 1, 2, 4, 8, 16, 32, 64, 128, 256
 
 _lib = None
 
@@ -46,7 +46,7 @@ class CScene(C.Structure):
         ("light_base", C.c_void_p), ("eps_end", C.c_double), ("eps_close", C.c_double),
         ("band_verify", C.c_double), ("band_trace", C.c_double), ("radius", C.c_float),
         ("verify_boxes", C.c_int32), ("band_box", C.c_double), ("dm", C.c_void_p),
-        ("light_kind", C.c_void_p), ("light_param", C.c_void_p),
+        ("light_kind", C.c_void_p), ("light_param", C.c_void_p), ("energy_test", C.c_int32),
     ]
 
 
@@ -143,6 +143,7 @@ class FrameScene:
     dm: object = None         # None, or the distribution-map grid (gu, gv, rings, sectors)
     light_kind: object = None   # None (all 0), or [L] i32: 0 rectangle / point, 1 spot, 2 camera
     light_param: object = None  # [L,2] f32: spot (cos of the half-angle, 0); camera (tan u, tan v)
+    energy_test: int = 0        # Equation 2's E_N: 0 albedo (arrival side), 1 also the cosine ratio
 
     def cstruct(self):
         self._keep = [_c(self.verts, np.float32), _c(self.tri_obj, np.uint32), _c(self.tri_mat, np.uint32),
@@ -157,7 +158,7 @@ class FrameScene:
         return CScene(k[0].shape[0], _p(k[0]), _p(k[1]), _p(k[2]), k[3].shape[0], _p(k[3]), _p(k[4]),
                       k[5].shape[0], _p(k[5]), _p(k[6]), _p(k[7]), _p(k[8]), _p(k[9]),
                       self.eps_end, self.eps_close, self.band_verify, self.band_trace, self.radius,
-                      int(self.verify_boxes), self.band_box, *opt)
+                      int(self.verify_boxes), self.band_box, *opt, int(self.energy_test))
 
     def kind(self, l):
         return 0 if self.light_kind is None else int(self.light_kind[l])

@@ -1138,6 +1138,26 @@ static void retrace_path(rctx* c, int64_t p, uint32_t* amb, int* traces) {
         reflect(s, ein, (uint32_t)h.tri, en);
       else
         en[0] = en[1] = en[2] = 0.0f;
+      if (s->energy_test == 1 && c1 * c2 < 0.0) {
+        /* BRDF(Segment, NextSeg) weighted by how the kept direction was       */
+        /* sampled: a diffuse bounce drawn cosine-weighted at the old vertex    */
+        /* carries the albedo; the same next photon reached from the new vertex */
+        /* carries the albedo times the ratio of the kept direction's cosines   */
+        /* at the new and at the old vertex (reading of the cosine ratio)       */
+        double no[3], d3[3];
+        tri_normal(s, vhit(st, p, j + 1), no);
+        sub3(xc, xb, d3);
+        const double l3 = norm3(d3);
+        const double co = l3 > 0.0 ? fabs(dot3(d3, no)) / l3 : 0.0;
+        if (co <= s->band_trace) *amb |= OR_AMB_HEMI;
+        const double ratio = co > 0.0 ? fabs(c2) / co : 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+          en[ch] = (float)((double)en[ch] * ratio);
+          /* Equation 2 near its bound: the kernels form the ratio in FP32 */
+          const double dd = fabs((double)en[ch] - (double)eo[ch]), te = (double)c->T * (double)eo[ch];
+          if (fabs(dd - te) <= 1e-5 * fabs((double)eo[ch])) *amb |= OR_AMB_EQ2;
+        }
+      }
       if (!or_eq2(en, eo, c->T)) {
         /* energies differ: keep the new hit and resample from it */
         float ej[3];

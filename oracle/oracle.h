@@ -52,6 +52,9 @@ typedef struct {
                                 light (cosine-weighted hemisphere), 1 spot light, 2 camera */
   const float* light_param;  /* [L][2]: spot: cos of the cone half-angle; camera: tangents of the
                                 half field of view along u and v */
+  int32_t energy_test;       /* Equation 2's E_N: 0 albedo of the new vertex (arrival side); 1 also
+                                times the ratio of the kept direction's cosines at the new and the
+                                old vertex (BRDF-weighted) */
 } or_scene;
 
 /* light kinds (emission set of a light of zero extent) */
@@ -79,5 +82,6 @@ typedef struct {
 #define OR_AMB_CLOSE 32u
 #define OR_AMB_BOX 64u
 #define OR_AMB_CELL 128u
+#define OR_AMB_EQ2 256u
 
 #endif

@@ -103,6 +103,11 @@ MUTATIONS = {
     "spot_restricted_radius": ("const double rho2 = ((double)ring + u[2]) / (double)nr * s2, rho = sqrt(rho2);",
                                "const double rho2 = ((double)ring + u[2]) / (double)nr, rho = sqrt(rho2);",
                                "uniform_over_cells"),
+    # the cosine ratio of Equation 2's E_N inverted
+    "cosine_ratio_inverted": ("const double ratio = co > 0.0 ? fabs(c2) / co : 0.0;",
+                              "const double ratio = co > 0.0 ? co / fabs(c2) : 0.0;", "cosine_ratio"),
+    # the old vertex's cosine taken along the new vertex's direction (ratio 1)
+    "cosine_ratio_old_direction": ("        sub3(xc, xb, d3);", "        sub3(xc, hp, d3);", "cosine_ratio"),
 }
 
 

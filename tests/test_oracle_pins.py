@@ -1284,3 +1284,86 @@ def test_spot_and_camera_paths_traced_inside_their_emission_and_moved_ones_verif
         else:
             assert f["replace"][p] == 1 and f["reuse"][p] == 0 and f["start"][p] == 0, p
     assert (f["replace"] == 1).sum() > 0 and (f["replace"] == 0).sum() > 0
+
+
+# ---------------------------------------------------------------------------
+# Equation 2 with the BRDF-weighted E_N (energy_test = 1): the albedo of the
+# new vertex times the ratio of the kept direction's cosines at the new and
+# the old vertex
+
+
+def _fig1_low_blocker(albedo_blocker, energy_test):
+    # the first segment is blocked by a slab whose top face lies 0.02 above
+    # the floor, right above the old first photon; the kept second photon on
+    # the right wall is seen from the new first photon at a slightly
+    # different angle
+    orig = [0.5, 0.999, 0.5]
+    photons = [([0.5, 0.0, 0.5], 0), ([1.0, 0.4, 0.5], 7), ([0.6, 0.5, 0.0], 8)]
+    fs = H.box_scene(blockers=[((0.503, -0.03, 0.498), 0.1)], albedo_blocker=albedo_blocker)
+    fs.energy_test = energy_test
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    return fs, st
+
+
+def test_cosine_ratio_energy_test_closed_form():
+    # old vertex (0.5, 0, 0.5) on the floor, new vertex (0.5, 0.02, 0.5) on
+    # the slab's top; both normals +y.  Kept direction towards (1, 0.4, 0.5):
+    # cos_old = 0.4 / |(0.5, 0.4, 0)|, cos_new = 0.38 / |(0.5, 0.38, 0)|.
+    c_old = 0.4 / np.hypot(0.5, 0.4)
+    c_new = 0.38 / np.hypot(0.5, 0.38)
+    r = c_new / c_old
+    assert 0.96 < r < 0.975
+    # blocker albedo 0.72 against the floor's 0.7, threshold 0.005: the plain
+    # albedo test sees 0.72 / 0.7 - 1 = 2.9% and resamples; with the cosine
+    # ratio the reflected energy is 0.72 r / 0.7 - 1 = -0.3%: the tail is kept
+    assert abs(0.72 / 0.7 - 1) > 0.005 and abs(0.72 * r / 0.7 - 1) < 0.005
+    kept, resampled = None, None
+    for et in (1, 0):
+        fs, st = _fig1_low_blocker(0.72, et)
+        before = st.copy()
+        amb, tr = O.retrace(fs, st, 0.005, 1, 1)
+        assert amb[0] == 0
+        assert 10 <= st.hit[0, 0] < 22 and abs(st.pos[0, 0, 1] - 0.02) < 1e-6   # new first photon on the slab
+        d1 = np.linalg.norm(st.pos[1, 0] - before.pos[1, 0])
+        if et == 1:
+            kept = d1
+        else:
+            resampled = d1
+    assert kept < 1e-5          # re-aimed from the new vertex: lands back on the kept photon
+    assert resampled > 1e-3     # a new direction was sampled from the new vertex
+    # the same slab with the floor's albedo: both tests keep the tail when the
+    # ratio stays within T, and the cosine-ratio test resamples when it does not
+    fs, st = _fig1_low_blocker(0.7, 1)
+    before = st.copy()
+    O.retrace(fs, st, 0.05, 1, 1)
+    assert np.linalg.norm(st.pos[1, 0] - before.pos[1, 0]) < 1e-5       # |r - 1| = 3.1% < 5%
+    fs, st = _fig1_low_blocker(0.7, 1)
+    O.retrace(fs, st, 0.02, 1, 1)
+    assert np.linalg.norm(st.pos[1, 0] - before.pos[1, 0]) > 1e-3       # 3.1% > 2%
+
+
+def test_cosine_ratio_energy_test_is_the_albedo_test_on_the_old_plane():
+    # a static frame re-traced with both tests from the same store: paths
+    # whose walks never meet a tilted surface agree, and every accepted reuse
+    # of the cosine-ratio test is valid geometry (no moved triangle crossed)
+    sc, fs1, st = _frame_pair(n_paths=512)
+    moved = _moved_tri_ids(fs1)
+    out = []
+    for et in (0, 1):
+        fs1.energy_test = et
+        s2 = st.copy()
+        amb, _ = O.retrace(fs1, s2, 0.01, sc.seed, 1)
+        out.append((s2, amb))
+        n = O.info_fields(s2.info)["nseg"]
+        for p in range(0, st.n_paths, 5):
+            if amb[p]:
+                continue
+            pts = [s2.origin[p].astype(np.float64)] + [s2.pos[r, p].astype(np.float64) for r in range(n[p])]
+            for j in range(n[p]):
+                assert not B.segment_blocked(fs1.verts, pts[j], pts[j + 1], fs1.eps_end, moved), (et, p, j)
+    # the ratio test differs from the albedo test on some walks, not on all
+    (a, am), (b, bm) = out
+    ok = (am == 0) & (bm == 0)
+    same = np.all(a.hit[:, ok] == b.hit[:, ok], axis=0)
+    assert same.mean() > 0.5
