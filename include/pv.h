@@ -103,7 +103,26 @@ typedef struct {
   float eps_end;                 /* segment endpoint tolerance (scene units) */
   float eps_close;               /* AreClose tolerance of Algorithm 1 (scene units) */
   float photon_radius;           /* radius written into new photons */
+  const int32_t* h_light_kind;   /* NULL (every light PV_LIGHT_AREA), or [n_lights]: the emission of
+                                    a light of zero extent (Section 3.1's spotlight; the camera of
+                                    Section 7's camera paths), PV_ERR_ARG for a nonzero kind with
+                                    nonzero extents or out-of-range parameters */
+  const float* h_light_param;    /* [n_lights][2] with h_light_kind: PV_LIGHT_SPOT {cos of the cone
+                                    half-angle in [0, 1), unused}; PV_LIGHT_CAMERA {tan of the half
+                                    field of view along local u, along local v}, both > 0 */
 } pv_scene_desc;
+
+/* Emission of a light (h_light_kind).  PV_LIGHT_AREA: a rectangle, or a point
+ * light for zero extents, cosine-weighted about the local z axis.
+ * PV_LIGHT_SPOT: a point emitting cosine-weighted inside the cone of
+ * directions within the half-angle about local z.  PV_LIGHT_CAMERA: a point
+ * emitting uniformly over its near plane at unit distance along local z,
+ * |x| <= tan_u, |y| <= tan_v (a pinhole camera whose paths are camera paths;
+ * its distribution map is the pixel grid of that plane).  A moved spot or
+ * camera, like a moved point light, re-aims segment 0 from its new position
+ * at the first photon and keeps the path only when the new direction lies in
+ * its emission set; segment 0 is then tested against every triangle. */
+enum { PV_LIGHT_AREA = 0, PV_LIGHT_SPOT = 1, PV_LIGHT_CAMERA = 2 };
 
 /* Device counters accumulated by the calls that take a pv_stats* (may be
  * NULL).  Zero them (device memory) before the frame if per-frame values are
@@ -276,6 +295,17 @@ pv_status pv_get_tuning(const pv_ctx* ctx, int32_t key, int32_t* value);
  * value. */
 enum { PV_VERIFY_TRIANGLES = 0, PV_VERIFY_BOXES = 1 };
 pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode);
+
+/* Equation 2's E_N in the error-based walk (Algorithm 1's
+ * BRDF(Segment, NextSeg)).  PV_ENERGY_ALBEDO (default): the energy arriving
+ * at the new vertex times its albedo when the kept outgoing direction leaves
+ * on the arrival side, else 0.  PV_ENERGY_COSINE_RATIO: that value times the
+ * ratio of the kept direction's cosine at the new vertex to its cosine at the
+ * old vertex (whose stored triangle gives the normal): a diffuse bounce drawn
+ * cosine-weighted at the old vertex, reached from the new one.  Takes effect
+ * for the context's next re-trace.  PV_ERR_ARG for any other value. */
+enum { PV_ENERGY_ALBEDO = 0, PV_ENERGY_COSINE_RATIO = 1 };
+pv_status pv_set_energy_test(pv_ctx* ctx, int32_t mode);
 
 /* --- distribution maps (Section 3.1) -------------------------------------- */
 

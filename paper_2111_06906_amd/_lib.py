@@ -38,7 +38,8 @@ class SceneDesc(C.Structure):
                 ("n_objects", C.c_uint32), ("h_obj_tris", C.c_void_p), ("h_obj_verts", C.c_void_p),
                 ("h_obj_mat", C.c_void_p), ("n_materials", C.c_uint32), ("h_albedo", C.c_void_p),
                 ("n_lights", C.c_uint32), ("h_light_half", C.c_void_p), ("h_light_power", C.c_void_p),
-                ("eps_end", C.c_float), ("eps_close", C.c_float), ("photon_radius", C.c_float)]
+                ("eps_end", C.c_float), ("eps_close", C.c_float), ("photon_radius", C.c_float),
+                ("h_light_kind", C.c_void_p), ("h_light_param", C.c_void_p)]
 
 
 STAT_FIELDS = ["segments_examined", "paths_invalid", "paths_light_lost", "rays_traced", "photons_written",
@@ -103,6 +104,7 @@ def lib():
         "pv_autotune": ([P, C.POINTER(PathStore), F, U64, U32, P], I32),
         "pv_autotune_report": ([P, P], I32),
         "pv_set_distribution_map": ([P, P], I32),
+        "pv_set_energy_test": ([P, I32], I32),
         "pv_distribution_cells": ([P], U32),
         "pv_update_distribution": ([P, C.POINTER(PathStore), U64, U32, P, P], I32),
     }
@@ -292,6 +294,12 @@ def set_tuning(ctx, key, value):
 
 
 PV_VERIFY_TRIANGLES, PV_VERIFY_BOXES = 0, 1
+PV_LIGHT_AREA, PV_LIGHT_SPOT, PV_LIGHT_CAMERA = 0, 1, 2
+PV_ENERGY_ALBEDO, PV_ENERGY_COSINE_RATIO = 0, 1
+
+
+def set_energy_test(ctx, mode):
+    check(lib().pv_set_energy_test(ctx, mode), ctx)
 
 
 def set_verify_mode(ctx, mode):

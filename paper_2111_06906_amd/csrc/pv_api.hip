@@ -78,6 +78,7 @@ struct pv_ctx {
   pv::LbvhWork lw{};          // scratch of the per-frame object rebuild
   bool object_rebuild = false;  // PV_TUNE_OBJECT_REBUILD
   bool verify_boxes = false;    // pv_set_verify_mode
+  int32_t energy_test = 0;      // pv_set_energy_test
   bool point_lights = false;    // a light of zero extent: verification walks the whole scene
   bool lbvh_used = false;       // a rebuilt hierarchy may be current: stacks sized for it
   std::vector<uint32_t> h_light_paths;  // filled at binding
@@ -799,6 +800,17 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       const float hu = d->h_light_half[2 * l], hv = d->h_light_half[2 * l + 1];
       if (!((hu > 0.0f && hv > 0.0f) || (hu == 0.0f && hv == 0.0f)))
         return fail(ctx, PV_ERR_ARG, "light half extents must both be positive (rectangle) or both 0 (point light)");
+      const int32_t kind = d->h_light_kind ? d->h_light_kind[l] : PV_LIGHT_AREA;
+      if (kind != PV_LIGHT_AREA) {
+        if (kind != PV_LIGHT_SPOT && kind != PV_LIGHT_CAMERA) return fail(ctx, PV_ERR_ARG, "unknown light kind");
+        if (hu != 0.0f || hv != 0.0f) return fail(ctx, PV_ERR_ARG, "spot lights and cameras have zero extents");
+        if (!d->h_light_param) return fail(ctx, PV_ERR_ARG, "light parameters NULL");
+        const float p0 = d->h_light_param[2 * l], p1 = d->h_light_param[2 * l + 1];
+        if (kind == PV_LIGHT_SPOT && !(p0 >= 0.0f && p0 < 1.0f))
+          return fail(ctx, PV_ERR_ARG, "spot cone cosine out of range [0, 1)");
+        if (kind == PV_LIGHT_CAMERA && !(p0 > 0.0f && p1 > 0.0f && std::isfinite(p0) && std::isfinite(p1)))
+          return fail(ctx, PV_ERR_ARG, "camera field-of-view tangents must be positive");
+      }
     }
     if (!(d->eps_end > 0.0f) || !(d->eps_close >= 0.0f)) return fail(ctx, PV_ERR_ARG, "bad tolerances");
     uint64_t n_dyn = 0;
@@ -1012,6 +1024,20 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     CK(upload(A, &hs.top, no_roots, 2, s));
     CK(upload(A, &d_dlocal, dlocal.data(), dlocal.size(), s));
     CK(upload(A, &d_dgid, dgid.data(), dgid.size(), s));
+    {
+      // record of each global triangle id in the leaf-order arrays (the
+      // refit topology's order, which k_transform keeps current)
+      std::vector<uint32_t> grec((size_t)S + n_dyn, 0u);
+      for (uint32_t i = 0; i < S; ++i) {
+        uint32_t g;
+        std::memcpy(&g, &stris[i].t0.w, 4);
+        grec[g] = i;
+      }
+      for (size_t k = 0; k < dgid.size(); ++k) grec[dgid[k]] = S + (uint32_t)k;
+      uint32_t* d_grec;
+      CK(upload(A, &d_grec, grec.data(), grec.size(), s));
+      hs.gid_rec = d_grec;
+    }
     CK(upload(A, &d_lnodes, level_nodes.data(), level_nodes.size(), s));
     CK(upload(A, &d_loff, level_off.data(), level_off.size(), s));
     CK(upload(A, &d_objs, objs.data(), objs.size(), s));
@@ -1066,6 +1092,10 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
       lights[l].half[1] = d->h_light_half[2 * l + 1];
       for (int c = 0; c < 3; ++c) lights[l].power[c] = d->h_light_power[3 * l + c];
       lights[l].path_base = lights[l].path_count = 0;
+      lights[l].kind = d->h_light_kind ? d->h_light_kind[l] : PV_LIGHT_AREA;
+      lights[l].param[0] = lights[l].kind != PV_LIGHT_AREA ? d->h_light_param[2 * l] : 0.0f;
+      lights[l].param[1] = lights[l].kind != PV_LIGHT_AREA ? d->h_light_param[2 * l + 1] : 0.0f;
+      lights[l].pad[0] = lights[l].pad[1] = 0;
     }
     LightDev* d_lights;
     CK(upload(A, &d_lights, lights.data(), lights.size(), s));
@@ -1075,6 +1105,7 @@ pv_status pv_upload_scene(pv_ctx* ctx, const pv_scene_desc* d) {
     CK(dalloc(A, &hs.light_xf_prev, 12 * (size_t)d->n_lights));
     CK(dalloc(A, &hs.light_moved, d->n_lights));
     hs.verify_boxes = ctx->verify_boxes ? 1u : 0u;
+    hs.energy_test = (uint32_t)ctx->energy_test;
     hs.eps_end = d->eps_end;
     hs.eps_close = d->eps_close;
     hs.radius = d->photon_radius;
@@ -1387,6 +1418,18 @@ pv_status pv_set_verify_mode(pv_ctx* ctx, int32_t mode) {
   return PV_OK;
 }
 
+pv_status pv_set_energy_test(pv_ctx* ctx, int32_t mode) {
+  if (!ctx) return PV_ERR_ARG;
+  if (mode != PV_ENERGY_ALBEDO && mode != PV_ENERGY_COSINE_RATIO)
+    return fail(ctx, PV_ERR_ARG, "energy test is PV_ENERGY_ALBEDO or PV_ENERGY_COSINE_RATIO");
+  ctx->energy_test = mode;
+  ctx->hs.energy_test = (uint32_t)mode;
+  if (pv_status w = wait_compaction(ctx)) return w;
+  if (ctx->uploaded)  // stream-ordered after the work already enqueued
+    CK(hipMemcpyAsync(ctx->d_scene, &ctx->hs, sizeof(SceneDev), hipMemcpyHostToDevice, ctx->stream));
+  return PV_OK;
+}
+
 pv_status pv_set_distribution_map(pv_ctx* ctx, const int32_t* h_grid) {
   if (!ctx) return PV_ERR_ARG;
   if (!ctx->uploaded) return fail(ctx, PV_ERR_STATE, "no scene uploaded");
@@ -1407,8 +1450,10 @@ pv_status pv_set_distribution_map(pv_ctx* ctx, const int32_t* h_grid) {
     uint64_t total = 0;
     uint32_t off[PV_MAX_LIGHTS + 1] = {0};
     for (uint32_t l = 0; l < ctx->n_lights; ++l) {
-      const uint64_t c = (uint64_t)(pv::dm_point(lights[l].half) ? 1 : (uint64_t)h_grid[0] * h_grid[1]) *
-                         (uint64_t)h_grid[2] * h_grid[3];
+      const uint64_t c = lights[l].kind == PV_LIGHT_CAMERA
+                             ? (uint64_t)h_grid[0] * h_grid[1]
+                             : (uint64_t)(pv::dm_point(lights[l].half) ? 1 : (uint64_t)h_grid[0] * h_grid[1]) *
+                                   (uint64_t)h_grid[2] * h_grid[3];
       if (c > (1u << 22)) return fail(ctx, PV_ERR_ARG, "more than 2^22 cells for a light (22-bit cell field)");
       off[l] = (uint32_t)total;
       total += c;

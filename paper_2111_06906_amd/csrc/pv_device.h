@@ -100,7 +100,9 @@ struct LightDev {
   float half[2];
   float power[3];
   uint32_t path_base, path_count;
-  uint32_t pad;
+  int32_t kind;     // PV_LIGHT_AREA / PV_LIGHT_SPOT / PV_LIGHT_CAMERA
+  float param[2];   // spot: cos of the cone half-angle; camera: tan of the half field of view along u, v
+  uint32_t pad[2];
 };
 
 struct LeafRec {          // a leaf of a hierarchy built on the host
@@ -165,6 +167,8 @@ struct SceneDev {
   uint32_t* info;
   uint32_t stride, n_paths, B;
   uint32_t verify_boxes;  // 1: a segment that reaches a moved object's box is invalid (no triangle test)
+  uint32_t energy_test;   // Equation 2's E_N: PV_ENERGY_ALBEDO or PV_ENERGY_COSINE_RATIO
+  const uint32_t* gid_rec;  // [T] record of each global triangle id in the leaf-order triangle array
   float eps_end, eps_close, radius;
   uint32_t gpath_base;    // offset of this scene's paths in the work-queue id space
   uint32_t n_blocks;      // path blocks of the bound store
@@ -559,8 +563,14 @@ __device__ inline float3 cosine_local(float u1, float u2) {
 
 __host__ __device__ inline bool dm_point(const float half[2]) { return half[0] == 0.0f && half[1] == 0.0f; }
 
-__host__ __device__ inline uint32_t dm_cells(const float half[2], const int32_t dm[4]) {
+__host__ __device__ inline uint32_t dm_cells(const float half[2], int32_t kind, const int32_t dm[4]) {
+  if (kind == PV_LIGHT_CAMERA) return (uint32_t)dm[0] * (uint32_t)dm[1];  // pixel grid of the near plane
   return (uint32_t)(dm_point(half) ? 1 : dm[0] * dm[1]) * (uint32_t)dm[2] * (uint32_t)dm[3];
+}
+
+// squared radius of a light's direction disk: 1, or sin^2 of a spot's cone
+__device__ inline float dm_disk2(int32_t kind, const float param[2]) {
+  return kind == PV_LIGHT_SPOT ? (1.0f - param[0]) * (1.0f + param[0]) : 1.0f;
 }
 
 // DM_T: a light's paths spread evenly over its cells, the first N mod C
@@ -575,12 +585,21 @@ constexpr float kPiF = 3.14159265358979323846f;
 // -1 when the parametrisation has no value for it (origin off the rectangle,
 // direction not on the emitting side).  xf: the light's 3x4 transform
 // (columns eu, ev, n, centre).
-__device__ inline int32_t dm_cell(const float* xf, const float half[2], const int32_t dm[4], float3 x0,
-                                  float3 w) {
+__device__ inline int32_t dm_cell(const float* xf, const LightDev& lt, const int32_t dm[4], float3 x0, float3 w) {
+  const float* half = lt.half;
   const float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
   const float3 c = f3(xf[3], xf[7], xf[11]);
   float3 n = f3(xf[2], xf[6], xf[10]);
   n = mul(n, 1.0f / length(n));
+  if (lt.kind == PV_LIGHT_CAMERA) {
+    const float z = dot(w, n);
+    if (!(z > 0.0f)) return -1;
+    const float fu = (dot(w, eu) / z + lt.param[0]) / (2.0f * lt.param[0]) * (float)dm[0];
+    const float fv = (dot(w, ev) / z + lt.param[1]) / (2.0f * lt.param[1]) * (float)dm[1];
+    if (!(fu >= 0.0f && fu <= (float)dm[0] && fv >= 0.0f && fv <= (float)dm[1])) return -1;
+    return min((int32_t)floorf(fu), dm[0] - 1) * dm[1] + min((int32_t)floorf(fv), dm[1] - 1);
+  }
+  const float s2 = dm_disk2(lt.kind, lt.param);
   const bool point = dm_point(half);
   const int32_t gu = point ? 1 : dm[0], gv = point ? 1 : dm[1], nr = dm[2], ns = dm[3];
   int32_t iu = 0, iv = 0;
@@ -596,7 +615,9 @@ __device__ inline int32_t dm_cell(const float* xf, const float half[2], const in
   const float x = dot(w, eu), y = dot(w, ev), z = dot(w, n);
   if (!(z > 0.0f)) return -1;
   const float rho2 = x * x + y * y;
-  const int32_t ring = min((int32_t)floorf(rho2 * (float)nr), nr - 1);
+  const float fr = rho2 / s2 * (float)nr;
+  if (lt.kind == PV_LIGHT_SPOT && !(fr <= (float)nr)) return -1;  // outside the cone
+  const int32_t ring = min((int32_t)floorf(fr), nr - 1);
   const float phi = atan2f(y, x);  // [-pi, pi]
   const float fs = (phi + kPiF) / (2.0f * kPiF) * (float)ns;
   const int32_t sector = max(0, min((int32_t)floorf(fs), ns - 1));
@@ -607,12 +628,23 @@ __device__ inline int32_t dm_cell(const float* xf, const float half[2], const in
 // sampling restricted to the cell): position uniform in the cell's part of
 // the rectangle, disk point uniform in the cell's ring (in x^2 + y^2) and
 // sector (in angle), lifted to the hemisphere; u: one Philox draw (tag 0).
-__device__ inline void dm_sample(const float* xf, const float half[2], const int32_t dm[4], uint32_t cell,
+__device__ inline void dm_sample(const float* xf, const LightDev& lt, const int32_t dm[4], uint32_t cell,
                                  const float u[4], float3* x0, float3* w) {
+  const float* half = lt.half;
   const float3 eu = f3(xf[0], xf[4], xf[8]), ev = f3(xf[1], xf[5], xf[9]);
   const float3 c = f3(xf[3], xf[7], xf[11]);
   float3 n = f3(xf[2], xf[6], xf[10]);
   n = mul(n, 1.0f / length(n));
+  if (lt.kind == PV_LIGHT_CAMERA) {
+    // uniform in the pixel's part of the near plane
+    const uint32_t iu = cell / (uint32_t)dm[1], iv = cell % (uint32_t)dm[1];
+    const float x = -lt.param[0] + ((float)iu + u[0]) * (2.0f * lt.param[0] / (float)dm[0]);
+    const float y = -lt.param[1] + ((float)iv + u[1]) * (2.0f * lt.param[1] / (float)dm[1]);
+    *x0 = c;
+    *w = mul(add(add(mul(eu, x), mul(ev, y)), n), 1.0f / sqrtf(x * x + y * y + 1.0f));
+    return;
+  }
+  const float s2 = dm_disk2(lt.kind, lt.param);
   const bool point = dm_point(half);
   const uint32_t gu = point ? 1u : (uint32_t)dm[0], gv = point ? 1u : (uint32_t)dm[1];
   const uint32_t nr = (uint32_t)dm[2], ns = (uint32_t)dm[3];
@@ -625,7 +657,7 @@ __device__ inline void dm_sample(const float* xf, const float half[2], const int
     const float b = -half[1] + ((float)iv + u[1]) * (2.0f * half[1] / (float)gv);
     *x0 = add(c, add(mul(eu, a), mul(ev, b)));
   }
-  const float rho2 = ((float)ring + u[2]) / (float)nr, rho = sqrtf(rho2);
+  const float rho2 = ((float)ring + u[2]) / (float)nr * s2, rho = sqrtf(rho2);
   const float phi = -kPiF + ((float)sector + u[3]) * (2.0f * kPiF / (float)ns);
   const float lx = rho * cosf(phi), ly = rho * sinf(phi), lz = sqrtf(fmaxf(1.0f - rho2, 0.0f));
   *w = add(add(mul(eu, lx), mul(ev, ly)), mul(n, lz));

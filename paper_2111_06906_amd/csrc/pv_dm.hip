@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_dm_count(const SceneDev* __restrict_
         const float len = length(d);
         const float* xf = G(S.light_xf_cur) + 12 * l;
         const LightDev lt = G(S.lights)[l];
-        const int32_t c = len > 0.0f ? dm_cell(xf, lt.half, S.dm, x0, mul(d, 1.0f / len)) : -1;
+        const int32_t c = len > 0.0f ? dm_cell(xf, lt, S.dm, x0, mul(d, 1.0f / len)) : -1;
         ok = c >= 0;
         if (ok) {
           cell = (uint32_t)c;

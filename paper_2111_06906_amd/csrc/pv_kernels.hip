@@ -457,7 +457,17 @@ __device__ inline bool light_update(const SceneDev& S, int l, float3 x0, float3 
   const PV_GLOBAL LightDev* lt = G(S.lights) + l;
   if (lt->half[0] == 0.0f && lt->half[1] == 0.0f) {
     const float3 w = sub(x1, c);
-    if (!(dot(w, w) > S.eps_end * S.eps_end) || !(dot(w, n) > 0.0f)) return false;
+    const float z = dot(w, n);
+    if (!(dot(w, w) > S.eps_end * S.eps_end) || !(z > 0.0f)) return false;
+    const int32_t kind = lt->kind;
+    if (kind == PV_LIGHT_SPOT) {
+      // inside the cone: z / |w| >= cos of the half-angle
+      if (!(z * __builtin_amdgcn_rsqf(dot(w, w) * dot(n, n)) >= lt->param[0])) return false;
+    } else if (kind == PV_LIGHT_CAMERA) {
+      // through the near plane: |u / z| <= tan_u, |v / z| <= tan_v (n unit length)
+      const float zn = z * __builtin_amdgcn_rsqf(dot(n, n));
+      if (!(fabsf(dot(w, eu)) <= lt->param[0] * zn && fabsf(dot(w, ev)) <= lt->param[1] * zn)) return false;
+    }
     *out = c;
     *vis = true;
     return true;
@@ -1297,14 +1307,26 @@ __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t fram
     float u[4];
     draw4(seed, L.p, frame, 0, 0, u);
     float3 x0;
+    const LightDev ld = *lt;
     if (S.dm[0] > 0) {
       // distribution maps: the sample is drawn inside the path's cell
-      const LightDev lc = *lt;
-      dm_sample((const float*)xf, lc.half, S.dm, L.cell, u, &x0, &L.w);
+      dm_sample((const float*)xf, ld, S.dm, L.cell, u, &x0, &L.w);
+    } else if (ld.kind == PV_LIGHT_CAMERA) {
+      // uniform over the near plane at unit distance
+      const float x = (2.0f * u[0] - 1.0f) * ld.param[0], y = (2.0f * u[1] - 1.0f) * ld.param[1];
+      x0 = c;
+      L.w = mul(add(add(mul(eu, x), mul(ev, y)), nl), 1.0f / sqrtf(x * x + y * y + 1.0f));
     } else {
-      float a = (2.0f * u[0] - 1.0f) * lt->half[0], b = (2.0f * u[1] - 1.0f) * lt->half[1];
+      float a = (2.0f * u[0] - 1.0f) * ld.half[0], b = (2.0f * u[1] - 1.0f) * ld.half[1];
       x0 = add(c, add(mul(eu, a), mul(ev, b)));
       float3 lc = cosine_local(u[2], u[3]);
+      if (ld.kind == PV_LIGHT_SPOT) {
+        // the disk point scaled to the cone's radius, then lifted
+        const float sr = sqrtf((1.0f - ld.param[0]) * (1.0f + ld.param[0]));
+        lc.x *= sr;
+        lc.y *= sr;
+        lc.z = sqrtf(fmaxf(1.0f - (lc.x * lc.x + lc.y * lc.y), 0.0f));
+      }
       L.w = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
     }
     const size_t stride = S.stride;
@@ -1514,6 +1536,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
         float c2 = l2 > 0.0f ? dot(d2, nh) / l2 : 0.0f;
         uint32_t mat = hit_material(S, h);
         float3 en = (c1 * c2 < 0.0f) ? reflect_energy(S, ej, mat) : f3(0.0f, 0.0f, 0.0f);
+        if (S.energy_test == PV_ENERGY_COSINE_RATIO && c1 * c2 < 0.0f) {
+          // the kept direction's cosine at the new vertex over the one at the
+          // old vertex (its stored triangle, from x_{j+1} to x_{j+2})
+          const Tri to = G(S.tris)[G(S.gid_rec)[vertex_hit(S, L.p, L.j + 1)]];
+          const float3 no = cross(sub(xyz(to.t1), xyz(to.t0)), sub(xyz(to.t2), xyz(to.t0)));
+          const float3 d3 = sub(xc, vertex(S, L.p, L.j + 1));
+          const float den = fabsf(dot(d3, no)), num = fabsf(c2) * length(d3) * length(no);
+          const float ratio = den > 0.0f ? num / den : 0.0f;
+          en = mul(en, ratio);
+        }
         float3 eo = energy_row(S, L.p, L.j + 1);
         if (!eq2(en, eo, T)) {
           // energies differ: keep the new hit and re-sample the rest

@@ -113,10 +113,13 @@ class Context:
         alb = np.ascontiguousarray(sc.albedo, np.float32)
         lh = np.ascontiguousarray(sc.light_half, np.float32)
         lp = np.ascontiguousarray(sc.light_power, np.float32)
-        self._keep = (sv, sm, ot, ov, om, alb, lh, lp)
+        lk = None if sc.light_kind is None else np.ascontiguousarray(sc.light_kind, np.int32)
+        lq = None if sc.light_param is None else np.ascontiguousarray(sc.light_param, np.float32)
+        self._keep = (sv, sm, ot, ov, om, alb, lh, lp, lk, lq)
         desc = L.SceneDesc(sv.shape[0], _np_ptr(sv), _np_ptr(sm), len(sc.obj_local), _np_ptr(ot), _np_ptr(ov),
                            _np_ptr(om), alb.shape[0], _np_ptr(alb), lh.shape[0], _np_ptr(lh), _np_ptr(lp),
-                           sc.eps_end, sc.eps_close, sc.photon_radius)
+                           sc.eps_end, sc.eps_close, sc.photon_radius,
+                           None if lk is None else _np_ptr(lk), None if lq is None else _np_ptr(lq))
         L.upload_scene(self.ctx, desc)
 
     def close(self):
@@ -238,6 +241,10 @@ class Context:
     def set_verify_mode(self, boxes):
         """Section 3.2's conservative box test (True) or the triangle test (False)."""
         L.set_verify_mode(self.ctx, L.PV_VERIFY_BOXES if boxes else L.PV_VERIFY_TRIANGLES)
+
+    def set_energy_test(self, cosine_ratio):
+        """Equation 2's E_N: the albedo test (False) or the cosine-ratio test (True)."""
+        L.set_energy_test(self.ctx, L.PV_ENERGY_COSINE_RATIO if cosine_ratio else L.PV_ENERGY_ALBEDO)
 
     def set_distribution_map(self, grid):
         """Section 3.1's distribution maps with grid (gu, gv, rings, sectors), or None."""

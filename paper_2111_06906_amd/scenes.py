@@ -62,6 +62,8 @@ class Scene:
     eps_close: float = 1e-4
     photon_radius: float = 0.01
     meta: dict = field(default_factory=dict)
+    light_kind: object = None         # None (every light a rectangle / point), or int32 [L]: 0, 1 spot, 2 camera
+    light_param: object = None        # float32 [L, 2]: spot (cos of the cone half-angle, 0); camera (tan u, tan v)
 
     @property
     def n_frames(self) -> int:
@@ -311,7 +313,8 @@ def _tess_count(panels, boxes, h):
 
 def make_rooms(name, nx, nz, static_target, n_dyn, torus_segs, n_paths, max_bounces,
                frames, threshold, seed, n_lights=2, lights_move=False,
-               torus_size=(0.16, 0.055), clutter_per_room=2, point_lights=False):
+               torus_size=(0.16, 0.055), clutter_per_room=2, point_lights=False, light_kind=0,
+               light_param=(0.0, 0.0)):
     rng = np.random.default_rng(seed)
     panels, wx, wz = _room_panels(nx, nz, rng)
     boxes = _clutter(nx, nz, clutter_per_room, rng)
@@ -346,7 +349,9 @@ def make_rooms(name, nx, nz, static_target, n_dyn, torus_segs, n_paths, max_boun
     order = rng.permutation(len(rooms))
     light_rooms = [rooms[j] for j in order[:n_lights]]
     y_light = 0.25 - (0.02 if lights_move else 0.001)
-    # rectangles of 0.1 x 0.1, or points (both half extents 0)
+    # rectangles of 0.1 x 0.1, or points (both half extents 0); spot lights
+    # and cameras (light_kind 1, 2) are points with a cone / near plane
+    point_lights = point_lights or light_kind != 0
     light_half = np.full((n_lights, 2), 0.0 if point_lights else 0.05, F32)
     light_power = np.ones((n_lights, 3), F32)
     lpos = np.array([[-1 + (i + 0.5) * wx, y_light, -1 + (k + 0.5) * wz] for i, k in light_rooms])
@@ -409,7 +414,9 @@ def make_rooms(name, nx, nz, static_target, n_dyn, torus_segs, n_paths, max_boun
         light_power=light_power, light_xforms=lxf, light_paths=per_light,
         max_bounces=max_bounces, threshold=threshold, seed=seed,
         meta={"static_tris": int(static.shape[0]), "dynamic_tris": int(sum(o.shape[0] for o in obj_local)),
-              "rooms": [nx, nz], "lights_move": bool(lights_move), "cell": h})
+              "rooms": [nx, nz], "lights_move": bool(lights_move), "cell": h},
+        light_kind=None if light_kind == 0 else np.full(n_lights, light_kind, np.int32),
+        light_param=None if light_kind == 0 else np.tile(np.asarray(light_param, F32), (n_lights, 1)))
 
 
 def make_mid(n_paths=1_000_000, frames=10, threshold=-1.0, seed=2, static_target=50_000):

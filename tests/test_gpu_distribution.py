@@ -137,6 +137,17 @@ def test_distribution_maps_point_lights(E):
     assert _run(E, sc, 3, 0.01, "dm point lights", grid=(1, 1, 4, 16)) >= 1
 
 
+@pytest.mark.parametrize("kind,param,grid", [(1, (0.8, 0.0), (1, 1, 3, 8)), (2, (0.6, 0.4), (8, 6, 1, 1))],
+                         ids=["spot", "camera"])
+def test_distribution_maps_spot_lights_and_cameras(E, kind, param, grid):
+    # a spot light's cells cover its cone; a camera's are the pixels of its
+    # near plane (Section 7: the map on the camera's near plane behaves like
+    # a spotlight's)
+    sc = scenes.make_rooms("dm%d" % kind, 3, 3, 20_000, 3, (40, 16), 4096 + 9, 5, 3, 0.01, 17, n_lights=2,
+                           lights_move=True, light_kind=kind, light_param=param)
+    assert _run(E, sc, 3, 0.01, "dm kind %d" % kind, grid=grid) >= 1
+
+
 def test_distribution_maps_full_size_first_frame(E):
     # the measured workload with maps: after the first frame every cell of
     # both lights holds exactly its target, and a following frame keeps the

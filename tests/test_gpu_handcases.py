@@ -57,7 +57,7 @@ def _light_shift(dx, dy=0.0):
     return xf
 
 
-def run_case(E, label, paths, T=None, boxes=False, **scene_kw):
+def run_case(E, label, paths, T=None, boxes=False, energy_test=0, **scene_kw):
     """Verify (and re-trace with threshold T, unless None) the hand-built paths
     on the device and in the oracle; compare outside the decision bands.
     Returns (oracle store after verify, oracle store at the end, device store
@@ -66,9 +66,11 @@ def run_case(E, label, paths, T=None, boxes=False, **scene_kw):
     sc = HS.device_scene(n_paths=len(paths), max_bounces=B, **scene_kw)
     fs = O.frame_scene(sc, 1, 0)
     fs.verify_boxes = int(boxes)
+    fs.energy_test = int(energy_test)
     ora = HS.store_from_paths(paths, B)
     ctx = E.Context(sc)
     ctx.set_verify_mode(boxes)
+    ctx.set_energy_test(bool(energy_test))
     ctx.frame_begin(0)
     st = ctx.new_store()
     st.load_numpy(H.from_oracle(ora))
@@ -257,3 +259,20 @@ def test_device_scene_equals_oracle_hand_scene():
         for k in ("verts", "tri_obj", "tri_mat", "obj_moved", "albedo", "light_xf", "light_half",
                   "light_power", "light_moved", "light_base"):
             assert np.array_equal(np.asarray(getattr(a, k)), np.asarray(getattr(b, k))), k
+
+
+@pytest.mark.gpu
+def test_cosine_ratio_energy_test_closed_form(E):
+    # first segment blocked by a slab 0.02 above the floor, albedo 0.72
+    # against the floor's 0.7: with T = 0.5% the albedo test resamples the
+    # tail, while the cosine ratio (0.968) keeps it and re-aims the second
+    # photon from the new first one
+    path = _fig1_path()
+    blk = [((0.503, -0.03, 0.498), 0.1)]
+    v, o, g, av, ar, s = run_case(E, "cosine ratio: kept", [path], 0.005, energy_test=1, blockers=blk,
+                                  albedo_blocker=0.72)
+    assert av[0] == 0 and ar[0] == 0
+    assert 10 <= g["hit"][0, 0] < 22 and np.linalg.norm(g["pos"][1, 0] - np.array(path[1][1][0])) < 1e-5
+    v, o, g, av, ar, s = run_case(E, "cosine ratio: albedo test resamples", [path], 0.005, energy_test=0,
+                                  blockers=blk, albedo_blocker=0.72)
+    assert np.linalg.norm(g["pos"][1, 0] - np.array(path[1][1][0])) > 1e-3

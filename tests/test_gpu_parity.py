@@ -166,13 +166,14 @@ def test_max_bounces_fifteen(E):
 # the oracle's store of the previous frame)
 
 
-def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False):
+def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False, energy_test=0):
     ora, _ = _oracle_frame0(sc)
     ctx = E.Context(sc)
     if tuning:
         ctx.set_tuning(**tuning)
     if boxes:
         ctx.set_verify_mode(True)
+    ctx.set_energy_test(bool(energy_test))
     ctx.frame_begin(0)
     st = ctx.new_store()
     total_rep = 0
@@ -184,6 +185,7 @@ def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False):
         gv = st.to_numpy()
         fs = O.frame_scene(sc, f, f - 1)
         fs.verify_boxes = int(boxes)
+        fs.energy_test = int(energy_test)
         ambv, _ = O.verify(fs, ora)
         ok = _amb_ok(ambv)  # both sides start this frame from the same oracle store
         assert np.array_equal(gv["info"][ok], ora.info[ok])
@@ -214,6 +216,15 @@ def test_mid_rooms_lockstep_error_based(E):
 def test_paper_rooms_moving_lights(E):
     sc = scenes.make_paper(n_paths=4096 + 13, frames=3)
     _lockstep(E, sc, 3, 0.01, "paper")
+
+
+def test_cosine_ratio_energy_test_lockstep(E):
+    # Equation 2 with the BRDF-weighted E_N (cosine ratio of the kept
+    # direction) in the error-based walk, mid and paper-scale generators
+    sc = scenes.make_mid(n_paths=6000 + 19, frames=4, threshold=0.01)
+    _lockstep(E, sc, 4, 0.01, "mid, cosine ratio", energy_test=1)
+    sc = scenes.make_paper(n_paths=4096 + 13, frames=3)
+    _lockstep(E, sc, 3, 0.01, "paper, cosine ratio", energy_test=1)
 
 
 def test_objects_only_scene(E):
@@ -308,6 +319,42 @@ def test_point_lights_edge_cases(E):
     for f in range(3):
         sc.light_xforms[f, :, 3] += np.float32(0.004 * f)
     _lockstep(E, sc, 3, 0.01, "objects only, point light")
+
+
+@pytest.mark.parametrize("kind,param", [(1, (0.8, 0.0)), (2, (0.6, 0.4))], ids=["spot", "camera"])
+def test_spot_lights_and_cameras_lockstep(E, kind, param):
+    # Section 3.1's spotlight (cosine-weighted inside a cone) and Section 7's
+    # camera (uniform over its near plane): the frame-0 trace (their own
+    # samples) and moving frames in lockstep (re-aimed segment 0 kept only
+    # inside the new emission set, then tested against every triangle)
+    label = "spot" if kind == 1 else "camera"
+    sc = scenes.make_rooms(label, 3, 3, 20000, 4, (24, 12), 6000 + 11, 5, 3, 0.01, 21,
+                           lights_move=True, light_kind=kind, light_param=param)
+    fs0 = O.frame_scene(sc, 0)
+    ora, amb0, _ = O.initial_trace(fs0, sc.n_paths, sc.max_bounces, sc.seed)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    ctx.initial_trace(st, sc.seed, 0)
+    g = st.to_numpy()
+    ok = amb0 == 0
+    H.check_excluded((~ok).sum(), sc.n_paths, "%s frame0" % label, H.sampled_budget(H.PAPER_FULL_TRACE_RATE, sc.n_paths))
+    H.compare_stores(g, ora, ok, "%s frame0" % label, fs0.verts, (~ok).sum())
+    ctx.close()
+    _lockstep(E, sc, 3, 0.01, "%s lights" % label)
+    _lockstep(E, sc, 3, -1.0, "%s lights, naive" % label)
+
+
+def test_spot_and_camera_parameters_checked(E):
+    from paper_2111_06906_amd import _lib as L
+    for kind, param, half in ((1, (1.0, 0.0), 0.0), (1, (-0.1, 0.0), 0.0), (2, (0.5, 0.0), 0.0), (2, (0.5, 0.5), 0.1),
+                              (3, (0.5, 0.5), 0.0)):
+        sc = scenes.make_tiny(n_paths=1024)
+        sc.light_half[0] = (half, half)
+        sc.light_kind = np.array([kind], np.int32)
+        sc.light_param = np.array([param], np.float32)
+        with pytest.raises(L.PVError) as e:
+            E.Context(sc)
+        assert e.value.code == L.PV_ERR_ARG, (kind, param, half)
 
 
 def test_light_extents_and_verify_mode_checked(E):
