@@ -1696,8 +1696,11 @@ __global__ __launch_bounds__(kBlock) void k_energy_fwd(const SceneDev* __restric
 // Phi/N * P_j) and R_i = g_{i+1} + rho_{i+1} R_{i+1} (R_{n-1} = 0, photon
 // rows 0..n-1, vertex i = row i), the contribution of vertex i to the
 // albedo gradient is Phi/N * P_i * R_i (division free), and the power
-// gradient is sum_j g_j P_j / N.  Block partials (LDS atomics) go to
-// partial[block][M*3 + L*3] for a deterministic FP64 reduction.
+// gradient is sum_j g_j P_j / N.  Block partials go to
+// partial[block][M*3 + L*3], which a fixed-order FP64 reduction sums across
+// blocks; inside a block the contributions meet in FP32 LDS atomics, whose
+// order follows the scheduling, so the gradients agree from run to run only
+// to FP32 rounding of those sums, not bit for bit.
 __global__ __launch_bounds__(kBlock) void k_energy_bwd(const SceneDev* __restrict__ scenes, const uint2* __restrict__ tiles,
                                                        const float* __restrict__ albedo, const float* __restrict__ power,
                                                        const float* __restrict__ gE, uint32_t n_mat,
