@@ -140,8 +140,8 @@ def headline_graph(args, engine, sc, torch, np, T, tuning):
         stats.zero_()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for f in range(2, 2 + K):
-            frame(f, stats)
+        for i in range(K):
+            frame(1 + (1 + i) % max(1, sc.n_frames - 1), stats)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         seg = ctx.stats_dict(stats)["segments_examined"]
