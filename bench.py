@@ -107,19 +107,24 @@ def set_tuning(ctx, tuning):
 
 def headline_graph(args, engine, sc, torch, np, T, tuning):
     """The measured workload itself in the batched form: the whole frame of
-    the one scene captured in a HIP graph and replayed, against the plain
+    the one scene captured in a HIP graph and replayed, and all the timed
+    frames captured in one graph and launched once, against the plain
     per-frame calls, from identical frame-0 stores (stores compared bit for
     bit after the timed frames)."""
     K = args.headline_graph_frames
     seed = sc.seed
+    consecutive = 1 + K <= sc.n_frames - 1  # frames 2 .. K + 1 exist (one launch runs consecutive frames)
     runs = []
-    for graph in (False, True):
+    for mode in ("plain", "graph", "frames"):
+        if mode == "frames" and not consecutive:
+            runs.append(None)
+            continue
         ctx = engine.Context(sc)
         set_tuning(ctx, tuning)
         st = ctx.new_store()
         ctx.frame_begin(0)
         ctx.initial_trace(st, seed, 0)
-        b = engine.Batch([ctx], [st], T, seed) if graph else None
+        b = engine.Batch([ctx], [st], T, seed) if mode != "plain" else None
         cap = sc.n_paths * sc.max_bounces
         o = (torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
              torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
@@ -127,7 +132,7 @@ def headline_graph(args, engine, sc, torch, np, T, tuning):
         stats = ctx.new_stats()
 
         def frame(f, s=None):
-            if graph:
+            if b is not None:
                 b.frame(f, s)
             else:
                 ctx.frame_begin(f)
@@ -137,11 +142,23 @@ def headline_graph(args, engine, sc, torch, np, T, tuning):
 
         frame(1, stats)  # warm-up (graph capture)
         torch.cuda.synchronize()
+        if mode == "frames":
+            # capture the K-frame graph outside the timed region, then return
+            # to the state after frame 1: transforms of frame 1 (one more
+            # frame 1), the store as it was
+            snap = st.to_numpy()
+            b.frames(2, K, stats)
+            frame(1, stats)
+            torch.cuda.synchronize()
+            st.load_numpy(snap)
         stats.zero_()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for i in range(K):
-            frame(1 + (1 + i) % max(1, sc.n_frames - 1), stats)
+        if mode == "frames":
+            b.frames(2, K, stats)
+        else:
+            for i in range(K):
+                frame(1 + (1 + i) % max(1, sc.n_frames - 1), stats)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         seg = ctx.stats_dict(stats)["segments_examined"]
@@ -149,10 +166,17 @@ def headline_graph(args, engine, sc, torch, np, T, tuning):
         if b is not None:
             b.close()
         ctx.close()
-    (pm, ps, sp), (bm, bs, sb) = runs
+    (pm, ps, sp), (bm, bs, sb) = runs[0], runs[1]
     same = all(np.array_equal(sp[k].view(np.uint32), sb[k].view(np.uint32)) for k in sp)
-    return {"frames_timed": K, "plain_ms_per_frame": pm, "graph_ms_per_frame": bm, "plain_segments_per_s": ps,
-            "graph_segments_per_s": bs, "speedup": pm / bm, "stores_bit_identical": bool(same)}
+    res = {"frames_timed": K, "plain_ms_per_frame": pm, "graph_ms_per_frame": bm, "plain_segments_per_s": ps,
+           "graph_segments_per_s": bs, "speedup": pm / bm, "stores_bit_identical": bool(same)}
+    if runs[2] is not None:
+        fm, fs, sf = runs[2]
+        res.update({"frames_per_launch": K, "one_launch_ms_per_frame": fm, "one_launch_segments_per_s": fs,
+                    "one_launch_speedup": pm / fm,
+                    "one_launch_stores_bit_identical": bool(all(np.array_equal(sp[k].view(np.uint32),
+                                                                               sf[k].view(np.uint32)) for k in sp))})
+    return res
 
 
 def cache_resident_mid(engine, scenes, torch, tuning):

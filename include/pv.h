@@ -442,6 +442,26 @@ void pv_batch_destroy(pv_batch* b);
  * d_stats) captures the frame into a HIP graph; later calls replay it, with
  * the frame number read from device memory.  Never synchronises. */
 pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats);
+/* Frames first_frame .. first_frame + k - 1 of every scene, in order, with one
+ * graph launch (the batched form over frames as well as scenes: each frame is
+ * the sequence pv_batch_frame runs, Sections 3.2 and 3.3 in turn, and a frame
+ * verifies the paths the one before it wrote).  d_obj_xf / d_light_xf are
+ * host arrays of k * n device pointers, frame-major (frame f of scene i at
+ * [f * n + i]), each a transform array of pv_frame_begin's layout; a scene
+ * without objects may pass NULL for its object arrays.  The tables and frame
+ * numbers are copied (stream-ordered) before the launch, so the caller may
+ * reuse the host arrays at once; the device arrays they point to must hold
+ * their transforms until the launch has run.  The graph is captured on the
+ * first call and again when k or d_stats changes (a larger k than any before
+ * also synchronises the batch's stream once, to grow the tables); later calls
+ * replay it.  Photon compaction runs in every frame, so the buffer that
+ * pv_batch_copy_photons reads holds the last frame's photons.  Results are
+ * bit-identical to k calls of pv_batch_frame.  1 <= k <= PV_BATCH_MAX_FRAMES,
+ * else PV_ERR_ARG; a NULL table or a NULL light array (or object array of a
+ * scene with objects) is PV_ERR_ARG.  Never synchronises otherwise. */
+#define PV_BATCH_MAX_FRAMES 1024u
+pv_status pv_batch_frames(pv_batch* b, uint32_t first_frame, uint32_t k, const float* const* d_obj_xf,
+                          const float* const* d_light_xf, pv_stats* d_stats);
 /* Point the batch at other per-scene transform arrays for the next frames
  * (host arrays of n device pointers, copied; stream-ordered, no
  * synchronisation, no graph re-capture: the frame reads the pointer tables

@@ -113,6 +113,7 @@ def lib():
         "pv_batch_create": ([C.POINTER(P), P, P, U32, P, P, F, U64], I32),
         "pv_batch_destroy": ([P], None),
         "pv_batch_frame": ([P, U32, P], I32),
+        "pv_batch_frames": ([P, U32, U32, P, P, P], I32),
         "pv_batch_copy_photons": ([P, P, P, U32, P], I32),
         "pv_batch_set_transforms": ([P, P, P], I32),
     })
@@ -266,6 +267,13 @@ def batch_destroy(b):
 
 def batch_frame(b, frame, d_stats=None, owner=None):
     check(lib().pv_batch_frame(b, frame, d_stats), owner)
+
+
+def batch_frames(b, first_frame, k, d_obj_xf, d_light_xf, d_stats=None, owner=None):
+    """d_obj_xf / d_light_xf: k * n device pointers, frame-major."""
+    oarr = (C.c_void_p * len(d_obj_xf))(*d_obj_xf)
+    larr = (C.c_void_p * len(d_light_xf))(*d_light_xf)
+    check(lib().pv_batch_frames(b, first_frame, k, oarr, larr, d_stats), owner)
 
 
 def batch_copy_photons(b, d_pos, d_energy, capacity, d_base, owner=None):

@@ -149,7 +149,21 @@ struct pv_batch {
   pv_stats* captured_stats = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // several frames per launch (pv_batch_frames): frame numbers and per-frame
+  // transform pointer tables, and the graph of that many frames
+  std::vector<uint32_t> n_obj;  // objects of each scene
+  Alloc tab_mem;
+  uint32_t tab_frames = 0;      // frames the tables hold
+  uint32_t* d_frames = nullptr;
+  const float** d_obj_tab = nullptr;
+  const float** d_light_tab = nullptr;
+  uint32_t multi_k = 0;         // frames of the captured graph (0: none)
+  pv_stats* multi_stats = nullptr;
+  hipGraph_t multi_graph = nullptr;
+  hipGraphExec_t multi_exec = nullptr;
   ~pv_batch() {
+    if (multi_exec) (void)hipGraphExecDestroy(multi_exec);
+    if (multi_graph) (void)hipGraphDestroy(multi_graph);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -1879,10 +1893,13 @@ pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const floa
 // ---------------------------------------------------------------------------
 // batched form: every phase of a frame is one launch over all scenes
 
-static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
+// one frame of every scene on the batch's capture stream: transforms from the
+// device pointer tables obj_in / light_in, frame number from frame_ptr
+static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats, const float* const* obj_in,
+                               const float* const* light_in, const uint32_t* frame_ptr) {
   pv_ctx* ctx = b->owner;
   hipStream_t st = b->cap_stream;
-  CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, b->d_obj_in, b->d_light_in, st));
+  CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, obj_in, light_in, st));
   CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, b->d_xf_tiles, b->n_xf_tiles, st));
   CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_gbase, (int)b->n, b->vw, b->d_block_cnt,
@@ -1890,7 +1907,7 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats) {
   CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_scan_tmp, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->T, b->seed, 0,
-                        b->d_frame, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
+                        frame_ptr, d_stats, (uint32_t)(ctx->n_cu * ctx->retrace_blocks_per_cu), ctx->retrace_variant,
                         b->stack_entries, ctx->walk_min_active, b->ow, st));
   CK(pv::launch_photon_count(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_pcounts, st));
   CK(pv::launch_scan(b->d_pcounts, b->d_poffsets, b->n_counts, b->d_ptotal, b->d_scan_tmp, st));
@@ -1936,6 +1953,7 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       if (st->max_bounces < 1 || st->max_bounces > PV_MAX_BOUNCES) return bad("max_bounces out of range");
       if (st->stride < st->n_paths || st->stride % 64 != 0) return bad("bad stride");
       if ((c->n_objects && !d_obj_xf[i]) || !d_light_xf[i]) return bad("transform array is NULL");
+      b->n_obj.push_back(c->n_objects);
       uint32_t lp = 0;
       for (uint32_t l = 0; l < c->n_lights; ++l) lp += c->h_light_paths[l];
       if (lp != st->n_paths) return bad("light path counts do not add up to n_paths");
@@ -2043,7 +2061,7 @@ pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats) {
       b->graph = nullptr;
     }
     CK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    pv_status st = batch_enqueue(b, d_stats);
+    pv_status st = batch_enqueue(b, d_stats, b->d_obj_in, b->d_light_in, b->d_frame);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (st != PV_OK) {
@@ -2057,6 +2075,68 @@ pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats) {
     b->captured_stats = d_stats;
   }
   CK(hipGraphLaunch(b->exec, b->cap_stream));
+  CK(hipEventRecord(b->ev_out, b->cap_stream));
+  CK(hipStreamWaitEvent(b->stream, b->ev_out, 0));
+  return PV_OK;
+}
+
+pv_status pv_batch_frames(pv_batch* b, uint32_t first_frame, uint32_t k, const float* const* d_obj_xf,
+                          const float* const* d_light_xf, pv_stats* d_stats) {
+  if (!b) return PV_ERR_ARG;
+  pv_ctx* ctx = b->owner;
+  if (k == 0 || k > PV_BATCH_MAX_FRAMES) return fail(ctx, PV_ERR_ARG, "frame count out of range");
+  if (!d_obj_xf || !d_light_xf) return fail(ctx, PV_ERR_ARG, "NULL transform table");
+  for (uint32_t f = 0; f < k; ++f)
+    for (uint32_t i = 0; i < b->n; ++i)
+      if ((b->n_obj[i] && !d_obj_xf[(size_t)f * b->n + i]) || !d_light_xf[(size_t)f * b->n + i])
+        return fail(ctx, PV_ERR_ARG, "transform array is NULL");
+  if (first_frame > UINT32_MAX - (k - 1)) return fail(ctx, PV_ERR_ARG, "frame numbers overflow");
+  if (k > b->tab_frames) {
+    // larger tables: nothing captured may still read the old ones
+    CK(hipStreamSynchronize(b->cap_stream));
+    if (b->multi_exec) CK(hipGraphExecDestroy(b->multi_exec));
+    if (b->multi_graph) CK(hipGraphDestroy(b->multi_graph));
+    b->multi_exec = nullptr;
+    b->multi_graph = nullptr;
+    b->multi_k = 0;
+    b->tab_mem.release();
+    b->tab_frames = 0;
+    CK(dalloc(b->tab_mem, &b->d_frames, k));
+    CK(dalloc(b->tab_mem, &b->d_obj_tab, (size_t)k * b->n));
+    CK(dalloc(b->tab_mem, &b->d_light_tab, (size_t)k * b->n));
+    b->tab_frames = k;
+  }
+  std::vector<uint32_t> frames(k);
+  for (uint32_t f = 0; f < k; ++f) frames[f] = first_frame + f;
+  CK(hipMemcpyAsync(b->d_frames, frames.data(), sizeof(uint32_t) * k, hipMemcpyHostToDevice, b->stream));
+  CK(hipMemcpyAsync(b->d_obj_tab, d_obj_xf, sizeof(float*) * k * b->n, hipMemcpyHostToDevice, b->stream));
+  CK(hipMemcpyAsync(b->d_light_tab, d_light_xf, sizeof(float*) * k * b->n, hipMemcpyHostToDevice, b->stream));
+  CK(hipEventRecord(b->ev_in, b->stream));
+  CK(hipStreamWaitEvent(b->cap_stream, b->ev_in, 0));
+  if (b->multi_k != k || b->multi_stats != d_stats) {
+    if (b->multi_exec) CK(hipGraphExecDestroy(b->multi_exec));
+    if (b->multi_graph) CK(hipGraphDestroy(b->multi_graph));
+    b->multi_exec = nullptr;
+    b->multi_graph = nullptr;
+    b->multi_k = 0;
+    CK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    pv_status st = PV_OK;
+    for (uint32_t f = 0; f < k && st == PV_OK; ++f)
+      st = batch_enqueue(b, d_stats, b->d_obj_tab + (size_t)f * b->n, b->d_light_tab + (size_t)f * b->n,
+                         b->d_frames + f);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (st != PV_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    CK(e);
+    b->multi_graph = g;
+    CK(hipGraphInstantiate(&b->multi_exec, b->multi_graph, nullptr, nullptr, 0));
+    b->multi_k = k;
+    b->multi_stats = d_stats;
+  }
+  CK(hipGraphLaunch(b->multi_exec, b->cap_stream));
   CK(hipEventRecord(b->ev_out, b->cap_stream));
   CK(hipStreamWaitEvent(b->stream, b->ev_out, 0));
   return PV_OK;

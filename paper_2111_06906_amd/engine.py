@@ -290,6 +290,15 @@ class Batch:
                                [c.light_xf[f].data_ptr() for c in self.contexts], owner)
         L.batch_frame(self.b, int(f), _ptr(stats), owner)
 
+    def frames(self, first, k, stats=None):
+        """Frames first .. first + k - 1 of every scene in one graph launch."""
+        owner = self.contexts[0].ctx
+        obj, light = [], []
+        for f in range(first, first + k):
+            obj += [c.obj_xf[f].data_ptr() for c in self.contexts]
+            light += [c.light_xf[f].data_ptr() for c in self.contexts]
+        L.batch_frames(self.b, int(first), int(k), obj, light, _ptr(stats), owner)
+
     def photons(self):
         """(positions [cap,3], energies [cap,3], per-scene first photon [n+1]) of the last frame."""
         cap = sum(s.n_paths * s.B for s in self.stores)

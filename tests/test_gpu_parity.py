@@ -542,6 +542,46 @@ def test_batch_scenes_match_oracle(E):
         c.close()
 
 
+def test_batch_frames_match_single_frames(E):
+    # several frames in one graph launch equal the same frames one launch at a
+    # time (stores bit for bit, statistics, the last frame's photons); the
+    # second multi-frame call has another frame count, so it captures again
+    import torch
+    T, seed = 0.01, 7
+    scs = scenes.make_batch(n_scenes=4, frames=6, path_range=(2000, 20000), tri_range=(5000, 30000))
+    log("multi-frame batch of %d scenes, %d paths" % (len(scs), sum(s.n_paths for s in scs)))
+    ca = [E.Context(s) for s in scs]
+    cb = [E.Context(s) for s in scs]
+    sa = [c.new_store() for c in ca]
+    sb = [c.new_store() for c in cb]
+    for c, st in list(zip(ca, sa)) + list(zip(cb, sb)):
+        c.frame_begin(0)
+        c.initial_trace(st, seed, 0)
+    ba = E.Batch(ca, sa, T, seed)
+    bb = E.Batch(cb, sb, T, seed)
+    for first, k in ((1, 3), (4, 2)):
+        qa, qb = ca[0].new_stats(), cb[0].new_stats()
+        for f in range(first, first + k):
+            ba.frame(f, qa)
+        bb.frames(first, k, qb)
+        torch.cuda.synchronize()
+        for i, (x, y) in enumerate(zip(sa, sb)):
+            dx, dy = x.to_numpy(), y.to_numpy()
+            for key in dx:
+                assert np.array_equal(dx[key].view(np.uint32), dy[key].view(np.uint32)), (first, k, i, key)
+        assert ca[0].stats_dict(qa) == cb[0].stats_dict(qb), (first, k)
+        pa, ea, na = ba.photons()
+        pb, eb, nb = bb.photons()
+        assert torch.equal(na, nb) and torch.equal(pa, pb) and torch.equal(ea, eb)
+    # frame counts outside 1 .. PV_BATCH_MAX_FRAMES are rejected before any work
+    for k in (0, 1025):
+        with pytest.raises(RuntimeError):
+            E.L.batch_frames(bb.b, 1, k, [0] * max(k, 1) * len(scs), [0] * max(k, 1) * len(scs), None,
+                             cb[0].ctx)
+    ba.close()
+    bb.close()
+
+
 def _batch_vs_plain(E, scs, boxes):
     import torch
     T, seed = 0.01, 7
