@@ -295,7 +295,7 @@ def main():
                     help="first copy this many MiB device to device (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--no-headline-graph", action="store_true")
     ap.add_argument("--no-cache-resident", action="store_true")
-    ap.add_argument("--headline-graph-frames", type=int, default=10)
+    ap.add_argument("--headline-graph-frames", type=int, default=22)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
