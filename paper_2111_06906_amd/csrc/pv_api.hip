@@ -1900,7 +1900,15 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats, const float* cons
   pv_ctx* ctx = b->owner;
   hipStream_t st = b->cap_stream;
   CK(pv::launch_frame_begin(b->d_scenes, (int)b->n, obj_in, light_in, st));
-  CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, b->d_xf_tiles, b->n_xf_tiles, st));
+  if (b->n == 1) {
+    // one scene (its context is the owner): the plain frame's refit, the
+    // topologies' boxes as unions over leaf-order ranges, with many more
+    // threads than the per-object level-by-level refit and the same boxes
+    CK(pv::launch_transform_objects(b->d_scenes, b->d_xf_tiles, b->n_xf_tiles, st));
+    CK(pv::launch_refit_objects(b->d_scenes, ctx->lw, ctx->n_objects, ctx->hs.n_obj_nodes, st));
+  } else {
+    CK(pv::launch_update_objects(b->d_scenes, b->d_obj_tiles, b->n_obj_tiles, b->d_xf_tiles, b->n_xf_tiles, st));
+  }
   CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_gbase, (int)b->n, b->vw, b->d_block_cnt,
                        d_stats, b->stack_moved, verify_blocks(ctx), ctx->verify_min_active, b->d_scan_tmp, st));

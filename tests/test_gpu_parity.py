@@ -499,6 +499,12 @@ def test_batch_matches_plain(E):
     _batch_vs_plain(E, scs, [False] * len(scs))
 
 
+def test_batch_single_scene_matches_plain(E):
+    # a batch of one scene refits its objects with the plain frame's kernels
+    scs = scenes.make_batch(n_scenes=1, frames=3, path_range=(20000, 30000), tri_range=(20000, 40000))
+    _batch_vs_plain(E, scs, [False])
+
+
 def test_batch_mixed_modes_matches_plain(E):
     # scenes with point lights (visibility tasks in the multi-scene traversal)
     # and contexts on the box test, batched together with ordinary ones
