@@ -61,6 +61,38 @@ def test_argument_errors_without_device():
         assert b"HIP" in lib.pv_last_error(None) or b"device" in lib.pv_last_error(None)
 
 
+def test_every_entry_point_rejects_a_null_handle():
+    # every call that takes a context or a batch returns PV_ERR_ARG for a NULL
+    # one (nothing is enqueued, no device is touched); the out-parameter
+    # constructors reject a NULL out pointer; the destructors accept NULL
+    lib = L.lib()
+    skip = {"pv_store_bytes", "pv_info_pack", "pv_info_unpack", "pv_version", "pv_last_error"}
+    checked = []
+    for name in sorted(L.declared_symbols()):
+        if name in skip:
+            continue
+        fn = getattr(lib, name)
+        args = []
+        for t in fn.argtypes:
+            if t in (C.c_uint32, C.c_int32, C.c_uint64):
+                args.append(0)
+            elif t is C.c_float:
+                args.append(0.0)
+            else:
+                args.append(None)
+        res = fn(*args)
+        if fn.restype is None:
+            continue  # pv_destroy / pv_batch_destroy: no crash is the check
+        if name == "pv_distribution_cells":
+            assert res == 0, name
+        else:
+            assert res == L.PV_ERR_ARG, (name, res)
+        checked.append(name)
+    assert {"pv_verify_paths", "pv_retrace_paths", "pv_compact_photons", "pv_batch_frames",
+            "pv_compact_photons_noalloc", "pv_update_distribution"} <= set(checked)
+    assert lib.pv_last_error(None) is not None
+
+
 def test_declared_symbols_parse():
     names = L.declared_symbols()
     for n in ("pv_create", "pv_upload_scene", "pv_frame_begin", "pv_verify_paths", "pv_retrace_paths",
