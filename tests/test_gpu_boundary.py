@@ -127,3 +127,62 @@ def test_boundary_argument_errors(E):
     ctx.verify(st)
     assert ctx.queue().size == 0
     ctx.close()
+
+
+def test_boundary_call_order_and_store_errors(E):
+    # calls out of order return PV_ERR_STATE, malformed stores PV_ERR_ARG, a
+    # store beyond the reservation PV_ERR_CAPACITY; each before anything is
+    # enqueued, and the context stays usable: a frame run afterwards matches
+    # the same frame on a fresh context bit for bit
+    import ctypes as C
+    import torch
+    from paper_2111_06906_amd import _lib as L
+    sc = scenes.make_tiny(n_paths=512)
+    lib = L.lib()
+
+    def code(fn, *args):
+        return fn(*args)
+
+    # a context without a scene
+    bare = L.create(C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert code(lib.pv_frame_begin, bare, None, None) == L.PV_ERR_STATE
+    out = (C.c_uint32 * 4)()
+    assert code(lib.pv_object_hierarchy_info, bare, 0, out) == L.PV_ERR_STATE
+    L.destroy(bare)
+
+    ctx = E.Context(sc)
+    st = ctx.new_store()
+    good = st.cstruct()
+    # verification before any transforms; the queue before any verification
+    assert code(lib.pv_verify_paths, ctx.ctx, C.byref(good), None) == L.PV_ERR_STATE
+    assert code(lib.pv_build_queue, ctx.ctx, C.byref(good)) == L.PV_ERR_STATE
+    # the distribution-map update without maps
+    assert code(lib.pv_update_distribution, ctx.ctx, C.byref(good), 1, 1, None, None) == L.PV_ERR_STATE
+    # malformed stores
+    bad = []
+    s1 = st.cstruct(); s1.stride = st.stride + 1; bad.append((s1, L.PV_ERR_ARG))          # stride not a multiple of 64
+    s2 = st.cstruct(); s2.max_bounces = 0; bad.append((s2, L.PV_ERR_ARG))                  # no rows
+    s3 = st.cstruct(); s3.d_info = None; bad.append((s3, L.PV_ERR_ARG))                    # a NULL array
+    s4 = st.cstruct(); s4.d_pos_hit = st.pos_hit.data_ptr() + 4; bad.append((s4, L.PV_ERR_ARG))  # misaligned rows
+    s5 = st.cstruct(); s5.n_paths = st.n_paths - 64; bad.append((s5, L.PV_ERR_ARG))       # light ranges do not add up
+    s6 = st.cstruct(); s6.n_paths = ctx.max_paths + 64; s6.stride = ((ctx.max_paths + 64 + 63) // 64) * 64
+    bad.append((s6, L.PV_ERR_CAPACITY))                                                    # beyond the reservation
+    ctx.frame_begin(0)
+    for sv, want in bad:
+        assert code(lib.pv_verify_paths, ctx.ctx, C.byref(sv), None) == want, (sv.n_paths, sv.stride, want)
+        assert code(lib.pv_retrace_paths, ctx.ctx, C.byref(sv), 0.01, 1, 1, None) == want
+    # still usable: the same two frames as on a fresh context
+    ref = E.Context(sc)
+    sr = ref.new_store()
+    for c, x in ((ctx, st), (ref, sr)):
+        c.frame_begin(0)
+        c.initial_trace(x, sc.seed, 0)
+        c.frame_begin(1)
+        c.verify(x)
+        c.retrace(x, 0.01, sc.seed, 1)
+    torch.cuda.synchronize()
+    da, db = st.to_numpy(), sr.to_numpy()
+    for k in da:
+        assert np.array_equal(da[k].view(np.uint32), db[k].view(np.uint32)), k
+    ctx.close()
+    ref.close()
