@@ -213,6 +213,15 @@ def test_mid_rooms_lockstep_error_based(E):
     _lockstep(E, sc, 4, 0.01, "mid error-based")
 
 
+@pytest.mark.parametrize("seed", [101, 202, 303])
+def test_rooms_lockstep_other_seeds(E, seed):
+    # other random scenes (room layout, tori, moving lights, paths) of the
+    # same recipe, error-based walk with both energy tests in turn
+    sc = scenes.make_rooms("seed%d" % seed, 3, 3, 20000, 4, (40, 16), 5000 + seed % 64, 6, 4, 0.01, seed,
+                           n_lights=2, lights_move=True)
+    _lockstep(E, sc, 4, 0.01, "rooms seed %d" % seed, energy_test=seed % 2)
+
+
 def test_paper_rooms_moving_lights(E):
     sc = scenes.make_paper(n_paths=4096 + 13, frames=3)
     _lockstep(E, sc, 3, 0.01, "paper")
