@@ -47,6 +47,10 @@ MUTATIONS = {
     "normal_not_flipped": ("    if (dot3(n, w) > 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
                            "    if (dot3(n, w) < 0.0)\n      for (int i = 0; i < 3; ++i) n[i] = -n[i];",
                            "energies or initial_trace or retrace"),
+    # the walk keeps the segment after a close re-hit without checking it
+    "close_rehit_unchecked": ("          !hit_on_moved(s, vhit(st, p, j + 2)) &&\n"
+                              "          !seg_blocked(c->A, xb, xc, s->band_trace, 0, amb)) {",
+                              "          !hit_on_moved(s, vhit(st, p, j + 2))) {", "close_rehit"),
     # equal-distance hits: the later triangle wins instead of the lowest id
     "tie_rule": ("if (tt < h.t || (tt == h.t && t < h.tri)) { h.t = tt; h.tri = t; }",
                  "if (tt <= h.t) { h.t = tt; h.tri = t; }", "tie"),

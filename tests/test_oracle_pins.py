@@ -835,6 +835,38 @@ def test_figure1_first_segment_kept_tail_when_energy_close():
     assert np.array_equal(st.energy, before.energy)
 
 
+def test_walk_close_rehit_then_next_segment_blocked():
+    # Figure 1's kept-tail case (segment 0 blocked by a cube of the floor's
+    # albedo) with a second moved cube across segment 2.  The walk re-hits the
+    # old second photon from the new first one (a close re-hit), checks the
+    # following segment against the moved objects before keeping it, finds the
+    # second cube there, so it writes the re-hit and traces segment 2 again
+    # from it: the third photon lands on the second cube's face z = 0.275, at
+    # (1, 0.4, 0.5) + 0.45 * (-0.4, 0.1, -0.5) = (0.82, 0.445, 0.275).
+    orig = [0.5, 0.999, 0.5]
+    photons = [([0.5, 0.0, 0.5], 0), ([1.0, 0.4, 0.5], 7), ([0.6, 0.5, 0.0], 8)]
+    blockers = [((0.503, 0.3, 0.498), 0.1), ((0.8, 0.45, 0.25), 0.05)]
+    fs = H.box_scene(blockers=blockers, albedo_blocker=0.7)
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    f = O.info_fields(st.info)
+    assert f["replace"][0] == 1 and f["start"][0] == 0
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert amb[0] == 0 and tr[0] == 3                   # segments 0, 1 and 2 traced
+    assert 10 <= st.hit[0, 0] < 22 and abs(st.pos[0, 0, 1] - 0.35) < 1e-6   # top of the first cube
+    assert st.hit[1, 0] == 7 and np.linalg.norm(st.pos[1, 0] - before.pos[1, 0]) < 1e-6
+    assert 22 <= st.hit[2, 0] < 34
+    assert np.abs(st.pos[2, 0] - np.array([0.82, 0.445, 0.275])).max() < 1e-6
+    assert np.array_equal(st.energy, before.energy)
+    # without the second cube the segment after the close re-hit is kept as is
+    fs1 = H.box_scene(blockers=blockers[:1], albedo_blocker=0.7)
+    st1 = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs1, st1)
+    amb1, tr1 = O.retrace(fs1, st1, 0.001, 1, 1)
+    assert tr1[0] == 2 and st1.hit[2, 0] == 8 and np.array_equal(st1.pos[2], before.pos[2])
+
+
 # ---------------------------------------------------------------------------
 # queue, compaction: library routines and brute force
 
