@@ -174,6 +174,20 @@ def test_figure1_first_segment_kept_tail_when_energy_close(E):
 
 
 @pytest.mark.gpu
+def test_walk_close_rehit_then_next_segment_blocked(E):
+    # kept-tail case plus a moved cube across segment 2: the close re-hit is
+    # written and segment 2 traced again, ending on the cube at (0.82, 0.445, 0.275)
+    blockers = [((0.503, 0.3, 0.498), 0.1), ((0.8, 0.45, 0.25), 0.05)]
+    v, o, g, av, ar, s = run_case(E, "close re-hit, next segment blocked", [_fig1_path()], 0.001,
+                                  blockers=blockers, albedo_blocker=0.7)
+    assert av[0] == 0 and ar[0] == 0 and s["rays_traced"] == 3
+    assert 10 <= g["hit"][0, 0] < 22 and g["hit"][1, 0] == 7 and 22 <= g["hit"][2, 0] < 34
+    assert np.linalg.norm(g["pos"][1, 0] - v.pos[1, 0]) < 1e-5
+    assert np.abs(g["pos"][2, 0] - np.array([0.82, 0.445, 0.275])).max() < 1e-5
+    assert np.array_equal(g["energy"], v.energy)
+
+
+@pytest.mark.gpu
 def test_box_test_box_without_triangle_casts_no_ray(E):
     # triangle test: the path stays valid
     v, o, g, av, ar, s = run_case(E, "box without triangle, triangle test", [_worked_path()], 0.001,
