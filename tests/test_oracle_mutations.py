@@ -51,6 +51,10 @@ MUTATIONS = {
     "close_rehit_unchecked": ("          !hit_on_moved(s, vhit(st, p, j + 2)) &&\n"
                               "          !seg_blocked(c->A, xb, xc, s->band_trace, 0, amb)) {",
                               "          !hit_on_moved(s, vhit(st, p, j + 2))) {", "close_rehit"),
+    # after an accepted far hit the next segment is only checked, not traced
+    "far_hit_not_traced_on": ("      put_photon(st, p, j, hp, (uint32_t)h.tri, ej, s->radius);\n      ++j;\n      need = 1;",
+                              "      put_photon(st, p, j, hp, (uint32_t)h.tri, ej, s->radius);\n      ++j;\n      need = 0;",
+                              "far_hit"),
     # equal-distance hits: the later triangle wins instead of the lowest id
     "tie_rule": ("if (tt < h.t || (tt == h.t && t < h.tri)) { h.t = tt; h.tri = t; }",
                  "if (tt <= h.t) { h.t = tt; h.tri = t; }", "tie"),

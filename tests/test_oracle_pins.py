@@ -867,6 +867,30 @@ def test_walk_close_rehit_then_next_segment_blocked():
     assert tr1[0] == 2 and st1.hit[2, 0] == 8 and np.array_equal(st1.pos[2], before.pos[2])
 
 
+def test_walk_accepted_far_hit_continues_from_it():
+    # kept-tail case with a second moved cube across the new segment 1 (from
+    # the first cube's top at (0.5, 0.35, 0.5) towards the old second photon
+    # (1, 0.4, 0.5)), of the same albedo: the new hit on the cube's face
+    # x = 0.725, at (0.5, 0.35, 0.5) + 0.45 * (0.5, 0.05, 0) = (0.725, 0.3725,
+    # 0.5), reflects the same energy (Equation 2 holds) but is far from the old
+    # photon, so it is written and the walk traces segment 2 from it towards
+    # the old third photon, which it reaches (0.6, 0.5, 0) on the back wall.
+    orig = [0.5, 0.999, 0.5]
+    photons = [([0.5, 0.0, 0.5], 0), ([1.0, 0.4, 0.5], 7), ([0.6, 0.5, 0.0], 8)]
+    fs = H.box_scene(blockers=[((0.503, 0.3, 0.498), 0.1), ((0.75, 0.375, 0.5), 0.05)], albedo_blocker=0.7)
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    assert O.info_fields(st.info)["start"][0] == 0
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert amb[0] == 0 and tr[0] == 3
+    expect = np.array([[0.5, 0.35, 0.5], [0.725, 0.3725, 0.5], [0.6, 0.5, 0.0]])
+    assert np.abs(st.pos[:, 0] - expect).max() < 1e-6
+    assert 10 <= st.hit[0, 0] < 22 and 22 <= st.hit[1, 0] < 34 and st.hit[2, 0] in (8, 9)
+    assert np.array_equal(st.energy, before.energy)
+    assert O.info_fields(st.info)["nseg"][0] == 3 and O.info_fields(st.info)["replace"][0] == 0
+
+
 # ---------------------------------------------------------------------------
 # queue, compaction: library routines and brute force
 
