@@ -188,6 +188,20 @@ def test_walk_close_rehit_then_next_segment_blocked(E):
 
 
 @pytest.mark.gpu
+def test_walk_accepted_far_hit_continues_from_it(E):
+    # kept-tail case plus a same-albedo cube across the new segment 1: the far
+    # new hit is written and the walk goes on from it to the old third photon
+    blockers = [((0.503, 0.3, 0.498), 0.1), ((0.75, 0.375, 0.5), 0.05)]
+    v, o, g, av, ar, s = run_case(E, "accepted far hit, walk continues", [_fig1_path()], 0.001,
+                                  blockers=blockers, albedo_blocker=0.7)
+    assert av[0] == 0 and ar[0] == 0 and s["rays_traced"] == 3
+    expect = np.array([[0.5, 0.35, 0.5], [0.725, 0.3725, 0.5], [0.6, 0.5, 0.0]])
+    assert np.abs(g["pos"][:, 0] - expect).max() < 1e-5
+    assert 10 <= g["hit"][0, 0] < 22 and 22 <= g["hit"][1, 0] < 34
+    assert np.array_equal(g["energy"], v.energy)
+
+
+@pytest.mark.gpu
 def test_box_test_box_without_triangle_casts_no_ray(E):
     # triangle test: the path stays valid
     v, o, g, av, ar, s = run_case(E, "box without triangle, triangle test", [_worked_path()], 0.001,
