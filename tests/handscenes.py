@@ -39,8 +39,18 @@ def cube_tris(center, side):
 LIGHT_DOWN = np.array([1, 0, 0, 0.5, 0, 0, -1, 0.999, 0, 1, 0, 0.5], np.float32)
 
 
+def _blocker_materials(n_parts, albedo_box, albedo_blocker, blocker_albedos):
+    """(material of each blocker, albedo table): every blocker takes material 1
+    (albedo_blocker), or blocker i material 1 + i with blocker_albedos[i]."""
+    if blocker_albedos is None:
+        return [1] * n_parts, np.array([[albedo_box] * 3, [albedo_blocker] * 3], np.float32)
+    assert len(blocker_albedos) == n_parts
+    return [1 + i for i in range(n_parts)], np.array([[albedo_box] * 3] + [[a] * 3 for a in blocker_albedos],
+                                                     np.float32)
+
+
 def box_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_paths=1, light_moved=False,
-              light_xf=LIGHT_DOWN, tri_blockers=(), light_half=(0.1, 0.1)):
+              light_xf=LIGHT_DOWN, tri_blockers=(), light_half=(0.1, 0.1), blocker_albedos=None):
     """Box plus optional cube blockers and single-triangle blockers (each its
     own object, cubes first), as a FrameScene."""
     tris = [BOX]
@@ -48,15 +58,16 @@ def box_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_pat
     mat = [np.zeros(10, np.uint32)]
     parts = [cube_tris(center, side) for center, side in blockers]
     parts += [np.asarray(t, np.float32).reshape(1, 3, 3) for t in tri_blockers]
+    mats, albedo = _blocker_materials(len(parts), albedo_box, albedo_blocker, blocker_albedos)
     for i, t in enumerate(parts):
         tris.append(t)
         obj.append(np.full(t.shape[0], i + 1, np.uint32))
-        mat.append(np.ones(t.shape[0], np.uint32))
+        mat.append(np.full(t.shape[0], mats[i], np.uint32))
     verts = np.concatenate(tris).reshape(-1, 9)
     return O.FrameScene(
         verts=verts, tri_obj=np.concatenate(obj), tri_mat=np.concatenate(mat),
         obj_moved=np.array([0] + [1 if moved else 0] * len(parts), np.uint8),
-        albedo=np.array([[albedo_box] * 3, [albedo_blocker] * 3], np.float32),
+        albedo=albedo,
         light_xf=np.asarray(light_xf, np.float32)[None], light_half=np.array([light_half], np.float32),
         light_power=np.ones((1, 3), np.float32), light_moved=np.array([1 if light_moved else 0], np.uint8),
         light_base=np.array([0, n_paths], np.int64))
@@ -83,7 +94,7 @@ PARKED = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 5], np.float32)   # frame-0 
 
 
 def device_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_paths=1, light_moved=False,
-                 light_xf=LIGHT_DOWN, tri_blockers=(), light_half=(0.1, 0.1), max_bounces=3):
+                 light_xf=LIGHT_DOWN, tri_blockers=(), light_half=(0.1, 0.1), max_bounces=3, blocker_albedos=None):
     """The scene of box_scene(...) with the same arguments as a two-frame
     Scene for the device context: frame 1 holds the blockers at their world
     positions (identity transforms, so the world vertices are the given ones
@@ -93,6 +104,7 @@ def device_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_
     parts = [cube_tris(center, side) for center, side in blockers]
     parts += [np.asarray(t, np.float32).reshape(1, 3, 3) for t in tri_blockers]
     D = len(parts)
+    mats, albedo = _blocker_materials(D, albedo_box, albedo_blocker, blocker_albedos)
     xf1 = np.tile(IDENTITY, (D, 1))
     xf0 = np.tile(PARKED if moved else IDENTITY, (D, 1))
     lxf1 = np.asarray(light_xf, np.float32)[None]
@@ -101,9 +113,9 @@ def device_scene(blockers=(), moved=True, albedo_box=0.7, albedo_blocker=0.5, n_
         assert not np.array_equal(lxf0, lxf1), "a moved light needs a transform other than LIGHT_DOWN"
     return scenes.Scene(
         name="hand", static_verts=BOX.copy(), static_mat=np.zeros(10, np.uint32),
-        obj_local=parts, obj_mat=[np.ones(p.shape[0], np.uint32) for p in parts],
+        obj_local=parts, obj_mat=[np.full(p.shape[0], m, np.uint32) for p, m in zip(parts, mats)],
         obj_xforms=np.stack([xf0, xf1]).reshape(2, D, 12).astype(np.float32),
-        albedo=np.array([[albedo_box] * 3, [albedo_blocker] * 3], np.float32),
+        albedo=albedo,
         light_half=np.array([light_half], np.float32), light_power=np.ones((1, 3), np.float32),
         light_xforms=np.stack([lxf0, lxf1]).astype(np.float32),
         light_paths=np.array([n_paths], np.int64), max_bounces=max_bounces, threshold=-1.0, seed=1)

@@ -55,6 +55,10 @@ MUTATIONS = {
     "far_hit_not_traced_on": ("      put_photon(st, p, j, hp, (uint32_t)h.tri, ej, s->radius);\n      ++j;\n      need = 1;",
                               "      put_photon(st, p, j, hp, (uint32_t)h.tri, ej, s->radius);\n      ++j;\n      need = 0;",
                               "far_hit"),
+    # a re-sampled path keeps the reflected instead of the arriving energy at its new vertex
+    "kept_vertex_energy": ("        put_photon(st, p, j, hp, (uint32_t)h.tri, ej, s->radius);\n        newn = naive_tail(",
+                           "        put_photon(st, p, j, hp, (uint32_t)h.tri, en, s->radius);\n        newn = naive_tail(",
+                           "energy_differs_after or figure1"),
     # equal-distance hits: the later triangle wins instead of the lowest id
     "tie_rule": ("if (tt < h.t || (tt == h.t && t < h.tri)) { h.t = tt; h.tri = t; }",
                  "if (tt <= h.t) { h.t = tt; h.tri = t; }", "tie"),

@@ -891,6 +891,31 @@ def test_walk_accepted_far_hit_continues_from_it():
     assert O.info_fields(st.info)["nseg"][0] == 3 and O.info_fields(st.info)["replace"][0] == 0
 
 
+def test_walk_energy_differs_after_an_accepted_segment():
+    # as the accepted-far-hit case, but the second cube's albedo is 0.3: the
+    # first cube (the floor's albedo 0.7) is accepted at segment 0, Equation 2
+    # fails at segment 1 (0.7 * 0.3 against the stored 0.7 * 0.7), so the new
+    # hit on the second cube is kept with its arriving energy 0.7 and the rest
+    # is re-sampled from it: one bounce, whose photon carries 0.7 * 0.3 and
+    # leaves the cube's face x = 0.725 towards -x.
+    orig = [0.5, 0.999, 0.5]
+    photons = [([0.5, 0.0, 0.5], 0), ([1.0, 0.4, 0.5], 7), ([0.6, 0.5, 0.0], 8)]
+    fs = H.box_scene(blockers=[((0.503, 0.3, 0.498), 0.1), ((0.75, 0.375, 0.5), 0.05)],
+                     blocker_albedos=[0.7, 0.3])
+    st = H.store_from_paths([(orig, photons)], 3)
+    O.verify(fs, st)
+    before = st.copy()
+    amb, tr = O.retrace(fs, st, 0.001, 1, 1)
+    assert amb[0] == 0 and tr[0] == 3
+    assert np.abs(st.pos[:2, 0] - np.array([[0.5, 0.35, 0.5], [0.725, 0.3725, 0.5]])).max() < 1e-6
+    assert 10 <= st.hit[0, 0] < 22 and 22 <= st.hit[1, 0] < 34 and st.hit[2, 0] < 10
+    assert np.array_equal(st.energy[:2], before.energy[:2])
+    e2 = np.float32(np.float32(0.7) * np.float32(0.3))
+    assert np.all(st.energy[2, 0] == e2)
+    assert st.pos[2, 0, 0] < 0.725 and np.linalg.norm(st.pos[2, 0] - before.pos[2, 0]) > 1e-3
+    assert O.info_fields(st.info)["nseg"][0] == 3
+
+
 # ---------------------------------------------------------------------------
 # queue, compaction: library routines and brute force
 
