@@ -202,6 +202,19 @@ def test_walk_accepted_far_hit_continues_from_it(E):
 
 
 @pytest.mark.gpu
+def test_walk_energy_differs_after_an_accepted_segment(E):
+    # the first cube accepted at segment 0, Equation 2 fails at segment 1 on
+    # the darker second cube: its hit is kept and one bounce re-sampled from it
+    blockers = [((0.503, 0.3, 0.498), 0.1), ((0.75, 0.375, 0.5), 0.05)]
+    v, o, g, av, ar, s = run_case(E, "energy differs after an accepted segment", [_fig1_path()], 0.001,
+                                  blockers=blockers, blocker_albedos=[0.7, 0.3])
+    assert av[0] == 0 and ar[0] == 0 and s["rays_traced"] == 3
+    assert np.abs(g["pos"][:2, 0] - np.array([[0.5, 0.35, 0.5], [0.725, 0.3725, 0.5]])).max() < 1e-5
+    assert 22 <= g["hit"][1, 0] < 34
+    assert np.all(g["energy"][2, 0] == np.float32(np.float32(0.7) * np.float32(0.3)))
+
+
+@pytest.mark.gpu
 def test_box_test_box_without_triangle_casts_no_ray(E):
     # triangle test: the path stays valid
     v, o, g, av, ar, s = run_case(E, "box without triangle, triangle test", [_worked_path()], 0.001,
