@@ -2100,7 +2100,8 @@ pv_status pv_batch_frames(pv_batch* b, uint32_t first_frame, uint32_t k, const f
         return fail(ctx, PV_ERR_ARG, "transform array is NULL");
   if (first_frame > UINT32_MAX - (k - 1)) return fail(ctx, PV_ERR_ARG, "frame numbers overflow");
   if (k > b->tab_frames) {
-    // larger tables: nothing captured may still read the old ones
+    // larger tables: nothing enqueued may still read or write the old ones
+    CK(hipStreamSynchronize(b->stream));
     CK(hipStreamSynchronize(b->cap_stream));
     if (b->multi_exec) CK(hipGraphExecDestroy(b->multi_exec));
     if (b->multi_graph) CK(hipGraphDestroy(b->multi_graph));
