@@ -453,8 +453,8 @@ pv_status pv_batch_frame(pv_batch* b, uint32_t frame, pv_stats* d_stats);
  * reuse the host arrays at once; the device arrays they point to must hold
  * their transforms until the launch has run.  The graph is captured on the
  * first call and again when k or d_stats changes (a larger k than any before
- * also synchronises the batch's stream once, to grow the tables); later calls
- * replay it.  Photon compaction runs in every frame, so the buffer that
+ * also synchronises the owner's and the batch's streams once, to grow the
+ * tables); later calls replay it.  Photon compaction runs in every frame, so the buffer that
  * pv_batch_copy_photons reads holds the last frame's photons.  Results are
  * bit-identical to k calls of pv_batch_frame.  1 <= k <= PV_BATCH_MAX_FRAMES,
  * else PV_ERR_ARG; a NULL table or a NULL light array (or object array of a
