@@ -113,6 +113,14 @@ def headline_graph(args, engine, sc, torch, np, T, tuning):
     bit after the timed frames)."""
     K = args.headline_graph_frames
     seed = sc.seed
+    if K + 2 > sc.n_frames:
+        # more frames than the scene holds: the same scene, its motion played
+        # back and forth (0 .. n-1, n-2 .. 0, 1 ..), so that frames 2 .. K + 1
+        # exist and consecutive frames still differ
+        import dataclasses
+        per = 2 * max(1, sc.n_frames - 1)
+        idx = [f % per if f % per < sc.n_frames else per - f % per for f in range(K + 2)]
+        sc = dataclasses.replace(sc, obj_xforms=sc.obj_xforms[idx], light_xforms=sc.light_xforms[idx])
     consecutive = 1 + K <= sc.n_frames - 1  # frames 2 .. K + 1 exist (one launch runs consecutive frames)
     runs = []
     for mode in ("plain", "graph", "frames"):
@@ -295,7 +303,7 @@ def main():
                     help="first copy this many MiB device to device (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--no-headline-graph", action="store_true")
     ap.add_argument("--no-cache-resident", action="store_true")
-    ap.add_argument("--headline-graph-frames", type=int, default=22)
+    ap.add_argument("--headline-graph-frames", type=int, default=30)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
