@@ -738,6 +738,50 @@ def test_paper_full_size_sampled(E):
     assert cnt == int(((info2 >> 22) & 15).sum())
 
 
+@pytest.mark.parametrize("kind,param", [(1, (0.8, 0.0)), (2, (0.6, 0.4))], ids=["spot", "camera"])
+def test_paper_full_size_emitters_sampled(E, kind, param):
+    # the 3M x 7 launch configuration lit by two moving spotlights or cameras
+    # (Section 3.1's cone emitter, Section 7's camera): sampled columns of the
+    # frame-0 trace and of a frame-1 verify and re-trace in lockstep
+    import torch
+    label = "spot" if kind == 1 else "camera"
+    sc = scenes.make_rooms("paper", 6, 6, 300_000, 8, (100, 50), 3_000_000, 7, 3, 0.01, 3, n_lights=2,
+                           lights_move=True, torus_size=(0.2, 0.07), light_kind=kind, light_param=param)
+    N, B = sc.n_paths, sc.max_bounces
+    rng = np.random.default_rng(31 + kind)
+    lb = sc.light_base
+    cols = np.unique(np.concatenate([[0, 1, N - 1, lb[1] - 1, lb[1]], rng.choice(N, 507, replace=False)]))
+    log("paper full size, %s: N=%d, %d sampled columns" % (label, N, cols.size))
+    fs0 = O.frame_scene(sc, 0)
+    ora, amb0, _ = O.initial_trace(fs0, N, B, sc.seed, paths=cols)
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    stats = ctx.new_stats()
+    ctx.initial_trace(st, sc.seed, 0, stats)
+    o0 = ora.select(cols)
+    H.check_excluded((amb0 != 0).sum(), cols.size, "paper full size %s frame0 (sampled)" % label,
+                     H.sampled_budget(H.PAPER_FULL_EMITTER_TRACE_RATE[kind], cols.size))
+    H.compare_stores(st.to_numpy(cols), o0, amb0 == 0, "paper full size %s frame0 (sampled)" % label, fs0.verts,
+                     (amb0 != 0).sum())
+    info = st.info[:N].cpu().numpy().view(np.uint32)
+    assert int(((info >> 22) & 15).sum()) == ctx.stats_dict(stats)["photons_written"]
+    st.load_numpy(H.from_oracle(o0), cols=cols)
+    ctx.frame_begin(1)
+    ctx.verify(st)
+    ctx.retrace(st, 0.01, sc.seed, 1)
+    torch.cuda.synchronize()
+    fs1 = O.frame_scene(sc, 1, 0)
+    ambv, _ = O.verify(fs1, ora, paths=cols)
+    vinfo = ora.info[cols].copy()
+    ambr, _ = O.retrace(fs1, ora, 0.01, sc.seed, 1, paths=cols)
+    ok = (ambv == 0) & (ambr == 0)
+    log("  sampled: %d replaced, %d excluded" % (((vinfo >> 30) & 1).sum(), (~ok).sum()))
+    H.check_excluded((~ok).sum(), cols.size, "paper full size %s frame1 (sampled)" % label)
+    H.compare_stores(st.to_numpy(cols), ora.select(cols), ok, "paper full size %s frame1 (sampled)" % label,
+                     fs1.verts, (~ok).sum())
+    ctx.close()
+
+
 def test_autotune_restores_store_and_tuning_does_not_change_results(E):
     import torch
     sc = scenes.make_mid(n_paths=50000, frames=3, threshold=0.01)
