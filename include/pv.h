@@ -432,7 +432,13 @@ pv_status pv_energy_backward(pv_ctx* ctx, const pv_path_store* store, const floa
  * threshold and seed as in pv_retrace_paths.  Frames are ordered on the
  * stream of contexts[0] (they run on a stream of the batch's own, which may
  * be captured, fenced with events); every context must have been uploaded with pv_set_light_paths
- * matching its store.  Results are bit-identical to the per-context calls.
+ * matching its store.  A context that has a distribution map when the batch
+ * is created (pv_set_distribution_map) keeps it in the batch: every frame
+ * runs pv_update_distribution's steps for that scene after verification,
+ * with the batch's seed and the frame's number, on batch-owned scratch (a map
+ * set or cleared on the context later does not reach the batch).  Results are
+ * bit-identical to the per-context calls (pv_verify_paths, pv_update_distribution
+ * for a scene with a map, pv_retrace_paths).
  * Synchronises.  Errors are reported through pv_last_error(contexts[0]). */
 pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path_store* stores, uint32_t n,
                           const float* const* d_obj_xf, const float* const* d_light_xf, float threshold,

@@ -161,6 +161,13 @@ struct pv_batch {
   pv_stats* multi_stats = nullptr;
   hipGraph_t multi_graph = nullptr;
   hipGraphExec_t multi_exec = nullptr;
+  // distribution maps of the scenes whose context had one when the batch was
+  // created (Section 3.1's update after verification, on batch-owned scratch)
+  struct Dm {
+    uint32_t scene, tile_base, n_tiles, cells, n_lights;
+    pv::DmWork D;
+  };
+  std::vector<Dm> dms;
   ~pv_batch() {
     if (multi_exec) (void)hipGraphExecDestroy(multi_exec);
     if (multi_graph) (void)hipGraphDestroy(multi_graph);
@@ -1507,8 +1514,8 @@ pv_status pv_update_distribution(pv_ctx* ctx, const pv_path_store* store, uint64
   if (!ctx->frame_started) return fail(ctx, PV_ERR_STATE, "no transforms given (pv_frame_begin or pv_update_*)");
   if ((st = wait_compaction(ctx))) return st;
   const uint32_t nb = path_blocks(store->n_paths);
-  CK(pv::launch_dm_update(ctx->d_scene, ctx->d_path_tiles, nb, ctx->dm_cells, ctx->n_lights, ctx->dw,
-                          ctx->d_block_cnt, seed, frame, ctx->stream));
+  CK(pv::launch_dm_update(ctx->d_scene, ctx->d_scene, ctx->d_path_tiles, nb, ctx->dm_cells, ctx->n_lights, ctx->dw,
+                          ctx->d_block_cnt, seed, frame, nullptr, ctx->stream));
   if (d_dm_c)
     CK(hipMemcpyAsync(d_dm_c, ctx->dw.dm_c, 4 * (size_t)ctx->dm_cells, hipMemcpyDeviceToDevice, ctx->stream));
   if (d_pruned)
@@ -1912,6 +1919,11 @@ static pv_status batch_enqueue(pv_batch* b, pv_stats* d_stats, const float* cons
   CK(pv::launch_build_top(b->d_scenes, (int)b->n, st));
   CK(pv::launch_verify(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_gbase, (int)b->n, b->vw, b->d_block_cnt,
                        d_stats, b->stack_moved, verify_blocks(ctx), ctx->verify_min_active, b->d_scan_tmp, st));
+  // distribution maps: compute DM_C, prune, fill, scene by scene (each
+  // rewrites its own tiles' replace counts before the queue is built)
+  for (const pv_batch::Dm& d : b->dms)
+    CK(pv::launch_dm_update(b->d_scenes, b->d_scenes + d.scene, b->d_path_tiles + d.tile_base, d.n_tiles, d.cells,
+                            d.n_lights, d.D, b->d_block_cnt + d.tile_base, b->seed, 0, frame_ptr, st));
   CK(pv::launch_scan(b->d_block_cnt, b->d_offsets, b->n_path_tiles, b->d_qcount, b->d_scan_tmp, st));
   CK(pv::launch_scatter_queue(b->d_scenes, b->d_path_tiles, b->n_path_tiles, b->d_offsets, b->d_queue, st));
   CK(pv::launch_retrace(b->d_scenes, b->d_gbase, (int)b->n, b->d_queue, b->d_qcount, b->T, b->seed, 0,
@@ -1982,6 +1994,8 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
       hs.tile_base = (uint32_t)ptiles.size();
       hs.task_base = (uint32_t)task_cap;
       table[i] = hs;
+      if (c->dm_enabled)
+        b->dms.push_back(pv_batch::Dm{i, hs.tile_base, hs.n_blocks, c->dm_cells, c->n_lights, pv::DmWork{}});
       gbase[i] = (uint32_t)total_paths;
       for (uint2 t : make_tiles(i, st->n_paths)) ptiles.push_back(t);
       for (uint32_t o = 0; o < c->n_objects; ++o) otiles.push_back(make_uint2(i, o));
@@ -2022,6 +2036,14 @@ pv_status pv_batch_create(pv_batch** out, pv_ctx* const* contexts, const pv_path
               chk(dalloc(A, &b->vw.part, 4 * ptiles.size() + 2 * (size_t)pv::verify_finish_blocks(verify_blocks_max(ctx)))) &&
               chk(upload(A, &b->d_obj_in, const_cast<const float**>(d_obj_xf), n, s)) &&
               chk(upload(A, &b->d_light_in, const_cast<const float**>(d_light_xf), n, s));
+    for (pv_batch::Dm& d : b->dms) {
+      pv::DmWork& D = d.D;
+      ok = ok && chk(dalloc(A, &D.dm_c, d.cells)) && chk(dalloc(A, &D.pruned, d.cells)) &&
+           chk(dalloc(A, &D.def, d.cells)) && chk(dalloc(A, &D.dex, (size_t)d.cells + 1)) &&
+           chk(dalloc(A, &D.tcnt, d.n_tiles)) && chk(dalloc(A, &D.toff, d.n_tiles)) && chk(dalloc(A, &D.ttotal, 1)) &&
+           chk(dalloc(A, &D.rank0, PV_MAX_LIGHTS)) && chk(dalloc(A, &D.scan_tmp, pv::scan_tmp_words(d.cells))) &&
+           chk(dalloc(A, &D.scan_tmp2, pv::scan_tmp_words(d.n_tiles)));
+    }
     if (!ok || hipStreamSynchronize(s) != hipSuccess) {
       delete b;
       return fail(ctx, PV_ERR_OOM, "batch allocation failed");

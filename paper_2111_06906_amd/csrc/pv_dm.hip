@@ -106,8 +106,10 @@ __global__ __launch_bounds__(kBlock) void k_dm_count(const SceneDev* __restrict_
 // pruning (Section 4's two passes: decide, then count the pruned paths).
 __global__ __launch_bounds__(kBlock) void k_dm_prune(const SceneDev* __restrict__ scenes,
                                                      const uint2* __restrict__ tiles, const uint32_t* __restrict__ dm_c,
-                                                     uint32_t* __restrict__ pruned, uint64_t seed, uint32_t frame) {
+                                                     uint32_t* __restrict__ pruned, uint64_t seed, uint32_t frame,
+                                                     const uint32_t* __restrict__ frame_ptr) {
   __shared__ uint32_t h[kLdsCells];
+  if (frame_ptr) frame = *frame_ptr;  // a captured frame reads its number from device memory
   const uint2 tile = tiles[blockIdx.x];
   const SceneDev& S = scenes[tile.x];
   const uint32_t cells = S.dm_off[S.n_lights];
@@ -233,23 +235,24 @@ __global__ __launch_bounds__(kBlock) void k_dm_fill(const SceneDev* __restrict__
   G(S.info)[p] = info_pack(cell, info_nseg(w), info_start(w), 1, 0);
 }
 
-hipError_t launch_dm_update(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t cells,
-                            uint32_t n_lights, const DmWork& D, uint32_t* block_cnt, uint64_t seed, uint32_t frame,
-                            hipStream_t s) {
+hipError_t launch_dm_update(const SceneDev* table, const SceneDev* scene, const uint2* tiles, uint32_t n_tiles,
+                            uint32_t cells, uint32_t n_lights, const DmWork& D, uint32_t* block_cnt, uint64_t seed,
+                            uint32_t frame, const uint32_t* frame_ptr, hipStream_t s) {
   if (!n_tiles || !cells) return hipSuccess;
   if (n_lights < 1 || n_lights > PV_MAX_LIGHTS) return hipErrorInvalidValue;
   const uint32_t cb = std::min(1024u, (cells + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_dm_clear, dim3(cb), dim3(kBlock), 0, s, D.dm_c, D.pruned, cells);
-  hipLaunchKernelGGL(k_dm_count, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, D.dm_c);
-  hipLaunchKernelGGL(k_dm_prune, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, D.dm_c, D.pruned, seed, frame);
-  hipLaunchKernelGGL(k_dm_deficit, dim3(cb), dim3(kBlock), 0, s, scenes, D.dm_c, D.pruned, D.def);
+  hipLaunchKernelGGL(k_dm_count, dim3(n_tiles), dim3(kBlock), 0, s, table, tiles, D.dm_c);
+  hipLaunchKernelGGL(k_dm_prune, dim3(n_tiles), dim3(kBlock), 0, s, table, tiles, D.dm_c, D.pruned, seed, frame,
+                     frame_ptr);
+  hipLaunchKernelGGL(k_dm_deficit, dim3(cb), dim3(kBlock), 0, s, scene, D.dm_c, D.pruned, D.def);
   hipError_t e = launch_scan(D.def, D.dex, cells, D.dex + cells, D.scan_tmp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dm_flags, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, D.tcnt);
+  hipLaunchKernelGGL(k_dm_flags, dim3(n_tiles), dim3(kBlock), 0, s, table, tiles, D.tcnt);
   e = launch_scan(D.tcnt, D.toff, n_tiles, D.ttotal, D.scan_tmp2, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dm_rank0, dim3(1), dim3(64), 0, s, scenes, D.toff, D.rank0);
-  hipLaunchKernelGGL(k_dm_fill, dim3(n_tiles), dim3(kBlock), 0, s, scenes, tiles, D.dex, D.toff, D.rank0,
+  hipLaunchKernelGGL(k_dm_rank0, dim3(1), dim3(64), 0, s, scene, D.toff, D.rank0);
+  hipLaunchKernelGGL(k_dm_fill, dim3(n_tiles), dim3(kBlock), 0, s, table, tiles, D.dex, D.toff, D.rank0,
                      block_cnt);
   return hipGetLastError();
 }

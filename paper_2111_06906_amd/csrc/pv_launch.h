@@ -90,10 +90,13 @@ struct DmWork {
   uint32_t* scan_tmp2; // scan_tmp_words(tiles)
 };
 // Compute DM_C, prune (Equation 1), fill (Section 3.1) on one scene's store
-// (information words updated, tiles' replace counts into block_cnt)
-hipError_t launch_dm_update(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, uint32_t cells,
-                            uint32_t n_lights, const DmWork& D, uint32_t* block_cnt, uint64_t seed, uint32_t frame,
-                            hipStream_t s);
+// (information words updated, tiles' replace counts into block_cnt[0 ..
+// n_tiles)).  tiles index the descriptor table 'table', and every tile names
+// the same scene, 'scene'; the frame number is *frame_ptr when frame_ptr is
+// not NULL (graph replays), else 'frame'.
+hipError_t launch_dm_update(const SceneDev* table, const SceneDev* scene, const uint2* tiles, uint32_t n_tiles,
+                            uint32_t cells, uint32_t n_lights, const DmWork& D, uint32_t* block_cnt, uint64_t seed,
+                            uint32_t frame, const uint32_t* frame_ptr, hipStream_t s);
 hipError_t launch_energy_fwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,
                              const float* power, float* E, hipStream_t s);
 hipError_t launch_energy_bwd(const SceneDev* scenes, const uint2* tiles, uint32_t n_tiles, const float* albedo,

@@ -525,6 +525,18 @@ def test_batch_mixed_modes_matches_plain(E):
     _batch_vs_plain(E, scs, [False, True, False, True])
 
 
+def test_batch_distribution_maps_match_plain(E):
+    # scenes whose contexts carry distribution maps (rectangle lights, spot
+    # lights, cameras) batched with one that has none: every frame runs the
+    # maps' update for those scenes between verification and the queue
+    scs = scenes.make_batch(n_scenes=2, frames=3, path_range=(3000, 20000), tri_range=(5000, 30000))
+    scs.append(scenes.make_rooms("bdm_spot", 2, 2, 8000, 3, (20, 10), 6000 + 5, 5, 3, 0.01, 33, n_lights=2,
+                                 lights_move=True, light_kind=1, light_param=(0.8, 0.0)))
+    scs.append(scenes.make_rooms("bdm_cam", 2, 2, 8000, 3, (20, 10), 5000 + 3, 6, 3, 0.01, 34, n_lights=2,
+                                 lights_move=True, light_kind=2, light_param=(0.6, 0.4)))
+    _batch_vs_plain(E, scs, [False, False, False, True], grids=[(2, 2, 4, 8), None, (1, 1, 3, 8), (8, 6, 1, 1)])
+
+
 def test_batch_scenes_match_oracle(E):
     # the batched form compared with the oracle directly: every scene of a
     # batch starts each frame from the oracle's store of the previous frame
@@ -597,14 +609,17 @@ def test_batch_frames_match_single_frames(E):
     bb.close()
 
 
-def _batch_vs_plain(E, scs, boxes):
+def _batch_vs_plain(E, scs, boxes, grids=None):
     import torch
     T, seed = 0.01, 7
+    grids = grids or [None] * len(scs)
     log("batch of %d scenes, %d paths" % (len(scs), sum(s.n_paths for s in scs)))
     plain = [E.Context(s) for s in scs]
     batch_ctx = [E.Context(s) for s in scs]
-    for c, bx in list(zip(plain, boxes)) + list(zip(batch_ctx, boxes)):
+    for c, bx, g in list(zip(plain, boxes, grids)) + list(zip(batch_ctx, boxes, grids)):
         c.set_verify_mode(bx)
+        if g is not None:
+            c.set_distribution_map(g)
     sp = [c.new_store() for c in plain]
     sb = [c.new_store() for c in batch_ctx]
     for c, st in list(zip(plain, sp)) + list(zip(batch_ctx, sb)):
@@ -612,9 +627,11 @@ def _batch_vs_plain(E, scs, boxes):
         c.initial_trace(st, seed, 0)
     b = E.Batch(batch_ctx, sb, T, seed)
     for f in (1, 2):
-        for c, st in zip(plain, sp):
+        for c, st, g in zip(plain, sp, grids):
             c.frame_begin(f)
-            c.verify(st)
+            c.verify(st, build_queue=g is None)
+            if g is not None:
+                c.update_distribution(st, seed, f)
             c.retrace(st, T, seed, f)
         b.frame(f)
         torch.cuda.synchronize()
