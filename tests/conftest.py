@@ -13,12 +13,13 @@ def pytest_configure(config):
 
 def pytest_sessionfinish(session, exitstatus):
     """Write the parity counts the GPU tests recorded (exclusions, largest
-    differences and tolerances) as JSON, by default under gpurun_out/."""
+    differences and tolerances) as JSON: reports/parity_report.json at the
+    repository root unless PV_PARITY_REPORT names another file."""
     from tests import harness
     if not harness.REPORT:
         return
     import json
-    path = os.environ.get("PV_PARITY_REPORT", os.path.join(ROOT, "gpurun_out", "parity_report.json"))
+    path = os.environ.get("PV_PARITY_REPORT", os.path.join(ROOT, "reports", "parity_report.json"))
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
         json.dump({"exitstatus": int(exitstatus), "comparisons": harness.REPORT}, f, indent=1, sort_keys=True)
