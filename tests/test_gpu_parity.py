@@ -767,6 +767,71 @@ def test_paper_full_size_sampled(E):
     assert cnt == int(((info2 >> 22) & 15).sum())
 
 
+def test_paper_full_size_invariants_over_frames(E):
+    # the 3M x 7 store after four free-running frames of verification and
+    # error-based re-tracing (T = 1%) on the device, checked at every path
+    # against properties the method fixes: each path ends its replacement,
+    # each photon lies on its triangle at the current frame, the first
+    # photon carries its light's power share, and Equation 2 holds along
+    # every pair of consecutive photons (a traced photon carries the exact
+    # albedo product; a kept one differs from it by at most T, per channel)
+    import torch
+    T = 0.01
+    sc = scenes.make_paper(frames=6)
+    N, B = sc.n_paths, sc.max_bounces
+    ctx = _setup(E, sc)
+    st = ctx.new_store()
+    ctx.initial_trace(st, sc.seed, 0)
+    for f in range(1, 5):
+        ctx.frame_begin(f)
+        ctx.verify(st)
+        ctx.retrace(st, T, sc.seed, f)
+    torch.cuda.synchronize()
+    g = st.to_numpy()
+    ctx.close()
+    fs = O.frame_scene(sc, 4)
+    info = g["info"]
+    n = (info >> 22) & 15
+    assert ((info >> 30) & 1).sum() == 0 and (n <= B).all()
+    rows = np.arange(B)[:, None] < n[None, :]
+    assert (g["hit"][~rows] == O.HIT_NONE).all() and (g["hit"][rows] < fs.verts.shape[0]).all()
+    # first photon: the light's power over its path count
+    lb = sc.light_base
+    for l in range(len(lb) - 1):
+        has = n[lb[l]:lb[l + 1]] > 0
+        e0 = g["energy"][0, lb[l]:lb[l + 1]][has].astype(np.float64)
+        share = sc.light_power[l].astype(np.float64) / float(lb[l + 1] - lb[l])
+        np.testing.assert_allclose(e0, np.broadcast_to(share, e0.shape), rtol=1e-6)
+    alb = sc.albedo.astype(np.float64)
+    V = fs.verts.reshape(-1, 3, 3).astype(np.float64)
+    worst_plane, worst_bary, worst_dev, kept = 0.0, 0.0, 0.0, 0
+    for r in range(B):
+        ok = rows[r]
+        h = g["hit"][r, ok].astype(np.int64)
+        p = g["pos"][r, ok].astype(np.float64)
+        tri = V[h]
+        nrm = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+        a2 = np.einsum("ij,ij->i", nrm, nrm)
+        worst_plane = max(worst_plane, float((np.abs(np.einsum("ij,ij->i", p - tri[:, 0], nrm)) / np.sqrt(a2)).max()))
+        bary = np.stack([np.einsum("ij,ij->i", np.cross(tri[:, (k + 1) % 3] - p, tri[:, (k + 2) % 3] - p), nrm) / a2
+                         for k in range(3)], 1)
+        worst_bary = max(worst_bary, float(-bary.min()))
+        if r + 1 < B:
+            nx = rows[r + 1]
+            e0 = g["energy"][r, nx].astype(np.float64)
+            e1 = g["energy"][r + 1, nx].astype(np.float64)
+            dev = np.abs(e0 * alb[fs.tri_mat[g["hit"][r, nx]]] - e1) / e1
+            worst_dev = max(worst_dev, float(dev.max()))
+            kept += int((dev > 1e-5).any(1).sum())
+    log("full-size invariants after 4 frames: photons %d, plane distance %.2e, barycentric undershoot %.2e, "
+        "Equation 2 deviation %.4f (%d pairs kept within T)" % (int(rows.sum()), worst_plane, worst_bary, worst_dev,
+                                                                kept))
+    H.record("paper full size invariants", photons=int(rows.sum()), plane=worst_plane, bary=worst_bary,
+             eq2_dev=worst_dev, kept_within_T=kept)
+    assert worst_plane < 1e-4 and worst_bary < 1e-3
+    assert worst_dev <= T + 1e-6
+
+
 @pytest.mark.parametrize("kind,param", [(1, (0.8, 0.0)), (2, (0.6, 0.4))], ids=["spot", "camera"])
 def test_paper_full_size_emitters_sampled(E, kind, param):
     # the 3M x 7 launch configuration lit by two moving spotlights or cameras

@@ -29,6 +29,9 @@ MUTATIONS = {
                        "out[c] = (float)((double)e[c] * (double)rho[1]);", "energies or figure1 or gradient or coloured"),
     # origin update: wrong sign of the distance to the light plane
     "light_plane_sign": ("double sdist = dot3(q, n) / dn;", "double sdist = -dot3(q, n) / dn;", "light_update"),
+    # Equation 2 tested on the green and blue channels only
+    "eq2_channels_skipped": ("  for (int c = 0; c < 3; ++c) {\n    volatile float d = en[c] - eo[c];",
+                             "  for (int c = 1; c < 3; ++c) {\n    volatile float d = en[c] - eo[c];", "equation2"),
     # Equation 2 made exclusive on the upper bound
     "eq2_exclusive": ("if (!(mte <= d && d <= te)) return 0;", "if (!(mte <= d && d < te)) return 0;", "eq2"),
     # Malley's lift with a dropped factor

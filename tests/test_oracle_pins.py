@@ -786,6 +786,47 @@ def test_retrace_result_is_valid_at_new_frame():
             assert checked > 20
 
 
+def _eq2_chain_deviation(st, albedo, tri_mat):
+    """Per channel, |E[r] rho(m(hit r)) - E[r+1]| / E[r+1] over every pair of
+    consecutive stored photons of every path."""
+    n = O.info_fields(st.info)["nseg"]
+    alb = albedo.astype(np.float64)
+    dev = []
+    for r in range(st.pos.shape[0] - 1):
+        ok = n > r + 1
+        e0 = st.energy[r, ok].astype(np.float64)
+        e1 = st.energy[r + 1, ok].astype(np.float64)
+        dev.append(np.abs(e0 * alb[tri_mat[st.hit[r, ok]]] - e1) / e1)
+    return np.concatenate(dev)
+
+
+@pytest.mark.parametrize("T", [0.01, 0.02])
+def test_equation2_holds_along_every_stored_path(T):
+    # Equation 2 accepts a kept photon only when the energy the new vertex
+    # would send on is within T of the stored one, per channel; a traced
+    # photon carries the exact albedo product.  So after any number of
+    # error-based frames every pair of consecutive photons satisfies
+    # |E_r rho(m_r) - E_{r+1}| <= T E_{r+1}.  The cube's albedo differs from
+    # the walls' by 1.43% (red) and 0.71% (green): a re-hit that swaps the two
+    # surfaces is kept at T = 2% (such pairs must appear) and never at T = 1%.
+    sc = scenes.make_tiny(n_paths=16384, frames=5)
+    sc.albedo[1] = np.array([0.69, 0.705, 0.7], np.float32)
+    fs = O.frame_scene(sc, 0)
+    st, _, _ = O.initial_trace(fs, sc.n_paths, sc.max_bounces, sc.seed)
+    assert _eq2_chain_deviation(st, sc.albedo, fs.tri_mat).max() < 1e-6
+    for f in range(1, 5):
+        fs = O.frame_scene(sc, f, f - 1)
+        O.verify(fs, st)
+        O.retrace(fs, st, T, sc.seed, f)
+    dev = _eq2_chain_deviation(st, sc.albedo, fs.tri_mat)
+    assert dev.max() <= T + 1e-6
+    swapped = (dev > 0.0142) & (dev < 0.0144)  # the red channel of a wall/cube swap
+    if T == 0.02:
+        assert swapped.sum() > 100
+    else:
+        assert swapped.sum() == 0 and dev.max() < 1e-6
+
+
 def test_figure1_last_segment_only_new_hit():
     # path: light -> floor -> right wall -> back wall; blocker in front of the back wall
     orig = [0.5, 0.999, 0.5]
