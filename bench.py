@@ -187,6 +187,76 @@ def headline_graph(args, engine, sc, torch, np, T, tuning):
     return res
 
 
+def method_modes(engine, scenes, torch, sc_paper, T, tuning, frames=6):
+    """The method's other forms on the paper-scale workload, each on its own
+    context from its own frame-0 trace: distribution maps (4x4 positions x
+    8 rings x 16 sectors per light, updated after every verification), the
+    cosine-ratio reading of Equation 2, and the same rooms lit by two moving
+    spotlights or two cameras.  Per-phase times are HIP events on the
+    context's stream, averaged over the timed frames."""
+    out = {}
+    for mode in ("distribution_maps", "cosine_ratio", "spot_lights", "cameras"):
+        if mode in ("spot_lights", "cameras"):
+            kind, param = (1, (0.8, 0.0)) if mode == "spot_lights" else (2, (0.6, 0.4))
+            sc = scenes.make_rooms("paper", 6, 6, 300_000, 8, (100, 50), 3_000_000, 7, frames + 3, T, 3,
+                                   n_lights=2, lights_move=True, torus_size=(0.2, 0.07), light_kind=kind,
+                                   light_param=param)
+        else:
+            sc = sc_paper if sc_paper.n_frames >= frames + 3 else scenes.make_paper(frames=frames + 3)
+        ctx = engine.Context(sc)
+        set_tuning(ctx, tuning)
+        if mode == "distribution_maps":
+            ctx.set_distribution_map((4, 4, 8, 16))
+        if mode == "cosine_ratio":
+            ctx.set_energy_test(True)
+        st = ctx.new_store()
+        ctx.frame_begin(0)
+        ctx.initial_trace(st, sc.seed, 0)
+        cap = sc.n_paths * sc.max_bounces
+        o = (torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
+             torch.empty((cap, 3), dtype=torch.float32, device="cuda"),
+             torch.zeros(1, dtype=torch.int32, device="cuda"))
+        names = ["frame_begin", "verify", "distribution", "queue", "retrace", "compact_photons"]
+        acc = {k: 0.0 for k in names}
+        seg = rays = inv = 0
+        for i in range(2 + frames):
+            f = 1 + i
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+            s = ctx.new_stats()
+            ev[0].record()
+            ctx.frame_begin(f)
+            ev[1].record()
+            ctx.verify(st, s, build_queue=False)
+            ev[2].record()
+            if mode == "distribution_maps":
+                ctx.update_distribution(st, sc.seed, f)
+            ev[3].record()
+            ctx.build_queue(st)
+            ev[4].record()
+            ctx.retrace(st, T, sc.seed, f, s)
+            ev[5].record()
+            ctx.compact_photons_into(st, *o)
+            ev[6].record()
+            torch.cuda.synchronize()
+            if i < 2:
+                continue  # warm-up frames
+            for j, k in enumerate(names):
+                acc[k] += ev[j].elapsed_time(ev[j + 1]) / frames
+            d = ctx.stats_dict(s)
+            seg += d["segments_examined"]
+            rays += d["rays_traced"]
+            inv += d["paths_invalid"]
+        ctx.close()
+        del st, o
+        torch.cuda.empty_cache()
+        ms = sum(acc.values())
+        out[mode] = {"ms_per_frame": ms, "segments_per_s": seg / frames / (ms / 1e3),
+                     "phases_ms": {k: v for k, v in acc.items() if k != "distribution" or mode == "distribution_maps"},
+                     "paths_invalid_per_frame": inv / frames, "rays_per_frame": rays / frames}
+        log("mode %s: %.3f ms per frame" % (mode, ms))
+    return out
+
+
 def cache_resident_mid(engine, scenes, torch, tuning):
     """The mid workload (1M paths x 7 bounces, 3 moving objects): its
     verification reads (about 130 MB) fit in the 256 MB Infinity Cache, so
@@ -303,6 +373,8 @@ def main():
                     help="first copy this many MiB device to device (counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--no-headline-graph", action="store_true")
     ap.add_argument("--no-cache-resident", action="store_true")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the distribution-map, cosine-ratio, spotlight and camera frames")
     ap.add_argument("--headline-graph-frames", type=int, default=30)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -577,6 +649,8 @@ def main():
         res["batched_headline"] = headline_graph(args, engine, sc, torch, np, T, tuning)
     if not args.no_cache_resident and args.config == "paper":
         res["cache_resident_mid"] = cache_resident_mid(engine, scenes, torch, tuning)
+    if not args.no_modes and args.config == "paper":
+        res["method_modes"] = method_modes(engine, scenes, torch, sc, T, tuning)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sc, engine, torch, T, args.cpu_seconds)
     print(json.dumps(res), flush=True)
