@@ -175,17 +175,24 @@ __global__ __launch_bounds__(kBlock) void k_dm_flags(const SceneDev* __restrict_
   }
 }
 
-// rank of each light's first path among the re-sampled paths of the store
-__global__ void k_dm_rank0(const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ toff,
-                           uint32_t* __restrict__ rank0) {
+// rank of each light's first path among the re-sampled paths of the store:
+// the scanned count of the tiles before its first path's tile plus the
+// re-sampled paths of that tile ahead of it (one wave per light, a ballot
+// per 64 of those paths)
+__global__ __launch_bounds__(64) void k_dm_rank0(const SceneDev* __restrict__ scenes,
+                                                 const uint32_t* __restrict__ toff, uint32_t* __restrict__ rank0) {
   const SceneDev& S = scenes[0];
-  const uint32_t l = threadIdx.x;
+  const uint32_t l = blockIdx.x;
   if (l >= S.n_lights) return;
   const uint32_t base = G(S.lights)[l].path_base;
   const uint32_t t0 = base / kBlock * kBlock;
-  uint32_t r = base / kBlock < S.n_blocks ? toff[base / kBlock] : 0u;
-  for (uint32_t q = t0; q < base; ++q) r += (light_index(S, q) >= 0 && resampled(G(S.info)[q])) ? 1u : 0u;
-  rank0[l] = r;
+  uint32_t r = 0;
+  for (uint32_t q0 = t0; q0 < base; q0 += 64) {
+    const uint32_t q = q0 + lane();
+    const bool f = q < base && light_index(S, q) >= 0 && resampled(G(S.info)[q]);
+    r += (uint32_t)__popcll(__ballot(f));
+  }
+  if (lane() == 0) rank0[l] = (base / kBlock < S.n_blocks ? toff[base / kBlock] : 0u) + r;
 }
 
 // Fill DM_C: the i-th re-sampled path of a light (path order) takes the cell
@@ -251,7 +258,7 @@ hipError_t launch_dm_update(const SceneDev* table, const SceneDev* scene, const 
   hipLaunchKernelGGL(k_dm_flags, dim3(n_tiles), dim3(kBlock), 0, s, table, tiles, D.tcnt);
   e = launch_scan(D.tcnt, D.toff, n_tiles, D.ttotal, D.scan_tmp2, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dm_rank0, dim3(1), dim3(64), 0, s, scene, D.toff, D.rank0);
+  hipLaunchKernelGGL(k_dm_rank0, dim3(n_lights), dim3(64), 0, s, scene, D.toff, D.rank0);
   hipLaunchKernelGGL(k_dm_fill, dim3(n_tiles), dim3(kBlock), 0, s, table, tiles, D.dex, D.toff, D.rank0,
                      block_cnt);
   return hipGetLastError();
