@@ -149,3 +149,16 @@ def test_hierarchy_invariants(make, kind):
     assert info["depth"] <= MAX_DEPTH
     if kind == 1:
         assert info["leaves"] >= n // 2                  # leaves of at most 2 triangles
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; another count is refused with a message
+    # before anything touches a device
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
