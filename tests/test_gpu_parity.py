@@ -166,7 +166,8 @@ def test_max_bounces_fifteen(E):
 # the oracle's store of the previous frame)
 
 
-def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False, energy_test=0):
+def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False, energy_test=0, require_replaced=True,
+              excl_frac=H.EXCL_FRAC):
     ora, _ = _oracle_frame0(sc)
     ctx = E.Context(sc)
     if tuning:
@@ -197,10 +198,11 @@ def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False, energy_test=0
         ok2 = ok & _amb_ok(ambr)
         log("  replaced %d, excluded (within a decision band) %d of %d" % (
             ((gv["info"] >> 30) & 1).sum(), (~ok2).sum(), sc.n_paths))
-        H.check_excluded((~ok2).sum(), sc.n_paths, "%s frame %d" % (label, f))
+        H.check_excluded((~ok2).sum(), sc.n_paths, "%s frame %d" % (label, f), excl_frac)
         H.compare_stores(gr, ora, ok2, "%s frame %d" % (label, f), fs.verts, (~ok2).sum())
-    assert total_rep > 0
+    assert total_rep > 0 or not require_replaced
     ctx.close()
+    return total_rep
 
 
 def test_mid_rooms_lockstep(E):
@@ -220,6 +222,40 @@ def test_rooms_lockstep_other_seeds(E, seed):
     sc = scenes.make_rooms("seed%d" % seed, 3, 3, 20000, 4, (40, 16), 5000 + seed % 64, 6, 4, 0.01, seed,
                            n_lights=2, lights_move=True)
     _lockstep(E, sc, 4, 0.01, "rooms seed %d" % seed, energy_test=seed % 2)
+
+
+def random_configuration(seed):
+    """A scene and run settings drawn from seed: room grid, triangle budget,
+    moving tori, path count (ragged), bounce limit, lights (area, point, spot
+    or camera; moving or not), threshold, verification mode and energy test."""
+    rng = np.random.default_rng(seed)
+    kind = int(rng.integers(0, 4))  # 0 area, 1 spot, 2 camera, 3 point
+    param = {1: (float(rng.uniform(0.5, 0.9)), 0.0), 2: (float(rng.uniform(0.3, 0.8)), float(rng.uniform(0.3, 0.8)))}
+    segs = [(16, 8), (24, 12), (40, 16)][int(rng.integers(0, 3))]
+    nx, nz = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+    n_static, n_dyn = int(rng.integers(2000, 30000)), int(rng.integers(1, 7))
+    n_paths, B = int(rng.integers(1000, 6000)) + int(rng.integers(0, 64)), int(rng.integers(1, 8))
+    n_lights = min(int(rng.integers(1, 3)), nx * nz)  # one light per room at most
+    sc = scenes.make_rooms("random%d" % seed, nx, nz, n_static, n_dyn, segs, n_paths, B, 3, 0.01, seed,
+                           n_lights=n_lights, lights_move=bool(rng.integers(0, 2)), point_lights=kind == 3,
+                           light_kind=kind if kind in (1, 2) else 0, light_param=param.get(kind, (0.0, 0.0)))
+    T = [-1.0, 0.0, 0.01, 0.3][int(rng.integers(0, 4))]
+    boxes = bool(rng.integers(0, 2))
+    energy_test = int(rng.integers(0, 2)) if T >= 0 else 0
+    return sc, T, boxes, energy_test
+
+
+@pytest.mark.parametrize("seed", list(range(1000, 1012)))
+def test_random_configurations_lockstep(E, seed):
+    # twelve configurations drawn at random from the method's options, each
+    # in lockstep with the oracle for two frames.  A random layout can put a
+    # light within the box test's decision band of a moved object's box (seed
+    # 1005: the spotlight 1e-5 from a box face, 8.3% of the paths flagged by
+    # the oracle), so these runs allow 15% of a frame's paths excluded
+    sc, T, boxes, energy_test = random_configuration(seed)
+    label = "random %d (%s, N=%d, B=%d, T=%g, boxes %d, energy test %d)" % (
+        seed, sc.name, sc.n_paths, sc.max_bounces, T, boxes, energy_test)
+    _lockstep(E, sc, 3, T, label, boxes=boxes, energy_test=energy_test, require_replaced=False, excl_frac=0.15)
 
 
 def test_paper_rooms_moving_lights(E):
