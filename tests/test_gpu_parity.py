@@ -575,6 +575,16 @@ def test_batch_distribution_maps_match_plain(E):
                     cosine=[False, True, True, False])
 
 
+def test_batch_random_configurations_match_plain(E):
+    # six randomly drawn configurations (lights of every kind, both
+    # verification modes, both energy tests, three with distribution maps)
+    # batched together against the plain per-scene calls
+    drawn = [random_configuration(seed) for seed in range(1000, 1006)]
+    scs = [d[0] for d in drawn]
+    grids = [(2, 2, 2, 4), None, (1, 1, 2, 8), None, (2, 2, 4, 8), None]
+    _batch_vs_plain(E, scs, [d[2] for d in drawn], grids=grids, cosine=[bool(d[3]) for d in drawn])
+
+
 def test_batch_scenes_match_oracle(E):
     # the batched form compared with the oracle directly: every scene of a
     # batch starts each frame from the oracle's store of the previous frame
