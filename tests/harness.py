@@ -34,19 +34,28 @@ EPS_POS = 2e-7   # FP32 rounding of a computed position (coordinates within [-1,
 EPS_DIR = 4e-7   # FP32 error of a sampled or normalised unit direction
 
 
-def photon_tolerance(ora, verts9):
+def photon_tolerance(ora, verts9, before=None):
     """Per-photon position tolerance: first-order bound of |FP32 - FP64|.
 
     A ray whose origin is off by e and whose direction is off by EPS_DIR hits a
     surface at incidence cosine c with an error of at most (e + d EPS_DIR) / c,
     d being the ray length; the bound is propagated along the path from the
-    light sample and the tolerance is 1e-5 plus four times it."""
+    light sample and the tolerance is 1e-5 plus four times it.
+
+    With 'before' (the store as the frame found it), a vertex that the frame
+    hit anew may start a segment aimed at the old next photon (Algorithm 1
+    checks, then traces, the segment from the new vertex to the old photon):
+    that direction is the difference of two points a distance l apart, so the
+    new vertex's error e tilts it by up to e / l on top of EPS_DIR."""
     V = verts9.reshape(-1, 3, 3).astype(np.float64)
     B, N = ora.hit.shape
     n = (ora.info >> 22) & 15
     tol = np.full((B, N), POS_TOL)
     err = np.full(N, EPS_POS)
     prev = ora.origin.astype(np.float64)
+    if before is not None:
+        prev_old = before.origin.astype(np.float64)
+        n_old = (before.info >> 22) & 15
     for r in range(B):
         valid = r < n
         p = ora.pos[r].astype(np.float64)
@@ -58,7 +67,16 @@ def photon_tolerance(ora, verts9):
         d = p - prev
         dist = np.linalg.norm(d, axis=1)
         c = np.abs(np.einsum("ij,ij->i", d, nrm)) / np.maximum(dist, 1e-300)
-        err = np.where(valid, (err + dist * EPS_DIR) / np.maximum(c, 1e-3) + EPS_POS, err)
+        eps_d = np.full(N, EPS_DIR)
+        if before is not None:
+            # the vertex this segment starts from was hit anew and an old
+            # photon r existed: the segment may have been aimed at it
+            moved = np.any(prev != prev_old, axis=1) & (r < n_old)
+            target = before.pos[r].astype(np.float64)
+            ell = np.linalg.norm(target - prev, axis=1)
+            eps_d = np.where(moved & (ell > 0), eps_d + err / np.maximum(ell, 1e-300), eps_d)
+            prev_old = np.where((r < n_old)[:, None], target, prev_old)
+        err = np.where(valid, (err + dist * eps_d) / np.maximum(c, 1e-3) + EPS_POS, err)
         tol[r] = POS_TOL + 4.0 * err
         prev = np.where(valid[:, None], p, prev)
     return tol
@@ -107,7 +125,7 @@ def from_oracle(st):
     return dict(pos=st.pos, hit=st.hit, energy=st.energy, radius=st.radius, origin=st.origin, info=st.info)
 
 
-def compare_stores(gpu, ora, mask, label="", verts9=None, excluded=None):
+def compare_stores(gpu, ora, mask, label="", verts9=None, excluded=None, before=None):
     """Element-wise comparison of the columns selected by mask (bool [N]).
 
     Positions use the per-photon tolerance, capped at POS_CAP, when the
@@ -127,7 +145,7 @@ def compare_stores(gpu, ora, mask, label="", verts9=None, excluded=None):
     assert not diff.any(), "%s hit ids differ at %d photons (first path %d)" % (
         label, diff.sum(), idx[np.flatnonzero(diff.any(0))[0]])
     dp = np.abs(gpu["pos"][:, idx] - ora.pos[:, idx]).max(axis=-1)
-    bound = photon_tolerance(ora, verts9)[:, idx] if verts9 is not None else np.full(dp.shape, POS_TOL)
+    bound = photon_tolerance(ora, verts9, before)[:, idx] if verts9 is not None else np.full(dp.shape, POS_TOL)
     tol = np.minimum(bound, POS_CAP)
     flagged = rows & (dp > tol) & (dp <= bound)
     over = rows & (dp > bound)

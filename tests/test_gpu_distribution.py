@@ -108,12 +108,13 @@ def _run(E, sc, frames, T, label, grid=GRID):
                 strict_frames += 1
         ctx.retrace(st, T, sc.seed, f)
         gr = st.to_numpy()
+        before = ora.copy()
         ambr, _ = O.retrace(fs, ora, T, sc.seed, f)
         if not same_hist:
             continue
         ok = ~flagged & (ambr == 0)
         H.check_excluded((~ok).sum(), sc.n_paths, "%s frame %d" % (label, f))
-        H.compare_stores(gr, ora, ok, "%s frame %d" % (label, f), fs.verts, (~ok).sum())
+        H.compare_stores(gr, ora, ok, "%s frame %d" % (label, f), fs.verts, (~ok).sum(), before)
     ctx.close()
     return strict_frames
 
@@ -146,6 +147,15 @@ def test_distribution_maps_spot_lights_and_cameras(E, kind, param, grid):
     sc = scenes.make_rooms("dm%d" % kind, 3, 3, 20_000, 3, (40, 16), 4096 + 9, 5, 3, 0.01, 17, n_lights=2,
                            lights_move=True, light_kind=kind, light_param=param)
     assert _run(E, sc, 3, 0.01, "dm kind %d" % kind, grid=grid) >= 1
+
+
+@pytest.mark.parametrize("seed", list(range(1000, 1006)))
+def test_distribution_maps_random_configurations(E, seed):
+    # the randomly drawn configurations of the parity tests (lights of every
+    # kind, moving or not; their thresholds) with maps, against the oracle
+    from tests.test_gpu_parity import random_configuration
+    sc, T, _, _ = random_configuration(seed)
+    _run(E, sc, 3, T, "dm random %d" % seed)
 
 
 def test_distribution_maps_full_size_first_frame(E):

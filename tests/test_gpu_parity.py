@@ -194,12 +194,13 @@ def _lockstep(E, sc, n_frames, T, label, tuning=None, boxes=False, energy_test=0
         total_rep += int(((gv["info"] >> 30) & 1).sum())
         ctx.retrace(st, T, sc.seed, f)
         gr = st.to_numpy()
+        before = ora.copy()
         ambr, _ = O.retrace(fs, ora, T, sc.seed, f)
         ok2 = ok & _amb_ok(ambr)
         log("  replaced %d, excluded (within a decision band) %d of %d" % (
             ((gv["info"] >> 30) & 1).sum(), (~ok2).sum(), sc.n_paths))
         H.check_excluded((~ok2).sum(), sc.n_paths, "%s frame %d" % (label, f), excl_frac)
-        H.compare_stores(gr, ora, ok2, "%s frame %d" % (label, f), fs.verts, (~ok2).sum())
+        H.compare_stores(gr, ora, ok2, "%s frame %d" % (label, f), fs.verts, (~ok2).sum(), before)
     assert total_rep > 0 or not require_replaced
     ctx.close()
     return total_rep
