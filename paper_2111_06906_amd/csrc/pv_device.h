@@ -659,7 +659,12 @@ __device__ inline void dm_sample(const float* xf, const LightDev& lt, const int3
   }
   const float rho2 = ((float)ring + u[2]) / (float)nr * s2, rho = sqrtf(rho2);
   const float phi = -kPiF + ((float)sector + u[3]) * (2.0f * kPiF / (float)ns);
-  const float lx = rho * cosf(phi), ly = rho * sinf(phi), lz = sqrtf(fmaxf(1.0f - rho2, 0.0f));
+  // height over the disk point, sqrt(1 - rho^2), formed without cancellation
+  // near the disk's rim: 1 - rho^2 = (1 - s2) + s2 (1 - t) for rho^2 = s2 t,
+  // with 1 - t = ((nr - ring) - u) / nr and 1 - s2 the squared cone cosine
+  const float om = ((float)(nr - ring) - u[2]) / (float)nr;
+  const float c2 = lt.kind == PV_LIGHT_SPOT ? lt.param[0] * lt.param[0] : 0.0f;
+  const float lx = rho * cosf(phi), ly = rho * sinf(phi), lz = sqrtf(fmaxf(c2 + s2 * om, 0.0f));
   *w = add(add(mul(eu, lx), mul(ev, ly)), mul(n, lz));
 }
 

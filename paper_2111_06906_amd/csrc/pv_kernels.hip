@@ -1321,11 +1321,14 @@ __device__ inline void start_path(Lane& L, float T, uint64_t seed, uint32_t fram
       x0 = add(c, add(mul(eu, a), mul(ev, b)));
       float3 lc = cosine_local(u[2], u[3]);
       if (ld.kind == PV_LIGHT_SPOT) {
-        // the disk point scaled to the cone's radius, then lifted
+        // the disk point scaled to the cone's radius, then lifted: with the
+        // unit disk's height z0, 1 - sr^2 r^2 = cos^2 + sr^2 z0^2 (no
+        // cancellation near the cone's rim)
         const float sr = sqrtf((1.0f - ld.param[0]) * (1.0f + ld.param[0]));
+        const float z0 = lc.z;
         lc.x *= sr;
         lc.y *= sr;
-        lc.z = sqrtf(fmaxf(1.0f - (lc.x * lc.x + lc.y * lc.y), 0.0f));
+        lc.z = sqrtf(ld.param[0] * ld.param[0] + (sr * sr) * (z0 * z0));
       }
       L.w = add(add(mul(eu, lc.x), mul(ev, lc.y)), mul(nl, lc.z));
     }

@@ -58,6 +58,10 @@ def photon_tolerance(ora, verts9, before=None):
     if before is not None:
         prev_old = before.origin.astype(np.float64)
         n_old = (before.info >> 22) & 15
+        # vertices the re-trace may hit anew: photons k.. of a replaced path
+        # (their FP32 value can even equal the old one on one side only)
+        rep = ((before.info >> 30) & 1).astype(bool)
+        k_old = ((before.info >> 26) & 15).astype(np.int64)
     for r in range(B):
         valid = r < n
         p = ora.pos[r].astype(np.float64)
@@ -73,7 +77,7 @@ def photon_tolerance(ora, verts9, before=None):
         if before is not None:
             # the vertex this segment starts from was hit anew and an old
             # photon r existed: the segment may have been aimed at it
-            moved = np.any(prev != prev_old, axis=1) & (r < n_old)
+            moved = (np.any(prev != prev_old, axis=1) | (rep & (r - 1 >= k_old))) & (r < n_old)
             target = before.pos[r].astype(np.float64)
             ell = np.linalg.norm(target - prev, axis=1)
             eps_d = np.where(moved & (ell > 0), eps_d + err / np.maximum(ell, 1e-300), eps_d)
