@@ -149,10 +149,13 @@ def test_distribution_maps_spot_lights_and_cameras(E, kind, param, grid):
     assert _run(E, sc, 3, 0.01, "dm kind %d" % kind, grid=grid) >= 1
 
 
-@pytest.mark.parametrize("seed", list(range(1000, 1006)))
+@pytest.mark.parametrize("seed", list(range(1000, 1006)) + [2208, 2301, 2337, 2736])
 def test_distribution_maps_random_configurations(E, seed):
     # the randomly drawn configurations of the parity tests (lights of every
-    # kind, moving or not; their thresholds) with maps, against the oracle
+    # kind, moving or not; their thresholds) with maps, against the oracle;
+    # the last four come from a wider sweep: paths that part after a grazing
+    # chain (2208, 2301, 2337) and a cell sample 1e-3 above the light's plane
+    # (2736)
     from tests.test_gpu_parity import random_configuration
     sc, T, _, _ = random_configuration(seed)
     _run(E, sc, 3, T, "dm random %d" % seed)
