@@ -261,6 +261,37 @@ def test_random_configurations_lockstep(E, seed):
     _lockstep(E, sc, 3, T, label, boxes=boxes, energy_test=energy_test, require_replaced=False, excl_frac=0.15)
 
 
+@pytest.mark.parametrize("seed", [7000, 7001, 7002])
+def test_random_configurations_tuning_invariant(E, seed):
+    # results never depend on the tuning: a drawn configuration run for two
+    # frames with the default tuning and with two drawn ones (re-trace
+    # occupancy variant, both grids, both yield thresholds), stores bit for bit
+    import torch
+    sc, T, boxes, et = random_configuration(seed)
+    rng = np.random.default_rng(seed)
+    stores = []
+    for trial in range(3):
+        ctx = E.Context(sc)
+        ctx.set_verify_mode(boxes)
+        ctx.set_energy_test(bool(et))
+        if trial:
+            ctx.set_tuning(int(rng.integers(0, 4)), int(rng.choice([1, 2, 4, 8, 16])), int(rng.integers(1, 65)),
+                           int(rng.choice([1, 2, 4, 8, 16, 32])), int(rng.integers(1, 65)))
+        st = ctx.new_store()
+        ctx.frame_begin(0)
+        ctx.initial_trace(st, sc.seed, 0)
+        for f in (1, 2):
+            ctx.frame_begin(f)
+            ctx.verify(st)
+            ctx.retrace(st, T, sc.seed, f)
+        torch.cuda.synchronize()
+        stores.append(st.to_numpy())
+        ctx.close()
+    for s in stores[1:]:
+        for k in s:
+            assert np.array_equal(stores[0][k].view(np.uint32), s[k].view(np.uint32)), (seed, k)
+
+
 def test_paper_rooms_moving_lights(E):
     sc = scenes.make_paper(n_paths=4096 + 13, frames=3)
     _lockstep(E, sc, 3, 0.01, "paper")
